@@ -1,0 +1,248 @@
+"""gj: radix-partitioned joins and grouped aggregations on one MI355X.
+
+Thin ctypes binding over libgj.so (C ABI in include/gj.h). It only marshals
+arguments: every step of the join and group-by runs in the library's HIP
+kernels. torch supplies device memory (through the allocator callback) and the
+HIP stream. If libgj.so is missing, every call raises; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgj.so")
+
+GJ_I32, GJ_I64 = 1, 2
+MAT = {"auto": 0, "gftr": 1, "gfur": 2}
+GB_ALGO = {"auto": 0, "hash": 1, "sort": 2, "partition": 3}
+AGG_OP = {"sum": 1, "count": 2, "min": 3, "max": 4}
+DIGIT = {"bits": 0, "hash": 1, "ordered": 2}
+ERRORS = {-1: "GJ_EINVAL", -2: "GJ_ENOMEM", -3: "GJ_EHIP", -4: "GJ_EUNSUPPORTED",
+          -5: "GJ_ECAPACITY", -6: "GJ_EOVERFLOW"}
+
+
+class GJError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Col(ctypes.Structure):
+    _fields_ = [("data", ctypes.c_void_p), ("dtype", ctypes.c_int32)]
+
+
+class Rel(ctypes.Structure):
+    _fields_ = [("key", Col), ("payloads", ctypes.POINTER(Col)), ("n_payloads", ctypes.c_int32),
+                ("n_rows", ctypes.c_int64)]
+
+
+_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+_FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class Allocator(ctypes.Structure):
+    _fields_ = [("alloc", _ALLOC_FN), ("free", _FREE_FN), ("ctx", ctypes.c_void_p)]
+
+
+class JoinOpts(ctypes.Structure):
+    _fields_ = [("mat", ctypes.c_int32), ("unique_build_keys", ctypes.c_int32),
+                ("radix_bits", ctypes.c_int32), ("passes", ctypes.c_int32),
+                ("block_size", ctypes.c_int32), ("ht_occupancy", ctypes.c_float),
+                ("lds_budget", ctypes.c_int32), ("flags", ctypes.c_uint64)]
+
+
+class JoinOut(ctypes.Structure):
+    _fields_ = [("key", ctypes.c_void_p), ("r_payloads", ctypes.POINTER(ctypes.c_void_p)),
+                ("s_payloads", ctypes.POINTER(ctypes.c_void_p)), ("n_rows", ctypes.c_int64)]
+
+
+class Agg(ctypes.Structure):
+    _fields_ = [("col", ctypes.c_int32), ("op", ctypes.c_int32)]
+
+
+class GroupByOpts(ctypes.Structure):
+    _fields_ = [("algo", ctypes.c_int32), ("mat", ctypes.c_int32), ("radix_bits", ctypes.c_int32),
+                ("block_size", ctypes.c_int32), ("ht_occupancy", ctypes.c_float),
+                ("lds_budget", ctypes.c_int32)]
+
+
+class GroupByOut(ctypes.Structure):
+    _fields_ = [("key", ctypes.c_void_p), ("aggs", ctypes.POINTER(ctypes.c_void_p)),
+                ("n_groups", ctypes.c_int64)]
+
+
+_lib = None
+_lib_lock = threading.Lock()
+
+
+def lib() -> ctypes.CDLL:
+    """Load libgj.so; raises if it has not been built."""
+    global _lib
+    with _lib_lock:
+        if _lib is None:
+            if not os.path.exists(LIB_PATH):
+                raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                                   "`python -m paper_2312_00720_amd.build`")
+            L = ctypes.CDLL(LIB_PATH)
+            vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+            L.gj_join.restype = ctypes.c_int
+            L.gj_join.argtypes = [ctypes.POINTER(Rel), ctypes.POINTER(Rel), ctypes.POINTER(JoinOpts),
+                                  ctypes.POINTER(Allocator), vp, ctypes.POINTER(JoinOut)]
+            L.gj_partition.restype = ctypes.c_int
+            L.gj_partition.argtypes = [Col, ctypes.POINTER(Col), i32, i64, i32, i32, i32, i32,
+                                       vp, ctypes.POINTER(vp), vp, vp, ctypes.POINTER(Allocator), vp]
+            L.gj_groupby.restype = ctypes.c_int
+            L.gj_groupby.argtypes = [Col, ctypes.POINTER(Col), i32, i64, ctypes.POINTER(Agg), i32,
+                                     ctypes.POINTER(GroupByOpts), ctypes.POINTER(Allocator), vp,
+                                     ctypes.POINTER(GroupByOut)]
+            L.gj_last_error.restype = ctypes.c_char_p
+            L.gj_last_error.argtypes = []
+            L.gj_version.restype = ctypes.c_char_p
+            L.gj_version.argtypes = []
+            _lib = L
+    return _lib
+
+
+class _TorchAllocator:
+    """Device memory for one library call, from torch's caching allocator on the
+    current stream. Blocks handed out as outputs are kept; scratch blocks are
+    dropped when the library frees them."""
+
+    def __init__(self, device: torch.device):
+        self.device = device
+        self.live: dict[int, torch.Tensor] = {}
+
+        def _alloc(nbytes, _ctx):
+            try:
+                t = torch.empty(int(nbytes), dtype=torch.uint8, device=self.device)
+            except RuntimeError:
+                return None
+            p = t.data_ptr()
+            self.live[p] = t
+            return p
+
+        def _free(ptr, _ctx):
+            self.live.pop(int(ptr or 0), None)
+
+        self._a = _ALLOC_FN(_alloc)
+        self._f = _FREE_FN(_free)
+        self.struct = Allocator(self._a, self._f, None)
+
+    def take(self, ptr: int, dtype: torch.dtype, n: int) -> torch.Tensor:
+        if n == 0 or not ptr:
+            return torch.empty(0, dtype=dtype, device=self.device)
+        buf = self.live.pop(int(ptr))
+        return buf[: n * torch.empty(0, dtype=dtype).element_size()].view(dtype)
+
+
+def _dtype_code(t: torch.Tensor) -> int:
+    if t.dtype == torch.int32:
+        return GJ_I32
+    if t.dtype == torch.int64:
+        return GJ_I64
+    raise TypeError(f"columns must be int32 or int64 tensors, got {t.dtype}")
+
+
+def _check_cols(cols, n, device):
+    for c in cols:
+        if c.device != device or not c.is_contiguous() or c.dim() != 1 or c.numel() != n:
+            raise ValueError("columns must be contiguous 1-D tensors of equal length on one device")
+
+
+def _col(t: torch.Tensor) -> Col:
+    return Col(t.data_ptr() if t.numel() else None, _dtype_code(t))
+
+
+def _stream(device) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def _raise(rc: int):
+    if rc != 0:
+        raise GJError(rc, lib().gj_last_error().decode())
+
+
+def join(r_key: torch.Tensor, r_pay, s_key: torch.Tensor, s_pay, *, mat: str = "auto",
+         radix_bits: int = 0, passes: int = 0, lds_budget: int = 0, unique_build_keys: bool = False):
+    """Inner equi-join on key. Returns (key, [R payloads], [S payloads]) as
+    device tensors; row order is unspecified but deterministic."""
+    L = lib()
+    r_pay, s_pay = list(r_pay), list(s_pay)
+    dev = r_key.device
+    _check_cols([r_key, *r_pay], r_key.numel(), dev)
+    _check_cols([s_key, *s_pay], s_key.numel(), dev)
+    rp = (Col * max(1, len(r_pay)))(*[_col(t) for t in r_pay])
+    sp = (Col * max(1, len(s_pay)))(*[_col(t) for t in s_pay])
+    R = Rel(_col(r_key), rp, len(r_pay), r_key.numel())
+    S = Rel(_col(s_key), sp, len(s_pay), s_key.numel())
+    o = JoinOpts(MAT[mat], int(unique_build_keys), radix_bits, passes, 0, 0.0, lds_budget, 0)
+    ro = (ctypes.c_void_p * max(1, len(r_pay)))()
+    so = (ctypes.c_void_p * max(1, len(s_pay)))()
+    out = JoinOut(None, ro, so, 0)
+    A = _TorchAllocator(dev)
+    rc = L.gj_join(ctypes.byref(R), ctypes.byref(S), ctypes.byref(o), ctypes.byref(A.struct),
+                   _stream(dev), ctypes.byref(out))
+    _raise(rc)
+    n = out.n_rows
+    key = A.take(out.key, r_key.dtype, n)
+    rr = [A.take(ro[i], r_pay[i].dtype, n) for i in range(len(r_pay))]
+    ss = [A.take(so[i], s_pay[i].dtype, n) for i in range(len(s_pay))]
+    return key, rr, ss
+
+
+def partition(key: torch.Tensor, cols=(), *, bit_lo: int = 0, bits: int = 8, passes: int = 0,
+              mode: str = "bits", rowid: bool = False):
+    """Stable radix partition. Returns (key', [cols'], rowid' or None, offsets[2^bits+1])."""
+    L = lib()
+    cols = list(cols)
+    n = key.numel()
+    dev = key.device
+    _check_cols([key, *cols], n, dev)
+    ok = torch.empty_like(key)
+    oc = [torch.empty_like(c) for c in cols]
+    orow = torch.empty(n, dtype=torch.int32, device=dev) if rowid else None
+    off = torch.empty((1 << bits) + 1, dtype=torch.int32, device=dev)
+    ci = (Col * max(1, len(cols)))(*[_col(t) for t in cols])
+    co = (ctypes.c_void_p * max(1, len(cols)))(*[t.data_ptr() if n else None for t in oc])
+    A = _TorchAllocator(dev)
+    rc = L.gj_partition(_col(key), ci, len(cols), n, bit_lo, bits, passes, DIGIT[mode],
+                        ok.data_ptr() if n else None, co,
+                        orow.data_ptr() if (rowid and n) else None, off.data_ptr(),
+                        ctypes.byref(A.struct), _stream(dev))
+    _raise(rc)
+    return ok, oc, orow, off
+
+
+def groupby(key: torch.Tensor, vals, aggs, *, algo: str = "auto", mat: str = "auto",
+            radix_bits: int = 0, lds_budget: int = 0):
+    """Grouped aggregation. `aggs` is a list of (column index, op) with op in
+    {"sum", "count", "min", "max"}. Returns (keys, [aggregate columns])."""
+    L = lib()
+    vals = list(vals)
+    n = key.numel()
+    dev = key.device
+    _check_cols([key, *vals], n, dev)
+    vp = (Col * max(1, len(vals)))(*[_col(t) for t in vals])
+    ag = (Agg * max(1, len(aggs)))(*[Agg(int(c), AGG_OP[op]) for c, op in aggs])
+    o = GroupByOpts(GB_ALGO[algo], MAT[mat], radix_bits, 0, 0.0, lds_budget)
+    ao = (ctypes.c_void_p * max(1, len(aggs)))()
+    out = GroupByOut(None, ao, 0)
+    A = _TorchAllocator(dev)
+    rc = L.gj_groupby(_col(key), vp, len(vals), n, ag, len(aggs), ctypes.byref(o),
+                      ctypes.byref(A.struct), _stream(dev), ctypes.byref(out))
+    _raise(rc)
+    g = out.n_groups
+    keys = A.take(out.key, key.dtype, g)
+    res = []
+    for i, (c, op) in enumerate(aggs):
+        dt = torch.int64 if op in ("sum", "count") else vals[c].dtype
+        res.append(A.take(ao[i], dt, g))
+    return keys, res
+
+
+def version() -> str:
+    return lib().gj_version().decode()

@@ -1,0 +1,192 @@
+// C ABI of libgj: argument checks, planning (bits, passes, materialization),
+// scratch management and dispatch to the kernel drivers.
+#include <string.h>
+
+#include <string>
+
+#include "internal.hpp"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string &msg) {
+    g_last_error = msg;
+    return code;
+}
+
+constexpr int64_t kMaxRows = 2147483647LL;
+
+int dtype_bytes(int32_t dt) { return dt == GJ_I32 ? 4 : (dt == GJ_I64 ? 8 : 0); }
+
+int ceil_log2(uint64_t x) {
+    int b = 0;
+    while ((1ull << b) < x) ++b;
+    return b;
+}
+
+void check_col(const gj_col &c, int64_t n, const char *what) {
+    gj::require(dtype_bytes(c.dtype) != 0, std::string(what) + ": dtype must be GJ_I32 or GJ_I64");
+    gj::require(n == 0 || c.data != nullptr, std::string(what) + ": null data");
+}
+
+void check_rel(const gj_rel *r, const char *what) {
+    gj::require(r != nullptr, std::string(what) + ": null relation");
+    gj::require(r->n_rows >= 0, std::string(what) + ": negative row count");
+    gj::require(r->n_rows <= kMaxRows, std::string(what) + ": more than 2^31-1 rows", GJ_EOVERFLOW);
+    gj::require(r->n_payloads >= 0 && r->n_payloads <= 8, std::string(what) + ": 0..8 payload columns");
+    gj::require(r->n_payloads == 0 || r->payloads != nullptr, std::string(what) + ": null payload array");
+    check_col(r->key, r->n_rows, what);
+    for (int i = 0; i < r->n_payloads; ++i) check_col(r->payloads[i], r->n_rows, what);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *gj_last_error(void) { return g_last_error.c_str(); }
+
+const char *gj_version(void) { return "gj 0.1 (gfx950)"; }
+
+int gj_partition(gj_col key, const gj_col *cols, int32_t n_cols, int64_t n_rows, int32_t bit_lo,
+                 int32_t bits, int32_t passes, int32_t mode, void *out_key, void *const *out_cols,
+                 void *out_rowid, int32_t *out_offsets, const gj_allocator *alloc, void *stream) {
+    try {
+        g_last_error.clear();
+        gj::require(n_rows >= 0, "negative row count");
+        gj::require(n_rows <= kMaxRows, "more than 2^31-1 rows", GJ_EOVERFLOW);
+        gj::require(n_cols >= 0 && n_cols <= 8, "0..8 columns");
+        gj::require(n_cols == 0 || (cols && out_cols), "null column arrays");
+        gj::require(bits >= 1 && bits <= 16, "bits must be 1..16");
+        gj::require(mode >= 0 && mode <= 2, "bad digit mode");
+        const int kb = dtype_bytes(key.dtype);
+        check_col(key, n_rows, "key");
+        gj::require(bit_lo >= 0 && bit_lo + bits <= 8 * kb, "digit bits outside the key");
+        gj::require(n_rows == 0 || out_key, "null output key");
+        if (passes == 0) passes = bits > 8 ? 2 : 1;
+        gj::require(passes == 1 || passes == 2, "passes must be 0, 1 or 2");
+        gj::require(bits <= 8 * passes, "at most 8 bits per pass");
+        gj::Ctx ctx(alloc, (hipStream_t)stream);
+        gj::PartCols pc;
+        pc.n = n_cols;
+        for (int i = 0; i < n_cols; ++i) {
+            check_col(cols[i], n_rows, "column");
+            gj::require(n_rows == 0 || out_cols[i], "null output column");
+            pc.in[i] = cols[i].data;
+            pc.out[i] = out_cols[i];
+            pc.width[i] = dtype_bytes(cols[i].dtype);
+        }
+        pc.gen_rowid = out_rowid != nullptr;
+        pc.rowid_out = out_rowid;
+        uint32_t *poff = out_offsets ? reinterpret_cast<uint32_t *>(out_offsets)
+                                     : ctx.scratch_n<uint32_t>(((size_t)1 << bits) + 1);
+        gj::partition_run(ctx, kb, key.data, out_key, pc, (uint32_t)n_rows, bit_lo, bits, passes, mode, poff);
+        return GJ_OK;
+    } catch (const gj::Error &e) {
+        return fail(e.code, e.what());
+    } catch (const std::exception &e) {
+        return fail(GJ_EHIP, e.what());
+    }
+}
+
+int gj_join(const gj_rel *R, const gj_rel *S, const gj_join_opts *opts, const gj_allocator *alloc,
+            void *stream, gj_join_out *out) {
+    try {
+        g_last_error.clear();
+        gj::require(out != nullptr, "null output");
+        check_rel(R, "R");
+        check_rel(S, "S");
+        gj::require(R->key.dtype == S->key.dtype, "R.key and S.key dtypes differ");
+        gj::require(R->n_payloads == 0 || out->r_payloads, "null r_payloads array");
+        gj::require(S->n_payloads == 0 || out->s_payloads, "null s_payloads array");
+        gj_join_opts o{};
+        if (opts) o = *opts;
+        gj::require(o.mat >= 0 && o.mat <= 2, "bad materialization");
+        gj::require(o.passes >= 0 && o.passes <= 2, "passes must be 0, 1 or 2");
+        gj::require(o.radix_bits >= 0 && o.radix_bits <= 16, "radix_bits must be 0..16");
+        gj::require(o.block_size == 0 || o.block_size == gj::kBlock, "block_size must be 0 or 256");
+        gj::require(o.lds_budget == 0 || (o.lds_budget >= 64 && o.lds_budget <= 4096), "lds_budget must be 64..4096");
+        gj::require(o.flags == 0, "flags must be 0");
+
+        out->n_rows = 0;
+        out->key = nullptr;
+        for (int i = 0; i < R->n_payloads; ++i) out->r_payloads[i] = nullptr;
+        for (int i = 0; i < S->n_payloads; ++i) out->s_payloads[i] = nullptr;
+        if (R->n_rows == 0 || S->n_rows == 0) return GJ_OK;
+
+        const int kb = dtype_bytes(R->key.dtype);
+        const bool gfur = (o.mat == GJ_MAT_GFUR);
+        const int r_block = o.lds_budget ? o.lds_budget : 4096;
+        // Partitions of about r_block/2 R rows on average leave room for variance.
+        int bits = o.radix_bits;
+        if (bits == 0) {
+            const uint64_t target = (uint64_t)std::max(1, r_block / 2);
+            bits = ceil_log2(((uint64_t)R->n_rows + target - 1) / target);
+            bits = std::min(16, std::max(1, bits));
+        }
+        int passes = o.passes ? o.passes : (bits > 8 ? 2 : 1);
+        gj::require(bits <= 8 * passes, "at most 8 bits per pass");
+        if (passes == 2 && bits < 2) passes = 1;
+
+        gj::Ctx ctx(alloc, (hipStream_t)stream);
+        gj::JoinSide side[2];
+        const gj_rel *rel[2] = {R, S};
+        for (int t = 0; t < 2; ++t) {
+            const gj_rel *X = rel[t];
+            const uint32_t n = (uint32_t)X->n_rows;
+            gj::PartCols pc;
+            void *kout = ctx.scratch((size_t)n * kb);
+            gj::JoinSide &js = side[t];
+            js.key = kout;
+            js.n_pay = X->n_payloads;
+            for (int i = 0; i < X->n_payloads; ++i) js.width[i] = dtype_bytes(X->payloads[i].dtype);
+            if (!gfur) {
+                pc.n = X->n_payloads;
+                for (int i = 0; i < X->n_payloads; ++i) {
+                    pc.in[i] = X->payloads[i].data;
+                    pc.width[i] = js.width[i];
+                    pc.out[i] = ctx.scratch((size_t)n * js.width[i]);
+                    js.pay[i] = pc.out[i];
+                }
+                js.rowid = nullptr;
+            } else {
+                pc.n = 0;
+                pc.gen_rowid = true;
+                pc.rowid_out = ctx.scratch((size_t)n * 4);
+                for (int i = 0; i < X->n_payloads; ++i) js.pay[i] = X->payloads[i].data;
+                js.rowid = static_cast<const int32_t *>(pc.rowid_out);
+            }
+            uint32_t *poff = ctx.scratch_n<uint32_t>(((size_t)1 << bits) + 1);
+            js.poff = poff;
+            gj::partition_run(ctx, kb, X->key.data, kout, pc, n, 0, bits, passes, gj::kDigitBits, poff);
+        }
+        gj::JoinOut jo{};
+        const int64_t T = gj::join_partitioned(ctx, kb, side[0], side[1], bits, r_block, gfur, &jo);
+        out->n_rows = T;
+        if (T > 0) {
+            out->key = jo.key;
+            for (int i = 0; i < R->n_payloads; ++i) out->r_payloads[i] = jo.r[i];
+            for (int i = 0; i < S->n_payloads; ++i) out->s_payloads[i] = jo.s[i];
+        }
+        ctx.commit();
+        return GJ_OK;
+    } catch (const gj::Error &e) {
+        if (out) {
+            out->n_rows = 0;
+            out->key = nullptr;
+        }
+        return fail(e.code, e.what());
+    } catch (const std::exception &e) {
+        return fail(GJ_EHIP, e.what());
+    }
+}
+
+int gj_groupby(gj_col key, const gj_col *vals, int32_t n_vals, int64_t n_rows, const gj_agg *aggs,
+               int32_t n_aggs, const gj_groupby_opts *opts, const gj_allocator *alloc, void *stream,
+               gj_groupby_out *out) {
+    (void)key; (void)vals; (void)n_vals; (void)n_rows; (void)aggs; (void)n_aggs; (void)opts;
+    (void)alloc; (void)stream; (void)out;
+    return fail(GJ_EUNSUPPORTED, "group-by is not built yet");
+}
+
+}  // extern "C"

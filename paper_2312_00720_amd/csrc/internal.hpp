@@ -1,0 +1,143 @@
+// Host-side internals of libgj: error model, scratch and output memory, and
+// the launchers each kernel file exports to the C ABI layer.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/gj.h"
+#include "common.hpp"
+
+namespace gj {
+
+struct Error : std::runtime_error {
+    int code;
+    Error(int c, const std::string &m) : std::runtime_error(m), code(c) {}
+};
+
+#define GJ_HIP(call)                                                                         \
+    do {                                                                                     \
+        hipError_t e_ = (call);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            throw ::gj::Error(GJ_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+#define GJ_LAUNCHED(name)                                                                   \
+    do {                                                                                    \
+        hipError_t e_ = hipGetLastError();                                                  \
+        if (e_ != hipSuccess)                                                               \
+            throw ::gj::Error(GJ_EHIP, std::string("launch ") + name + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+inline void require(bool ok, const std::string &msg, int code = GJ_EINVAL) {
+    if (!ok) throw Error(code, msg);
+}
+
+// Memory for one C-ABI call. Scratch is released at the end of the call;
+// outputs are released only if the call fails.
+class Ctx {
+  public:
+    Ctx(const gj_allocator *a, hipStream_t s) : alloc_(a), stream(s) {}
+    ~Ctx() {
+        for (void *p : scratch_) release(p);
+        if (!committed_)
+            for (void *p : outputs_) release(p);
+    }
+    void *scratch(size_t bytes) {
+        void *p = get(bytes);
+        scratch_.push_back(p);
+        return p;
+    }
+    template <typename T>
+    T *scratch_n(size_t n) { return static_cast<T *>(scratch(n * sizeof(T))); }
+    void *output(size_t bytes) {
+        void *p = get(bytes);
+        outputs_.push_back(p);
+        return p;
+    }
+    void commit() { committed_ = true; }
+    const gj_allocator *alloc_;
+    hipStream_t stream;
+
+  private:
+    void *get(size_t bytes) {
+        if (bytes == 0) bytes = 256;
+        bytes = (bytes + 255) & ~size_t(255);
+        void *p = nullptr;
+        if (alloc_ && alloc_->alloc) {
+            p = alloc_->alloc(bytes, alloc_->ctx);
+        } else {
+            if (hipMallocAsync(&p, bytes, stream) != hipSuccess) p = nullptr;
+        }
+        if (!p) throw Error(GJ_ENOMEM, "allocation of " + std::to_string(bytes) + " bytes failed");
+        return p;
+    }
+    void release(void *p) {
+        if (!p) return;
+        if (alloc_ && alloc_->alloc) {
+            if (alloc_->free) alloc_->free(p, alloc_->ctx);
+        } else {
+            (void)hipFreeAsync(p, stream);
+        }
+    }
+    std::vector<void *> scratch_, outputs_;
+    bool committed_ = false;
+};
+
+template <typename T>
+inline T read_back(const T *dev, hipStream_t s) {
+    T v{};
+    GJ_HIP(hipMemcpyAsync(&v, dev, sizeof(T), hipMemcpyDeviceToHost, s));
+    GJ_HIP(hipStreamSynchronize(s));
+    return v;
+}
+
+// ---- scan.hip ---------------------------------------------------------------------
+// Exclusive prefix sum of n elements (in == out allowed). If total != nullptr the
+// grand total is written there (device). Scratch comes from ctx.
+void scan_exclusive_u32(Ctx &ctx, const uint32_t *in, uint32_t *out, uint64_t n, uint32_t *total);
+void scan_exclusive_u64(Ctx &ctx, const uint64_t *in, uint64_t *out, uint64_t n, uint64_t *total);
+void fill_u32(hipStream_t s, uint32_t *p, uint32_t v, uint64_t n);
+void fill_u64(hipStream_t s, uint64_t *p, uint64_t v, uint64_t n);
+
+// ---- partition.hip ------------------------------------------------------------------
+struct PartCols {
+    int n = 0;                   // payload columns moved with the key
+    const void *in[kMaxCols];
+    void *out[kMaxCols];
+    int width[kMaxCols];     // 4 or 8 bytes
+    bool gen_rowid = false;      // append an int32 row-id column (output only, slot n)
+    void *rowid_out = nullptr;
+};
+
+// Stable radix partition of n rows on digit bits [bit_lo, bit_lo + bits) of the
+// digit source `mode`, in `passes` MSD passes. Writes 2^bits + 1 uint32 offsets to
+// poff (device). n == 0 is allowed.
+void partition_run(Ctx &ctx, int key_bytes, const void *key_in, void *key_out, const PartCols &cols,
+                   uint32_t n, int bit_lo, int bits, int passes, int mode, uint32_t *poff);
+
+// ---- join.hip -------------------------------------------------------------------------
+struct JoinSide {
+    const void *key;          // partitioned keys
+    const void *pay[8];       // GFTR: partitioned payload columns; GFUR: original columns
+    int width[8];
+    int n_pay;
+    const int32_t *rowid;     // GFUR: partitioned row ids; GFTR: nullptr
+    const uint32_t *poff;     // partition offsets (2^bits + 1)
+};
+struct JoinOut {
+    void *key;
+    void *r[8];
+    void *s[8];
+};
+// Runs work-unit generation, the count pass and, after sizing, the write pass on
+// partitioned R and S. Output columns are allocated through ctx.output() with the
+// key width and the payload widths of R and S. Returns the number of output rows.
+int64_t join_partitioned(Ctx &ctx, int key_bytes, const JoinSide &R, const JoinSide &S, int bits,
+                         int r_block, bool gfur, JoinOut *out);
+
+}  // namespace gj

@@ -1,0 +1,289 @@
+// Match finding and materialization of the partitioned hash join
+// (Section 4.1.4, steps 2 and 3).
+//
+// After partitioning, partition p of R and of S are contiguous ranges. Work
+// units cut a partition pair into (R block of at most r_block rows) x (S piece
+// of at most kSPiece rows), so that an oversized or skewed partition is spread
+// over many workgroups (the load balancing of Sections 3.1.2 and 4.1.4). Per
+// unit, a workgroup builds a bucketed hash table on the R block in LDS and
+// streams the S piece through it.
+//
+// The output size is unknown (Section 2.2), so a count pass runs first: every
+// wave counts its matches; an exclusive scan over (unit, wave) gives every wave
+// its output range, and the write pass enumerates the same matches again and
+// writes (key, R payloads, S payloads) contiguously. GFTR reads payloads from
+// the partitioned copies at partition-local positions (clustered); GFUR reads
+// the original columns through the partitioned row ids (unclustered).
+//
+// Chains of the LDS table list R rows in input order, so an S row with several
+// matches emits them in R's input order, and the output is the same on every
+// run.
+#include "internal.hpp"
+
+namespace gj {
+namespace {
+
+constexpr uint32_t kMaxBuild = 4096;  // R rows per build block (LDS capacity)
+constexpr uint32_t kSPiece = 8192;    // S rows per work unit
+constexpr uint32_t kMaxChainSort = 32;
+
+struct JoinArgs {
+    const void *rkey;
+    const void *skey;
+    const uint32_t *rpo;
+    const uint32_t *spo;
+    uint32_t np;
+    const uint32_t *ubase;  // exclusive prefix of units per partition
+    uint32_t rc;            // R rows per build block
+    int skip_bits;          // partition bits, excluded from the bucket hash
+    uint64_t *wcnt;         // count pass: matches per (unit, wave)
+    const uint64_t *woff;   // write pass: output offset per (unit, wave)
+    uint64_t t_rows;        // write pass: output rows; every store is checked against it
+    void *tkey;
+    int nr, ns;
+    const void *rp[8];
+    int rw[8];
+    void *tr[8];
+    const void *sp[8];
+    int sw[8];
+    void *ts[8];
+    const int32_t *rrow;  // GFUR: partitioned row ids of R
+    const int32_t *srow;  // GFUR: partitioned row ids of S
+};
+
+__global__ void k_unit_count(const uint32_t *__restrict__ rpo, const uint32_t *__restrict__ spo,
+                             uint32_t np, uint32_t rc, uint32_t *__restrict__ ucnt) {
+    for (uint32_t p = blockIdx.x * blockDim.x + threadIdx.x; p < np; p += gridDim.x * blockDim.x) {
+        const uint32_t nr = rpo[p + 1] - rpo[p], ns = spo[p + 1] - spo[p];
+        ucnt[p] = (nr && ns) ? ceil_div_u32(nr, rc) * ceil_div_u32(ns, kSPiece) : 0u;
+    }
+}
+
+__device__ __forceinline__ void copy_val(void *dst, int dw, uint64_t di, const void *src, uint64_t si) {
+    if (dw == 4) static_cast<uint32_t *>(dst)[di] = static_cast<const uint32_t *>(src)[si];
+    else static_cast<uint64_t *>(dst)[di] = static_cast<const uint64_t *>(src)[si];
+}
+
+template <typename K, bool WRITE>
+__global__ __launch_bounds__(kBlock) void k_join(JoinArgs a) {
+    __shared__ K s_rkey[kMaxBuild];
+    __shared__ uint32_t s_b[kMaxBuild + 1];   // bucket boundaries
+    __shared__ uint16_t s_entry[kMaxBuild];  // R block rows, grouped by bucket
+    __shared__ uint32_t s_tmp[kWaves];
+    __shared__ uint32_t s_unit[6];
+    __shared__ int s_long;
+
+    const int tid = threadIdx.x, w = tid / kWave, lane = lane_id();
+    const uint32_t u = blockIdx.x;
+    if (tid == 0) {
+        uint32_t lo = 0, hi = a.np;  // ubase[lo] <= u < ubase[hi] (ubase[np] = units)
+        while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (a.ubase[mid] <= u) lo = mid;
+            else hi = mid;
+        }
+        const uint32_t p = lo;
+        const uint32_t nr = a.rpo[p + 1] - a.rpo[p], ns = a.spo[p + 1] - a.spo[p];
+        const uint32_t nsb = ceil_div_u32(ns, kSPiece);
+        const uint32_t local = u - a.ubase[p];
+        const uint32_t ra = local / nsb, sb = local % nsb;
+        s_unit[0] = a.rpo[p] + ra * a.rc;
+        s_unit[1] = min(a.rc, nr - ra * a.rc);
+        s_unit[2] = a.spo[p] + sb * kSPiece;
+        s_unit[3] = min(kSPiece, ns - sb * kSPiece);
+        s_long = 0;
+    }
+    __syncthreads();
+    const uint32_t r0 = s_unit[0], rn = s_unit[1], s0 = s_unit[2], sn = s_unit[3];
+    int log2nb = 0;
+    while ((1u << log2nb) < rn) ++log2nb;
+    const uint32_t nb = 1u << log2nb;
+
+    // ---- build: bucket counts, scan, placement, per-bucket order by row ----
+    const K *__restrict__ rkey = static_cast<const K *>(a.rkey);
+    for (uint32_t i = tid; i < rn; i += kBlock) s_rkey[i] = rkey[r0 + i];
+    for (uint32_t b = tid; b <= nb; b += kBlock) s_b[b] = 0;
+    __syncthreads();
+    for (uint32_t i = tid; i < rn; i += kBlock) atomicAdd(&s_b[bucket_of<K>(s_rkey[i], a.skip_bits, log2nb)], 1u);
+    __syncthreads();
+    {
+        // inclusive scan of the nb counts: s_b[b] = end of bucket b
+        constexpr int per = (kMaxBuild + kBlock - 1) / kBlock;
+        const uint32_t first = tid * per;
+        uint32_t v[per];
+        uint32_t sum = 0;
+#pragma unroll
+        for (int k = 0; k < per; ++k) {
+            v[k] = (first + k < nb) ? s_b[first + k] : 0u;
+            sum += v[k];
+        }
+        uint32_t run = block_exclusive_sum<uint32_t>(sum, s_tmp, (uint32_t *)nullptr);
+#pragma unroll
+        for (int k = 0; k < per; ++k) {
+            run += v[k];
+            if (first + k < nb) s_b[first + k] = run;
+        }
+        if (tid == 0) s_b[nb] = rn;
+    }
+    __syncthreads();
+    // placement from the end of each bucket; afterwards s_b[b] = start of bucket b
+    for (uint32_t i = tid; i < rn; i += kBlock) {
+        const uint32_t b = bucket_of<K>(s_rkey[i], a.skip_bits, log2nb);
+        const uint32_t slot = atomicSub(&s_b[b], 1u) - 1u;
+        s_entry[slot] = (uint16_t)i;
+    }
+    __syncthreads();
+    for (uint32_t b = tid; b < nb; b += kBlock) {
+        const uint32_t lo = s_b[b], hi = s_b[b + 1];
+        if (hi - lo > kMaxChainSort) {
+            s_long = 1;
+        } else {
+            for (uint32_t x = lo + 1; x < hi; ++x) {
+                const uint16_t e = s_entry[x];
+                uint32_t y = x;
+                while (y > lo && s_entry[y - 1] > e) {
+                    s_entry[y] = s_entry[y - 1];
+                    --y;
+                }
+                s_entry[y] = e;
+            }
+        }
+    }
+    __syncthreads();
+    if (s_long) {
+        // Rare (heavy duplicate keys): one wave places all rows again in row
+        // order, ranking equal buckets within a round by ballot.
+        if (w == 0) {
+            for (uint32_t base = 0; base < rn; base += kWave) {
+                const uint32_t i = base + lane;
+                const bool valid = i < rn;
+                const uint32_t b = valid ? bucket_of<K>(s_rkey[i], a.skip_bits, log2nb) : 0u;
+                const uint64_t peers = match_peers(b, log2nb, valid);
+                if (valid) {
+                    const uint32_t rk = rank_below(peers);
+                    const uint32_t st = s_b[b];
+                    if (rk == 0) s_b[b] = st + (uint32_t)__popcll(peers);
+                    s_entry[st + rk] = (uint16_t)i;
+                }
+            }
+            // s_b[b] now holds the end of bucket b: shift right by one, top down
+            for (int c = (int)((nb + kWave - 1) / kWave) - 1; c >= 0; --c) {
+                const uint32_t b = (uint32_t)c * kWave + lane;
+                const uint32_t v = b < nb ? s_b[b] : 0u;
+                if (b < nb) s_b[b + 1] = v;
+            }
+            if (lane == 0) s_b[0] = 0;
+        }
+        __syncthreads();
+    }
+
+    // ---- probe: each wave streams a contiguous quarter of the S piece ----
+    const K *__restrict__ skey = static_cast<const K *>(a.skey);
+    const uint32_t q = ceil_div_u32(sn, kWaves);
+    const uint32_t ws = min(sn, w * q), we = min(sn, ws + q);
+    if constexpr (!WRITE) {
+        uint32_t cnt = 0;
+        for (uint32_t base = ws; base < we; base += kWave) {
+            const uint32_t i = base + lane;
+            if (i < we) {
+                const K key = skey[s0 + i];
+                const uint32_t b = bucket_of<K>(key, a.skip_bits, log2nb);
+                for (uint32_t e = s_b[b], end = s_b[b + 1]; e < end; ++e) cnt += (s_rkey[s_entry[e]] == key);
+            }
+        }
+        const uint64_t tot = wave_sum<uint64_t>((uint64_t)cnt);
+        if (lane == 0) a.wcnt[(uint64_t)u * kWaves + w] = tot;
+    } else {
+        uint64_t outpos = a.woff[(uint64_t)u * kWaves + w];
+        K *__restrict__ tkey = static_cast<K *>(a.tkey);
+        for (uint32_t base = ws; base < we; base += kWave) {
+            const uint32_t i = base + lane;
+            const bool valid = i < we;
+            K key = K(0);
+            uint32_t b = 0, c = 0;
+            if (valid) {
+                key = skey[s0 + i];
+                b = bucket_of<K>(key, a.skip_bits, log2nb);
+                for (uint32_t e = s_b[b], end = s_b[b + 1]; e < end; ++e) c += (s_rkey[s_entry[e]] == key);
+            }
+            const uint32_t incl = wave_inclusive_sum<uint32_t>(c);
+            const uint32_t tot = __shfl(incl, kWave - 1, kWave);
+            if (c) {
+                uint64_t pos = outpos + incl - c;
+                const uint64_t srow = a.srow ? (uint64_t)a.srow[s0 + i] : (uint64_t)(s0 + i);
+                for (uint32_t e = s_b[b], end = s_b[b + 1]; e < end; ++e) {
+                    const uint32_t ri = s_entry[e];
+                    if (s_rkey[ri] != key || pos >= a.t_rows) continue;
+                    const uint64_t rrow = a.rrow ? (uint64_t)a.rrow[r0 + ri] : (uint64_t)(r0 + ri);
+                    tkey[pos] = key;
+                    for (int j = 0; j < a.nr; ++j) copy_val(a.tr[j], a.rw[j], pos, a.rp[j], rrow);
+                    for (int j = 0; j < a.ns; ++j) copy_val(a.ts[j], a.sw[j], pos, a.sp[j], srow);
+                    ++pos;
+                }
+            }
+            outpos += tot;
+        }
+    }
+}
+
+}  // namespace
+
+int64_t join_partitioned(Ctx &ctx, int key_bytes, const JoinSide &R, const JoinSide &S, int bits,
+                         int r_block, bool gfur, JoinOut *out) {
+    hipStream_t s = ctx.stream;
+    require(r_block >= 64 && r_block <= (int)kMaxBuild, "R build block must be 64..4096 rows");
+    const uint32_t np = 1u << bits;
+    uint32_t *ucnt = ctx.scratch_n<uint32_t>(np + 1);
+    hipLaunchKernelGGL(k_unit_count, dim3(std::min<uint32_t>((np + 255) / 256, 1024)), dim3(256), 0, s,
+                       R.poff, S.poff, np, (uint32_t)r_block, ucnt);
+    GJ_LAUNCHED("k_unit_count");
+    scan_exclusive_u32(ctx, ucnt, ucnt, np, ucnt + np);
+    const uint32_t nunits = read_back(ucnt + np, s);
+    if (nunits == 0) return 0;
+
+    JoinArgs a{};
+    a.rkey = R.key;
+    a.skey = S.key;
+    a.rpo = R.poff;
+    a.spo = S.poff;
+    a.np = np;
+    a.ubase = ucnt;
+    a.rc = (uint32_t)r_block;
+    a.skip_bits = bits;
+    const uint64_t nw = (uint64_t)nunits * kWaves;
+    uint64_t *wcnt = ctx.scratch_n<uint64_t>(nw + 1);
+    a.wcnt = wcnt;
+    if (key_bytes == 4) hipLaunchKernelGGL((k_join<int32_t, false>), dim3(nunits), dim3(kBlock), 0, s, a);
+    else hipLaunchKernelGGL((k_join<int64_t, false>), dim3(nunits), dim3(kBlock), 0, s, a);
+    GJ_LAUNCHED("k_join count");
+    scan_exclusive_u64(ctx, wcnt, wcnt, nw, wcnt + nw);
+    const uint64_t T = read_back(wcnt + nw, s);
+    if (T == 0) return 0;
+
+    out->key = ctx.output(T * (uint64_t)key_bytes);
+    for (int j = 0; j < R.n_pay; ++j) out->r[j] = ctx.output(T * (uint64_t)R.width[j]);
+    for (int j = 0; j < S.n_pay; ++j) out->s[j] = ctx.output(T * (uint64_t)S.width[j]);
+    a.woff = wcnt;
+    a.t_rows = T;
+    a.tkey = out->key;
+    a.nr = R.n_pay;
+    a.ns = S.n_pay;
+    for (int j = 0; j < R.n_pay; ++j) {
+        a.rp[j] = R.pay[j];
+        a.rw[j] = R.width[j];
+        a.tr[j] = out->r[j];
+    }
+    for (int j = 0; j < S.n_pay; ++j) {
+        a.sp[j] = S.pay[j];
+        a.sw[j] = S.width[j];
+        a.ts[j] = out->s[j];
+    }
+    a.rrow = gfur ? R.rowid : nullptr;
+    a.srow = gfur ? S.rowid : nullptr;
+    if (key_bytes == 4) hipLaunchKernelGGL((k_join<int32_t, true>), dim3(nunits), dim3(kBlock), 0, s, a);
+    else hipLaunchKernelGGL((k_join<int64_t, true>), dim3(nunits), dim3(kBlock), 0, s, a);
+    GJ_LAUNCHED("k_join write");
+    return (int64_t)T;
+}
+
+}  // namespace gj

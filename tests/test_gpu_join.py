@@ -1,0 +1,116 @@
+"""GPU parity: the partitioned hash join (Section 4.1.4) against the oracle.
+
+Join outputs are compared as multisets: both sides are put in canonical row
+order and compared element by element (exact; integer data)."""
+import numpy as np
+import pytest
+
+import datagen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+
+def gpu_join(d, mat, **kw):
+    import paper_2312_00720_amd as gj
+    from gpu_util import dev, host, say
+    say(f"join |R|={len(d['r_key'])} |S|={len(d['s_key'])} key={d['r_key'].dtype} mat={mat} {kw}")
+    k, r, s = gj.join(dev(d["r_key"]), [dev(x) for x in d["r_pay"]], dev(d["s_key"]),
+                      [dev(x) for x in d["s_pay"]], mat=mat, **kw)
+    return [host(k)] + [host(x) for x in r] + [host(x) for x in s]
+
+
+def check(d, mat, **kw):
+    from gpu_util import canon
+    got = gpu_join(d, mat, **kw)
+    want = oracle.join(d["r_key"], d["r_pay"], d["s_key"], d["s_pay"])
+    assert len(got[0]) == len(want[0])
+    for a, b in zip(canon(got), canon(want)):
+        np.testing.assert_array_equal(a, b)
+    return got
+
+
+@pytest.mark.parametrize("mat", ["gftr", "gfur"])
+def test_config_small_pkfk(mat):
+    """|R| = 2^16 (keys a permutation), |S| = 2^20 uniform FKs, one payload each."""
+    d = datagen.pk_fk_join(1 << 16, 1 << 20, 1, 1, seed=datagen.seed_for(0))
+    got = check(d, mat)
+    assert len(got[0]) == 1 << 20
+
+
+@pytest.mark.parametrize("mat", ["gftr", "gfur"])
+@pytest.mark.parametrize("kb", [4, 8])
+@pytest.mark.parametrize("mr,alpha", [(1.0, 0.0), (0.5, 0.0), (1.0, 1.0), (0.5, 0.5)])
+def test_pkfk_variants(mat, kb, mr, alpha):
+    d = datagen.pk_fk_join(20000, 70001, 2, 3, seed=datagen.seed_for(1, 7), alpha=alpha,
+                           match_ratio=mr, key_bytes=kb)
+    got = check(d, mat)
+    assert len(got[0]) == d["n_match"]
+
+
+@pytest.mark.parametrize("mat", ["gftr", "gfur"])
+def test_many_to_many(mat):
+    d = datagen.many_to_many_join(30000, 40000, 5000, 2, 2, seed=21)
+    check(d, mat)
+
+
+def test_many_to_many_long_chains():
+    """Keys with hundreds of duplicates in R force the ordered re-placement path."""
+    d = datagen.many_to_many_join(6000, 3000, 8, 1, 1, seed=22)
+    check(d, "gftr", lds_budget=4096)
+    check(d, "gfur", lds_budget=256)
+
+
+@pytest.mark.parametrize("kw", [dict(radix_bits=1), dict(radix_bits=9, passes=2),
+                                dict(radix_bits=16, passes=2), dict(lds_budget=64),
+                                dict(lds_budget=100, radix_bits=3)])
+def test_options_do_not_change_results(kw):
+    d = datagen.pk_fk_join(5000, 23456, 1, 2, seed=31, match_ratio=0.7)
+    check(d, "gftr", **kw)
+
+
+def test_edge_cases():
+    g = datagen.rng(0)
+    empty = np.zeros(0, np.int32)
+    one = np.array([7], np.int32)
+    pay = lambda n: [g.integers(-5, 5, size=n).astype(np.int32)]
+    for rk, sk in [(empty, empty), (one, empty), (empty, one), (one, one),
+                   (one, np.array([8], np.int32)),
+                   (np.array([-2**31, 2**31 - 1, 0, -1], np.int32),
+                    np.array([2**31 - 1, -1, -2**31, 5, -2**31], np.int32))]:
+        d = {"r_key": rk, "r_pay": pay(len(rk)), "s_key": sk, "s_pay": pay(len(sk))}
+        for mat in ("gftr", "gfur"):
+            check(d, mat)
+
+
+def test_no_payload_columns():
+    d = datagen.pk_fk_join(3000, 9000, 0, 0, seed=4)
+    check(d, "gftr")
+
+
+def test_eight_byte_payloads():
+    g = datagen.rng(5)
+    d = datagen.pk_fk_join(4000, 10000, 0, 0, seed=6)
+    d["r_pay"] = [g.integers(-2**62, 2**62, size=4000, dtype=np.int64)]
+    d["s_pay"] = [g.integers(-2**62, 2**62, size=10000, dtype=np.int64),
+                  g.integers(-9, 9, size=10000).astype(np.int32)]
+    for mat in ("gftr", "gfur"):
+        check(d, mat)
+
+
+def test_deterministic_output_order():
+    d = datagen.many_to_many_join(20000, 20000, 3000, 1, 1, seed=41)
+    a = gpu_join(d, "gftr")
+    b = gpu_join(d, "gftr")
+    for x, y in zip(a, b):
+        np.testing.assert_array_equal(x, y)
+
+
+def test_bad_arguments_raise():
+    import torch
+    import paper_2312_00720_amd as gj
+    r = torch.zeros(10, dtype=torch.int32, device="cuda")
+    s = torch.zeros(10, dtype=torch.int64, device="cuda")
+    with pytest.raises(gj.GJError) as e:
+        gj.join(r, [], s, [])
+    assert e.value.code == -1
