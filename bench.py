@@ -1,0 +1,159 @@
+#!/usr/bin/env python3
+"""Benchmark of the join hot path on one MI355X.
+
+Workload (default): the large PK-FK join of the paper's wide-join experiments
+(Section 5.1): |R| = 2^27 (keys a random permutation of 0..2^27-1), |S| = 2^28
+foreign keys uniform over R's keys (match ratio 100%), 4 int32 payload columns
+per side, GFTR materialization. One step = one gj_join call: histogram, scan and
+stable scatter of both relations (two passes), work units, LDS hash build and
+probe (count pass), output sizing, and the write pass that materializes
+(key, 4 R payloads, 4 S payloads) for all 2^28 output rows. Output allocation
+is inside the step (torch's caching allocator, warm after the first step).
+
+Prints one JSON line. `value` is materialized join tuples/s (|T| / time). The
+roofline object is for the kernel with the largest total time in the timed
+region: its algorithmic bytes (compulsory reads + writes, computed by the
+library per launch) over its HIP-event-measured time on the library's stream.
+The CPU baseline is the plain oracle (single thread) on a smaller sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+
+
+def log(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def cpu_baseline(n_r_log2: int = 22, payloads: int = 4) -> dict:
+    import datagen
+    import oracle
+    oracle.build(force=False)
+    n_r, n_s = 1 << n_r_log2, 1 << (n_r_log2 + 1)
+    d = datagen.pk_fk_join(n_r, n_s, payloads, payloads, seed=datagen.seed_for(1, 500))
+    t0 = time.perf_counter()
+    cols = oracle.join(d["r_key"], d["r_pay"], d["s_key"], d["s_pay"])
+    dt = time.perf_counter() - t0
+    return {"value": len(cols[0]) / dt, "unit": "tuples/s", "cores": 1, "kind": "oracle",
+            "sample": f"PK-FK join |R|=2^{n_r_log2}, |S|=2^{n_r_log2 + 1}, {payloads}+{payloads} int32 "
+                      f"payloads, uniform FK, mr=100%; {dt:.1f} s single-threaded (qsort + binary search)"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--mat", default="gftr", choices=["gftr", "gfur"])
+    ap.add_argument("--r-log2", type=int, default=27)
+    ap.add_argument("--s-log2", type=int, default=28)
+    ap.add_argument("--payloads", type=int, default=4)
+    ap.add_argument("--key-bytes", type=int, default=4, choices=[4, 8])
+    ap.add_argument("--alpha", type=float, default=0.0)
+    ap.add_argument("--match-ratio", type=float, default=1.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the join and group-by "
+              "run on a single device and no multi-GPU path is built.", file=sys.stderr)
+        return 2
+
+    import torch
+    import datagen
+    import datagen.device as dd
+    import paper_2312_00720_amd as gj
+
+    n_r, n_s, c = 1 << args.r_log2, 1 << args.s_log2, args.payloads
+    log(f"generating |R|=2^{args.r_log2} |S|=2^{args.s_log2} payloads={c} key_bytes={args.key_bytes}")
+    d = dd.pk_fk_join(n_r, n_s, c, c, seed=datagen.seed_for(1), alpha=args.alpha,
+                      match_ratio=args.match_ratio, key_bytes=args.key_bytes)
+    torch.cuda.synchronize()
+    rk, rp, sk, sp = d["r_key"], d["r_pay"], d["s_key"], d["s_pay"]
+
+    def step():
+        return gj.join(rk, rp, sk, sp, mat=args.mat)
+
+    n_out = None
+    for i in range(args.warmup):
+        out = step()
+        n_out = out[0].numel()
+        del out
+        log(f"warmup {i + 1}/{args.warmup} done (|T| = {n_out})")
+    torch.cuda.synchronize()
+
+    gj.profile_start()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        out = step()
+        n_out = out[0].numel()
+        del out
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    stats = gj.profile_stop()
+    log(f"timed {args.steps} steps")
+
+    ms = (t1 - t0) / args.steps * 1e3
+    value = n_out / (ms / 1e3)
+    kern = {k: dict(v, ms_per_step=v["total_ms"] / args.steps,
+                    gbs=(v["alg_bytes"] / (v["total_ms"] / 1e3) / 1e9) if v["total_ms"] > 0 else 0.0)
+            for k, v in stats.items()}
+    dom = max(kern, key=lambda k: kern[k]["total_ms"])
+    dk = kern[dom]
+    achieved = dk["gbs"]
+    alg_total = sum(v["alg_bytes"] for v in stats.values()) / args.steps
+    phases = {
+        "transform_ms": sum(kern[k]["ms_per_step"] for k in kern
+                            if k.startswith(("k_hist", "k_scatter", "k_scan", "k_chunk", "k_poff",
+                                             "k_fill", "k_set"))),
+        "match_ms": sum(kern[k]["ms_per_step"] for k in kern if k in ("k_unit_count", "k_join_count")),
+        "materialize_ms": kern.get("k_join_write", {}).get("ms_per_step", 0.0),
+    }
+    res = {
+        "metric": "materialized join tuples/s",
+        "value": value,
+        "unit": "tuples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32" if args.key_bytes == 4 else "int64",
+        "data": "synthetic",
+        "config": {"workload": f"PK-FK join |R|=2^{args.r_log2} |S|=2^{args.s_log2}, "
+                               f"{c}+{c} int32 payloads, {'int32' if args.key_bytes == 4 else 'int64'} keys, "
+                               f"FK {'uniform' if args.alpha == 0 else f'zipf {args.alpha}'}, "
+                               f"mr={args.match_ratio:g}, {args.mat.upper()}",
+                   "n_r": n_r, "n_s": n_s, "payloads_per_side": c, "mat": args.mat,
+                   "output_rows": n_out},
+        "paper_throughput_rows_per_s": (n_r + n_s) / (ms / 1e3),
+        "hbm_gbs_whole_step": alg_total / (ms / 1e3) / 1e9,
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "alg_bytes_per_launch": dk["alg_bytes"] / max(1, dk["launches"]),
+                     "avg_launch_ms": dk["total_ms"] / max(1, dk["launches"])},
+        "phases_ms": phases,
+        "kernels": {k: {"launches_per_step": v["launches"] / args.steps, "ms_per_step": v["ms_per_step"],
+                        "alg_gbs": v["gbs"]} for k, v in sorted(kern.items(), key=lambda x: -x[1]["total_ms"])},
+    }
+    if not args.no_cpu_baseline:
+        del d, rk, rp, sk, sp
+        log("timing the CPU oracle on a bounded sample")
+        res["cpu_baseline"] = cpu_baseline(payloads=c)
+    print(json.dumps(res), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

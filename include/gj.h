@@ -167,6 +167,24 @@ int gj_partition(gj_col key, const gj_col *cols, int32_t n_cols, int64_t n_rows,
                  void *out_key, void *const *out_cols, void *out_rowid, int32_t *out_offsets,
                  const gj_allocator *alloc, void *stream);
 
+/* Per-kernel timing of this thread's launches (for benchmarks and phase
+ * breakdowns). */
+typedef struct {
+    char name[48];     /* kernel name */
+    int64_t launches;  /* launches recorded */
+    double total_ms;   /* sum of event-measured durations on the launch stream */
+    double alg_bytes;  /* sum of algorithmic bytes: compulsory reads + writes */
+} gj_kernel_stat;
+
+/* Start recording: every later launch made by this thread is bracketed by two
+ * HIP events on its stream. Adds two event records per launch. */
+int gj_profile_start(void);
+
+/* Stop recording, wait for the recorded events, and write up to `cap` per-kernel
+ * aggregates to `stats` (host memory); *n_out receives the number of distinct
+ * kernels. Returns GJ_EHIP if an event could not be read. */
+int gj_profile_stop(gj_kernel_stat *stats, int32_t cap, int32_t *n_out);
+
 /* Thread-local text of the last error on this thread ("" if none). */
 const char *gj_last_error(void);
 

@@ -70,6 +70,11 @@ class GroupByOpts(ctypes.Structure):
                 ("lds_budget", ctypes.c_int32)]
 
 
+class KernelStat(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 48), ("launches", ctypes.c_int64),
+                ("total_ms", ctypes.c_double), ("alg_bytes", ctypes.c_double)]
+
+
 class GroupByOut(ctypes.Structure):
     _fields_ = [("key", ctypes.c_void_p), ("aggs", ctypes.POINTER(ctypes.c_void_p)),
                 ("n_groups", ctypes.c_int64)]
@@ -99,6 +104,10 @@ def lib() -> ctypes.CDLL:
             L.gj_groupby.argtypes = [Col, ctypes.POINTER(Col), i32, i64, ctypes.POINTER(Agg), i32,
                                      ctypes.POINTER(GroupByOpts), ctypes.POINTER(Allocator), vp,
                                      ctypes.POINTER(GroupByOut)]
+            L.gj_profile_start.restype = ctypes.c_int
+            L.gj_profile_start.argtypes = []
+            L.gj_profile_stop.restype = ctypes.c_int
+            L.gj_profile_stop.argtypes = [ctypes.POINTER(KernelStat), i32, ctypes.POINTER(i32)]
             L.gj_last_error.restype = ctypes.c_char_p
             L.gj_last_error.argtypes = []
             L.gj_version.restype = ctypes.c_char_p
@@ -242,6 +251,23 @@ def groupby(key: torch.Tensor, vals, aggs, *, algo: str = "auto", mat: str = "au
         dt = torch.int64 if op in ("sum", "count") else vals[c].dtype
         res.append(A.take(ao[i], dt, g))
     return keys, res
+
+
+def profile_start() -> None:
+    """Record HIP events around every later launch of this thread."""
+    _raise(lib().gj_profile_start())
+
+
+def profile_stop() -> dict:
+    """Stop recording; returns {kernel: {launches, total_ms, alg_bytes}}."""
+    L = lib()
+    cap = 128
+    buf = (KernelStat * cap)()
+    n = ctypes.c_int32(0)
+    _raise(L.gj_profile_stop(buf, cap, ctypes.byref(n)))
+    return {buf[i].name.decode(): {"launches": int(buf[i].launches), "total_ms": float(buf[i].total_ms),
+                                   "alg_bytes": float(buf[i].alg_bytes)}
+            for i in range(min(n.value, cap))}
 
 
 def version() -> str:

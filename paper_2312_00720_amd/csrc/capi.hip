@@ -138,6 +138,7 @@ int gj_join(const gj_rel *R, const gj_rel *S, const gj_join_opts *opts, const gj
             void *kout = ctx.scratch((size_t)n * kb);
             gj::JoinSide &js = side[t];
             js.key = kout;
+            js.rows = n;
             js.n_pay = X->n_payloads;
             for (int i = 0; i < X->n_payloads; ++i) js.width[i] = dtype_bytes(X->payloads[i].dtype);
             if (!gfur) {

@@ -37,6 +37,21 @@ inline void require(bool ok, const std::string &msg, int code = GJ_EINVAL) {
     if (!ok) throw Error(code, msg);
 }
 
+// ---- prof.hip: optional per-launch event timing ------------------------------------
+// When profiling is on for the calling thread, every launch made through GJ_LAUNCH
+// is bracketed by two HIP events on its stream and tagged with its algorithmic
+// byte count (the compulsory reads and writes of the method, no re-reads).
+void prof_before(const char *name, double alg_bytes, hipStream_t s);
+void prof_after(hipStream_t s);
+
+#define GJ_LAUNCH(name, alg_bytes, kernel, grid, block, shm, stream, ...)              \
+    do {                                                                                \
+        ::gj::prof_before(name, (double)(alg_bytes), stream);                           \
+        hipLaunchKernelGGL(kernel, grid, block, shm, stream, __VA_ARGS__);              \
+        GJ_LAUNCHED(name);                                                              \
+        ::gj::prof_after(stream);                                                       \
+    } while (0)
+
 // Memory for one C-ABI call. Scratch is released at the end of the call;
 // outputs are released only if the call fails.
 class Ctx {
@@ -128,6 +143,7 @@ struct JoinSide {
     int n_pay;
     const int32_t *rowid;     // GFUR: partitioned row ids; GFTR: nullptr
     const uint32_t *poff;     // partition offsets (2^bits + 1)
+    uint32_t rows;            // rows of the relation
 };
 struct JoinOut {
     void *key;

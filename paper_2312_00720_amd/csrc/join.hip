@@ -234,9 +234,8 @@ int64_t join_partitioned(Ctx &ctx, int key_bytes, const JoinSide &R, const JoinS
     require(r_block >= 64 && r_block <= (int)kMaxBuild, "R build block must be 64..4096 rows");
     const uint32_t np = 1u << bits;
     uint32_t *ucnt = ctx.scratch_n<uint32_t>(np + 1);
-    hipLaunchKernelGGL(k_unit_count, dim3(std::min<uint32_t>((np + 255) / 256, 1024)), dim3(256), 0, s,
-                       R.poff, S.poff, np, (uint32_t)r_block, ucnt);
-    GJ_LAUNCHED("k_unit_count");
+    GJ_LAUNCH("k_unit_count", 20.0 * np, k_unit_count, dim3(std::min<uint32_t>((np + 255) / 256, 1024)),
+              dim3(256), 0, s, R.poff, S.poff, np, (uint32_t)r_block, ucnt);
     scan_exclusive_u32(ctx, ucnt, ucnt, np, ucnt + np);
     const uint32_t nunits = read_back(ucnt + np, s);
     if (nunits == 0) return 0;
@@ -253,9 +252,12 @@ int64_t join_partitioned(Ctx &ctx, int key_bytes, const JoinSide &R, const JoinS
     const uint64_t nw = (uint64_t)nunits * kWaves;
     uint64_t *wcnt = ctx.scratch_n<uint64_t>(nw + 1);
     a.wcnt = wcnt;
-    if (key_bytes == 4) hipLaunchKernelGGL((k_join<int32_t, false>), dim3(nunits), dim3(kBlock), 0, s, a);
-    else hipLaunchKernelGGL((k_join<int64_t, false>), dim3(nunits), dim3(kBlock), 0, s, a);
-    GJ_LAUNCHED("k_join count");
+    const double nrows_r = R.rows, nrows_s = S.rows;
+    const double key_reads = (nrows_r + nrows_s) * key_bytes;
+    if (key_bytes == 4)
+        GJ_LAUNCH("k_join_count", key_reads, (k_join<int32_t, false>), dim3(nunits), dim3(kBlock), 0, s, a);
+    else
+        GJ_LAUNCH("k_join_count", key_reads, (k_join<int64_t, false>), dim3(nunits), dim3(kBlock), 0, s, a);
     scan_exclusive_u64(ctx, wcnt, wcnt, nw, wcnt + nw);
     const uint64_t T = read_back(wcnt + nw, s);
     if (T == 0) return 0;
@@ -280,9 +282,19 @@ int64_t join_partitioned(Ctx &ctx, int key_bytes, const JoinSide &R, const JoinS
     }
     a.rrow = gfur ? R.rowid : nullptr;
     a.srow = gfur ? S.rowid : nullptr;
-    if (key_bytes == 4) hipLaunchKernelGGL((k_join<int32_t, true>), dim3(nunits), dim3(kBlock), 0, s, a);
-    else hipLaunchKernelGGL((k_join<int64_t, true>), dim3(nunits), dim3(kBlock), 0, s, a);
-    GJ_LAUNCHED("k_join write");
+    // algorithmic bytes: keys of both sides, payload reads (GFTR: each partitioned
+    // row once; GFUR: one gathered value per output row and column, plus row ids),
+    // and the output rows
+    double rw_sum = 0, sw_sum = 0;
+    for (int j = 0; j < R.n_pay; ++j) rw_sum += R.width[j];
+    for (int j = 0; j < S.n_pay; ++j) sw_sum += S.width[j];
+    double wbytes = key_reads + (double)T * (key_bytes + rw_sum + sw_sum);
+    if (gfur) wbytes += (double)T * (rw_sum + sw_sum) + 4.0 * (nrows_r + nrows_s);
+    else wbytes += nrows_r * rw_sum + nrows_s * sw_sum;
+    if (key_bytes == 4)
+        GJ_LAUNCH("k_join_write", wbytes, (k_join<int32_t, true>), dim3(nunits), dim3(kBlock), 0, s, a);
+    else
+        GJ_LAUNCH("k_join_write", wbytes, (k_join<int64_t, true>), dim3(nunits), dim3(kBlock), 0, s, a);
     return (int64_t)T;
 }
 

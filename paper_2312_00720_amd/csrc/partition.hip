@@ -289,15 +289,17 @@ void run_pass(Ctx &ctx, PassArgs &a, uint32_t n) {
     const uint64_t hn = max_chunks * R;
     uint32_t *hist = ctx.scratch_n<uint32_t>(hn);
     a.hist = hist;
-    hipLaunchKernelGGL(k_chunk_table, dim3(1), dim3(kBlock), 0, s, a.seg_off, a.nseg, a.chunk_rows,
-                       chunk_base);
-    GJ_LAUNCHED("k_chunk_table");
+    // algorithmic bytes of one scatter: read and write the key and every column
+    // once (a generated row id is only written)
+    double row_bytes = 2.0 * sizeof(K);
+    for (int c = 0; c < a.ncols; ++c) row_bytes += (c == a.rowid_col ? 0 : a.col_w[c]) + a.col_w[c];
+    GJ_LAUNCH("k_chunk_table", 8.0 * (a.nseg + 1), k_chunk_table, dim3(1), dim3(kBlock), 0, s, a.seg_off,
+              a.nseg, a.chunk_rows, chunk_base);
     fill_u32(s, hist, 0u, hn);
-    hipLaunchKernelGGL(k_hist<K>, dim3((uint32_t)max_chunks), dim3(kBlock), 0, s, a);
-    GJ_LAUNCHED("k_hist");
+    GJ_LAUNCH("k_hist", (double)n * sizeof(K), k_hist<K>, dim3((uint32_t)max_chunks), dim3(kBlock), 0, s, a);
     scan_exclusive_u32(ctx, hist, hist, hn, nullptr);
-    hipLaunchKernelGGL((k_scatter<K, kItems>), dim3((uint32_t)max_chunks), dim3(kBlock), 0, s, a);
-    GJ_LAUNCHED("k_scatter");
+    GJ_LAUNCH("k_scatter", (double)n * row_bytes, (k_scatter<K, kItems>), dim3((uint32_t)max_chunks),
+              dim3(kBlock), 0, s, a);
 }
 
 }  // namespace
@@ -324,8 +326,7 @@ void partition_run(Ctx &ctx, int key_bytes, const void *key_in, void *key_out, c
     if (cols.gen_rowid) cin[cols.n] = nullptr;
 
     uint32_t *seg = ctx.scratch_n<uint32_t>(2);
-    hipLaunchKernelGGL(k_set_range, dim3(1), dim3(64), 0, s, seg, 0u, n);
-    GJ_LAUNCHED("k_set_range");
+    GJ_LAUNCH("k_set_range", 8.0, k_set_range, dim3(1), dim3(64), 0, s, seg, 0u, n);
     uint32_t nseg = 1;
 
     for (int p = 0; p < passes; ++p) {
@@ -361,9 +362,8 @@ void partition_run(Ctx &ctx, int key_bytes, const void *key_in, void *key_out, c
         }
         const uint64_t np = (uint64_t)nseg << b[p];
         uint32_t *next = last ? poff : ctx.scratch_n<uint32_t>(np + 1);
-        hipLaunchKernelGGL(k_poff, dim3((uint32_t)std::min<uint64_t>((np + 255) / 256, 4096)), dim3(256),
-                           0, s, seg, nseg, a.chunk_base, a.hist, b[p], next);
-        GJ_LAUNCHED("k_poff");
+        GJ_LAUNCH("k_poff", 8.0 * (np + 1), k_poff, dim3((uint32_t)std::min<uint64_t>((np + 255) / 256, 4096)),
+                  dim3(256), 0, s, seg, nseg, a.chunk_base, a.hist, b[p], next);
         seg = next;
         nseg = (uint32_t)np;
         kin = a.key_out;

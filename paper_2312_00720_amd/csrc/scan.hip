@@ -90,20 +90,19 @@ void scan_exclusive(Ctx &ctx, const T *in, T *out, uint64_t n, T *total) {
     hipStream_t s = ctx.stream;
     if (n == 0) {
         if (total) {
-            hipLaunchKernelGGL(k_fill<T>, dim3(1), dim3(64), 0, s, total, T(0), (uint64_t)1);
-            GJ_LAUNCHED("k_fill");
+            GJ_LAUNCH("k_fill", sizeof(T), k_fill<T>, dim3(1), dim3(64), 0, s, total, T(0), (uint64_t)1);
         }
         return;
     }
     const uint64_t blocks = (n + kTile - 1) / kTile;
     T *partial = ctx.scratch_n<T>(blocks);
-    hipLaunchKernelGGL(k_scan_reduce<T>, dim3((uint32_t)blocks), dim3(kBlock), 0, s, in, n, partial);
-    GJ_LAUNCHED("k_scan_reduce");
-    hipLaunchKernelGGL(k_scan_partials<T>, dim3(1), dim3(kBlock), 0, s, partial, blocks, total);
-    GJ_LAUNCHED("k_scan_partials");
-    hipLaunchKernelGGL(k_scan_down<T>, dim3((uint32_t)blocks), dim3(kBlock), 0, s, in, out, n,
-                       (const T *)partial);
-    GJ_LAUNCHED("k_scan_down");
+    const double nb = (double)n * sizeof(T);
+    GJ_LAUNCH("k_scan_reduce", nb, k_scan_reduce<T>, dim3((uint32_t)blocks), dim3(kBlock), 0, s, in, n,
+              partial);
+    GJ_LAUNCH("k_scan_partials", 2.0 * blocks * sizeof(T), k_scan_partials<T>, dim3(1), dim3(kBlock), 0, s,
+              partial, blocks, total);
+    GJ_LAUNCH("k_scan_down", 2.0 * nb, k_scan_down<T>, dim3((uint32_t)blocks), dim3(kBlock), 0, s, in, out,
+              n, (const T *)partial);
 }
 
 template <typename T>
@@ -111,8 +110,7 @@ void fill(hipStream_t s, T *p, T v, uint64_t n) {
     if (n == 0) return;
     uint64_t blocks = (n + 255) / 256;
     if (blocks > 8192) blocks = 8192;
-    hipLaunchKernelGGL(k_fill<T>, dim3((uint32_t)blocks), dim3(256), 0, s, p, v, n);
-    GJ_LAUNCHED("k_fill");
+    GJ_LAUNCH("k_fill", (double)n * sizeof(T), k_fill<T>, dim3((uint32_t)blocks), dim3(256), 0, s, p, v, n);
 }
 
 }  // namespace
