@@ -48,6 +48,26 @@ def cpu_baseline(n_r_log2: int = 22, payloads: int = 4) -> dict:
                       f"payloads, uniform FK, mr=100%; {dt:.1f} s single-threaded (qsort + binary search)"}
 
 
+def copy_ceiling(nbytes: int = 1 << 31, reps: int = 5) -> float:
+    """Bandwidth of a plain device copy (read n + write n bytes), in GB/s: the
+    practical ceiling for streaming kernels, and the kernel the HBM counters
+    are calibrated against."""
+    import torch
+    x = torch.ones(nbytes // 4, dtype=torch.int32, device="cuda")
+    y = torch.empty_like(x)
+    y.copy_(x)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        y.copy_(x)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / reps
+    del x, y
+    return 2.0 * nbytes / (ms / 1e3) / 1e9
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -61,6 +81,8 @@ def main() -> int:
     ap.add_argument("--alpha", type=float, default=0.0)
     ap.add_argument("--match-ratio", type=float, default=1.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-only", action="store_true",
+                    help="only run the plain copy (counter calibration) and print its GB/s")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -72,6 +94,12 @@ def main() -> int:
     import datagen
     import datagen.device as dd
     import paper_2312_00720_amd as gj
+
+    if args.copy_only:
+        print(json.dumps({"copy_gbs": copy_ceiling(), "bytes_each_way": 1 << 31}), flush=True)
+        return 0
+    copy_gbs = copy_ceiling()
+    log(f"plain copy: {copy_gbs:.0f} GB/s")
 
     n_r, n_s, c = 1 << args.r_log2, 1 << args.s_log2, args.payloads
     log(f"generating |R|=2^{args.r_log2} |S|=2^{args.s_log2} payloads={c} key_bytes={args.key_bytes}")
@@ -139,6 +167,7 @@ def main() -> int:
                    "output_rows": n_out},
         "paper_throughput_rows_per_s": (n_r + n_s) / (ms / 1e3),
         "hbm_gbs_whole_step": alg_total / (ms / 1e3) / 1e9,
+        "copy_ceiling_gbs": copy_gbs,
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "alg_bytes_per_launch": dk["alg_bytes"] / max(1, dk["launches"]),

@@ -185,9 +185,75 @@ int gj_join(const gj_rel *R, const gj_rel *S, const gj_join_opts *opts, const gj
 int gj_groupby(gj_col key, const gj_col *vals, int32_t n_vals, int64_t n_rows, const gj_agg *aggs,
                int32_t n_aggs, const gj_groupby_opts *opts, const gj_allocator *alloc, void *stream,
                gj_groupby_out *out) {
-    (void)key; (void)vals; (void)n_vals; (void)n_rows; (void)aggs; (void)n_aggs; (void)opts;
-    (void)alloc; (void)stream; (void)out;
-    return fail(GJ_EUNSUPPORTED, "group-by is not built yet");
+    try {
+        g_last_error.clear();
+        gj::require(out != nullptr, "null output");
+        gj::require(n_rows >= 0, "negative row count");
+        gj::require(n_rows <= kMaxRows, "more than 2^31-1 rows", GJ_EOVERFLOW);
+        check_col(key, n_rows, "key");
+        gj::require(n_vals >= 0 && n_vals <= 8, "0..8 value columns");
+        gj::require(n_vals == 0 || vals != nullptr, "null value array");
+        for (int i = 0; i < n_vals; ++i) {
+            check_col(vals[i], n_rows, "value");
+            gj::require(vals[i].dtype == GJ_I32, "value columns must be GJ_I32");
+        }
+        gj::require(n_aggs >= 1 && n_aggs <= 16, "1..16 aggregates");
+        gj::require(aggs != nullptr && out->aggs != nullptr, "null aggregate arrays");
+        for (int j = 0; j < n_aggs; ++j) {
+            gj::require(aggs[j].op >= GJ_SUM && aggs[j].op <= GJ_MAX, "unknown aggregate");
+            gj::require(aggs[j].op == GJ_COUNT || (aggs[j].col >= 0 && aggs[j].col < n_vals),
+                        "aggregate column out of range");
+        }
+        gj_groupby_opts o{};
+        if (opts) o = *opts;
+        gj::require(o.algo >= GJ_GB_AUTO && o.algo <= GJ_GB_PARTITION, "bad group-by algorithm");
+        gj::require(o.mat >= 0 && o.mat <= 2, "bad materialization");
+        gj::require(o.radix_bits >= 0 && o.radix_bits <= 16, "radix_bits must be 0..16");
+        gj::require(o.block_size == 0 || o.block_size == gj::kBlock, "block_size must be 0 or 256");
+        gj::require(o.lds_budget >= 0, "negative lds_budget");
+
+        out->n_groups = 0;
+        out->key = nullptr;
+        for (int j = 0; j < n_aggs; ++j) out->aggs[j] = nullptr;
+        if (n_rows == 0) return GJ_OK;
+
+        const int kb = dtype_bytes(key.dtype);
+        const uint32_t n = (uint32_t)n_rows;
+        const bool gfur = (o.mat == GJ_MAT_GFUR);
+        int algo = o.algo == GJ_GB_AUTO ? GJ_GB_PARTITION : o.algo;
+        const int32_t *vcols[8];
+        for (int i = 0; i < n_vals; ++i) vcols[i] = static_cast<const int32_t *>(vals[i].data);
+
+        gj::Ctx ctx(alloc, (hipStream_t)stream);
+        void *okey = nullptr;
+        void *oaggs[16] = {nullptr};
+        int64_t g = -1;
+        if (algo == GJ_GB_PARTITION) {
+            int bits = o.radix_bits;
+            if (bits == 0) bits = std::min(16, std::max(1, ceil_log2((n + 2047) / 2048)));
+            int fell_back = 0;
+            g = gj::groupby_partition(ctx, kb, key.data, vcols, n_vals, n, aggs, n_aggs, gfur, bits, &okey, oaggs,
+                                      &fell_back);
+            if (fell_back) algo = GJ_GB_HASH;  // too many distinct keys per partition
+        }
+        if (algo == GJ_GB_HASH)
+            g = gj::groupby_hash(ctx, kb, key.data, vcols, n_vals, n, aggs, n_aggs, o.lds_budget, &okey, oaggs);
+        else if (algo == GJ_GB_SORT)
+            g = gj::groupby_sort(ctx, kb, key.data, vcols, n_vals, n, aggs, n_aggs, gfur, &okey, oaggs);
+        out->n_groups = g;
+        out->key = okey;
+        for (int j = 0; j < n_aggs; ++j) out->aggs[j] = oaggs[j];
+        ctx.commit();
+        return GJ_OK;
+    } catch (const gj::Error &e) {
+        if (out) {
+            out->n_groups = 0;
+            out->key = nullptr;
+        }
+        return fail(e.code, e.what());
+    } catch (const std::exception &e) {
+        return fail(GJ_EHIP, e.what());
+    }
 }
 
 }  // extern "C"

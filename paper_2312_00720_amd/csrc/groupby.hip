@@ -1,0 +1,906 @@
+// Grouped aggregation: partition-based (Section 4.3), hash-based (Section 4.2,
+// Algorithm 1) and sort-based (Sections 3.2.2 and 4.1.3).
+//
+// Aggregates: COUNT, and SUM / MIN / MAX of int32 value columns. While a group
+// is being aggregated in LDS, its record holds the 64-bit sums first, then
+// 32-bit counts, minima and maxima (one 4-byte word each), padded to an even
+// number of words. Outputs: SUM and COUNT as int64, MIN and MAX as int32.
+#include <stdio.h>
+#include <stdlib.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "internal.hpp"
+
+namespace gj {
+
+namespace {
+
+constexpr int kMaxAggs = 16;
+constexpr int kMaxVals = 8;
+constexpr uint32_t kDiscoverCap = 4096;  // LDS table slots of the discover pass
+constexpr uint32_t kUnitRows = 8192;     // rows per aggregation work unit
+
+struct AggSpec {
+    int n;
+    int op[kMaxAggs];   // GJ_SUM / GJ_COUNT / GJ_MIN / GJ_MAX
+    int col[kMaxAggs];  // value column
+    int word[kMaxAggs]; // word offset in the LDS record
+    int words;          // record size in 4-byte words (even)
+    void *out[kMaxAggs];
+};
+
+struct ValSrc {
+    int n;
+    const int32_t *col[kMaxVals];  // GFTR: partitioned/sorted columns; GFUR: original columns
+    const int32_t *rowid;          // GFUR: row ids aligned with the keys; else nullptr
+};
+
+__device__ __forceinline__ int32_t load_val(const ValSrc &v, int c, uint32_t row) {
+    const uint32_t r = v.rowid ? (uint32_t)v.rowid[row] : row;
+    return v.col[c][r];
+}
+
+__device__ __forceinline__ void rec_init(uint32_t *rec, const AggSpec &s) {
+    for (int j = 0; j < s.n; ++j) {
+        uint32_t *p = rec + s.word[j];
+        switch (s.op[j]) {
+            case GJ_SUM: p[0] = 0; p[1] = 0; break;
+            case GJ_COUNT: p[0] = 0; break;
+            case GJ_MIN: p[0] = (uint32_t)INT32_MAX; break;
+            default: p[0] = (uint32_t)INT32_MIN; break;
+        }
+    }
+}
+
+// Accumulate one row into an LDS record.
+__device__ __forceinline__ void rec_add_lds(uint32_t *rec, const AggSpec &s, const ValSrc &v, uint32_t row) {
+    for (int j = 0; j < s.n; ++j) {
+        uint32_t *p = rec + s.word[j];
+        switch (s.op[j]) {
+            case GJ_SUM:
+                atomicAdd(reinterpret_cast<unsigned long long *>(p), (unsigned long long)(long long)load_val(v, s.col[j], row));
+                break;
+            case GJ_COUNT: atomicAdd(p, 1u); break;
+            case GJ_MIN: atomicMin(reinterpret_cast<int *>(p), load_val(v, s.col[j], row)); break;
+            default: atomicMax(reinterpret_cast<int *>(p), load_val(v, s.col[j], row)); break;
+        }
+    }
+}
+
+// Write (plain) or fold (atomic) an LDS record into output group o.
+__device__ __forceinline__ void rec_flush(const uint32_t *rec, const AggSpec &s, uint64_t o, bool atomic) {
+    for (int j = 0; j < s.n; ++j) {
+        const uint32_t *p = rec + s.word[j];
+        switch (s.op[j]) {
+            case GJ_SUM: {
+                const unsigned long long x = *reinterpret_cast<const unsigned long long *>(p);
+                unsigned long long *q = static_cast<unsigned long long *>(s.out[j]) + o;
+                if (atomic) atomicAdd(q, x);
+                else *q = x;
+                break;
+            }
+            case GJ_COUNT: {
+                unsigned long long *q = static_cast<unsigned long long *>(s.out[j]) + o;
+                if (atomic) atomicAdd(q, (unsigned long long)p[0]);
+                else *q = p[0];
+                break;
+            }
+            case GJ_MIN: {
+                int *q = static_cast<int *>(s.out[j]) + o;
+                if (atomic) atomicMin(q, (int)p[0]);
+                else *q = (int)p[0];
+                break;
+            }
+            default: {
+                int *q = static_cast<int *>(s.out[j]) + o;
+                if (atomic) atomicMax(q, (int)p[0]);
+                else *q = (int)p[0];
+                break;
+            }
+        }
+    }
+}
+
+// Fold one row directly into output group o with global atomics.
+__device__ __forceinline__ void row_add_global(const AggSpec &s, const ValSrc &v, uint32_t row, uint64_t o) {
+    for (int j = 0; j < s.n; ++j) {
+        switch (s.op[j]) {
+            case GJ_SUM:
+                atomicAdd(static_cast<unsigned long long *>(s.out[j]) + o,
+                          (unsigned long long)(long long)load_val(v, s.col[j], row));
+                break;
+            case GJ_COUNT: atomicAdd(static_cast<unsigned long long *>(s.out[j]) + o, 1ull); break;
+            case GJ_MIN: atomicMin(static_cast<int *>(s.out[j]) + o, load_val(v, s.col[j], row)); break;
+            default: atomicMax(static_cast<int *>(s.out[j]) + o, load_val(v, s.col[j], row)); break;
+        }
+    }
+}
+
+// Identity values for every output column over groups [0, g).
+__global__ void k_out_init(AggSpec s, uint64_t g) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < g; i += (uint64_t)gridDim.x * blockDim.x) {
+        for (int j = 0; j < s.n; ++j) {
+            switch (s.op[j]) {
+                case GJ_SUM:
+                case GJ_COUNT: static_cast<long long *>(s.out[j])[i] = 0; break;
+                case GJ_MIN: static_cast<int *>(s.out[j])[i] = INT32_MAX; break;
+                default: static_cast<int *>(s.out[j])[i] = INT32_MIN; break;
+            }
+        }
+    }
+}
+
+template <typename K>
+__device__ __forceinline__ K empty_key() {
+    if constexpr (sizeof(K) == 4) return (K)INT32_MIN;
+    else return (K)INT64_MIN;
+}
+
+// Slot hash for LDS tables: the top bits of the MurmurHash3 finalizer. The
+// partition digit of the partition-based group-by takes the low bits of the
+// same hash, so keys of one partition still spread over the table.
+template <typename K>
+__device__ __forceinline__ uint32_t slot_hash(K key, int log2cap) {
+    uint32_t x;
+    if constexpr (sizeof(K) == 4) x = (uint32_t)key;
+    else x = (uint32_t)(uint64_t)key ^ (uint32_t)((uint64_t)key >> 32);
+    return log2cap == 0 ? 0u : fmix32(x) >> (32 - log2cap);
+}
+
+// Insert-or-find in an LDS open-addressing table (linear probing). The key equal
+// to the empty marker never reaches here. Returns the slot, or -1 if full.
+template <typename K>
+__device__ __forceinline__ int lds_insert(K *tab, int log2cap, K key) {
+    const uint32_t mask = (1u << log2cap) - 1u;
+    uint32_t h = slot_hash<K>(key, log2cap);
+    const K e = empty_key<K>();
+    for (uint32_t step = 0; step <= mask; ++step) {
+        K cur;
+        if constexpr (sizeof(K) == 4) cur = (K)atomicCAS(reinterpret_cast<int *>(&tab[h]), (int)e, (int)key);
+        else
+            cur = (K)atomicCAS(reinterpret_cast<unsigned long long *>(&tab[h]), (unsigned long long)e,
+                               (unsigned long long)key);
+        if (cur == e || cur == key) return (int)h;
+        h = (h + 1) & mask;
+    }
+    return -1;
+}
+
+template <typename K>
+__device__ __forceinline__ int lds_find(const K *tab, int log2cap, K key) {
+    const uint32_t mask = (1u << log2cap) - 1u;
+    uint32_t h = slot_hash<K>(key, log2cap);
+    for (uint32_t step = 0; step <= mask; ++step) {
+        if (tab[h] == key) return (int)h;
+        if (tab[h] == empty_key<K>()) return -1;
+        h = (h + 1) & mask;
+    }
+    return -1;
+}
+
+// ---------------------------------------------------------------------------------
+// Partition-based group-by (Section 4.3). After partitioning on the hashed key,
+// the discover pass inserts every key of a partition into an LDS table before any
+// aggregation, which gives the partition's group count and hence dense output
+// offsets. Local group ids follow the first occurrence of each key in the
+// (stable) partitioned order, so the output order is deterministic.
+
+struct PgbArgs {
+    const void *keys;       // partitioned keys
+    const uint32_t *poff;   // partition offsets (np + 1)
+    uint32_t np;
+    void *tmp_keys;         // per partition: its distinct keys in id order, at the partition's row offset
+    uint32_t *gcnt;         // groups per partition (np + 1; scanned into offsets later)
+    uint32_t *stat;         // [0] = max groups in one partition, [1] = overflow flag
+    // aggregation pass
+    const uint32_t *goff;   // exclusive prefix of gcnt
+    const uint32_t *ubase;  // exclusive prefix of units per partition
+    void *out_key;
+    AggSpec spec;
+    ValSrc vals;
+    int log2cap;            // LDS table size of the aggregation pass
+    int lds_records;        // 1: aggregate in LDS records; 0: global atomics
+};
+
+template <typename K>
+__global__ __launch_bounds__(kBlock) void k_pgb_discover(PgbArgs a) {
+    __shared__ K s_key[kDiscoverCap];
+    __shared__ uint32_t s_first[kDiscoverCap];
+    __shared__ uint32_t s_tmp[kWaves];
+    __shared__ uint32_t s_sent;  // first row holding the key equal to the empty marker
+    __shared__ int s_over;
+    constexpr int log2cap = 12;
+    static_assert((1u << log2cap) == kDiscoverCap, "table size");
+    const uint32_t p = blockIdx.x;
+    const uint32_t p0 = a.poff[p], p1 = a.poff[p + 1];
+    const int tid = threadIdx.x;
+    if (p0 == p1) {
+        if (tid == 0) a.gcnt[p] = 0;
+        return;
+    }
+    const K *__restrict__ keys = static_cast<const K *>(a.keys);
+    const K e = empty_key<K>();
+    for (uint32_t i = tid; i < kDiscoverCap; i += kBlock) {
+        s_key[i] = e;
+        s_first[i] = 0xFFFFFFFFu;
+    }
+    if (tid == 0) {
+        s_sent = 0xFFFFFFFFu;
+        s_over = 0;
+    }
+    __syncthreads();
+    for (uint32_t i = p0 + tid; i < p1; i += kBlock) {
+        const K k = keys[i];
+        const uint32_t local = i - p0;
+        if (k == e) {
+            atomicMin(&s_sent, local);
+        } else {
+            const int slot = lds_insert<K>(s_key, log2cap, k);
+            if (slot < 0) s_over = 1;
+            else atomicMin(&s_first[slot], local);
+        }
+    }
+    __syncthreads();
+    if (s_over) {
+        if (tid == 0) {
+            a.gcnt[p] = 0;
+            atomicOr(&a.stat[1], 1u);
+        }
+        return;
+    }
+    // ids in order of first occurrence: a block scan over head flags in row order
+    K *__restrict__ tk = static_cast<K *>(a.tmp_keys);
+    uint32_t ids = 0;
+    for (uint32_t c0 = p0; c0 < p1; c0 += kBlock) {
+        const uint32_t i = c0 + tid;
+        uint32_t head = 0;
+        K k = e;
+        if (i < p1) {
+            k = keys[i];
+            const uint32_t local = i - p0;
+            head = (k == e) ? (s_sent == local) : (s_first[lds_find<K>(s_key, log2cap, k)] == local);
+        }
+        uint32_t tot;
+        const uint32_t pre = block_exclusive_sum<uint32_t>(head, s_tmp, &tot);
+        if (head) tk[p0 + ids + pre] = k;
+        ids += tot;
+    }
+    if (tid == 0) {
+        a.gcnt[p] = ids;
+        atomicMax(&a.stat[0], ids);
+    }
+}
+
+__global__ void k_pgb_units(const uint32_t *__restrict__ poff, uint32_t np, uint32_t *__restrict__ ucnt,
+                            uint32_t *__restrict__ max_units) {
+    uint32_t mx = 0;
+    for (uint32_t p = blockIdx.x * blockDim.x + threadIdx.x; p < np; p += gridDim.x * blockDim.x) {
+        const uint32_t u = ceil_div_u32(poff[p + 1] - poff[p], kUnitRows);
+        ucnt[p] = u;
+        mx = max(mx, u);
+    }
+    atomicMax(max_units, mx);
+}
+
+template <typename K>
+__global__ __launch_bounds__(kBlock) void k_pgb_aggregate(PgbArgs a) {
+    extern __shared__ __align__(16) uint32_t s_dyn[];
+    __shared__ uint32_t s_unit[5];
+    const int tid = threadIdx.x;
+    const uint32_t u = blockIdx.x;
+    if (tid == 0) {
+        uint32_t lo = 0, hi = a.np;  // ubase[lo] <= u < ubase[hi]
+        while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (a.ubase[mid] <= u) lo = mid;
+            else hi = mid;
+        }
+        const uint32_t p = lo;
+        const uint32_t p0 = a.poff[p], p1 = a.poff[p + 1];
+        const uint32_t j = u - a.ubase[p];
+        s_unit[0] = p;
+        s_unit[1] = p0 + j * kUnitRows;
+        s_unit[2] = min(p0 + (j + 1) * kUnitRows, p1);
+        s_unit[3] = (a.ubase[p + 1] - a.ubase[p]) > 1;  // several units share the partition
+        s_unit[4] = j;
+    }
+    __syncthreads();
+    const uint32_t p = s_unit[0], r0 = s_unit[1], r1 = s_unit[2];
+    const bool multi = s_unit[3] != 0;
+    const uint32_t j = s_unit[4];
+    const uint32_t p0 = a.poff[p];
+    const uint32_t g = a.goff[p + 1] - a.goff[p];  // group counts were scanned in place into offsets
+    const uint64_t gb = a.goff[p];
+    if (g == 0) return;
+    const K *__restrict__ keys = static_cast<const K *>(a.keys);
+    const K *__restrict__ tk = static_cast<const K *>(a.tmp_keys);
+    if (j == 0) {
+        K *ok = static_cast<K *>(a.out_key);
+        for (uint32_t i = tid; i < g; i += kBlock) ok[gb + i] = tk[p0 + i];
+    }
+    const AggSpec &s = a.spec;
+    if (g == 1) {
+        // one group: every row folds into it; a wave-level pass then one LDS record
+        uint32_t *rec = s_dyn;
+        if (tid == 0) rec_init(rec, s);
+        __syncthreads();
+        for (uint32_t i = r0 + tid; i < r1; i += kBlock) rec_add_lds(rec, s, a.vals, i);
+        __syncthreads();
+        if (tid == 0) rec_flush(rec, s, gb, multi);
+        return;
+    }
+    const int log2cap = a.log2cap;
+    const uint32_t cap = 1u << log2cap;
+    K *tab = reinterpret_cast<K *>(s_dyn);
+    uint16_t *tid_of = reinterpret_cast<uint16_t *>(tab + cap);  // slot -> group id
+    uint32_t *recs = reinterpret_cast<uint32_t *>(tid_of + cap);
+    recs = reinterpret_cast<uint32_t *>((reinterpret_cast<uintptr_t>(recs) + 7) & ~uintptr_t(7));
+    const K e = empty_key<K>();
+    for (uint32_t i = tid; i < cap; i += kBlock) tab[i] = e;
+    __shared__ uint32_t s_sent_id;
+    if (tid == 0) s_sent_id = 0xFFFFFFFFu;
+    if (a.lds_records)
+        for (uint32_t i = tid; i < g; i += kBlock) rec_init(recs + (uint64_t)i * s.words, s);
+    __syncthreads();
+    for (uint32_t i = tid; i < g; i += kBlock) {
+        const K k = tk[p0 + i];
+        if (k == e) {
+            s_sent_id = i;
+        } else {
+            const int slot = lds_insert<K>(tab, log2cap, k);
+            tid_of[slot] = (uint16_t)i;
+        }
+    }
+    __syncthreads();
+    for (uint32_t i = r0 + tid; i < r1; i += kBlock) {
+        const K k = keys[i];
+        const uint32_t id = (k == e) ? s_sent_id : tid_of[lds_find<K>(tab, log2cap, k)];
+        if (a.lds_records) rec_add_lds(recs + (uint64_t)id * s.words, s, a.vals, i);
+        else row_add_global(s, a.vals, i, gb + id);
+    }
+    if (a.lds_records) {
+        __syncthreads();
+        for (uint32_t i = tid; i < g; i += kBlock) rec_flush(recs + (uint64_t)i * s.words, s, gb + i, multi);
+    }
+}
+
+// ---------------------------------------------------------------------------------
+// Hash-based group-by (Algorithm 1). Stage 1 inserts (key, row) into a global
+// open-addressing table; the inserting row takes the next dense group id from an
+// atomic counter and every row records the row its key was inserted with. Stage 2
+// aggregates into a dense buffer: LDS records when all groups fit, else global.
+
+struct HgbArgs {
+    const void *keys;
+    uint32_t n;
+    void *table;          // 4-byte keys: packed (key << 32 | row); 8-byte keys: row index
+    int log2cap;
+    uint32_t *gid;        // group id of inserting rows
+    uint32_t *gid_loc;    // row with which the key was inserted
+    uint32_t *ngroups;
+    void *tmp_keys;       // key of each group id
+    // stage 2
+    AggSpec spec;
+    ValSrc vals;
+    void *out_key;
+    uint32_t g;
+    int lds_records;
+};
+
+template <typename K>
+__device__ __forceinline__ uint64_t global_slot_hash(K key) {
+    uint64_t u = (uint64_t)key;
+    if constexpr (sizeof(K) == 4) u &= 0xFFFFFFFFull;
+    // splitmix64 output function (Steele, Lea, Flood 2014)
+    u += 0x9E3779B97F4A7C15ull;
+    u = (u ^ (u >> 30)) * 0xBF58476D1CE4E5B9ull;
+    u = (u ^ (u >> 27)) * 0x94D049BB133111EBull;
+    return u ^ (u >> 31);
+}
+
+template <typename K>
+__global__ __launch_bounds__(kBlock) void k_hgb_insert(HgbArgs a) {
+    const K *__restrict__ keys = static_cast<const K *>(a.keys);
+    const uint64_t mask = (1ull << a.log2cap) - 1ull;
+    for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < a.n; i += gridDim.x * kBlock) {
+        const K k = keys[i];
+        uint64_t h = global_slot_hash<K>(k) & mask;
+        for (uint64_t step = 0; step <= mask; ++step) {
+            if constexpr (sizeof(K) == 4) {
+                unsigned long long *t = static_cast<unsigned long long *>(a.table);
+                const unsigned long long mine = ((unsigned long long)(uint32_t)k << 32) | i;
+                const unsigned long long cur = atomicCAS(&t[h], ~0ull, mine);
+                if (cur == ~0ull) {
+                    const uint32_t g = atomicAdd(a.ngroups, 1u);
+                    a.gid[i] = g;
+                    static_cast<K *>(a.tmp_keys)[g] = k;
+                    a.gid_loc[i] = i;
+                    break;
+                }
+                if ((uint32_t)(cur >> 32) == (uint32_t)k) {
+                    a.gid_loc[i] = (uint32_t)cur;
+                    break;
+                }
+            } else {
+                uint32_t *t = static_cast<uint32_t *>(a.table);
+                const uint32_t cur = atomicCAS(&t[h], 0xFFFFFFFFu, i);
+                if (cur == 0xFFFFFFFFu) {
+                    const uint32_t g = atomicAdd(a.ngroups, 1u);
+                    a.gid[i] = g;
+                    static_cast<K *>(a.tmp_keys)[g] = k;
+                    a.gid_loc[i] = i;
+                    break;
+                }
+                if (keys[cur] == k) {
+                    a.gid_loc[i] = cur;
+                    break;
+                }
+            }
+            h = (h + 1) & mask;
+        }
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_hgb_aggregate(HgbArgs a) {
+    extern __shared__ __align__(16) uint32_t s_dyn[];
+    const AggSpec &s = a.spec;
+    if (a.lds_records) {
+        for (uint32_t i = threadIdx.x; i < a.g; i += kBlock) rec_init(s_dyn + (uint64_t)i * s.words, s);
+        __syncthreads();
+    }
+    for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < a.n; i += gridDim.x * kBlock) {
+        const uint32_t g = a.gid[a.gid_loc[i]];
+        if (a.lds_records) rec_add_lds(s_dyn + (uint64_t)g * s.words, s, a.vals, i);
+        else row_add_global(s, a.vals, i, g);
+    }
+    if (a.lds_records) {
+        __syncthreads();
+        for (uint32_t i = threadIdx.x; i < a.g; i += kBlock) rec_flush(s_dyn + (uint64_t)i * s.words, s, i, true);
+    }
+}
+
+template <typename K>
+__global__ void k_copy_keys(const K *__restrict__ in, K *__restrict__ out, uint64_t n) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+        out[i] = in[i];
+}
+
+// ---------------------------------------------------------------------------------
+// Sort-based group-by: keys sorted (with the value columns under GFTR, with row
+// ids under GFUR); a head marks the first row of each run of equal keys. The
+// reduction walks rows in tiles of kBlock x 16: each thread reduces its 16 rows
+// sequentially, a block-level segmented scan carries each run across threads,
+// and the thread holding the last row of a run writes it. Runs that start
+// before the tile or reach past it are folded in with atomics.
+
+constexpr int kSgbItems = 16;
+constexpr uint32_t kSgbTile = kBlock * kSgbItems;
+
+struct SgbArgs {
+    const void *keys;     // sorted keys
+    uint32_t n;
+    uint32_t *tile_heads; // heads per tile -> exclusive prefix
+    AggSpec spec;
+    ValSrc vals;
+    void *out_key;
+};
+
+template <typename K>
+__global__ __launch_bounds__(kBlock) void k_sgb_heads(SgbArgs a) {
+    __shared__ uint32_t s_tmp[kWaves];
+    const K *__restrict__ keys = static_cast<const K *>(a.keys);
+    const uint32_t t0 = blockIdx.x * kSgbTile;
+    uint32_t c = 0;
+#pragma unroll
+    for (int k = 0; k < kSgbItems; ++k) {
+        const uint32_t i = t0 + k * kBlock + threadIdx.x;
+        if (i < a.n) c += (i == 0 || keys[i] != keys[i - 1]);
+    }
+    uint32_t tot;
+    block_exclusive_sum<uint32_t>(c, s_tmp, &tot);
+    if (threadIdx.x == 0) a.tile_heads[blockIdx.x] = tot;
+}
+
+// Running aggregate of one run: count, and per value column sum / min / max.
+// All loops over columns are unrolled to kMaxVals with a bound check, so the
+// arrays stay in registers.
+struct Acc {
+    uint32_t cnt;
+    long long sum[kMaxVals];
+    int mn[kMaxVals], mx[kMaxVals];
+};
+
+__device__ __forceinline__ void acc_clear(Acc &x) {
+    x.cnt = 0;
+#pragma unroll
+    for (int c = 0; c < kMaxVals; ++c) {
+        x.sum[c] = 0;
+        x.mn[c] = INT32_MAX;
+        x.mx[c] = INT32_MIN;
+    }
+}
+__device__ __forceinline__ void acc_merge(Acc &x, const Acc &y) {
+    x.cnt += y.cnt;
+#pragma unroll
+    for (int c = 0; c < kMaxVals; ++c) {
+        x.sum[c] += y.sum[c];
+        x.mn[c] = min(x.mn[c], y.mn[c]);
+        x.mx[c] = max(x.mx[c], y.mx[c]);
+    }
+}
+__device__ __forceinline__ void acc_row(Acc &x, const ValSrc &v, uint32_t row) {
+    x.cnt += 1;
+#pragma unroll
+    for (int c = 0; c < kMaxVals; ++c) {
+        if (c < v.n) {
+            const int val = load_val(v, c, row);
+            x.sum[c] += val;
+            x.mn[c] = min(x.mn[c], val);
+            x.mx[c] = max(x.mx[c], val);
+        }
+    }
+}
+
+__device__ __forceinline__ void acc_flush(const Acc &x, const AggSpec &s, uint64_t o, bool atomic) {
+    for (int j = 0; j < s.n; ++j) {
+        const int c = s.col[j];
+        long long sum = 0;
+        int mn = 0, mx = 0;
+#pragma unroll
+        for (int cc = 0; cc < kMaxVals; ++cc) {
+            if (cc == c) {
+                sum = x.sum[cc];
+                mn = x.mn[cc];
+                mx = x.mx[cc];
+            }
+        }
+        switch (s.op[j]) {
+            case GJ_SUM: {
+                unsigned long long *q = static_cast<unsigned long long *>(s.out[j]) + o;
+                if (atomic) atomicAdd(q, (unsigned long long)sum);
+                else *q = (unsigned long long)sum;
+                break;
+            }
+            case GJ_COUNT: {
+                unsigned long long *q = static_cast<unsigned long long *>(s.out[j]) + o;
+                if (atomic) atomicAdd(q, (unsigned long long)x.cnt);
+                else *q = x.cnt;
+                break;
+            }
+            case GJ_MIN: {
+                int *q = static_cast<int *>(s.out[j]) + o;
+                if (atomic) atomicMin(q, mn);
+                else *q = mn;
+                break;
+            }
+            default: {
+                int *q = static_cast<int *>(s.out[j]) + o;
+                if (atomic) atomicMax(q, mx);
+                else *q = mx;
+                break;
+            }
+        }
+    }
+}
+
+template <typename K>
+__global__ __launch_bounds__(kBlock) void k_sgb_reduce(SgbArgs a) {
+    __shared__ Acc s_acc[kBlock];
+    __shared__ uint32_t s_flag[kBlock];
+    __shared__ uint32_t s_tmp[kWaves];
+    const K *__restrict__ keys = static_cast<const K *>(a.keys);
+    const int tid = threadIdx.x;
+    const uint32_t t0 = blockIdx.x * kSgbTile;
+    const uint32_t first = t0 + tid * kSgbItems;  // this thread's rows: [first, first + 16)
+    // head flags of this thread's rows (row 0 always starts a run)
+    uint32_t hmask = 0, hc = 0;
+    if (first < a.n) {
+        K prev = first > 0 ? keys[first - 1] : K(0);
+        for (int k = 0; k < kSgbItems; ++k) {
+            const uint32_t i = first + k;
+            if (i >= a.n) break;
+            const K key = keys[i];
+            if (i == 0 || key != prev) {
+                hmask |= 1u << k;
+                ++hc;
+            }
+            prev = key;
+        }
+    }
+    const uint32_t hpre = block_exclusive_sum<uint32_t>(hc, s_tmp, (uint32_t *)nullptr);
+    // the thread's tail: rows after its last head (all its rows if it has none)
+    Acc cur;
+    acc_clear(cur);
+    for (int k = 0; k < kSgbItems; ++k) {
+        const uint32_t i = first + k;
+        if (i >= a.n) break;
+        if (hmask & (1u << k)) acc_clear(cur);
+        acc_row(cur, a.vals, i);
+    }
+    s_acc[tid] = cur;
+    s_flag[tid] = hc != 0;
+    __syncthreads();
+    // carry into each thread: serial segmented scan over the 256 thread tails
+    if (tid == 0) {
+        Acc run;
+        acc_clear(run);
+        for (int t = 0; t < kBlock; ++t) {
+            const Acc here = s_acc[t];
+            s_acc[t] = run;
+            if (s_flag[t]) run = here;
+            else acc_merge(run, here);
+        }
+    }
+    __syncthreads();
+    // Group id of a row = heads before the tile + heads of the tile up to the row - 1.
+    // A run that began before this thread began inside the tile iff an earlier
+    // thread of the tile had a head; only runs inside the tile are written plainly.
+    const uint64_t gbase = a.tile_heads[blockIdx.x];
+    cur = s_acc[tid];
+    bool cur_in_tile = hpre > 0;
+    uint64_t cur_gid = gbase + hpre - 1;  // wraps to 2^64-1 only before row 0, where cur is empty
+    K *ok = static_cast<K *>(a.out_key);
+    for (int k = 0; k < kSgbItems; ++k) {
+        const uint32_t i = first + k;
+        if (i >= a.n) break;
+        if (hmask & (1u << k)) {
+            if (cur.cnt > 0) acc_flush(cur, a.spec, cur_gid, !cur_in_tile);
+            acc_clear(cur);
+            cur_gid += 1;
+            cur_in_tile = true;
+            ok[cur_gid] = keys[i];
+        }
+        acc_row(cur, a.vals, i);
+    }
+    // the thread holding the tile's last row flushes the run that reaches it
+    const uint32_t tile_end = min(t0 + kSgbTile, a.n);
+    if (first < tile_end && first + kSgbItems >= tile_end && cur.cnt > 0) acc_flush(cur, a.spec, cur_gid, true);
+}
+
+}  // namespace
+
+// ---- host drivers ------------------------------------------------------------------
+
+namespace {
+
+AggSpec make_spec(const gj_agg *aggs, int n_aggs, void *const *outs) {
+    AggSpec s{};
+    s.n = n_aggs;
+    int w = 0;
+    for (int pass = 0; pass < 2; ++pass) {  // 64-bit sums first, then 32-bit fields
+        for (int j = 0; j < n_aggs; ++j) {
+            const bool is_sum = aggs[j].op == GJ_SUM;
+            if ((pass == 0) != is_sum) continue;
+            s.op[j] = aggs[j].op;
+            s.col[j] = aggs[j].op == GJ_COUNT ? 0 : aggs[j].col;
+            s.word[j] = w;
+            w += is_sum ? 2 : 1;
+            s.out[j] = outs[j];
+        }
+    }
+    s.words = (w + 1) & ~1;
+    if (s.words == 0) s.words = 2;
+    return s;
+}
+
+void init_outputs(hipStream_t st, const AggSpec &s, uint64_t g) {
+    if (g == 0) return;
+    const uint32_t blocks = (uint32_t)std::min<uint64_t>((g + 255) / 256, 4096);
+    GJ_LAUNCH("k_out_init", (double)g * 4.0 * s.words, k_out_init, dim3(blocks), dim3(256), 0, st, s, g);
+}
+
+}  // namespace
+
+int64_t groupby_partition(Ctx &ctx, int key_bytes, const void *key, const int32_t *const *vals, int n_vals,
+                          uint32_t n, const gj_agg *aggs, int n_aggs, bool gfur, int bits, void **out_key,
+                          void **out_aggs, int *fell_back) {
+    hipStream_t st = ctx.stream;
+    *fell_back = 0;
+    const int passes = bits > 8 ? 2 : 1;
+    // transformation: partition keys (and, under GFTR, the value columns) on the hashed key
+    void *pkey = ctx.scratch((size_t)n * key_bytes);
+    PartCols pc;
+    ValSrc vs{};
+    vs.n = n_vals;
+    if (!gfur) {
+        pc.n = n_vals;
+        for (int c = 0; c < n_vals; ++c) {
+            pc.in[c] = vals[c];
+            pc.width[c] = 4;
+            pc.out[c] = ctx.scratch((size_t)n * 4);
+            vs.col[c] = static_cast<const int32_t *>(pc.out[c]);
+        }
+        vs.rowid = nullptr;
+    } else {
+        pc.n = 0;
+        pc.gen_rowid = true;
+        pc.rowid_out = ctx.scratch((size_t)n * 4);
+        for (int c = 0; c < n_vals; ++c) vs.col[c] = vals[c];
+        vs.rowid = static_cast<const int32_t *>(pc.rowid_out);
+    }
+    const uint32_t np = 1u << bits;
+    uint32_t *poff = ctx.scratch_n<uint32_t>(np + 1);
+    partition_run(ctx, key_bytes, key, pkey, pc, n, 0, bits, passes, kDigitHash, poff);
+
+    // discover: groups per partition, distinct keys in first-occurrence order
+    PgbArgs a{};
+    a.keys = pkey;
+    a.poff = poff;
+    a.np = np;
+    a.tmp_keys = ctx.scratch((size_t)n * key_bytes);
+    uint32_t *gcnt = ctx.scratch_n<uint32_t>(np + 1);
+    uint32_t *stat = ctx.scratch_n<uint32_t>(4);
+    fill_u32(st, stat, 0u, 4);
+    a.gcnt = gcnt;
+    a.stat = stat;
+    if (key_bytes == 4)
+        GJ_LAUNCH("k_pgb_discover", 8.0 * n, k_pgb_discover<int32_t>, dim3(np), dim3(kBlock), 0, st, a);
+    else
+        GJ_LAUNCH("k_pgb_discover", 16.0 * n, k_pgb_discover<int64_t>, dim3(np), dim3(kBlock), 0, st, a);
+    scan_exclusive_u32(ctx, gcnt, gcnt, np, gcnt + np);
+    uint32_t *ucnt = ctx.scratch_n<uint32_t>(np + 1);
+    GJ_LAUNCH("k_pgb_units", 12.0 * np, k_pgb_units, dim3(std::min<uint32_t>((np + 255) / 256, 1024)), dim3(256),
+              0, st, poff, np, ucnt, stat + 2);
+    scan_exclusive_u32(ctx, ucnt, ucnt, np, ucnt + np);
+    uint32_t host[5];
+    GJ_HIP(hipMemcpyAsync(&host[0], gcnt + np, 4, hipMemcpyDeviceToHost, st));
+    GJ_HIP(hipMemcpyAsync(&host[1], stat, 12, hipMemcpyDeviceToHost, st));
+    GJ_HIP(hipMemcpyAsync(&host[4], ucnt + np, 4, hipMemcpyDeviceToHost, st));
+    GJ_HIP(hipStreamSynchronize(st));
+    const uint32_t g = host[0], maxg = host[1], over = host[2], max_units = host[3], units = host[4];
+    if (over) {
+        *fell_back = 1;  // some partition holds more distinct keys than its LDS table
+        return -1;
+    }
+    // outputs
+    *out_key = ctx.output((size_t)std::max<uint32_t>(g, 1) * key_bytes);
+    std::vector<void *> outs(n_aggs);
+    for (int j = 0; j < n_aggs; ++j) {
+        const bool wide = aggs[j].op == GJ_SUM || aggs[j].op == GJ_COUNT;
+        outs[j] = ctx.output((size_t)std::max<uint32_t>(g, 1) * (wide ? 8 : 4));
+        out_aggs[j] = outs[j];
+    }
+    if (g == 0) return 0;
+    a.spec = make_spec(aggs, n_aggs, outs.data());
+    a.vals = vs;
+    a.goff = gcnt;
+    a.ubase = ucnt;
+    a.out_key = *out_key;
+    // LDS: table of 2*maxg slots (key + 16-bit id), then maxg records
+    int log2cap = 6;
+    while ((1u << log2cap) < 2u * maxg) ++log2cap;
+    a.log2cap = log2cap;
+    const size_t tab_bytes = ((size_t)1 << log2cap) * (key_bytes + 2) + 8;
+    const size_t rec_bytes = (size_t)maxg * a.spec.words * 4;
+    size_t lds = tab_bytes + rec_bytes;
+    a.lds_records = 1;
+    if (lds > 120 * 1024 || log2cap > 16) {
+        a.lds_records = 0;  // too many groups per partition for LDS records: global atomics
+        lds = tab_bytes;
+    }
+    require(lds <= 150 * 1024, "partition group-by: too many groups per partition", GJ_EUNSUPPORTED);
+    lds = std::max<size_t>(lds, (size_t)a.spec.words * 4 + 8);
+    // outputs of partitions split over several units are folded with atomics
+    if (max_units > 1 || !a.lds_records) init_outputs(st, a.spec, g);
+    const double bytes = (double)n * (key_bytes + 4.0 * n_vals + (gfur ? 4.0 : 0.0)) +
+                         (double)g * (key_bytes + 4.0 * a.spec.words);
+    if (key_bytes == 4)
+        GJ_LAUNCH("k_pgb_aggregate", bytes, k_pgb_aggregate<int32_t>, dim3(units), dim3(kBlock), lds, st, a);
+    else
+        GJ_LAUNCH("k_pgb_aggregate", bytes, k_pgb_aggregate<int64_t>, dim3(units), dim3(kBlock), lds, st, a);
+    return g;
+}
+
+int64_t groupby_hash(Ctx &ctx, int key_bytes, const void *key, const int32_t *const *vals, int n_vals, uint32_t n,
+                     const gj_agg *aggs, int n_aggs, int lds_budget, void **out_key, void **out_aggs) {
+    hipStream_t st = ctx.stream;
+    HgbArgs a{};
+    a.keys = key;
+    a.n = n;
+    int log2cap = 4;
+    while ((1ull << log2cap) < (uint64_t)n + n / 2) ++log2cap;
+    a.log2cap = log2cap;
+    const size_t slot = key_bytes == 4 ? 8 : 4;
+    a.table = ctx.scratch(((size_t)1 << log2cap) * slot);
+    if (key_bytes == 4) fill_u64(st, static_cast<uint64_t *>(a.table), ~0ull, (uint64_t)1 << log2cap);
+    else fill_u32(st, static_cast<uint32_t *>(a.table), 0xFFFFFFFFu, (uint64_t)1 << log2cap);
+    a.gid = ctx.scratch_n<uint32_t>(n);
+    a.gid_loc = ctx.scratch_n<uint32_t>(n);
+    a.ngroups = ctx.scratch_n<uint32_t>(1);
+    fill_u32(st, a.ngroups, 0u, 1);
+    a.tmp_keys = ctx.scratch((size_t)n * key_bytes);
+    const uint32_t grid = std::min<uint32_t>(ceil_div_u32(n, kBlock), 256u * 16u);
+    if (key_bytes == 4)
+        GJ_LAUNCH("k_hgb_insert", 16.0 * n, k_hgb_insert<int32_t>, dim3(grid), dim3(kBlock), 0, st, a);
+    else
+        GJ_LAUNCH("k_hgb_insert", 20.0 * n, k_hgb_insert<int64_t>, dim3(grid), dim3(kBlock), 0, st, a);
+    const uint32_t g = read_back(a.ngroups, st);
+    *out_key = ctx.output((size_t)std::max<uint32_t>(g, 1) * key_bytes);
+    std::vector<void *> outs(n_aggs);
+    for (int j = 0; j < n_aggs; ++j) {
+        const bool wide = aggs[j].op == GJ_SUM || aggs[j].op == GJ_COUNT;
+        outs[j] = ctx.output((size_t)std::max<uint32_t>(g, 1) * (wide ? 8 : 4));
+        out_aggs[j] = outs[j];
+    }
+    if (g == 0) return 0;
+    a.spec = make_spec(aggs, n_aggs, outs.data());
+    a.vals.n = n_vals;
+    for (int c = 0; c < n_vals; ++c) a.vals.col[c] = vals[c];
+    a.vals.rowid = nullptr;
+    a.g = g;
+    const size_t rec_bytes = (size_t)g * a.spec.words * 4;
+    const size_t budget = lds_budget > 0 ? (size_t)lds_budget : (size_t)64 * 1024;
+    a.lds_records = rec_bytes <= budget;  // is_smem_enough
+    init_outputs(st, a.spec, g);
+    const double bytes = (double)n * (4.0 * n_vals + 8.0) + (double)g * (key_bytes + 4.0 * a.spec.words);
+    GJ_LAUNCH("k_hgb_aggregate", bytes, k_hgb_aggregate, dim3(grid), dim3(kBlock),
+              a.lds_records ? rec_bytes : 0, st, a);
+    const uint32_t cb = std::min<uint32_t>(ceil_div_u32(g, 256), 4096);
+    if (key_bytes == 4)
+        GJ_LAUNCH("k_copy_keys", 8.0 * g, k_copy_keys<int32_t>, dim3(cb), dim3(256), 0, st,
+                  static_cast<const int32_t *>(a.tmp_keys), static_cast<int32_t *>(*out_key), (uint64_t)g);
+    else
+        GJ_LAUNCH("k_copy_keys", 16.0 * g, k_copy_keys<int64_t>, dim3(cb), dim3(256), 0, st,
+                  static_cast<const int64_t *>(a.tmp_keys), static_cast<int64_t *>(*out_key), (uint64_t)g);
+    return g;
+}
+
+int64_t groupby_sort(Ctx &ctx, int key_bytes, const void *key, const int32_t *const *vals, int n_vals, uint32_t n,
+                     const gj_agg *aggs, int n_aggs, bool gfur, void **out_key, void **out_aggs) {
+    hipStream_t st = ctx.stream;
+    // transformation: LSD radix sort on the order-preserving key bits
+    void *skey = ctx.scratch((size_t)n * key_bytes);
+    PartCols pc;
+    ValSrc vs{};
+    vs.n = n_vals;
+    if (!gfur) {
+        pc.n = n_vals;
+        for (int c = 0; c < n_vals; ++c) {
+            pc.in[c] = vals[c];
+            pc.width[c] = 4;
+            pc.out[c] = ctx.scratch((size_t)n * 4);
+            vs.col[c] = static_cast<const int32_t *>(pc.out[c]);
+        }
+    } else {
+        pc.gen_rowid = true;
+        pc.rowid_out = ctx.scratch((size_t)n * 4);
+        for (int c = 0; c < n_vals; ++c) vs.col[c] = vals[c];
+        vs.rowid = static_cast<const int32_t *>(pc.rowid_out);
+    }
+    sort_run(ctx, key_bytes, key, skey, pc, n);
+
+    SgbArgs a{};
+    a.keys = skey;
+    a.n = n;
+    const uint32_t tiles = ceil_div_u32(n, kSgbTile);
+    a.tile_heads = ctx.scratch_n<uint32_t>(tiles + 1);
+    if (key_bytes == 4)
+        GJ_LAUNCH("k_sgb_heads", 4.0 * n, k_sgb_heads<int32_t>, dim3(tiles), dim3(kBlock), 0, st, a);
+    else
+        GJ_LAUNCH("k_sgb_heads", 8.0 * n, k_sgb_heads<int64_t>, dim3(tiles), dim3(kBlock), 0, st, a);
+    scan_exclusive_u32(ctx, a.tile_heads, a.tile_heads, tiles, a.tile_heads + tiles);
+    const uint32_t g = read_back(a.tile_heads + tiles, st);
+    *out_key = ctx.output((size_t)std::max<uint32_t>(g, 1) * key_bytes);
+    std::vector<void *> outs(n_aggs);
+    for (int j = 0; j < n_aggs; ++j) {
+        const bool wide = aggs[j].op == GJ_SUM || aggs[j].op == GJ_COUNT;
+        outs[j] = ctx.output((size_t)std::max<uint32_t>(g, 1) * (wide ? 8 : 4));
+        out_aggs[j] = outs[j];
+    }
+    if (g == 0) return 0;
+    a.spec = make_spec(aggs, n_aggs, outs.data());
+    a.vals = vs;
+    a.out_key = *out_key;
+    init_outputs(st, a.spec, g);
+    const double bytes = (double)n * (key_bytes + 4.0 * n_vals + (gfur ? 4.0 : 0.0)) +
+                         (double)g * (key_bytes + 4.0 * a.spec.words);
+    if (key_bytes == 4)
+        GJ_LAUNCH("k_sgb_reduce", bytes, k_sgb_reduce<int32_t>, dim3(tiles), dim3(kBlock), 0, st, a);
+    else
+        GJ_LAUNCH("k_sgb_reduce", bytes, k_sgb_reduce<int64_t>, dim3(tiles), dim3(kBlock), 0, st, a);
+    return g;
+}
+
+}  // namespace gj

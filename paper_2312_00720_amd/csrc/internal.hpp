@@ -135,6 +135,22 @@ struct PartCols {
 void partition_run(Ctx &ctx, int key_bytes, const void *key_in, void *key_out, const PartCols &cols,
                    uint32_t n, int bit_lo, int bits, int passes, int mode, uint32_t *poff);
 
+// Stable LSD radix sort of n rows by the signed key (8 bits per pass; bytes that are
+// equal in every key are skipped). Moves the columns of `cols` along.
+void sort_run(Ctx &ctx, int key_bytes, const void *key_in, void *key_out, const PartCols &cols, uint32_t n);
+
+// ---- groupby.hip ----------------------------------------------------------------------
+// Each returns the number of groups and allocates the key and aggregate outputs
+// through ctx.output(). groupby_partition returns -1 with *fell_back = 1 when a
+// partition holds more distinct keys than its LDS table.
+int64_t groupby_partition(Ctx &ctx, int key_bytes, const void *key, const int32_t *const *vals, int n_vals,
+                          uint32_t n, const gj_agg *aggs, int n_aggs, bool gfur, int bits, void **out_key,
+                          void **out_aggs, int *fell_back);
+int64_t groupby_hash(Ctx &ctx, int key_bytes, const void *key, const int32_t *const *vals, int n_vals, uint32_t n,
+                     const gj_agg *aggs, int n_aggs, int lds_budget, void **out_key, void **out_aggs);
+int64_t groupby_sort(Ctx &ctx, int key_bytes, const void *key, const int32_t *const *vals, int n_vals, uint32_t n,
+                     const gj_agg *aggs, int n_aggs, bool gfur, void **out_key, void **out_aggs);
+
 // ---- join.hip -------------------------------------------------------------------------
 struct JoinSide {
     const void *key;          // partitioned keys

@@ -64,8 +64,39 @@ __device__ __forceinline__ void copy_val(void *dst, int dw, uint64_t di, const v
     else static_cast<uint64_t *>(dst)[di] = static_cast<const uint64_t *>(src)[si];
 }
 
+// Copies column values src[j][row[r]] to dst[j][pos[r]] for the PB rounds of a
+// wave whose flag c[r] is set; all loads of one column are issued before its
+// stores, so PB loads per lane are in flight.
+template <int PB>
+__device__ __forceinline__ void gather_cols(int ncols, const void *const *src, const int *width,
+                                            void *const *dst, const uint32_t *row, const uint32_t *c,
+                                            const uint64_t *pos, uint64_t t_rows) {
+    for (int j = 0; j < ncols; ++j) {
+        if (width[j] == 4) {
+            const uint32_t *__restrict__ in = static_cast<const uint32_t *>(src[j]);
+            uint32_t *__restrict__ out = static_cast<uint32_t *>(dst[j]);
+            uint32_t v[PB];
+#pragma unroll
+            for (int r = 0; r < PB; ++r) v[r] = c[r] ? in[row[r]] : 0u;
+#pragma unroll
+            for (int r = 0; r < PB; ++r)
+                if (c[r] && pos[r] < t_rows) out[pos[r]] = v[r];
+        } else {
+            const uint64_t *__restrict__ in = static_cast<const uint64_t *>(src[j]);
+            uint64_t *__restrict__ out = static_cast<uint64_t *>(dst[j]);
+            uint64_t v[PB];
+#pragma unroll
+            for (int r = 0; r < PB; ++r) v[r] = c[r] ? in[row[r]] : 0ull;
+#pragma unroll
+            for (int r = 0; r < PB; ++r)
+                if (c[r] && pos[r] < t_rows) out[pos[r]] = v[r];
+        }
+    }
+}
+
 template <typename K, bool WRITE>
 __global__ __launch_bounds__(kBlock) void k_join(JoinArgs a) {
+    constexpr int PB = 16;
     __shared__ K s_rkey[kMaxBuild];
     __shared__ uint32_t s_b[kMaxBuild + 1];   // bucket boundaries
     __shared__ uint16_t s_entry[kMaxBuild];  // R block rows, grouped by bucket
@@ -177,18 +208,26 @@ __global__ __launch_bounds__(kBlock) void k_join(JoinArgs a) {
         __syncthreads();
     }
 
-    // ---- probe: each wave streams a contiguous quarter of the S piece ----
+    // ---- probe: each wave streams a contiguous quarter of the S piece, PB
+    // rounds of 64 rows at a time so that many loads are in flight ----
     const K *__restrict__ skey = static_cast<const K *>(a.skey);
     const uint32_t q = ceil_div_u32(sn, kWaves);
     const uint32_t ws = min(sn, w * q), we = min(sn, ws + q);
     if constexpr (!WRITE) {
         uint32_t cnt = 0;
-        for (uint32_t base = ws; base < we; base += kWave) {
-            const uint32_t i = base + lane;
-            if (i < we) {
-                const K key = skey[s0 + i];
-                const uint32_t b = bucket_of<K>(key, a.skip_bits, log2nb);
-                for (uint32_t e = s_b[b], end = s_b[b + 1]; e < end; ++e) cnt += (s_rkey[s_entry[e]] == key);
+        for (uint32_t base = ws; base < we; base += PB * kWave) {
+            K key[PB];
+#pragma unroll
+            for (int r = 0; r < PB; ++r) {
+                const uint32_t i = base + r * kWave + lane;
+                key[r] = i < we ? skey[s0 + i] : K(0);
+            }
+#pragma unroll
+            for (int r = 0; r < PB; ++r) {
+                if (base + r * kWave + lane < we) {
+                    const uint32_t b = bucket_of<K>(key[r], a.skip_bits, log2nb);
+                    for (uint32_t e = s_b[b], end = s_b[b + 1]; e < end; ++e) cnt += (s_rkey[s_entry[e]] == key[r]);
+                }
             }
         }
         const uint64_t tot = wave_sum<uint64_t>((uint64_t)cnt);
@@ -196,32 +235,74 @@ __global__ __launch_bounds__(kBlock) void k_join(JoinArgs a) {
     } else {
         uint64_t outpos = a.woff[(uint64_t)u * kWaves + w];
         K *__restrict__ tkey = static_cast<K *>(a.tkey);
-        for (uint32_t base = ws; base < we; base += kWave) {
-            const uint32_t i = base + lane;
-            const bool valid = i < we;
-            K key = K(0);
-            uint32_t b = 0, c = 0;
-            if (valid) {
-                key = skey[s0 + i];
-                b = bucket_of<K>(key, a.skip_bits, log2nb);
-                for (uint32_t e = s_b[b], end = s_b[b + 1]; e < end; ++e) c += (s_rkey[s_entry[e]] == key);
+        for (uint32_t base = ws; base < we; base += PB * kWave) {
+            K key[PB];
+            uint32_t c[PB], e1[PB];
+#pragma unroll
+            for (int r = 0; r < PB; ++r) {
+                const uint32_t i = base + r * kWave + lane;
+                key[r] = i < we ? skey[s0 + i] : K(0);
             }
-            const uint32_t incl = wave_inclusive_sum<uint32_t>(c);
-            const uint32_t tot = __shfl(incl, kWave - 1, kWave);
-            if (c) {
-                uint64_t pos = outpos + incl - c;
-                const uint64_t srow = a.srow ? (uint64_t)a.srow[s0 + i] : (uint64_t)(s0 + i);
-                for (uint32_t e = s_b[b], end = s_b[b + 1]; e < end; ++e) {
-                    const uint32_t ri = s_entry[e];
-                    if (s_rkey[ri] != key || pos >= a.t_rows) continue;
-                    const uint64_t rrow = a.rrow ? (uint64_t)a.rrow[r0 + ri] : (uint64_t)(r0 + ri);
-                    tkey[pos] = key;
-                    for (int j = 0; j < a.nr; ++j) copy_val(a.tr[j], a.rw[j], pos, a.rp[j], rrow);
-                    for (int j = 0; j < a.ns; ++j) copy_val(a.ts[j], a.sw[j], pos, a.sp[j], srow);
-                    ++pos;
+#pragma unroll
+            for (int r = 0; r < PB; ++r) {
+                c[r] = 0;
+                e1[r] = 0;
+                if (base + r * kWave + lane < we) {
+                    const uint32_t b = bucket_of<K>(key[r], a.skip_bits, log2nb);
+                    for (uint32_t e = s_b[b], end = s_b[b + 1]; e < end; ++e) {
+                        const uint32_t ri = s_entry[e];
+                        if (s_rkey[ri] == key[r]) {
+                            if (c[r] == 0) e1[r] = ri;
+                            ++c[r];
+                        }
+                    }
                 }
             }
-            outpos += tot;
+            uint64_t pos[PB];
+            bool multi = false;
+#pragma unroll
+            for (int r = 0; r < PB; ++r) {
+                const uint32_t incl = wave_inclusive_sum<uint32_t>(c[r]);
+                pos[r] = outpos + incl - c[r];
+                outpos += __shfl(incl, kWave - 1, kWave);
+                multi |= __ballot(c[r] > 1) != 0ull;
+            }
+            if (!multi) {
+                // at most one match per S row: every output row is (S row, its R row)
+#pragma unroll
+                for (int r = 0; r < PB; ++r)
+                    if (c[r] && pos[r] < a.t_rows) tkey[pos[r]] = key[r];
+                uint32_t srow[PB], rrow[PB];
+#pragma unroll
+                for (int r = 0; r < PB; ++r) {
+                    const uint32_t i = base + r * kWave + lane;
+                    srow[r] = s0 + i;
+                    rrow[r] = r0 + e1[r];
+                    if (a.srow && c[r]) srow[r] = (uint32_t)a.srow[srow[r]];
+                    if (a.rrow && c[r]) rrow[r] = (uint32_t)a.rrow[rrow[r]];
+                }
+                gather_cols<PB>(a.ns, a.sp, a.sw, a.ts, srow, c, pos, a.t_rows);
+                gather_cols<PB>(a.nr, a.rp, a.rw, a.tr, rrow, c, pos, a.t_rows);
+            } else {
+                // several matches for some row: enumerate the chain per lane
+#pragma unroll
+                for (int r = 0; r < PB; ++r) {
+                    if (!c[r]) continue;
+                    const uint32_t i = base + r * kWave + lane;
+                    uint64_t p = pos[r];
+                    const uint64_t sr = a.srow ? (uint64_t)a.srow[s0 + i] : (uint64_t)(s0 + i);
+                    const uint32_t b = bucket_of<K>(key[r], a.skip_bits, log2nb);
+                    for (uint32_t e = s_b[b], end = s_b[b + 1]; e < end; ++e) {
+                        const uint32_t ri = s_entry[e];
+                        if (s_rkey[ri] != key[r] || p >= a.t_rows) continue;
+                        const uint64_t rr = a.rrow ? (uint64_t)a.rrow[r0 + ri] : (uint64_t)(r0 + ri);
+                        tkey[p] = key[r];
+                        for (int j = 0; j < a.nr; ++j) copy_val(a.tr[j], a.rw[j], p, a.rp[j], rr);
+                        for (int j = 0; j < a.ns; ++j) copy_val(a.ts[j], a.sw[j], p, a.sp[j], sr);
+                        ++p;
+                    }
+                }
+            }
         }
     }
 }

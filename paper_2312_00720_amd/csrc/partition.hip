@@ -17,18 +17,26 @@
 //   k_poff         partition boundaries (segment, digit) for the next pass
 // Two passes with the top bits first give rows sorted stably by the full digit,
 // i.e. every partition contiguous and in input order.
+#include <stdio.h>
+#include <stdlib.h>
+
+#include <vector>
+
 #include "internal.hpp"
 
 namespace gj {
 namespace {
 
-constexpr int kItems = 16;
+constexpr int kScatterBlock = 1024;  // default scatter shape: 1024 threads x 8 rows, 4 columns per load group
+constexpr int kItems = 8;
+constexpr int kGroup = 4;
 constexpr uint32_t kTile = kBlock * kItems;
 
 struct PassArgs {
     const void *key_in;
     void *key_out;
     int ncols;
+    int n4;         // columns 0..n4-1 are 4 bytes wide, the rest 8 bytes
     int rowid_col;  // index of the generated row-id column, or -1
     const void *col_in[kMaxCols];
     void *col_out[kMaxCols];
@@ -91,6 +99,7 @@ __global__ __launch_bounds__(kBlock) void k_chunk_table(const uint32_t *__restri
 
 template <typename K>
 __global__ __launch_bounds__(kBlock) void k_hist(PassArgs a) {
+    constexpr int U = 16;  // loads in flight per thread
     __shared__ uint32_t s_cnt[kWaves][kRadix];
     __shared__ ChunkLoc s_loc;
     if (threadIdx.x == 0) s_loc = locate_chunk(a, blockIdx.x);
@@ -99,13 +108,21 @@ __global__ __launch_bounds__(kBlock) void k_hist(PassArgs a) {
     const ChunkLoc L = s_loc;
     if (!L.ok) return;
     const K *__restrict__ keys = static_cast<const K *>(a.key_in);
-    const int w = threadIdx.x / kWave, lane = lane_id();
-    for (uint32_t base = L.row0 + w * kWave; base < L.row1; base += kBlock) {
-        const uint32_t row = base + lane;
-        const bool valid = row < L.row1;
-        const uint32_t d = valid ? digit_of<K>(keys[row], a.dig) : 0u;
-        const uint64_t peers = match_peers(d, a.bits, valid);
-        if (valid && rank_below(peers) == 0) s_cnt[w][d] += (uint32_t)__popcll(peers);
+    const int tid = threadIdx.x, w = tid / kWave;
+    for (uint32_t base = L.row0; base < L.row1; base += kBlock * U) {
+        K k[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint32_t row = base + u * kBlock + tid;
+            k[u] = row < L.row1 ? keys[row] : K(0);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const bool valid = base + u * kBlock + tid < L.row1;
+            const uint32_t d = digit_of<K>(k[u], a.dig);
+            const uint64_t peers = match_peers(d, a.bits, valid);
+            if (valid && rank_below(peers) == 0) s_cnt[w][d] += (uint32_t)__popcll(peers);
+        }
     }
     __syncthreads();
     const uint32_t R = 1u << a.bits;
@@ -117,15 +134,187 @@ __global__ __launch_bounds__(kBlock) void k_hist(PassArgs a) {
     }
 }
 
-template <typename K, int ITEMS>
-__global__ __launch_bounds__(kBlock) void k_scatter(PassArgs a) {
-    constexpr uint32_t TILE = kBlock * ITEMS;
-    __shared__ uint32_t s_wcnt[kWaves][kRadix];
-    __shared__ uint32_t s_start[kRadix];
-    __shared__ uint32_t s_tot[kRadix];
-    __shared__ uint32_t s_cur[kRadix];
-    __shared__ uint32_t s_tmp[kWaves];
-    __shared__ uint64_t s_buf[TILE];
+__device__ __forceinline__ uint32_t load_col4(const PassArgs &a, int c, uint32_t row) {
+    return c == a.rowid_col ? row : static_cast<const uint32_t *>(a.col_in[c])[row];
+}
+
+// One tile of the stable scatter: TILE rows starting at tile0 (nt valid; FULL
+// means nt == TILE and no row needs a bounds check). Columns 0..n4-1 are 4-byte
+// (the generated row id among them), columns n4..ncols-1 are 8-byte.
+template <int BLOCK>
+struct ScatterShared {
+    static constexpr int W = BLOCK / kWave;
+    uint32_t wcnt[W][kRadix];
+    uint32_t start[kRadix];
+    uint32_t tot[kRadix];
+    uint32_t cur[kRadix];
+    uint32_t tmp[kWaves];
+};
+
+template <typename K, int BLOCK, int ITEMS, int G, bool FULL>
+__device__ __forceinline__ void scatter_tile(const PassArgs &a, ScatterShared<BLOCK> &S,
+                                             uint32_t (*s_buf)[BLOCK * ITEMS], uint32_t tile0, uint32_t nt) {
+    constexpr uint32_t TILE = BLOCK * ITEMS;
+    constexpr int W = BLOCK / kWave;
+    const int tid = threadIdx.x, w = tid / kWave, lane = lane_id();
+    const K *__restrict__ keys = static_cast<const K *>(a.key_in);
+    K *__restrict__ kout = static_cast<K *>(a.key_out);
+    K *sk = reinterpret_cast<K *>(&s_buf[0][0]);
+    uint64_t *s8 = reinterpret_cast<uint64_t *>(&s_buf[0][0]);
+    const int n4 = a.n4;
+    const uint32_t lbase = (uint32_t)(w * kWave * ITEMS + lane);
+#define GJ_VALID(r) (FULL || lbase + (r) * kWave < nt)
+
+    for (int i = tid; i < W * kRadix; i += BLOCK) (&S.wcnt[0][0])[i] = 0;
+
+    // issue the loads of the keys and of the first group of 4-byte columns
+    K key[ITEMS];
+    uint32_t v[G][ITEMS];
+#pragma unroll
+    for (int r = 0; r < ITEMS; ++r) key[r] = GJ_VALID(r) ? keys[tile0 + lbase + r * kWave] : K(0);
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        if (g < n4) {
+            const bool gen = (g == a.rowid_col);
+            const uint32_t *__restrict__ in = static_cast<const uint32_t *>(a.col_in[g]);
+#pragma unroll
+            for (int r = 0; r < ITEMS; ++r) {
+                const uint32_t row = tile0 + lbase + r * kWave;
+                v[g][r] = gen ? row : (GJ_VALID(r) ? in[row] : 0u);
+            }
+        }
+    }
+    __syncthreads();
+
+    // stable rank within the wave: ballot peers, the leader bumps the wave counter
+    uint32_t pos[ITEMS];
+#pragma unroll
+    for (int r = 0; r < ITEMS; ++r) {
+        const bool valid = GJ_VALID(r);
+        const uint32_t d = digit_of<K>(key[r], a.dig);
+        const uint64_t peers = match_peers(d, a.bits, valid);
+        uint32_t p = 0;
+        if (valid) {
+            const uint32_t rk = rank_below(peers);
+            const uint32_t b = S.wcnt[w][d];
+            if (rk == 0) S.wcnt[w][d] = b + (uint32_t)__popcll(peers);
+            p = b + rk;
+        }
+        pos[r] = p;
+    }
+    __syncthreads();
+    if (tid < kRadix) {
+        // threads 0..255 (one per digit): tile totals and cross-wave exclusive prefix
+        uint32_t t = 0;
+#pragma unroll
+        for (int q = 0; q < W; ++q) {
+            const uint32_t c = S.wcnt[q][tid];
+            S.wcnt[q][tid] = t;
+            t += c;
+        }
+        S.tot[tid] = t;
+        // exclusive scan over the 256 digits by the first four waves
+        const uint32_t inc = wave_inclusive_sum<uint32_t>(t);
+        if (lane == kWave - 1) S.tmp[w] = inc;
+        S.start[tid] = inc - t;
+    }
+    __syncthreads();
+    if (tid < kRadix) {
+        uint32_t before = 0;
+#pragma unroll
+        for (int q = 0; q < kWaves; ++q) before += (q < w) ? S.tmp[q] : 0u;
+        S.start[tid] += before;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < ITEMS; ++r) {
+        if (GJ_VALID(r)) {
+            const uint32_t d = digit_of<K>(key[r], a.dig);
+            pos[r] += S.start[d] + S.wcnt[w][d];
+            sk[pos[r]] = key[r];
+        }
+    }
+    __syncthreads();
+
+    uint32_t dst[ITEMS];
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) {
+        const uint32_t i = (uint32_t)(k * BLOCK + tid);
+        dst[k] = 0xFFFFFFFFu;
+        if (FULL || i < nt) {
+            const K kk = sk[i];
+            const uint32_t d = digit_of<K>(kk, a.dig);
+            const uint32_t t = S.cur[d] + i - S.start[d];
+            if (t < a.n_rows) {  // always true when the offsets are right
+                dst[k] = t;
+                kout[t] = kk;
+            }
+        }
+    }
+    // 4-byte keys sit in buffer 0, so the first column goes to buffer 1; 8-byte
+    // keys use both buffers and need a barrier before reuse.
+    int par = 1;
+    if constexpr (sizeof(K) == 8) {
+        __syncthreads();
+        par = 0;
+    }
+    for (int c0 = 0; c0 < n4; c0 += G) {
+        if (c0 > 0) {
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                if (c0 + g < n4) {
+                    const bool gen = (c0 + g == a.rowid_col);
+                    const uint32_t *__restrict__ in = static_cast<const uint32_t *>(a.col_in[c0 + g]);
+#pragma unroll
+                    for (int r = 0; r < ITEMS; ++r) {
+                        const uint32_t row = tile0 + lbase + r * kWave;
+                        v[g][r] = gen ? row : (GJ_VALID(r) ? in[row] : 0u);
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            if (c0 + g < n4) {
+                uint32_t *sb = s_buf[par];
+#pragma unroll
+                for (int r = 0; r < ITEMS; ++r)
+                    if (GJ_VALID(r)) sb[pos[r]] = v[g][r];
+                __syncthreads();
+                uint32_t *__restrict__ out = static_cast<uint32_t *>(a.col_out[c0 + g]);
+#pragma unroll
+                for (int k = 0; k < ITEMS; ++k)
+                    if (dst[k] != 0xFFFFFFFFu) out[dst[k]] = sb[k * BLOCK + tid];
+                par ^= 1;
+            }
+        }
+    }
+    for (int c = n4; c < a.ncols; ++c) {
+        uint64_t x[ITEMS];
+        const uint64_t *__restrict__ in = static_cast<const uint64_t *>(a.col_in[c]);
+#pragma unroll
+        for (int r = 0; r < ITEMS; ++r) x[r] = GJ_VALID(r) ? in[tile0 + lbase + r * kWave] : 0ull;
+        __syncthreads();  // both buffers free
+#pragma unroll
+        for (int r = 0; r < ITEMS; ++r)
+            if (GJ_VALID(r)) s8[pos[r]] = x[r];
+        __syncthreads();
+        uint64_t *__restrict__ out = static_cast<uint64_t *>(a.col_out[c]);
+#pragma unroll
+        for (int k = 0; k < ITEMS; ++k)
+            if (dst[k] != 0xFFFFFFFFu) out[dst[k]] = s8[k * BLOCK + tid];
+    }
+#undef GJ_VALID
+    __syncthreads();
+    if (tid < kRadix) S.cur[tid] += S.tot[tid];
+    __syncthreads();
+}
+
+template <typename K, int BLOCK, int ITEMS, int G>
+__global__ __launch_bounds__(BLOCK) void k_scatter(PassArgs a) {
+    constexpr uint32_t TILE = BLOCK * ITEMS;
+    __shared__ ScatterShared<BLOCK> S;
+    __shared__ uint32_t s_buf[2][TILE];  // double buffer for 4-byte columns; 8-byte data spans both
     __shared__ ChunkLoc s_loc;
 
     if (threadIdx.x == 0) s_loc = locate_chunk(a, blockIdx.x);
@@ -134,123 +323,14 @@ __global__ __launch_bounds__(kBlock) void k_scatter(PassArgs a) {
     if (!L.ok) return;
 
     const uint32_t R = 1u << a.bits;
-    const int tid = threadIdx.x, w = tid / kWave, lane = lane_id();
     const uint32_t base_off = a.seg_off[0];
-    for (uint32_t d = tid; d < kRadix; d += kBlock)
-        s_cur[d] = d < R ? base_off + a.hist[L.hbase + d * L.m + L.j] : 0u;
+    for (uint32_t d = threadIdx.x; d < kRadix; d += BLOCK)
+        S.cur[d] = d < R ? base_off + a.hist[L.hbase + d * L.m + L.j] : 0u;
 
-    const K *__restrict__ keys = static_cast<const K *>(a.key_in);
-    K *__restrict__ kout = static_cast<K *>(a.key_out);
-    K *sk = reinterpret_cast<K *>(s_buf);
-
-    for (uint32_t tile0 = L.row0; tile0 < L.row1; tile0 += TILE) {
-        const uint32_t nt = min(TILE, L.row1 - tile0);
-        for (int i = tid; i < kWaves * kRadix; i += kBlock) (&s_wcnt[0][0])[i] = 0;
-        __syncthreads();
-
-        K key[ITEMS];
-        uint32_t dg[ITEMS], pos[ITEMS];
-#pragma unroll
-        for (int r = 0; r < ITEMS; ++r) {
-            const uint32_t local = (uint32_t)(w * kWave * ITEMS + r * kWave + lane);
-            const bool valid = local < nt;
-            key[r] = valid ? keys[tile0 + local] : K(0);
-            const uint32_t d = digit_of<K>(key[r], a.dig);
-            const uint64_t peers = match_peers(d, a.bits, valid);
-            uint32_t p = 0;
-            if (valid) {
-                const uint32_t rk = rank_below(peers);
-                const uint32_t b = s_wcnt[w][d];
-                if (rk == 0) s_wcnt[w][d] = b + (uint32_t)__popcll(peers);
-                p = b + rk;
-            }
-            pos[r] = p;
-            dg[r] = valid ? d : 0xFFFFFFFFu;
-        }
-        __syncthreads();
-        {
-            // tid == digit: per-digit tile totals and cross-wave exclusive prefix
-            uint32_t t = 0;
-#pragma unroll
-            for (int q = 0; q < kWaves; ++q) {
-                const uint32_t c = s_wcnt[q][tid];
-                s_wcnt[q][tid] = t;
-                t += c;
-            }
-            s_tot[tid] = t;
-            s_start[tid] = block_exclusive_sum<uint32_t>(t, s_tmp, (uint32_t *)nullptr);
-        }
-        __syncthreads();
-#pragma unroll
-        for (int r = 0; r < ITEMS; ++r) {
-            if (dg[r] != 0xFFFFFFFFu) {
-                pos[r] += s_start[dg[r]] + s_wcnt[w][dg[r]];
-                sk[pos[r]] = key[r];
-            }
-        }
-        __syncthreads();
-
-        uint32_t dst[ITEMS];
-#pragma unroll
-        for (int k = 0; k < ITEMS; ++k) {
-            const uint32_t i = (uint32_t)(k * kBlock + tid);
-            dst[k] = 0;
-            if (i < nt) {
-                const K kk = sk[i];
-                const uint32_t d = digit_of<K>(kk, a.dig);
-                dst[k] = s_cur[d] + i - s_start[d];
-                if (dst[k] >= a.n_rows) dst[k] = 0xFFFFFFFFu;  // never taken when offsets are right
-                else kout[dst[k]] = kk;
-            }
-        }
-
-        for (int c = 0; c < a.ncols; ++c) {
-            __syncthreads();
-            if (a.col_w[c] == 4) {
-                uint32_t *sb = reinterpret_cast<uint32_t *>(s_buf);
-                if (c == a.rowid_col) {
-#pragma unroll
-                    for (int r = 0; r < ITEMS; ++r) {
-                        if (dg[r] != 0xFFFFFFFFu)
-                            sb[pos[r]] = tile0 + (uint32_t)(w * kWave * ITEMS + r * kWave + lane);
-                    }
-                } else {
-                    const uint32_t *__restrict__ in = static_cast<const uint32_t *>(a.col_in[c]);
-#pragma unroll
-                    for (int r = 0; r < ITEMS; ++r) {
-                        if (dg[r] != 0xFFFFFFFFu)
-                            sb[pos[r]] = in[tile0 + (uint32_t)(w * kWave * ITEMS + r * kWave + lane)];
-                    }
-                }
-                __syncthreads();
-                uint32_t *__restrict__ out = static_cast<uint32_t *>(a.col_out[c]);
-#pragma unroll
-                for (int k = 0; k < ITEMS; ++k) {
-                    const uint32_t i = (uint32_t)(k * kBlock + tid);
-                    if (i < nt && dst[k] != 0xFFFFFFFFu) out[dst[k]] = sb[i];
-                }
-            } else {
-                const uint64_t *__restrict__ in = static_cast<const uint64_t *>(a.col_in[c]);
-#pragma unroll
-                for (int r = 0; r < ITEMS; ++r) {
-                    if (dg[r] != 0xFFFFFFFFu) {
-                        const uint32_t row = tile0 + (uint32_t)(w * kWave * ITEMS + r * kWave + lane);
-                        s_buf[pos[r]] = in[row];
-                    }
-                }
-                __syncthreads();
-                uint64_t *__restrict__ out = static_cast<uint64_t *>(a.col_out[c]);
-#pragma unroll
-                for (int k = 0; k < ITEMS; ++k) {
-                    const uint32_t i = (uint32_t)(k * kBlock + tid);
-                    if (i < nt && dst[k] != 0xFFFFFFFFu) out[dst[k]] = s_buf[i];
-                }
-            }
-        }
-        __syncthreads();
-        s_cur[tid] += s_tot[tid];
-        __syncthreads();
-    }
+    uint32_t tile0 = L.row0;
+    for (; tile0 + TILE <= L.row1; tile0 += TILE)
+        scatter_tile<K, BLOCK, ITEMS, G, true>(a, S, s_buf, tile0, TILE);
+    if (tile0 < L.row1) scatter_tile<K, BLOCK, ITEMS, G, false>(a, S, s_buf, tile0, L.row1 - tile0);
 }
 
 __global__ void k_poff(const uint32_t *__restrict__ seg_off, uint32_t nseg,
@@ -275,14 +355,92 @@ __global__ void k_set_range(uint32_t *p, uint32_t a, uint32_t b) {
     }
 }
 
+// Scatter tile shapes (rows per thread x 4-byte columns loaded together). The
+// shape changes speed only; GJ_SCATTER_SHAPE=<items>x<group> picks one.
+struct Shape {
+    int block, items, group;
+};
+Shape scatter_shape() {
+    static Shape sh = [] {
+        Shape x{kScatterBlock, kItems, kGroup};
+        if (const char *e = getenv("GJ_SCATTER_SHAPE")) {
+            int b = 0, i = 0, g = 0;
+            if (sscanf(e, "%dx%dx%d", &b, &i, &g) == 3) x = Shape{b, i, g};
+        }
+        return x;
+    }();
+    return sh;
+}
+
+template <typename K>
+void launch_scatter(const Shape &sh, dim3 grid, hipStream_t s, const PassArgs &a, double bytes) {
+#define GJ_SC(B, I, G_)                                                                    \
+    if (sh.block == B && sh.items == I && sh.group == G_) {                                \
+        GJ_LAUNCH("k_scatter", bytes, (k_scatter<K, B, I, G_>), grid, dim3(B), 0, s, a);    \
+        return;                                                                            \
+    }
+    GJ_SC(256, 8, 4) GJ_SC(512, 8, 4) GJ_SC(1024, 8, 4) GJ_SC(512, 4, 4) GJ_SC(1024, 4, 4)
+    GJ_SC(256, 16, 2) GJ_SC(512, 8, 2)
+#undef GJ_SC
+    throw Error(GJ_EINVAL, "unknown scatter shape");
+}
+
+// Fills the column part of PassArgs: 4-byte columns first (the scatter loads them in
+// groups), then 8-byte ones. cin/cout are indexed by logical column (the row id, if
+// generated, is column cols.n); map[c] receives the slot of logical column c.
+void assign_cols(PassArgs &a, const PartCols &cols, const void *const *cin, void *const *cout, bool first_pass,
+                 int *map) {
+    const int ncols = cols.n + (cols.gen_rowid ? 1 : 0);
+    a.ncols = ncols;
+    a.rowid_col = -1;
+    a.n4 = 0;
+    int slot = 0;
+    for (int pass4 = 1; pass4 >= 0; --pass4) {
+        for (int c = 0; c < ncols; ++c) {
+            const bool is_rowid = cols.gen_rowid && c == cols.n;
+            const int w = is_rowid ? 4 : cols.width[c];
+            if ((w == 4) != (pass4 == 1)) continue;
+            a.col_w[slot] = w;
+            a.col_in[slot] = cin[c];
+            a.col_out[slot] = cout[c];
+            // the row id is generated in the first pass and moved like a payload afterwards
+            if (is_rowid && first_pass) a.rowid_col = slot;
+            map[c] = slot;
+            if (w == 4) a.n4++;
+            ++slot;
+        }
+    }
+}
+
+template <typename K>
+__global__ void k_key_bits(const K *__restrict__ keys, uint32_t n, unsigned long long *__restrict__ acc) {
+    // OR and AND of the order-preserving key bits over all keys
+    unsigned long long o = 0, x = ~0ull;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const unsigned long long v = digit_source<K>(keys[i], kDigitOrdered);
+        o |= v;
+        x &= v;
+    }
+    for (int d = kWave / 2; d > 0; d >>= 1) {
+        o |= __shfl_xor(o, d, kWave);
+        x &= __shfl_xor(x, d, kWave);
+    }
+    if (lane_id() == 0) {
+        atomicOr(&acc[0], o);
+        atomicAnd(&acc[1], x);
+    }
+}
+
 template <typename K>
 void run_pass(Ctx &ctx, PassArgs &a, uint32_t n) {
     hipStream_t s = ctx.stream;
     const uint32_t R = 1u << a.bits;
+    const Shape sh = scatter_shape();
+    const uint32_t tile = (uint32_t)(sh.block * sh.items);
     // Aim for ~4096 chunks: a few per resident workgroup, each a whole number of tiles.
-    uint32_t tiles = ceil_div_u32(n, kTile);
+    uint32_t tiles = ceil_div_u32(n, tile);
     uint32_t per = tiles > 4096 ? ceil_div_u32(tiles, 4096) : 1;
-    a.chunk_rows = per * kTile;
+    a.chunk_rows = per * tile;
     const uint64_t max_chunks = (uint64_t)ceil_div_u32(n, a.chunk_rows) + a.nseg;
     uint32_t *chunk_base = ctx.scratch_n<uint32_t>(a.nseg + 1);
     a.chunk_base = chunk_base;
@@ -298,8 +456,7 @@ void run_pass(Ctx &ctx, PassArgs &a, uint32_t n) {
     fill_u32(s, hist, 0u, hn);
     GJ_LAUNCH("k_hist", (double)n * sizeof(K), k_hist<K>, dim3((uint32_t)max_chunks), dim3(kBlock), 0, s, a);
     scan_exclusive_u32(ctx, hist, hist, hn, nullptr);
-    GJ_LAUNCH("k_scatter", (double)n * row_bytes, (k_scatter<K, kItems>), dim3((uint32_t)max_chunks),
-              dim3(kBlock), 0, s, a);
+    launch_scatter<K>(sh, dim3((uint32_t)max_chunks), s, a, (double)n * row_bytes);
 }
 
 }  // namespace
@@ -325,6 +482,7 @@ void partition_run(Ctx &ctx, int key_bytes, const void *key_in, void *key_out, c
     for (int c = 0; c < cols.n; ++c) cin[c] = cols.in[c];
     if (cols.gen_rowid) cin[cols.n] = nullptr;
 
+    int map[kMaxCols];
     uint32_t *seg = ctx.scratch_n<uint32_t>(2);
     GJ_LAUNCH("k_set_range", 8.0, k_set_range, dim3(1), dim3(64), 0, s, seg, 0u, n);
     uint32_t nseg = 1;
@@ -334,17 +492,13 @@ void partition_run(Ctx &ctx, int key_bytes, const void *key_in, void *key_out, c
         PassArgs a{};
         a.key_in = kin;
         a.key_out = last ? key_out : ctx.scratch((size_t)n * key_bytes);
-        a.ncols = ncols;
-        a.rowid_col = -1;
+        void *cout[kMaxCols];
         for (int c = 0; c < ncols; ++c) {
             const bool is_rowid = cols.gen_rowid && c == cols.n;
             const int w = is_rowid ? 4 : cols.width[c];
-            a.col_w[c] = w;
-            a.col_in[c] = cin[c];
-            a.col_out[c] = last ? (is_rowid ? cols.rowid_out : cols.out[c]) : ctx.scratch((size_t)n * w);
-            // the row id is generated in pass 1 and moved like a payload afterwards
-            if (is_rowid && p == 0) a.rowid_col = c;
+            cout[c] = last ? (is_rowid ? cols.rowid_out : cols.out[c]) : ctx.scratch((size_t)n * w);
         }
+        assign_cols(a, cols, cin, cout, p == 0, map);
         const int shift = bit_lo + (p == 0 ? b[1] : 0);
         a.bits = b[p];
         a.dig = DigitFn{mode, shift, (1u << b[p]) - 1u};
@@ -367,7 +521,78 @@ void partition_run(Ctx &ctx, int key_bytes, const void *key_in, void *key_out, c
         seg = next;
         nseg = (uint32_t)np;
         kin = a.key_out;
-        for (int c = 0; c < ncols; ++c) cin[c] = a.col_out[c];
+        for (int c = 0; c < ncols; ++c) cin[c] = a.col_out[map[c]];
+    }
+}
+
+
+void sort_run(Ctx &ctx, int key_bytes, const void *key_in, void *key_out, const PartCols &cols, uint32_t n) {
+    require(key_bytes == 4 || key_bytes == 8, "key width must be 4 or 8 bytes");
+    hipStream_t s = ctx.stream;
+    const int ncols = cols.n + (cols.gen_rowid ? 1 : 0);
+    // bytes of the order-preserving key that differ between keys; equal bytes need no pass
+    std::vector<int> passes;
+    if (n > 0) {
+        unsigned long long *acc = reinterpret_cast<unsigned long long *>(ctx.scratch_n<uint64_t>(2));
+        fill_u64(s, reinterpret_cast<uint64_t *>(acc), 0ull, 1);
+        fill_u64(s, reinterpret_cast<uint64_t *>(acc) + 1, ~0ull, 1);
+        const uint32_t grid = std::min<uint32_t>(ceil_div_u32(n, 256), 2048);
+        if (key_bytes == 4)
+            GJ_LAUNCH("k_key_bits", 4.0 * n, k_key_bits<int32_t>, dim3(grid), dim3(256), 0, s,
+                      static_cast<const int32_t *>(key_in), n, acc);
+        else
+            GJ_LAUNCH("k_key_bits", 8.0 * n, k_key_bits<int64_t>, dim3(grid), dim3(256), 0, s,
+                      static_cast<const int64_t *>(key_in), n, acc);
+        uint64_t h[2];
+        GJ_HIP(hipMemcpyAsync(h, acc, 16, hipMemcpyDeviceToHost, s));
+        GJ_HIP(hipStreamSynchronize(s));
+        const uint64_t diff = h[0] ^ h[1];
+        for (int b = 0; b < key_bytes; ++b)
+            if ((diff >> (8 * b)) & 0xFF) passes.push_back(b);
+    }
+    if (passes.empty()) passes.push_back(0);  // a pass on an equal digit is a stable copy
+    uint32_t *seg = ctx.scratch_n<uint32_t>(2);
+    GJ_LAUNCH("k_set_range", 8.0, k_set_range, dim3(1), dim3(64), 0, s, seg, 0u, n);
+    const void *kin = key_in;
+    const void *cin[kMaxCols];
+    for (int c = 0; c < cols.n; ++c) cin[c] = cols.in[c];
+    if (cols.gen_rowid) cin[cols.n] = nullptr;
+    void *bufk[2] = {nullptr, nullptr};
+    void *bufc[2][kMaxCols];
+    const int P = (int)passes.size();
+    for (int p = 0; p < P; ++p) {
+        const bool last = (p == P - 1);
+        PassArgs a{};
+        void *cout[kMaxCols];
+        void *kout;
+        if (last) {
+            kout = key_out;
+            for (int c = 0; c < ncols; ++c) cout[c] = (cols.gen_rowid && c == cols.n) ? cols.rowid_out : cols.out[c];
+        } else {
+            const int b = p & 1;
+            if (!bufk[b]) {
+                bufk[b] = ctx.scratch((size_t)n * key_bytes);
+                for (int c = 0; c < ncols; ++c)
+                    bufc[b][c] = ctx.scratch((size_t)n * ((cols.gen_rowid && c == cols.n) ? 4 : cols.width[c]));
+            }
+            kout = bufk[b];
+            for (int c = 0; c < ncols; ++c) cout[c] = bufc[b][c];
+        }
+        a.key_in = kin;
+        a.key_out = kout;
+        int map[kMaxCols];
+        assign_cols(a, cols, cin, cout, p == 0, map);
+        a.bits = 8;
+        a.dig = DigitFn{kDigitOrdered, 8 * passes[p], 0xFFu};
+        a.seg_off = seg;
+        a.nseg = 1;
+        a.n_rows = n;
+        if (n > 0) {
+            if (key_bytes == 4) run_pass<int32_t>(ctx, a, n);
+            else run_pass<int64_t>(ctx, a, n);
+        }
+        kin = kout;
+        for (int c = 0; c < ncols; ++c) cin[c] = cout[c];
     }
 }
 

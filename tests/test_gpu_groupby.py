@@ -1,0 +1,119 @@
+"""GPU parity: hash-, sort- and partition-based group-by (Sections 4.2, 4.1.3,
+4.3) against the oracle. Integer aggregates are compared exactly, groups
+matched by key."""
+import numpy as np
+import pytest
+
+import datagen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+AGGS = [(0, "count"), (0, "sum"), (0, "min"), (0, "max"), (1, "sum"), (1, "min"), (1, "max")]
+
+
+def gpu_groupby(keys, vals, aggs, **kw):
+    import paper_2312_00720_amd as gj
+    from gpu_util import dev, host, say
+    say(f"groupby n={len(keys)} key={keys.dtype} nv={len(vals)} {kw}")
+    k, res = gj.groupby(dev(keys), [dev(v) for v in vals], aggs, **kw)
+    return host(k), [host(r) for r in res]
+
+
+def expected(keys, vals, aggs):
+    o = oracle.groupby(keys, vals)
+    cols = []
+    for c, op in aggs:
+        if op == "count":
+            cols.append(o["count"])
+        else:
+            cols.append(o[op][c])
+    return o["key"], cols
+
+
+def check(keys, vals, aggs=AGGS, sorted_out=False, **kw):
+    gk, gcols = gpu_groupby(keys, vals, aggs, **kw)
+    ek, ecols = expected(keys, vals, aggs)
+    assert len(gk) == len(ek)
+    if sorted_out:
+        np.testing.assert_array_equal(gk, ek)  # sort-based group-by emits keys in order
+    order = np.argsort(gk, kind="stable")
+    np.testing.assert_array_equal(gk[order], ek)
+    for (c, op), g, e in zip(aggs, gcols, ecols):
+        assert g.dtype == (np.int64 if op in ("sum", "count") else np.int32)
+        np.testing.assert_array_equal(g[order], e, err_msg=f"{op}({c})")
+    return gk, gcols
+
+
+ALGOS = [("partition", "gftr"), ("partition", "gfur"), ("hash", "auto"), ("sort", "gftr"), ("sort", "gfur")]
+
+
+@pytest.mark.parametrize("algo,mat", ALGOS)
+@pytest.mark.parametrize("n,card,alpha", [(1000, 7, 0.0), (200003, 16, 0.0), (200003, 3000, 0.0),
+                                          (200003, 150000, 0.0), (300001, 4096, 1.0)])
+def test_groupby_matches_oracle(algo, mat, n, card, alpha):
+    d = datagen.groupby_input(n, card, 2, seed=datagen.seed_for(2, card + n), alpha=alpha)
+    check(d["key"], d["vals"], algo=algo, mat=mat, sorted_out=(algo == "sort"))
+
+
+@pytest.mark.parametrize("algo", ["partition", "hash", "sort"])
+def test_groupby_int64_keys(algo):
+    d = datagen.groupby_input(100000, 5000, 2, seed=12, key_bytes=8)
+    check(d["key"], d["vals"], algo=algo, sorted_out=(algo == "sort"))
+
+
+@pytest.mark.parametrize("algo", ["partition", "hash", "sort"])
+def test_groupby_edge_keys(algo):
+    """Keys at the extremes of the signed range, including the value the LDS
+    tables use as their empty marker, and a single group."""
+    g = datagen.rng(3)
+    for dt, lo, hi in [(np.int32, -2**31, 2**31 - 1), (np.int64, -2**63, 2**63 - 1)]:
+        keys = np.array([lo, hi, 0, -1, lo, lo, 5, hi] * 1000, dtype=dt)
+        vals = [g.integers(-2**20, 2**20 + 1, size=len(keys)).astype(np.int32) for _ in range(2)]
+        check(keys, vals, algo=algo, sorted_out=(algo == "sort"))
+    keys = np.full(50000, 42, np.int32)
+    vals = [g.integers(-2**20, 2**20 + 1, size=50000).astype(np.int32) for _ in range(2)]
+    check(keys, vals, algo=algo, sorted_out=(algo == "sort"))
+
+
+@pytest.mark.parametrize("algo", ["partition", "hash", "sort"])
+def test_groupby_tiny_and_empty(algo):
+    for n in (0, 1, 2, 17):
+        keys = np.arange(n, dtype=np.int32) % 3
+        vals = [np.arange(n, dtype=np.int32) - 5, np.full(n, 7, np.int32)]
+        check(keys, vals, algo=algo, sorted_out=(algo == "sort"))
+
+
+def test_aggregate_list_variants():
+    d = datagen.groupby_input(50000, 300, 3, seed=4)
+    for aggs in ([(0, "count")], [(2, "max"), (0, "sum"), (2, "max"), (1, "min")], [(1, "sum")] * 3):
+        for algo in ("partition", "hash", "sort"):
+            check(d["key"], d["vals"], aggs=aggs, algo=algo)
+
+
+def test_partition_overflow_falls_back():
+    """Two partitions for 20000 distinct keys overflow the per-partition LDS table;
+    the result must still be exact."""
+    d = datagen.groupby_input(60000, 20000, 2, seed=5)
+    check(d["key"], d["vals"], algo="partition", radix_bits=1)
+
+
+def test_hash_global_aggregation_path():
+    d = datagen.groupby_input(100000, 2000, 2, seed=6)
+    check(d["key"], d["vals"], algo="hash", lds_budget=64)
+
+
+@pytest.mark.parametrize("bits", [1, 4, 9, 16])
+def test_partition_bits_do_not_change_results(bits):
+    d = datagen.groupby_input(120000, 1500, 2, seed=7, alpha=0.8)
+    check(d["key"], d["vals"], algo="partition", radix_bits=bits)
+
+
+@pytest.mark.parametrize("algo", ["partition", "sort"])
+def test_groupby_deterministic(algo):
+    d = datagen.groupby_input(150000, 20000, 2, seed=8)
+    a = gpu_groupby(d["key"], d["vals"], AGGS, algo=algo)
+    b = gpu_groupby(d["key"], d["vals"], AGGS, algo=algo)
+    np.testing.assert_array_equal(a[0], b[0])
+    for x, y in zip(a[1], b[1]):
+        np.testing.assert_array_equal(x, y)
