@@ -68,6 +68,72 @@ def copy_ceiling(nbytes: int = 1 << 31, reps: int = 5) -> float:
     return 2.0 * nbytes / (ms / 1e3) / 1e9
 
 
+GB_AGGS = [(0, "count"), (0, "sum"), (0, "min"), (0, "max"), (1, "sum"), (1, "min"), (1, "max")]
+
+
+def timed(step, steps, warmup):
+    """Warm up, then time `steps` calls with per-launch event profiling on."""
+    import torch
+    import paper_2312_00720_amd as gj
+    out = None
+    for _ in range(warmup):
+        out = step()
+        del out
+    torch.cuda.synchronize()
+    gj.profile_start()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        out = step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    stats = gj.profile_stop()
+    return (t1 - t0) / steps * 1e3, stats, out
+
+
+def kernel_table(stats, steps):
+    kern = {k: dict(v, ms_per_step=v["total_ms"] / steps,
+                    gbs=(v["alg_bytes"] / (v["total_ms"] / 1e3) / 1e9) if v["total_ms"] > 0 else 0.0)
+            for k, v in stats.items()}
+    return dict(sorted(kern.items(), key=lambda x: -x[1]["total_ms"]))
+
+
+def bench_groupby(args, copy_gbs) -> int:
+    import torch
+    import datagen
+    import datagen.device as dd
+    import paper_2312_00720_amd as gj
+    n, g = 1 << args.n_log2, 1 << args.g_log2
+    log(f"generating group-by N=2^{args.n_log2} g=2^{args.g_log2} alpha={args.alpha}")
+    d = dd.groupby_input(n, g, 2, seed=datagen.seed_for(2, args.g_log2), alpha=args.alpha)
+    torch.cuda.synchronize()
+    mat = args.mat if args.algo != "hash" else "auto"
+
+    def step():
+        return gj.groupby(d["key"], d["vals"], GB_AGGS, algo=args.algo, mat=mat)
+
+    ms, stats, out = timed(step, args.steps, args.warmup)
+    groups = out[0].numel()
+    kern = kernel_table(stats, args.steps)
+    dom = next(iter(kern))
+    dk = kern[dom]
+    res = {
+        "metric": "group-by rows/s", "value": n / (ms / 1e3), "unit": "rows/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+        "config": {"workload": f"group-by N=2^{args.n_log2}, int32 key over 2^{args.g_log2} values "
+                               f"({'uniform' if args.alpha == 0 else f'zipf {args.alpha}'}), 2 int32 values, "
+                               f"COUNT+SUM+MIN+MAX, {args.algo}" + ("" if args.algo == "hash" else f" {mat.upper()}"),
+                   "groups": groups},
+        "copy_ceiling_gbs": copy_gbs,
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": dk["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": dk["gbs"] / HBM_PEAK_GBS, "traffic": None},
+        "kernels": {k: {"launches_per_step": v["launches"] / args.steps, "ms_per_step": v["ms_per_step"],
+                        "alg_gbs": v["gbs"]} for k, v in kern.items()},
+    }
+    print(json.dumps(res), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -81,6 +147,10 @@ def main() -> int:
     ap.add_argument("--alpha", type=float, default=0.0)
     ap.add_argument("--match-ratio", type=float, default=1.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", default="join", choices=["join", "groupby"])
+    ap.add_argument("--n-log2", type=int, default=28, help="group-by rows")
+    ap.add_argument("--g-log2", type=int, default=16, help="group-by key cardinality")
+    ap.add_argument("--algo", default="partition", choices=["partition", "hash", "sort"])
     ap.add_argument("--copy-only", action="store_true",
                     help="only run the plain copy (counter calibration) and print its GB/s")
     args = ap.parse_args()
@@ -100,6 +170,9 @@ def main() -> int:
         return 0
     copy_gbs = copy_ceiling()
     log(f"plain copy: {copy_gbs:.0f} GB/s")
+
+    if args.workload == "groupby":
+        return bench_groupby(args, copy_gbs)
 
     n_r, n_s, c = 1 << args.r_log2, 1 << args.s_log2, args.payloads
     log(f"generating |R|=2^{args.r_log2} |S|=2^{args.s_log2} payloads={c} key_bytes={args.key_bytes}")

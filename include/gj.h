@@ -105,6 +105,31 @@ typedef struct {
 int gj_join(const gj_rel *R, const gj_rel *S, const gj_join_opts *opts,
             const gj_allocator *alloc, void *stream, gj_join_out *out);
 
+/* A batch of independent relations stored back to back ("ragged" layout):
+ * instance i owns rows [offsets[i], offsets[i+1]) of every column. */
+typedef struct {
+    gj_col key;
+    const gj_col *payloads; /* n_payloads concatenated columns */
+    int32_t n_payloads;     /* 0..8 */
+    const int64_t *offsets; /* host array of n_instances + 1 row offsets, offsets[0] = 0 */
+    int32_t n_instances;
+} gj_rel_batch;
+
+/*
+ * Many independent joins T_i = R_i |><| S_i in one call (no counterpart in the
+ * paper; the method of gj_join applied to every instance at once). Instance i is
+ * a segment of one partitioning pass with its own partition bits (at most 8), and
+ * one count pass, one scan and one write pass serve all instances, so the number
+ * of kernel launches does not grow with the number of instances.
+ * R and S must have the same n_instances, key dtype, and payload column counts
+ * and dtypes per side across the batch. The output T is concatenated in instance
+ * order; out_offsets (host, n_instances + 1 entries) receives where each
+ * instance's rows begin. Each side's total row count must be below 2^31
+ * (GJ_EOVERFLOW otherwise). Synchronizes with `stream` twice.
+ */
+int gj_join_batch(const gj_rel_batch *R, const gj_rel_batch *S, const gj_join_opts *opts,
+                  const gj_allocator *alloc, void *stream, gj_join_out *out, int64_t *out_offsets);
+
 typedef enum { GJ_SUM = 1, GJ_COUNT = 2, GJ_MIN = 3, GJ_MAX = 4 } gj_agg_op;
 typedef struct {
     int32_t col; /* value column index (ignored for GJ_COUNT) */
@@ -166,6 +191,65 @@ int gj_partition(gj_col key, const gj_col *cols, int32_t n_cols, int64_t n_rows,
                  int32_t bit_lo, int32_t bits, int32_t passes, int32_t mode,
                  void *out_key, void *const *out_cols, void *out_rowid, int32_t *out_offsets,
                  const gj_allocator *alloc, void *stream);
+
+/* ---- Algorithm selection -----------------------------------------------------
+ * Workload features (12 floats, each scaled to about [0, 1]):
+ *   [0] 1 for a join, 0 for a group-by
+ *   [1] log2 |R| / 32 (group-by: log2 N / 32)
+ *   [2] log2 |S| / 32 (group-by: 0)
+ *   [3] log2 g / 32 (join: log2 |R| / 32)
+ *   [4] key bytes / 8
+ *   [5] R payload columns / 8 (group-by: value columns / 8)
+ *   [6] S payload columns / 8 (group-by: 0)
+ *   [7] Zipf factor of the foreign keys or group keys / 1.2
+ *   [8] match ratio (group-by: 1)
+ *   [9] log2(|S| / |R|) / 32 (group-by: log2(N / g) / 32)
+ *   [10] log2 expected output rows / 32
+ *   [11] log2 input bytes / 48
+ * Classes: 0 GFTR join, 1 GFUR join, 2 hash, 3 sort, 4 partition group-by.
+ * op_kind 0 = join (classes 0-1 valid), 1 = group-by (classes 2-4 valid). */
+
+/* The analytical model: predicted seconds per class (infinity for invalid
+ * classes), built on the paper's bandwidth models (Sections 4.1.3, 4.1.4) over
+ * this implementation's passes, with MI355X constants. */
+int gj_cost_model(const float features[12], int32_t op_kind, double predicted_seconds[5]);
+
+/* The class to run: the learned network's argmax when weights are loaded and its
+ * output is finite, else the cost model's argmin. probs (may be NULL) receives
+ * the network's probabilities, or a one-hot of the cost model's choice. The
+ * choice never changes a result. */
+int gj_select(const float features[12], int32_t op_kind, int32_t *choice, float probs[5]);
+
+/* Load trained network weights (host array of GJ_MLP_PARAMS floats; NULL or n = 0
+ * unloads them). Thread-safe. */
+int gj_selector_set_weights(const float *params, int32_t n);
+
+/* Override the cost model's constants (bytes/s of streaming, B_G/B_R of 4-byte
+ * gathers, scattered global atomics per second). */
+int gj_set_cost_constants(double seq_bytes_per_s, double rand_ratio, double atomic_rate);
+
+/* ---- Selector network ------------------------------------------------------
+ * 12 workload features -> 64 -> 64 (ReLU) -> 5 logits over {GFTR, GFUR, hash,
+ * sort, partition}, softmax over the classes valid for the sample (mask), loss =
+ * batch mean of -log p[label]. FP32; parameters are one flat device vector of
+ * GJ_MLP_PARAMS floats: W1 (64x12 row-major), b1, W2 (64x64), b2, W3 (5x64), b3.
+ * X is [batch x 12], mask [batch x 5] (1 = valid class), labels [batch], all
+ * device arrays. Results are deterministic (fixed summation order). */
+#define GJ_MLP_PARAMS 5317
+
+/* probs [batch x 5] = masked softmax of the network's logits. */
+int gj_mlp_forward(const float *params, const float *X, const float *mask, int32_t batch, float *probs,
+                   const gj_allocator *alloc, void *stream);
+
+/* grad [GJ_MLP_PARAMS] = gradient of the batch-mean cross-entropy; *loss (device,
+ * may be NULL) = that loss. */
+int gj_mlp_grad(const float *params, const float *X, const float *mask, const int32_t *labels,
+                int32_t batch, float *grad, float *loss, const gj_allocator *alloc, void *stream);
+
+/* One Adam step (Kingma and Ba, 2015) with bias correction at step t >= 1,
+ * updating params, m and v in place (device arrays of GJ_MLP_PARAMS). */
+int gj_mlp_adam(float *params, const float *grad, float *m, float *v, int32_t t, float lr, float beta1,
+                float beta2, float eps, void *stream);
 
 /* Per-kernel timing of this thread's launches (for benchmarks and phase
  * breakdowns). */

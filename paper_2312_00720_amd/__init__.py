@@ -48,6 +48,11 @@ class Allocator(ctypes.Structure):
     _fields_ = [("alloc", _ALLOC_FN), ("free", _FREE_FN), ("ctx", ctypes.c_void_p)]
 
 
+class RelBatch(ctypes.Structure):
+    _fields_ = [("key", Col), ("payloads", ctypes.POINTER(Col)), ("n_payloads", ctypes.c_int32),
+                ("offsets", ctypes.POINTER(ctypes.c_int64)), ("n_instances", ctypes.c_int32)]
+
+
 class JoinOpts(ctypes.Structure):
     _fields_ = [("mat", ctypes.c_int32), ("unique_build_keys", ctypes.c_int32),
                 ("radix_bits", ctypes.c_int32), ("passes", ctypes.c_int32),
@@ -97,6 +102,10 @@ def lib() -> ctypes.CDLL:
             L.gj_join.restype = ctypes.c_int
             L.gj_join.argtypes = [ctypes.POINTER(Rel), ctypes.POINTER(Rel), ctypes.POINTER(JoinOpts),
                                   ctypes.POINTER(Allocator), vp, ctypes.POINTER(JoinOut)]
+            L.gj_join_batch.restype = ctypes.c_int
+            L.gj_join_batch.argtypes = [ctypes.POINTER(RelBatch), ctypes.POINTER(RelBatch),
+                                        ctypes.POINTER(JoinOpts), ctypes.POINTER(Allocator), vp,
+                                        ctypes.POINTER(JoinOut), ctypes.POINTER(ctypes.c_int64)]
             L.gj_partition.restype = ctypes.c_int
             L.gj_partition.argtypes = [Col, ctypes.POINTER(Col), i32, i64, i32, i32, i32, i32,
                                        vp, ctypes.POINTER(vp), vp, vp, ctypes.POINTER(Allocator), vp]
@@ -108,6 +117,23 @@ def lib() -> ctypes.CDLL:
             L.gj_profile_start.argtypes = []
             L.gj_profile_stop.restype = ctypes.c_int
             L.gj_profile_stop.argtypes = [ctypes.POINTER(KernelStat), i32, ctypes.POINTER(i32)]
+            fp = ctypes.c_void_p
+            L.gj_cost_model.restype = ctypes.c_int
+            L.gj_cost_model.argtypes = [ctypes.POINTER(ctypes.c_float), i32, ctypes.POINTER(ctypes.c_double)]
+            L.gj_select.restype = ctypes.c_int
+            L.gj_select.argtypes = [ctypes.POINTER(ctypes.c_float), i32, ctypes.POINTER(i32),
+                                    ctypes.POINTER(ctypes.c_float)]
+            L.gj_selector_set_weights.restype = ctypes.c_int
+            L.gj_selector_set_weights.argtypes = [ctypes.POINTER(ctypes.c_float), i32]
+            L.gj_set_cost_constants.restype = ctypes.c_int
+            L.gj_set_cost_constants.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double]
+            L.gj_mlp_forward.restype = ctypes.c_int
+            L.gj_mlp_forward.argtypes = [fp, fp, fp, i32, fp, ctypes.POINTER(Allocator), vp]
+            L.gj_mlp_grad.restype = ctypes.c_int
+            L.gj_mlp_grad.argtypes = [fp, fp, fp, fp, i32, fp, fp, ctypes.POINTER(Allocator), vp]
+            L.gj_mlp_adam.restype = ctypes.c_int
+            L.gj_mlp_adam.argtypes = [fp, fp, fp, fp, i32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                      ctypes.c_float, vp]
             L.gj_last_error.restype = ctypes.c_char_p
             L.gj_last_error.argtypes = []
             L.gj_version.restype = ctypes.c_char_p
@@ -203,6 +229,42 @@ def join(r_key: torch.Tensor, r_pay, s_key: torch.Tensor, s_pay, *, mat: str = "
     return key, rr, ss
 
 
+def join_batch(r_key: torch.Tensor, r_pay, r_offsets, s_key: torch.Tensor, s_pay, s_offsets, *,
+               mat: str = "auto", lds_budget: int = 0):
+    """Many independent joins in one call. Columns hold the instances back to back;
+    r_offsets / s_offsets (length n+1, host ints) delimit them. Returns
+    (key, [R payloads], [S payloads], offsets) with the output concatenated in
+    instance order and offsets[i] its first row of instance i."""
+    L = lib()
+    r_pay, s_pay = list(r_pay), list(s_pay)
+    dev = r_key.device
+    _check_cols([r_key, *r_pay], r_key.numel(), dev)
+    _check_cols([s_key, *s_pay], s_key.numel(), dev)
+    n = len(r_offsets) - 1
+    if len(s_offsets) != n + 1 or n < 1:
+        raise ValueError("offsets of R and S must have the same length >= 2")
+    ro = (ctypes.c_int64 * (n + 1))(*[int(x) for x in r_offsets])
+    so = (ctypes.c_int64 * (n + 1))(*[int(x) for x in s_offsets])
+    rp = (Col * max(1, len(r_pay)))(*[_col(t) for t in r_pay])
+    sp = (Col * max(1, len(s_pay)))(*[_col(t) for t in s_pay])
+    R = RelBatch(_col(r_key), rp, len(r_pay), ro, n)
+    S = RelBatch(_col(s_key), sp, len(s_pay), so, n)
+    o = JoinOpts(MAT[mat], 0, 0, 0, 0, 0.0, lds_budget, 0)
+    rpo = (ctypes.c_void_p * max(1, len(r_pay)))()
+    spo = (ctypes.c_void_p * max(1, len(s_pay)))()
+    out = JoinOut(None, rpo, spo, 0)
+    offs = (ctypes.c_int64 * (n + 1))()
+    A = _TorchAllocator(dev)
+    rc = L.gj_join_batch(ctypes.byref(R), ctypes.byref(S), ctypes.byref(o), ctypes.byref(A.struct),
+                         _stream(dev), ctypes.byref(out), offs)
+    _raise(rc)
+    t = out.n_rows
+    key = A.take(out.key, r_key.dtype, t)
+    rr = [A.take(rpo[i], r_pay[i].dtype, t) for i in range(len(r_pay))]
+    ss = [A.take(spo[i], s_pay[i].dtype, t) for i in range(len(s_pay))]
+    return key, rr, ss, [int(offs[i]) for i in range(n + 1)]
+
+
 def partition(key: torch.Tensor, cols=(), *, bit_lo: int = 0, bits: int = 8, passes: int = 0,
               mode: str = "bits", rowid: bool = False):
     """Stable radix partition. Returns (key', [cols'], rowid' or None, offsets[2^bits+1])."""
@@ -251,6 +313,67 @@ def groupby(key: torch.Tensor, vals, aggs, *, algo: str = "auto", mat: str = "au
         dt = torch.int64 if op in ("sum", "count") else vals[c].dtype
         res.append(A.take(ao[i], dt, g))
     return keys, res
+
+
+MLP_PARAMS = 5317
+CLASSES = ["gftr", "gfur", "hash", "sort", "partition"]
+
+
+def cost_model(features, op_kind: int):
+    """Predicted seconds per class (inf for classes invalid for op_kind)."""
+    f = (ctypes.c_float * 12)(*[float(x) for x in features])
+    out = (ctypes.c_double * 5)()
+    _raise(lib().gj_cost_model(f, op_kind, out))
+    return [out[i] for i in range(5)]
+
+
+def select(features, op_kind: int):
+    """(class index, probabilities) chosen by the network, else the cost model."""
+    f = (ctypes.c_float * 12)(*[float(x) for x in features])
+    c = ctypes.c_int32(-1)
+    p = (ctypes.c_float * 5)()
+    _raise(lib().gj_select(f, op_kind, ctypes.byref(c), p))
+    return c.value, [p[i] for i in range(5)]
+
+
+def selector_set_weights(params) -> None:
+    """Load trained weights (5317 floats) into the library; None unloads them."""
+    if params is None:
+        _raise(lib().gj_selector_set_weights(None, 0))
+        return
+    arr = (ctypes.c_float * MLP_PARAMS)(*[float(x) for x in params])
+    _raise(lib().gj_selector_set_weights(arr, MLP_PARAMS))
+
+
+def set_cost_constants(seq_bytes_per_s: float, rand_ratio: float, atomic_rate: float) -> None:
+    _raise(lib().gj_set_cost_constants(seq_bytes_per_s, rand_ratio, atomic_rate))
+
+
+def mlp_forward(params: torch.Tensor, X: torch.Tensor, mask: torch.Tensor) -> torch.Tensor:
+    """Masked softmax probabilities [B, 5] of the selector network (FP32, device)."""
+    B = X.shape[0]
+    out = torch.empty((B, 5), dtype=torch.float32, device=X.device)
+    A = _TorchAllocator(X.device)
+    _raise(lib().gj_mlp_forward(params.data_ptr(), X.data_ptr(), mask.data_ptr(), B, out.data_ptr(),
+                                ctypes.byref(A.struct), _stream(X.device)))
+    return out
+
+
+def mlp_grad(params: torch.Tensor, X: torch.Tensor, mask: torch.Tensor, y: torch.Tensor):
+    """(loss, gradient) of the batch-mean cross-entropy (FP32, device)."""
+    B = X.shape[0]
+    g = torch.empty(MLP_PARAMS, dtype=torch.float32, device=X.device)
+    loss = torch.empty(1, dtype=torch.float32, device=X.device)
+    A = _TorchAllocator(X.device)
+    _raise(lib().gj_mlp_grad(params.data_ptr(), X.data_ptr(), mask.data_ptr(), y.data_ptr(), B, g.data_ptr(),
+                             loss.data_ptr(), ctypes.byref(A.struct), _stream(X.device)))
+    return loss, g
+
+
+def mlp_adam(params, grad, m, v, t: int, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8) -> None:
+    """In-place Adam step on device tensors."""
+    _raise(lib().gj_mlp_adam(params.data_ptr(), grad.data_ptr(), m.data_ptr(), v.data_ptr(), t, lr, b1, b2, eps,
+                             _stream(params.device)))
 
 
 def profile_start() -> None:

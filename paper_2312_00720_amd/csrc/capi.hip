@@ -3,6 +3,7 @@
 #include <string.h>
 
 #include <string>
+#include <vector>
 
 #include "internal.hpp"
 
@@ -115,7 +116,13 @@ int gj_join(const gj_rel *R, const gj_rel *S, const gj_join_opts *opts, const gj
         if (R->n_rows == 0 || S->n_rows == 0) return GJ_OK;
 
         const int kb = dtype_bytes(R->key.dtype);
-        const bool gfur = (o.mat == GJ_MAT_GFUR);
+        int mat = o.mat;
+        if (mat == GJ_MAT_AUTO) {
+            float f[12];
+            gj::features_join(f, (double)R->n_rows, (double)S->n_rows, kb, R->n_payloads, S->n_payloads);
+            mat = gj::select_algorithm(f, 0, nullptr) == 1 ? GJ_MAT_GFUR : GJ_MAT_GFTR;
+        }
+        const bool gfur = (mat == GJ_MAT_GFUR);
         const int r_block = o.lds_budget ? o.lds_budget : 4096;
         // Partitions of about r_block/2 R rows on average leave room for variance.
         int bits = o.radix_bits;
@@ -182,6 +189,120 @@ int gj_join(const gj_rel *R, const gj_rel *S, const gj_join_opts *opts, const gj
     }
 }
 
+int gj_join_batch(const gj_rel_batch *R, const gj_rel_batch *S, const gj_join_opts *opts,
+                  const gj_allocator *alloc, void *stream, gj_join_out *out, int64_t *out_offsets) {
+    try {
+        g_last_error.clear();
+        gj::require(R && S && out && out_offsets, "null argument");
+        const int32_t n = R->n_instances;
+        gj::require(n >= 1 && S->n_instances == n, "R and S need the same positive instance count");
+        gj::require(R->offsets && S->offsets, "null offsets");
+        gj::require(R->key.dtype == S->key.dtype, "R.key and S.key dtypes differ");
+        const gj_rel_batch *rel[2] = {R, S};
+        for (int t = 0; t < 2; ++t) {
+            const gj_rel_batch *X = rel[t];
+            gj::require(X->offsets[0] == 0, "offsets[0] must be 0");
+            for (int i = 0; i < n; ++i) gj::require(X->offsets[i + 1] >= X->offsets[i], "offsets must not decrease");
+            gj::require(X->offsets[n] <= kMaxRows, "a side of the batch has more than 2^31-1 rows", GJ_EOVERFLOW);
+            gj::require(X->n_payloads >= 0 && X->n_payloads <= 8, "0..8 payload columns");
+            gj::require(X->n_payloads == 0 || X->payloads, "null payload array");
+            check_col(X->key, X->offsets[n], "key");
+            for (int i = 0; i < X->n_payloads; ++i) check_col(X->payloads[i], X->offsets[n], "payload");
+        }
+        gj::require(R->n_payloads == 0 || out->r_payloads, "null r_payloads array");
+        gj::require(S->n_payloads == 0 || out->s_payloads, "null s_payloads array");
+        gj_join_opts o{};
+        if (opts) o = *opts;
+        gj::require(o.mat >= 0 && o.mat <= 2, "bad materialization");
+        gj::require(o.lds_budget == 0 || (o.lds_budget >= 64 && o.lds_budget <= 4096), "lds_budget must be 64..4096");
+        gj::require(o.flags == 0, "flags must be 0");
+        out->n_rows = 0;
+        out->key = nullptr;
+        for (int i = 0; i < R->n_payloads; ++i) out->r_payloads[i] = nullptr;
+        for (int i = 0; i < S->n_payloads; ++i) out->s_payloads[i] = nullptr;
+        for (int i = 0; i <= n; ++i) out_offsets[i] = 0;
+        const uint32_t nr = (uint32_t)R->offsets[n], ns = (uint32_t)S->offsets[n];
+        if (nr == 0 || ns == 0) return GJ_OK;
+
+        const int kb = dtype_bytes(R->key.dtype);
+        const bool gfur = (o.mat == GJ_MAT_GFUR);
+        const int r_block = o.lds_budget ? o.lds_budget : 4096;
+        const uint64_t target = (uint64_t)std::max(1, r_block / 2);
+        std::vector<uint8_t> bits(n);
+        std::vector<uint32_t> roff(n + 1), soff(n + 1);
+        for (int i = 0; i < n; ++i) {
+            const uint64_t rows = (uint64_t)(R->offsets[i + 1] - R->offsets[i]);
+            bits[i] = (uint8_t)std::min(8, ceil_log2((rows + target - 1) / target));
+        }
+        for (int i = 0; i <= n; ++i) {
+            roff[i] = (uint32_t)R->offsets[i];
+            soff[i] = (uint32_t)S->offsets[i];
+        }
+        gj::Ctx ctx(alloc, (hipStream_t)stream);
+        hipStream_t st = (hipStream_t)stream;
+        uint8_t *d_bits = static_cast<uint8_t *>(ctx.scratch(n));
+        uint32_t *d_off[2] = {ctx.scratch_n<uint32_t>(n + 1), ctx.scratch_n<uint32_t>(n + 1)};
+        GJ_HIP(hipMemcpyAsync(d_bits, bits.data(), n, hipMemcpyHostToDevice, st));
+        GJ_HIP(hipMemcpyAsync(d_off[0], roff.data(), 4ull * (n + 1), hipMemcpyHostToDevice, st));
+        GJ_HIP(hipMemcpyAsync(d_off[1], soff.data(), 4ull * (n + 1), hipMemcpyHostToDevice, st));
+
+        gj::JoinSide side[2];
+        for (int t = 0; t < 2; ++t) {
+            const gj_rel_batch *X = rel[t];
+            const uint32_t rows = (uint32_t)X->offsets[n];
+            gj::PartCols pc;
+            void *kout = ctx.scratch((size_t)rows * kb);
+            gj::JoinSide &js = side[t];
+            js.key = kout;
+            js.rows = rows;
+            js.n_pay = X->n_payloads;
+            for (int i = 0; i < X->n_payloads; ++i) js.width[i] = dtype_bytes(X->payloads[i].dtype);
+            if (!gfur) {
+                pc.n = X->n_payloads;
+                for (int i = 0; i < X->n_payloads; ++i) {
+                    pc.in[i] = X->payloads[i].data;
+                    pc.width[i] = js.width[i];
+                    pc.out[i] = ctx.scratch((size_t)rows * js.width[i]);
+                    js.pay[i] = pc.out[i];
+                }
+                js.rowid = nullptr;
+            } else {
+                pc.gen_rowid = true;
+                pc.rowid_out = ctx.scratch((size_t)rows * 4);
+                for (int i = 0; i < X->n_payloads; ++i) js.pay[i] = X->payloads[i].data;
+                js.rowid = static_cast<const int32_t *>(pc.rowid_out);
+            }
+            uint32_t *poff = ctx.scratch_n<uint32_t>(((size_t)n << 8) + 1);
+            js.poff = poff;
+            gj::partition_run_segments(ctx, kb, X->key.data, kout, pc, rows, d_off[t], (uint32_t)n, d_bits, poff);
+        }
+        uint64_t *inst_off = ctx.scratch_n<uint64_t>(n + 1);
+        gj::JoinOut jo{};
+        const int64_t T = gj::join_partitioned(ctx, kb, side[0], side[1], 0, r_block, gfur, &jo, d_bits, (uint32_t)n,
+                                               inst_off);
+        std::vector<uint64_t> h(n + 1);
+        GJ_HIP(hipMemcpyAsync(h.data(), inst_off, 8ull * (n + 1), hipMemcpyDeviceToHost, st));
+        GJ_HIP(hipStreamSynchronize(st));
+        for (int i = 0; i <= n; ++i) out_offsets[i] = (int64_t)h[i];
+        out->n_rows = T;
+        if (T > 0) {
+            out->key = jo.key;
+            for (int i = 0; i < R->n_payloads; ++i) out->r_payloads[i] = jo.r[i];
+            for (int i = 0; i < S->n_payloads; ++i) out->s_payloads[i] = jo.s[i];
+        }
+        ctx.commit();
+        return GJ_OK;
+    } catch (const gj::Error &e) {
+        if (out) {
+            out->n_rows = 0;
+            out->key = nullptr;
+        }
+        return fail(e.code, e.what());
+    } catch (const std::exception &e) {
+        return fail(GJ_EHIP, e.what());
+    }
+}
+
 int gj_groupby(gj_col key, const gj_col *vals, int32_t n_vals, int64_t n_rows, const gj_agg *aggs,
                int32_t n_aggs, const gj_groupby_opts *opts, const gj_allocator *alloc, void *stream,
                gj_groupby_out *out) {
@@ -220,7 +341,13 @@ int gj_groupby(gj_col key, const gj_col *vals, int32_t n_vals, int64_t n_rows, c
         const int kb = dtype_bytes(key.dtype);
         const uint32_t n = (uint32_t)n_rows;
         const bool gfur = (o.mat == GJ_MAT_GFUR);
-        int algo = o.algo == GJ_GB_AUTO ? GJ_GB_PARTITION : o.algo;
+        int algo = o.algo;
+        if (algo == GJ_GB_AUTO) {
+            float f[12];
+            gj::features_groupby(f, (double)n, kb, n_vals);
+            const int c = gj::select_algorithm(f, 1, nullptr);
+            algo = c == 2 ? GJ_GB_HASH : (c == 3 ? GJ_GB_SORT : GJ_GB_PARTITION);
+        }
         const int32_t *vcols[8];
         for (int i = 0; i < n_vals; ++i) vcols[i] = static_cast<const int32_t *>(vals[i].data);
 

@@ -21,6 +21,7 @@ constexpr int kMaxAggs = 16;
 constexpr int kMaxVals = 8;
 constexpr uint32_t kDiscoverCap = 4096;  // LDS table slots of the discover pass
 constexpr uint32_t kUnitRows = 8192;     // rows per aggregation work unit
+constexpr uint32_t kDiscoverUnit = 65536; // partitions above this size are discovered by several workgroups
 
 struct AggSpec {
     int n;
@@ -118,6 +119,217 @@ __device__ __forceinline__ void row_add_global(const AggSpec &s, const ValSrc &v
     }
 }
 
+// Values of one row for value columns 0..NV-1 (NV >= the number of columns in use).
+template <int NV>
+struct Row {
+    int v[NV];
+};
+
+template <int NV>
+__device__ __forceinline__ Row<NV> load_row(const ValSrc &vs, uint32_t row) {
+    Row<NV> r;
+    const uint32_t src = vs.rowid ? (uint32_t)vs.rowid[row] : row;
+#pragma unroll
+    for (int c = 0; c < NV; ++c) r.v[c] = c < vs.n ? vs.col[c][src] : 0;
+    return r;
+}
+
+template <int NV>
+__device__ __forceinline__ int pick(const Row<NV> &r, int c) {
+    int x = r.v[0];
+#pragma unroll
+    for (int cc = 1; cc < NV; ++cc)
+        if (cc == c) x = r.v[cc];
+    return x;
+}
+
+// Accumulate one row (values in registers) into an LDS record.
+template <int NV>
+__device__ __forceinline__ void rec_add_row(uint32_t *rec, const AggSpec &s, const Row<NV> &r) {
+    for (int j = 0; j < s.n; ++j) {
+        uint32_t *p = rec + s.word[j];
+        switch (s.op[j]) {
+            case GJ_SUM:
+                atomicAdd(reinterpret_cast<unsigned long long *>(p), (unsigned long long)(long long)pick(r, s.col[j]));
+                break;
+            case GJ_COUNT: atomicAdd(p, 1u); break;
+            case GJ_MIN: atomicMin(reinterpret_cast<int *>(p), pick(r, s.col[j])); break;
+            default: atomicMax(reinterpret_cast<int *>(p), pick(r, s.col[j])); break;
+        }
+    }
+}
+
+template <int NV>
+__device__ __forceinline__ void row_add_global_r(const AggSpec &s, const Row<NV> &r, uint64_t o) {
+    for (int j = 0; j < s.n; ++j) {
+        switch (s.op[j]) {
+            case GJ_SUM:
+                atomicAdd(static_cast<unsigned long long *>(s.out[j]) + o, (unsigned long long)(long long)pick(r, s.col[j]));
+                break;
+            case GJ_COUNT: atomicAdd(static_cast<unsigned long long *>(s.out[j]) + o, 1ull); break;
+            case GJ_MIN: atomicMin(static_cast<int *>(s.out[j]) + o, pick(r, s.col[j])); break;
+            default: atomicMax(static_cast<int *>(s.out[j]) + o, pick(r, s.col[j])); break;
+        }
+    }
+}
+
+// Running aggregate of a set of rows: count, and per value column sum / min / max.
+template <int NV>
+struct Acc {
+    uint32_t cnt;
+    long long sum[NV];
+    int mn[NV], mx[NV];
+};
+
+template <int NV>
+__device__ __forceinline__ void acc_clear(Acc<NV> &x) {
+    x.cnt = 0;
+#pragma unroll
+    for (int c = 0; c < NV; ++c) {
+        x.sum[c] = 0;
+        x.mn[c] = INT32_MAX;
+        x.mx[c] = INT32_MIN;
+    }
+}
+template <int NV>
+__device__ __forceinline__ void acc_merge(Acc<NV> &x, const Acc<NV> &y) {
+    x.cnt += y.cnt;
+#pragma unroll
+    for (int c = 0; c < NV; ++c) {
+        x.sum[c] += y.sum[c];
+        x.mn[c] = min(x.mn[c], y.mn[c]);
+        x.mx[c] = max(x.mx[c], y.mx[c]);
+    }
+}
+template <int NV>
+__device__ __forceinline__ void acc_row(Acc<NV> &x, const Row<NV> &r) {
+    x.cnt += 1;
+#pragma unroll
+    for (int c = 0; c < NV; ++c) {
+        x.sum[c] += r.v[c];
+        x.mn[c] = min(x.mn[c], r.v[c]);
+        x.mx[c] = max(x.mx[c], r.v[c]);
+    }
+}
+// Acc of the lane `src` (all lanes call).
+template <int NV>
+__device__ __forceinline__ Acc<NV> acc_shfl(const Acc<NV> &x, int src) {
+    Acc<NV> y;
+    y.cnt = __shfl(x.cnt, src, kWave);
+#pragma unroll
+    for (int c = 0; c < NV; ++c) {
+        y.sum[c] = __shfl(x.sum[c], src, kWave);
+        y.mn[c] = __shfl(x.mn[c], src, kWave);
+        y.mx[c] = __shfl(x.mx[c], src, kWave);
+    }
+    return y;
+}
+template <int NV>
+__device__ __forceinline__ Acc<NV> acc_wave_reduce(Acc<NV> x) {
+#pragma unroll
+    for (int d = kWave / 2; d > 0; d >>= 1) {
+        Acc<NV> y;
+        y.cnt = __shfl_xor(x.cnt, d, kWave);
+#pragma unroll
+        for (int c = 0; c < NV; ++c) {
+            y.sum[c] = __shfl_xor(x.sum[c], d, kWave);
+            y.mn[c] = __shfl_xor(x.mn[c], d, kWave);
+            y.mx[c] = __shfl_xor(x.mx[c], d, kWave);
+        }
+        acc_merge(x, y);
+    }
+    return x;
+}
+
+template <int NV>
+__device__ __forceinline__ void acc_flush(const Acc<NV> &x, const AggSpec &s, uint64_t o, bool atomic) {
+    for (int j = 0; j < s.n; ++j) {
+        const int c = s.col[j];
+        long long sum = x.sum[0];
+        int mn = x.mn[0], mx = x.mx[0];
+#pragma unroll
+        for (int cc = 1; cc < NV; ++cc) {
+            if (cc == c) {
+                sum = x.sum[cc];
+                mn = x.mn[cc];
+                mx = x.mx[cc];
+            }
+        }
+        switch (s.op[j]) {
+            case GJ_SUM: {
+                unsigned long long *q = static_cast<unsigned long long *>(s.out[j]) + o;
+                if (atomic) atomicAdd(q, (unsigned long long)sum);
+                else *q = (unsigned long long)sum;
+                break;
+            }
+            case GJ_COUNT: {
+                unsigned long long *q = static_cast<unsigned long long *>(s.out[j]) + o;
+                if (atomic) atomicAdd(q, (unsigned long long)x.cnt);
+                else *q = x.cnt;
+                break;
+            }
+            case GJ_MIN: {
+                int *q = static_cast<int *>(s.out[j]) + o;
+                if (atomic) atomicMin(q, mn);
+                else *q = mn;
+                break;
+            }
+            default: {
+                int *q = static_cast<int *>(s.out[j]) + o;
+                if (atomic) atomicMax(q, mx);
+                else *q = mx;
+                break;
+            }
+        }
+    }
+}
+
+// Fold an Acc into an LDS record (leader lane of a wave-aggregated update).
+template <int NV>
+__device__ __forceinline__ void rec_add_acc(uint32_t *rec, const AggSpec &s, const Acc<NV> &x) {
+    for (int j = 0; j < s.n; ++j) {
+        uint32_t *p = rec + s.word[j];
+        const int c = s.col[j];
+        long long sum = x.sum[0];
+        int mn = x.mn[0], mx = x.mx[0];
+#pragma unroll
+        for (int cc = 1; cc < NV; ++cc) {
+            if (cc == c) {
+                sum = x.sum[cc];
+                mn = x.mn[cc];
+                mx = x.mx[cc];
+            }
+        }
+        switch (s.op[j]) {
+            case GJ_SUM: atomicAdd(reinterpret_cast<unsigned long long *>(p), (unsigned long long)sum); break;
+            case GJ_COUNT: atomicAdd(p, x.cnt); break;
+            case GJ_MIN: atomicMin(reinterpret_cast<int *>(p), mn); break;
+            default: atomicMax(reinterpret_cast<int *>(p), mx); break;
+        }
+    }
+}
+
+// Rows of one wave round with group ids: lanes sharing an id are combined in
+// registers first, so each distinct id costs one set of LDS atomics per wave
+// instead of one per lane (the case of few groups, where lanes collide).
+template <int NV>
+__device__ __forceinline__ void wave_aggregate(uint32_t *recs, const AggSpec &s, bool valid, uint32_t id,
+                                               const Row<NV> &r) {
+    uint64_t todo = __ballot(valid);
+    while (todo) {
+        const int leader = __ffsll((long long)todo) - 1;
+        const uint32_t lid = __shfl(id, leader, kWave);
+        const bool mine = valid && id == lid;
+        const uint64_t peers = __ballot(mine);
+        Acc<NV> x;
+        acc_clear(x);
+        if (mine) acc_row(x, r);
+        x = acc_wave_reduce(x);
+        if (lane_id() == leader) rec_add_acc(recs + (uint64_t)lid * s.words, s, x);
+        todo &= ~peers;
+    }
+}
+
 // Identity values for every output column over groups [0, g).
 __global__ void k_out_init(AggSpec s, uint64_t g) {
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < g; i += (uint64_t)gridDim.x * blockDim.x) {
@@ -157,7 +369,12 @@ __device__ __forceinline__ int lds_insert(K *tab, int log2cap, K key) {
     uint32_t h = slot_hash<K>(key, log2cap);
     const K e = empty_key<K>();
     for (uint32_t step = 0; step <= mask; ++step) {
-        K cur;
+        K cur = tab[h];  // a plain read first: keys already present need no atomic
+        if (cur == key) return (int)h;
+        if (cur != e) {
+            h = (h + 1) & mask;
+            continue;
+        }
         if constexpr (sizeof(K) == 4) cur = (K)atomicCAS(reinterpret_cast<int *>(&tab[h]), (int)e, (int)key);
         else
             cur = (K)atomicCAS(reinterpret_cast<unsigned long long *>(&tab[h]), (unsigned long long)e,
@@ -202,6 +419,9 @@ struct PgbArgs {
     ValSrc vals;
     int log2cap;            // LDS table size of the aggregation pass
     int lds_records;        // 1: aggregate in LDS records; 0: global atomics
+    // discovery of oversized partitions by several workgroups
+    const uint32_t *dubase; // exclusive prefix of discovery units per partition (np + 1)
+    uint32_t *dcount;       // distinct keys found by each discovery unit
 };
 
 template <typename K>
@@ -220,6 +440,7 @@ __global__ __launch_bounds__(kBlock) void k_pgb_discover(PgbArgs a) {
         if (tid == 0) a.gcnt[p] = 0;
         return;
     }
+    if (p1 - p0 > kDiscoverUnit) return;  // discovered by k_pgb_discover_unit + k_pgb_merge
     const K *__restrict__ keys = static_cast<const K *>(a.keys);
     const K e = empty_key<K>();
     for (uint32_t i = tid; i < kDiscoverCap; i += kBlock) {
@@ -231,15 +452,26 @@ __global__ __launch_bounds__(kBlock) void k_pgb_discover(PgbArgs a) {
         s_over = 0;
     }
     __syncthreads();
-    for (uint32_t i = p0 + tid; i < p1; i += kBlock) {
-        const K k = keys[i];
-        const uint32_t local = i - p0;
-        if (k == e) {
-            atomicMin(&s_sent, local);
-        } else {
-            const int slot = lds_insert<K>(s_key, log2cap, k);
-            if (slot < 0) s_over = 1;
-            else atomicMin(&s_first[slot], local);
+    constexpr int RB = 16;  // keys loaded per thread before they are inserted
+    for (uint32_t base = p0; base < p1; base += kBlock * RB) {
+        K kk[RB];
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+            const uint32_t i = base + r * kBlock + tid;
+            kk[r] = i < p1 ? keys[i] : e;
+        }
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+            const uint32_t i = base + r * kBlock + tid;
+            if (i >= p1) continue;
+            const uint32_t local = i - p0;
+            if (kk[r] == e) {
+                atomicMin(&s_sent, local);
+            } else {
+                const int slot = lds_insert<K>(s_key, log2cap, kk[r]);
+                if (slot < 0) s_over = 1;
+                else if (s_first[slot] > local) atomicMin(&s_first[slot], local);
+            }
         }
     }
     __syncthreads();
@@ -250,26 +482,194 @@ __global__ __launch_bounds__(kBlock) void k_pgb_discover(PgbArgs a) {
         }
         return;
     }
-    // ids in order of first occurrence: a block scan over head flags in row order
+    // ids in order of first occurrence: a block scan over head flags in row order,
+    // each thread taking 16 consecutive rows so that one scan covers 4096 rows
     K *__restrict__ tk = static_cast<K *>(a.tmp_keys);
+    constexpr int HB = 16;
     uint32_t ids = 0;
-    for (uint32_t c0 = p0; c0 < p1; c0 += kBlock) {
-        const uint32_t i = c0 + tid;
-        uint32_t head = 0;
-        K k = e;
-        if (i < p1) {
-            k = keys[i];
-            const uint32_t local = i - p0;
-            head = (k == e) ? (s_sent == local) : (s_first[lds_find<K>(s_key, log2cap, k)] == local);
+    for (uint32_t c0 = p0; c0 < p1; c0 += kBlock * HB) {
+        const uint32_t mine = c0 + tid * HB;
+        K kk[HB];
+        uint32_t hmask = 0, hc = 0;
+#pragma unroll
+        for (int r = 0; r < HB; ++r) kk[r] = mine + r < p1 ? keys[mine + r] : e;
+#pragma unroll
+        for (int r = 0; r < HB; ++r) {
+            const uint32_t i = mine + r;
+            if (i < p1) {
+                const uint32_t local = i - p0;
+                const bool head = (kk[r] == e) ? (s_sent == local)
+                                               : (s_first[lds_find<K>(s_key, log2cap, kk[r])] == local);
+                if (head) {
+                    hmask |= 1u << r;
+                    ++hc;
+                }
+            }
         }
         uint32_t tot;
-        const uint32_t pre = block_exclusive_sum<uint32_t>(head, s_tmp, &tot);
-        if (head) tk[p0 + ids + pre] = k;
+        uint32_t pre = block_exclusive_sum<uint32_t>(hc, s_tmp, &tot);
+#pragma unroll
+        for (int r = 0; r < HB; ++r)
+            if (hmask & (1u << r)) tk[p0 + ids + pre++] = kk[r];
         ids += tot;
     }
     if (tid == 0) {
         a.gcnt[p] = ids;
         atomicMax(&a.stat[0], ids);
+    }
+}
+
+__global__ void k_pgb_dunits(const uint32_t *__restrict__ poff, uint32_t np, uint32_t *__restrict__ du) {
+    for (uint32_t p = blockIdx.x * blockDim.x + threadIdx.x; p < np; p += gridDim.x * blockDim.x) {
+        const uint32_t n = poff[p + 1] - poff[p];
+        du[p] = n > kDiscoverUnit ? ceil_div_u32(n, kDiscoverUnit) : 0u;
+    }
+}
+
+// One slice of an oversized partition: its distinct keys (in table order) are
+// written over the slice's own rows of tmp_keys, their number to dcount.
+template <typename K>
+__global__ __launch_bounds__(kBlock) void k_pgb_discover_unit(PgbArgs a) {
+    __shared__ K s_key[kDiscoverCap];
+    __shared__ uint32_t s_tmp[kWaves];
+    __shared__ uint32_t s_unit[3];
+    __shared__ int s_sent, s_over;
+    constexpr int log2cap = 12;
+    const int tid = threadIdx.x;
+    const uint32_t u = blockIdx.x;
+    const uint32_t total = a.dubase[a.np];
+    if (u >= total) return;
+    if (tid == 0) {
+        uint32_t lo = 0, hi = a.np;  // dubase[lo] <= u < dubase[hi]
+        while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (a.dubase[mid] <= u) lo = mid;
+            else hi = mid;
+        }
+        const uint32_t p0 = a.poff[lo], p1 = a.poff[lo + 1];
+        const uint32_t j = u - a.dubase[lo];
+        s_unit[0] = p0 + j * kDiscoverUnit;
+        s_unit[1] = min(p0 + (j + 1) * kDiscoverUnit, p1);
+        s_sent = 0;
+        s_over = 0;
+    }
+    const K e = empty_key<K>();
+    for (uint32_t i = tid; i < kDiscoverCap; i += kBlock) s_key[i] = e;
+    __syncthreads();
+    const uint32_t r0 = s_unit[0], r1 = s_unit[1];
+    const K *__restrict__ keys = static_cast<const K *>(a.keys);
+    constexpr int RB = 16;
+    for (uint32_t base = r0; base < r1; base += kBlock * RB) {
+        K kk[RB];
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+            const uint32_t i = base + r * kBlock + tid;
+            kk[r] = i < r1 ? keys[i] : e;
+        }
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+            if (base + r * kBlock + tid >= r1) continue;
+            if (kk[r] == e) s_sent = 1;
+            else if (lds_insert<K>(s_key, log2cap, kk[r]) < 0) s_over = 1;
+        }
+    }
+    __syncthreads();
+    if (s_over) {
+        if (tid == 0) atomicOr(&a.stat[1], 1u);
+        return;
+    }
+    K *__restrict__ tk = static_cast<K *>(a.tmp_keys);
+    uint32_t cnt = 0;
+    for (uint32_t c0 = 0; c0 < kDiscoverCap; c0 += kBlock) {
+        const K k = s_key[c0 + tid];
+        const uint32_t f = k != e;
+        uint32_t tot;
+        const uint32_t pre = block_exclusive_sum<uint32_t>(f, s_tmp, &tot);
+        if (f) tk[r0 + cnt + pre] = k;
+        cnt += tot;
+    }
+    if (tid == 0) {
+        if (s_sent) tk[r0 + cnt++] = e;
+        a.dcount[u] = cnt;
+    }
+}
+
+// Union of the slices' key lists of an oversized partition, sorted by key (a
+// deterministic group order), written to the partition's tmp_keys range.
+template <typename K>
+__global__ __launch_bounds__(kBlock) void k_pgb_merge(PgbArgs a) {
+    __shared__ K s_key[kDiscoverCap];
+    __shared__ K s_sort[kDiscoverCap];
+    __shared__ uint32_t s_tmp[kWaves];
+    __shared__ int s_sent, s_over;
+    constexpr int log2cap = 12;
+    const uint32_t p = blockIdx.x;
+    const int tid = threadIdx.x;
+    const uint32_t u0 = a.dubase[p], u1 = a.dubase[p + 1];
+    if (u0 == u1) return;  // not an oversized partition
+    const uint32_t p0 = a.poff[p];
+    const K e = empty_key<K>();
+    for (uint32_t i = tid; i < kDiscoverCap; i += kBlock) s_key[i] = e;
+    if (tid == 0) {
+        s_sent = 0;
+        s_over = 0;
+    }
+    __syncthreads();
+    K *__restrict__ tk = static_cast<K *>(a.tmp_keys);
+    for (uint32_t u = u0; u < u1; ++u) {
+        const uint32_t r0 = p0 + (u - u0) * kDiscoverUnit, d = a.dcount[u];
+        for (uint32_t i = tid; i < d; i += kBlock) {
+            const K k = tk[r0 + i];
+            if (k == e) s_sent = 1;
+            else if (lds_insert<K>(s_key, log2cap, k) < 0) s_over = 1;
+        }
+    }
+    __syncthreads();
+    if (s_over) {
+        if (tid == 0) {
+            a.gcnt[p] = 0;
+            atomicOr(&a.stat[1], 1u);
+        }
+        return;
+    }
+    // compact, pad with the largest key, bitonic sort ascending
+    uint32_t cnt = 0;
+    for (uint32_t c0 = 0; c0 < kDiscoverCap; c0 += kBlock) {
+        const K k = s_key[c0 + tid];
+        const uint32_t f = k != e;
+        uint32_t tot;
+        const uint32_t pre = block_exclusive_sum<uint32_t>(f, s_tmp, &tot);
+        if (f) s_sort[cnt + pre] = k;
+        cnt += tot;
+    }
+    uint32_t n2 = 1;
+    while (n2 < cnt) n2 <<= 1;
+    const K big = sizeof(K) == 4 ? (K)INT32_MAX : (K)INT64_MAX;
+    for (uint32_t i = cnt + tid; i < n2; i += kBlock) s_sort[i] = big;
+    __syncthreads();
+    for (uint32_t k2 = 2; k2 <= n2; k2 <<= 1) {
+        for (uint32_t j = k2 >> 1; j > 0; j >>= 1) {
+            for (uint32_t i = tid; i < n2; i += kBlock) {
+                const uint32_t l = i ^ j;
+                if (l > i) {
+                    const K x = s_sort[i], y = s_sort[l];
+                    const bool up = (i & k2) == 0;
+                    if ((x > y) == up) {
+                        s_sort[i] = y;
+                        s_sort[l] = x;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    // the key equal to the empty marker is the smallest key of all
+    const uint32_t off = s_sent ? 1u : 0u;
+    if (tid == 0 && s_sent) tk[p0] = e;
+    for (uint32_t i = tid; i < cnt; i += kBlock) tk[p0 + off + i] = s_sort[i];
+    if (tid == 0) {
+        a.gcnt[p] = cnt + off;
+        atomicMax(&a.stat[0], cnt + off);
     }
 }
 
@@ -284,11 +684,13 @@ __global__ void k_pgb_units(const uint32_t *__restrict__ poff, uint32_t np, uint
     atomicMax(max_units, mx);
 }
 
-template <typename K>
+template <typename K, int NV>
 __global__ __launch_bounds__(kBlock) void k_pgb_aggregate(PgbArgs a) {
+    constexpr int RB = NV <= 2 ? 8 : 16 / NV;  // rows loaded per thread before they are aggregated
     extern __shared__ __align__(16) uint32_t s_dyn[];
     __shared__ uint32_t s_unit[5];
-    const int tid = threadIdx.x;
+    __shared__ uint32_t s_sent_id;
+    const int tid = threadIdx.x, lane = lane_id();
     const uint32_t u = blockIdx.x;
     if (tid == 0) {
         uint32_t lo = 0, hi = a.np;  // ubase[lo] <= u < ubase[hi]
@@ -305,6 +707,7 @@ __global__ __launch_bounds__(kBlock) void k_pgb_aggregate(PgbArgs a) {
         s_unit[2] = min(p0 + (j + 1) * kUnitRows, p1);
         s_unit[3] = (a.ubase[p + 1] - a.ubase[p]) > 1;  // several units share the partition
         s_unit[4] = j;
+        s_sent_id = 0xFFFFFFFFu;
     }
     __syncthreads();
     const uint32_t p = s_unit[0], r0 = s_unit[1], r1 = s_unit[2];
@@ -322,25 +725,39 @@ __global__ __launch_bounds__(kBlock) void k_pgb_aggregate(PgbArgs a) {
     }
     const AggSpec &s = a.spec;
     if (g == 1) {
-        // one group: every row folds into it; a wave-level pass then one LDS record
-        uint32_t *rec = s_dyn;
-        if (tid == 0) rec_init(rec, s);
+        // one group (case 1): registers, then a block-wide reduction
+        Acc<NV> x;
+        acc_clear(x);
+        for (uint32_t base = r0; base < r1; base += kBlock * RB) {
+            Row<NV> rr[RB];
+#pragma unroll
+            for (int r = 0; r < RB; ++r) {
+                const uint32_t i = base + r * kBlock + tid;
+                if (i < r1) rr[r] = load_row<NV>(a.vals, i);
+            }
+#pragma unroll
+            for (int r = 0; r < RB; ++r)
+                if (base + r * kBlock + tid < r1) acc_row(x, rr[r]);
+        }
+        x = acc_wave_reduce(x);
+        Acc<NV> *s_acc = reinterpret_cast<Acc<NV> *>(s_dyn);
+        if (lane == 0) s_acc[tid / kWave] = x;
         __syncthreads();
-        for (uint32_t i = r0 + tid; i < r1; i += kBlock) rec_add_lds(rec, s, a.vals, i);
-        __syncthreads();
-        if (tid == 0) rec_flush(rec, s, gb, multi);
+        if (tid == 0) {
+            Acc<NV> t = s_acc[0];
+            for (int w = 1; w < kWaves; ++w) acc_merge(t, s_acc[w]);
+            acc_flush(t, s, gb, multi);
+        }
         return;
     }
     const int log2cap = a.log2cap;
     const uint32_t cap = 1u << log2cap;
     K *tab = reinterpret_cast<K *>(s_dyn);
-    uint16_t *tid_of = reinterpret_cast<uint16_t *>(tab + cap);  // slot -> group id
-    uint32_t *recs = reinterpret_cast<uint32_t *>(tid_of + cap);
+    uint16_t *id_of = reinterpret_cast<uint16_t *>(tab + cap);  // slot -> group id
+    uint32_t *recs = reinterpret_cast<uint32_t *>(id_of + cap);
     recs = reinterpret_cast<uint32_t *>((reinterpret_cast<uintptr_t>(recs) + 7) & ~uintptr_t(7));
     const K e = empty_key<K>();
     for (uint32_t i = tid; i < cap; i += kBlock) tab[i] = e;
-    __shared__ uint32_t s_sent_id;
-    if (tid == 0) s_sent_id = 0xFFFFFFFFu;
     if (a.lds_records)
         for (uint32_t i = tid; i < g; i += kBlock) rec_init(recs + (uint64_t)i * s.words, s);
     __syncthreads();
@@ -350,15 +767,34 @@ __global__ __launch_bounds__(kBlock) void k_pgb_aggregate(PgbArgs a) {
             s_sent_id = i;
         } else {
             const int slot = lds_insert<K>(tab, log2cap, k);
-            tid_of[slot] = (uint16_t)i;
+            id_of[slot] = (uint16_t)i;
         }
     }
     __syncthreads();
-    for (uint32_t i = r0 + tid; i < r1; i += kBlock) {
-        const K k = keys[i];
-        const uint32_t id = (k == e) ? s_sent_id : tid_of[lds_find<K>(tab, log2cap, k)];
-        if (a.lds_records) rec_add_lds(recs + (uint64_t)id * s.words, s, a.vals, i);
-        else row_add_global(s, a.vals, i, gb + id);
+    // case 2 (records in LDS) or case 3 (global atomics); few groups per
+    // partition means colliding lanes, which are combined per wave first
+    const bool few = g <= 2;
+    for (uint32_t base = r0; base < r1; base += kBlock * RB) {
+        K kk[RB];
+        Row<NV> rr[RB];
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+            const uint32_t i = base + r * kBlock + tid;
+            kk[r] = i < r1 ? keys[i] : e;
+            if (i < r1) rr[r] = load_row<NV>(a.vals, i);
+        }
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+            const bool valid = base + r * kBlock + tid < r1;
+            uint32_t id = 0;
+            if (valid) id = (kk[r] == e) ? s_sent_id : id_of[lds_find<K>(tab, log2cap, kk[r])];
+            if (a.lds_records) {
+                if (few) wave_aggregate<NV>(recs, s, valid, id, rr[r]);
+                else if (valid) rec_add_row<NV>(recs + (uint64_t)id * s.words, s, rr[r]);
+            } else if (valid) {
+                row_add_global_r<NV>(s, rr[r], gb + id);
+            }
+        }
     }
     if (a.lds_records) {
         __syncthreads();
@@ -401,59 +837,102 @@ __device__ __forceinline__ uint64_t global_slot_hash(K key) {
 }
 
 template <typename K>
-__global__ __launch_bounds__(kBlock) void k_hgb_insert(HgbArgs a) {
-    const K *__restrict__ keys = static_cast<const K *>(a.keys);
+__device__ __forceinline__ void hgb_insert_one(const HgbArgs &a, const K *keys, uint32_t i, K k) {
     const uint64_t mask = (1ull << a.log2cap) - 1ull;
-    for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < a.n; i += gridDim.x * kBlock) {
-        const K k = keys[i];
-        uint64_t h = global_slot_hash<K>(k) & mask;
-        for (uint64_t step = 0; step <= mask; ++step) {
-            if constexpr (sizeof(K) == 4) {
-                unsigned long long *t = static_cast<unsigned long long *>(a.table);
+    uint64_t h = global_slot_hash<K>(k) & mask;
+    for (uint64_t step = 0; step <= mask; ++step) {
+        if constexpr (sizeof(K) == 4) {
+            unsigned long long *t = static_cast<unsigned long long *>(a.table);
+            unsigned long long cur = __atomic_load_n(&t[h], __ATOMIC_RELAXED);
+            if (cur == ~0ull) {
                 const unsigned long long mine = ((unsigned long long)(uint32_t)k << 32) | i;
-                const unsigned long long cur = atomicCAS(&t[h], ~0ull, mine);
+                cur = atomicCAS(&t[h], ~0ull, mine);
                 if (cur == ~0ull) {
                     const uint32_t g = atomicAdd(a.ngroups, 1u);
                     a.gid[i] = g;
                     static_cast<K *>(a.tmp_keys)[g] = k;
                     a.gid_loc[i] = i;
-                    break;
+                    return;
                 }
-                if ((uint32_t)(cur >> 32) == (uint32_t)k) {
-                    a.gid_loc[i] = (uint32_t)cur;
-                    break;
-                }
-            } else {
-                uint32_t *t = static_cast<uint32_t *>(a.table);
-                const uint32_t cur = atomicCAS(&t[h], 0xFFFFFFFFu, i);
+            }
+            if ((uint32_t)(cur >> 32) == (uint32_t)k) {
+                a.gid_loc[i] = (uint32_t)cur;
+                return;
+            }
+        } else {
+            uint32_t *t = static_cast<uint32_t *>(a.table);
+            uint32_t cur = __atomic_load_n(&t[h], __ATOMIC_RELAXED);
+            if (cur == 0xFFFFFFFFu) {
+                cur = atomicCAS(&t[h], 0xFFFFFFFFu, i);
                 if (cur == 0xFFFFFFFFu) {
                     const uint32_t g = atomicAdd(a.ngroups, 1u);
                     a.gid[i] = g;
                     static_cast<K *>(a.tmp_keys)[g] = k;
                     a.gid_loc[i] = i;
-                    break;
-                }
-                if (keys[cur] == k) {
-                    a.gid_loc[i] = cur;
-                    break;
+                    return;
                 }
             }
-            h = (h + 1) & mask;
+            if (keys[cur] == k) {
+                a.gid_loc[i] = cur;
+                return;
+            }
+        }
+        h = (h + 1) & mask;
+    }
+}
+
+template <typename K>
+__global__ __launch_bounds__(kBlock) void k_hgb_insert(HgbArgs a) {
+    constexpr int RB = 8;
+    const K *__restrict__ keys = static_cast<const K *>(a.keys);
+    const uint32_t stride = gridDim.x * kBlock * RB;
+    for (uint32_t base = blockIdx.x * kBlock * RB; base < a.n; base += stride) {
+        K kk[RB];
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+            const uint32_t i = base + r * kBlock + threadIdx.x;
+            kk[r] = i < a.n ? keys[i] : K(0);
+        }
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+            const uint32_t i = base + r * kBlock + threadIdx.x;
+            if (i < a.n) hgb_insert_one<K>(a, keys, i, kk[r]);
         }
     }
 }
 
+template <int NV>
 __global__ __launch_bounds__(kBlock) void k_hgb_aggregate(HgbArgs a) {
+    constexpr int RB = NV <= 2 ? 8 : 16 / NV;
     extern __shared__ __align__(16) uint32_t s_dyn[];
     const AggSpec &s = a.spec;
     if (a.lds_records) {
         for (uint32_t i = threadIdx.x; i < a.g; i += kBlock) rec_init(s_dyn + (uint64_t)i * s.words, s);
         __syncthreads();
     }
-    for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < a.n; i += gridDim.x * kBlock) {
-        const uint32_t g = a.gid[a.gid_loc[i]];
-        if (a.lds_records) rec_add_lds(s_dyn + (uint64_t)g * s.words, s, a.vals, i);
-        else row_add_global(s, a.vals, i, g);
+    const bool few = a.g <= 2;
+    const uint32_t stride = gridDim.x * kBlock * RB;
+    for (uint32_t base = blockIdx.x * kBlock * RB; base < a.n; base += stride) {
+        uint32_t loc[RB], gid[RB];
+        Row<NV> rr[RB];
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+            const uint32_t i = base + r * kBlock + threadIdx.x;
+            loc[r] = i < a.n ? a.gid_loc[i] : 0u;
+            if (i < a.n) rr[r] = load_row<NV>(a.vals, i);
+        }
+#pragma unroll
+        for (int r = 0; r < RB; ++r) gid[r] = a.gid[loc[r]];
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+            const bool valid = base + r * kBlock + threadIdx.x < a.n;
+            if (a.lds_records) {
+                if (few) wave_aggregate<NV>(s_dyn, s, valid, gid[r], rr[r]);
+                else if (valid) rec_add_row<NV>(s_dyn + (uint64_t)gid[r] * s.words, s, rr[r]);
+            } else if (valid) {
+                row_add_global_r<NV>(s, rr[r], gid[r]);
+            }
+        }
     }
     if (a.lds_records) {
         __syncthreads();
@@ -503,160 +982,127 @@ __global__ __launch_bounds__(kBlock) void k_sgb_heads(SgbArgs a) {
     if (threadIdx.x == 0) a.tile_heads[blockIdx.x] = tot;
 }
 
-// Running aggregate of one run: count, and per value column sum / min / max.
-// All loops over columns are unrolled to kMaxVals with a bound check, so the
-// arrays stay in registers.
-struct Acc {
-    uint32_t cnt;
-    long long sum[kMaxVals];
-    int mn[kMaxVals], mx[kMaxVals];
-};
-
-__device__ __forceinline__ void acc_clear(Acc &x) {
-    x.cnt = 0;
+template <int NV>
+__device__ __forceinline__ Acc<NV> acc_shfl_up(const Acc<NV> &x, int d) {
+    Acc<NV> y;
+    y.cnt = __shfl_up(x.cnt, d, kWave);
 #pragma unroll
-    for (int c = 0; c < kMaxVals; ++c) {
-        x.sum[c] = 0;
-        x.mn[c] = INT32_MAX;
-        x.mx[c] = INT32_MIN;
+    for (int c = 0; c < NV; ++c) {
+        y.sum[c] = __shfl_up(x.sum[c], d, kWave);
+        y.mn[c] = __shfl_up(x.mn[c], d, kWave);
+        y.mx[c] = __shfl_up(x.mx[c], d, kWave);
     }
-}
-__device__ __forceinline__ void acc_merge(Acc &x, const Acc &y) {
-    x.cnt += y.cnt;
-#pragma unroll
-    for (int c = 0; c < kMaxVals; ++c) {
-        x.sum[c] += y.sum[c];
-        x.mn[c] = min(x.mn[c], y.mn[c]);
-        x.mx[c] = max(x.mx[c], y.mx[c]);
-    }
-}
-__device__ __forceinline__ void acc_row(Acc &x, const ValSrc &v, uint32_t row) {
-    x.cnt += 1;
-#pragma unroll
-    for (int c = 0; c < kMaxVals; ++c) {
-        if (c < v.n) {
-            const int val = load_val(v, c, row);
-            x.sum[c] += val;
-            x.mn[c] = min(x.mn[c], val);
-            x.mx[c] = max(x.mx[c], val);
-        }
-    }
+    return y;
 }
 
-__device__ __forceinline__ void acc_flush(const Acc &x, const AggSpec &s, uint64_t o, bool atomic) {
-    for (int j = 0; j < s.n; ++j) {
-        const int c = s.col[j];
-        long long sum = 0;
-        int mn = 0, mx = 0;
-#pragma unroll
-        for (int cc = 0; cc < kMaxVals; ++cc) {
-            if (cc == c) {
-                sum = x.sum[cc];
-                mn = x.mn[cc];
-                mx = x.mx[cc];
-            }
-        }
-        switch (s.op[j]) {
-            case GJ_SUM: {
-                unsigned long long *q = static_cast<unsigned long long *>(s.out[j]) + o;
-                if (atomic) atomicAdd(q, (unsigned long long)sum);
-                else *q = (unsigned long long)sum;
-                break;
-            }
-            case GJ_COUNT: {
-                unsigned long long *q = static_cast<unsigned long long *>(s.out[j]) + o;
-                if (atomic) atomicAdd(q, (unsigned long long)x.cnt);
-                else *q = x.cnt;
-                break;
-            }
-            case GJ_MIN: {
-                int *q = static_cast<int *>(s.out[j]) + o;
-                if (atomic) atomicMin(q, mn);
-                else *q = mn;
-                break;
-            }
-            default: {
-                int *q = static_cast<int *>(s.out[j]) + o;
-                if (atomic) atomicMax(q, mx);
-                else *q = mx;
-                break;
-            }
-        }
-    }
-}
-
-template <typename K>
+// Segmented combine: (f1, A1) then (f2, A2) = (f1 | f2, f2 ? A2 : A1 + A2).
+template <typename K, int NV>
 __global__ __launch_bounds__(kBlock) void k_sgb_reduce(SgbArgs a) {
-    __shared__ Acc s_acc[kBlock];
-    __shared__ uint32_t s_flag[kBlock];
+    constexpr int IT = kSgbItems;
+    __shared__ Acc<NV> s_wacc[kWaves];
+    __shared__ uint32_t s_wf[kWaves];
     __shared__ uint32_t s_tmp[kWaves];
     const K *__restrict__ keys = static_cast<const K *>(a.keys);
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, lane = lane_id(), w = tid / kWave;
     const uint32_t t0 = blockIdx.x * kSgbTile;
-    const uint32_t first = t0 + tid * kSgbItems;  // this thread's rows: [first, first + 16)
-    // head flags of this thread's rows (row 0 always starts a run)
+    const uint32_t first = t0 + tid * IT;  // this thread's rows: [first, first + IT)
+    K kk[IT];
+    Row<NV> rr[IT];
+#pragma unroll
+    for (int k = 0; k < IT; ++k) {
+        const uint32_t i = first + k;
+        kk[k] = K(0);
+        if (i < a.n) {
+            kk[k] = keys[i];
+            rr[k] = load_row<NV>(a.vals, i);
+        }
+    }
+    K prev = (first > 0 && first <= a.n) ? keys[first - 1] : K(0);
     uint32_t hmask = 0, hc = 0;
-    if (first < a.n) {
-        K prev = first > 0 ? keys[first - 1] : K(0);
-        for (int k = 0; k < kSgbItems; ++k) {
-            const uint32_t i = first + k;
-            if (i >= a.n) break;
-            const K key = keys[i];
-            if (i == 0 || key != prev) {
+#pragma unroll
+    for (int k = 0; k < IT; ++k) {
+        const uint32_t i = first + k;
+        if (i < a.n) {
+            if (i == 0 || kk[k] != prev) {
                 hmask |= 1u << k;
                 ++hc;
             }
-            prev = key;
+            prev = kk[k];
         }
     }
     const uint32_t hpre = block_exclusive_sum<uint32_t>(hc, s_tmp, (uint32_t *)nullptr);
-    // the thread's tail: rows after its last head (all its rows if it has none)
-    Acc cur;
-    acc_clear(cur);
-    for (int k = 0; k < kSgbItems; ++k) {
-        const uint32_t i = first + k;
-        if (i >= a.n) break;
-        if (hmask & (1u << k)) acc_clear(cur);
-        acc_row(cur, a.vals, i);
-    }
-    s_acc[tid] = cur;
-    s_flag[tid] = hc != 0;
-    __syncthreads();
-    // carry into each thread: serial segmented scan over the 256 thread tails
-    if (tid == 0) {
-        Acc run;
-        acc_clear(run);
-        for (int t = 0; t < kBlock; ++t) {
-            const Acc here = s_acc[t];
-            s_acc[t] = run;
-            if (s_flag[t]) run = here;
-            else acc_merge(run, here);
+    // this thread's tail: rows after its last head (all rows if it has none)
+    Acc<NV> A;
+    acc_clear(A);
+#pragma unroll
+    for (int k = 0; k < IT; ++k) {
+        if (first + k < a.n) {
+            if (hmask & (1u << k)) acc_clear(A);
+            acc_row(A, rr[k]);
         }
     }
+    uint32_t f = hc != 0;
+    // inclusive segmented scan over the wave
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const uint32_t fo = __shfl_up(f, d, kWave);
+        Acc<NV> Ao = acc_shfl_up(A, d);
+        if (lane >= d) {
+            if (!f) {
+                acc_merge(Ao, A);
+                A = Ao;
+            }
+            f |= fo;
+        }
+    }
+    if (lane == kWave - 1) {
+        s_wacc[w] = A;
+        s_wf[w] = f;
+    }
+    uint32_t fx = __shfl_up(f, 1, kWave);
+    Acc<NV> Ax = acc_shfl_up(A, 1);
+    if (lane == 0) {
+        fx = 0;
+        acc_clear(Ax);
+    }
     __syncthreads();
+    // carry into this thread = (earlier waves) then (earlier lanes of this wave)
+    Acc<NV> carry;
+    if (fx) {
+        carry = Ax;
+    } else {
+        acc_clear(carry);
+        for (int q = 0; q < w; ++q) {
+            if (s_wf[q]) carry = s_wacc[q];
+            else acc_merge(carry, s_wacc[q]);
+        }
+        acc_merge(carry, Ax);
+    }
     // Group id of a row = heads before the tile + heads of the tile up to the row - 1.
     // A run that began before this thread began inside the tile iff an earlier
     // thread of the tile had a head; only runs inside the tile are written plainly.
     const uint64_t gbase = a.tile_heads[blockIdx.x];
-    cur = s_acc[tid];
+    Acc<NV> cur = carry;
     bool cur_in_tile = hpre > 0;
-    uint64_t cur_gid = gbase + hpre - 1;  // wraps to 2^64-1 only before row 0, where cur is empty
+    uint64_t cur_gid = gbase + hpre - 1;  // wraps only before row 0, where cur is empty
     K *ok = static_cast<K *>(a.out_key);
-    for (int k = 0; k < kSgbItems; ++k) {
+#pragma unroll
+    for (int k = 0; k < IT; ++k) {
         const uint32_t i = first + k;
-        if (i >= a.n) break;
-        if (hmask & (1u << k)) {
-            if (cur.cnt > 0) acc_flush(cur, a.spec, cur_gid, !cur_in_tile);
-            acc_clear(cur);
-            cur_gid += 1;
-            cur_in_tile = true;
-            ok[cur_gid] = keys[i];
+        if (i < a.n) {
+            if (hmask & (1u << k)) {
+                if (cur.cnt > 0) acc_flush(cur, a.spec, cur_gid, !cur_in_tile);
+                acc_clear(cur);
+                cur_gid += 1;
+                cur_in_tile = true;
+                ok[cur_gid] = kk[k];
+            }
+            acc_row(cur, rr[k]);
         }
-        acc_row(cur, a.vals, i);
     }
     // the thread holding the tile's last row flushes the run that reaches it
     const uint32_t tile_end = min(t0 + kSgbTile, a.n);
-    if (first < tile_end && first + kSgbItems >= tile_end && cur.cnt > 0) acc_flush(cur, a.spec, cur_gid, true);
+    if (first < tile_end && first + IT >= tile_end && cur.cnt > 0) acc_flush(cur, a.spec, cur_gid, true);
 }
 
 }  // namespace
@@ -664,6 +1110,9 @@ __global__ __launch_bounds__(kBlock) void k_sgb_reduce(SgbArgs a) {
 // ---- host drivers ------------------------------------------------------------------
 
 namespace {
+
+// Register tier for the value columns: kernels are built for 1, 2, 4 and 8.
+int nv_tier(int n_vals) { return n_vals <= 1 ? 1 : n_vals <= 2 ? 2 : n_vals <= 4 ? 4 : 8; }
 
 AggSpec make_spec(const gj_agg *aggs, int n_aggs, void *const *outs) {
     AggSpec s{};
@@ -735,10 +1184,23 @@ int64_t groupby_partition(Ctx &ctx, int key_bytes, const void *key, const int32_
     fill_u32(st, stat, 0u, 4);
     a.gcnt = gcnt;
     a.stat = stat;
-    if (key_bytes == 4)
+    // oversized partitions (skew, few groups) are discovered in slices by many workgroups
+    uint32_t *du = ctx.scratch_n<uint32_t>(np + 1);
+    GJ_LAUNCH("k_pgb_dunits", 12.0 * np, k_pgb_dunits, dim3(std::min<uint32_t>((np + 255) / 256, 1024)), dim3(256),
+              0, st, poff, np, du);
+    scan_exclusive_u32(ctx, du, du, np, du + np);
+    a.dubase = du;
+    const uint32_t max_du = 2 * ceil_div_u32(n, kDiscoverUnit) + 1;
+    a.dcount = ctx.scratch_n<uint32_t>(max_du);
+    if (key_bytes == 4) {
         GJ_LAUNCH("k_pgb_discover", 8.0 * n, k_pgb_discover<int32_t>, dim3(np), dim3(kBlock), 0, st, a);
-    else
+        GJ_LAUNCH("k_pgb_discover_unit", 4.0 * n, k_pgb_discover_unit<int32_t>, dim3(max_du), dim3(kBlock), 0, st, a);
+        GJ_LAUNCH("k_pgb_merge", 8.0 * np, k_pgb_merge<int32_t>, dim3(np), dim3(kBlock), 0, st, a);
+    } else {
         GJ_LAUNCH("k_pgb_discover", 16.0 * n, k_pgb_discover<int64_t>, dim3(np), dim3(kBlock), 0, st, a);
+        GJ_LAUNCH("k_pgb_discover_unit", 8.0 * n, k_pgb_discover_unit<int64_t>, dim3(max_du), dim3(kBlock), 0, st, a);
+        GJ_LAUNCH("k_pgb_merge", 16.0 * np, k_pgb_merge<int64_t>, dim3(np), dim3(kBlock), 0, st, a);
+    }
     scan_exclusive_u32(ctx, gcnt, gcnt, np, gcnt + np);
     uint32_t *ucnt = ctx.scratch_n<uint32_t>(np + 1);
     GJ_LAUNCH("k_pgb_units", 12.0 * np, k_pgb_units, dim3(std::min<uint32_t>((np + 255) / 256, 1024)), dim3(256),
@@ -781,15 +1243,19 @@ int64_t groupby_partition(Ctx &ctx, int key_bytes, const void *key, const int32_
         lds = tab_bytes;
     }
     require(lds <= 150 * 1024, "partition group-by: too many groups per partition", GJ_EUNSUPPORTED);
-    lds = std::max<size_t>(lds, (size_t)a.spec.words * 4 + 8);
+    lds = std::max<size_t>(lds, (size_t)kWaves * 160 + 16);  // the one-group path keeps a per-wave total
     // outputs of partitions split over several units are folded with atomics
     if (max_units > 1 || !a.lds_records) init_outputs(st, a.spec, g);
     const double bytes = (double)n * (key_bytes + 4.0 * n_vals + (gfur ? 4.0 : 0.0)) +
                          (double)g * (key_bytes + 4.0 * a.spec.words);
-    if (key_bytes == 4)
-        GJ_LAUNCH("k_pgb_aggregate", bytes, k_pgb_aggregate<int32_t>, dim3(units), dim3(kBlock), lds, st, a);
-    else
-        GJ_LAUNCH("k_pgb_aggregate", bytes, k_pgb_aggregate<int64_t>, dim3(units), dim3(kBlock), lds, st, a);
+#define GJ_PGB(K, NV) GJ_LAUNCH("k_pgb_aggregate", bytes, (k_pgb_aggregate<K, NV>), dim3(units), dim3(kBlock), lds, st, a)
+    const int nvt = nv_tier(n_vals);
+    if (key_bytes == 4) {
+        if (nvt == 1) GJ_PGB(int32_t, 1); else if (nvt == 2) GJ_PGB(int32_t, 2); else if (nvt == 4) GJ_PGB(int32_t, 4); else GJ_PGB(int32_t, 8);
+    } else {
+        if (nvt == 1) GJ_PGB(int64_t, 1); else if (nvt == 2) GJ_PGB(int64_t, 2); else if (nvt == 4) GJ_PGB(int64_t, 4); else GJ_PGB(int64_t, 8);
+    }
+#undef GJ_PGB
     return g;
 }
 
@@ -835,8 +1301,13 @@ int64_t groupby_hash(Ctx &ctx, int key_bytes, const void *key, const int32_t *co
     a.lds_records = rec_bytes <= budget;  // is_smem_enough
     init_outputs(st, a.spec, g);
     const double bytes = (double)n * (4.0 * n_vals + 8.0) + (double)g * (key_bytes + 4.0 * a.spec.words);
-    GJ_LAUNCH("k_hgb_aggregate", bytes, k_hgb_aggregate, dim3(grid), dim3(kBlock),
-              a.lds_records ? rec_bytes : 0, st, a);
+    // LDS records are flushed by every workgroup, so fewer workgroups keep the flush cheap
+    const uint32_t agrid = a.lds_records ? std::min<uint32_t>(grid, 512) : grid;
+    const size_t alds = a.lds_records ? rec_bytes : 0;
+#define GJ_HAGG(NV) GJ_LAUNCH("k_hgb_aggregate", bytes, k_hgb_aggregate<NV>, dim3(agrid), dim3(kBlock), alds, st, a)
+    const int nvt = nv_tier(n_vals);
+    if (nvt == 1) GJ_HAGG(1); else if (nvt == 2) GJ_HAGG(2); else if (nvt == 4) GJ_HAGG(4); else GJ_HAGG(8);
+#undef GJ_HAGG
     const uint32_t cb = std::min<uint32_t>(ceil_div_u32(g, 256), 4096);
     if (key_bytes == 4)
         GJ_LAUNCH("k_copy_keys", 8.0 * g, k_copy_keys<int32_t>, dim3(cb), dim3(256), 0, st,
@@ -896,10 +1367,14 @@ int64_t groupby_sort(Ctx &ctx, int key_bytes, const void *key, const int32_t *co
     init_outputs(st, a.spec, g);
     const double bytes = (double)n * (key_bytes + 4.0 * n_vals + (gfur ? 4.0 : 0.0)) +
                          (double)g * (key_bytes + 4.0 * a.spec.words);
-    if (key_bytes == 4)
-        GJ_LAUNCH("k_sgb_reduce", bytes, k_sgb_reduce<int32_t>, dim3(tiles), dim3(kBlock), 0, st, a);
-    else
-        GJ_LAUNCH("k_sgb_reduce", bytes, k_sgb_reduce<int64_t>, dim3(tiles), dim3(kBlock), 0, st, a);
+#define GJ_SGB(K, NV) GJ_LAUNCH("k_sgb_reduce", bytes, (k_sgb_reduce<K, NV>), dim3(tiles), dim3(kBlock), 0, st, a)
+    const int nvt = nv_tier(n_vals);
+    if (key_bytes == 4) {
+        if (nvt == 1) GJ_SGB(int32_t, 1); else if (nvt == 2) GJ_SGB(int32_t, 2); else if (nvt == 4) GJ_SGB(int32_t, 4); else GJ_SGB(int32_t, 8);
+    } else {
+        if (nvt == 1) GJ_SGB(int64_t, 1); else if (nvt == 2) GJ_SGB(int64_t, 2); else if (nvt == 4) GJ_SGB(int64_t, 4); else GJ_SGB(int64_t, 8);
+    }
+#undef GJ_SGB
     return g;
 }
 

@@ -135,6 +135,13 @@ struct PartCols {
 void partition_run(Ctx &ctx, int key_bytes, const void *key_in, void *key_out, const PartCols &cols,
                    uint32_t n, int bit_lo, int bits, int passes, int mode, uint32_t *poff);
 
+// One stable pass over nseg segments (device offsets seg_off[0..nseg]), the digit of
+// segment s being the low seg_bits[s] (<= 8) bits of the key: partition (s, d) gets
+// index s * 256 + d in poff (nseg * 256 + 1 entries). Used for batches of instances.
+void partition_run_segments(Ctx &ctx, int key_bytes, const void *key_in, void *key_out, const PartCols &cols,
+                            uint32_t n, const uint32_t *seg_off, uint32_t nseg, const uint8_t *seg_bits,
+                            uint32_t *poff);
+
 // Stable LSD radix sort of n rows by the signed key (8 bits per pass; bytes that are
 // equal in every key are skipped). Moves the columns of `cols` along.
 void sort_run(Ctx &ctx, int key_bytes, const void *key_in, void *key_out, const PartCols &cols, uint32_t n);
@@ -150,6 +157,12 @@ int64_t groupby_hash(Ctx &ctx, int key_bytes, const void *key, const int32_t *co
                      const gj_agg *aggs, int n_aggs, int lds_budget, void **out_key, void **out_aggs);
 int64_t groupby_sort(Ctx &ctx, int key_bytes, const void *key, const int32_t *const *vals, int n_vals, uint32_t n,
                      const gj_agg *aggs, int n_aggs, bool gfur, void **out_key, void **out_aggs);
+
+// ---- select.hip -----------------------------------------------------------------------
+// Class 0..4 for the features (see gj.h); the network when loaded, else the cost model.
+int select_algorithm(const float *features, int op_kind, float *probs_out);
+void features_join(float *f, double nr, double ns, int key_bytes, int cr, int cs);
+void features_groupby(float *f, double n, int key_bytes, int nv);
 
 // ---- join.hip -------------------------------------------------------------------------
 struct JoinSide {
@@ -169,7 +182,11 @@ struct JoinOut {
 // Runs work-unit generation, the count pass and, after sizing, the write pass on
 // partitioned R and S. Output columns are allocated through ctx.output() with the
 // key width and the payload widths of R and S. Returns the number of output rows.
+// Batches (seg_bits != nullptr): partitions are (instance, digit) with index
+// instance * 256 + digit, instance i using seg_bits[i] partition bits; inst_off
+// (device, n_inst + 1) receives each instance's first output row.
 int64_t join_partitioned(Ctx &ctx, int key_bytes, const JoinSide &R, const JoinSide &S, int bits,
-                         int r_block, bool gfur, JoinOut *out);
+                         int r_block, bool gfur, JoinOut *out, const uint8_t *seg_bits = nullptr,
+                         uint32_t n_inst = 0, uint64_t *inst_off = nullptr);
 
 }  // namespace gj

@@ -49,6 +49,7 @@ struct JoinArgs {
     void *ts[8];
     const int32_t *rrow;  // GFUR: partitioned row ids of R
     const int32_t *srow;  // GFUR: partitioned row ids of S
+    const uint8_t *seg_bits;  // batches: partition bits of instance p >> 8 (skip_bits unused)
 };
 
 __global__ void k_unit_count(const uint32_t *__restrict__ rpo, const uint32_t *__restrict__ spo,
@@ -122,10 +123,12 @@ __global__ __launch_bounds__(kBlock) void k_join(JoinArgs a) {
         s_unit[1] = min(a.rc, nr - ra * a.rc);
         s_unit[2] = a.spo[p] + sb * kSPiece;
         s_unit[3] = min(kSPiece, ns - sb * kSPiece);
+        s_unit[4] = a.seg_bits ? a.seg_bits[p >> 8] : (uint32_t)a.skip_bits;
         s_long = 0;
     }
     __syncthreads();
     const uint32_t r0 = s_unit[0], rn = s_unit[1], s0 = s_unit[2], sn = s_unit[3];
+    const int skip_bits = (int)s_unit[4];
     int log2nb = 0;
     while ((1u << log2nb) < rn) ++log2nb;
     const uint32_t nb = 1u << log2nb;
@@ -135,7 +138,7 @@ __global__ __launch_bounds__(kBlock) void k_join(JoinArgs a) {
     for (uint32_t i = tid; i < rn; i += kBlock) s_rkey[i] = rkey[r0 + i];
     for (uint32_t b = tid; b <= nb; b += kBlock) s_b[b] = 0;
     __syncthreads();
-    for (uint32_t i = tid; i < rn; i += kBlock) atomicAdd(&s_b[bucket_of<K>(s_rkey[i], a.skip_bits, log2nb)], 1u);
+    for (uint32_t i = tid; i < rn; i += kBlock) atomicAdd(&s_b[bucket_of<K>(s_rkey[i], skip_bits, log2nb)], 1u);
     __syncthreads();
     {
         // inclusive scan of the nb counts: s_b[b] = end of bucket b
@@ -159,7 +162,7 @@ __global__ __launch_bounds__(kBlock) void k_join(JoinArgs a) {
     __syncthreads();
     // placement from the end of each bucket; afterwards s_b[b] = start of bucket b
     for (uint32_t i = tid; i < rn; i += kBlock) {
-        const uint32_t b = bucket_of<K>(s_rkey[i], a.skip_bits, log2nb);
+        const uint32_t b = bucket_of<K>(s_rkey[i], skip_bits, log2nb);
         const uint32_t slot = atomicSub(&s_b[b], 1u) - 1u;
         s_entry[slot] = (uint16_t)i;
     }
@@ -188,7 +191,7 @@ __global__ __launch_bounds__(kBlock) void k_join(JoinArgs a) {
             for (uint32_t base = 0; base < rn; base += kWave) {
                 const uint32_t i = base + lane;
                 const bool valid = i < rn;
-                const uint32_t b = valid ? bucket_of<K>(s_rkey[i], a.skip_bits, log2nb) : 0u;
+                const uint32_t b = valid ? bucket_of<K>(s_rkey[i], skip_bits, log2nb) : 0u;
                 const uint64_t peers = match_peers(b, log2nb, valid);
                 if (valid) {
                     const uint32_t rk = rank_below(peers);
@@ -225,7 +228,7 @@ __global__ __launch_bounds__(kBlock) void k_join(JoinArgs a) {
 #pragma unroll
             for (int r = 0; r < PB; ++r) {
                 if (base + r * kWave + lane < we) {
-                    const uint32_t b = bucket_of<K>(key[r], a.skip_bits, log2nb);
+                    const uint32_t b = bucket_of<K>(key[r], skip_bits, log2nb);
                     for (uint32_t e = s_b[b], end = s_b[b + 1]; e < end; ++e) cnt += (s_rkey[s_entry[e]] == key[r]);
                 }
             }
@@ -248,7 +251,7 @@ __global__ __launch_bounds__(kBlock) void k_join(JoinArgs a) {
                 c[r] = 0;
                 e1[r] = 0;
                 if (base + r * kWave + lane < we) {
-                    const uint32_t b = bucket_of<K>(key[r], a.skip_bits, log2nb);
+                    const uint32_t b = bucket_of<K>(key[r], skip_bits, log2nb);
                     for (uint32_t e = s_b[b], end = s_b[b + 1]; e < end; ++e) {
                         const uint32_t ri = s_entry[e];
                         if (s_rkey[ri] == key[r]) {
@@ -291,7 +294,7 @@ __global__ __launch_bounds__(kBlock) void k_join(JoinArgs a) {
                     const uint32_t i = base + r * kWave + lane;
                     uint64_t p = pos[r];
                     const uint64_t sr = a.srow ? (uint64_t)a.srow[s0 + i] : (uint64_t)(s0 + i);
-                    const uint32_t b = bucket_of<K>(key[r], a.skip_bits, log2nb);
+                    const uint32_t b = bucket_of<K>(key[r], skip_bits, log2nb);
                     for (uint32_t e = s_b[b], end = s_b[b + 1]; e < end; ++e) {
                         const uint32_t ri = s_entry[e];
                         if (s_rkey[ri] != key[r] || p >= a.t_rows) continue;
@@ -307,19 +310,30 @@ __global__ __launch_bounds__(kBlock) void k_join(JoinArgs a) {
     }
 }
 
+// Output offset of each instance of a batch: the write offset of its first unit.
+__global__ void k_instance_offsets(const uint32_t *__restrict__ ubase, const uint64_t *__restrict__ woff,
+                                   uint32_t n_inst, uint64_t total, uint64_t *__restrict__ out) {
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i <= n_inst; i += gridDim.x * blockDim.x)
+        out[i] = (i == n_inst) ? total : woff[(uint64_t)ubase[i << 8] * kWaves];
+}
+
 }  // namespace
 
 int64_t join_partitioned(Ctx &ctx, int key_bytes, const JoinSide &R, const JoinSide &S, int bits,
-                         int r_block, bool gfur, JoinOut *out) {
+                         int r_block, bool gfur, JoinOut *out, const uint8_t *seg_bits, uint32_t n_inst,
+                         uint64_t *inst_off) {
     hipStream_t s = ctx.stream;
     require(r_block >= 64 && r_block <= (int)kMaxBuild, "R build block must be 64..4096 rows");
-    const uint32_t np = 1u << bits;
+    const uint32_t np = seg_bits ? (n_inst << 8) : (1u << bits);
     uint32_t *ucnt = ctx.scratch_n<uint32_t>(np + 1);
     GJ_LAUNCH("k_unit_count", 20.0 * np, k_unit_count, dim3(std::min<uint32_t>((np + 255) / 256, 1024)),
               dim3(256), 0, s, R.poff, S.poff, np, (uint32_t)r_block, ucnt);
     scan_exclusive_u32(ctx, ucnt, ucnt, np, ucnt + np);
     const uint32_t nunits = read_back(ucnt + np, s);
-    if (nunits == 0) return 0;
+    if (nunits == 0) {
+        if (inst_off) fill_u64(s, inst_off, 0ull, (uint64_t)n_inst + 1);
+        return 0;
+    }
 
     JoinArgs a{};
     a.rkey = R.key;
@@ -330,6 +344,7 @@ int64_t join_partitioned(Ctx &ctx, int key_bytes, const JoinSide &R, const JoinS
     a.ubase = ucnt;
     a.rc = (uint32_t)r_block;
     a.skip_bits = bits;
+    a.seg_bits = seg_bits;
     const uint64_t nw = (uint64_t)nunits * kWaves;
     uint64_t *wcnt = ctx.scratch_n<uint64_t>(nw + 1);
     a.wcnt = wcnt;
@@ -341,6 +356,10 @@ int64_t join_partitioned(Ctx &ctx, int key_bytes, const JoinSide &R, const JoinS
         GJ_LAUNCH("k_join_count", key_reads, (k_join<int64_t, false>), dim3(nunits), dim3(kBlock), 0, s, a);
     scan_exclusive_u64(ctx, wcnt, wcnt, nw, wcnt + nw);
     const uint64_t T = read_back(wcnt + nw, s);
+    if (inst_off)
+        GJ_LAUNCH("k_instance_offsets", 16.0 * n_inst, k_instance_offsets,
+                  dim3(std::min<uint32_t>(ceil_div_u32(n_inst + 1, 256), 1024)), dim3(256), 0, s, ucnt, wcnt, n_inst,
+                  T, inst_off);
     if (T == 0) return 0;
 
     out->key = ctx.output(T * (uint64_t)key_bytes);

@@ -49,7 +49,15 @@ struct PassArgs {
     uint32_t chunk_rows;
     uint32_t *hist;  // [chunks][2^bits], laid out as (segment, digit, chunk)
     uint32_t n_rows; // rows of the output columns; every store is checked against it
+    const uint8_t *seg_bits;  // optional: digit bits per segment (<= bits; batches of instances)
 };
+
+// The digit function of the segment a chunk belongs to.
+__device__ __forceinline__ DigitFn seg_digit(const PassArgs &a, uint32_t seg) {
+    DigitFn d = a.dig;
+    if (a.seg_bits) d.mask = (1u << a.seg_bits[seg]) - 1u;
+    return d;
+}
 
 struct ChunkLoc {
     uint32_t seg, j, m, row0, row1, hbase;
@@ -109,6 +117,7 @@ __global__ __launch_bounds__(kBlock) void k_hist(PassArgs a) {
     if (!L.ok) return;
     const K *__restrict__ keys = static_cast<const K *>(a.key_in);
     const int tid = threadIdx.x, w = tid / kWave;
+    const DigitFn dig = seg_digit(a, L.seg);
     for (uint32_t base = L.row0; base < L.row1; base += kBlock * U) {
         K k[U];
 #pragma unroll
@@ -119,7 +128,7 @@ __global__ __launch_bounds__(kBlock) void k_hist(PassArgs a) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const bool valid = base + u * kBlock + tid < L.row1;
-            const uint32_t d = digit_of<K>(k[u], a.dig);
+            const uint32_t d = digit_of<K>(k[u], dig);
             const uint64_t peers = match_peers(d, a.bits, valid);
             if (valid && rank_below(peers) == 0) s_cnt[w][d] += (uint32_t)__popcll(peers);
         }
@@ -152,7 +161,7 @@ struct ScatterShared {
 };
 
 template <typename K, int BLOCK, int ITEMS, int G, bool FULL>
-__device__ __forceinline__ void scatter_tile(const PassArgs &a, ScatterShared<BLOCK> &S,
+__device__ __forceinline__ void scatter_tile(const PassArgs &a, const DigitFn &dig, ScatterShared<BLOCK> &S,
                                              uint32_t (*s_buf)[BLOCK * ITEMS], uint32_t tile0, uint32_t nt) {
     constexpr uint32_t TILE = BLOCK * ITEMS;
     constexpr int W = BLOCK / kWave;
@@ -191,7 +200,7 @@ __device__ __forceinline__ void scatter_tile(const PassArgs &a, ScatterShared<BL
 #pragma unroll
     for (int r = 0; r < ITEMS; ++r) {
         const bool valid = GJ_VALID(r);
-        const uint32_t d = digit_of<K>(key[r], a.dig);
+        const uint32_t d = digit_of<K>(key[r], dig);
         const uint64_t peers = match_peers(d, a.bits, valid);
         uint32_t p = 0;
         if (valid) {
@@ -229,7 +238,7 @@ __device__ __forceinline__ void scatter_tile(const PassArgs &a, ScatterShared<BL
 #pragma unroll
     for (int r = 0; r < ITEMS; ++r) {
         if (GJ_VALID(r)) {
-            const uint32_t d = digit_of<K>(key[r], a.dig);
+            const uint32_t d = digit_of<K>(key[r], dig);
             pos[r] += S.start[d] + S.wcnt[w][d];
             sk[pos[r]] = key[r];
         }
@@ -243,7 +252,7 @@ __device__ __forceinline__ void scatter_tile(const PassArgs &a, ScatterShared<BL
         dst[k] = 0xFFFFFFFFu;
         if (FULL || i < nt) {
             const K kk = sk[i];
-            const uint32_t d = digit_of<K>(kk, a.dig);
+            const uint32_t d = digit_of<K>(kk, dig);
             const uint32_t t = S.cur[d] + i - S.start[d];
             if (t < a.n_rows) {  // always true when the offsets are right
                 dst[k] = t;
@@ -327,10 +336,11 @@ __global__ __launch_bounds__(BLOCK) void k_scatter(PassArgs a) {
     for (uint32_t d = threadIdx.x; d < kRadix; d += BLOCK)
         S.cur[d] = d < R ? base_off + a.hist[L.hbase + d * L.m + L.j] : 0u;
 
+    const DigitFn dig = seg_digit(a, L.seg);
     uint32_t tile0 = L.row0;
     for (; tile0 + TILE <= L.row1; tile0 += TILE)
-        scatter_tile<K, BLOCK, ITEMS, G, true>(a, S, s_buf, tile0, TILE);
-    if (tile0 < L.row1) scatter_tile<K, BLOCK, ITEMS, G, false>(a, S, s_buf, tile0, L.row1 - tile0);
+        scatter_tile<K, BLOCK, ITEMS, G, true>(a, dig, S, s_buf, tile0, TILE);
+    if (tile0 < L.row1) scatter_tile<K, BLOCK, ITEMS, G, false>(a, dig, S, s_buf, tile0, L.row1 - tile0);
 }
 
 __global__ void k_poff(const uint32_t *__restrict__ seg_off, uint32_t nseg,
@@ -594,6 +604,46 @@ void sort_run(Ctx &ctx, int key_bytes, const void *key_in, void *key_out, const 
         kin = kout;
         for (int c = 0; c < ncols; ++c) cin[c] = cout[c];
     }
+}
+
+
+void partition_run_segments(Ctx &ctx, int key_bytes, const void *key_in, void *key_out, const PartCols &cols,
+                            uint32_t n, const uint32_t *seg_off, uint32_t nseg, const uint8_t *seg_bits,
+                            uint32_t *poff) {
+    require(key_bytes == 4 || key_bytes == 8, "key width must be 4 or 8 bytes");
+    hipStream_t s = ctx.stream;
+    const int ncols = cols.n + (cols.gen_rowid ? 1 : 0);
+    require(ncols <= kMaxCols, "too many columns");
+    const void *cin[kMaxCols];
+    void *cout[kMaxCols];
+    for (int c = 0; c < ncols; ++c) {
+        const bool is_rowid = cols.gen_rowid && c == cols.n;
+        cin[c] = is_rowid ? nullptr : cols.in[c];
+        cout[c] = is_rowid ? cols.rowid_out : cols.out[c];
+    }
+    PassArgs a{};
+    a.key_in = key_in;
+    a.key_out = key_out;
+    int map[kMaxCols];
+    assign_cols(a, cols, cin, cout, true, map);
+    a.bits = 8;
+    a.dig = DigitFn{kDigitBits, 0, 0xFFu};
+    a.seg_off = seg_off;
+    a.nseg = nseg;
+    a.n_rows = n;
+    a.seg_bits = seg_bits;
+    if (n > 0) {
+        if (key_bytes == 4) run_pass<int32_t>(ctx, a, n);
+        else run_pass<int64_t>(ctx, a, n);
+    } else {
+        uint32_t *cb = ctx.scratch_n<uint32_t>(nseg + 1);
+        fill_u32(s, cb, 0u, nseg + 1);
+        a.chunk_base = cb;
+        a.hist = ctx.scratch_n<uint32_t>(1);
+    }
+    const uint64_t np = (uint64_t)nseg << 8;
+    GJ_LAUNCH("k_poff", 8.0 * (np + 1), k_poff, dim3((uint32_t)std::min<uint64_t>((np + 255) / 256, 4096)),
+              dim3(256), 0, s, seg_off, nseg, a.chunk_base, a.hist, 8, poff);
 }
 
 }  // namespace gj

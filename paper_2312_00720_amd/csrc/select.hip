@@ -1,0 +1,230 @@
+// Algorithm selection: an analytical bandwidth cost model (the paper's models of
+// Sections 4.1.3 and 4.1.4 applied to this implementation's passes, with
+// constants measured on MI355X) and a small learned network over the same
+// workload features. The network decides when trained weights are loaded and
+// finite; the cost model decides otherwise. Either way only speed changes:
+// every algorithm computes the same result.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <mutex>
+#include <vector>
+
+#include "internal.hpp"
+
+namespace gj {
+namespace {
+
+// MI355X constants (bytes/s): effective streaming rate of the partition and
+// materialization kernels, and the random-access penalty of 4-byte gathers
+// (the B_G / B_R ratio of Section 4.1.1, re-measured on this GPU).
+struct Consts {
+    double seq = 2.7e12;
+    double rand_ratio = 24.0;
+    double atomic_rate = 2.5e10;  // global atomic updates per second (scattered)
+    double lds_record_bytes = 65536.0;
+};
+Consts g_c;
+
+struct Workload {
+    bool join;
+    double nr, ns, g, w, cr, cs, alpha, mr;
+};
+
+Workload decode(const float *f) {
+    Workload x{};
+    x.join = f[0] > 0.5f;
+    x.nr = exp2(32.0 * f[1]);
+    x.ns = exp2(32.0 * f[2]);
+    x.g = exp2(32.0 * f[3]);
+    x.w = 8.0 * f[4];
+    x.cr = std::max(0.0, std::round(8.0 * f[5]));
+    x.cs = std::max(0.0, std::round(8.0 * f[6]));
+    x.alpha = 1.2 * f[7];
+    x.mr = f[8];
+    return x;
+}
+
+int passes_for(double rows) {
+    const int bits = std::max(1, (int)std::ceil(std::log2(std::max(1.0, rows / 2048.0))));
+    return std::min(bits, 16) > 8 ? 2 : 1;
+}
+
+void cost_join(const Workload &x, double *t) {
+    const double R = x.nr, S = x.ns, w = x.w;
+    const double T = x.mr * S;  // PK-FK
+    const double P = passes_for(R);
+    const double r = 4.0 * x.cr, s = 4.0 * x.cs;
+    const double hist = P * w * (R + S), count = w * (R + S);
+    const double gftr = hist + 2 * P * ((w + r) * R + (w + s) * S) + count + w * (R + S) + r * R + s * S +
+                        T * (w + r + s);
+    const double gfur_seq = hist + 2 * P * (w + 4) * (R + S) + count + w * (R + S) + 4 * (R + S) + T * (w + r + s);
+    const double gfur_rand = T * (r + s) * g_c.rand_ratio;  // each gathered byte at B_G / ratio
+    t[0] = gftr / g_c.seq;
+    t[1] = (gfur_seq + gfur_rand) / g_c.seq;
+    t[2] = t[3] = t[4] = INFINITY;
+}
+
+void cost_groupby(const Workload &x, double *t) {
+    const double N = x.nr, g = std::min(x.g, x.nr), w = x.w, v = x.cr;
+    const double rec = 8 + 16 * v;  // count + (sum, min, max) per value column
+    const double out = g * (w + rec);
+    // hash: table fill and insert stream; aggregation in LDS records when they fit,
+    // else one scattered global atomic per row and aggregate
+    const double table = 1.5 * N * (w == 4 ? 8 : 4);
+    const double hstream = table + N * (w + 8) + N * (8 + 4 * v) + out;
+    double th = hstream / g_c.seq;
+    if (g * (rec + 4) > g_c.lds_record_bytes) th += N * (1 + 3 * v) / g_c.atomic_rate;
+    if (g * 16 > 32e6) th += N * 64 * 2 / g_c.seq;  // table probes miss the caches
+    // sort: LSD passes over the bytes that differ, then the segmented reduction
+    const double sp = std::max(1.0, std::ceil(std::log2(std::max(2.0, g)) / 8.0));
+    const double ts = (w * N + sp * (w * N + 2 * (w + 4 * v) * N) + (w + 4 * v) * N + out) / g_c.seq;
+    // partition: hashed partitioning, discovery (two key reads), aggregation
+    const double P = passes_for(N);
+    double tp = (P * w * N + 2 * P * (w + 4 * v) * N + 2 * w * N + (w + 4 * v) * N + out) / g_c.seq;
+    if (g < 256) tp *= 1.0 + 256.0 / std::max(1.0, g) * 0.05;  // few busy partitions
+    t[0] = t[1] = INFINITY;
+    t[2] = th;
+    t[3] = ts;
+    t[4] = tp;
+}
+
+// ---- the learned network, evaluated on the host for one sample ----
+constexpr int F = 12, H = 64, C = 5;
+std::mutex g_mu;
+std::vector<float> g_w;  // empty = no trained weights
+
+void mlp_probs(const float *theta, const float *x, const float *mask, float *p) {
+    const float *W1 = theta, *b1 = W1 + H * F, *W2 = b1 + H, *b2 = W2 + H * H, *W3 = b2 + H, *b3 = W3 + C * H;
+    float h1[H], h2[H], z[C];
+    for (int i = 0; i < H; ++i) {
+        float a = 0.f;
+        for (int k = 0; k < F; ++k) a = fmaf(x[k], W1[i * F + k], a);
+        h1[i] = std::max(a + b1[i], 0.f);
+    }
+    for (int i = 0; i < H; ++i) {
+        float a = 0.f;
+        for (int k = 0; k < H; ++k) a = fmaf(h1[k], W2[i * H + k], a);
+        h2[i] = std::max(a + b2[i], 0.f);
+    }
+    float mx = -INFINITY;
+    for (int c = 0; c < C; ++c) {
+        float a = 0.f;
+        for (int k = 0; k < H; ++k) a = fmaf(h2[k], W3[c * H + k], a);
+        z[c] = a + b3[c];
+        if (mask[c] > 0.f) mx = std::max(mx, z[c]);
+    }
+    float sum = 0.f;
+    for (int c = 0; c < C; ++c) {
+        p[c] = mask[c] > 0.f ? expf(z[c] - mx) : 0.f;
+        sum += p[c];
+    }
+    for (int c = 0; c < C; ++c) p[c] /= sum;
+}
+
+}  // namespace
+
+int select_algorithm(const float *features, int op_kind, float *probs_out) {
+    const Workload x = decode(features);
+    float mask[C] = {0, 0, 0, 0, 0};
+    if (op_kind == 0) mask[0] = mask[1] = 1;
+    else mask[2] = mask[3] = mask[4] = 1;
+    std::vector<float> w;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        w = g_w;
+    }
+    if (!w.empty()) {
+        float p[C];
+        mlp_probs(w.data(), features, mask, p);
+        bool ok = true;
+        for (int c = 0; c < C; ++c) ok &= std::isfinite(p[c]);
+        if (ok) {
+            int best = -1;
+            for (int c = 0; c < C; ++c)
+                if (mask[c] > 0 && (best < 0 || p[c] > p[best])) best = c;
+            if (probs_out) memcpy(probs_out, p, sizeof(p));
+            return best;
+        }
+    }
+    double t[C];
+    if (x.join) cost_join(x, t);
+    else cost_groupby(x, t);
+    int best = -1;
+    for (int c = 0; c < C; ++c)
+        if (mask[c] > 0 && (best < 0 || t[c] < t[best])) best = c;
+    if (probs_out)
+        for (int c = 0; c < C; ++c) probs_out[c] = (c == best) ? 1.f : 0.f;
+    return best;
+}
+
+void features_join(float *f, double nr, double ns, int key_bytes, int cr, int cs) {
+    memset(f, 0, 12 * sizeof(float));
+    f[0] = 1.f;
+    f[1] = (float)(std::log2(std::max(1.0, nr)) / 32.0);
+    f[2] = (float)(std::log2(std::max(1.0, ns)) / 32.0);
+    f[3] = f[1];
+    f[4] = key_bytes / 8.f;
+    f[5] = cr / 8.f;
+    f[6] = cs / 8.f;
+    f[7] = 0.f;  // skew unknown to the operator: assume uniform
+    f[8] = 1.f;  // match ratio unknown: assume every probe row matches
+    f[9] = (float)(std::log2(std::max(1.0, ns) / std::max(1.0, nr)) / 32.0);
+    f[10] = f[2];
+    f[11] = (float)(std::log2(std::max(1.0, nr * (key_bytes + 4.0 * cr) + ns * (key_bytes + 4.0 * cs))) / 48.0);
+}
+
+void features_groupby(float *f, double n, int key_bytes, int nv) {
+    memset(f, 0, 12 * sizeof(float));
+    f[0] = 0.f;
+    f[1] = (float)(std::log2(std::max(1.0, n)) / 32.0);
+    // the group count is unknown before the call (Section 2.2): assume about n / 16
+    const double g = std::max(1.0, n / 16.0);
+    f[3] = (float)(std::log2(g) / 32.0);
+    f[4] = key_bytes / 8.f;
+    f[5] = nv / 8.f;
+    f[8] = 1.f;
+    f[9] = (float)(std::log2(n / g) / 32.0);
+    f[10] = f[3];
+    f[11] = (float)(std::log2(std::max(1.0, n * (key_bytes + 4.0 * nv))) / 48.0);
+}
+
+}  // namespace gj
+
+extern "C" {
+
+int gj_cost_model(const float features[12], int32_t op_kind, double predicted_seconds[5]) {
+    if (!features || !predicted_seconds || op_kind < 0 || op_kind > 1) return GJ_EINVAL;
+    const gj::Workload x = gj::decode(features);
+    if (op_kind == 0) gj::cost_join(x, predicted_seconds);
+    else gj::cost_groupby(x, predicted_seconds);
+    return GJ_OK;
+}
+
+int gj_select(const float features[12], int32_t op_kind, int32_t *choice, float probs[5]) {
+    if (!features || !choice || op_kind < 0 || op_kind > 1) return GJ_EINVAL;
+    *choice = gj::select_algorithm(features, op_kind, probs);
+    return GJ_OK;
+}
+
+int gj_selector_set_weights(const float *params, int32_t n) {
+    std::lock_guard<std::mutex> lk(gj::g_mu);
+    if (!params || n == 0) {
+        gj::g_w.clear();
+        return GJ_OK;
+    }
+    if (n != 5317) return GJ_EINVAL;
+    gj::g_w.assign(params, params + n);
+    return GJ_OK;
+}
+
+int gj_set_cost_constants(double seq_bytes_per_s, double rand_ratio, double atomic_rate) {
+    if (!(seq_bytes_per_s > 0) || !(rand_ratio >= 1) || !(atomic_rate > 0)) return GJ_EINVAL;
+    gj::g_c.seq = seq_bytes_per_s;
+    gj::g_c.rand_ratio = rand_ratio;
+    gj::g_c.atomic_rate = atomic_rate;
+    return GJ_OK;
+}
+
+}  // extern "C"

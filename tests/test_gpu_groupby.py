@@ -117,3 +117,20 @@ def test_groupby_deterministic(algo):
     np.testing.assert_array_equal(a[0], b[0])
     for x, y in zip(a[1], b[1]):
         np.testing.assert_array_equal(x, y)
+
+
+@pytest.mark.parametrize("dt", [np.int32, np.int64])
+def test_partition_oversized_partitions(dt):
+    """Partitions above one discovery slice (65536 rows) are discovered by several
+    workgroups and merged: few groups, a Zipf-hot key, and the key value that the
+    LDS tables use as their empty marker inside an oversized partition."""
+    g = datagen.rng(21)
+    n = 400000
+    lo = np.iinfo(dt).min
+    keys = np.where(g.uniform(size=n) < 0.7, 0, g.integers(-3, 4, size=n)).astype(dt)
+    keys[g.choice(n, 5000, replace=False)] = lo
+    vals = [g.integers(-2**20, 2**20 + 1, size=n).astype(np.int32) for _ in range(2)]
+    check(keys, vals, algo="partition")
+    check(keys, vals, algo="partition", radix_bits=2, mat="gfur")
+    d = datagen.groupby_input(n, 16, 2, seed=22, alpha=1.0)
+    check(d["key"], d["vals"], algo="partition")

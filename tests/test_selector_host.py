@@ -1,0 +1,97 @@
+"""Host-side selection logic of libgj (no GPU work is launched): the network's
+host forward against the float64 reference, the fallback to the cost model, and
+properties of the cost model."""
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import mlp
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def gj():
+    lib = os.path.join(ROOT, "paper_2312_00720_amd", "libgj.so")
+    if not os.path.exists(lib):
+        from paper_2312_00720_amd import build
+        build.build()
+    import paper_2312_00720_amd as g
+    yield g
+    g.selector_set_weights(None)
+
+
+def join_features(log_r, log_s, mr, cols=2, kb=4):
+    return [1, log_r / 32, log_s / 32, log_r / 32, kb / 8, cols / 8, cols / 8, 0, mr,
+            (log_s - log_r) / 32, math.log2(mr * 2 ** log_s) / 32, 30 / 48]
+
+
+def gb_features(log_n, log_g, nv=2, kb=4):
+    return [0, log_n / 32, 0, log_g / 32, kb / 8, nv / 8, 0, 0, 1, (log_n - log_g) / 32, log_g / 32, 30 / 48]
+
+
+def test_cost_model_marks_invalid_classes(gj):
+    t = gj.cost_model(join_features(20, 21, 1.0), 0)
+    assert all(math.isinf(x) for x in t[2:]) and all(x > 0 and math.isfinite(x) for x in t[:2])
+    t = gj.cost_model(gb_features(24, 12), 1)
+    assert all(math.isinf(x) for x in t[:2]) and all(x > 0 and math.isfinite(x) for x in t[2:])
+
+
+def test_cost_model_gftr_gfur_crossover_in_match_ratio(gj):
+    """As in Section 4.1.4, GFTR wins at high match ratios and GFUR at low ones."""
+    hi = gj.cost_model(join_features(27, 28, 1.0), 0)
+    lo = gj.cost_model(join_features(27, 28, 0.02), 0)
+    assert hi[0] < hi[1]
+    assert lo[1] < lo[0]
+    # the GFUR - GFTR gap grows with the match ratio
+    gaps = [(lambda t: t[1] - t[0])(gj.cost_model(join_features(27, 28, m), 0)) for m in (0.1, 0.3, 0.6, 1.0)]
+    assert all(b > a for a, b in zip(gaps, gaps[1:]))
+
+
+def test_cost_model_hash_wins_small_g_loses_large_g(gj):
+    small = gj.cost_model(gb_features(26, 8), 1)
+    large = gj.cost_model(gb_features(26, 22), 1)
+    assert small[2] < 2 * min(small[3], small[4])
+    assert large[2] > min(large[3], large[4])
+
+
+def test_select_without_weights_is_cost_model_argmin(gj):
+    gj.selector_set_weights(None)
+    for f, k in [(join_features(22, 24, 0.9), 0), (join_features(22, 24, 0.03), 0),
+                 (gb_features(24, 6), 1), (gb_features(24, 20), 1)]:
+        c, p = gj.select(f, k)
+        t = gj.cost_model(f, k)
+        assert c == int(np.argmin(t))
+        assert p[c] == 1.0
+
+
+def test_host_network_matches_reference(gj):
+    theta = mlp.init(11)
+    gj.selector_set_weights(theta.astype(np.float32))
+    rng = np.random.default_rng(12)
+    for _ in range(50):
+        f = rng.uniform(0, 1, size=12).astype(np.float32)
+        k = int(rng.integers(0, 2))
+        f[0] = 1.0 if k == 0 else 0.0
+        mask = np.zeros((1, 5))
+        mask[0, 0:2] = 1 if k == 0 else 0
+        mask[0, 2:5] = 0 if k == 0 else 1
+        p_ref, _ = mlp.forward(theta.astype(np.float32).astype(np.float64), f[None].astype(np.float64), mask)
+        c, p = gj.select(list(f), k)
+        np.testing.assert_allclose(p, p_ref[0], rtol=1e-4, atol=1e-6)
+        assert mask[0, c] == 1
+        if np.sort(p_ref[0])[-1] - np.sort(p_ref[0])[-2] > 1e-4:
+            assert c == int(np.argmax(p_ref[0]))
+    gj.selector_set_weights(None)
+
+
+def test_non_finite_weights_fall_back_to_cost_model(gj):
+    theta = mlp.init(13).astype(np.float32)
+    theta[5] = np.nan
+    gj.selector_set_weights(theta)
+    f = gb_features(24, 20)
+    c, p = gj.select(f, 1)
+    assert c == int(np.argmin(gj.cost_model(f, 1)))
+    gj.selector_set_weights(None)
