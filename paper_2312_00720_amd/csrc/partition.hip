@@ -125,12 +125,10 @@ __global__ __launch_bounds__(kBlock) void k_hist(PassArgs a) {
             const uint32_t row = base + u * kBlock + tid;
             k[u] = row < L.row1 ? keys[row] : K(0);
         }
+        // counting needs no order, so plain LDS atomics into the wave's own histogram
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const bool valid = base + u * kBlock + tid < L.row1;
-            const uint32_t d = digit_of<K>(k[u], dig);
-            const uint64_t peers = match_peers(d, a.bits, valid);
-            if (valid && rank_below(peers) == 0) s_cnt[w][d] += (uint32_t)__popcll(peers);
+            if (base + u * kBlock + tid < L.row1) atomicAdd(&s_cnt[w][digit_of<K>(k[u], dig)], 1u);
         }
     }
     __syncthreads();
