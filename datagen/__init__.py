@@ -164,3 +164,12 @@ def raw_keys(n: int, seed: int, key_bytes: int = 4, lo=None, hi=None) -> np.ndar
     lo = -(2 ** 63) if lo is None else lo
     hi = 2 ** 63 - 1 if hi is None else hi
     return g.integers(lo, hi, size=n, dtype=np.int64, endpoint=True)
+
+
+def batch_sizes(n: int, seed: int, lo_log2: float = 8.0, hi_log2: float = 20.0, m_lo: int = 4, m_hi: int = 16):
+    """Instance sizes of a join batch: |R_i| = round(2^U(lo, hi)) and
+    |S_i| = m_i |R_i| with m_i uniform over {m_lo..m_hi}."""
+    g = rng(seed)
+    r = np.rint(2.0 ** g.uniform(lo_log2, hi_log2, size=n)).astype(np.int64)
+    m = g.integers(m_lo, m_hi + 1, size=n)
+    return r, r * m

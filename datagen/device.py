@@ -76,3 +76,47 @@ def groupby_input(n: int, g_card: int, n_vals: int, seed: int, *, alpha: float =
     vals = [torch.randint(lo, hi + 1, (n,), generator=g, device=device, dtype=torch.int64)
             .to(torch.int32) for _ in range(n_vals)]
     return {"key": k, "vals": vals}
+
+
+def join_batch(r_sizes, s_sizes, c: int, seed: int, device="cuda", chunk_rows: int = 1 << 28) -> dict:
+    """A batch of independent PK-FK joins, stored back to back: instance i has
+    R_i.key a random permutation of 0..|R_i|-1 and S_i.key uniform over R_i's
+    keys (every S row matches), c int32 payload columns per side uniform over the
+    full range. Drawn in chunks of instances so temporaries stay small."""
+    import numpy as np
+    r_sizes = np.asarray(r_sizes, dtype=np.int64)
+    s_sizes = np.asarray(s_sizes, dtype=np.int64)
+    n = len(r_sizes)
+    ro = np.concatenate([[0], np.cumsum(r_sizes)])
+    so = np.concatenate([[0], np.cumsum(s_sizes)])
+    g = generator(seed, device)
+    r_key = torch.empty(int(ro[-1]), dtype=torch.int32, device=device)
+    s_key = torch.empty(int(so[-1]), dtype=torch.int32, device=device)
+    i = 0
+    while i < n:
+        j, rows = i, 0
+        while j < n and (j == i or rows + int(s_sizes[j]) <= chunk_rows):
+            rows += int(s_sizes[j])
+            j += 1
+        rs = torch.from_numpy(r_sizes[i:j]).to(device)
+        ss = torch.from_numpy(s_sizes[i:j]).to(device)
+        m = torch.arange(j - i, device=device)
+        # R: local row ids, shuffled within each instance
+        inst = torch.repeat_interleave(m, rs)
+        start = torch.from_numpy(ro[i:j] - ro[i]).to(device)
+        local = torch.arange(int(ro[j] - ro[i]), device=device) - start[inst]
+        rnd = torch.randint(0, 1 << 31, (local.numel(),), generator=g, device=device, dtype=torch.int64)
+        order = torch.argsort(inst * (1 << 31) + rnd)
+        r_key[int(ro[i]):int(ro[j])] = local[order].to(torch.int32)
+        del inst, local, rnd, order
+        # S: uniform over the instance's keys
+        sinst = torch.repeat_interleave(m, ss)
+        u = torch.rand(int(so[j] - so[i]), generator=g, device=device, dtype=torch.float64)
+        k = torch.minimum((u * rs[sinst]).to(torch.int64), rs[sinst] - 1)
+        s_key[int(so[i]):int(so[j])] = k.to(torch.int32)
+        del sinst, u, k
+        i = j
+    r_pay = payloads(g, int(ro[-1]), c, device)
+    s_pay = payloads(g, int(so[-1]), c, device)
+    return {"r_key": r_key, "r_pay": r_pay, "s_key": s_key, "s_pay": s_pay,
+            "r_off": [int(x) for x in ro], "s_off": [int(x) for x in so]}

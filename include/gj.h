@@ -130,6 +130,92 @@ typedef struct {
 int gj_join_batch(const gj_rel_batch *R, const gj_rel_batch *S, const gj_join_opts *opts,
                   const gj_allocator *alloc, void *stream, gj_join_out *out, int64_t *out_offsets);
 
+/* ---- Batch plans: persistent kernels replayed as one HIP graph ----------------
+ * A plan fixes the shape of a batch (row counts per instance, column types,
+ * options), borrows its input columns (their addresses are baked in) and owns
+ * every block of device memory the batch needs: scratch, per-instance device
+ * parameters and output columns of a capacity fixed at creation. Running a plan
+ * enqueues kernels only: no allocation, no host synchronization, no copy, no
+ * memset. Every data-dependent size (work units, output rows) stays in device
+ * memory, and the kernels that depend on it are persistent workgroups looping
+ * over the device count. So the run can be captured once into a HIP graph and
+ * replayed with one hipGraphLaunch per batch; refilling the input columns in
+ * place and launching again processes new data of the same shape.
+ * Calls on one plan must not overlap (its scratch is shared); different plans
+ * are independent. Plan memory comes from `alloc` (hipMalloc when NULL) and is
+ * returned by gj_plan_destroy; `alloc` must stay valid until then.
+ */
+typedef struct gj_plan gj_plan;
+
+/* Tuning of a join plan per size class c = floor(log2 |R_i|) (0..31). A zero
+ * field selects the built-in rule. Tuning changes speed, never results. */
+#define GJ_TUNE_CLASSES 32
+typedef struct {
+    int8_t part_log2[GJ_TUNE_CLASSES];    /* target rows per partition 2^v, v in 6..12 (rule: 11); the
+                                             instance gets clamp(ceil(log2 |R_i|) - v, 0, 8) bits */
+    int8_t bucket_shift[GJ_TUNE_CLASSES]; /* LDS hash buckets per build block: 2^(ceil(log2 rows) + shift),
+                                             shift 0 or 1, capped at 4096 (rule: 0) */
+    int32_t scatter_variant;              /* partition scatter shape, 1..10 (rule: 0 = built-in) */
+} gj_join_tuning;
+
+/*
+ * Plan for the batch of gj_join_batch (same layout and rules), with one
+ * difference: instances are grouped into consecutive runs of at most 2^30 rows
+ * per side, each run partitioned and joined as one segment, so the batch itself
+ * may exceed 2^31 rows (each instance may not). Output columns hold
+ * out_capacity rows (0 = the sum of |S_i|, which bounds every PK-FK batch);
+ * rows past the capacity are dropped and reported by gj_join_plan_result.
+ * mat must be GJ_MAT_GFTR or GJ_MAT_GFUR (GJ_MAT_AUTO picks GFTR). tuning may
+ * be NULL (built-in rules). Work-unit room per instance assumes that no R
+ * partition of it exceeds twice the build block (always true for unique R keys
+ * and the default rules); otherwise the result reports GJ_ECAPACITY.
+ * Synchronizes with `stream` once, to upload the per-instance parameters.
+ */
+int gj_join_plan_create(const gj_rel_batch *R, const gj_rel_batch *S, const gj_join_opts *opts,
+                        const gj_join_tuning *tuning, int64_t out_capacity, const gj_allocator *alloc,
+                        void *stream, gj_plan **plan);
+
+/* Enqueue one run of the plan on `stream` (kernels only). */
+int gj_plan_run(gj_plan *plan, void *stream);
+
+/* Capture one run into a HIP graph and instantiate it (once per plan; the
+ * capture itself runs nothing). */
+int gj_plan_capture(gj_plan *plan);
+
+/* Launch the captured graph on `stream` (one hipGraphLaunch). */
+int gj_plan_launch(gj_plan *plan, void *stream);
+
+/* Synchronizes with `stream` and reports the last run of a join plan: out
+ * receives the plan's output columns (owned by the plan, valid until
+ * gj_plan_destroy) and n_rows = |T|; out_offsets (host, n_instances + 1) the
+ * first output row of each instance. Returns GJ_ECAPACITY, with n_rows set to
+ * the required output rows, when the output or the work-unit room was too
+ * small; the columns then hold a truncated result. */
+int gj_join_plan_result(gj_plan *plan, void *stream, gj_join_out *out, int64_t *out_offsets);
+
+typedef struct {
+    int64_t launches_per_run; /* kernels one run enqueues */
+    int64_t groups;           /* consecutive instance runs of the plan */
+    int64_t scratch_bytes;    /* device scratch the plan holds */
+    int64_t output_bytes;     /* device output the plan holds */
+    int64_t unit_capacity;    /* work units the plan has room for */
+} gj_plan_info;
+int gj_plan_get_info(const gj_plan *plan, gj_plan_info *info);
+
+/* Releases the graph and every block of device memory of the plan. */
+int gj_plan_destroy(gj_plan *plan);
+
+/*
+ * Autotuner for join plans: for each size class present in the batch, copies up
+ * to 64 of its instances into a staging batch and times plan runs (graph
+ * launches, median of `reps`) over the candidates part_log2 in {9, 10, 11, 12}
+ * x bucket_shift in {0, 1}; then times the 10 scatter variants with the chosen
+ * table on the staging batch of the class with the most rows. Writes the best
+ * table to *out. Allocates and synchronizes freely; results never change.
+ */
+int gj_join_autotune(const gj_rel_batch *R, const gj_rel_batch *S, const gj_join_opts *opts, int32_t reps,
+                     const gj_allocator *alloc, void *stream, gj_join_tuning *out);
+
 typedef enum { GJ_SUM = 1, GJ_COUNT = 2, GJ_MIN = 3, GJ_MAX = 4 } gj_agg_op;
 typedef struct {
     int32_t col; /* value column index (ignored for GJ_COUNT) */
@@ -169,6 +255,41 @@ typedef struct {
 int gj_groupby(gj_col key, const gj_col *vals, int32_t n_vals, int64_t n_rows,
                const gj_agg *aggs, int32_t n_aggs, const gj_groupby_opts *opts,
                const gj_allocator *alloc, void *stream, gj_groupby_out *out);
+
+/* A batch of independent group-by inputs stored back to back: instance i owns
+ * rows [offsets[i], offsets[i+1]) of the key and of every value column. */
+typedef struct {
+    gj_col key;
+    const gj_col *vals;     /* n_vals GJ_I32 columns */
+    int32_t n_vals;         /* 0..8 */
+    const int64_t *offsets; /* host array of n_instances + 1 row offsets, offsets[0] = 0 */
+    int32_t n_instances;
+} gj_gb_batch;
+
+/*
+ * Plan (see gj_join_plan_create) for the partition group-by of Section 4.3 on
+ * every instance of a batch: one hashed, segmented partitioning pass (instance i
+ * with its own bits: radix_bits of opts, or clamp(ceil(log2 N_i) - 10, 0, 8)),
+ * group discovery in LDS, and a persistent aggregation over all instances'
+ * partitions (per partition: one group in registers, records in LDS when they
+ * fit, else global atomics). Output groups are dense over the batch, instance by
+ * instance, in the order of gj_groupby's partition algorithm; the output columns
+ * hold sum(N_i) groups. opts->algo must be GJ_GB_AUTO or GJ_GB_PARTITION; mat
+ * GFTR (default) or GFUR. A partition with more than 4096 distinct keys cannot
+ * be discovered in LDS: the result then reports GJ_ECAPACITY (use gj_groupby
+ * for such instances; keeping N_i <= 2^20 makes this practically impossible
+ * unless the keys are chosen to collide). Runs, capture, launch and destroy are
+ * the gj_plan_* calls.
+ */
+int gj_groupby_plan_create(const gj_gb_batch *B, const gj_agg *aggs, int32_t n_aggs,
+                           const gj_groupby_opts *opts, const gj_allocator *alloc, void *stream,
+                           gj_plan **plan);
+
+/* Synchronizes with `stream` and reports the last run of a group-by plan: out
+ * receives the plan's key and aggregate columns (owned by the plan) and n_groups
+ * the total; group_offsets (host, n_instances + 1) the first group of each
+ * instance. GJ_ECAPACITY when a partition overflowed its LDS table. */
+int gj_groupby_plan_result(gj_plan *plan, void *stream, gj_groupby_out *out, int64_t *group_offsets);
 
 /* Digit source of the partition primitive. */
 typedef enum {

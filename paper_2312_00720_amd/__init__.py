@@ -65,6 +65,22 @@ class JoinOut(ctypes.Structure):
                 ("s_payloads", ctypes.POINTER(ctypes.c_void_p)), ("n_rows", ctypes.c_int64)]
 
 
+class GbBatch(ctypes.Structure):
+    _fields_ = [("key", Col), ("vals", ctypes.POINTER(Col)), ("n_vals", ctypes.c_int32),
+                ("offsets", ctypes.POINTER(ctypes.c_int64)), ("n_instances", ctypes.c_int32)]
+
+
+class JoinTuning(ctypes.Structure):
+    _fields_ = [("part_log2", ctypes.c_int8 * 32), ("bucket_shift", ctypes.c_int8 * 32),
+                ("scatter_variant", ctypes.c_int32)]
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [("launches_per_run", ctypes.c_int64), ("groups", ctypes.c_int64),
+                ("scratch_bytes", ctypes.c_int64), ("output_bytes", ctypes.c_int64),
+                ("unit_capacity", ctypes.c_int64)]
+
+
 class Agg(ctypes.Structure):
     _fields_ = [("col", ctypes.c_int32), ("op", ctypes.c_int32)]
 
@@ -134,6 +150,31 @@ def lib() -> ctypes.CDLL:
             L.gj_mlp_adam.restype = ctypes.c_int
             L.gj_mlp_adam.argtypes = [fp, fp, fp, fp, i32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                       ctypes.c_float, vp]
+            pp = ctypes.POINTER(ctypes.c_void_p)
+            L.gj_join_plan_create.restype = ctypes.c_int
+            L.gj_join_plan_create.argtypes = [ctypes.POINTER(RelBatch), ctypes.POINTER(RelBatch),
+                                              ctypes.POINTER(JoinOpts), ctypes.POINTER(JoinTuning), i64,
+                                              ctypes.POINTER(Allocator), vp, pp]
+            for name in ("gj_plan_run", "gj_plan_launch"):
+                getattr(L, name).restype = ctypes.c_int
+                getattr(L, name).argtypes = [vp, vp]
+            L.gj_plan_capture.restype = ctypes.c_int
+            L.gj_plan_capture.argtypes = [vp]
+            L.gj_join_plan_result.restype = ctypes.c_int
+            L.gj_join_plan_result.argtypes = [vp, vp, ctypes.POINTER(JoinOut), ctypes.POINTER(ctypes.c_int64)]
+            L.gj_plan_get_info.restype = ctypes.c_int
+            L.gj_plan_get_info.argtypes = [vp, ctypes.POINTER(PlanInfo)]
+            L.gj_plan_destroy.restype = ctypes.c_int
+            L.gj_plan_destroy.argtypes = [vp]
+            L.gj_join_autotune.restype = ctypes.c_int
+            L.gj_join_autotune.argtypes = [ctypes.POINTER(RelBatch), ctypes.POINTER(RelBatch),
+                                           ctypes.POINTER(JoinOpts), i32, ctypes.POINTER(Allocator), vp,
+                                           ctypes.POINTER(JoinTuning)]
+            L.gj_groupby_plan_create.restype = ctypes.c_int
+            L.gj_groupby_plan_create.argtypes = [ctypes.POINTER(GbBatch), ctypes.POINTER(Agg), i32,
+                                                 ctypes.POINTER(GroupByOpts), ctypes.POINTER(Allocator), vp, pp]
+            L.gj_groupby_plan_result.restype = ctypes.c_int
+            L.gj_groupby_plan_result.argtypes = [vp, vp, ctypes.POINTER(GroupByOut), ctypes.POINTER(ctypes.c_int64)]
             L.gj_last_error.restype = ctypes.c_char_p
             L.gj_last_error.argtypes = []
             L.gj_version.restype = ctypes.c_char_p
@@ -263,6 +304,172 @@ def join_batch(r_key: torch.Tensor, r_pay, r_offsets, s_key: torch.Tensor, s_pay
     rr = [A.take(rpo[i], r_pay[i].dtype, t) for i in range(len(r_pay))]
     ss = [A.take(spo[i], s_pay[i].dtype, t) for i in range(len(s_pay))]
     return key, rr, ss, [int(offs[i]) for i in range(n + 1)]
+
+
+def _batch_structs(r_key, r_pay, r_offsets, s_key, s_pay, s_offsets):
+    r_pay, s_pay = list(r_pay), list(s_pay)
+    dev = r_key.device
+    _check_cols([r_key, *r_pay], r_key.numel(), dev)
+    _check_cols([s_key, *s_pay], s_key.numel(), dev)
+    n = len(r_offsets) - 1
+    if len(s_offsets) != n + 1 or n < 1:
+        raise ValueError("offsets of R and S must have the same length >= 2")
+    if int(r_offsets[-1]) != r_key.numel() or int(s_offsets[-1]) != s_key.numel():
+        raise ValueError("the last offset must equal the column length")
+    keep = dict(ro=(ctypes.c_int64 * (n + 1))(*[int(x) for x in r_offsets]),
+                so=(ctypes.c_int64 * (n + 1))(*[int(x) for x in s_offsets]),
+                rp=(Col * max(1, len(r_pay)))(*[_col(t) for t in r_pay]),
+                sp=(Col * max(1, len(s_pay)))(*[_col(t) for t in s_pay]))
+    R = RelBatch(_col(r_key), keep["rp"], len(r_pay), keep["ro"], n)
+    S = RelBatch(_col(s_key), keep["sp"], len(s_pay), keep["so"], n)
+    return R, S, keep, n
+
+
+def tuning_table(part_log2=None, bucket_shift=None, scatter_variant: int = 0) -> JoinTuning:
+    """A join-plan tuning table; part_log2 / bucket_shift map size class -> value."""
+    t = JoinTuning()
+    for c, v in (part_log2 or {}).items():
+        t.part_log2[int(c)] = int(v)
+    for c, v in (bucket_shift or {}).items():
+        t.bucket_shift[int(c)] = int(v)
+    t.scatter_variant = int(scatter_variant)
+    return t
+
+
+def tuning_dict(t: JoinTuning) -> dict:
+    return {"part_log2": {c: int(t.part_log2[c]) for c in range(32) if t.part_log2[c]},
+            "bucket_shift": {c: int(t.bucket_shift[c]) for c in range(32) if t.bucket_shift[c]},
+            "scatter_variant": int(t.scatter_variant)}
+
+
+class JoinPlan:
+    """A batch of joins planned once and replayed as one HIP graph (gj_join_plan_*).
+    The input columns are borrowed: refill them in place and launch again to join
+    new data of the same shape. Results are views of the plan's output columns."""
+
+    def __init__(self, r_key, r_pay, r_offsets, s_key, s_pay, s_offsets, *, mat: str = "gftr",
+                 lds_budget: int = 0, tuning: JoinTuning | None = None, out_capacity: int = 0):
+        L = lib()
+        self._p = None
+        self.device = r_key.device
+        self._inputs = (r_key, list(r_pay), s_key, list(s_pay))
+        R, S, self._keep, self.n = _batch_structs(r_key, r_pay, r_offsets, s_key, s_pay, s_offsets)
+        self._alloc = _TorchAllocator(self.device)
+        o = JoinOpts(MAT[mat], 0, 0, 0, 0, 0.0, lds_budget, 0)
+        p = ctypes.c_void_p()
+        rc = L.gj_join_plan_create(ctypes.byref(R), ctypes.byref(S), ctypes.byref(o),
+                                   ctypes.byref(tuning) if tuning is not None else None, int(out_capacity),
+                                   ctypes.byref(self._alloc.struct), _stream(self.device), ctypes.byref(p))
+        _raise(rc)
+        self._p = p
+
+    def run(self) -> None:
+        _raise(lib().gj_plan_run(self._p, _stream(self.device)))
+
+    def capture(self) -> None:
+        _raise(lib().gj_plan_capture(self._p))
+
+    def launch(self) -> None:
+        _raise(lib().gj_plan_launch(self._p, _stream(self.device)))
+
+    def info(self) -> dict:
+        i = PlanInfo()
+        _raise(lib().gj_plan_get_info(self._p, ctypes.byref(i)))
+        return {k: int(getattr(i, k)) for k, _ in PlanInfo._fields_}
+
+    def result(self):
+        """(key, [R payloads], [S payloads], offsets) of the last run; raises
+        GJError (GJ_ECAPACITY) with the needed rows when the plan was too small."""
+        r_key, r_pay, s_key, s_pay = self._inputs
+        ro = (ctypes.c_void_p * max(1, len(r_pay)))()
+        so = (ctypes.c_void_p * max(1, len(s_pay)))()
+        out = JoinOut(None, ro, so, 0)
+        offs = (ctypes.c_int64 * (self.n + 1))()
+        rc = lib().gj_join_plan_result(self._p, _stream(self.device), ctypes.byref(out), offs)
+        if rc != 0:
+            err = GJError(rc, lib().gj_last_error().decode())
+            err.n_rows = int(out.n_rows)
+            raise err
+        t = int(out.n_rows)
+
+        def view(ptr, dtype):
+            buf = self._alloc.live[int(ptr)]
+            return buf[: t * torch.empty(0, dtype=dtype).element_size()].view(dtype)
+
+        key = view(out.key, r_key.dtype)
+        rr = [view(ro[i], r_pay[i].dtype) for i in range(len(r_pay))]
+        ss = [view(so[i], s_pay[i].dtype) for i in range(len(s_pay))]
+        return key, rr, ss, [int(offs[i]) for i in range(self.n + 1)]
+
+    def close(self) -> None:
+        if self._p is not None:
+            lib().gj_plan_destroy(self._p)
+            self._p = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class GroupByPlan(JoinPlan):
+    """Partition group-by of a batch of instances, planned once and replayed as one
+    HIP graph (gj_groupby_plan_*). Key and value columns hold the instances back
+    to back; offsets (n+1 host ints) delimit them. Inputs are borrowed."""
+
+    def __init__(self, key, vals, offsets, aggs, *, mat: str = "gftr", radix_bits: int = 0):
+        L = lib()
+        self._p = None
+        vals = list(vals)
+        self.device = key.device
+        _check_cols([key, *vals], key.numel(), self.device)
+        self.n = len(offsets) - 1
+        if self.n < 1 or int(offsets[-1]) != key.numel():
+            raise ValueError("offsets must have >= 2 entries and end at the column length")
+        self._inputs = (key, vals)
+        self.aggs = [(int(c), op) for c, op in aggs]
+        self._keep = dict(off=(ctypes.c_int64 * (self.n + 1))(*[int(x) for x in offsets]),
+                          vals=(Col * max(1, len(vals)))(*[_col(t) for t in vals]),
+                          aggs=(Agg * max(1, len(aggs)))(*[Agg(int(c), AGG_OP[op]) for c, op in aggs]))
+        B = GbBatch(_col(key), self._keep["vals"], len(vals), self._keep["off"], self.n)
+        o = GroupByOpts(GB_ALGO["partition"], MAT[mat], radix_bits, 0, 0.0, 0)
+        self._alloc = _TorchAllocator(self.device)
+        p = ctypes.c_void_p()
+        _raise(L.gj_groupby_plan_create(ctypes.byref(B), self._keep["aggs"], len(aggs), ctypes.byref(o),
+                                        ctypes.byref(self._alloc.struct), _stream(self.device), ctypes.byref(p)))
+        self._p = p
+
+    def result(self):
+        """(keys, [aggregate columns], group offsets per instance) of the last run."""
+        key, vals = self._inputs
+        ao = (ctypes.c_void_p * max(1, len(self.aggs)))()
+        out = GroupByOut(None, ao, 0)
+        offs = (ctypes.c_int64 * (self.n + 1))()
+        _raise(lib().gj_groupby_plan_result(self._p, _stream(self.device), ctypes.byref(out), offs))
+        g = int(out.n_groups)
+
+        def view(ptr, dtype):
+            buf = self._alloc.live[int(ptr)]
+            return buf[: g * torch.empty(0, dtype=dtype).element_size()].view(dtype)
+
+        keys = view(out.key, key.dtype)
+        res = [view(ao[i], torch.int64 if op in ("sum", "count") else torch.int32)
+               for i, (c, op) in enumerate(self.aggs)]
+        return keys, res, [int(offs[i]) for i in range(self.n + 1)]
+
+
+def join_autotune(r_key, r_pay, r_offsets, s_key, s_pay, s_offsets, *, mat: str = "gftr", lds_budget: int = 0,
+                  reps: int = 3) -> JoinTuning:
+    """Autotuned plan parameters per size class for this batch (gj_join_autotune)."""
+    L = lib()
+    R, S, keep, _ = _batch_structs(r_key, r_pay, r_offsets, s_key, s_pay, s_offsets)
+    A = _TorchAllocator(r_key.device)
+    o = JoinOpts(MAT[mat], 0, 0, 0, 0, 0.0, lds_budget, 0)
+    t = JoinTuning()
+    _raise(L.gj_join_autotune(ctypes.byref(R), ctypes.byref(S), ctypes.byref(o), int(reps),
+                              ctypes.byref(A.struct), _stream(r_key.device), ctypes.byref(t)))
+    return t
 
 
 def partition(key: torch.Tensor, cols=(), *, bit_lo: int = 0, bits: int = 8, passes: int = 0,

@@ -11,10 +11,7 @@ namespace {
 
 thread_local std::string g_last_error;
 
-int fail(int code, const std::string &msg) {
-    g_last_error = msg;
-    return code;
-}
+using gj::fail;
 
 constexpr int64_t kMaxRows = 2147483647LL;
 
@@ -42,6 +39,14 @@ void check_rel(const gj_rel *r, const char *what) {
 }
 
 }  // namespace
+
+namespace gj {
+int fail(int code, const std::string &msg) {
+    g_last_error = msg;
+    return code;
+}
+void clear_error() { g_last_error.clear(); }
+}  // namespace gj
 
 extern "C" {
 

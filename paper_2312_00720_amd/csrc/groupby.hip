@@ -344,6 +344,42 @@ __global__ void k_out_init(AggSpec s, uint64_t g) {
     }
 }
 
+// The same for groups [base, base + min(g, cap)), base and g read on the device.
+__global__ void k_out_init_dev(AggSpec s, const uint64_t *__restrict__ base, const uint32_t *__restrict__ g_dev,
+                               uint64_t cap) {
+    const uint64_t b = base ? *base : 0ull, g = min((uint64_t)*g_dev, cap);
+    for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < g; k += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t i = b + k;
+        for (int j = 0; j < s.n; ++j) {
+            switch (s.op[j]) {
+                case GJ_SUM:
+                case GJ_COUNT: static_cast<long long *>(s.out[j])[i] = 0; break;
+                case GJ_MIN: static_cast<int *>(s.out[j])[i] = INT32_MAX; break;
+                default: static_cast<int *>(s.out[j])[i] = INT32_MIN; break;
+            }
+        }
+    }
+}
+
+// Batches: first output group of each instance (partitions are instance * 256 + digit).
+__global__ void k_pgb_inst_offsets(const uint32_t *__restrict__ goff, uint32_t nseg,
+                                   const uint64_t *__restrict__ base, uint64_t *__restrict__ out) {
+    const uint64_t b = base ? *base : 0ull;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i <= nseg; i += gridDim.x * blockDim.x)
+        out[i] = b + goff[(uint64_t)i << 8];
+}
+
+// Plan bookkeeping: next group base, the overflow flag and the unit count.
+__global__ void k_pgb_status(const uint64_t *__restrict__ base, const uint32_t *__restrict__ g_dev,
+                             uint64_t *__restrict__ next, const uint32_t *__restrict__ stat,
+                             const uint32_t *__restrict__ nunits, uint32_t *__restrict__ status) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        *next = (base ? *base : 0ull) + *g_dev;
+        status[0] = stat[1];
+        status[1] = *nunits;
+    }
+}
+
 template <typename K>
 __device__ __forceinline__ K empty_key() {
     if constexpr (sizeof(K) == 4) return (K)INT32_MIN;
@@ -422,6 +458,11 @@ struct PgbArgs {
     // discovery of oversized partitions by several workgroups
     const uint32_t *dubase; // exclusive prefix of discovery units per partition (np + 1)
     uint32_t *dcount;       // distinct keys found by each discovery unit
+    // persistent aggregation (plans): unit count in device memory, output offset
+    const uint32_t *nunits; // device: aggregation units
+    uint32_t cap_units;     // units beyond this are not processed
+    const uint64_t *out_base; // device: first output group of this call (nullptr = 0)
+    uint32_t lds_bytes;     // > 0: table size and records chosen per partition within this LDS
 };
 
 template <typename K>
@@ -685,13 +726,10 @@ __global__ void k_pgb_units(const uint32_t *__restrict__ poff, uint32_t np, uint
 }
 
 template <typename K, int NV>
-__global__ __launch_bounds__(kBlock) void k_pgb_aggregate(PgbArgs a) {
+__device__ __forceinline__ void pgb_unit(const PgbArgs &a, uint32_t u, uint64_t out_base, uint32_t *s_dyn,
+                                         uint32_t *s_unit, uint32_t &s_sent_id) {
     constexpr int RB = NV <= 2 ? 8 : 16 / NV;  // rows loaded per thread before they are aggregated
-    extern __shared__ __align__(16) uint32_t s_dyn[];
-    __shared__ uint32_t s_unit[5];
-    __shared__ uint32_t s_sent_id;
     const int tid = threadIdx.x, lane = lane_id();
-    const uint32_t u = blockIdx.x;
     if (tid == 0) {
         uint32_t lo = 0, hi = a.np;  // ubase[lo] <= u < ubase[hi]
         while (hi - lo > 1) {
@@ -715,7 +753,7 @@ __global__ __launch_bounds__(kBlock) void k_pgb_aggregate(PgbArgs a) {
     const uint32_t j = s_unit[4];
     const uint32_t p0 = a.poff[p];
     const uint32_t g = a.goff[p + 1] - a.goff[p];  // group counts were scanned in place into offsets
-    const uint64_t gb = a.goff[p];
+    const uint64_t gb = out_base + a.goff[p];
     if (g == 0) return;
     const K *__restrict__ keys = static_cast<const K *>(a.keys);
     const K *__restrict__ tk = static_cast<const K *>(a.tmp_keys);
@@ -750,7 +788,15 @@ __global__ __launch_bounds__(kBlock) void k_pgb_aggregate(PgbArgs a) {
         }
         return;
     }
-    const int log2cap = a.log2cap;
+    int log2cap = a.log2cap;
+    bool lds_records = a.lds_records != 0;
+    if (a.lds_bytes) {
+        // the table holds 2g slots; records stay in LDS when they fit beside it
+        log2cap = 6;
+        while ((1u << log2cap) < 2u * g) ++log2cap;
+        const uint32_t tab = (1u << log2cap) * (uint32_t)(sizeof(K) + 2) + 8;
+        lds_records = tab + g * (uint32_t)a.spec.words * 4u <= a.lds_bytes;
+    }
     const uint32_t cap = 1u << log2cap;
     K *tab = reinterpret_cast<K *>(s_dyn);
     uint16_t *id_of = reinterpret_cast<uint16_t *>(tab + cap);  // slot -> group id
@@ -758,7 +804,7 @@ __global__ __launch_bounds__(kBlock) void k_pgb_aggregate(PgbArgs a) {
     recs = reinterpret_cast<uint32_t *>((reinterpret_cast<uintptr_t>(recs) + 7) & ~uintptr_t(7));
     const K e = empty_key<K>();
     for (uint32_t i = tid; i < cap; i += kBlock) tab[i] = e;
-    if (a.lds_records)
+    if (lds_records)
         for (uint32_t i = tid; i < g; i += kBlock) rec_init(recs + (uint64_t)i * s.words, s);
     __syncthreads();
     for (uint32_t i = tid; i < g; i += kBlock) {
@@ -788,7 +834,7 @@ __global__ __launch_bounds__(kBlock) void k_pgb_aggregate(PgbArgs a) {
             const bool valid = base + r * kBlock + tid < r1;
             uint32_t id = 0;
             if (valid) id = (kk[r] == e) ? s_sent_id : id_of[lds_find<K>(tab, log2cap, kk[r])];
-            if (a.lds_records) {
+            if (lds_records) {
                 if (few) wave_aggregate<NV>(recs, s, valid, id, rr[r]);
                 else if (valid) rec_add_row<NV>(recs + (uint64_t)id * s.words, s, rr[r]);
             } else if (valid) {
@@ -796,9 +842,23 @@ __global__ __launch_bounds__(kBlock) void k_pgb_aggregate(PgbArgs a) {
             }
         }
     }
-    if (a.lds_records) {
+    if (lds_records) {
         __syncthreads();
         for (uint32_t i = tid; i < g; i += kBlock) rec_flush(recs + (uint64_t)i * s.words, s, gb + i, multi);
+    }
+}
+
+template <typename K, int NV>
+__global__ __launch_bounds__(kBlock) void k_pgb_aggregate(PgbArgs a) {
+    extern __shared__ __align__(16) uint32_t s_dyn[];
+    __shared__ uint32_t s_unit[5];
+    __shared__ uint32_t s_sent_id;
+    const uint32_t n_units = min(*a.nunits, a.cap_units);
+    const uint64_t out_base = a.out_base ? *a.out_base : 0ull;
+    // persistent: a workgroup takes units blockIdx.x, blockIdx.x + gridDim.x, ...
+    for (uint32_t u = blockIdx.x; u < n_units; u += gridDim.x) {
+        pgb_unit<K, NV>(a, u, out_base, s_dyn, s_unit, s_sent_id);
+        __syncthreads();  // the unit's LDS state is rebuilt by the next one
     }
 }
 
@@ -1194,11 +1254,11 @@ int64_t groupby_partition(Ctx &ctx, int key_bytes, const void *key, const int32_
     a.dcount = ctx.scratch_n<uint32_t>(max_du);
     if (key_bytes == 4) {
         GJ_LAUNCH("k_pgb_discover", 8.0 * n, k_pgb_discover<int32_t>, dim3(np), dim3(kBlock), 0, st, a);
-        GJ_LAUNCH("k_pgb_discover_unit", 4.0 * n, k_pgb_discover_unit<int32_t>, dim3(max_du), dim3(kBlock), 0, st, a);
+        GJ_LAUNCH("k_pgb_discover_unit", 0.0, k_pgb_discover_unit<int32_t>, dim3(max_du), dim3(kBlock), 0, st, a);
         GJ_LAUNCH("k_pgb_merge", 8.0 * np, k_pgb_merge<int32_t>, dim3(np), dim3(kBlock), 0, st, a);
     } else {
         GJ_LAUNCH("k_pgb_discover", 16.0 * n, k_pgb_discover<int64_t>, dim3(np), dim3(kBlock), 0, st, a);
-        GJ_LAUNCH("k_pgb_discover_unit", 8.0 * n, k_pgb_discover_unit<int64_t>, dim3(max_du), dim3(kBlock), 0, st, a);
+        GJ_LAUNCH("k_pgb_discover_unit", 0.0, k_pgb_discover_unit<int64_t>, dim3(max_du), dim3(kBlock), 0, st, a);
         GJ_LAUNCH("k_pgb_merge", 16.0 * np, k_pgb_merge<int64_t>, dim3(np), dim3(kBlock), 0, st, a);
     }
     scan_exclusive_u32(ctx, gcnt, gcnt, np, gcnt + np);
@@ -1230,6 +1290,10 @@ int64_t groupby_partition(Ctx &ctx, int key_bytes, const void *key, const int32_
     a.goff = gcnt;
     a.ubase = ucnt;
     a.out_key = *out_key;
+    a.nunits = ucnt + np;
+    a.cap_units = units;
+    a.out_base = nullptr;
+    a.lds_bytes = 0;
     // LDS: table of 2*maxg slots (key + 16-bit id), then maxg records
     int log2cap = 6;
     while ((1u << log2cap) < 2u * maxg) ++log2cap;
@@ -1257,6 +1321,105 @@ int64_t groupby_partition(Ctx &ctx, int key_bytes, const void *key, const int32_
     }
 #undef GJ_PGB
     return g;
+}
+
+uint32_t pgb_plan_lds_bytes(int key_bytes) {
+    // room for the largest per-partition table (2 x kDiscoverCap slots of key and
+    // 16-bit id), and at least 64 KiB so that records of ~1000 groups fit beside
+    // a small table
+    return std::max<uint32_t>(2u * kDiscoverCap * (uint32_t)(key_bytes + 2) + 8, 65536u);
+}
+
+void groupby_partition_segments(Ctx &ctx, int key_bytes, const void *key, const int32_t *const *vals, int n_vals,
+                                uint32_t n, const gj_agg *aggs, int n_aggs, bool gfur, const uint32_t *seg_off,
+                                uint32_t nseg, const uint8_t *seg_bits, const PgbPlanned &pl) {
+    hipStream_t st = ctx.stream;
+    void *pkey = ctx.scratch((size_t)n * key_bytes);
+    PartCols pc;
+    ValSrc vs{};
+    vs.n = n_vals;
+    if (!gfur) {
+        pc.n = n_vals;
+        for (int c = 0; c < n_vals; ++c) {
+            pc.in[c] = vals[c];
+            pc.width[c] = 4;
+            pc.out[c] = ctx.scratch((size_t)n * 4);
+            vs.col[c] = static_cast<const int32_t *>(pc.out[c]);
+        }
+        vs.rowid = nullptr;
+    } else {
+        pc.gen_rowid = true;
+        pc.rowid_out = ctx.scratch((size_t)n * 4);
+        for (int c = 0; c < n_vals; ++c) vs.col[c] = vals[c];
+        vs.rowid = static_cast<const int32_t *>(pc.rowid_out);
+    }
+    const uint32_t np = nseg << 8;
+    uint32_t *poff = ctx.scratch_n<uint32_t>(np + 1);
+    partition_run_segments(ctx, key_bytes, key, pkey, pc, n, seg_off, nseg, seg_bits, poff, kDigitHash);
+
+    PgbArgs a{};
+    a.keys = pkey;
+    a.poff = poff;
+    a.np = np;
+    a.tmp_keys = ctx.scratch((size_t)n * key_bytes);
+    uint32_t *gcnt = ctx.scratch_n<uint32_t>(np + 1);
+    uint32_t *stat = ctx.scratch_n<uint32_t>(4);
+    fill_u32(st, stat, 0u, 4);
+    a.gcnt = gcnt;
+    a.stat = stat;
+    uint32_t *du = ctx.scratch_n<uint32_t>(np + 1);
+    GJ_LAUNCH("k_pgb_dunits", 12.0 * np, k_pgb_dunits, dim3(std::min<uint32_t>((np + 255) / 256, 1024)), dim3(256),
+              0, st, poff, np, du);
+    scan_exclusive_u32(ctx, du, du, np, du + np);
+    a.dubase = du;
+    const uint32_t max_du = 2 * ceil_div_u32(n, kDiscoverUnit) + 1;
+    a.dcount = ctx.scratch_n<uint32_t>(max_du);
+    if (key_bytes == 4) {
+        GJ_LAUNCH("k_pgb_discover", 8.0 * n, k_pgb_discover<int32_t>, dim3(np), dim3(kBlock), 0, st, a);
+        GJ_LAUNCH("k_pgb_discover_unit", 0.0, k_pgb_discover_unit<int32_t>, dim3(max_du), dim3(kBlock), 0, st, a);
+        GJ_LAUNCH("k_pgb_merge", 8.0 * np, k_pgb_merge<int32_t>, dim3(np), dim3(kBlock), 0, st, a);
+    } else {
+        GJ_LAUNCH("k_pgb_discover", 16.0 * n, k_pgb_discover<int64_t>, dim3(np), dim3(kBlock), 0, st, a);
+        GJ_LAUNCH("k_pgb_discover_unit", 0.0, k_pgb_discover_unit<int64_t>, dim3(max_du), dim3(kBlock), 0, st, a);
+        GJ_LAUNCH("k_pgb_merge", 16.0 * np, k_pgb_merge<int64_t>, dim3(np), dim3(kBlock), 0, st, a);
+    }
+    scan_exclusive_u32(ctx, gcnt, gcnt, np, gcnt + np);
+    uint32_t *ucnt = ctx.scratch_n<uint32_t>(np + 1);
+    GJ_LAUNCH("k_pgb_units", 12.0 * np, k_pgb_units, dim3(std::min<uint32_t>((np + 255) / 256, 1024)), dim3(256),
+              0, st, poff, np, ucnt, stat + 2);
+    scan_exclusive_u32(ctx, ucnt, ucnt, np, ucnt + np);
+
+    a.spec = make_spec(aggs, n_aggs, pl.out_aggs);
+    a.vals = vs;
+    a.goff = gcnt;
+    a.ubase = ucnt;
+    a.out_key = pl.out_key;
+    a.nunits = ucnt + np;
+    a.cap_units = pl.cap_units;
+    a.out_base = pl.out_base;
+    a.lds_bytes = pl.lds_bytes;
+    a.log2cap = 6;
+    a.lds_records = 0;
+    const uint32_t init_blocks = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((n + 255) / 256, 4096));
+    GJ_LAUNCH("k_out_init", 4.0 * a.spec.words * n, k_out_init_dev, dim3(init_blocks), dim3(256), 0, st, a.spec,
+              pl.out_base, (const uint32_t *)(gcnt + np), pl.out_cap);
+    GJ_LAUNCH("k_pgb_inst_offsets", 12.0 * (nseg + 1), k_pgb_inst_offsets,
+              dim3(std::min<uint32_t>(ceil_div_u32(nseg + 1, 256), 1024)), dim3(256), 0, st, (const uint32_t *)gcnt,
+              nseg, pl.out_base, pl.inst_goff);
+    GJ_LAUNCH("k_pgb_status", 16.0, k_pgb_status, dim3(1), dim3(64), 0, st, pl.out_base,
+              (const uint32_t *)(gcnt + np), pl.next_base, (const uint32_t *)stat, (const uint32_t *)(ucnt + np),
+              pl.status);
+    const uint32_t grid = std::max<uint32_t>(1, std::min<uint32_t>(pl.cap_units, 4096));
+    const double bytes = (double)n * (key_bytes + 4.0 * n_vals + (gfur ? 4.0 : 0.0));
+    const uint32_t lds = pl.lds_bytes;
+#define GJ_PGB(K, NV) GJ_LAUNCH("k_pgb_aggregate", bytes, (k_pgb_aggregate<K, NV>), dim3(grid), dim3(kBlock), lds, st, a)
+    const int nvt = nv_tier(n_vals);
+    if (key_bytes == 4) {
+        if (nvt == 1) GJ_PGB(int32_t, 1); else if (nvt == 2) GJ_PGB(int32_t, 2); else if (nvt == 4) GJ_PGB(int32_t, 4); else GJ_PGB(int32_t, 8);
+    } else {
+        if (nvt == 1) GJ_PGB(int64_t, 1); else if (nvt == 2) GJ_PGB(int64_t, 2); else if (nvt == 4) GJ_PGB(int64_t, 4); else GJ_PGB(int64_t, 8);
+    }
+#undef GJ_PGB
 }
 
 int64_t groupby_hash(Ctx &ctx, int key_bytes, const void *key, const int32_t *const *vals, int n_vals, uint32_t n,

@@ -37,6 +37,10 @@ inline void require(bool ok, const std::string &msg, int code = GJ_EINVAL) {
     if (!ok) throw Error(code, msg);
 }
 
+// The thread's message for gj_last_error() (capi.hip): fail() sets it and returns code.
+int fail(int code, const std::string &msg);
+void clear_error();
+
 // ---- prof.hip: optional per-launch event timing ------------------------------------
 // When profiling is on for the calling thread, every launch made through GJ_LAUNCH
 // is bracketed by two HIP events on its stream and tagged with its algorithmic
@@ -44,19 +48,43 @@ inline void require(bool ok, const std::string &msg, int code = GJ_EINVAL) {
 void prof_before(const char *name, double alg_bytes, hipStream_t s);
 void prof_after(hipStream_t s);
 
+// While a plan measures the memory of its run (plan.hip), launches are counted
+// and skipped: no kernel runs and no placeholder address is touched.
+extern thread_local bool g_dry_run;
+extern thread_local int64_t g_dry_launches;
+
 #define GJ_LAUNCH(name, alg_bytes, kernel, grid, block, shm, stream, ...)              \
     do {                                                                                \
+        if (::gj::g_dry_run) {                                                          \
+            ++::gj::g_dry_launches;                                                     \
+            break;                                                                      \
+        }                                                                               \
         ::gj::prof_before(name, (double)(alg_bytes), stream);                           \
         hipLaunchKernelGGL(kernel, grid, block, shm, stream, __VA_ARGS__);              \
         GJ_LAUNCHED(name);                                                              \
         ::gj::prof_after(stream);                                                       \
     } while (0)
 
+// Pauses the per-launch profiler for a scope (HIP graph capture records no events).
+struct ProfPause {
+    ProfPause();
+    ~ProfPause();
+    bool was;
+};
+
+// Bump allocation over one preallocated device block (a plan's scratch). With
+// base == nullptr it only measures: addresses are placeholders, never used.
+struct Arena {
+    char *base = nullptr;
+    size_t size = 0, used = 0, peak = 0;
+};
+
 // Memory for one C-ABI call. Scratch is released at the end of the call;
-// outputs are released only if the call fails.
+// outputs are released only if the call fails. Over an arena, nothing is released.
 class Ctx {
   public:
     Ctx(const gj_allocator *a, hipStream_t s) : alloc_(a), stream(s) {}
+    Ctx(Arena *ar, hipStream_t s) : alloc_(nullptr), stream(s), arena_(ar) {}
     ~Ctx() {
         for (void *p : scratch_) release(p);
         if (!committed_)
@@ -82,6 +110,14 @@ class Ctx {
     void *get(size_t bytes) {
         if (bytes == 0) bytes = 256;
         bytes = (bytes + 255) & ~size_t(255);
+        if (arena_) {
+            const size_t off = arena_->used;
+            arena_->used += bytes;
+            if (arena_->used > arena_->peak) arena_->peak = arena_->used;
+            if (!arena_->base) return reinterpret_cast<char *>(uintptr_t(1) << 44) + off;
+            if (arena_->used > arena_->size) throw Error(GJ_ENOMEM, "plan scratch exhausted");
+            return arena_->base + off;
+        }
         void *p = nullptr;
         if (alloc_ && alloc_->alloc) {
             p = alloc_->alloc(bytes, alloc_->ctx);
@@ -92,7 +128,7 @@ class Ctx {
         return p;
     }
     void release(void *p) {
-        if (!p) return;
+        if (!p || arena_) return;
         if (alloc_ && alloc_->alloc) {
             if (alloc_->free) alloc_->free(p, alloc_->ctx);
         } else {
@@ -101,6 +137,7 @@ class Ctx {
     }
     std::vector<void *> scratch_, outputs_;
     bool committed_ = false;
+    Arena *arena_ = nullptr;
 };
 
 template <typename T>
@@ -116,6 +153,10 @@ inline T read_back(const T *dev, hipStream_t s) {
 // grand total is written there (device). Scratch comes from ctx.
 void scan_exclusive_u32(Ctx &ctx, const uint32_t *in, uint32_t *out, uint64_t n, uint32_t *total);
 void scan_exclusive_u64(Ctx &ctx, const uint64_t *in, uint64_t *out, uint64_t n, uint64_t *total);
+// The same over min(nmax, *n_dev * mult) elements, the count read on the device
+// (launch sizes depend on nmax only).
+void scan_exclusive_u64_dev(Ctx &ctx, const uint64_t *in, uint64_t *out, uint64_t nmax, const uint32_t *n_dev,
+                            uint32_t mult, uint64_t *total);
 void fill_u32(hipStream_t s, uint32_t *p, uint32_t v, uint64_t n);
 void fill_u64(hipStream_t s, uint64_t *p, uint64_t v, uint64_t n);
 
@@ -136,15 +177,21 @@ void partition_run(Ctx &ctx, int key_bytes, const void *key_in, void *key_out, c
                    uint32_t n, int bit_lo, int bits, int passes, int mode, uint32_t *poff);
 
 // One stable pass over nseg segments (device offsets seg_off[0..nseg]), the digit of
-// segment s being the low seg_bits[s] (<= 8) bits of the key: partition (s, d) gets
-// index s * 256 + d in poff (nseg * 256 + 1 entries). Used for batches of instances.
+// segment s being the low seg_bits[s] (<= 8) bits of the digit source `mode` (the key
+// bits, or its hash): partition (s, d) gets index s * 256 + d in poff (nseg * 256 + 1
+// entries). Used for batches of instances.
 void partition_run_segments(Ctx &ctx, int key_bytes, const void *key_in, void *key_out, const PartCols &cols,
                             uint32_t n, const uint32_t *seg_off, uint32_t nseg, const uint8_t *seg_bits,
-                            uint32_t *poff);
+                            uint32_t *poff, int mode = kDigitBits);
 
 // Stable LSD radix sort of n rows by the signed key (8 bits per pass; bytes that are
 // equal in every key are skipped). Moves the columns of `cols` along.
 void sort_run(Ctx &ctx, int key_bytes, const void *key_in, void *key_out, const PartCols &cols, uint32_t n);
+
+// Scatter tile shape for the calling thread: 0 = default (or GJ_SCATTER_SHAPE),
+// 1..kScatterVariants = a compiled (block, rows per thread, column group) shape.
+constexpr int kScatterVariants = 10;
+void set_scatter_variant(int v);
 
 // ---- groupby.hip ----------------------------------------------------------------------
 // Each returns the number of groups and allocates the key and aggregate outputs
@@ -158,6 +205,26 @@ int64_t groupby_hash(Ctx &ctx, int key_bytes, const void *key, const int32_t *co
 int64_t groupby_sort(Ctx &ctx, int key_bytes, const void *key, const int32_t *const *vals, int n_vals, uint32_t n,
                      const gj_agg *aggs, int n_aggs, bool gfur, void **out_key, void **out_aggs);
 
+// Partition group-by of a batch of instances (segments seg_off[0..nseg] of the
+// columns) without any host read: one hashed segmented partition pass (instance i
+// with seg_bits[i] bits), discovery, a persistent aggregation over the device unit
+// count, outputs at group rows *pl.out_base + (dense position over the batch).
+struct PgbPlanned {
+    uint32_t cap_units;          // aggregation units room (an exact bound)
+    const uint64_t *out_base;    // device: first output group of this call
+    uint64_t *next_base;         // device: receives out_base + groups
+    uint32_t *status;            // device: [0] LDS table overflow flag, [1] units
+    void *out_key;
+    void *out_aggs[16];
+    uint64_t out_cap;            // rows of the output columns past out_base
+    uint32_t lds_bytes;          // dynamic LDS of the aggregation kernel
+    uint64_t *inst_goff;         // device: nseg + 1 first output groups per instance
+};
+void groupby_partition_segments(Ctx &ctx, int key_bytes, const void *key, const int32_t *const *vals, int n_vals,
+                                uint32_t n, const gj_agg *aggs, int n_aggs, bool gfur, const uint32_t *seg_off,
+                                uint32_t nseg, const uint8_t *seg_bits, const PgbPlanned &pl);
+uint32_t pgb_plan_lds_bytes(int key_bytes);
+
 // ---- select.hip -----------------------------------------------------------------------
 // Class 0..4 for the features (see gj.h); the network when loaded, else the cost model.
 int select_algorithm(const float *features, int op_kind, float *probs_out);
@@ -165,6 +232,9 @@ void features_join(float *f, double nr, double ns, int key_bytes, int cr, int cs
 void features_groupby(float *f, double n, int key_bytes, int nv);
 
 // ---- join.hip -------------------------------------------------------------------------
+constexpr uint32_t kJoinMaxBuild = 4096;  // R rows per LDS build block
+constexpr uint32_t kJoinSPiece = 8192;    // S rows per work unit
+
 struct JoinSide {
     const void *key;          // partitioned keys
     const void *pay[8];       // GFTR: partitioned payload columns; GFUR: original columns
@@ -185,8 +255,26 @@ struct JoinOut {
 // Batches (seg_bits != nullptr): partitions are (instance, digit) with index
 // instance * 256 + digit, instance i using seg_bits[i] partition bits; inst_off
 // (device, n_inst + 1) receives each instance's first output row.
+//
+// Planned runs (pl != nullptr) never read device memory from the host: the count
+// and write passes are launched for pl->cap_units units and loop over the device
+// count; output goes to the preallocated pl->out columns at rows *pl->out_base +
+// (scanned position), stores at or past pl->out_cap are dropped; the output row
+// count is written to pl->total, and *pl->out_base + total to pl->next_base when
+// that is set. Returns 0 in that mode.
+struct JoinPlanned {
+    uint32_t cap_units;
+    uint64_t out_cap;
+    const uint64_t *out_base;
+    uint64_t *total;
+    uint64_t *next_base;
+    JoinOut out;
+    const uint8_t *seg_bshift;  // per instance extra LDS bucket bits (0 or 1)
+    uint64_t expect_rows;       // for the profiler's byte count only
+    uint32_t *units_out;        // device: receives the unit count
+};
 int64_t join_partitioned(Ctx &ctx, int key_bytes, const JoinSide &R, const JoinSide &S, int bits,
                          int r_block, bool gfur, JoinOut *out, const uint8_t *seg_bits = nullptr,
-                         uint32_t n_inst = 0, uint64_t *inst_off = nullptr);
+                         uint32_t n_inst = 0, uint64_t *inst_off = nullptr, const JoinPlanned *pl = nullptr);
 
 }  // namespace gj

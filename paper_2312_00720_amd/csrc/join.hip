@@ -23,9 +23,10 @@
 namespace gj {
 namespace {
 
-constexpr uint32_t kMaxBuild = 4096;  // R rows per build block (LDS capacity)
-constexpr uint32_t kSPiece = 8192;    // S rows per work unit
+constexpr uint32_t kMaxBuild = kJoinMaxBuild;  // R rows per build block (LDS capacity)
+constexpr uint32_t kSPiece = kJoinSPiece;      // S rows per work unit
 constexpr uint32_t kMaxChainSort = 32;
+constexpr uint32_t kPersistentGrid = 4096;  // workgroups of a plan's count and write passes
 
 struct JoinArgs {
     const void *rkey;
@@ -50,6 +51,11 @@ struct JoinArgs {
     const int32_t *rrow;  // GFUR: partitioned row ids of R
     const int32_t *srow;  // GFUR: partitioned row ids of S
     const uint8_t *seg_bits;  // batches: partition bits of instance p >> 8 (skip_bits unused)
+    const uint8_t *seg_bshift;  // batches: extra LDS bucket bits of instance p >> 8 (else bshift)
+    int bshift;                 // LDS buckets = 2^(ceil(log2 rows) + bshift), at most kMaxBuild
+    const uint32_t *nunits;     // device: work units (the kernels loop over them)
+    uint32_t cap_units;         // units beyond this are not processed (a plan's capacity)
+    const uint64_t *out_base;   // device: first output row of this call (nullptr = 0)
 };
 
 __global__ void k_unit_count(const uint32_t *__restrict__ rpo, const uint32_t *__restrict__ spo,
@@ -95,18 +101,29 @@ __device__ __forceinline__ void gather_cols(int ncols, const void *const *src, c
     }
 }
 
-template <typename K, bool WRITE>
-__global__ __launch_bounds__(kBlock) void k_join(JoinArgs a) {
-    constexpr int PB = 16;
-    __shared__ K s_rkey[kMaxBuild];
-    __shared__ uint32_t s_b[kMaxBuild + 1];   // bucket boundaries
-    __shared__ uint16_t s_entry[kMaxBuild];  // R block rows, grouped by bucket
-    __shared__ uint32_t s_tmp[kWaves];
-    __shared__ uint32_t s_unit[6];
-    __shared__ int s_long;
+template <typename K>
+struct JoinShared {
+    K rkey[kMaxBuild];
+    uint32_t b[kMaxBuild + 1];   // bucket boundaries
+    uint16_t entry[kMaxBuild];  // R block rows, grouped by bucket
+    uint32_t tmp[kWaves];
+    uint32_t unit[6];
+    int is_long;
+};
 
+// Build on the R block of unit u and probe it with the unit's S piece: count
+// (WRITE = false) or write (WRITE = true) the matches.
+template <typename K, bool WRITE>
+__device__ __forceinline__ void join_unit(const JoinArgs &a, uint32_t u, uint64_t out_base, JoinShared<K> &sh) {
+    constexpr int PB = 16;
+    K *s_rkey = sh.rkey;
+    uint32_t *s_b = sh.b;
+    uint16_t *s_entry = sh.entry;
+    uint32_t *s_tmp = sh.tmp;
+    uint32_t *s_unit = sh.unit;
+    int &s_long = sh.is_long;
+    static_assert(kMaxBuild == 4096, "bucket bits are capped at 12");
     const int tid = threadIdx.x, w = tid / kWave, lane = lane_id();
-    const uint32_t u = blockIdx.x;
     if (tid == 0) {
         uint32_t lo = 0, hi = a.np;  // ubase[lo] <= u < ubase[hi] (ubase[np] = units)
         while (hi - lo > 1) {
@@ -124,6 +141,7 @@ __global__ __launch_bounds__(kBlock) void k_join(JoinArgs a) {
         s_unit[2] = a.spo[p] + sb * kSPiece;
         s_unit[3] = min(kSPiece, ns - sb * kSPiece);
         s_unit[4] = a.seg_bits ? a.seg_bits[p >> 8] : (uint32_t)a.skip_bits;
+        s_unit[5] = a.seg_bshift ? a.seg_bshift[p >> 8] : (uint32_t)a.bshift;
         s_long = 0;
     }
     __syncthreads();
@@ -131,6 +149,7 @@ __global__ __launch_bounds__(kBlock) void k_join(JoinArgs a) {
     const int skip_bits = (int)s_unit[4];
     int log2nb = 0;
     while ((1u << log2nb) < rn) ++log2nb;
+    log2nb = min(log2nb + (int)s_unit[5], 12);
     const uint32_t nb = 1u << log2nb;
 
     // ---- build: bucket counts, scan, placement, per-bucket order by row ----
@@ -236,7 +255,7 @@ __global__ __launch_bounds__(kBlock) void k_join(JoinArgs a) {
         const uint64_t tot = wave_sum<uint64_t>((uint64_t)cnt);
         if (lane == 0) a.wcnt[(uint64_t)u * kWaves + w] = tot;
     } else {
-        uint64_t outpos = a.woff[(uint64_t)u * kWaves + w];
+        uint64_t outpos = out_base + a.woff[(uint64_t)u * kWaves + w];
         K *__restrict__ tkey = static_cast<K *>(a.tkey);
         for (uint32_t base = ws; base < we; base += PB * kWave) {
             K key[PB];
@@ -310,18 +329,55 @@ __global__ __launch_bounds__(kBlock) void k_join(JoinArgs a) {
     }
 }
 
+// One work unit per workgroup (eager calls: the grid is the unit count).
+template <typename K, bool WRITE>
+__global__ __launch_bounds__(kBlock) void k_join(JoinArgs a) {
+    __shared__ JoinShared<K> sh;
+    if (blockIdx.x < min(*a.nunits, a.cap_units)) join_unit<K, WRITE>(a, blockIdx.x, 0ull, sh);
+}
+
+// Persistent workgroups over the unit count held in device memory (plans).
+template <typename K, bool WRITE>
+__global__ __launch_bounds__(kBlock, 3) void k_join_persist(JoinArgs a) {
+    __shared__ JoinShared<K> sh;
+    const uint32_t n_units = min(*a.nunits, a.cap_units);
+    const uint64_t out_base = a.out_base ? *a.out_base : 0ull;
+    for (uint32_t u = blockIdx.x; u < n_units; u += gridDim.x) {
+        join_unit<K, WRITE>(a, u, out_base, sh);
+        __syncthreads();  // the unit's LDS state is rebuilt by the next one
+    }
+}
+
 // Output offset of each instance of a batch: the write offset of its first unit.
+// Units past the processed count (a plan's capacity) contribute nothing.
 __global__ void k_instance_offsets(const uint32_t *__restrict__ ubase, const uint64_t *__restrict__ woff,
-                                   uint32_t n_inst, uint64_t total, uint64_t *__restrict__ out) {
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i <= n_inst; i += gridDim.x * blockDim.x)
-        out[i] = (i == n_inst) ? total : woff[(uint64_t)ubase[i << 8] * kWaves];
+                                   uint32_t n_inst, const uint32_t *__restrict__ nunits, uint32_t cap_units,
+                                   const uint64_t *__restrict__ total, const uint64_t *__restrict__ base,
+                                   uint64_t *__restrict__ out) {
+    const uint32_t nu = min(*nunits, cap_units);
+    const uint64_t b = base ? *base : 0ull;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i <= n_inst; i += gridDim.x * blockDim.x) {
+        const uint32_t u = (i == n_inst) ? nu : min(ubase[i << 8], nu);
+        out[i] = b + (u == nu ? *total : woff[(uint64_t)u * kWaves]);
+    }
+}
+
+// next = base + total (the first output row of a plan's next group), and the
+// group's unit count for the plan's capacity check.
+__global__ void k_advance_base(const uint64_t *__restrict__ base, const uint64_t *__restrict__ total,
+                               uint64_t *__restrict__ next, const uint32_t *__restrict__ nunits,
+                               uint32_t *__restrict__ units_out) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        if (next) *next = (base ? *base : 0ull) + *total;
+        if (units_out) *units_out = *nunits;
+    }
 }
 
 }  // namespace
 
 int64_t join_partitioned(Ctx &ctx, int key_bytes, const JoinSide &R, const JoinSide &S, int bits,
                          int r_block, bool gfur, JoinOut *out, const uint8_t *seg_bits, uint32_t n_inst,
-                         uint64_t *inst_off) {
+                         uint64_t *inst_off, const JoinPlanned *pl) {
     hipStream_t s = ctx.stream;
     require(r_block >= 64 && r_block <= (int)kMaxBuild, "R build block must be 64..4096 rows");
     const uint32_t np = seg_bits ? (n_inst << 8) : (1u << bits);
@@ -329,10 +385,19 @@ int64_t join_partitioned(Ctx &ctx, int key_bytes, const JoinSide &R, const JoinS
     GJ_LAUNCH("k_unit_count", 20.0 * np, k_unit_count, dim3(std::min<uint32_t>((np + 255) / 256, 1024)),
               dim3(256), 0, s, R.poff, S.poff, np, (uint32_t)r_block, ucnt);
     scan_exclusive_u32(ctx, ucnt, ucnt, np, ucnt + np);
-    const uint32_t nunits = read_back(ucnt + np, s);
-    if (nunits == 0) {
-        if (inst_off) fill_u64(s, inst_off, 0ull, (uint64_t)n_inst + 1);
-        return 0;
+    // Eager calls read the unit count and size every launch exactly; a plan sizes
+    // for its capacity and the kernels read the count from device memory.
+    uint32_t cap_units, grid;
+    if (pl) {
+        cap_units = pl->cap_units;
+        grid = std::max<uint32_t>(1, std::min<uint32_t>(cap_units, kPersistentGrid));
+    } else {
+        cap_units = read_back(ucnt + np, s);
+        grid = cap_units;
+        if (cap_units == 0) {
+            if (inst_off) fill_u64(s, inst_off, 0ull, (uint64_t)n_inst + 1);
+            return 0;
+        }
     }
 
     JoinArgs a{};
@@ -345,26 +410,47 @@ int64_t join_partitioned(Ctx &ctx, int key_bytes, const JoinSide &R, const JoinS
     a.rc = (uint32_t)r_block;
     a.skip_bits = bits;
     a.seg_bits = seg_bits;
-    const uint64_t nw = (uint64_t)nunits * kWaves;
+    a.seg_bshift = pl ? pl->seg_bshift : nullptr;
+    a.bshift = 0;
+    a.nunits = ucnt + np;
+    a.cap_units = cap_units;
+    a.out_base = pl ? pl->out_base : nullptr;
+    const uint64_t nw = (uint64_t)cap_units * kWaves;
     uint64_t *wcnt = ctx.scratch_n<uint64_t>(nw + 1);
+    uint64_t *total = pl ? pl->total : wcnt + nw;
     a.wcnt = wcnt;
     const double nrows_r = R.rows, nrows_s = S.rows;
     const double key_reads = (nrows_r + nrows_s) * key_bytes;
-    if (key_bytes == 4)
-        GJ_LAUNCH("k_join_count", key_reads, (k_join<int32_t, false>), dim3(nunits), dim3(kBlock), 0, s, a);
-    else
-        GJ_LAUNCH("k_join_count", key_reads, (k_join<int64_t, false>), dim3(nunits), dim3(kBlock), 0, s, a);
-    scan_exclusive_u64(ctx, wcnt, wcnt, nw, wcnt + nw);
-    const uint64_t T = read_back(wcnt + nw, s);
+    if (key_bytes == 4) {
+        if (pl) GJ_LAUNCH("k_join_count", key_reads, (k_join_persist<int32_t, false>), dim3(grid), dim3(kBlock), 0, s, a);
+        else GJ_LAUNCH("k_join_count", key_reads, (k_join<int32_t, false>), dim3(grid), dim3(kBlock), 0, s, a);
+    } else {
+        if (pl) GJ_LAUNCH("k_join_count", key_reads, (k_join_persist<int64_t, false>), dim3(grid), dim3(kBlock), 0, s, a);
+        else GJ_LAUNCH("k_join_count", key_reads, (k_join<int64_t, false>), dim3(grid), dim3(kBlock), 0, s, a);
+    }
+    if (pl) scan_exclusive_u64_dev(ctx, wcnt, wcnt, nw, ucnt + np, kWaves, total);
+    else scan_exclusive_u64(ctx, wcnt, wcnt, nw, total);
+    uint64_t T;
+    if (pl) {
+        T = pl->out_cap;  // stores are checked against the capacity; the true count stays on the device
+        *out = pl->out;
+    } else {
+        T = read_back(total, s);
+    }
     if (inst_off)
         GJ_LAUNCH("k_instance_offsets", 16.0 * n_inst, k_instance_offsets,
                   dim3(std::min<uint32_t>(ceil_div_u32(n_inst + 1, 256), 1024)), dim3(256), 0, s, ucnt, wcnt, n_inst,
-                  T, inst_off);
+                  ucnt + np, cap_units, total, a.out_base, inst_off);
+    if (pl && (pl->next_base || pl->units_out))
+        GJ_LAUNCH("k_advance_base", 16.0, k_advance_base, dim3(1), dim3(64), 0, s, a.out_base, total, pl->next_base,
+                  (const uint32_t *)(ucnt + np), pl->units_out);
     if (T == 0) return 0;
 
-    out->key = ctx.output(T * (uint64_t)key_bytes);
-    for (int j = 0; j < R.n_pay; ++j) out->r[j] = ctx.output(T * (uint64_t)R.width[j]);
-    for (int j = 0; j < S.n_pay; ++j) out->s[j] = ctx.output(T * (uint64_t)S.width[j]);
+    if (!pl) {
+        out->key = ctx.output(T * (uint64_t)key_bytes);
+        for (int j = 0; j < R.n_pay; ++j) out->r[j] = ctx.output(T * (uint64_t)R.width[j]);
+        for (int j = 0; j < S.n_pay; ++j) out->s[j] = ctx.output(T * (uint64_t)S.width[j]);
+    }
     a.woff = wcnt;
     a.t_rows = T;
     a.tkey = out->key;
@@ -384,18 +470,22 @@ int64_t join_partitioned(Ctx &ctx, int key_bytes, const JoinSide &R, const JoinS
     a.srow = gfur ? S.rowid : nullptr;
     // algorithmic bytes: keys of both sides, payload reads (GFTR: each partitioned
     // row once; GFUR: one gathered value per output row and column, plus row ids),
-    // and the output rows
+    // and the output rows (a plan counts its expected rows, given by the caller)
     double rw_sum = 0, sw_sum = 0;
     for (int j = 0; j < R.n_pay; ++j) rw_sum += R.width[j];
     for (int j = 0; j < S.n_pay; ++j) sw_sum += S.width[j];
-    double wbytes = key_reads + (double)T * (key_bytes + rw_sum + sw_sum);
-    if (gfur) wbytes += (double)T * (rw_sum + sw_sum) + 4.0 * (nrows_r + nrows_s);
+    const double t_rows = pl ? (double)pl->expect_rows : (double)T;
+    double wbytes = key_reads + t_rows * (key_bytes + rw_sum + sw_sum);
+    if (gfur) wbytes += t_rows * (rw_sum + sw_sum) + 4.0 * (nrows_r + nrows_s);
     else wbytes += nrows_r * rw_sum + nrows_s * sw_sum;
-    if (key_bytes == 4)
-        GJ_LAUNCH("k_join_write", wbytes, (k_join<int32_t, true>), dim3(nunits), dim3(kBlock), 0, s, a);
-    else
-        GJ_LAUNCH("k_join_write", wbytes, (k_join<int64_t, true>), dim3(nunits), dim3(kBlock), 0, s, a);
-    return (int64_t)T;
+    if (key_bytes == 4) {
+        if (pl) GJ_LAUNCH("k_join_write", wbytes, (k_join_persist<int32_t, true>), dim3(grid), dim3(kBlock), 0, s, a);
+        else GJ_LAUNCH("k_join_write", wbytes, (k_join<int32_t, true>), dim3(grid), dim3(kBlock), 0, s, a);
+    } else {
+        if (pl) GJ_LAUNCH("k_join_write", wbytes, (k_join_persist<int64_t, true>), dim3(grid), dim3(kBlock), 0, s, a);
+        else GJ_LAUNCH("k_join_write", wbytes, (k_join<int64_t, true>), dim3(grid), dim3(kBlock), 0, s, a);
+    }
+    return pl ? 0 : (int64_t)T;
 }
 
 }  // namespace gj

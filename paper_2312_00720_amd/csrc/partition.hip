@@ -368,7 +368,12 @@ __global__ void k_set_range(uint32_t *p, uint32_t a, uint32_t b) {
 struct Shape {
     int block, items, group;
 };
+constexpr Shape kVariants[kScatterVariants] = {{256, 8, 4},  {512, 8, 4},  {1024, 8, 4}, {512, 4, 4},
+                                               {1024, 4, 4}, {256, 16, 2}, {512, 8, 2},  {512, 16, 2},
+                                               {512, 16, 4}, {1024, 8, 2}};
+thread_local int g_variant = 0;
 Shape scatter_shape() {
+    if (g_variant >= 1 && g_variant <= kScatterVariants) return kVariants[g_variant - 1];
     static Shape sh = [] {
         Shape x{kScatterBlock, kItems, kGroup};
         if (const char *e = getenv("GJ_SCATTER_SHAPE")) {
@@ -388,7 +393,7 @@ void launch_scatter(const Shape &sh, dim3 grid, hipStream_t s, const PassArgs &a
         return;                                                                            \
     }
     GJ_SC(256, 8, 4) GJ_SC(512, 8, 4) GJ_SC(1024, 8, 4) GJ_SC(512, 4, 4) GJ_SC(1024, 4, 4)
-    GJ_SC(256, 16, 2) GJ_SC(512, 8, 2)
+    GJ_SC(256, 16, 2) GJ_SC(512, 8, 2) GJ_SC(512, 16, 2) GJ_SC(512, 16, 4) GJ_SC(1024, 8, 2)
 #undef GJ_SC
     throw Error(GJ_EINVAL, "unknown scatter shape");
 }
@@ -468,6 +473,8 @@ void run_pass(Ctx &ctx, PassArgs &a, uint32_t n) {
 }
 
 }  // namespace
+
+void set_scatter_variant(int v) { g_variant = v; }
 
 void partition_run(Ctx &ctx, int key_bytes, const void *key_in, void *key_out, const PartCols &cols,
                    uint32_t n, int bit_lo, int bits, int passes, int mode, uint32_t *poff) {
@@ -607,7 +614,7 @@ void sort_run(Ctx &ctx, int key_bytes, const void *key_in, void *key_out, const 
 
 void partition_run_segments(Ctx &ctx, int key_bytes, const void *key_in, void *key_out, const PartCols &cols,
                             uint32_t n, const uint32_t *seg_off, uint32_t nseg, const uint8_t *seg_bits,
-                            uint32_t *poff) {
+                            uint32_t *poff, int mode) {
     require(key_bytes == 4 || key_bytes == 8, "key width must be 4 or 8 bytes");
     hipStream_t s = ctx.stream;
     const int ncols = cols.n + (cols.gen_rowid ? 1 : 0);
@@ -625,7 +632,7 @@ void partition_run_segments(Ctx &ctx, int key_bytes, const void *key_in, void *k
     int map[kMaxCols];
     assign_cols(a, cols, cin, cout, true, map);
     a.bits = 8;
-    a.dig = DigitFn{kDigitBits, 0, 0xFFu};
+    a.dig = DigitFn{mode, 0, 0xFFu};
     a.seg_off = seg_off;
     a.nseg = nseg;
     a.n_rows = n;

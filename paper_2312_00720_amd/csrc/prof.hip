@@ -38,6 +38,9 @@ thread_local Prof g_prof;
 
 }  // namespace
 
+ProfPause::ProfPause() : was(g_prof.on) { g_prof.on = false; }
+ProfPause::~ProfPause() { g_prof.on = was; }
+
 void prof_before(const char *name, double alg_bytes, hipStream_t s) {
     if (!g_prof.on) return;
     Rec r{name, alg_bytes, g_prof.take(), g_prof.take()};

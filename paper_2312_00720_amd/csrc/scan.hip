@@ -11,10 +11,18 @@ namespace {
 constexpr int kItems = 16;
 constexpr uint32_t kTile = kBlock * kItems;
 
+// Element count: nmax, or min(nmax, *n_dev * mult) when the count lives in device
+// memory (launches sized for nmax; blocks past the count do nothing).
+__device__ __forceinline__ uint64_t scan_len(uint64_t nmax, const uint32_t *n_dev, uint32_t mult) {
+    return n_dev ? min(nmax, (uint64_t)(*n_dev) * mult) : nmax;
+}
+
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_scan_reduce(const T *__restrict__ in, uint64_t n,
+__global__ __launch_bounds__(kBlock) void k_scan_reduce(const T *__restrict__ in, uint64_t nmax,
+                                                        const uint32_t *n_dev, uint32_t mult,
                                                         T *__restrict__ partial) {
     __shared__ T s_tmp[kWaves];
+    const uint64_t n = scan_len(nmax, n_dev, mult);
     const uint64_t base = (uint64_t)blockIdx.x * kTile;
     T acc = 0;
 #pragma unroll
@@ -29,9 +37,11 @@ __global__ __launch_bounds__(kBlock) void k_scan_reduce(const T *__restrict__ in
 
 // One workgroup scans the block totals in place, carrying across tiles.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_scan_partials(T *__restrict__ partial, uint64_t n,
+__global__ __launch_bounds__(kBlock) void k_scan_partials(T *__restrict__ partial, uint64_t nmax,
+                                                          const uint32_t *n_dev, uint32_t mult,
                                                           T *__restrict__ total_out) {
     __shared__ T s_tmp[kWaves];
+    const uint64_t n = (scan_len(nmax * kTile, n_dev, mult) + kTile - 1) / kTile;  // block totals in use
     T carry = 0;
     for (uint64_t base = 0; base < n; base += kTile) {
         T v[kItems];
@@ -57,9 +67,12 @@ __global__ __launch_bounds__(kBlock) void k_scan_partials(T *__restrict__ partia
 }
 
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_scan_down(const T *in, T *out, uint64_t n,
+__global__ __launch_bounds__(kBlock) void k_scan_down(const T *in, T *out, uint64_t nmax,
+                                                      const uint32_t *n_dev, uint32_t mult,
                                                       const T *__restrict__ partial) {
     __shared__ T s_tmp[kWaves];
+    const uint64_t n = scan_len(nmax, n_dev, mult);
+    if ((uint64_t)blockIdx.x * kTile >= n) return;
     const uint64_t first = (uint64_t)blockIdx.x * kTile + (uint64_t)threadIdx.x * kItems;
     T v[kItems];
     T sum = 0;
@@ -86,7 +99,8 @@ __global__ void k_fill(T *p, T v, uint64_t n) {
 }
 
 template <typename T>
-void scan_exclusive(Ctx &ctx, const T *in, T *out, uint64_t n, T *total) {
+void scan_exclusive(Ctx &ctx, const T *in, T *out, uint64_t n, T *total, const uint32_t *n_dev = nullptr,
+                    uint32_t mult = 1) {
     hipStream_t s = ctx.stream;
     if (n == 0) {
         if (total) {
@@ -97,12 +111,12 @@ void scan_exclusive(Ctx &ctx, const T *in, T *out, uint64_t n, T *total) {
     const uint64_t blocks = (n + kTile - 1) / kTile;
     T *partial = ctx.scratch_n<T>(blocks);
     const double nb = (double)n * sizeof(T);
-    GJ_LAUNCH("k_scan_reduce", nb, k_scan_reduce<T>, dim3((uint32_t)blocks), dim3(kBlock), 0, s, in, n,
-              partial);
+    GJ_LAUNCH("k_scan_reduce", nb, k_scan_reduce<T>, dim3((uint32_t)blocks), dim3(kBlock), 0, s, in, n, n_dev,
+              mult, partial);
     GJ_LAUNCH("k_scan_partials", 2.0 * blocks * sizeof(T), k_scan_partials<T>, dim3(1), dim3(kBlock), 0, s,
-              partial, blocks, total);
+              partial, blocks, n_dev, mult, total);
     GJ_LAUNCH("k_scan_down", 2.0 * nb, k_scan_down<T>, dim3((uint32_t)blocks), dim3(kBlock), 0, s, in, out,
-              n, (const T *)partial);
+              n, n_dev, mult, (const T *)partial);
 }
 
 template <typename T>
@@ -120,6 +134,10 @@ void scan_exclusive_u32(Ctx &ctx, const uint32_t *in, uint32_t *out, uint64_t n,
 }
 void scan_exclusive_u64(Ctx &ctx, const uint64_t *in, uint64_t *out, uint64_t n, uint64_t *total) {
     scan_exclusive<uint64_t>(ctx, in, out, n, total);
+}
+void scan_exclusive_u64_dev(Ctx &ctx, const uint64_t *in, uint64_t *out, uint64_t nmax, const uint32_t *n_dev,
+                            uint32_t mult, uint64_t *total) {
+    scan_exclusive<uint64_t>(ctx, in, out, nmax, total, n_dev, mult);
 }
 void fill_u32(hipStream_t s, uint32_t *p, uint32_t v, uint64_t n) { fill<uint32_t>(s, p, v, n); }
 void fill_u64(hipStream_t s, uint64_t *p, uint64_t v, uint64_t n) { fill<uint64_t>(s, p, v, n); }

@@ -1,17 +1,21 @@
 """Training and evaluation of the algorithm selector on the GPU.
 
-1. Sample seeded workloads over the feature ranges (joins: log2|R| in [10, 22],
+1. Sample seeded workloads over the feature ranges (joins: log2|R| in [10, 24],
    |S|/|R| in [1, 16], 1-8 payload columns, 4- or 8-byte keys, Zipf factor in
-   [0, 1.2], match ratio in [0.05, 1]; group-bys: log2 N in [16, 24],
+   [0, 1.2], match ratio in [0.05, 1]; group-bys: log2 N in [16, 26],
    log2 g in [2, min(24, log2 N)], 1-8 value columns).
-2. Time every valid algorithm of each workload with libgj (median of `reps`).
+2. Time every valid algorithm of each workload with libgj (median of 5 runs
+   after one warm-up). Timing can be split into parts (`--part i --parts K`),
+   each saving its own file, and merged afterwards (`--merge`).
 3. Train the 12-64-64-5 network with libgj's own HIP gradient and Adam kernels;
    the label is the fastest class.
 4. Report regret on held-out workloads: t(choice) / t(best) - 1, for the network,
    the cost model, the paper's heuristics (the group-by decision tree of
    Section 5.2 and the join rule of Section 7) and fixed choices.
 
-Usage: python -m paper_2312_00720_amd.selector --train 1500 --test 500 --out DIR
+Usage: python -m paper_2312_00720_amd.selector --train 20000 --test 2000 --out DIR
+       [--part i --parts K]   time only part i of K of both sets
+       [--merge PARTS_DIR --parts K]   merge the timed parts, train and report
 """
 from __future__ import annotations
 
@@ -37,14 +41,14 @@ def sample(n: int, seed: int) -> list[dict]:
     out = []
     for i in range(n):
         if g.uniform() < 0.5:
-            lr = g.uniform(10, 22)
+            lr = g.uniform(10, 24)
             ratio = g.uniform(1, 16)
-            ls = min(lr + math.log2(ratio), 26.0)
+            ls = lr + math.log2(ratio)
             out.append(dict(kind="join", log_r=lr, log_s=ls, cr=int(g.integers(1, 9)), cs=int(g.integers(1, 9)),
                             kb=int(g.choice([4, 8])), alpha=float(g.choice([0.0, g.uniform(0, 1.2)])),
                             mr=float(g.uniform(0.05, 1.0)), seed=seed * 100000 + i))
         else:
-            ln = g.uniform(16, 24)
+            ln = g.uniform(16, 26)
             lg = g.uniform(2, min(24.0, ln))
             out.append(dict(kind="groupby", log_n=ln, log_g=lg, nv=int(g.integers(1, 9)), kb=int(g.choice([4, 8])),
                             alpha=float(g.choice([0.0, g.uniform(0, 1.2)])), seed=seed * 100000 + i))
@@ -86,11 +90,15 @@ def run(w: dict, d, cls: int):
     return gj.groupby(d["key"], d["vals"], aggs, algo=algo, mat="gftr" if algo != "hash" else "auto")
 
 
-def time_workload(w: dict, reps: int = 3) -> list[float]:
+def time_workload(w: dict, reps: int = 5) -> list[float]:
     d = _inputs(w)
     t = [math.inf] * 5
     for c in valid(w):
-        out = run(w, d, c)  # warm-up
+        try:
+            out = run(w, d, c)  # warm-up
+        except RuntimeError as e:  # a library error (e.g. out of memory): the class stays untimed
+            print(f"[selector] {CLASSES[c]} failed on {w}: {e}", flush=True)
+            continue
         del out
         samples = []
         for _ in range(reps):
@@ -106,15 +114,20 @@ def time_workload(w: dict, reps: int = 3) -> list[float]:
 
 
 def build(ws: list[dict], log_every: int = 100) -> tuple[np.ndarray, np.ndarray, np.ndarray]:
-    X = np.array([features(w) for w in ws], np.float32)
+    X = np.array([features(w) for w in ws], np.float32).reshape(len(ws), 12)
     M = np.zeros((len(ws), 5), np.float32)
     T = np.full((len(ws), 5), np.inf)
+    t0 = time.time()
     for i, w in enumerate(ws):
         M[i, valid(w)] = 1
         T[i] = time_workload(w)
         if (i + 1) % log_every == 0:
-            print(f"[selector] timed {i + 1}/{len(ws)}", flush=True)
+            print(f"[selector] timed {i + 1}/{len(ws)} ({time.time() - t0:.0f} s)", flush=True)
     return X, M, T
+
+
+def part_slice(n: int, part: int, parts: int) -> slice:
+    return slice(n * part // parts, n * (part + 1) // parts)
 
 
 def init_params(seed: int) -> np.ndarray:
@@ -186,15 +199,33 @@ def evaluate(ws, X, M, T, theta) -> dict:
 
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser()
-    ap.add_argument("--train", type=int, default=1500)
-    ap.add_argument("--test", type=int, default=500)
+    ap.add_argument("--train", type=int, default=20000)
+    ap.add_argument("--test", type=int, default=2000)
     ap.add_argument("--steps", type=int, default=3000)
     ap.add_argument("--out", default="gpurun_out/selector")
     ap.add_argument("--data", default=None, help="reuse timings from this .npz (no re-timing)")
+    ap.add_argument("--part", type=int, default=None)
+    ap.add_argument("--parts", type=int, default=1)
+    ap.add_argument("--merge", default=None, metavar="DIR", help="merge the timed parts found in DIR")
     args = ap.parse_args(argv)
     os.makedirs(args.out, exist_ok=True)
     tr, te = sample(args.train, 1), sample(args.test, 2)
-    if args.data:
+    if args.part is not None:
+        a, b = part_slice(len(tr), args.part, args.parts), part_slice(len(te), args.part, args.parts)
+        print(f"[selector] part {args.part}/{args.parts}: train {a.start}..{a.stop}, test {b.start}..{b.stop}",
+              flush=True)
+        Xtr, Mtr, Ttr = build(tr[a])
+        Xte, Mte, Tte = build(te[b])
+        np.savez(os.path.join(args.out, f"selector_part{args.part:03d}of{args.parts:03d}.npz"), Xtr=Xtr, Mtr=Mtr,
+                 Ttr=Ttr, Xte=Xte, Mte=Mte, Tte=Tte)
+        return 0
+    if args.merge:
+        z = [np.load(os.path.join(args.merge, f"selector_part{i:03d}of{args.parts:03d}.npz"))
+             for i in range(args.parts)]
+        Xtr, Mtr, Ttr, Xte, Mte, Tte = (np.concatenate([q[k] for q in z]) for k in
+                                        ("Xtr", "Mtr", "Ttr", "Xte", "Mte", "Tte"))
+        np.savez(os.path.join(args.out, "selector_data.npz"), Xtr=Xtr, Mtr=Mtr, Ttr=Ttr, Xte=Xte, Mte=Mte, Tte=Tte)
+    elif args.data:
         z = np.load(args.data)
         Xtr, Mtr, Ttr, Xte, Mte, Tte = (z[k] for k in ("Xtr", "Mtr", "Ttr", "Xte", "Mte", "Tte"))
     else:
