@@ -347,22 +347,31 @@ int gj_groupby(gj_col key, const gj_col *vals, int32_t n_vals, int64_t n_rows, c
         const uint32_t n = (uint32_t)n_rows;
         const bool gfur = (o.mat == GJ_MAT_GFUR);
         int algo = o.algo;
-        if (algo == GJ_GB_AUTO) {
-            float f[12];
-            gj::features_groupby(f, (double)n, kb, n_vals);
-            const int c = gj::select_algorithm(f, 1, nullptr);
-            algo = c == 2 ? GJ_GB_HASH : (c == 3 ? GJ_GB_SORT : GJ_GB_PARTITION);
-        }
         const int32_t *vcols[8];
         for (int i = 0; i < n_vals; ++i) vcols[i] = static_cast<const int32_t *>(vals[i].data);
 
         gj::Ctx ctx(alloc, (hipStream_t)stream);
+        // the group count decides the algorithm and the partition passes: estimate it
+        double g_est = 0.0;
+        if (algo == GJ_GB_AUTO || (algo == GJ_GB_PARTITION && o.radix_bits == 0))
+            g_est = gj::estimate_groups(ctx, kb, key.data, n);
+        if (algo == GJ_GB_AUTO) {
+            float f[12];
+            gj::features_groupby(f, (double)n, kb, n_vals, g_est);
+            const int c = gj::select_algorithm(f, 1, nullptr);
+            algo = c == 2 ? GJ_GB_HASH : (c == 3 ? GJ_GB_SORT : GJ_GB_PARTITION);
+        }
         void *okey = nullptr;
         void *oaggs[16] = {nullptr};
         int64_t g = -1;
         if (algo == GJ_GB_PARTITION) {
             int bits = o.radix_bits;
-            if (bits == 0) bits = std::min(16, std::max(1, ceil_log2((n + 2047) / 2048)));
+            if (bits == 0) {
+                // partitions of about 2048 rows; one pass (at most 8 bits) whenever the
+                // estimated groups leave about 1000 or fewer keys per partition
+                bits = std::min(16, std::max(1, ceil_log2((n + 2047) / 2048)));
+                if (g_est <= (double)(1u << 18)) bits = std::min(bits, 8);
+            }
             int fell_back = 0;
             g = gj::groupby_partition(ctx, kb, key.data, vcols, n_vals, n, aggs, n_aggs, gfur, bits, &okey, oaggs,
                                       &fell_back);

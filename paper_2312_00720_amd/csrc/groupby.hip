@@ -5,10 +5,12 @@
 // is being aggregated in LDS, its record holds the 64-bit sums first, then
 // 32-bit counts, minima and maxima (one 4-byte word each), padded to an even
 // number of words. Outputs: SUM and COUNT as int64, MIN and MAX as int32.
+#include <math.h>
 #include <stdio.h>
 #include <stdlib.h>
 
 #include <algorithm>
+#include <cmath>
 #include <vector>
 
 #include "internal.hpp"
@@ -434,6 +436,42 @@ __device__ __forceinline__ int lds_find(const K *tab, int log2cap, K key) {
 }
 
 // ---------------------------------------------------------------------------------
+// Group-count estimate before any group-by runs (the count is unknown up front,
+// Section 2.2): a HyperLogLog sketch (Flajolet, Fusy, Gandouet, Meunier 2007)
+// over the 32-bit MurmurHash3 finalizer of the keys, 2^10 registers. One read of
+// the key column; it picks the partition passes and feeds the selector.
+
+constexpr int kHllBits = 10;
+
+template <typename K>
+__global__ __launch_bounds__(kBlock) void k_hll(const K *__restrict__ keys, uint32_t n, uint32_t *__restrict__ regs) {
+    constexpr int U = 8;
+    __shared__ uint32_t s_reg[1 << kHllBits];
+    for (int i = threadIdx.x; i < (1 << kHllBits); i += kBlock) s_reg[i] = 0;
+    __syncthreads();
+    const uint32_t stride = gridDim.x * kBlock * U;
+    for (uint32_t base = blockIdx.x * kBlock * U; base < n; base += stride) {
+        K k[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint32_t i = base + u * kBlock + threadIdx.x;
+            k[u] = i < n ? keys[i] : K(0);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (base + u * kBlock + threadIdx.x < n) {
+                const uint32_t h = (uint32_t)digit_source<K>(k[u], kDigitHash);
+                const uint32_t w = (h << kHllBits) | (1u << (kHllBits - 1));  // the bits below the index
+                atomicMax(&s_reg[h >> (32 - kHllBits)], (uint32_t)__clz((int)w) + 1u);
+            }
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < (1 << kHllBits); i += kBlock)
+        if (s_reg[i]) atomicMax(&regs[i], s_reg[i]);
+}
+
+// ---------------------------------------------------------------------------------
 // Partition-based group-by (Section 4.3). After partitioning on the hashed key,
 // the discover pass inserts every key of a partition into an LDS table before any
 // aggregation, which gives the partition's group count and hence dense output
@@ -714,11 +752,19 @@ __global__ __launch_bounds__(kBlock) void k_pgb_merge(PgbArgs a) {
     }
 }
 
-__global__ void k_pgb_units(const uint32_t *__restrict__ poff, uint32_t np, uint32_t *__restrict__ ucnt,
-                            uint32_t *__restrict__ max_units) {
+// Rows per aggregation unit of a partition with g groups: at least 256 rows per
+// group (at most 2^20), so that folding a unit's records into the output (g
+// atomic updates per aggregate) stays small next to the rows the unit aggregated.
+__device__ __forceinline__ uint32_t unit_rows_for(uint32_t g) {
+    const uint32_t r = min(max(kUnitRows, g * 256u), 1u << 20);
+    return ceil_div_u32(r, kUnitRows) * kUnitRows;
+}
+
+__global__ void k_pgb_units(const uint32_t *__restrict__ poff, const uint32_t *__restrict__ goff, uint32_t np,
+                            uint32_t *__restrict__ ucnt, uint32_t *__restrict__ max_units) {
     uint32_t mx = 0;
     for (uint32_t p = blockIdx.x * blockDim.x + threadIdx.x; p < np; p += gridDim.x * blockDim.x) {
-        const uint32_t u = ceil_div_u32(poff[p + 1] - poff[p], kUnitRows);
+        const uint32_t u = ceil_div_u32(poff[p + 1] - poff[p], unit_rows_for(goff[p + 1] - goff[p]));
         ucnt[p] = u;
         mx = max(mx, u);
     }
@@ -740,9 +786,10 @@ __device__ __forceinline__ void pgb_unit(const PgbArgs &a, uint32_t u, uint64_t 
         const uint32_t p = lo;
         const uint32_t p0 = a.poff[p], p1 = a.poff[p + 1];
         const uint32_t j = u - a.ubase[p];
+        const uint32_t ur = unit_rows_for(a.goff[p + 1] - a.goff[p]);
         s_unit[0] = p;
-        s_unit[1] = p0 + j * kUnitRows;
-        s_unit[2] = min(p0 + (j + 1) * kUnitRows, p1);
+        s_unit[1] = p0 + j * ur;
+        s_unit[2] = min(p0 + (j + 1) * ur, p1);
         s_unit[3] = (a.ubase[p + 1] - a.ubase[p]) > 1;  // several units share the partition
         s_unit[4] = j;
         s_sent_id = 0xFFFFFFFFu;
@@ -1202,6 +1249,34 @@ void init_outputs(hipStream_t st, const AggSpec &s, uint64_t g) {
 
 }  // namespace
 
+double estimate_groups(Ctx &ctx, int key_bytes, const void *key, uint32_t n) {
+    if (n == 0) return 0.0;
+    hipStream_t st = ctx.stream;
+    constexpr int m = 1 << kHllBits;
+    uint32_t *regs = ctx.scratch_n<uint32_t>(m);
+    fill_u32(st, regs, 0u, m);
+    const uint32_t grid = std::max<uint32_t>(1, std::min<uint32_t>(ceil_div_u32(n, kBlock * 8), 2048));
+    if (key_bytes == 4)
+        GJ_LAUNCH("k_hll", 4.0 * n, k_hll<int32_t>, dim3(grid), dim3(kBlock), 0, st, static_cast<const int32_t *>(key), n,
+                  regs);
+    else
+        GJ_LAUNCH("k_hll", 8.0 * n, k_hll<int64_t>, dim3(grid), dim3(kBlock), 0, st, static_cast<const int64_t *>(key), n,
+                  regs);
+    std::vector<uint32_t> h(m);
+    GJ_HIP(hipMemcpyAsync(h.data(), regs, 4ull * m, hipMemcpyDeviceToHost, st));
+    GJ_HIP(hipStreamSynchronize(st));
+    double sum = 0.0;
+    int zeros = 0;
+    for (uint32_t r : h) {
+        sum += std::ldexp(1.0, -(int)r);
+        zeros += (r == 0);
+    }
+    const double alpha = 0.7213 / (1.0 + 1.079 / m);
+    double e = alpha * m * (double)m / sum;
+    if (e <= 2.5 * m && zeros > 0) e = m * std::log((double)m / zeros);  // small-range correction
+    return std::min(e, (double)n);
+}
+
 int64_t groupby_partition(Ctx &ctx, int key_bytes, const void *key, const int32_t *const *vals, int n_vals,
                           uint32_t n, const gj_agg *aggs, int n_aggs, bool gfur, int bits, void **out_key,
                           void **out_aggs, int *fell_back) {
@@ -1263,8 +1338,8 @@ int64_t groupby_partition(Ctx &ctx, int key_bytes, const void *key, const int32_
     }
     scan_exclusive_u32(ctx, gcnt, gcnt, np, gcnt + np);
     uint32_t *ucnt = ctx.scratch_n<uint32_t>(np + 1);
-    GJ_LAUNCH("k_pgb_units", 12.0 * np, k_pgb_units, dim3(std::min<uint32_t>((np + 255) / 256, 1024)), dim3(256),
-              0, st, poff, np, ucnt, stat + 2);
+    GJ_LAUNCH("k_pgb_units", 16.0 * np, k_pgb_units, dim3(std::min<uint32_t>((np + 255) / 256, 1024)), dim3(256),
+              0, st, poff, (const uint32_t *)gcnt, np, ucnt, stat + 2);
     scan_exclusive_u32(ctx, ucnt, ucnt, np, ucnt + np);
     uint32_t host[5];
     GJ_HIP(hipMemcpyAsync(&host[0], gcnt + np, 4, hipMemcpyDeviceToHost, st));
@@ -1385,8 +1460,8 @@ void groupby_partition_segments(Ctx &ctx, int key_bytes, const void *key, const 
     }
     scan_exclusive_u32(ctx, gcnt, gcnt, np, gcnt + np);
     uint32_t *ucnt = ctx.scratch_n<uint32_t>(np + 1);
-    GJ_LAUNCH("k_pgb_units", 12.0 * np, k_pgb_units, dim3(std::min<uint32_t>((np + 255) / 256, 1024)), dim3(256),
-              0, st, poff, np, ucnt, stat + 2);
+    GJ_LAUNCH("k_pgb_units", 16.0 * np, k_pgb_units, dim3(std::min<uint32_t>((np + 255) / 256, 1024)), dim3(256),
+              0, st, poff, (const uint32_t *)gcnt, np, ucnt, stat + 2);
     scan_exclusive_u32(ctx, ucnt, ucnt, np, ucnt + np);
 
     a.spec = make_spec(aggs, n_aggs, pl.out_aggs);

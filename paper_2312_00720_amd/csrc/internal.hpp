@@ -197,6 +197,9 @@ void set_scatter_variant(int v);
 // Each returns the number of groups and allocates the key and aggregate outputs
 // through ctx.output(). groupby_partition returns -1 with *fell_back = 1 when a
 // partition holds more distinct keys than its LDS table.
+// Estimated number of distinct keys (HyperLogLog, about 3% standard error);
+// synchronizes with the stream.
+double estimate_groups(Ctx &ctx, int key_bytes, const void *key, uint32_t n);
 int64_t groupby_partition(Ctx &ctx, int key_bytes, const void *key, const int32_t *const *vals, int n_vals,
                           uint32_t n, const gj_agg *aggs, int n_aggs, bool gfur, int bits, void **out_key,
                           void **out_aggs, int *fell_back);
@@ -229,7 +232,7 @@ uint32_t pgb_plan_lds_bytes(int key_bytes);
 // Class 0..4 for the features (see gj.h); the network when loaded, else the cost model.
 int select_algorithm(const float *features, int op_kind, float *probs_out);
 void features_join(float *f, double nr, double ns, int key_bytes, int cr, int cs);
-void features_groupby(float *f, double n, int key_bytes, int nv);
+void features_groupby(float *f, double n, int key_bytes, int nv, double g_est = 0.0);
 
 // ---- join.hip -------------------------------------------------------------------------
 constexpr uint32_t kJoinMaxBuild = 4096;  // R rows per LDS build block

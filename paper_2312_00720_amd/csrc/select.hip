@@ -175,12 +175,13 @@ void features_join(float *f, double nr, double ns, int key_bytes, int cr, int cs
     f[11] = (float)(std::log2(std::max(1.0, nr * (key_bytes + 4.0 * cr) + ns * (key_bytes + 4.0 * cs))) / 48.0);
 }
 
-void features_groupby(float *f, double n, int key_bytes, int nv) {
+void features_groupby(float *f, double n, int key_bytes, int nv, double g_est) {
     memset(f, 0, 12 * sizeof(float));
     f[0] = 0.f;
     f[1] = (float)(std::log2(std::max(1.0, n)) / 32.0);
-    // the group count is unknown before the call (Section 2.2): assume about n / 16
-    const double g = std::max(1.0, n / 16.0);
+    // the group count is unknown before the call (Section 2.2): the caller's
+    // estimate, else about n / 16
+    const double g = std::max(1.0, g_est > 0.0 ? g_est : n / 16.0);
     f[3] = (float)(std::log2(g) / 32.0);
     f[4] = key_bytes / 8.f;
     f[5] = nv / 8.f;
