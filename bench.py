@@ -310,7 +310,7 @@ def main() -> int:
                             if k.startswith(("k_hist", "k_scatter", "k_scan", "k_chunk", "k_poff",
                                              "k_fill", "k_set"))),
         "match_ms": sum(kern[k]["ms_per_step"] for k in kern if k in ("k_unit_count", "k_join_count")),
-        "materialize_ms": kern.get("k_join_write", {}).get("ms_per_step", 0.0),
+        "materialize_ms": sum(kern[k]["ms_per_step"] for k in kern if k.startswith("k_join_write")),
     }
     res = {
         "metric": "materialized join tuples/s",

@@ -56,13 +56,20 @@ struct JoinArgs {
     const uint32_t *nunits;     // device: work units (the kernels loop over them)
     uint32_t cap_units;         // units beyond this are not processed (a plan's capacity)
     const uint64_t *out_base;   // device: first output row of this call (nullptr = 0)
+    // Streaming write path: the count pass records each S row's match (its
+    // partitioned R row, or -1) when every partition has one R block and no S row
+    // matches twice; flags[0] / flags[1] mark the contrary.
+    int32_t *midx;
+    uint32_t *flags;
+    int lds_if_complex;         // LDS write pass: do nothing unless a flag is set (plans)
 };
 
 __global__ void k_unit_count(const uint32_t *__restrict__ rpo, const uint32_t *__restrict__ spo,
-                             uint32_t np, uint32_t rc, uint32_t *__restrict__ ucnt) {
+                             uint32_t np, uint32_t rc, uint32_t *__restrict__ ucnt, uint32_t *__restrict__ flags) {
     for (uint32_t p = blockIdx.x * blockDim.x + threadIdx.x; p < np; p += gridDim.x * blockDim.x) {
         const uint32_t nr = rpo[p + 1] - rpo[p], ns = spo[p + 1] - spo[p];
         ucnt[p] = (nr && ns) ? ceil_div_u32(nr, rc) * ceil_div_u32(ns, kSPiece) : 0u;
+        if (nr > rc && ns) atomicOr(&flags[0], 1u);  // a partition spans several R blocks
     }
 }
 
@@ -237,6 +244,7 @@ __device__ __forceinline__ void join_unit(const JoinArgs &a, uint32_t u, uint64_
     const uint32_t ws = min(sn, w * q), we = min(sn, ws + q);
     if constexpr (!WRITE) {
         uint32_t cnt = 0;
+        bool multi = false;
         for (uint32_t base = ws; base < we; base += PB * kWave) {
             K key[PB];
 #pragma unroll
@@ -246,14 +254,26 @@ __device__ __forceinline__ void join_unit(const JoinArgs &a, uint32_t u, uint64_
             }
 #pragma unroll
             for (int r = 0; r < PB; ++r) {
-                if (base + r * kWave + lane < we) {
+                const uint32_t i = base + r * kWave + lane;
+                if (i < we) {
                     const uint32_t b = bucket_of<K>(key[r], skip_bits, log2nb);
-                    for (uint32_t e = s_b[b], end = s_b[b + 1]; e < end; ++e) cnt += (s_rkey[s_entry[e]] == key[r]);
+                    uint32_t c = 0, e1 = 0;
+                    for (uint32_t e = s_b[b], end = s_b[b + 1]; e < end; ++e) {
+                        const uint32_t ri = s_entry[e];
+                        if (s_rkey[ri] == key[r]) {
+                            if (c == 0) e1 = ri;
+                            ++c;
+                        }
+                    }
+                    cnt += c;
+                    multi |= c > 1;
+                    if (a.midx) a.midx[s0 + i] = c ? (int32_t)(r0 + e1) : -1;
                 }
             }
         }
         const uint64_t tot = wave_sum<uint64_t>((uint64_t)cnt);
         if (lane == 0) a.wcnt[(uint64_t)u * kWaves + w] = tot;
+        if (a.flags && __ballot(multi) && lane == 0) atomicOr(&a.flags[1], 1u);
     } else {
         uint64_t outpos = out_base + a.woff[(uint64_t)u * kWaves + w];
         K *__restrict__ tkey = static_cast<K *>(a.tkey);
@@ -336,10 +356,68 @@ __global__ __launch_bounds__(kBlock) void k_join(JoinArgs a) {
     if (blockIdx.x < min(*a.nunits, a.cap_units)) join_unit<K, WRITE>(a, blockIdx.x, 0ull, sh);
 }
 
+// Write pass without a hash table, for the common case recorded by the count
+// pass (one R block per partition, at most one match per S row): each wave
+// streams its S rows with their recorded matches, takes output positions from
+// the scanned counts plus a ballot prefix, and gathers the payloads (GFTR:
+// partition-local R rows; GFUR: original rows through the row ids).
+template <typename K>
+__global__ __launch_bounds__(kBlock) void k_join_stream(JoinArgs a) {
+    constexpr int PB = 16;
+    if (a.flags[0] | a.flags[1]) return;  // the LDS write pass handles this input
+    const int tid = threadIdx.x, w = tid / kWave, lane = lane_id();
+    const uint32_t n_units = min(*a.nunits, a.cap_units);
+    const uint64_t out_base = a.out_base ? *a.out_base : 0ull;
+    const K *__restrict__ skey = static_cast<const K *>(a.skey);
+    K *__restrict__ tkey = static_cast<K *>(a.tkey);
+    for (uint32_t u = blockIdx.x; u < n_units; u += gridDim.x) {
+        uint32_t lo = 0, hi = a.np;  // ubase[lo] <= u < ubase[hi]
+        while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (a.ubase[mid] <= u) lo = mid;
+            else hi = mid;
+        }
+        const uint32_t p = lo, sb = u - a.ubase[p];  // one R block: the unit is the S piece
+        const uint32_t ns = a.spo[p + 1] - a.spo[p];
+        const uint32_t s0 = a.spo[p] + sb * kSPiece, sn = min(kSPiece, ns - sb * kSPiece);
+        const uint32_t q = ceil_div_u32(sn, kWaves);
+        const uint32_t ws = min(sn, w * q), we = min(sn, ws + q);
+        uint64_t outpos = out_base + a.woff[(uint64_t)u * kWaves + w];
+        for (uint32_t base = ws; base < we; base += PB * kWave) {
+            int32_t m[PB];
+            K key[PB];
+#pragma unroll
+            for (int r = 0; r < PB; ++r) {
+                const uint32_t i = base + r * kWave + lane;
+                m[r] = i < we ? a.midx[s0 + i] : -1;
+                key[r] = i < we ? skey[s0 + i] : K(0);
+            }
+            uint32_t c[PB], srow[PB], rrow[PB];
+            uint64_t pos[PB];
+#pragma unroll
+            for (int r = 0; r < PB; ++r) {
+                c[r] = m[r] >= 0;
+                const uint64_t hit = __ballot(c[r] != 0);
+                pos[r] = outpos + rank_below(hit);
+                outpos += (uint64_t)__popcll(hit);
+                if (c[r] && pos[r] < a.t_rows) tkey[pos[r]] = key[r];
+                const uint32_t i = base + r * kWave + lane;
+                srow[r] = s0 + i;
+                rrow[r] = c[r] ? (uint32_t)m[r] : 0u;
+                if (a.srow && c[r]) srow[r] = (uint32_t)a.srow[srow[r]];
+                if (a.rrow && c[r]) rrow[r] = (uint32_t)a.rrow[rrow[r]];
+            }
+            gather_cols<PB>(a.ns, a.sp, a.sw, a.ts, srow, c, pos, a.t_rows);
+            gather_cols<PB>(a.nr, a.rp, a.rw, a.tr, rrow, c, pos, a.t_rows);
+        }
+    }
+}
+
 // Persistent workgroups over the unit count held in device memory (plans).
 template <typename K, bool WRITE>
 __global__ __launch_bounds__(kBlock, 3) void k_join_persist(JoinArgs a) {
     __shared__ JoinShared<K> sh;
+    if (WRITE && a.lds_if_complex && !(a.flags[0] | a.flags[1])) return;  // the streaming pass writes
     const uint32_t n_units = min(*a.nunits, a.cap_units);
     const uint64_t out_base = a.out_base ? *a.out_base : 0ull;
     for (uint32_t u = blockIdx.x; u < n_units; u += gridDim.x) {
@@ -382,8 +460,10 @@ int64_t join_partitioned(Ctx &ctx, int key_bytes, const JoinSide &R, const JoinS
     require(r_block >= 64 && r_block <= (int)kMaxBuild, "R build block must be 64..4096 rows");
     const uint32_t np = seg_bits ? (n_inst << 8) : (1u << bits);
     uint32_t *ucnt = ctx.scratch_n<uint32_t>(np + 1);
+    uint32_t *flags = ctx.scratch_n<uint32_t>(2);
+    fill_u32(s, flags, 0u, 2);
     GJ_LAUNCH("k_unit_count", 20.0 * np, k_unit_count, dim3(std::min<uint32_t>((np + 255) / 256, 1024)),
-              dim3(256), 0, s, R.poff, S.poff, np, (uint32_t)r_block, ucnt);
+              dim3(256), 0, s, R.poff, S.poff, np, (uint32_t)r_block, ucnt, flags);
     scan_exclusive_u32(ctx, ucnt, ucnt, np, ucnt + np);
     // Eager calls read the unit count and size every launch exactly; a plan sizes
     // for its capacity and the kernels read the count from device memory.
@@ -415,6 +495,9 @@ int64_t join_partitioned(Ctx &ctx, int key_bytes, const JoinSide &R, const JoinS
     a.nunits = ucnt + np;
     a.cap_units = cap_units;
     a.out_base = pl ? pl->out_base : nullptr;
+    a.midx = ctx.scratch_n<int32_t>(std::max<uint32_t>(S.rows, 1));
+    a.flags = flags;
+    a.lds_if_complex = pl ? 1 : 0;
     const uint64_t nw = (uint64_t)cap_units * kWaves;
     uint64_t *wcnt = ctx.scratch_n<uint64_t>(nw + 1);
     uint64_t *total = pl ? pl->total : wcnt + nw;
@@ -431,11 +514,16 @@ int64_t join_partitioned(Ctx &ctx, int key_bytes, const JoinSide &R, const JoinS
     if (pl) scan_exclusive_u64_dev(ctx, wcnt, wcnt, nw, ucnt + np, kWaves, total);
     else scan_exclusive_u64(ctx, wcnt, wcnt, nw, total);
     uint64_t T;
+    bool complex = true;  // plans launch both write passes; each decides on the device
     if (pl) {
         T = pl->out_cap;  // stores are checked against the capacity; the true count stays on the device
         *out = pl->out;
     } else {
-        T = read_back(total, s);
+        uint32_t hf[2];
+        GJ_HIP(hipMemcpyAsync(&T, total, 8, hipMemcpyDeviceToHost, s));
+        GJ_HIP(hipMemcpyAsync(hf, flags, 8, hipMemcpyDeviceToHost, s));
+        GJ_HIP(hipStreamSynchronize(s));
+        complex = (hf[0] | hf[1]) != 0;
     }
     if (inst_off)
         GJ_LAUNCH("k_instance_offsets", 16.0 * n_inst, k_instance_offsets,
@@ -478,12 +566,25 @@ int64_t join_partitioned(Ctx &ctx, int key_bytes, const JoinSide &R, const JoinS
     double wbytes = key_reads + t_rows * (key_bytes + rw_sum + sw_sum);
     if (gfur) wbytes += t_rows * (rw_sum + sw_sum) + 4.0 * (nrows_r + nrows_s);
     else wbytes += nrows_r * rw_sum + nrows_s * sw_sum;
-    if (key_bytes == 4) {
-        if (pl) GJ_LAUNCH("k_join_write", wbytes, (k_join_persist<int32_t, true>), dim3(grid), dim3(kBlock), 0, s, a);
-        else GJ_LAUNCH("k_join_write", wbytes, (k_join<int32_t, true>), dim3(grid), dim3(kBlock), 0, s, a);
-    } else {
-        if (pl) GJ_LAUNCH("k_join_write", wbytes, (k_join_persist<int64_t, true>), dim3(grid), dim3(kBlock), 0, s, a);
-        else GJ_LAUNCH("k_join_write", wbytes, (k_join<int64_t, true>), dim3(grid), dim3(kBlock), 0, s, a);
+    // the streaming pass reads no R keys
+    const double sbytes = wbytes - nrows_r * key_bytes;
+    // Eager calls launch the one write pass the count pass chose; plans launch
+    // both, and the one that does not apply returns at once.
+    if (pl || !complex) {
+        if (key_bytes == 4)
+            GJ_LAUNCH("k_join_write", sbytes, k_join_stream<int32_t>, dim3(grid), dim3(kBlock), 0, s, a);
+        else
+            GJ_LAUNCH("k_join_write", sbytes, k_join_stream<int64_t>, dim3(grid), dim3(kBlock), 0, s, a);
+    }
+    if (pl || complex) {
+        const double lbytes = pl ? 0.0 : wbytes;  // a plan counts its bytes once, on the streaming pass
+        if (key_bytes == 4) {
+            if (pl) GJ_LAUNCH("k_join_write_lds", lbytes, (k_join_persist<int32_t, true>), dim3(grid), dim3(kBlock), 0, s, a);
+            else GJ_LAUNCH("k_join_write_lds", lbytes, (k_join<int32_t, true>), dim3(grid), dim3(kBlock), 0, s, a);
+        } else {
+            if (pl) GJ_LAUNCH("k_join_write_lds", lbytes, (k_join_persist<int64_t, true>), dim3(grid), dim3(kBlock), 0, s, a);
+            else GJ_LAUNCH("k_join_write_lds", lbytes, (k_join<int64_t, true>), dim3(grid), dim3(kBlock), 0, s, a);
+        }
     }
     return pl ? 0 : (int64_t)T;
 }

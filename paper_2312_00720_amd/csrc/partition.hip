@@ -141,13 +141,37 @@ __global__ __launch_bounds__(kBlock) void k_hist(PassArgs a) {
     }
 }
 
-__device__ __forceinline__ uint32_t load_col4(const PassArgs &a, int c, uint32_t row) {
-    return c == a.rowid_col ? row : static_cast<const uint32_t *>(a.col_in[c])[row];
+// Loads of one tile: ITEMS keys per thread and the first group of up to G 4-byte
+// columns (a generated row id is its row index). Rows past nt read as zero.
+template <typename K, int BLOCK, int ITEMS, int G>
+__device__ __forceinline__ void scatter_load_keys(const PassArgs &a, uint32_t tile0, uint32_t nt, K (&key)[ITEMS]) {
+    const K *__restrict__ keys = static_cast<const K *>(a.key_in);
+    const int w = threadIdx.x / kWave, lane = lane_id();
+    const uint32_t lbase = (uint32_t)(w * kWave * ITEMS + lane);
+#pragma unroll
+    for (int r = 0; r < ITEMS; ++r) key[r] = lbase + r * kWave < nt ? keys[tile0 + lbase + r * kWave] : K(0);
 }
 
-// One tile of the stable scatter: TILE rows starting at tile0 (nt valid; FULL
-// means nt == TILE and no row needs a bounds check). Columns 0..n4-1 are 4-byte
-// (the generated row id among them), columns n4..ncols-1 are 8-byte.
+template <int BLOCK, int ITEMS>
+__device__ __forceinline__ void scatter_load_col(const PassArgs &a, int c, uint32_t tile0, uint32_t nt,
+                                                 uint32_t (&v)[ITEMS]) {
+    const int w = threadIdx.x / kWave, lane = lane_id();
+    const uint32_t lbase = (uint32_t)(w * kWave * ITEMS + lane);
+    const bool gen = (c == a.rowid_col);
+    const uint32_t *__restrict__ in = static_cast<const uint32_t *>(a.col_in[c]);
+#pragma unroll
+    for (int r = 0; r < ITEMS; ++r) {
+        const uint32_t row = tile0 + lbase + r * kWave;
+        v[r] = gen ? row : (lbase + r * kWave < nt ? in[row] : 0u);
+    }
+}
+
+// One tile of the stable scatter: nt rows from tile0, whose keys are already in
+// `key`. Once the keys are in LDS, their registers receive the next tile's keys
+// (next0, next_nt rows; next_nt = 0: none), so that those loads are in flight
+// during this tile's column work and the next tile ranks without waiting.
+// Columns 0..n4-1 are 4-byte (the generated row id among them), columns
+// n4..ncols-1 are 8-byte.
 template <int BLOCK>
 struct ScatterShared {
     static constexpr int W = BLOCK / kWave;
@@ -158,39 +182,26 @@ struct ScatterShared {
     uint32_t tmp[kWaves];
 };
 
-template <typename K, int BLOCK, int ITEMS, int G, bool FULL>
+template <typename K, int BLOCK, int ITEMS, int G>
 __device__ __forceinline__ void scatter_tile(const PassArgs &a, const DigitFn &dig, ScatterShared<BLOCK> &S,
-                                             uint32_t (*s_buf)[BLOCK * ITEMS], uint32_t tile0, uint32_t nt) {
-    constexpr uint32_t TILE = BLOCK * ITEMS;
+                                             uint32_t (*s_buf)[BLOCK * ITEMS], uint32_t tile0, uint32_t nt,
+                                             K (&key)[ITEMS], uint32_t next0, uint32_t next_nt) {
     constexpr int W = BLOCK / kWave;
     const int tid = threadIdx.x, w = tid / kWave, lane = lane_id();
-    const K *__restrict__ keys = static_cast<const K *>(a.key_in);
     K *__restrict__ kout = static_cast<K *>(a.key_out);
     K *sk = reinterpret_cast<K *>(&s_buf[0][0]);
     uint64_t *s8 = reinterpret_cast<uint64_t *>(&s_buf[0][0]);
     const int n4 = a.n4;
+    const bool full = (nt == BLOCK * ITEMS);
     const uint32_t lbase = (uint32_t)(w * kWave * ITEMS + lane);
-#define GJ_VALID(r) (FULL || lbase + (r) * kWave < nt)
+#define GJ_VALID(r) (full || lbase + (r) * kWave < nt)
 
     for (int i = tid; i < W * kRadix; i += BLOCK) (&S.wcnt[0][0])[i] = 0;
-
-    // issue the loads of the keys and of the first group of 4-byte columns
-    K key[ITEMS];
+    // the first column group is loaded now and consumed after the ranking
     uint32_t v[G][ITEMS];
 #pragma unroll
-    for (int r = 0; r < ITEMS; ++r) key[r] = GJ_VALID(r) ? keys[tile0 + lbase + r * kWave] : K(0);
-#pragma unroll
-    for (int g = 0; g < G; ++g) {
-        if (g < n4) {
-            const bool gen = (g == a.rowid_col);
-            const uint32_t *__restrict__ in = static_cast<const uint32_t *>(a.col_in[g]);
-#pragma unroll
-            for (int r = 0; r < ITEMS; ++r) {
-                const uint32_t row = tile0 + lbase + r * kWave;
-                v[g][r] = gen ? row : (GJ_VALID(r) ? in[row] : 0u);
-            }
-        }
-    }
+    for (int g = 0; g < G; ++g)
+        if (g < n4) scatter_load_col<BLOCK, ITEMS>(a, g, tile0, nt, v[g]);
     __syncthreads();
 
     // stable rank within the wave: ballot peers, the leader bumps the wave counter
@@ -241,6 +252,8 @@ __device__ __forceinline__ void scatter_tile(const PassArgs &a, const DigitFn &d
             sk[pos[r]] = key[r];
         }
     }
+    // the key registers are free: next tile's keys
+    if (next_nt) scatter_load_keys<K, BLOCK, ITEMS, G>(a, next0, next_nt, key);
     __syncthreads();
 
     uint32_t dst[ITEMS];
@@ -248,7 +261,7 @@ __device__ __forceinline__ void scatter_tile(const PassArgs &a, const DigitFn &d
     for (int k = 0; k < ITEMS; ++k) {
         const uint32_t i = (uint32_t)(k * BLOCK + tid);
         dst[k] = 0xFFFFFFFFu;
-        if (FULL || i < nt) {
+        if (full || i < nt) {
             const K kk = sk[i];
             const uint32_t d = digit_of<K>(kk, dig);
             const uint32_t t = S.cur[d] + i - S.start[d];
@@ -268,17 +281,8 @@ __device__ __forceinline__ void scatter_tile(const PassArgs &a, const DigitFn &d
     for (int c0 = 0; c0 < n4; c0 += G) {
         if (c0 > 0) {
 #pragma unroll
-            for (int g = 0; g < G; ++g) {
-                if (c0 + g < n4) {
-                    const bool gen = (c0 + g == a.rowid_col);
-                    const uint32_t *__restrict__ in = static_cast<const uint32_t *>(a.col_in[c0 + g]);
-#pragma unroll
-                    for (int r = 0; r < ITEMS; ++r) {
-                        const uint32_t row = tile0 + lbase + r * kWave;
-                        v[g][r] = gen ? row : (GJ_VALID(r) ? in[row] : 0u);
-                    }
-                }
-            }
+            for (int g = 0; g < G; ++g)
+                if (c0 + g < n4) scatter_load_col<BLOCK, ITEMS>(a, c0 + g, tile0, nt, v[g]);
         }
 #pragma unroll
         for (int g = 0; g < G; ++g) {
@@ -335,10 +339,17 @@ __global__ __launch_bounds__(BLOCK) void k_scatter(PassArgs a) {
         S.cur[d] = d < R ? base_off + a.hist[L.hbase + d * L.m + L.j] : 0u;
 
     const DigitFn dig = seg_digit(a, L.seg);
+    K key[ITEMS];
     uint32_t tile0 = L.row0;
-    for (; tile0 + TILE <= L.row1; tile0 += TILE)
-        scatter_tile<K, BLOCK, ITEMS, G, true>(a, dig, S, s_buf, tile0, TILE);
-    if (tile0 < L.row1) scatter_tile<K, BLOCK, ITEMS, G, false>(a, dig, S, s_buf, tile0, L.row1 - tile0);
+    uint32_t nt = min(TILE, L.row1 - tile0);
+    if (nt) scatter_load_keys<K, BLOCK, ITEMS, G>(a, tile0, nt, key);
+    while (nt) {
+        const uint32_t next0 = tile0 + nt;
+        const uint32_t next_nt = next0 < L.row1 ? min(TILE, L.row1 - next0) : 0u;
+        scatter_tile<K, BLOCK, ITEMS, G>(a, dig, S, s_buf, tile0, nt, key, next0, next_nt);
+        tile0 = next0;
+        nt = next_nt;
+    }
 }
 
 __global__ void k_poff(const uint32_t *__restrict__ seg_off, uint32_t nseg,
