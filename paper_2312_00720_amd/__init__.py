@@ -180,7 +180,24 @@ def lib() -> ctypes.CDLL:
             L.gj_version.restype = ctypes.c_char_p
             L.gj_version.argtypes = []
             _lib = L
+            _load_shipped_weights(L)
     return _lib
+
+
+SELECTOR_WEIGHTS = os.path.join(_HERE, "selector_weights.f32")
+
+
+def _load_shipped_weights(L) -> None:
+    """The selector network trained on measured timings ships with the package
+    (5317 little-endian float32); once loaded, automatic choices use it (else
+    the cost model decides)."""
+    if not os.path.exists(SELECTOR_WEIGHTS):
+        return
+    with open(SELECTOR_WEIGHTS, "rb") as f:
+        raw = f.read()
+    if len(raw) == 4 * 5317:
+        arr = (ctypes.c_float * 5317).from_buffer_copy(raw)
+        L.gj_selector_set_weights(arr, 5317)
 
 
 class _TorchAllocator:

@@ -381,7 +381,7 @@ struct Shape {
 };
 constexpr Shape kVariants[kScatterVariants] = {{256, 8, 4},  {512, 8, 4},  {1024, 8, 4}, {512, 4, 4},
                                                {1024, 4, 4}, {256, 16, 2}, {512, 8, 2},  {512, 16, 2},
-                                               {512, 16, 4}, {1024, 8, 2}};
+                                               {512, 16, 4}, {1024, 8, 2},  {1024, 16, 2}, {1024, 16, 1}};
 thread_local int g_variant = 0;
 Shape scatter_shape() {
     if (g_variant >= 1 && g_variant <= kScatterVariants) return kVariants[g_variant - 1];
@@ -405,6 +405,7 @@ void launch_scatter(const Shape &sh, dim3 grid, hipStream_t s, const PassArgs &a
     }
     GJ_SC(256, 8, 4) GJ_SC(512, 8, 4) GJ_SC(1024, 8, 4) GJ_SC(512, 4, 4) GJ_SC(1024, 4, 4)
     GJ_SC(256, 16, 2) GJ_SC(512, 8, 2) GJ_SC(512, 16, 2) GJ_SC(512, 16, 4) GJ_SC(1024, 8, 2)
+    GJ_SC(1024, 16, 2) GJ_SC(1024, 16, 1)
 #undef GJ_SC
     throw Error(GJ_EINVAL, "unknown scatter shape");
 }

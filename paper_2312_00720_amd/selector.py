@@ -33,7 +33,7 @@ import paper_2312_00720_amd as gj
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 CLASSES = gj.CLASSES
-WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "selector_weights.npy")
+WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "selector_weights.f32")
 
 
 def sample(n: int, seed: int) -> list[dict]:
@@ -181,6 +181,22 @@ def regret(T: np.ndarray, M: np.ndarray, choice: np.ndarray) -> dict:
             "aggregate_pct": float(100 * (tc.sum() / best.sum() - 1.0)), "best_picked_pct": float(100 * np.mean(r == 0))}
 
 
+def evaluate_arrays(X, M, T, theta) -> dict:
+    """Regret of the network (theta), the cost model, and a fixed choice, from
+    feature and timing arrays alone."""
+    gj.selector_set_weights(theta)
+    mlp_c = np.array([gj.select(x, 0 if m[0] else 1)[0] for x, m in zip(X, M)])
+    gj.selector_set_weights(None)
+    cm_c = np.array([gj.select(x, 0 if m[0] else 1)[0] for x, m in zip(X, M)])
+    fixed = np.array([0 if m[0] else 4 for m in M])
+    rep = {"mlp": regret(T, M, mlp_c), "cost_model": regret(T, M, cm_c), "always_gftr_pgb": regret(T, M, fixed)}
+    t_mlp = T[np.arange(len(T)), mlp_c].sum()
+    t_cm = T[np.arange(len(T)), cm_c].sum()
+    rep["mlp_vs_cost_model_pct"] = float(100 * (t_mlp / t_cm - 1.0))
+    rep["n"] = int(len(X))
+    return rep
+
+
 def evaluate(ws, X, M, T, theta) -> dict:
     gj.selector_set_weights(theta)
     mlp_c = np.array([gj.select(x, 0 if m[0] else 1)[0] for x, m in zip(X, M)])
@@ -233,7 +249,7 @@ def main(argv=None) -> int:
         Xte, Mte, Tte = build(te)
         np.savez(os.path.join(args.out, "selector_data.npz"), Xtr=Xtr, Mtr=Mtr, Ttr=Ttr, Xte=Xte, Mte=Mte, Tte=Tte)
     theta = train(Xtr, Mtr, Ttr, steps=args.steps)
-    np.save(os.path.join(args.out, "selector_weights.npy"), theta)
+    theta.astype("<f4").tofile(os.path.join(args.out, "selector_weights.f32"))
     rep = {"train": evaluate(tr, Xtr, Mtr, Ttr, theta), "test": evaluate(te, Xte, Mte, Tte, theta)}
     with open(os.path.join(args.out, "selector_report.json"), "w") as f:
         json.dump(rep, f, indent=1)
