@@ -110,7 +110,7 @@ __device__ __forceinline__ void gather_cols(int ncols, const void *const *src, c
 
 template <typename K>
 struct JoinShared {
-    K rkey[kMaxBuild];
+    K rkey[kMaxBuild];          // R block keys: input order while building, bucket order after
     uint32_t b[kMaxBuild + 1];   // bucket boundaries
     uint16_t entry[kMaxBuild];  // R block rows, grouped by bucket
     uint32_t tmp[kWaves];
@@ -236,6 +236,24 @@ __device__ __forceinline__ void join_unit(const JoinArgs &a, uint32_t u, uint64_
         }
         __syncthreads();
     }
+    {
+        // keys in bucket order (s_rkey[e] = key of entry e), so that a probe
+        // compares keys without going through the row index
+        constexpr int per = (int)(kMaxBuild / kBlock);
+        K t[per];
+#pragma unroll
+        for (int k = 0; k < per; ++k) {
+            const uint32_t e = tid + k * kBlock;
+            t[k] = e < rn ? s_rkey[s_entry[e]] : K(0);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < per; ++k) {
+            const uint32_t e = tid + k * kBlock;
+            if (e < rn) s_rkey[e] = t[k];
+        }
+        __syncthreads();
+    }
 
     // ---- probe: each wave streams a contiguous quarter of the S piece, PB
     // rounds of 64 rows at a time so that many loads are in flight ----
@@ -259,9 +277,8 @@ __device__ __forceinline__ void join_unit(const JoinArgs &a, uint32_t u, uint64_
                     const uint32_t b = bucket_of<K>(key[r], skip_bits, log2nb);
                     uint32_t c = 0, e1 = 0;
                     for (uint32_t e = s_b[b], end = s_b[b + 1]; e < end; ++e) {
-                        const uint32_t ri = s_entry[e];
-                        if (s_rkey[ri] == key[r]) {
-                            if (c == 0) e1 = ri;
+                        if (s_rkey[e] == key[r]) {
+                            if (c == 0) e1 = s_entry[e];
                             ++c;
                         }
                     }
@@ -292,9 +309,8 @@ __device__ __forceinline__ void join_unit(const JoinArgs &a, uint32_t u, uint64_
                 if (base + r * kWave + lane < we) {
                     const uint32_t b = bucket_of<K>(key[r], skip_bits, log2nb);
                     for (uint32_t e = s_b[b], end = s_b[b + 1]; e < end; ++e) {
-                        const uint32_t ri = s_entry[e];
-                        if (s_rkey[ri] == key[r]) {
-                            if (c[r] == 0) e1[r] = ri;
+                        if (s_rkey[e] == key[r]) {
+                            if (c[r] == 0) e1[r] = s_entry[e];
                             ++c[r];
                         }
                     }
@@ -335,8 +351,8 @@ __device__ __forceinline__ void join_unit(const JoinArgs &a, uint32_t u, uint64_
                     const uint64_t sr = a.srow ? (uint64_t)a.srow[s0 + i] : (uint64_t)(s0 + i);
                     const uint32_t b = bucket_of<K>(key[r], skip_bits, log2nb);
                     for (uint32_t e = s_b[b], end = s_b[b + 1]; e < end; ++e) {
+                        if (s_rkey[e] != key[r] || p >= a.t_rows) continue;
                         const uint32_t ri = s_entry[e];
-                        if (s_rkey[ri] != key[r] || p >= a.t_rows) continue;
                         const uint64_t rr = a.rrow ? (uint64_t)a.rrow[r0 + ri] : (uint64_t)(r0 + ri);
                         tkey[p] = key[r];
                         for (int j = 0; j < a.nr; ++j) copy_val(a.tr[j], a.rw[j], p, a.rp[j], rr);
