@@ -501,7 +501,6 @@ struct PgbArgs {
     uint32_t cap_units;     // units beyond this are not processed
     const uint64_t *out_base; // device: first output group of this call (nullptr = 0)
     uint32_t lds_bytes;     // > 0: table size and records chosen per partition within this LDS
-    uint32_t lds_dyn;       // dynamic LDS of the launch, in bytes
 };
 
 template <typename K>
@@ -772,15 +771,6 @@ __global__ void k_pgb_units(const uint32_t *__restrict__ poff, const uint32_t *_
     atomicMax(max_units, mx);
 }
 
-// Rows per tile of the owner aggregation (8 per thread).
-constexpr uint32_t kOwnerRows = kBlock * 8;
-constexpr uint32_t kOwnerMaxGroups = 4 * kBlock;
-
-template <typename K>
-__host__ __device__ constexpr uint32_t owner_lds_bytes(uint32_t cap, uint32_t g, int nv) {
-    return cap * (uint32_t)(sizeof(K) + 2) + 8 + 8u * g + kOwnerRows * (uint32_t)nv * 4u + 16;
-}
-
 template <typename K, int NV>
 __device__ __forceinline__ void pgb_unit(const PgbArgs &a, uint32_t u, uint64_t out_base, uint32_t *s_dyn,
                                          uint32_t *s_unit, uint32_t &s_sent_id) {
@@ -874,91 +864,6 @@ __device__ __forceinline__ void pgb_unit(const PgbArgs &a, uint32_t u, uint64_t 
         }
     }
     __syncthreads();
-    // Owner aggregation (case 2 without LDS atomics per aggregate): for up to 1024
-    // groups and at most 2 value columns, each tile of rows is bucketed by group id
-    // in LDS (one atomic per row for its slot), and thread t folds the rows of
-    // groups t, t + 256, ... into registers; records never leave registers until
-    // the unit ends.
-    if (NV <= 2 && g >= 3 && g <= kOwnerMaxGroups && owner_lds_bytes<K>(cap, g, NV) <= a.lds_dyn) {
-        uint32_t *hist = reinterpret_cast<uint32_t *>((reinterpret_cast<uintptr_t>(id_of + cap) + 7) & ~uintptr_t(7));
-        uint32_t *start = hist + g;
-        int *stage = reinterpret_cast<int *>(start + g);
-        uint32_t *s_tmp = s_unit + 5;
-        for (uint32_t i = tid; i < g; i += kBlock) hist[i] = 0;
-        Acc<NV> own[kOwnerMaxGroups / kBlock];
-#pragma unroll
-        for (int j = 0; j < (int)(kOwnerMaxGroups / kBlock); ++j) acc_clear(own[j]);
-        __syncthreads();
-        constexpr int OB = (int)(kOwnerRows / kBlock);
-        for (uint32_t base = r0; base < r1; base += kOwnerRows) {
-            K kk[OB];
-            Row<NV> rr[OB];
-            uint32_t id[OB], slot[OB];
-#pragma unroll
-            for (int r = 0; r < OB; ++r) {
-                const uint32_t i = base + r * kBlock + tid;
-                kk[r] = i < r1 ? keys[i] : e;
-                if (i < r1) rr[r] = load_row<NV>(a.vals, i);
-            }
-#pragma unroll
-            for (int r = 0; r < OB; ++r) {
-                if (base + r * kBlock + tid < r1) {
-                    id[r] = (kk[r] == e) ? s_sent_id : id_of[lds_find<K>(tab, log2cap, kk[r])];
-                    slot[r] = atomicAdd(&hist[id[r]], 1u);
-                }
-            }
-            __syncthreads();
-            {
-                // exclusive scan of the g tile counts into start
-                constexpr int per = (int)(kOwnerMaxGroups / kBlock);
-                const uint32_t first = tid * per;
-                uint32_t v[per], sum = 0;
-#pragma unroll
-                for (int k = 0; k < per; ++k) {
-                    v[k] = first + k < g ? hist[first + k] : 0u;
-                    sum += v[k];
-                }
-                uint32_t run = block_exclusive_sum<uint32_t>(sum, s_tmp, (uint32_t *)nullptr);
-#pragma unroll
-                for (int k = 0; k < per; ++k) {
-                    if (first + k < g) start[first + k] = run;
-                    run += v[k];
-                }
-            }
-            __syncthreads();
-#pragma unroll
-            for (int r = 0; r < OB; ++r) {
-                if (base + r * kBlock + tid < r1) {
-                    const uint32_t p = start[id[r]] + slot[r];
-#pragma unroll
-                    for (int c = 0; c < NV; ++c) stage[p * NV + c] = rr[r].v[c];
-                }
-            }
-            __syncthreads();
-#pragma unroll
-            for (int j = 0; j < (int)(kOwnerMaxGroups / kBlock); ++j) {
-                const uint32_t gi = tid + j * kBlock;
-                if (gi < g) {
-                    const uint32_t b = start[gi], en = b + hist[gi];
-                    for (uint32_t k = b; k < en; ++k) {
-                        Row<NV> x;
-#pragma unroll
-                        for (int c = 0; c < NV; ++c) x.v[c] = stage[k * NV + c];
-                        acc_row(own[j], x);
-                    }
-                }
-            }
-            __syncthreads();
-            for (uint32_t i = tid; i < g; i += kBlock) hist[i] = 0;
-            __syncthreads();
-        }
-#pragma unroll
-        for (int j = 0; j < (int)(kOwnerMaxGroups / kBlock); ++j) {
-            const uint32_t gi = tid + j * kBlock;
-            if (gi < g && (!multi || own[j].cnt)) acc_flush(own[j], s, gb + gi, multi);
-        }
-        return;
-    }
     // case 2 (records in LDS) or case 3 (global atomics); few groups per
     // partition means colliding lanes, which are combined per wave first
     const bool few = g <= 2;
@@ -993,7 +898,7 @@ __device__ __forceinline__ void pgb_unit(const PgbArgs &a, uint32_t u, uint64_t 
 template <typename K, int NV>
 __global__ __launch_bounds__(kBlock) void k_pgb_aggregate(PgbArgs a) {
     extern __shared__ __align__(16) uint32_t s_dyn[];
-    __shared__ uint32_t s_unit[5 + kWaves];
+    __shared__ uint32_t s_unit[5];
     __shared__ uint32_t s_sent_id;
     const uint32_t n_units = min(*a.nunits, a.cap_units);
     const uint64_t out_base = a.out_base ? *a.out_base : 0ull;
@@ -1477,19 +1382,11 @@ int64_t groupby_partition(Ctx &ctx, int key_bytes, const void *key, const int32_
         lds = tab_bytes;
     }
     require(lds <= 150 * 1024, "partition group-by: too many groups per partition", GJ_EUNSUPPORTED);
-    // partitions of 3..1024 groups with at most 2 value columns use the owner path
-    if (n_vals <= 2 && maxg >= 3) {
-        const uint32_t og = std::min<uint32_t>(maxg, kOwnerMaxGroups), cap = 1u << log2cap;
-        const size_t ob = key_bytes == 4 ? owner_lds_bytes<int32_t>(cap, og, nv_tier(n_vals))
-                                         : owner_lds_bytes<int64_t>(cap, og, nv_tier(n_vals));
-        lds = maxg <= kOwnerMaxGroups ? ob : std::max(lds, ob);
-    }
     lds = std::max<size_t>(lds, (size_t)kWaves * 160 + 16);  // the one-group path keeps a per-wave total
     // outputs of partitions split over several units are folded with atomics
     if (max_units > 1 || !a.lds_records) init_outputs(st, a.spec, g);
     const double bytes = (double)n * (key_bytes + 4.0 * n_vals + (gfur ? 4.0 : 0.0)) +
                          (double)g * (key_bytes + 4.0 * a.spec.words);
-    a.lds_dyn = (uint32_t)lds;
 #define GJ_PGB(K, NV) GJ_LAUNCH("k_pgb_aggregate", bytes, (k_pgb_aggregate<K, NV>), dim3(units), dim3(kBlock), lds, st, a)
     const int nvt = nv_tier(n_vals);
     if (key_bytes == 4) {
@@ -1576,7 +1473,6 @@ void groupby_partition_segments(Ctx &ctx, int key_bytes, const void *key, const 
     a.cap_units = pl.cap_units;
     a.out_base = pl.out_base;
     a.lds_bytes = pl.lds_bytes;
-    a.lds_dyn = pl.lds_bytes;
     a.log2cap = 6;
     a.lds_records = 0;
     const uint32_t init_blocks = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((n + 255) / 256, 4096));

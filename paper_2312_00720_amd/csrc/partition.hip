@@ -27,9 +27,9 @@
 namespace gj {
 namespace {
 
-constexpr int kScatterBlock = 1024;  // default scatter shape: 1024 threads x 8 rows, 4 columns per load group
+constexpr int kScatterBlock = 1024;  // default scatter shape: 1024 threads x 8 rows, 2 columns per load group
 constexpr int kItems = 8;
-constexpr int kGroup = 4;
+constexpr int kGroup = 2;
 constexpr uint32_t kTile = kBlock * kItems;
 
 struct PassArgs {

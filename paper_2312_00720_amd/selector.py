@@ -85,7 +85,8 @@ def _inputs(w: dict):
 def run(w: dict, d, cls: int):
     if w["kind"] == "join":
         return gj.join(d["r_key"], d["r_pay"], d["s_key"], d["s_pay"], mat=CLASSES[cls])
-    aggs = [(0, "count")] + [(c, op) for c in range(w["nv"]) for op in ("sum", "max")]
+    # COUNT, then SUM of every value column and MAX of the first seven (16 aggregates at most)
+    aggs = [(0, "count")] + [(c, "sum") for c in range(w["nv"])] + [(c, "max") for c in range(min(w["nv"], 7))]
     algo = CLASSES[cls]
     return gj.groupby(d["key"], d["vals"], aggs, algo=algo, mat="gftr" if algo != "hash" else "auto")
 
