@@ -155,7 +155,7 @@ typedef struct {
                                              instance gets clamp(ceil(log2 |R_i|) - v, 0, 8) bits */
     int8_t bucket_shift[GJ_TUNE_CLASSES]; /* LDS hash buckets per build block: 2^(ceil(log2 rows) + shift),
                                              shift 0 or 1, capped at 4096 (rule: 0) */
-    int32_t scatter_variant;              /* partition scatter shape, 1..12 (rule: 0 = built-in) */
+    int32_t scatter_variant;              /* partition scatter shape, 1..13 (rule: 0 = built-in) */
 } gj_join_tuning;
 
 /*
@@ -209,7 +209,7 @@ int gj_plan_destroy(gj_plan *plan);
  * Autotuner for join plans: for each size class present in the batch, copies up
  * to 64 of its instances into a staging batch and times plan runs (graph
  * launches, median of `reps`) over the candidates part_log2 in {9, 10, 11, 12}
- * x bucket_shift in {0, 1}; then times the 12 scatter variants with the chosen
+ * x bucket_shift in {0, 1}; then times the 13 scatter variants with the chosen
  * table on the staging batch of the class with the most rows. Writes the best
  * table to *out. Allocates and synchronizes freely; results never change.
  */

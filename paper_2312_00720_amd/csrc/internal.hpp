@@ -190,7 +190,7 @@ void sort_run(Ctx &ctx, int key_bytes, const void *key_in, void *key_out, const 
 
 // Scatter tile shape for the calling thread: 0 = default (or GJ_SCATTER_SHAPE),
 // 1..kScatterVariants = a compiled (block, rows per thread, column group) shape.
-constexpr int kScatterVariants = 12;
+constexpr int kScatterVariants = 13;
 void set_scatter_variant(int v);
 
 // ---- groupby.hip ----------------------------------------------------------------------

@@ -321,8 +321,10 @@ __device__ __forceinline__ void scatter_tile(const PassArgs &a, const DigitFn &d
     __syncthreads();
 }
 
-template <typename K, int BLOCK, int ITEMS, int G>
-__global__ __launch_bounds__(BLOCK) void k_scatter(PassArgs a) {
+// MINW: minimum waves per SIMD the register allocation must allow (4 lets two
+// 512-thread workgroups share a compute unit).
+template <typename K, int BLOCK, int ITEMS, int G, int MINW>
+__global__ __launch_bounds__(BLOCK, MINW) void k_scatter(PassArgs a) {
     constexpr uint32_t TILE = BLOCK * ITEMS;
     __shared__ ScatterShared<BLOCK> S;
     __shared__ uint32_t s_buf[2][TILE];  // double buffer for 4-byte columns; 8-byte data spans both
@@ -381,7 +383,8 @@ struct Shape {
 };
 constexpr Shape kVariants[kScatterVariants] = {{256, 8, 4},  {512, 8, 4},  {1024, 8, 4}, {512, 4, 4},
                                                {1024, 4, 4}, {256, 16, 2}, {512, 8, 2},  {512, 16, 2},
-                                               {512, 16, 4}, {1024, 8, 2},  {1024, 16, 2}, {1024, 16, 1}};
+                                               {512, 16, 4}, {1024, 8, 2},  {1024, 16, 2}, {1024, 16, 1},
+                                               {512, 16, 1}};
 thread_local int g_variant = 0;
 Shape scatter_shape() {
     if (g_variant >= 1 && g_variant <= kScatterVariants) return kVariants[g_variant - 1];
@@ -400,12 +403,13 @@ template <typename K>
 void launch_scatter(const Shape &sh, dim3 grid, hipStream_t s, const PassArgs &a, double bytes) {
 #define GJ_SC(B, I, G_)                                                                    \
     if (sh.block == B && sh.items == I && sh.group == G_) {                                \
-        GJ_LAUNCH("k_scatter", bytes, (k_scatter<K, B, I, G_>), grid, dim3(B), 0, s, a);    \
+        GJ_LAUNCH("k_scatter", bytes, (k_scatter<K, B, I, G_, (B == 512 && I == 16 && G_ == 1) ? 4 : 1>), grid, \
+                  dim3(B), 0, s, a);                                                       \
         return;                                                                            \
     }
     GJ_SC(256, 8, 4) GJ_SC(512, 8, 4) GJ_SC(1024, 8, 4) GJ_SC(512, 4, 4) GJ_SC(1024, 4, 4)
     GJ_SC(256, 16, 2) GJ_SC(512, 8, 2) GJ_SC(512, 16, 2) GJ_SC(512, 16, 4) GJ_SC(1024, 8, 2)
-    GJ_SC(1024, 16, 2) GJ_SC(1024, 16, 1)
+    GJ_SC(1024, 16, 2) GJ_SC(1024, 16, 1) GJ_SC(512, 16, 1)
 #undef GJ_SC
     throw Error(GJ_EINVAL, "unknown scatter shape");
 }

@@ -265,7 +265,7 @@ void check_tuning(const gj_join_tuning *t) {
         require(t->part_log2[c] == 0 || (t->part_log2[c] >= 6 && t->part_log2[c] <= 12), "part_log2 must be 0 or 6..12");
         require(t->bucket_shift[c] == 0 || t->bucket_shift[c] == 1, "bucket_shift must be 0 or 1");
     }
-    require(t->scatter_variant >= 0 && t->scatter_variant <= gj::kScatterVariants, "scatter_variant must be 0..12");
+    require(t->scatter_variant >= 0 && t->scatter_variant <= gj::kScatterVariants, "scatter_variant must be 0..13");
 }
 
 void build_join_plan(gj_plan *P, const gj_rel_batch *R, const gj_rel_batch *S, const gj_join_opts *opts,
