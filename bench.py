@@ -71,6 +71,23 @@ def copy_ceiling(nbytes: int = 1 << 31, reps: int = 5) -> float:
 GB_AGGS = [(0, "count"), (0, "sum"), (0, "min"), (0, "max"), (1, "sum"), (1, "min"), (1, "max")]
 
 
+def measured_traffic(kernel: str, workload: str):
+    """HBM bytes per launch of `kernel` on `workload` from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE passes (profiles/traffic.json), or None when there is
+    no such measurement or the kernel's source has changed since it was taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    e = json.load(open(path)).get(f"{kernel}@{workload}")
+    if not e:
+        return None
+    src = os.path.join(ROOT, e["source"])
+    if not os.path.exists(src) or hashlib.sha256(open(src, "rb").read()).hexdigest() != e["sha256"]:
+        return None
+    return e["hbm_bytes_per_launch"]
+
+
 def timed(step, steps, warmup):
     """Warm up, then time `steps` calls with per-launch event profiling on."""
     import torch
@@ -124,6 +141,46 @@ def bench_groupby(args, copy_gbs) -> int:
                                f"({'uniform' if args.alpha == 0 else f'zipf {args.alpha}'}), 2 int32 values, "
                                f"COUNT+SUM+MIN+MAX, {args.algo}" + ("" if args.algo == "hash" else f" {mat.upper()}"),
                    "groups": groups},
+        "copy_ceiling_gbs": copy_gbs,
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": dk["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": dk["gbs"] / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(dom, f"groupby_{args.algo}_n{args.n_log2}_g{args.g_log2}")
+                     if args.alpha == 0 and mat in ("gftr", "auto") else None},
+        "kernels": {k: {"launches_per_step": v["launches"] / args.steps, "ms_per_step": v["ms_per_step"],
+                        "alg_gbs": v["gbs"]} for k, v in kern.items()},
+    }
+    print(json.dumps(res), flush=True)
+    return 0
+
+
+def bench_pipeline(args, copy_gbs) -> int:
+    """Join then group-by: R = 2^16 rows (keys a permutation, one int32 payload),
+    S = 2^26 foreign keys with one int32 payload; the join output is grouped on
+    its R payload (about 2^16 groups) with COUNT, SUM, MIN and MAX of the S payload."""
+    import torch
+    import datagen
+    import datagen.device as dd
+    import paper_2312_00720_amd as gj
+    n_r, n_s = 1 << 16, 1 << args.pipe_s_log2
+    d = dd.pk_fk_join(n_r, n_s, 1, 1, seed=datagen.seed_for(2, 900))
+    torch.cuda.synchronize()
+    aggs = [(0, "count"), (0, "sum"), (0, "min"), (0, "max")]
+
+    def step():
+        k, rp, sp = gj.join(d["r_key"], d["r_pay"], d["s_key"], d["s_pay"], mat=args.mat)
+        return gj.groupby(rp[0], [sp[0]], aggs, algo="auto")
+
+    ms, stats, out = timed(step, args.steps, args.warmup)
+    kern = kernel_table(stats, args.steps)
+    dom = next(iter(kern))
+    dk = kern[dom]
+    res = {
+        "metric": "join + group-by input rows/s", "value": n_s / (ms / 1e3), "unit": "rows/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+        "config": {"workload": f"PK-FK join |R|=2^16 |S|=2^{args.pipe_s_log2} (1+1 int32 payloads, {args.mat.upper()}) "
+                               "then group-by on the R payload, COUNT/SUM/MIN/MAX of the S payload, algorithm auto",
+                   "groups": int(out[0].numel())},
         "copy_ceiling_gbs": copy_gbs,
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": dk["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": dk["gbs"] / HBM_PEAK_GBS, "traffic": None},
@@ -236,7 +293,8 @@ def main() -> int:
     ap.add_argument("--alpha", type=float, default=0.0)
     ap.add_argument("--match-ratio", type=float, default=1.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default="join", choices=["join", "groupby", "batch"])
+    ap.add_argument("--workload", default="join", choices=["join", "groupby", "batch", "pipeline"])
+    ap.add_argument("--pipe-s-log2", type=int, default=26, help="pipeline: log2 |S|")
     ap.add_argument("--instances", type=int, default=4096, help="batch: join instances")
     ap.add_argument("--no-autotune", action="store_true", help="batch: built-in plan parameters")
     ap.add_argument("--n-log2", type=int, default=28, help="group-by rows")
@@ -266,6 +324,8 @@ def main() -> int:
         return bench_groupby(args, copy_gbs)
     if args.workload == "batch":
         return bench_batch(args, copy_gbs)
+    if args.workload == "pipeline":
+        return bench_pipeline(args, copy_gbs)
 
     n_r, n_s, c = 1 << args.r_log2, 1 << args.s_log2, args.payloads
     log(f"generating |R|=2^{args.r_log2} |S|=2^{args.s_log2} payloads={c} key_bytes={args.key_bytes}")
@@ -298,6 +358,8 @@ def main() -> int:
 
     ms = (t1 - t0) / args.steps * 1e3
     value = n_out / (ms / 1e3)
+    default_join = (args.r_log2, args.s_log2, c, args.key_bytes, args.alpha, args.match_ratio, args.mat) == \
+        (27, 28, 4, 4, 0.0, 1.0, "gftr")
     kern = {k: dict(v, ms_per_step=v["total_ms"] / args.steps,
                     gbs=(v["alg_bytes"] / (v["total_ms"] / 1e3) / 1e9) if v["total_ms"] > 0 else 0.0)
             for k, v in stats.items()}
@@ -335,7 +397,8 @@ def main() -> int:
         "hbm_gbs_whole_step": alg_total / (ms / 1e3) / 1e9,
         "copy_ceiling_gbs": copy_gbs,
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(dom, "join_default") if default_join else None,
                      "alg_bytes_per_launch": dk["alg_bytes"] / max(1, dk["launches"]),
                      "avg_launch_ms": dk["total_ms"] / max(1, dk["launches"])},
         "phases_ms": phases,
