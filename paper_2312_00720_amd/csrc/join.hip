@@ -120,6 +120,39 @@ struct JoinShared {
 
 // Build on the R block of unit u and probe it with the unit's S piece: count
 // (WRITE = false) or write (WRITE = true) the matches.
+// Probes of PB keys against the LDS table, shaped so that the PB lookups are
+// independent: bucket bounds, then the first entry of every chain, read for all
+// rows at once (clamped indices, so every read is in range); chains longer than
+// one entry, rare with at least as many buckets as rows, are walked afterwards.
+// c[r] = matches of key r, e1[r] = its first match's entry (bucket order).
+template <typename K, int PB>
+__device__ __forceinline__ void probe_rows(const K *s_rkey, const uint32_t *s_b, const K (&key)[PB],
+                                           const bool (&valid)[PB], int skip_bits, int log2nb, uint32_t rn,
+                                           uint32_t (&c)[PB], uint32_t (&e1)[PB]) {
+    uint32_t lo[PB], hi[PB];
+#pragma unroll
+    for (int r = 0; r < PB; ++r) {
+        const uint32_t b = bucket_of<K>(key[r], skip_bits, log2nb);
+        lo[r] = s_b[b];
+        hi[r] = valid[r] ? s_b[b + 1] : lo[r];
+    }
+#pragma unroll
+    for (int r = 0; r < PB; ++r) {
+        const K k0 = s_rkey[min(lo[r], rn - 1)];
+        c[r] = (lo[r] < hi[r] && k0 == key[r]) ? 1u : 0u;
+        e1[r] = lo[r];
+    }
+#pragma unroll
+    for (int r = 0; r < PB; ++r) {
+        for (uint32_t e = lo[r] + 1; e < hi[r]; ++e) {
+            if (s_rkey[e] == key[r]) {
+                if (c[r] == 0) e1[r] = e;
+                ++c[r];
+            }
+        }
+    }
+}
+
 template <typename K, bool WRITE>
 __device__ __forceinline__ void join_unit(const JoinArgs &a, uint32_t u, uint64_t out_base, JoinShared<K> &sh) {
     constexpr int PB = 16;
@@ -270,21 +303,18 @@ __device__ __forceinline__ void join_unit(const JoinArgs &a, uint32_t u, uint64_
                 const uint32_t i = base + r * kWave + lane;
                 key[r] = i < we ? skey[s0 + i] : K(0);
             }
+            bool valid[PB];
+#pragma unroll
+            for (int r = 0; r < PB; ++r) valid[r] = base + r * kWave + lane < we;
+            uint32_t c[PB], e1[PB];
+            probe_rows<K, PB>(s_rkey, s_b, key, valid, skip_bits, log2nb, rn, c, e1);
 #pragma unroll
             for (int r = 0; r < PB; ++r) {
                 const uint32_t i = base + r * kWave + lane;
-                if (i < we) {
-                    const uint32_t b = bucket_of<K>(key[r], skip_bits, log2nb);
-                    uint32_t c = 0, e1 = 0;
-                    for (uint32_t e = s_b[b], end = s_b[b + 1]; e < end; ++e) {
-                        if (s_rkey[e] == key[r]) {
-                            if (c == 0) e1 = s_entry[e];
-                            ++c;
-                        }
-                    }
-                    cnt += c;
-                    multi |= c > 1;
-                    if (a.midx) a.midx[s0 + i] = c ? (int32_t)(r0 + e1) : -1;
+                if (valid[r]) {
+                    cnt += c[r];
+                    multi |= c[r] > 1;
+                    if (a.midx) a.midx[s0 + i] = c[r] ? (int32_t)(r0 + s_entry[e1[r]]) : -1;
                 }
             }
         }
@@ -302,20 +332,12 @@ __device__ __forceinline__ void join_unit(const JoinArgs &a, uint32_t u, uint64_
                 const uint32_t i = base + r * kWave + lane;
                 key[r] = i < we ? skey[s0 + i] : K(0);
             }
+            bool valid[PB];
 #pragma unroll
-            for (int r = 0; r < PB; ++r) {
-                c[r] = 0;
-                e1[r] = 0;
-                if (base + r * kWave + lane < we) {
-                    const uint32_t b = bucket_of<K>(key[r], skip_bits, log2nb);
-                    for (uint32_t e = s_b[b], end = s_b[b + 1]; e < end; ++e) {
-                        if (s_rkey[e] == key[r]) {
-                            if (c[r] == 0) e1[r] = s_entry[e];
-                            ++c[r];
-                        }
-                    }
-                }
-            }
+            for (int r = 0; r < PB; ++r) valid[r] = base + r * kWave + lane < we;
+            probe_rows<K, PB>(s_rkey, s_b, key, valid, skip_bits, log2nb, rn, c, e1);
+#pragma unroll
+            for (int r = 0; r < PB; ++r) e1[r] = c[r] ? (uint32_t)s_entry[e1[r]] : 0u;
             uint64_t pos[PB];
             bool multi = false;
 #pragma unroll
