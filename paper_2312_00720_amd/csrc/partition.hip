@@ -321,157 +321,6 @@ __device__ __forceinline__ void scatter_tile(const PassArgs &a, const DigitFn &d
     __syncthreads();
 }
 
-// Scatter for the common layout (a key and NC = 1..4 four-byte columns, no 8-byte
-// column), 1024 threads x 8 rows. Every global load and store of a tile is
-// unconditional (rows past the tile end read the last row; output slots past it
-// repeat slot 0, the same value to the same row) and the column count is a
-// compile-time constant, so the compiler counts outstanding memory operations
-// exactly: using a loaded value never waits for stores issued after that load.
-// (On this GPU one in-order counter tracks loads and stores; an inexact count
-// makes every use of a loaded value wait for all earlier stores.) Order per tile:
-// rank with the keys prefetched during the previous tile, then issue the column
-// loads, stage the keys through LDS and prefetch the next tile's keys, write the
-// keys, then each column through LDS.
-template <typename K, int NC>
-__global__ __launch_bounds__(1024) void k_scatter_nc(PassArgs a) {
-    constexpr int BLOCK = 1024, ITEMS = 8, W = BLOCK / kWave;
-    constexpr uint32_t TILE = BLOCK * ITEMS;
-    __shared__ ScatterShared<BLOCK> S;
-    __shared__ uint32_t s_buf[2][TILE];
-    __shared__ ChunkLoc s_loc;
-    const int tid = threadIdx.x, w = tid / kWave, lane = lane_id();
-    if (tid == 0) s_loc = locate_chunk(a, blockIdx.x);
-    __syncthreads();
-    const ChunkLoc L = s_loc;
-    if (!L.ok || L.row1 <= L.row0) return;
-    const uint32_t R = 1u << a.bits;
-    const uint32_t base_off = a.seg_off[0];
-    for (uint32_t d = tid; d < kRadix; d += BLOCK) S.cur[d] = d < R ? base_off + a.hist[L.hbase + d * L.m + L.j] : 0u;
-    const DigitFn dig = seg_digit(a, L.seg);
-    const K *__restrict__ keys = static_cast<const K *>(a.key_in);
-    K *__restrict__ kout = static_cast<K *>(a.key_out);
-    K *sk = reinterpret_cast<K *>(&s_buf[0][0]);
-    const uint32_t lbase = (uint32_t)(w * kWave * ITEMS + lane);
-    const uint32_t *cin[NC];
-    uint32_t *cout[NC];
-    uint32_t keep[NC];  // all ones for a loaded column, zero for the generated row id
-#pragma unroll
-    for (int g = 0; g < NC; ++g) {
-        const bool gen = (g == a.rowid_col);
-        keep[g] = gen ? 0u : ~0u;
-        cin[g] = gen ? reinterpret_cast<const uint32_t *>(a.key_in) : static_cast<const uint32_t *>(a.col_in[g]);
-        cout[g] = static_cast<uint32_t *>(a.col_out[g]);
-    }
-
-    uint32_t tile0 = L.row0, nt = min(TILE, L.row1 - tile0);
-    K key[ITEMS];
-#pragma unroll
-    for (int r = 0; r < ITEMS; ++r) key[r] = keys[tile0 + min(lbase + r * kWave, nt - 1)];
-    while (true) {
-        for (int i = tid; i < W * kRadix; i += BLOCK) (&S.wcnt[0][0])[i] = 0;
-        __syncthreads();
-        uint32_t pos[ITEMS];
-#pragma unroll
-        for (int r = 0; r < ITEMS; ++r) {
-            const bool valid = lbase + r * kWave < nt;
-            const uint32_t d = digit_of<K>(key[r], dig);
-            const uint64_t peers = match_peers(d, a.bits, valid);
-            uint32_t p = 0;
-            if (valid) {
-                const uint32_t rk = rank_below(peers);
-                const uint32_t b = S.wcnt[w][d];
-                if (rk == 0) S.wcnt[w][d] = b + (uint32_t)__popcll(peers);
-                p = b + rk;
-            }
-            pos[r] = p;
-        }
-        // the tile's column loads go out now; the scan and key phases cover them
-        uint32_t v[NC][ITEMS];
-#pragma unroll
-        for (int g = 0; g < NC; ++g) {
-#pragma unroll
-            for (int r = 0; r < ITEMS; ++r) {
-                const uint32_t row = tile0 + min(lbase + r * kWave, nt - 1);
-                const uint32_t x = cin[g][row];
-                // a blend, not a branch: a generated column still issues (and ignores) its load
-                v[g][r] = (x & keep[g]) | ((tile0 + lbase + r * kWave) & ~keep[g]);
-            }
-        }
-        __syncthreads();
-        if (tid < kRadix) {
-            uint32_t t = 0;
-#pragma unroll
-            for (int q = 0; q < W; ++q) {
-                const uint32_t c = S.wcnt[q][tid];
-                S.wcnt[q][tid] = t;
-                t += c;
-            }
-            S.tot[tid] = t;
-            const uint32_t inc = wave_inclusive_sum<uint32_t>(t);
-            if (lane == kWave - 1) S.tmp[w] = inc;
-            S.start[tid] = inc - t;
-        }
-        __syncthreads();
-        if (tid < kRadix) {
-            uint32_t before = 0;
-#pragma unroll
-            for (int q = 0; q < kWaves; ++q) before += (q < w) ? S.tmp[q] : 0u;
-            S.start[tid] += before;
-        }
-        __syncthreads();
-#pragma unroll
-        for (int r = 0; r < ITEMS; ++r) {
-            if (lbase + r * kWave < nt) {
-                const uint32_t d = digit_of<K>(key[r], dig);
-                pos[r] += S.start[d] + S.wcnt[w][d];
-                sk[pos[r]] = key[r];
-            }
-        }
-        // next tile's keys (the last tile reloads its own: the same operations every tile)
-        const uint32_t next0 = tile0 + nt;
-        const bool more = next0 < L.row1;
-        const uint32_t n0 = more ? next0 : tile0, nn = more ? min(TILE, L.row1 - next0) : nt;
-#pragma unroll
-        for (int r = 0; r < ITEMS; ++r) key[r] = keys[n0 + min(lbase + r * kWave, nn - 1)];
-        __syncthreads();
-        uint32_t dst[ITEMS];
-#pragma unroll
-        for (int k = 0; k < ITEMS; ++k) {
-            const uint32_t i0 = (uint32_t)(k * BLOCK + tid);
-            const uint32_t i = i0 < nt ? i0 : 0u;
-            const K kk = sk[i];
-            const uint32_t d = digit_of<K>(kk, dig);
-            dst[k] = min(S.cur[d] + i - S.start[d], a.n_rows - 1);  // in range when the offsets are right
-            kout[dst[k]] = kk;
-        }
-        int par = 1;
-        if constexpr (sizeof(K) == 8) {
-            __syncthreads();
-            par = 0;
-        }
-#pragma unroll
-        for (int g = 0; g < NC; ++g) {
-            uint32_t *sb = s_buf[par];
-#pragma unroll
-            for (int r = 0; r < ITEMS; ++r)
-                if (lbase + r * kWave < nt) sb[pos[r]] = v[g][r];
-            __syncthreads();
-#pragma unroll
-            for (int k = 0; k < ITEMS; ++k) {
-                const uint32_t i0 = (uint32_t)(k * BLOCK + tid);
-                cout[g][dst[k]] = sb[i0 < nt ? i0 : 0u];
-            }
-            par ^= 1;
-        }
-        __syncthreads();
-        if (tid < kRadix) S.cur[tid] += S.tot[tid];
-        __syncthreads();
-        if (!more) break;
-        tile0 = next0;
-        nt = nn;
-    }
-}
-
 // MINW: minimum waves per SIMD the register allocation must allow (4 lets two
 // 512-thread workgroups share a compute unit).
 template <typename K, int BLOCK, int ITEMS, int G, int MINW>
@@ -552,16 +401,6 @@ Shape scatter_shape() {
 
 template <typename K>
 void launch_scatter(const Shape &sh, dim3 grid, hipStream_t s, const PassArgs &a, double bytes) {
-    // the common layout: key plus 1..4 four-byte columns, default shape
-    if (sh.block == kScatterBlock && sh.items == kItems && sh.group == kGroup && a.ncols == a.n4 && a.n4 >= 1 &&
-        a.n4 <= 4 && !g_variant) {
-        switch (a.n4) {
-            case 1: GJ_LAUNCH("k_scatter", bytes, (k_scatter_nc<K, 1>), grid, dim3(1024), 0, s, a); return;
-            case 2: GJ_LAUNCH("k_scatter", bytes, (k_scatter_nc<K, 2>), grid, dim3(1024), 0, s, a); return;
-            case 3: GJ_LAUNCH("k_scatter", bytes, (k_scatter_nc<K, 3>), grid, dim3(1024), 0, s, a); return;
-            default: GJ_LAUNCH("k_scatter", bytes, (k_scatter_nc<K, 4>), grid, dim3(1024), 0, s, a); return;
-        }
-    }
 #define GJ_SC(B, I, G_)                                                                    \
     if (sh.block == B && sh.items == I && sh.group == G_) {                                \
         GJ_LAUNCH("k_scatter", bytes, (k_scatter<K, B, I, G_, (B == 512 && I == 16 && G_ == 1) ? 4 : 1>), grid, \
