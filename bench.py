@@ -294,6 +294,7 @@ def main() -> int:
     ap.add_argument("--match-ratio", type=float, default=1.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--radix-bits", type=int, default=0, help="join: partition bits (0 = automatic)")
+    ap.add_argument("--lds-budget", type=int, default=0, help="join: max R rows per build block (0 = automatic)")
     ap.add_argument("--workload", default="join", choices=["join", "groupby", "batch", "pipeline"])
     ap.add_argument("--pipe-s-log2", type=int, default=26, help="pipeline: log2 |S|")
     ap.add_argument("--instances", type=int, default=4096, help="batch: join instances")
@@ -336,7 +337,7 @@ def main() -> int:
     rk, rp, sk, sp = d["r_key"], d["r_pay"], d["s_key"], d["s_pay"]
 
     def step():
-        return gj.join(rk, rp, sk, sp, mat=args.mat, radix_bits=args.radix_bits)
+        return gj.join(rk, rp, sk, sp, mat=args.mat, radix_bits=args.radix_bits, lds_budget=args.lds_budget)
 
     n_out = None
     for i in range(args.warmup):
@@ -360,7 +361,7 @@ def main() -> int:
     ms = (t1 - t0) / args.steps * 1e3
     value = n_out / (ms / 1e3)
     default_join = (args.r_log2, args.s_log2, c, args.key_bytes, args.alpha, args.match_ratio, args.mat,
-                    args.radix_bits) == (27, 28, 4, 4, 0.0, 1.0, "gftr", 0)
+                    args.radix_bits, args.lds_budget) == (27, 28, 4, 4, 0.0, 1.0, "gftr", 0, 0)
     kern = {k: dict(v, ms_per_step=v["total_ms"] / args.steps,
                     gbs=(v["alg_bytes"] / (v["total_ms"] / 1e3) / 1e9) if v["total_ms"] > 0 else 0.0)
             for k, v in stats.items()}

@@ -76,7 +76,9 @@ typedef struct {
     int32_t passes;            /* 1 or 2 (each pass uses at most 8 bits) */
     int32_t block_size;        /* reserved; must be 0 or 256 */
     float ht_occupancy;        /* reserved */
-    int32_t lds_budget;        /* max R rows per build block, 64..4096 */
+    int32_t lds_budget;        /* max R rows per build block, 64..16384 (8-byte keys: 64..8192);
+                                  0: 8192 when |R| >= 2^24, else 4096; the LDS table
+                                  has 4096, 8192 or 16384 rows, the smallest that holds it */
     uint64_t flags;            /* reserved, must be 0 */
 } gj_join_opts;
 
@@ -100,6 +102,7 @@ typedef struct {
  * R and S keys must share a dtype (GJ_I32 or GJ_I64); payload columns may be
  * GJ_I32 or GJ_I64. Output row order is unspecified but deterministic for a
  * given input and options. Empty inputs give n_rows = 0 and NULL columns.
+ * Default radix_bits: partitions of about lds_budget / 2 R rows (at least 1 bit).
  * Synchronizes with `stream` twice (unit count and output size).
  */
 int gj_join(const gj_rel *R, const gj_rel *S, const gj_join_opts *opts,

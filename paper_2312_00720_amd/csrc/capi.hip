@@ -111,7 +111,7 @@ int gj_join(const gj_rel *R, const gj_rel *S, const gj_join_opts *opts, const gj
         gj::require(o.passes >= 0 && o.passes <= 2, "passes must be 0, 1 or 2");
         gj::require(o.radix_bits >= 0 && o.radix_bits <= 16, "radix_bits must be 0..16");
         gj::require(o.block_size == 0 || o.block_size == gj::kBlock, "block_size must be 0 or 256");
-        gj::require(o.lds_budget == 0 || (o.lds_budget >= 64 && o.lds_budget <= 4096), "lds_budget must be 64..4096");
+        gj::check_join_lds_budget(o.lds_budget, dtype_bytes(R->key.dtype));
         gj::require(o.flags == 0, "flags must be 0");
 
         out->n_rows = 0;
@@ -128,14 +128,8 @@ int gj_join(const gj_rel *R, const gj_rel *S, const gj_join_opts *opts, const gj
             mat = gj::select_algorithm(f, 0, nullptr) == 1 ? GJ_MAT_GFUR : GJ_MAT_GFTR;
         }
         const bool gfur = (mat == GJ_MAT_GFUR);
-        const int r_block = o.lds_budget ? o.lds_budget : 4096;
-        // Partitions of about r_block/2 R rows on average leave room for variance.
-        int bits = o.radix_bits;
-        if (bits == 0) {
-            const uint64_t target = (uint64_t)std::max(1, r_block / 2);
-            bits = ceil_log2(((uint64_t)R->n_rows + target - 1) / target);
-            bits = std::min(16, std::max(1, bits));
-        }
+        const int r_block = o.lds_budget ? o.lds_budget : gj::join_default_r_block((uint64_t)R->n_rows);
+        const int bits = o.radix_bits ? o.radix_bits : gj::join_default_bits((uint64_t)R->n_rows, r_block);
         int passes = o.passes ? o.passes : (bits > 8 ? 2 : 1);
         gj::require(bits <= 8 * passes, "at most 8 bits per pass");
         if (passes == 2 && bits < 2) passes = 1;
@@ -219,7 +213,7 @@ int gj_join_batch(const gj_rel_batch *R, const gj_rel_batch *S, const gj_join_op
         gj_join_opts o{};
         if (opts) o = *opts;
         gj::require(o.mat >= 0 && o.mat <= 2, "bad materialization");
-        gj::require(o.lds_budget == 0 || (o.lds_budget >= 64 && o.lds_budget <= 4096), "lds_budget must be 64..4096");
+        gj::check_join_lds_budget(o.lds_budget, dtype_bytes(R->key.dtype));
         gj::require(o.flags == 0, "flags must be 0");
         out->n_rows = 0;
         out->key = nullptr;

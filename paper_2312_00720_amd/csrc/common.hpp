@@ -91,9 +91,9 @@ __device__ __forceinline__ T wave_sum(T v) {
     return v;
 }
 
-// Exclusive prefix sum over a workgroup of kBlock threads. `s_tmp` holds
-// kWaves values; returns the exclusive prefix and writes the total to *total.
-template <typename T>
+// Exclusive prefix sum over a workgroup of W waves (kBlock threads by default).
+// `s_tmp` holds W values; returns the exclusive prefix and writes the total to *total.
+template <typename T, int W = kWaves>
 __device__ __forceinline__ T block_exclusive_sum(T v, T *s_tmp, T *total) {
     const int w = threadIdx.x / kWave, lane = lane_id();
     T inc = wave_inclusive_sum(v);
@@ -101,7 +101,7 @@ __device__ __forceinline__ T block_exclusive_sum(T v, T *s_tmp, T *total) {
     __syncthreads();
     T before = 0, all = 0;
 #pragma unroll
-    for (int i = 0; i < kWaves; ++i) {
+    for (int i = 0; i < W; ++i) {
         T x = s_tmp[i];
         if (i < w) before += x;
         all += x;

@@ -190,7 +190,7 @@ void sort_run(Ctx &ctx, int key_bytes, const void *key_in, void *key_out, const 
 
 // Scatter tile shape for the calling thread: 0 = default (or GJ_SCATTER_SHAPE),
 // 1..kScatterVariants = a compiled (block, rows per thread, column group) shape.
-constexpr int kScatterVariants = 13;
+constexpr int kScatterVariants = 14;
 void set_scatter_variant(int v);
 
 // ---- groupby.hip ----------------------------------------------------------------------
@@ -235,8 +235,32 @@ void features_join(float *f, double nr, double ns, int key_bytes, int cr, int cs
 void features_groupby(float *f, double n, int key_bytes, int nv, double g_est = 0.0);
 
 // ---- join.hip -------------------------------------------------------------------------
-constexpr uint32_t kJoinMaxBuild = 4096;  // R rows per LDS build block
-constexpr uint32_t kJoinSPiece = 8192;    // S rows per work unit
+// Work-unit geometry. An R build block of at most r_block rows runs in one of
+// three kernel shapes, 4096, 8192 or 16384 table rows (16 rows per thread), and
+// a work unit probes an S piece of twice the table rows. 8-byte keys stop at 8192
+// (their 16384-row table would not fit in one compute unit's LDS).
+constexpr uint32_t kJoinMaxBuild = 16384;
+inline uint32_t join_table_rows(int r_block) { return r_block <= 4096 ? 4096u : r_block <= 8192 ? 8192u : 16384u; }
+inline uint32_t join_s_piece(int r_block) { return 2u * join_table_rows(r_block); }
+inline int join_max_r_block(int key_bytes) { return key_bytes == 4 ? 16384 : 8192; }
+inline void check_join_lds_budget(int lds_budget, int key_bytes) {
+    require(lds_budget == 0 || (lds_budget >= 64 && lds_budget <= join_max_r_block(key_bytes)),
+            key_bytes == 8 ? "lds_budget must be 64..8192 for 8-byte keys" : "lds_budget must be 64..16384");
+}
+// Default R build block and partition bits of a single join: partitions of
+// about r_block / 2 rows leave room for variance. R relations of 2^24 rows and
+// more use 8192-row blocks (partitions of about 4096 rows): one partition bit
+// fewer than with 4096 (longer scatter runs, half the work units), while the
+// write pass's gathers from an R partition still hit L2. Larger partitions
+// (16384-row blocks) make the scatter faster still but the gathers slower.
+inline int join_default_r_block(uint64_t n_r) { return n_r >= (1ull << 24) ? 8192 : 4096; }
+inline int join_default_bits(uint64_t n_r, int r_block) {
+    const uint64_t target = (uint64_t)(r_block / 2 > 1 ? r_block / 2 : 1);
+    const uint64_t parts = (n_r + target - 1) / target;
+    int b = 0;
+    while ((1ull << b) < parts) ++b;
+    return b < 1 ? 1 : (b > 16 ? 16 : b);
+}
 
 struct JoinSide {
     const void *key;          // partitioned keys

@@ -3,10 +3,11 @@
 //
 // After partitioning, partition p of R and of S are contiguous ranges. Work
 // units cut a partition pair into (R block of at most r_block rows) x (S piece
-// of at most kSPiece rows), so that an oversized or skewed partition is spread
+// of at most 2 x table rows), so that an oversized or skewed partition is spread
 // over many workgroups (the load balancing of Sections 3.1.2 and 4.1.4). Per
 // unit, a workgroup builds a bucketed hash table on the R block in LDS and
-// streams the S piece through it.
+// streams the S piece through it. The table has 4096, 8192 or 16384 rows (the
+// smallest that holds r_block) and the workgroup 16 table rows per thread.
 //
 // The output size is unknown (Section 2.2), so a count pass runs first: every
 // wave counts its matches; an exclusive scan over (unit, wave) gives every wave
@@ -23,10 +24,29 @@
 namespace gj {
 namespace {
 
-constexpr uint32_t kMaxBuild = kJoinMaxBuild;  // R rows per build block (LDS capacity)
-constexpr uint32_t kSPiece = kJoinSPiece;      // S rows per work unit
 constexpr uint32_t kMaxChainSort = 32;
 constexpr uint32_t kPersistentGrid = 4096;  // workgroups of a plan's count and write passes
+
+// Shape of a work unit for a table of BUILD rows: threads, waves, S piece rows,
+// bucket-count limit (12 bits up to 8192 rows, 13 for 16384, so that a table
+// filled to half its rows has as many buckets as keys) and probe rounds in
+// flight per lane (the larger shapes have at most 128 registers per lane).
+template <uint32_t BUILD>
+struct Geo {
+    static constexpr uint32_t kBuild = BUILD;
+    static constexpr int kThreads = (int)(BUILD / 16);
+    static constexpr int kWv = kThreads / kWave;
+    static constexpr uint32_t kSPiece = 2 * BUILD;
+    static constexpr int kMaxLog2nb = BUILD >= 16384 ? 13 : 12;
+    static constexpr uint32_t kMaxNb = 1u << kMaxLog2nb;
+    static constexpr int kPB = 16;                    // count pass
+    static constexpr int kPBWrite = BUILD == 4096 ? 16 : 8;  // LDS write pass
+    // waves per SIMD the register allocation must allow: the persistent
+    // kernels and the one-unit-per-workgroup kernels (two 512-thread
+    // workgroups per compute unit)
+    static constexpr int kMinW = BUILD == 4096 ? 3 : 4;
+    static constexpr int kMinWEager = BUILD == 4096 ? 1 : 4;
+};
 
 struct JoinArgs {
     const void *rkey;
@@ -35,7 +55,7 @@ struct JoinArgs {
     const uint32_t *spo;
     uint32_t np;
     const uint32_t *ubase;  // exclusive prefix of units per partition
-    uint32_t rc;            // R rows per build block
+    uint32_t rc;            // R rows per build block (at most the table rows)
     int skip_bits;          // partition bits, excluded from the bucket hash
     uint64_t *wcnt;         // count pass: matches per (unit, wave)
     const uint64_t *woff;   // write pass: output offset per (unit, wave)
@@ -52,7 +72,7 @@ struct JoinArgs {
     const int32_t *srow;  // GFUR: partitioned row ids of S
     const uint8_t *seg_bits;  // batches: partition bits of instance p >> 8 (skip_bits unused)
     const uint8_t *seg_bshift;  // batches: extra LDS bucket bits of instance p >> 8 (else bshift)
-    int bshift;                 // LDS buckets = 2^(ceil(log2 rows) + bshift), at most kMaxBuild
+    int bshift;                 // LDS buckets = 2^(ceil(log2 rows) + bshift), within the table's limit
     const uint32_t *nunits;     // device: work units (the kernels loop over them)
     uint32_t cap_units;         // units beyond this are not processed (a plan's capacity)
     const uint64_t *out_base;   // device: first output row of this call (nullptr = 0)
@@ -65,10 +85,11 @@ struct JoinArgs {
 };
 
 __global__ void k_unit_count(const uint32_t *__restrict__ rpo, const uint32_t *__restrict__ spo,
-                             uint32_t np, uint32_t rc, uint32_t *__restrict__ ucnt, uint32_t *__restrict__ flags) {
+                             uint32_t np, uint32_t rc, uint32_t spiece, uint32_t *__restrict__ ucnt,
+                             uint32_t *__restrict__ flags) {
     for (uint32_t p = blockIdx.x * blockDim.x + threadIdx.x; p < np; p += gridDim.x * blockDim.x) {
         const uint32_t nr = rpo[p + 1] - rpo[p], ns = spo[p + 1] - spo[p];
-        ucnt[p] = (nr && ns) ? ceil_div_u32(nr, rc) * ceil_div_u32(ns, kSPiece) : 0u;
+        ucnt[p] = (nr && ns) ? ceil_div_u32(nr, rc) * ceil_div_u32(ns, spiece) : 0u;
         if (nr > rc && ns) atomicOr(&flags[0], 1u);  // a partition spans several R blocks
     }
 }
@@ -108,12 +129,13 @@ __device__ __forceinline__ void gather_cols(int ncols, const void *const *src, c
     }
 }
 
-template <typename K>
+template <typename K, uint32_t BUILD>
 struct JoinShared {
-    K rkey[kMaxBuild];          // R block keys: input order while building, bucket order after
-    uint32_t b[kMaxBuild + 1];   // bucket boundaries
-    uint16_t entry[kMaxBuild];  // R block rows, grouped by bucket
-    uint32_t tmp[kWaves];
+    using G = Geo<BUILD>;
+    K rkey[BUILD];               // R block keys: input order while building, bucket order after
+    uint32_t b[G::kMaxNb + 1];   // bucket boundaries
+    uint16_t entry[BUILD];       // R block rows, grouped by bucket
+    uint32_t tmp[G::kWv];
     uint32_t unit[6];
     int is_long;
 };
@@ -153,16 +175,19 @@ __device__ __forceinline__ void probe_rows(const K *s_rkey, const uint32_t *s_b,
     }
 }
 
-template <typename K, bool WRITE>
-__device__ __forceinline__ void join_unit(const JoinArgs &a, uint32_t u, uint64_t out_base, JoinShared<K> &sh) {
-    constexpr int PB = 16;
+template <typename K, uint32_t BUILD, bool WRITE>
+__device__ __forceinline__ void join_unit(const JoinArgs &a, uint32_t u, uint64_t out_base, JoinShared<K, BUILD> &sh) {
+    using G = Geo<BUILD>;
+    constexpr int PB = WRITE ? G::kPBWrite : G::kPB;
+    constexpr int kBlockT = G::kThreads;
+    constexpr int kWv = G::kWv;
+    constexpr uint32_t kSPiece = G::kSPiece;
     K *s_rkey = sh.rkey;
     uint32_t *s_b = sh.b;
     uint16_t *s_entry = sh.entry;
     uint32_t *s_tmp = sh.tmp;
     uint32_t *s_unit = sh.unit;
     int &s_long = sh.is_long;
-    static_assert(kMaxBuild == 4096, "bucket bits are capped at 12");
     const int tid = threadIdx.x, w = tid / kWave, lane = lane_id();
     if (tid == 0) {
         uint32_t lo = 0, hi = a.np;  // ubase[lo] <= u < ubase[hi] (ubase[np] = units)
@@ -189,19 +214,19 @@ __device__ __forceinline__ void join_unit(const JoinArgs &a, uint32_t u, uint64_
     const int skip_bits = (int)s_unit[4];
     int log2nb = 0;
     while ((1u << log2nb) < rn) ++log2nb;
-    log2nb = min(log2nb + (int)s_unit[5], 12);
+    log2nb = min(log2nb + (int)s_unit[5], G::kMaxLog2nb);
     const uint32_t nb = 1u << log2nb;
 
     // ---- build: bucket counts, scan, placement, per-bucket order by row ----
     const K *__restrict__ rkey = static_cast<const K *>(a.rkey);
-    for (uint32_t i = tid; i < rn; i += kBlock) s_rkey[i] = rkey[r0 + i];
-    for (uint32_t b = tid; b <= nb; b += kBlock) s_b[b] = 0;
+    for (uint32_t i = tid; i < rn; i += kBlockT) s_rkey[i] = rkey[r0 + i];
+    for (uint32_t b = tid; b <= nb; b += kBlockT) s_b[b] = 0;
     __syncthreads();
-    for (uint32_t i = tid; i < rn; i += kBlock) atomicAdd(&s_b[bucket_of<K>(s_rkey[i], skip_bits, log2nb)], 1u);
+    for (uint32_t i = tid; i < rn; i += kBlockT) atomicAdd(&s_b[bucket_of<K>(s_rkey[i], skip_bits, log2nb)], 1u);
     __syncthreads();
     {
         // inclusive scan of the nb counts: s_b[b] = end of bucket b
-        constexpr int per = (kMaxBuild + kBlock - 1) / kBlock;
+        constexpr int per = (int)((G::kMaxNb + kBlockT - 1) / kBlockT);
         const uint32_t first = tid * per;
         uint32_t v[per];
         uint32_t sum = 0;
@@ -210,7 +235,7 @@ __device__ __forceinline__ void join_unit(const JoinArgs &a, uint32_t u, uint64_
             v[k] = (first + k < nb) ? s_b[first + k] : 0u;
             sum += v[k];
         }
-        uint32_t run = block_exclusive_sum<uint32_t>(sum, s_tmp, (uint32_t *)nullptr);
+        uint32_t run = block_exclusive_sum<uint32_t, kWv>(sum, s_tmp, (uint32_t *)nullptr);
 #pragma unroll
         for (int k = 0; k < per; ++k) {
             run += v[k];
@@ -220,13 +245,13 @@ __device__ __forceinline__ void join_unit(const JoinArgs &a, uint32_t u, uint64_
     }
     __syncthreads();
     // placement from the end of each bucket; afterwards s_b[b] = start of bucket b
-    for (uint32_t i = tid; i < rn; i += kBlock) {
+    for (uint32_t i = tid; i < rn; i += kBlockT) {
         const uint32_t b = bucket_of<K>(s_rkey[i], skip_bits, log2nb);
         const uint32_t slot = atomicSub(&s_b[b], 1u) - 1u;
         s_entry[slot] = (uint16_t)i;
     }
     __syncthreads();
-    for (uint32_t b = tid; b < nb; b += kBlock) {
+    for (uint32_t b = tid; b < nb; b += kBlockT) {
         const uint32_t lo = s_b[b], hi = s_b[b + 1];
         if (hi - lo > kMaxChainSort) {
             s_long = 1;
@@ -272,26 +297,26 @@ __device__ __forceinline__ void join_unit(const JoinArgs &a, uint32_t u, uint64_
     {
         // keys in bucket order (s_rkey[e] = key of entry e), so that a probe
         // compares keys without going through the row index
-        constexpr int per = (int)(kMaxBuild / kBlock);
+        constexpr int per = (int)(BUILD / kBlockT);
         K t[per];
 #pragma unroll
         for (int k = 0; k < per; ++k) {
-            const uint32_t e = tid + k * kBlock;
+            const uint32_t e = tid + k * kBlockT;
             t[k] = e < rn ? s_rkey[s_entry[e]] : K(0);
         }
         __syncthreads();
 #pragma unroll
         for (int k = 0; k < per; ++k) {
-            const uint32_t e = tid + k * kBlock;
+            const uint32_t e = tid + k * kBlockT;
             if (e < rn) s_rkey[e] = t[k];
         }
         __syncthreads();
     }
 
-    // ---- probe: each wave streams a contiguous quarter of the S piece, PB
+    // ---- probe: each wave streams a contiguous share of the S piece, PB
     // rounds of 64 rows at a time so that many loads are in flight ----
     const K *__restrict__ skey = static_cast<const K *>(a.skey);
-    const uint32_t q = ceil_div_u32(sn, kWaves);
+    const uint32_t q = ceil_div_u32(sn, kWv);
     const uint32_t ws = min(sn, w * q), we = min(sn, ws + q);
     if constexpr (!WRITE) {
         uint32_t cnt = 0;
@@ -319,10 +344,10 @@ __device__ __forceinline__ void join_unit(const JoinArgs &a, uint32_t u, uint64_
             }
         }
         const uint64_t tot = wave_sum<uint64_t>((uint64_t)cnt);
-        if (lane == 0) a.wcnt[(uint64_t)u * kWaves + w] = tot;
+        if (lane == 0) a.wcnt[(uint64_t)u * kWv + w] = tot;
         if (a.flags && __ballot(multi) && lane == 0) atomicOr(&a.flags[1], 1u);
     } else {
-        uint64_t outpos = out_base + a.woff[(uint64_t)u * kWaves + w];
+        uint64_t outpos = out_base + a.woff[(uint64_t)u * kWv + w];
         K *__restrict__ tkey = static_cast<K *>(a.tkey);
         for (uint32_t base = ws; base < we; base += PB * kWave) {
             K key[PB];
@@ -388,27 +413,35 @@ __device__ __forceinline__ void join_unit(const JoinArgs &a, uint32_t u, uint64_
 }
 
 // One work unit per workgroup (eager calls: the grid is the unit count).
-template <typename K, bool WRITE>
-__global__ __launch_bounds__(kBlock) void k_join(JoinArgs a) {
-    __shared__ JoinShared<K> sh;
-    if (blockIdx.x < min(*a.nunits, a.cap_units)) join_unit<K, WRITE>(a, blockIdx.x, 0ull, sh);
+template <typename K, uint32_t BUILD, bool WRITE>
+__global__ __launch_bounds__(Geo<BUILD>::kThreads, Geo<BUILD>::kMinWEager) void k_join(JoinArgs a) {
+    __shared__ JoinShared<K, BUILD> sh;
+    if (blockIdx.x < min(*a.nunits, a.cap_units)) join_unit<K, BUILD, WRITE>(a, blockIdx.x, 0ull, sh);
 }
 
 // Write pass without a hash table, for the common case recorded by the count
 // pass (one R block per partition, at most one match per S row): each wave
 // streams its S rows with their recorded matches, takes output positions from
 // the scanned counts plus a ballot prefix, and gathers the payloads (GFTR:
-// partition-local R rows; GFUR: original rows through the row ids).
-template <typename K>
+// partition-local R rows; GFUR: original rows through the row ids). It needs no
+// LDS, so it always runs 256-thread workgroups whose waves take the count
+// pass's (unit, wave) slots one by one, whatever the table shape.
+template <typename K, uint32_t BUILD>
 __global__ __launch_bounds__(kBlock) void k_join_stream(JoinArgs a) {
+    using G = Geo<BUILD>;
     constexpr int PB = 16;
+    constexpr int kWv = G::kWv;
+    constexpr uint32_t kSPiece = G::kSPiece;
     if (a.flags[0] | a.flags[1]) return;  // the LDS write pass handles this input
-    const int tid = threadIdx.x, w = tid / kWave, lane = lane_id();
+    const int lane = lane_id();
     const uint32_t n_units = min(*a.nunits, a.cap_units);
+    const uint64_t n_slots = (uint64_t)n_units * kWv;
     const uint64_t out_base = a.out_base ? *a.out_base : 0ull;
     const K *__restrict__ skey = static_cast<const K *>(a.skey);
     K *__restrict__ tkey = static_cast<K *>(a.tkey);
-    for (uint32_t u = blockIdx.x; u < n_units; u += gridDim.x) {
+    for (uint64_t slot = (uint64_t)blockIdx.x * kWaves + threadIdx.x / kWave; slot < n_slots;
+         slot += (uint64_t)gridDim.x * kWaves) {
+        const uint32_t u = (uint32_t)(slot / kWv), w = (uint32_t)(slot % kWv);
         uint32_t lo = 0, hi = a.np;  // ubase[lo] <= u < ubase[hi]
         while (hi - lo > 1) {
             const uint32_t mid = (lo + hi) >> 1;
@@ -418,9 +451,9 @@ __global__ __launch_bounds__(kBlock) void k_join_stream(JoinArgs a) {
         const uint32_t p = lo, sb = u - a.ubase[p];  // one R block: the unit is the S piece
         const uint32_t ns = a.spo[p + 1] - a.spo[p];
         const uint32_t s0 = a.spo[p] + sb * kSPiece, sn = min(kSPiece, ns - sb * kSPiece);
-        const uint32_t q = ceil_div_u32(sn, kWaves);
+        const uint32_t q = ceil_div_u32(sn, kWv);
         const uint32_t ws = min(sn, w * q), we = min(sn, ws + q);
-        uint64_t outpos = out_base + a.woff[(uint64_t)u * kWaves + w];
+        uint64_t outpos = out_base + a.woff[slot];
         for (uint32_t base = ws; base < we; base += PB * kWave) {
             int32_t m[PB];
             K key[PB];
@@ -452,14 +485,14 @@ __global__ __launch_bounds__(kBlock) void k_join_stream(JoinArgs a) {
 }
 
 // Persistent workgroups over the unit count held in device memory (plans).
-template <typename K, bool WRITE>
-__global__ __launch_bounds__(kBlock, 3) void k_join_persist(JoinArgs a) {
-    __shared__ JoinShared<K> sh;
+template <typename K, uint32_t BUILD, bool WRITE>
+__global__ __launch_bounds__(Geo<BUILD>::kThreads, Geo<BUILD>::kMinW) void k_join_persist(JoinArgs a) {
+    __shared__ JoinShared<K, BUILD> sh;
     if (WRITE && a.lds_if_complex && !(a.flags[0] | a.flags[1])) return;  // the streaming pass writes
     const uint32_t n_units = min(*a.nunits, a.cap_units);
     const uint64_t out_base = a.out_base ? *a.out_base : 0ull;
     for (uint32_t u = blockIdx.x; u < n_units; u += gridDim.x) {
-        join_unit<K, WRITE>(a, u, out_base, sh);
+        join_unit<K, BUILD, WRITE>(a, u, out_base, sh);
         __syncthreads();  // the unit's LDS state is rebuilt by the next one
     }
 }
@@ -467,14 +500,14 @@ __global__ __launch_bounds__(kBlock, 3) void k_join_persist(JoinArgs a) {
 // Output offset of each instance of a batch: the write offset of its first unit.
 // Units past the processed count (a plan's capacity) contribute nothing.
 __global__ void k_instance_offsets(const uint32_t *__restrict__ ubase, const uint64_t *__restrict__ woff,
-                                   uint32_t n_inst, const uint32_t *__restrict__ nunits, uint32_t cap_units,
-                                   const uint64_t *__restrict__ total, const uint64_t *__restrict__ base,
-                                   uint64_t *__restrict__ out) {
+                                   uint32_t waves_per_unit, uint32_t n_inst, const uint32_t *__restrict__ nunits,
+                                   uint32_t cap_units, const uint64_t *__restrict__ total,
+                                   const uint64_t *__restrict__ base, uint64_t *__restrict__ out) {
     const uint32_t nu = min(*nunits, cap_units);
     const uint64_t b = base ? *base : 0ull;
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i <= n_inst; i += gridDim.x * blockDim.x) {
         const uint32_t u = (i == n_inst) ? nu : min(ubase[i << 8], nu);
-        out[i] = b + (u == nu ? *total : woff[(uint64_t)u * kWaves]);
+        out[i] = b + (u == nu ? *total : woff[(uint64_t)u * waves_per_unit]);
     }
 }
 
@@ -489,19 +522,63 @@ __global__ void k_advance_base(const uint64_t *__restrict__ base, const uint64_t
     }
 }
 
+// The count and write kernels of one table shape.
+template <typename K, uint32_t BUILD>
+struct JoinKernels {
+    using G = Geo<BUILD>;
+    static void count(hipStream_t s, bool planned, uint32_t grid, const JoinArgs &a, double bytes) {
+        if (planned) GJ_LAUNCH("k_join_count", bytes, (k_join_persist<K, BUILD, false>), dim3(grid), dim3(G::kThreads), 0, s, a);
+        else GJ_LAUNCH("k_join_count", bytes, (k_join<K, BUILD, false>), dim3(grid), dim3(G::kThreads), 0, s, a);
+    }
+    // grid: workgroups of the unit passes; the streaming pass has kWaves-wave workgroups
+    static void stream(hipStream_t s, uint32_t grid, const JoinArgs &a, double bytes) {
+        grid = (uint32_t)std::min<uint64_t>((uint64_t)grid * G::kWv / kWaves, 1u << 30);
+        GJ_LAUNCH("k_join_write", bytes, (k_join_stream<K, BUILD>), dim3(grid), dim3(kBlock), 0, s, a);
+    }
+    static void write_lds(hipStream_t s, bool planned, uint32_t grid, const JoinArgs &a, double bytes) {
+        if (planned) GJ_LAUNCH("k_join_write_lds", bytes, (k_join_persist<K, BUILD, true>), dim3(grid), dim3(G::kThreads), 0, s, a);
+        else GJ_LAUNCH("k_join_write_lds", bytes, (k_join<K, BUILD, true>), dim3(grid), dim3(G::kThreads), 0, s, a);
+    }
+};
+
+// Pass 0 = count, 1 = streaming write, 2 = LDS write; the table shape holds r_block rows.
+void launch_join_pass(int pass, int key_bytes, uint32_t table_rows, hipStream_t s, bool planned, uint32_t grid,
+                      const JoinArgs &a, double bytes) {
+#define GJ_JP(K, B)                                                 \
+    do {                                                            \
+        if (pass == 0) JoinKernels<K, B>::count(s, planned, grid, a, bytes);     \
+        else if (pass == 1) JoinKernels<K, B>::stream(s, grid, a, bytes);        \
+        else JoinKernels<K, B>::write_lds(s, planned, grid, a, bytes);           \
+    } while (0)
+    if (key_bytes == 4) {
+        if (table_rows == 4096) GJ_JP(int32_t, 4096);
+        else if (table_rows == 8192) GJ_JP(int32_t, 8192);
+        else GJ_JP(int32_t, 16384);
+    } else {
+        if (table_rows == 4096) GJ_JP(int64_t, 4096);
+        else GJ_JP(int64_t, 8192);
+    }
+#undef GJ_JP
+}
+
+uint32_t waves_per_unit(uint32_t table_rows) { return table_rows / 16 / kWave; }
+
 }  // namespace
 
 int64_t join_partitioned(Ctx &ctx, int key_bytes, const JoinSide &R, const JoinSide &S, int bits,
                          int r_block, bool gfur, JoinOut *out, const uint8_t *seg_bits, uint32_t n_inst,
                          uint64_t *inst_off, const JoinPlanned *pl) {
     hipStream_t s = ctx.stream;
-    require(r_block >= 64 && r_block <= (int)kMaxBuild, "R build block must be 64..4096 rows");
+    require(r_block >= 64 && r_block <= join_max_r_block(key_bytes),
+            key_bytes == 4 ? "R build block must be 64..16384 rows" : "R build block must be 64..8192 rows for 8-byte keys");
+    const uint32_t table_rows = join_table_rows(r_block);
+    const uint32_t wpu = waves_per_unit(table_rows);
     const uint32_t np = seg_bits ? (n_inst << 8) : (1u << bits);
     uint32_t *ucnt = ctx.scratch_n<uint32_t>(np + 1);
     uint32_t *flags = ctx.scratch_n<uint32_t>(2);
     fill_u32(s, flags, 0u, 2);
     GJ_LAUNCH("k_unit_count", 20.0 * np, k_unit_count, dim3(std::min<uint32_t>((np + 255) / 256, 1024)),
-              dim3(256), 0, s, R.poff, S.poff, np, (uint32_t)r_block, ucnt, flags);
+              dim3(256), 0, s, R.poff, S.poff, np, (uint32_t)r_block, join_s_piece(r_block), ucnt, flags);
     scan_exclusive_u32(ctx, ucnt, ucnt, np, ucnt + np);
     // Eager calls read the unit count and size every launch exactly; a plan sizes
     // for its capacity and the kernels read the count from device memory.
@@ -536,20 +613,14 @@ int64_t join_partitioned(Ctx &ctx, int key_bytes, const JoinSide &R, const JoinS
     a.midx = ctx.scratch_n<int32_t>(std::max<uint32_t>(S.rows, 1));
     a.flags = flags;
     a.lds_if_complex = pl ? 1 : 0;
-    const uint64_t nw = (uint64_t)cap_units * kWaves;
+    const uint64_t nw = (uint64_t)cap_units * wpu;
     uint64_t *wcnt = ctx.scratch_n<uint64_t>(nw + 1);
     uint64_t *total = pl ? pl->total : wcnt + nw;
     a.wcnt = wcnt;
     const double nrows_r = R.rows, nrows_s = S.rows;
     const double key_reads = (nrows_r + nrows_s) * key_bytes;
-    if (key_bytes == 4) {
-        if (pl) GJ_LAUNCH("k_join_count", key_reads, (k_join_persist<int32_t, false>), dim3(grid), dim3(kBlock), 0, s, a);
-        else GJ_LAUNCH("k_join_count", key_reads, (k_join<int32_t, false>), dim3(grid), dim3(kBlock), 0, s, a);
-    } else {
-        if (pl) GJ_LAUNCH("k_join_count", key_reads, (k_join_persist<int64_t, false>), dim3(grid), dim3(kBlock), 0, s, a);
-        else GJ_LAUNCH("k_join_count", key_reads, (k_join<int64_t, false>), dim3(grid), dim3(kBlock), 0, s, a);
-    }
-    if (pl) scan_exclusive_u64_dev(ctx, wcnt, wcnt, nw, ucnt + np, kWaves, total);
+    launch_join_pass(0, key_bytes, table_rows, s, pl != nullptr, grid, a, key_reads);
+    if (pl) scan_exclusive_u64_dev(ctx, wcnt, wcnt, nw, ucnt + np, wpu, total);
     else scan_exclusive_u64(ctx, wcnt, wcnt, nw, total);
     uint64_t T;
     bool complex = true;  // plans launch both write passes; each decides on the device
@@ -565,8 +636,8 @@ int64_t join_partitioned(Ctx &ctx, int key_bytes, const JoinSide &R, const JoinS
     }
     if (inst_off)
         GJ_LAUNCH("k_instance_offsets", 16.0 * n_inst, k_instance_offsets,
-                  dim3(std::min<uint32_t>(ceil_div_u32(n_inst + 1, 256), 1024)), dim3(256), 0, s, ucnt, wcnt, n_inst,
-                  ucnt + np, cap_units, total, a.out_base, inst_off);
+                  dim3(std::min<uint32_t>(ceil_div_u32(n_inst + 1, 256), 1024)), dim3(256), 0, s, ucnt, wcnt, wpu,
+                  n_inst, ucnt + np, cap_units, total, a.out_base, inst_off);
     if (pl && (pl->next_base || pl->units_out))
         GJ_LAUNCH("k_advance_base", 16.0, k_advance_base, dim3(1), dim3(64), 0, s, a.out_base, total, pl->next_base,
                   (const uint32_t *)(ucnt + np), pl->units_out);
@@ -608,21 +679,10 @@ int64_t join_partitioned(Ctx &ctx, int key_bytes, const JoinSide &R, const JoinS
     const double sbytes = wbytes - nrows_r * key_bytes;
     // Eager calls launch the one write pass the count pass chose; plans launch
     // both, and the one that does not apply returns at once.
-    if (pl || !complex) {
-        if (key_bytes == 4)
-            GJ_LAUNCH("k_join_write", sbytes, k_join_stream<int32_t>, dim3(grid), dim3(kBlock), 0, s, a);
-        else
-            GJ_LAUNCH("k_join_write", sbytes, k_join_stream<int64_t>, dim3(grid), dim3(kBlock), 0, s, a);
-    }
+    if (pl || !complex) launch_join_pass(1, key_bytes, table_rows, s, pl != nullptr, grid, a, sbytes);
     if (pl || complex) {
         const double lbytes = pl ? 0.0 : wbytes;  // a plan counts its bytes once, on the streaming pass
-        if (key_bytes == 4) {
-            if (pl) GJ_LAUNCH("k_join_write_lds", lbytes, (k_join_persist<int32_t, true>), dim3(grid), dim3(kBlock), 0, s, a);
-            else GJ_LAUNCH("k_join_write_lds", lbytes, (k_join<int32_t, true>), dim3(grid), dim3(kBlock), 0, s, a);
-        } else {
-            if (pl) GJ_LAUNCH("k_join_write_lds", lbytes, (k_join_persist<int64_t, true>), dim3(grid), dim3(kBlock), 0, s, a);
-            else GJ_LAUNCH("k_join_write_lds", lbytes, (k_join<int64_t, true>), dim3(grid), dim3(kBlock), 0, s, a);
-        }
+        launch_join_pass(2, key_bytes, table_rows, s, pl != nullptr, grid, a, lbytes);
     }
     return pl ? 0 : (int64_t)T;
 }

@@ -27,9 +27,11 @@
 namespace gj {
 namespace {
 
-constexpr int kScatterBlock = 1024;  // default scatter shape: 1024 threads x 8 rows, 2 columns per load group
-constexpr int kItems = 8;
-constexpr int kGroup = 2;
+// Default scatter shape: the wide kernel (1024 threads x 16 rows, one column at
+// a time with a rolling prefetch); group 0 names it among the shapes.
+constexpr int kScatterBlock = 1024;
+constexpr int kItems = 16;
+constexpr int kGroup = 0;
 constexpr uint32_t kTile = kBlock * kItems;
 
 struct PassArgs {
@@ -321,6 +323,238 @@ __device__ __forceinline__ void scatter_tile(const PassArgs &a, const DigitFn &d
     __syncthreads();
 }
 
+// Loads of the wide kernel: one 64-bit base address per thread, every row at a
+// constant offset from it (r * 64 rows), so that the 16 loads of a column need
+// no per-row address registers. A full tile loads without row checks; in a
+// partial one, rows past nt read as zero. A generated row id is its row index.
+template <typename K, int ITEMS>
+__device__ __forceinline__ void wide_load_keys(const PassArgs &a, uint32_t tile0, uint32_t nt, K (&key)[ITEMS]) {
+    constexpr uint32_t TILE = 1024u * ITEMS;
+    const uint32_t lbase = (uint32_t)((threadIdx.x / kWave) * kWave * ITEMS + lane_id());
+    const K *__restrict__ p = static_cast<const K *>(a.key_in) + (tile0 + lbase);
+    if (nt == TILE) {
+#pragma unroll
+        for (int r = 0; r < ITEMS; ++r) key[r] = p[r * kWave];
+    } else {
+        const uint32_t rem = nt > lbase ? nt - lbase : 0u;
+#pragma unroll
+        for (int r = 0; r < ITEMS; ++r) key[r] = (uint32_t)(r * kWave) < rem ? p[r * kWave] : K(0);
+    }
+}
+
+template <int ITEMS>
+__device__ __forceinline__ void wide_load_col(const PassArgs &a, int c, uint32_t tile0, uint32_t nt,
+                                              uint32_t (&v)[ITEMS]) {
+    constexpr uint32_t TILE = 1024u * ITEMS;
+    const uint32_t lbase = (uint32_t)((threadIdx.x / kWave) * kWave * ITEMS + lane_id());
+    if (c == a.rowid_col) {
+#pragma unroll
+        for (int r = 0; r < ITEMS; ++r) v[r] = tile0 + lbase + r * kWave;
+        return;
+    }
+    const uint32_t *__restrict__ p = static_cast<const uint32_t *>(a.col_in[c]) + (tile0 + lbase);
+    if (nt == TILE) {
+#pragma unroll
+        for (int r = 0; r < ITEMS; ++r) v[r] = p[r * kWave];
+    } else {
+        const uint32_t rem = nt > lbase ? nt - lbase : 0u;
+#pragma unroll
+        for (int r = 0; r < ITEMS; ++r) v[r] = (uint32_t)(r * kWave) < rem ? p[r * kWave] : 0u;
+    }
+}
+
+// Wide tiles: 1024 threads x 16 rows = 16384-row tiles, twice the rows of the
+// default shape, so that every digit's run per tile (the burst each column
+// writes to HBM) is twice as long. The shorter the bursts, the slower the
+// scatter: at equal work, 8-bit digits over 8192-row tiles write at about 55%
+// of the rate of one-digit tiles. The larger tile fits the registers because
+// columns move one at a time: while column c is staged and stored, column
+// c + 1 (or the next tile's first column) is already loading into the one
+// column register array, and 8-byte columns move in two halves of 8 rows.
+// FULL tiles (all but a chunk's last) carry no per-row checks.
+template <typename K, int BLOCK, int ITEMS, bool FULL>
+__device__ __forceinline__ void scatter_tile_wide(const PassArgs &a, const DigitFn &dig, ScatterShared<BLOCK> &S,
+                                                  uint32_t (*s_buf)[BLOCK * ITEMS], uint32_t tile0, uint32_t nt,
+                                                  K (&key)[ITEMS], uint32_t (&v)[ITEMS], uint32_t next0,
+                                                  uint32_t next_nt) {
+    constexpr int W = BLOCK / kWave;
+    const int tid = threadIdx.x, w = tid / kWave, lane = lane_id();
+    K *__restrict__ kout = static_cast<K *>(a.key_out);
+    K *sk = reinterpret_cast<K *>(&s_buf[0][0]);
+    uint64_t *s8 = reinterpret_cast<uint64_t *>(&s_buf[0][0]);
+    const int n4 = a.n4;
+    const uint32_t lbase = (uint32_t)(w * kWave * ITEMS + lane);
+    // rows of this thread (r * 64 < lrem) and staged slots of this thread (k * BLOCK < srem)
+    const uint32_t lrem = FULL ? 0xFFFFFFFFu : (nt > lbase ? nt - lbase : 0u);
+    const uint32_t srem = FULL ? 0xFFFFFFFFu : (nt > (uint32_t)tid ? nt - (uint32_t)tid : 0u);
+#define GJ_VALID(r) (FULL || (uint32_t)((r) * kWave) < lrem)
+
+    for (int i = tid; i < W * kRadix; i += BLOCK) (&S.wcnt[0][0])[i] = 0;
+    __syncthreads();
+
+    // stable rank within the wave: ballot peers, the leader bumps the wave counter
+    uint32_t pos[ITEMS];
+#pragma unroll
+    for (int r = 0; r < ITEMS; ++r) {
+        const bool valid = GJ_VALID(r);
+        const uint32_t d = digit_of<K>(key[r], dig);
+        const uint64_t peers = match_peers(d, a.bits, valid);
+        uint32_t p = 0;
+        if (valid) {
+            const uint32_t rk = rank_below(peers);
+            const uint32_t b = S.wcnt[w][d];
+            if (rk == 0) S.wcnt[w][d] = b + (uint32_t)__popcll(peers);
+            p = b + rk;
+        }
+        pos[r] = p;
+    }
+    __syncthreads();
+    if (tid < kRadix) {
+        uint32_t t = 0;
+#pragma unroll
+        for (int q = 0; q < W; ++q) {
+            const uint32_t c = S.wcnt[q][tid];
+            S.wcnt[q][tid] = t;
+            t += c;
+        }
+        S.tot[tid] = t;
+        const uint32_t inc = wave_inclusive_sum<uint32_t>(t);
+        if (lane == kWave - 1) S.tmp[w] = inc;
+        S.start[tid] = inc - t;
+    }
+    __syncthreads();
+    if (tid < kRadix) {
+        uint32_t before = 0;
+#pragma unroll
+        for (int q = 0; q < kWaves; ++q) before += (q < w) ? S.tmp[q] : 0u;
+        S.start[tid] += before;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < ITEMS; ++r) {
+        if (GJ_VALID(r)) {
+            const uint32_t d = digit_of<K>(key[r], dig);
+            pos[r] += S.start[d] + S.wcnt[w][d];
+            sk[pos[r]] = key[r];
+        }
+    }
+    // the key registers are free: next tile's keys
+    if (next_nt) wide_load_keys<K, ITEMS>(a, next0, next_nt, key);
+    // LDS slots (< 16384) two to a register from here on
+    uint32_t pp[ITEMS / 2];
+#pragma unroll
+    for (int r = 0; r < ITEMS / 2; ++r) pp[r] = (pos[2 * r] & 0xFFFFu) | (pos[2 * r + 1] << 16);
+#define GJ_POS(r) ((pp[(r) >> 1] >> (16 * ((r) & 1))) & 0xFFFFu)
+    __syncthreads();
+
+    uint32_t dst[ITEMS];
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) {
+        const uint32_t i = (uint32_t)(k * BLOCK + tid);
+        dst[k] = 0xFFFFFFFFu;
+        if (FULL || (uint32_t)(k * BLOCK) < srem) {
+            const K kk = sk[i];
+            const uint32_t d = digit_of<K>(kk, dig);
+            const uint32_t t = S.cur[d] + i - S.start[d];
+            if (t < a.n_rows) {  // always true when the offsets are right
+                dst[k] = t;
+                kout[t] = kk;
+            }
+        }
+    }
+
+    // 4-byte keys sit in buffer 0, so the first column goes to buffer 1; 8-byte
+    // keys use both buffers and need a barrier before reuse.
+    int par = 1;
+    if constexpr (sizeof(K) == 8) {
+        __syncthreads();
+        par = 0;
+    }
+#pragma unroll 1
+    for (int c = 0; c < n4; ++c) {
+        uint32_t *sb = s_buf[par];
+#pragma unroll
+        for (int r = 0; r < ITEMS; ++r)
+            if (GJ_VALID(r)) sb[GJ_POS(r)] = v[r];
+        // v is free: the next column of this tile, or the next tile's first one
+        // (one load sequence for both cases keeps the register count down)
+        const bool more = c + 1 < n4;
+        if (more || next_nt)
+            wide_load_col<ITEMS>(a, more ? c + 1 : 0, more ? tile0 : next0, more ? nt : next_nt, v);
+        __syncthreads();
+        uint32_t *__restrict__ out = static_cast<uint32_t *>(a.col_out[c]);
+#pragma unroll
+        for (int k = 0; k < ITEMS; ++k)
+            if (dst[k] != 0xFFFFFFFFu) out[dst[k]] = sb[k * BLOCK + tid];
+        par ^= 1;
+    }
+#pragma unroll 1
+    for (int c = n4; c < a.ncols; ++c) {
+        constexpr int HI = ITEMS / 2;
+        const uint64_t *__restrict__ in = static_cast<const uint64_t *>(a.col_in[c]) + (tile0 + lbase);
+        uint64_t x[HI];
+#pragma unroll
+        for (int r = 0; r < HI; ++r) x[r] = GJ_VALID(r) ? in[r * kWave] : 0ull;
+        __syncthreads();  // both buffers free
+#pragma unroll
+        for (int r = 0; r < HI; ++r)
+            if (GJ_VALID(r)) s8[GJ_POS(r)] = x[r];
+#pragma unroll
+        for (int r = 0; r < HI; ++r) x[r] = GJ_VALID(HI + r) ? in[(HI + r) * kWave] : 0ull;
+#pragma unroll
+        for (int r = 0; r < HI; ++r)
+            if (GJ_VALID(HI + r)) s8[GJ_POS(HI + r)] = x[r];
+        __syncthreads();
+        uint64_t *__restrict__ out = static_cast<uint64_t *>(a.col_out[c]);
+#pragma unroll
+        for (int k = 0; k < ITEMS; ++k)
+            if (dst[k] != 0xFFFFFFFFu) out[dst[k]] = s8[k * BLOCK + tid];
+    }
+#undef GJ_POS
+#undef GJ_VALID
+    __syncthreads();
+    if (tid < kRadix) S.cur[tid] += S.tot[tid];
+    __syncthreads();
+}
+
+template <typename K, int BLOCK, int ITEMS>
+__global__ __launch_bounds__(BLOCK) void k_scatter_wide(PassArgs a) {
+    constexpr uint32_t TILE = BLOCK * ITEMS;
+    static_assert(BLOCK == 1024, "the wide loads assume 1024 threads");
+    __shared__ ScatterShared<BLOCK> S;
+    __shared__ uint32_t s_buf[2][TILE];  // double buffer for 4-byte columns; 8-byte data spans both
+    __shared__ ChunkLoc s_loc;
+
+    if (threadIdx.x == 0) s_loc = locate_chunk(a, blockIdx.x);
+    __syncthreads();
+    const ChunkLoc L = s_loc;
+    if (!L.ok) return;
+
+    const uint32_t R = 1u << a.bits;
+    const uint32_t base_off = a.seg_off[0];
+    for (uint32_t d = threadIdx.x; d < kRadix; d += BLOCK)
+        S.cur[d] = d < R ? base_off + a.hist[L.hbase + d * L.m + L.j] : 0u;
+
+    const DigitFn dig = seg_digit(a, L.seg);
+    K key[ITEMS];
+    uint32_t v[ITEMS];
+    uint32_t tile0 = L.row0;
+    uint32_t nt = min(TILE, L.row1 - tile0);
+    if (nt) {
+        wide_load_keys<K, ITEMS>(a, tile0, nt, key);
+        if (a.n4 > 0) wide_load_col<ITEMS>(a, 0, tile0, nt, v);
+    }
+    // full tiles, then at most one partial tile (a chunk's last)
+    while (nt == TILE) {
+        const uint32_t next0 = tile0 + nt;
+        const uint32_t next_nt = next0 < L.row1 ? min(TILE, L.row1 - next0) : 0u;
+        scatter_tile_wide<K, BLOCK, ITEMS, true>(a, dig, S, s_buf, tile0, nt, key, v, next0, next_nt);
+        tile0 = next0;
+        nt = next_nt;
+    }
+    if (nt) scatter_tile_wide<K, BLOCK, ITEMS, false>(a, dig, S, s_buf, tile0, nt, key, v, 0u, 0u);
+}
+
 // MINW: minimum waves per SIMD the register allocation must allow (4 lets two
 // 512-thread workgroups share a compute unit).
 template <typename K, int BLOCK, int ITEMS, int G, int MINW>
@@ -381,10 +615,11 @@ __global__ void k_set_range(uint32_t *p, uint32_t a, uint32_t b) {
 struct Shape {
     int block, items, group;
 };
+// Group 0 is the wide-tile kernel (one column at a time, rolling prefetch).
 constexpr Shape kVariants[kScatterVariants] = {{256, 8, 4},  {512, 8, 4},  {1024, 8, 4}, {512, 4, 4},
                                                {1024, 4, 4}, {256, 16, 2}, {512, 8, 2},  {512, 16, 2},
                                                {512, 16, 4}, {1024, 8, 2},  {1024, 16, 2}, {1024, 16, 1},
-                                               {512, 16, 1}};
+                                               {512, 16, 1}, {1024, 16, 0}};
 thread_local int g_variant = 0;
 Shape scatter_shape() {
     if (g_variant >= 1 && g_variant <= kScatterVariants) return kVariants[g_variant - 1];
@@ -411,6 +646,10 @@ void launch_scatter(const Shape &sh, dim3 grid, hipStream_t s, const PassArgs &a
     GJ_SC(256, 16, 2) GJ_SC(512, 8, 2) GJ_SC(512, 16, 2) GJ_SC(512, 16, 4) GJ_SC(1024, 8, 2)
     GJ_SC(1024, 16, 2) GJ_SC(1024, 16, 1) GJ_SC(512, 16, 1)
 #undef GJ_SC
+    if (sh.block == 1024 && sh.items == 16 && sh.group == 0) {
+        GJ_LAUNCH("k_scatter", bytes, (k_scatter_wide<K, 1024, 16>), grid, dim3(1024), 0, s, a);
+        return;
+    }
     throw Error(GJ_EINVAL, "unknown scatter shape");
 }
 

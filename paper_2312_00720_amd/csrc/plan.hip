@@ -265,7 +265,7 @@ void check_tuning(const gj_join_tuning *t) {
         require(t->part_log2[c] == 0 || (t->part_log2[c] >= 6 && t->part_log2[c] <= 12), "part_log2 must be 0 or 6..12");
         require(t->bucket_shift[c] == 0 || t->bucket_shift[c] == 1, "bucket_shift must be 0 or 1");
     }
-    require(t->scatter_variant >= 0 && t->scatter_variant <= gj::kScatterVariants, "scatter_variant must be 0..13");
+    require(t->scatter_variant >= 0 && t->scatter_variant <= gj::kScatterVariants, "scatter_variant must be 0..14");
 }
 
 void build_join_plan(gj_plan *P, const gj_rel_batch *R, const gj_rel_batch *S, const gj_join_opts *opts,
@@ -275,14 +275,14 @@ void build_join_plan(gj_plan *P, const gj_rel_batch *R, const gj_rel_batch *S, c
     gj_join_opts o{};
     if (opts) o = *opts;
     require(o.mat >= 0 && o.mat <= 2, "bad materialization");
-    require(o.lds_budget == 0 || (o.lds_budget >= 64 && o.lds_budget <= 4096), "lds_budget must be 64..4096");
+    gj::check_join_lds_budget(o.lds_budget, dtype_bytes(R->key.dtype));
     require(o.flags == 0, "flags must be 0");
     require(out_capacity >= 0, "negative output capacity");
     const int n = R->n_instances;
     P->n = n;
     P->kb = dtype_bytes(R->key.dtype);
     P->gfur = (o.mat == GJ_MAT_GFUR);
-    P->r_block = o.lds_budget ? o.lds_budget : (int)gj::kJoinMaxBuild;
+    P->r_block = o.lds_budget ? o.lds_budget : 4096;
     P->variant = tuning ? tuning->scatter_variant : 0;
     P->rkey = R->key.data;
     P->skey = S->key.data;
@@ -329,7 +329,8 @@ void build_join_plan(gj_plan *P, const gj_rel_batch *R, const gj_rel_batch *S, c
             if (j > i && (nr > group_rows || ns > group_rows)) break;
             if (r > 0 && s > 0) {
                 const uint64_t a = std::min<uint64_t>(((uint64_t)r + P->r_block - 1) / P->r_block, kUnitFactor);
-                units += a * (((uint64_t)s + gj::kJoinSPiece - 1) / gj::kJoinSPiece + (1ull << bits[j]));
+                const uint64_t piece = gj::join_s_piece(P->r_block);
+                units += a * (((uint64_t)s + piece - 1) / piece + (1ull << bits[j]));
             }
             ++j;
         }

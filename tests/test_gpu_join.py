@@ -69,6 +69,24 @@ def test_options_do_not_change_results(kw):
     check(d, "gftr", **kw)
 
 
+@pytest.mark.parametrize("budget", [6000, 8192, 16384])
+@pytest.mark.parametrize("kb", [4, 8])
+def test_large_table_shapes(budget, kb):
+    """Build blocks past 4096 rows run the 8192- and 16384-row table shapes
+    (512 and 1024 threads; S pieces of twice the table rows). Cases: partitions
+    that fit one block, partitions spanning several blocks (LDS write pass),
+    skewed FKs, and heavy duplicates (ordered re-placement of long chains)."""
+    if kb == 8 and budget > 8192:
+        pytest.skip("8-byte keys stop at 8192-row tables (checked in test_bad_arguments_raise)")
+    d = datagen.pk_fk_join(200000, 700001, 2, 2, seed=51, key_bytes=kb, match_ratio=0.8)
+    check(d, "gftr", lds_budget=budget)
+    check(d, "gfur", lds_budget=budget, radix_bits=2)  # ~50000-row R partitions: several blocks
+    d = datagen.pk_fk_join(100000, 300000, 1, 1, seed=52, key_bytes=kb, alpha=1.0)
+    check(d, "gftr", lds_budget=budget, radix_bits=3)
+    d = datagen.many_to_many_join(8000, 2000, 12, 1, 1, seed=53, key_bytes=kb)
+    check(d, "gfur", lds_budget=budget, radix_bits=1)
+
+
 def test_edge_cases():
     g = datagen.rng(0)
     empty = np.zeros(0, np.int32)
@@ -114,3 +132,9 @@ def test_bad_arguments_raise():
     with pytest.raises(gj.GJError) as e:
         gj.join(r, [], s, [])
     assert e.value.code == -1
+    r8 = torch.zeros(10, dtype=torch.int64, device="cuda")
+    for kw in (dict(lds_budget=16385), dict(lds_budget=63)):
+        with pytest.raises(gj.GJError):
+            gj.join(r, [], r, [], **kw)
+    with pytest.raises(gj.GJError):
+        gj.join(r8, [], s, [], lds_budget=16384)

@@ -50,6 +50,22 @@ def test_partition_matches_oracle(case):
     np.testing.assert_array_equal(off, np.concatenate([[0], np.cumsum(hist)]).astype(np.int32))
 
 
+@pytest.mark.timeout(600)
+def test_partition_chunks_of_several_tiles():
+    """Past 4096 tiles, a chunk spans several 16384-row tiles: the scatter's
+    next-tile prefetch and the partial last tile of every segment are used."""
+    n = (1 << 26) + 12345
+    g = datagen.rng(77)
+    keys = datagen.raw_keys(n, seed=78)
+    cols = [g.integers(-2**31, 2**31, size=n, dtype=np.int64).astype(np.int32)]
+    k, c, r, off = _run(keys, cols, 0, 16, 2, "bits")
+    perm, hist = oracle.partition(keys, 0, 16, oracle.DIGIT_BITS)
+    np.testing.assert_array_equal(r, perm.astype(np.int32))
+    np.testing.assert_array_equal(k, keys[perm])
+    np.testing.assert_array_equal(c[0], cols[0][perm])
+    np.testing.assert_array_equal(off, np.concatenate([[0], np.cumsum(hist)]).astype(np.int32))
+
+
 def test_partition_skewed_digits():
     """A single hot digit (all keys equal) and Zipf-skewed keys stay stable."""
     n = 200000

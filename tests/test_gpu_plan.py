@@ -155,11 +155,25 @@ def test_tuning_tables_never_change_results():
     rng = datagen.rng(36)
     for trial in range(3):
         t = gj.tuning_table({c: int(rng.integers(6, 13)) for c in range(16)},
-                            {c: int(rng.integers(0, 2)) for c in range(16)}, int(rng.integers(0, 13)))
+                            {c: int(rng.integers(0, 2)) for c in range(16)}, int(rng.integers(0, 15)))
         plan = gj.JoinPlan(*d, mat="gftr" if trial % 2 == 0 else "gfur", tuning=t)
         cols, off = run_plan(plan, "graph")
         check_vs_oracle(parts, cols, off)
         plan.close()
+
+
+@pytest.mark.parametrize("variant", list(range(1, 15)))
+def test_every_scatter_shape_matches_oracle(variant):
+    """Each compiled scatter shape (variant 14 is the wide 16384-row tile) gives
+    the oracle's join on uneven instances, 8-byte keys included."""
+    import paper_2312_00720_amd as gj
+    sizes = uneven_sizes(12, 38 + variant, lo=0, hi=15)
+    parts, b = make_batch(sizes, seed=9600 + variant, key_bytes=8 if variant % 2 else 4)
+    d = device_batch(b)
+    plan = gj.JoinPlan(*d, mat="gftr" if variant % 3 else "gfur", tuning=gj.tuning_table(scatter_variant=variant))
+    cols, off = run_plan(plan, "eager")
+    check_vs_oracle(parts, cols, off)
+    plan.close()
 
 
 def test_autotune_gives_a_valid_table():
@@ -172,7 +186,7 @@ def test_autotune_gives_a_valid_table():
     classes = {int(np.floor(np.log2(r))) for r, s in sizes if r > 0 and s > 0}
     assert set(td["part_log2"]) == classes
     assert all(9 <= v <= 12 for v in td["part_log2"].values())
-    assert 0 <= td["scatter_variant"] <= 12
+    assert 0 <= td["scatter_variant"] <= 14
     plan = gj.JoinPlan(*d, mat="gftr", tuning=t)
     cols, off = run_plan(plan, "graph")
     check_vs_oracle(parts, cols, off)
