@@ -74,7 +74,8 @@ GB_AGGS = [(0, "count"), (0, "sum"), (0, "min"), (0, "max"), (1, "sum"), (1, "mi
 def measured_traffic(kernel: str, workload: str):
     """HBM bytes per launch of `kernel` on `workload` from the committed rocprofv3
     FETCH_SIZE / WRITE_SIZE passes (profiles/traffic.json), or None when there is
-    no such measurement or the kernel's source has changed since it was taken."""
+    no such measurement or any source it depends on (the kernels, the launch
+    rules) has changed since it was taken."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
@@ -82,9 +83,11 @@ def measured_traffic(kernel: str, workload: str):
     e = json.load(open(path)).get(f"{kernel}@{workload}")
     if not e:
         return None
-    src = os.path.join(ROOT, e["source"])
-    if not os.path.exists(src) or hashlib.sha256(open(src, "rb").read()).hexdigest() != e["sha256"]:
-        return None
+    # every source that shapes the measured launches (kernel and launch rules)
+    for rel, sha in e["sources"].items():
+        src = os.path.join(ROOT, rel)
+        if not os.path.exists(src) or hashlib.sha256(open(src, "rb").read()).hexdigest() != sha:
+            return None
     return e["hbm_bytes_per_launch"]
 
 

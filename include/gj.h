@@ -77,7 +77,9 @@ typedef struct {
     int32_t block_size;        /* reserved; must be 0 or 256 */
     float ht_occupancy;        /* reserved */
     int32_t lds_budget;        /* max R rows per build block, 64..16384 (8-byte keys: 64..8192);
-                                  0: 8192 when |R| >= 2^24, else 4096; the LDS table
+                                  0: 4096 below |R| = 2^24; from there 16384 for GFTR with
+                                  4-byte keys and at most 18 bytes of R payload per row,
+                                  else 8192; the LDS table
                                   has 4096, 8192 or 16384 rows, the smallest that holds it */
     uint64_t flags;            /* reserved, must be 0 */
 } gj_join_opts;

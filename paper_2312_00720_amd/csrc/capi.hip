@@ -128,7 +128,10 @@ int gj_join(const gj_rel *R, const gj_rel *S, const gj_join_opts *opts, const gj
             mat = gj::select_algorithm(f, 0, nullptr) == 1 ? GJ_MAT_GFUR : GJ_MAT_GFTR;
         }
         const bool gfur = (mat == GJ_MAT_GFUR);
-        const int r_block = o.lds_budget ? o.lds_budget : gj::join_default_r_block((uint64_t)R->n_rows);
+        int r_pay_bytes = 0;
+        for (int i = 0; i < R->n_payloads; ++i) r_pay_bytes += dtype_bytes(R->payloads[i].dtype);
+        const int r_block = o.lds_budget ? o.lds_budget
+                                         : gj::join_default_r_block((uint64_t)R->n_rows, kb, gfur, r_pay_bytes);
         const int bits = o.radix_bits ? o.radix_bits : gj::join_default_bits((uint64_t)R->n_rows, r_block);
         int passes = o.passes ? o.passes : (bits > 8 ? 2 : 1);
         gj::require(bits <= 8 * passes, "at most 8 bits per pass");

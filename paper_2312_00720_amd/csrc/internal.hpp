@@ -247,13 +247,20 @@ inline void check_join_lds_budget(int lds_budget, int key_bytes) {
     require(lds_budget == 0 || (lds_budget >= 64 && lds_budget <= join_max_r_block(key_bytes)),
             key_bytes == 8 ? "lds_budget must be 64..8192 for 8-byte keys" : "lds_budget must be 64..16384");
 }
+// LDS the staged streaming write pass may use for one partition's R payloads.
+constexpr size_t kJoinStagedLds = 144 * 1024;
 // Default R build block and partition bits of a single join: partitions of
 // about r_block / 2 rows leave room for variance. R relations of 2^24 rows and
-// more use 8192-row blocks (partitions of about 4096 rows): one partition bit
-// fewer than with 4096 (longer scatter runs, half the work units), while the
-// write pass's gathers from an R partition still hit L2. Larger partitions
-// (16384-row blocks) make the scatter faster still but the gathers slower.
-inline int join_default_r_block(uint64_t n_r) { return n_r >= (1ull << 24) ? 8192 : 4096; }
+// more use larger blocks, so that fewer partition bits (fewer, longer scatter
+// runs per pass) suffice: 16384-row blocks (partitions of about 8192 rows) for
+// GFTR with 4-byte keys when such a partition's R payload fits the staged
+// write pass's LDS, else 8192-row blocks, whose 4096-row partitions keep the
+// write pass's R gathers mostly in L2.
+inline int join_default_r_block(uint64_t n_r, int key_bytes, bool gfur, int r_pay_bytes) {
+    if (n_r < (1ull << 24)) return 4096;
+    if (!gfur && key_bytes == 4 && (size_t)8192 * (size_t)r_pay_bytes <= kJoinStagedLds) return 16384;
+    return 8192;
+}
 inline int join_default_bits(uint64_t n_r, int r_block) {
     const uint64_t target = (uint64_t)(r_block / 2 > 1 ? r_block / 2 : 1);
     const uint64_t parts = (n_r + target - 1) / target;

@@ -46,6 +46,7 @@ struct Geo {
     // workgroups per compute unit)
     static constexpr int kMinW = BUILD == 4096 ? 3 : 4;
     static constexpr int kMinWEager = BUILD == 4096 ? 1 : 4;
+    static constexpr int kMinWStaged = BUILD == 4096 ? 2 : 4;
 };
 
 struct JoinArgs {
@@ -80,8 +81,9 @@ struct JoinArgs {
     // partitioned R row, or -1) when every partition has one R block and no S row
     // matches twice; flags[0] / flags[1] mark the contrary.
     int32_t *midx;
-    uint32_t *flags;
+    uint32_t *flags;            // [2]: most R rows in one partition (for LDS staging)
     int lds_if_complex;         // LDS write pass: do nothing unless a flag is set (plans)
+    uint32_t rlds_off[8];       // staged streaming pass: byte offset of R column j in LDS
 };
 
 __global__ void k_unit_count(const uint32_t *__restrict__ rpo, const uint32_t *__restrict__ spo,
@@ -91,6 +93,7 @@ __global__ void k_unit_count(const uint32_t *__restrict__ rpo, const uint32_t *_
         const uint32_t nr = rpo[p + 1] - rpo[p], ns = spo[p + 1] - spo[p];
         ucnt[p] = (nr && ns) ? ceil_div_u32(nr, rc) * ceil_div_u32(ns, spiece) : 0u;
         if (nr > rc && ns) atomicOr(&flags[0], 1u);  // a partition spans several R blocks
+        if (ns) atomicMax(&flags[2], nr);
     }
 }
 
@@ -484,6 +487,157 @@ __global__ __launch_bounds__(kBlock) void k_join_stream(JoinArgs a) {
     }
 }
 
+// Streaming write pass with the R side staged in LDS (GFTR, one R block per
+// partition, at most one match per S row): a workgroup takes one unit (an S
+// piece of one partition), copies the partition's R payload columns into LDS
+// with coalesced reads, and streams the S piece as k_join_stream does, reading
+// R values from LDS. Every R payload value then crosses HBM once per S piece,
+// where the gathers of k_join_stream re-read lines that L2 has dropped when a
+// compute unit's partitions outgrow its share of L2. A unit whose S piece has
+// fewer rows than its R block (cold partitions under skew) gathers from HBM
+// instead, since staging would move more bytes than it saves. Launched when
+// the largest partition's R payload fits the dynamic LDS.
+template <typename K, uint32_t BUILD>
+__global__ __launch_bounds__(Geo<BUILD>::kThreads, Geo<BUILD>::kMinWStaged) void k_join_stream_staged(JoinArgs a) {
+    using G = Geo<BUILD>;
+    constexpr int PB = 16;
+    constexpr int kWv = G::kWv;
+    constexpr int kT = G::kThreads;
+    constexpr uint32_t kSPiece = G::kSPiece;
+    extern __shared__ uint4 s_dyn4[];
+    uint8_t *s_dyn = reinterpret_cast<uint8_t *>(s_dyn4);
+    __shared__ uint32_t s_unit[4];
+    if (a.flags[0] | a.flags[1]) return;
+    const int tid = threadIdx.x, w = tid / kWave, lane = lane_id();
+    const uint32_t n_units = min(*a.nunits, a.cap_units);
+    const uint64_t out_base = a.out_base ? *a.out_base : 0ull;
+    const K *__restrict__ skey = static_cast<const K *>(a.skey);
+    K *__restrict__ tkey = static_cast<K *>(a.tkey);
+    for (uint32_t u = blockIdx.x; u < n_units; u += gridDim.x) {
+        if (tid == 0) {
+            uint32_t lo = 0, hi = a.np;  // ubase[lo] <= u < ubase[hi]
+            while (hi - lo > 1) {
+                const uint32_t mid = (lo + hi) >> 1;
+                if (a.ubase[mid] <= u) lo = mid;
+                else hi = mid;
+            }
+            const uint32_t p = lo, sb = u - a.ubase[p];  // one R block: the unit is the S piece
+            const uint32_t ns = a.spo[p + 1] - a.spo[p];
+            s_unit[0] = a.rpo[p];
+            s_unit[1] = min(a.rpo[p + 1] - a.rpo[p], a.flags[2]);  // never past the staged rows
+            s_unit[2] = a.spo[p] + sb * kSPiece;
+            s_unit[3] = min(kSPiece, ns - sb * kSPiece);
+        }
+        __syncthreads();
+        const uint32_t r0 = s_unit[0], rn = s_unit[1], s0 = s_unit[2], sn = s_unit[3];
+        const bool staged = sn >= rn;  // uniform over the workgroup
+        for (int j = 0; j < a.nr && staged; ++j) {
+            if (a.rw[j] == 4) {
+                const uint32_t *__restrict__ in = static_cast<const uint32_t *>(a.rp[j]) + r0;
+                uint32_t *d = reinterpret_cast<uint32_t *>(s_dyn + a.rlds_off[j]);
+                for (uint32_t i = tid; i < rn; i += kT) d[i] = in[i];
+            } else {
+                const uint64_t *__restrict__ in = static_cast<const uint64_t *>(a.rp[j]) + r0;
+                uint64_t *d = reinterpret_cast<uint64_t *>(s_dyn + a.rlds_off[j]);
+                for (uint32_t i = tid; i < rn; i += kT) d[i] = in[i];
+            }
+        }
+        __syncthreads();
+        const uint32_t q = ceil_div_u32(sn, kWv);
+        const uint32_t ws = min(sn, w * q), we = min(sn, ws + q);
+        // output rows of this wave: wbase + a 32-bit offset (a wave writes at most q rows)
+        const uint64_t wbase = out_base + a.woff[(uint64_t)u * kWv + w];
+        const uint32_t lim = a.t_rows > wbase ? (uint32_t)min<uint64_t>(a.t_rows - wbase, 0xFFFFFFFFull) : 0u;
+        uint32_t off = 0;
+        for (uint32_t base = ws; base < we; base += PB * kWave) {
+            // lrow[r]: LDS row of the match, or ~0 (no match, or a row past the
+            // staged block, impossible when the count pass ran on the same input)
+            uint32_t lrow[PB], pos[PB];
+            {
+                int32_t m[PB];
+                K key[PB];
+                const int32_t *__restrict__ mp = a.midx + (s0 + base + lane);
+                const K *__restrict__ kp = skey + (s0 + base + lane);
+#pragma unroll
+                for (int r = 0; r < PB; ++r) {
+                    const bool in = base + r * kWave + lane < we;
+                    m[r] = in ? mp[r * kWave] : -1;
+                    key[r] = in ? kp[r * kWave] : K(0);
+                }
+                K *__restrict__ tk = tkey + wbase;
+#pragma unroll
+                for (int r = 0; r < PB; ++r) {
+                    const uint32_t l = (uint32_t)m[r] - r0;
+                    lrow[r] = (m[r] >= 0 && l < rn) ? l : ~0u;
+                    const uint64_t hit = __ballot(lrow[r] != ~0u);
+                    pos[r] = off + rank_below(hit);
+                    off += (uint32_t)__popcll(hit);
+                    if (lrow[r] != ~0u && pos[r] < lim) tk[pos[r]] = key[r];
+                }
+            }
+            // S payloads: contiguous partitioned rows, one base address per column
+            for (int j = 0; j < a.ns; ++j) {
+                if (a.sw[j] == 4) {
+                    const uint32_t *__restrict__ in = static_cast<const uint32_t *>(a.sp[j]) + (s0 + base + lane);
+                    uint32_t *__restrict__ out = static_cast<uint32_t *>(a.ts[j]) + wbase;
+                    uint32_t v[PB];
+#pragma unroll
+                    for (int r = 0; r < PB; ++r) v[r] = lrow[r] != ~0u ? in[r * kWave] : 0u;
+#pragma unroll
+                    for (int r = 0; r < PB; ++r)
+                        if (lrow[r] != ~0u && pos[r] < lim) out[pos[r]] = v[r];
+                } else {
+                    const uint64_t *__restrict__ in = static_cast<const uint64_t *>(a.sp[j]) + (s0 + base + lane);
+                    uint64_t *__restrict__ out = static_cast<uint64_t *>(a.ts[j]) + wbase;
+                    uint64_t v[PB];
+#pragma unroll
+                    for (int r = 0; r < PB; ++r) v[r] = lrow[r] != ~0u ? in[r * kWave] : 0ull;
+#pragma unroll
+                    for (int r = 0; r < PB; ++r)
+                        if (lrow[r] != ~0u && pos[r] < lim) out[pos[r]] = v[r];
+                }
+            }
+            // R payloads from LDS, or from the partitioned column in HBM
+            for (int j = 0; j < a.nr; ++j) {
+                if (!staged) {
+                    if (a.rw[j] == 4) {
+                        const uint32_t *__restrict__ col = static_cast<const uint32_t *>(a.rp[j]) + r0;
+                        uint32_t *__restrict__ out = static_cast<uint32_t *>(a.tr[j]) + wbase;
+                        uint32_t v[PB];
+#pragma unroll
+                        for (int r = 0; r < PB; ++r) v[r] = lrow[r] != ~0u ? col[lrow[r]] : 0u;
+#pragma unroll
+                        for (int r = 0; r < PB; ++r)
+                            if (lrow[r] != ~0u && pos[r] < lim) out[pos[r]] = v[r];
+                    } else {
+                        const uint64_t *__restrict__ col = static_cast<const uint64_t *>(a.rp[j]) + r0;
+                        uint64_t *__restrict__ out = static_cast<uint64_t *>(a.tr[j]) + wbase;
+                        uint64_t v[PB];
+#pragma unroll
+                        for (int r = 0; r < PB; ++r) v[r] = lrow[r] != ~0u ? col[lrow[r]] : 0ull;
+#pragma unroll
+                        for (int r = 0; r < PB; ++r)
+                            if (lrow[r] != ~0u && pos[r] < lim) out[pos[r]] = v[r];
+                    }
+                } else if (a.rw[j] == 4) {
+                    const uint32_t *col = reinterpret_cast<const uint32_t *>(s_dyn + a.rlds_off[j]);
+                    uint32_t *__restrict__ out = static_cast<uint32_t *>(a.tr[j]) + wbase;
+#pragma unroll
+                    for (int r = 0; r < PB; ++r)
+                        if (lrow[r] != ~0u && pos[r] < lim) out[pos[r]] = col[lrow[r]];
+                } else {
+                    const uint64_t *col = reinterpret_cast<const uint64_t *>(s_dyn + a.rlds_off[j]);
+                    uint64_t *__restrict__ out = static_cast<uint64_t *>(a.tr[j]) + wbase;
+#pragma unroll
+                    for (int r = 0; r < PB; ++r)
+                        if (lrow[r] != ~0u && pos[r] < lim) out[pos[r]] = col[lrow[r]];
+                }
+            }
+        }
+        __syncthreads();  // the next unit restages the LDS
+    }
+}
+
 // Persistent workgroups over the unit count held in device memory (plans).
 template <typename K, uint32_t BUILD, bool WRITE>
 __global__ __launch_bounds__(Geo<BUILD>::kThreads, Geo<BUILD>::kMinW) void k_join_persist(JoinArgs a) {
@@ -535,19 +689,24 @@ struct JoinKernels {
         grid = (uint32_t)std::min<uint64_t>((uint64_t)grid * G::kWv / kWaves, 1u << 30);
         GJ_LAUNCH("k_join_write", bytes, (k_join_stream<K, BUILD>), dim3(grid), dim3(kBlock), 0, s, a);
     }
+    static void staged(hipStream_t s, uint32_t grid, size_t shm, const JoinArgs &a, double bytes) {
+        GJ_LAUNCH("k_join_write", bytes, (k_join_stream_staged<K, BUILD>), dim3(grid), dim3(G::kThreads), shm, s, a);
+    }
     static void write_lds(hipStream_t s, bool planned, uint32_t grid, const JoinArgs &a, double bytes) {
         if (planned) GJ_LAUNCH("k_join_write_lds", bytes, (k_join_persist<K, BUILD, true>), dim3(grid), dim3(G::kThreads), 0, s, a);
         else GJ_LAUNCH("k_join_write_lds", bytes, (k_join<K, BUILD, true>), dim3(grid), dim3(G::kThreads), 0, s, a);
     }
 };
 
-// Pass 0 = count, 1 = streaming write, 2 = LDS write; the table shape holds r_block rows.
+// Pass 0 = count, 1 = streaming write, 2 = LDS write, 3 = streaming write with
+// the R side staged in shm bytes of LDS; the table shape holds r_block rows.
 void launch_join_pass(int pass, int key_bytes, uint32_t table_rows, hipStream_t s, bool planned, uint32_t grid,
-                      const JoinArgs &a, double bytes) {
+                      const JoinArgs &a, double bytes, size_t shm = 0) {
 #define GJ_JP(K, B)                                                 \
     do {                                                            \
         if (pass == 0) JoinKernels<K, B>::count(s, planned, grid, a, bytes);     \
         else if (pass == 1) JoinKernels<K, B>::stream(s, grid, a, bytes);        \
+        else if (pass == 3) JoinKernels<K, B>::staged(s, grid, shm, a, bytes);   \
         else JoinKernels<K, B>::write_lds(s, planned, grid, a, bytes);           \
     } while (0)
     if (key_bytes == 4) {
@@ -563,6 +722,16 @@ void launch_join_pass(int pass, int key_bytes, uint32_t table_rows, hipStream_t 
 
 uint32_t waves_per_unit(uint32_t table_rows) { return table_rows / 16 / kWave; }
 
+// Largest LDS the staged streaming pass may take (GJ_JOIN_STAGED_LDS overrides;
+// 0 turns the staged pass off).
+size_t staged_lds_limit() {
+    static const size_t lim = [] {
+        if (const char *e = getenv("GJ_JOIN_STAGED_LDS")) return (size_t)strtoull(e, nullptr, 10);
+        return kJoinStagedLds;
+    }();
+    return lim;
+}
+
 }  // namespace
 
 int64_t join_partitioned(Ctx &ctx, int key_bytes, const JoinSide &R, const JoinSide &S, int bits,
@@ -575,8 +744,8 @@ int64_t join_partitioned(Ctx &ctx, int key_bytes, const JoinSide &R, const JoinS
     const uint32_t wpu = waves_per_unit(table_rows);
     const uint32_t np = seg_bits ? (n_inst << 8) : (1u << bits);
     uint32_t *ucnt = ctx.scratch_n<uint32_t>(np + 1);
-    uint32_t *flags = ctx.scratch_n<uint32_t>(2);
-    fill_u32(s, flags, 0u, 2);
+    uint32_t *flags = ctx.scratch_n<uint32_t>(3);
+    fill_u32(s, flags, 0u, 3);
     GJ_LAUNCH("k_unit_count", 20.0 * np, k_unit_count, dim3(std::min<uint32_t>((np + 255) / 256, 1024)),
               dim3(256), 0, s, R.poff, S.poff, np, (uint32_t)r_block, join_s_piece(r_block), ucnt, flags);
     scan_exclusive_u32(ctx, ucnt, ucnt, np, ucnt + np);
@@ -624,15 +793,17 @@ int64_t join_partitioned(Ctx &ctx, int key_bytes, const JoinSide &R, const JoinS
     else scan_exclusive_u64(ctx, wcnt, wcnt, nw, total);
     uint64_t T;
     bool complex = true;  // plans launch both write passes; each decides on the device
+    uint32_t max_r_rows = 0;
     if (pl) {
         T = pl->out_cap;  // stores are checked against the capacity; the true count stays on the device
         *out = pl->out;
     } else {
-        uint32_t hf[2];
+        uint32_t hf[3];
         GJ_HIP(hipMemcpyAsync(&T, total, 8, hipMemcpyDeviceToHost, s));
-        GJ_HIP(hipMemcpyAsync(hf, flags, 8, hipMemcpyDeviceToHost, s));
+        GJ_HIP(hipMemcpyAsync(hf, flags, 12, hipMemcpyDeviceToHost, s));
         GJ_HIP(hipStreamSynchronize(s));
         complex = (hf[0] | hf[1]) != 0;
+        max_r_rows = hf[2];
     }
     if (inst_off)
         GJ_LAUNCH("k_instance_offsets", 16.0 * n_inst, k_instance_offsets,
@@ -677,9 +848,20 @@ int64_t join_partitioned(Ctx &ctx, int key_bytes, const JoinSide &R, const JoinS
     else wbytes += nrows_r * rw_sum + nrows_s * sw_sum;
     // the streaming pass reads no R keys
     const double sbytes = wbytes - nrows_r * key_bytes;
+    // Eager GFTR calls stage the R side in LDS when the largest partition's R
+    // payload fits (staged_lds_limit() bytes).
+    size_t shm = 0;
+    if (!pl && !complex && !gfur && R.n_pay > 0) {
+        for (int j = 0; j < R.n_pay; ++j) {
+            a.rlds_off[j] = (uint32_t)shm;
+            shm += ((size_t)max_r_rows * R.width[j] + 15) & ~(size_t)15;
+        }
+        if (shm > staged_lds_limit()) shm = 0;
+    }
     // Eager calls launch the one write pass the count pass chose; plans launch
     // both, and the one that does not apply returns at once.
-    if (pl || !complex) launch_join_pass(1, key_bytes, table_rows, s, pl != nullptr, grid, a, sbytes);
+    if (shm) launch_join_pass(3, key_bytes, table_rows, s, false, grid, a, sbytes, shm);
+    else if (pl || !complex) launch_join_pass(1, key_bytes, table_rows, s, pl != nullptr, grid, a, sbytes);
     if (pl || complex) {
         const double lbytes = pl ? 0.0 : wbytes;  // a plan counts its bytes once, on the streaming pass
         launch_join_pass(2, key_bytes, table_rows, s, pl != nullptr, grid, a, lbytes);

@@ -52,15 +52,15 @@ int passes_for(double rows) {
 }
 
 // Partition passes of a join over R rows with the default build block.
-int join_passes_for(double rows) {
+int join_passes_for(double rows, int key_bytes, int r_pay_bytes) {
     const uint64_t n = (uint64_t)std::max(1.0, rows);
-    return join_default_bits(n, join_default_r_block(n)) > 8 ? 2 : 1;
+    return join_default_bits(n, join_default_r_block(n, key_bytes, false, r_pay_bytes)) > 8 ? 2 : 1;
 }
 
 void cost_join(const Workload &x, double *t) {
     const double R = x.nr, S = x.ns, w = x.w;
     const double T = x.mr * S;  // PK-FK
-    const double P = join_passes_for(R);
+    const double P = join_passes_for(R, w > 4.0 ? 8 : 4, (int)(4.0 * x.cr));
     const double r = 4.0 * x.cr, s = 4.0 * x.cs;
     const double hist = P * w * (R + S), count = w * (R + S);
     const double gftr = hist + 2 * P * ((w + r) * R + (w + s) * S) + count + w * (R + S) + r * R + s * S +

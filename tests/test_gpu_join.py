@@ -87,6 +87,21 @@ def test_large_table_shapes(budget, kb):
     check(d, "gfur", lds_budget=budget, radix_bits=1)
 
 
+@pytest.mark.parametrize("kb", [4, 8])
+def test_staged_write_units(kb):
+    """GFTR PK-FK joins take the staged streaming write: a unit copies its R
+    partition's payloads into LDS when its S piece has at least as many rows,
+    else gathers them from HBM. Skewed FKs and |S| < |R| give both kinds of unit
+    in one call; 8-byte payloads use the 8-byte LDS columns."""
+    d = datagen.pk_fk_join(60000, 20000, 2, 1, seed=61, key_bytes=kb, alpha=1.0)
+    check(d, "gftr", radix_bits=4)
+    d = datagen.pk_fk_join(30000, 200000, 1, 2, seed=62, key_bytes=kb, match_ratio=0.5)
+    g = datagen.rng(63)
+    d["r_pay"].append(g.integers(-2**62, 2**62, size=30000, dtype=np.int64))
+    check(d, "gftr", radix_bits=3)
+    check(d, "gftr", lds_budget=8192)
+
+
 def test_edge_cases():
     g = datagen.rng(0)
     empty = np.zeros(0, np.int32)
