@@ -25,6 +25,7 @@ namespace gj {
 namespace {
 
 constexpr uint32_t kMaxChainSort = 32;
+constexpr uint16_t kNoMatch = 0xFFFF;  // blocks hold at most 16384 rows
 constexpr uint32_t kPersistentGrid = 4096;  // workgroups of a plan's count and write passes
 
 // Shape of a work unit for a table of BUILD rows: threads, waves, S piece rows,
@@ -77,10 +78,10 @@ struct JoinArgs {
     const uint32_t *nunits;     // device: work units (the kernels loop over them)
     uint32_t cap_units;         // units beyond this are not processed (a plan's capacity)
     const uint64_t *out_base;   // device: first output row of this call (nullptr = 0)
-    // Streaming write path: the count pass records each S row's match (its
-    // partitioned R row, or -1) when every partition has one R block and no S row
-    // matches twice; flags[0] / flags[1] mark the contrary.
-    int32_t *midx;
+    // Streaming write path: the count pass records each S row's match (its row
+    // in the R block, or kNoMatch), used when every partition has one R block
+    // and no S row matches twice; flags[0] / flags[1] mark the contrary.
+    uint16_t *midx;
     uint32_t *flags;            // [2]: most R rows in one partition (for LDS staging)
     int lds_if_complex;         // LDS write pass: do nothing unless a flag is set (plans)
     uint32_t rlds_off[8];       // staged streaming pass: byte offset of R column j in LDS
@@ -128,6 +129,66 @@ __device__ __forceinline__ void gather_cols(int ncols, const void *const *src, c
 #pragma unroll
             for (int r = 0; r < PB; ++r)
                 if (c[r] && pos[r] < t_rows) out[pos[r]] = v[r];
+        }
+    }
+}
+
+// Column moves of the streaming passes. Rows whose lrow[r] is ~0 have no match;
+// output row = wbase + pos[r] (a 32-bit offset within the wave's range), dropped
+// unless pos[r] < lim. gather_cols_wave reads src[j][rbase + row[r]];
+// stream_cols_contig reads the contiguous rows row0 + r * 64 (one base address).
+template <int PB>
+__device__ __forceinline__ void gather_cols_wave(int ncols, const void *const *src, const int *width,
+                                                 void *const *dst, uint32_t rbase, const void *unused,
+                                                 const uint32_t *row, const uint32_t *lrow, const uint32_t *pos,
+                                                 uint64_t wbase, uint32_t lim) {
+    (void)unused;
+    for (int j = 0; j < ncols; ++j) {
+        if (width[j] == 4) {
+            const uint32_t *__restrict__ in = static_cast<const uint32_t *>(src[j]) + rbase;
+            uint32_t *__restrict__ out = static_cast<uint32_t *>(dst[j]) + wbase;
+            uint32_t v[PB];
+#pragma unroll
+            for (int r = 0; r < PB; ++r) v[r] = lrow[r] != ~0u ? in[row[r]] : 0u;
+#pragma unroll
+            for (int r = 0; r < PB; ++r)
+                if (lrow[r] != ~0u && pos[r] < lim) out[pos[r]] = v[r];
+        } else {
+            const uint64_t *__restrict__ in = static_cast<const uint64_t *>(src[j]) + rbase;
+            uint64_t *__restrict__ out = static_cast<uint64_t *>(dst[j]) + wbase;
+            uint64_t v[PB];
+#pragma unroll
+            for (int r = 0; r < PB; ++r) v[r] = lrow[r] != ~0u ? in[row[r]] : 0ull;
+#pragma unroll
+            for (int r = 0; r < PB; ++r)
+                if (lrow[r] != ~0u && pos[r] < lim) out[pos[r]] = v[r];
+        }
+    }
+}
+
+template <int PB>
+__device__ __forceinline__ void stream_cols_contig(int ncols, const void *const *src, const int *width,
+                                                   void *const *dst, uint32_t row0, const uint32_t *lrow,
+                                                   const uint32_t *pos, uint64_t wbase, uint32_t lim) {
+    for (int j = 0; j < ncols; ++j) {
+        if (width[j] == 4) {
+            const uint32_t *__restrict__ in = static_cast<const uint32_t *>(src[j]) + row0;
+            uint32_t *__restrict__ out = static_cast<uint32_t *>(dst[j]) + wbase;
+            uint32_t v[PB];
+#pragma unroll
+            for (int r = 0; r < PB; ++r) v[r] = lrow[r] != ~0u ? in[r * kWave] : 0u;
+#pragma unroll
+            for (int r = 0; r < PB; ++r)
+                if (lrow[r] != ~0u && pos[r] < lim) out[pos[r]] = v[r];
+        } else {
+            const uint64_t *__restrict__ in = static_cast<const uint64_t *>(src[j]) + row0;
+            uint64_t *__restrict__ out = static_cast<uint64_t *>(dst[j]) + wbase;
+            uint64_t v[PB];
+#pragma unroll
+            for (int r = 0; r < PB; ++r) v[r] = lrow[r] != ~0u ? in[r * kWave] : 0ull;
+#pragma unroll
+            for (int r = 0; r < PB; ++r)
+                if (lrow[r] != ~0u && pos[r] < lim) out[pos[r]] = v[r];
         }
     }
 }
@@ -254,48 +315,53 @@ __device__ __forceinline__ void join_unit(const JoinArgs &a, uint32_t u, uint64_
         s_entry[slot] = (uint16_t)i;
     }
     __syncthreads();
-    for (uint32_t b = tid; b < nb; b += kBlockT) {
-        const uint32_t lo = s_b[b], hi = s_b[b + 1];
-        if (hi - lo > kMaxChainSort) {
-            s_long = 1;
-        } else {
-            for (uint32_t x = lo + 1; x < hi; ++x) {
-                const uint16_t e = s_entry[x];
-                uint32_t y = x;
-                while (y > lo && s_entry[y - 1] > e) {
-                    s_entry[y] = s_entry[y - 1];
-                    --y;
-                }
-                s_entry[y] = e;
-            }
-        }
-    }
-    __syncthreads();
-    if (s_long) {
-        // Rare (heavy duplicate keys): one wave places all rows again in row
-        // order, ranking equal buckets within a round by ballot.
-        if (w == 0) {
-            for (uint32_t base = 0; base < rn; base += kWave) {
-                const uint32_t i = base + lane;
-                const bool valid = i < rn;
-                const uint32_t b = valid ? bucket_of<K>(s_rkey[i], skip_bits, log2nb) : 0u;
-                const uint64_t peers = match_peers(b, log2nb, valid);
-                if (valid) {
-                    const uint32_t rk = rank_below(peers);
-                    const uint32_t st = s_b[b];
-                    if (rk == 0) s_b[b] = st + (uint32_t)__popcll(peers);
-                    s_entry[st + rk] = (uint16_t)i;
+    // Chains in row order only matter when rows are written: counts do not depend
+    // on the order, and the count pass's record of the first match is used only
+    // when no S row matches twice.
+    if constexpr (WRITE) {
+        for (uint32_t b = tid; b < nb; b += kBlockT) {
+            const uint32_t lo = s_b[b], hi = s_b[b + 1];
+            if (hi - lo > kMaxChainSort) {
+                s_long = 1;
+            } else {
+                for (uint32_t x = lo + 1; x < hi; ++x) {
+                    const uint16_t e = s_entry[x];
+                    uint32_t y = x;
+                    while (y > lo && s_entry[y - 1] > e) {
+                        s_entry[y] = s_entry[y - 1];
+                        --y;
+                    }
+                    s_entry[y] = e;
                 }
             }
-            // s_b[b] now holds the end of bucket b: shift right by one, top down
-            for (int c = (int)((nb + kWave - 1) / kWave) - 1; c >= 0; --c) {
-                const uint32_t b = (uint32_t)c * kWave + lane;
-                const uint32_t v = b < nb ? s_b[b] : 0u;
-                if (b < nb) s_b[b + 1] = v;
-            }
-            if (lane == 0) s_b[0] = 0;
         }
         __syncthreads();
+        if (s_long) {
+            // Rare (heavy duplicate keys): one wave places all rows again in row
+            // order, ranking equal buckets within a round by ballot.
+            if (w == 0) {
+                for (uint32_t base = 0; base < rn; base += kWave) {
+                    const uint32_t i = base + lane;
+                    const bool valid = i < rn;
+                    const uint32_t b = valid ? bucket_of<K>(s_rkey[i], skip_bits, log2nb) : 0u;
+                    const uint64_t peers = match_peers(b, log2nb, valid);
+                    if (valid) {
+                        const uint32_t rk = rank_below(peers);
+                        const uint32_t st = s_b[b];
+                        if (rk == 0) s_b[b] = st + (uint32_t)__popcll(peers);
+                        s_entry[st + rk] = (uint16_t)i;
+                    }
+                }
+                // s_b[b] now holds the end of bucket b: shift right by one, top down
+                for (int c = (int)((nb + kWave - 1) / kWave) - 1; c >= 0; --c) {
+                    const uint32_t b = (uint32_t)c * kWave + lane;
+                    const uint32_t v = b < nb ? s_b[b] : 0u;
+                    if (b < nb) s_b[b + 1] = v;
+                }
+                if (lane == 0) s_b[0] = 0;
+            }
+            __syncthreads();
+        }
     }
     {
         // keys in bucket order (s_rkey[e] = key of entry e), so that a probe
@@ -342,7 +408,7 @@ __device__ __forceinline__ void join_unit(const JoinArgs &a, uint32_t u, uint64_
                 if (valid[r]) {
                     cnt += c[r];
                     multi |= c[r] > 1;
-                    if (a.midx) a.midx[s0 + i] = c[r] ? (int32_t)(r0 + s_entry[e1[r]]) : -1;
+                    if (a.midx) a.midx[s0 + i] = c[r] ? s_entry[e1[r]] : kNoMatch;
                 }
             }
         }
@@ -429,8 +495,8 @@ __global__ __launch_bounds__(Geo<BUILD>::kThreads, Geo<BUILD>::kMinWEager) void 
 // partition-local R rows; GFUR: original rows through the row ids). It needs no
 // LDS, so it always runs 256-thread workgroups whose waves take the count
 // pass's (unit, wave) slots one by one, whatever the table shape.
-template <typename K, uint32_t BUILD>
-__global__ __launch_bounds__(kBlock) void k_join_stream(JoinArgs a) {
+template <typename K, uint32_t BUILD, bool GFUR>
+__global__ __launch_bounds__(kBlock, GFUR ? 4 : 1) void k_join_stream(JoinArgs a) {
     using G = Geo<BUILD>;
     constexpr int PB = 16;
     constexpr int kWv = G::kWv;
@@ -454,35 +520,52 @@ __global__ __launch_bounds__(kBlock) void k_join_stream(JoinArgs a) {
         const uint32_t p = lo, sb = u - a.ubase[p];  // one R block: the unit is the S piece
         const uint32_t ns = a.spo[p + 1] - a.spo[p];
         const uint32_t s0 = a.spo[p] + sb * kSPiece, sn = min(kSPiece, ns - sb * kSPiece);
+        const uint32_t r0 = a.rpo[p], rn = a.rpo[p + 1] - r0;
         const uint32_t q = ceil_div_u32(sn, kWv);
         const uint32_t ws = min(sn, w * q), we = min(sn, ws + q);
-        uint64_t outpos = out_base + a.woff[slot];
+        // output rows of this wave: wbase + a 32-bit offset (a wave writes at most q rows)
+        const uint64_t wbase = out_base + a.woff[slot];
+        const uint32_t lim = a.t_rows > wbase ? (uint32_t)min<uint64_t>(a.t_rows - wbase, 0xFFFFFFFFull) : 0u;
+        uint32_t off = 0;
         for (uint32_t base = ws; base < we; base += PB * kWave) {
-            int32_t m[PB];
-            K key[PB];
+            // lrow[r]: the match's row in the R block, or ~0 (none; a recorded row
+            // past the block is impossible when the count pass ran on this input)
+            uint32_t lrow[PB], pos[PB];
+            {
+                uint32_t m[PB];
+                K key[PB];
+                const uint16_t *__restrict__ mp = a.midx + (s0 + base + lane);
+                const K *__restrict__ kp = skey + (s0 + base + lane);
 #pragma unroll
-            for (int r = 0; r < PB; ++r) {
-                const uint32_t i = base + r * kWave + lane;
-                m[r] = i < we ? a.midx[s0 + i] : -1;
-                key[r] = i < we ? skey[s0 + i] : K(0);
-            }
-            uint32_t c[PB], srow[PB], rrow[PB];
-            uint64_t pos[PB];
+                for (int r = 0; r < PB; ++r) {
+                    const bool in = base + r * kWave + lane < we;
+                    m[r] = in ? mp[r * kWave] : kNoMatch;
+                    key[r] = in ? kp[r * kWave] : K(0);
+                }
+                K *__restrict__ tk = tkey + wbase;
 #pragma unroll
-            for (int r = 0; r < PB; ++r) {
-                c[r] = m[r] >= 0;
-                const uint64_t hit = __ballot(c[r] != 0);
-                pos[r] = outpos + rank_below(hit);
-                outpos += (uint64_t)__popcll(hit);
-                if (c[r] && pos[r] < a.t_rows) tkey[pos[r]] = key[r];
-                const uint32_t i = base + r * kWave + lane;
-                srow[r] = s0 + i;
-                rrow[r] = c[r] ? (uint32_t)m[r] : 0u;
-                if (a.srow && c[r]) srow[r] = (uint32_t)a.srow[srow[r]];
-                if (a.rrow && c[r]) rrow[r] = (uint32_t)a.rrow[rrow[r]];
+                for (int r = 0; r < PB; ++r) {
+                    lrow[r] = m[r] < rn ? m[r] : ~0u;
+                    const uint64_t hit = __ballot(lrow[r] != ~0u);
+                    pos[r] = off + rank_below(hit);
+                    off += (uint32_t)__popcll(hit);
+                    if (lrow[r] != ~0u && pos[r] < lim) tk[pos[r]] = key[r];
+                }
             }
-            gather_cols<PB>(a.ns, a.sp, a.sw, a.ts, srow, c, pos, a.t_rows);
-            gather_cols<PB>(a.nr, a.rp, a.rw, a.tr, rrow, c, pos, a.t_rows);
+            if constexpr (!GFUR) {
+                // GFTR: S rows are contiguous, R rows partition-local
+                stream_cols_contig<PB>(a.ns, a.sp, a.sw, a.ts, s0 + base + lane, lrow, pos, wbase, lim);
+                gather_cols_wave<PB>(a.nr, a.rp, a.rw, a.tr, r0, nullptr, lrow, lrow, pos, wbase, lim);
+            } else {
+                // GFUR: original rows through the row ids
+                uint32_t row[PB];
+#pragma unroll
+                for (int r = 0; r < PB; ++r) row[r] = lrow[r] != ~0u ? (uint32_t)a.srow[s0 + base + r * kWave + lane] : 0u;
+                gather_cols_wave<PB>(a.ns, a.sp, a.sw, a.ts, 0u, nullptr, row, lrow, pos, wbase, lim);
+#pragma unroll
+                for (int r = 0; r < PB; ++r) row[r] = lrow[r] != ~0u ? (uint32_t)a.rrow[r0 + lrow[r]] : 0u;
+                gather_cols_wave<PB>(a.nr, a.rp, a.rw, a.tr, 0u, nullptr, row, lrow, pos, wbase, lim);
+            }
         }
     }
 }
@@ -554,21 +637,20 @@ __global__ __launch_bounds__(Geo<BUILD>::kThreads, Geo<BUILD>::kMinWStaged) void
             // staged block, impossible when the count pass ran on the same input)
             uint32_t lrow[PB], pos[PB];
             {
-                int32_t m[PB];
+                uint32_t m[PB];
                 K key[PB];
-                const int32_t *__restrict__ mp = a.midx + (s0 + base + lane);
+                const uint16_t *__restrict__ mp = a.midx + (s0 + base + lane);
                 const K *__restrict__ kp = skey + (s0 + base + lane);
 #pragma unroll
                 for (int r = 0; r < PB; ++r) {
                     const bool in = base + r * kWave + lane < we;
-                    m[r] = in ? mp[r * kWave] : -1;
+                    m[r] = in ? mp[r * kWave] : kNoMatch;
                     key[r] = in ? kp[r * kWave] : K(0);
                 }
                 K *__restrict__ tk = tkey + wbase;
 #pragma unroll
                 for (int r = 0; r < PB; ++r) {
-                    const uint32_t l = (uint32_t)m[r] - r0;
-                    lrow[r] = (m[r] >= 0 && l < rn) ? l : ~0u;
+                    lrow[r] = m[r] < rn ? m[r] : ~0u;
                     const uint64_t hit = __ballot(lrow[r] != ~0u);
                     pos[r] = off + rank_below(hit);
                     off += (uint32_t)__popcll(hit);
@@ -687,7 +769,8 @@ struct JoinKernels {
     // grid: workgroups of the unit passes; the streaming pass has kWaves-wave workgroups
     static void stream(hipStream_t s, uint32_t grid, const JoinArgs &a, double bytes) {
         grid = (uint32_t)std::min<uint64_t>((uint64_t)grid * G::kWv / kWaves, 1u << 30);
-        GJ_LAUNCH("k_join_write", bytes, (k_join_stream<K, BUILD>), dim3(grid), dim3(kBlock), 0, s, a);
+        if (a.srow) GJ_LAUNCH("k_join_write", bytes, (k_join_stream<K, BUILD, true>), dim3(grid), dim3(kBlock), 0, s, a);
+        else GJ_LAUNCH("k_join_write", bytes, (k_join_stream<K, BUILD, false>), dim3(grid), dim3(kBlock), 0, s, a);
     }
     static void staged(hipStream_t s, uint32_t grid, size_t shm, const JoinArgs &a, double bytes) {
         GJ_LAUNCH("k_join_write", bytes, (k_join_stream_staged<K, BUILD>), dim3(grid), dim3(G::kThreads), shm, s, a);
@@ -779,7 +862,7 @@ int64_t join_partitioned(Ctx &ctx, int key_bytes, const JoinSide &R, const JoinS
     a.nunits = ucnt + np;
     a.cap_units = cap_units;
     a.out_base = pl ? pl->out_base : nullptr;
-    a.midx = ctx.scratch_n<int32_t>(std::max<uint32_t>(S.rows, 1));
+    a.midx = ctx.scratch_n<uint16_t>(std::max<uint32_t>(S.rows, 1));
     a.flags = flags;
     a.lds_if_complex = pl ? 1 : 0;
     const uint64_t nw = (uint64_t)cap_units * wpu;
