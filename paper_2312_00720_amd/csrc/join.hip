@@ -239,38 +239,153 @@ __device__ __forceinline__ void probe_rows(const K *s_rkey, const uint32_t *s_b,
     }
 }
 
-template <typename K, uint32_t BUILD, bool WRITE>
-__device__ __forceinline__ void join_unit(const JoinArgs &a, uint32_t u, uint64_t out_base, JoinShared<K, BUILD> &sh) {
+// Unit u of the (R block) x (S piece) decomposition: s_unit[0..5] = first R
+// row, R rows, first S row, S rows, partition bits, extra bucket bits.
+template <uint32_t kSPiece>
+__device__ __forceinline__ void decode_unit(const JoinArgs &a, uint32_t u, uint32_t *s_unit) {
+    uint32_t lo = 0, hi = a.np;  // ubase[lo] <= u < ubase[hi] (ubase[np] = units)
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (a.ubase[mid] <= u) lo = mid;
+        else hi = mid;
+    }
+    const uint32_t p = lo;
+    const uint32_t nr = a.rpo[p + 1] - a.rpo[p], ns = a.spo[p + 1] - a.spo[p];
+    const uint32_t nsb = ceil_div_u32(ns, kSPiece);
+    const uint32_t local = u - a.ubase[p];
+    const uint32_t ra = local / nsb, sb = local % nsb;
+    s_unit[0] = a.rpo[p] + ra * a.rc;
+    s_unit[1] = min(a.rc, nr - ra * a.rc);
+    s_unit[2] = a.spo[p] + sb * kSPiece;
+    s_unit[3] = min(kSPiece, ns - sb * kSPiece);
+    s_unit[4] = a.seg_bits ? a.seg_bits[p >> 8] : (uint32_t)a.skip_bits;
+    s_unit[5] = a.seg_bshift ? a.seg_bshift[p >> 8] : (uint32_t)a.bshift;
+}
+
+// Inclusive scan of the nb bucket counts in s_b (s_b[b] = end of bucket b), and
+// s_b[nb] = rn.
+template <uint32_t BUILD>
+__device__ __forceinline__ void scan_buckets(uint32_t *s_b, uint32_t *s_tmp, uint32_t nb, uint32_t rn) {
     using G = Geo<BUILD>;
-    constexpr int PB = WRITE ? G::kPBWrite : G::kPB;
+    constexpr int per = (int)((G::kMaxNb + G::kThreads - 1) / G::kThreads);
+    const uint32_t first = threadIdx.x * per;
+    uint32_t v[per];
+    uint32_t sum = 0;
+#pragma unroll
+    for (int k = 0; k < per; ++k) {
+        v[k] = (first + k < nb) ? s_b[first + k] : 0u;
+        sum += v[k];
+    }
+    uint32_t run = block_exclusive_sum<uint32_t, G::kWv>(sum, s_tmp, (uint32_t *)nullptr);
+#pragma unroll
+    for (int k = 0; k < per; ++k) {
+        run += v[k];
+        if (first + k < nb) s_b[first + k] = run;
+    }
+    if (threadIdx.x == 0) s_b[nb] = rn;
+}
+
+// Count pass of unit u: matches per (unit, wave), each S row's match recorded
+// for the streaming write pass, and the flag for S rows with several matches.
+// The table is built straight into bucket order from registers (the R keys of
+// this thread: counts, scan, placement), since counts need no ordered chains;
+// the wave's first round of S keys loads during the build.
+template <typename K, uint32_t BUILD>
+__device__ __forceinline__ void count_unit(const JoinArgs &a, uint32_t u, JoinShared<K, BUILD> &sh) {
+    using G = Geo<BUILD>;
+    constexpr int PB = G::kPB;
+    constexpr int kT = G::kThreads;
+    constexpr int kWv = G::kWv;
+    constexpr int PER = (int)(BUILD / kT);
+    K *s_rkey = sh.rkey;
+    uint32_t *s_b = sh.b;
+    uint16_t *s_entry = sh.entry;
+    uint32_t *s_unit = sh.unit;
+    const int tid = threadIdx.x, w = tid / kWave, lane = lane_id();
+    if (tid == 0) decode_unit<G::kSPiece>(a, u, s_unit);
+    __syncthreads();
+    const uint32_t r0 = s_unit[0], rn = s_unit[1], s0 = s_unit[2], sn = s_unit[3];
+    const int skip_bits = (int)s_unit[4];
+    int log2nb = 0;
+    while ((1u << log2nb) < rn) ++log2nb;
+    log2nb = min(log2nb + (int)s_unit[5], G::kMaxLog2nb);
+    const uint32_t nb = 1u << log2nb;
+
+    // loads in flight during the build: this thread's R keys, its wave's first S keys
+    const K *__restrict__ rk = static_cast<const K *>(a.rkey) + r0;
+    K kr[PER];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) kr[k] = (uint32_t)(tid + k * kT) < rn ? rk[tid + k * kT] : K(0);
+    const uint32_t q = ceil_div_u32(sn, kWv);
+    const uint32_t ws = min(sn, w * q), we = min(sn, ws + q);
+    const K *__restrict__ skey = static_cast<const K *>(a.skey) + s0;
+    K key[PB];
+#pragma unroll
+    for (int r = 0; r < PB; ++r) key[r] = ws + r * kWave + lane < we ? skey[ws + r * kWave + lane] : K(0);
+
+    for (uint32_t b = tid; b <= nb; b += kT) s_b[b] = 0;
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < PER; ++k)
+        if ((uint32_t)(tid + k * kT) < rn) atomicAdd(&s_b[bucket_of<K>(kr[k], skip_bits, log2nb)], 1u);
+    __syncthreads();
+    scan_buckets<BUILD>(s_b, sh.tmp, nb, rn);
+    __syncthreads();
+    // placement from the end of each bucket; afterwards s_b[b] = start of bucket b
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        if ((uint32_t)(tid + k * kT) < rn) {
+            const uint32_t slot = atomicSub(&s_b[bucket_of<K>(kr[k], skip_bits, log2nb)], 1u) - 1u;
+            s_rkey[slot] = kr[k];
+            s_entry[slot] = (uint16_t)(tid + k * kT);
+        }
+    }
+    __syncthreads();
+
+    uint32_t cnt = 0;
+    bool multi = false;
+    for (uint32_t base = ws; base < we; base += PB * kWave) {
+        if (base != ws) {
+#pragma unroll
+            for (int r = 0; r < PB; ++r) key[r] = base + r * kWave + lane < we ? skey[base + r * kWave + lane] : K(0);
+        }
+        bool valid[PB];
+#pragma unroll
+        for (int r = 0; r < PB; ++r) valid[r] = base + r * kWave + lane < we;
+        uint32_t c[PB], e1[PB];
+        probe_rows<K, PB>(s_rkey, s_b, key, valid, skip_bits, log2nb, rn, c, e1);
+#pragma unroll
+        for (int r = 0; r < PB; ++r) {
+            if (valid[r]) {
+                cnt += c[r];
+                multi |= c[r] > 1;
+                if (a.midx) a.midx[s0 + base + r * kWave + lane] = c[r] ? s_entry[e1[r]] : kNoMatch;
+            }
+        }
+    }
+    const uint64_t tot = wave_sum<uint64_t>((uint64_t)cnt);
+    if (lane == 0) a.wcnt[(uint64_t)u * kWv + w] = tot;
+    if (a.flags && __ballot(multi) && lane == 0) atomicOr(&a.flags[1], 1u);
+}
+
+// Write pass of unit u on the LDS table (the general case: partitions spanning
+// several R blocks, or S rows with several matches): build with chains in row
+// order, probe, and write every match at the positions the count pass sized.
+template <typename K, uint32_t BUILD>
+__device__ __forceinline__ void write_unit(const JoinArgs &a, uint32_t u, uint64_t out_base, JoinShared<K, BUILD> &sh) {
+    using G = Geo<BUILD>;
+    constexpr int PB = G::kPBWrite;
     constexpr int kBlockT = G::kThreads;
     constexpr int kWv = G::kWv;
     constexpr uint32_t kSPiece = G::kSPiece;
     K *s_rkey = sh.rkey;
     uint32_t *s_b = sh.b;
     uint16_t *s_entry = sh.entry;
-    uint32_t *s_tmp = sh.tmp;
     uint32_t *s_unit = sh.unit;
     int &s_long = sh.is_long;
     const int tid = threadIdx.x, w = tid / kWave, lane = lane_id();
     if (tid == 0) {
-        uint32_t lo = 0, hi = a.np;  // ubase[lo] <= u < ubase[hi] (ubase[np] = units)
-        while (hi - lo > 1) {
-            const uint32_t mid = (lo + hi) >> 1;
-            if (a.ubase[mid] <= u) lo = mid;
-            else hi = mid;
-        }
-        const uint32_t p = lo;
-        const uint32_t nr = a.rpo[p + 1] - a.rpo[p], ns = a.spo[p + 1] - a.spo[p];
-        const uint32_t nsb = ceil_div_u32(ns, kSPiece);
-        const uint32_t local = u - a.ubase[p];
-        const uint32_t ra = local / nsb, sb = local % nsb;
-        s_unit[0] = a.rpo[p] + ra * a.rc;
-        s_unit[1] = min(a.rc, nr - ra * a.rc);
-        s_unit[2] = a.spo[p] + sb * kSPiece;
-        s_unit[3] = min(kSPiece, ns - sb * kSPiece);
-        s_unit[4] = a.seg_bits ? a.seg_bits[p >> 8] : (uint32_t)a.skip_bits;
-        s_unit[5] = a.seg_bshift ? a.seg_bshift[p >> 8] : (uint32_t)a.bshift;
+        decode_unit<kSPiece>(a, u, s_unit);
         s_long = 0;
     }
     __syncthreads();
@@ -288,25 +403,7 @@ __device__ __forceinline__ void join_unit(const JoinArgs &a, uint32_t u, uint64_
     __syncthreads();
     for (uint32_t i = tid; i < rn; i += kBlockT) atomicAdd(&s_b[bucket_of<K>(s_rkey[i], skip_bits, log2nb)], 1u);
     __syncthreads();
-    {
-        // inclusive scan of the nb counts: s_b[b] = end of bucket b
-        constexpr int per = (int)((G::kMaxNb + kBlockT - 1) / kBlockT);
-        const uint32_t first = tid * per;
-        uint32_t v[per];
-        uint32_t sum = 0;
-#pragma unroll
-        for (int k = 0; k < per; ++k) {
-            v[k] = (first + k < nb) ? s_b[first + k] : 0u;
-            sum += v[k];
-        }
-        uint32_t run = block_exclusive_sum<uint32_t, kWv>(sum, s_tmp, (uint32_t *)nullptr);
-#pragma unroll
-        for (int k = 0; k < per; ++k) {
-            run += v[k];
-            if (first + k < nb) s_b[first + k] = run;
-        }
-        if (tid == 0) s_b[nb] = rn;
-    }
+    scan_buckets<BUILD>(s_b, sh.tmp, nb, rn);
     __syncthreads();
     // placement from the end of each bucket; afterwards s_b[b] = start of bucket b
     for (uint32_t i = tid; i < rn; i += kBlockT) {
@@ -315,53 +412,49 @@ __device__ __forceinline__ void join_unit(const JoinArgs &a, uint32_t u, uint64_
         s_entry[slot] = (uint16_t)i;
     }
     __syncthreads();
-    // Chains in row order only matter when rows are written: counts do not depend
-    // on the order, and the count pass's record of the first match is used only
-    // when no S row matches twice.
-    if constexpr (WRITE) {
-        for (uint32_t b = tid; b < nb; b += kBlockT) {
-            const uint32_t lo = s_b[b], hi = s_b[b + 1];
-            if (hi - lo > kMaxChainSort) {
-                s_long = 1;
-            } else {
-                for (uint32_t x = lo + 1; x < hi; ++x) {
-                    const uint16_t e = s_entry[x];
-                    uint32_t y = x;
-                    while (y > lo && s_entry[y - 1] > e) {
-                        s_entry[y] = s_entry[y - 1];
-                        --y;
-                    }
-                    s_entry[y] = e;
+    // chains in row order, so that every S row emits its matches in R's input order
+    for (uint32_t b = tid; b < nb; b += kBlockT) {
+        const uint32_t lo = s_b[b], hi = s_b[b + 1];
+        if (hi - lo > kMaxChainSort) {
+            s_long = 1;
+        } else {
+            for (uint32_t x = lo + 1; x < hi; ++x) {
+                const uint16_t e = s_entry[x];
+                uint32_t y = x;
+                while (y > lo && s_entry[y - 1] > e) {
+                    s_entry[y] = s_entry[y - 1];
+                    --y;
+                }
+                s_entry[y] = e;
+            }
+        }
+    }
+    __syncthreads();
+    if (s_long) {
+        // Rare (heavy duplicate keys): one wave places all rows again in row
+        // order, ranking equal buckets within a round by ballot.
+        if (w == 0) {
+            for (uint32_t base = 0; base < rn; base += kWave) {
+                const uint32_t i = base + lane;
+                const bool valid = i < rn;
+                const uint32_t b = valid ? bucket_of<K>(s_rkey[i], skip_bits, log2nb) : 0u;
+                const uint64_t peers = match_peers(b, log2nb, valid);
+                if (valid) {
+                    const uint32_t rk = rank_below(peers);
+                    const uint32_t st = s_b[b];
+                    if (rk == 0) s_b[b] = st + (uint32_t)__popcll(peers);
+                    s_entry[st + rk] = (uint16_t)i;
                 }
             }
+            // s_b[b] now holds the end of bucket b: shift right by one, top down
+            for (int c = (int)((nb + kWave - 1) / kWave) - 1; c >= 0; --c) {
+                const uint32_t b = (uint32_t)c * kWave + lane;
+                const uint32_t v = b < nb ? s_b[b] : 0u;
+                if (b < nb) s_b[b + 1] = v;
+            }
+            if (lane == 0) s_b[0] = 0;
         }
         __syncthreads();
-        if (s_long) {
-            // Rare (heavy duplicate keys): one wave places all rows again in row
-            // order, ranking equal buckets within a round by ballot.
-            if (w == 0) {
-                for (uint32_t base = 0; base < rn; base += kWave) {
-                    const uint32_t i = base + lane;
-                    const bool valid = i < rn;
-                    const uint32_t b = valid ? bucket_of<K>(s_rkey[i], skip_bits, log2nb) : 0u;
-                    const uint64_t peers = match_peers(b, log2nb, valid);
-                    if (valid) {
-                        const uint32_t rk = rank_below(peers);
-                        const uint32_t st = s_b[b];
-                        if (rk == 0) s_b[b] = st + (uint32_t)__popcll(peers);
-                        s_entry[st + rk] = (uint16_t)i;
-                    }
-                }
-                // s_b[b] now holds the end of bucket b: shift right by one, top down
-                for (int c = (int)((nb + kWave - 1) / kWave) - 1; c >= 0; --c) {
-                    const uint32_t b = (uint32_t)c * kWave + lane;
-                    const uint32_t v = b < nb ? s_b[b] : 0u;
-                    if (b < nb) s_b[b + 1] = v;
-                }
-                if (lane == 0) s_b[0] = 0;
-            }
-            __syncthreads();
-        }
     }
     {
         // keys in bucket order (s_rkey[e] = key of entry e), so that a probe
@@ -387,35 +480,7 @@ __device__ __forceinline__ void join_unit(const JoinArgs &a, uint32_t u, uint64_
     const K *__restrict__ skey = static_cast<const K *>(a.skey);
     const uint32_t q = ceil_div_u32(sn, kWv);
     const uint32_t ws = min(sn, w * q), we = min(sn, ws + q);
-    if constexpr (!WRITE) {
-        uint32_t cnt = 0;
-        bool multi = false;
-        for (uint32_t base = ws; base < we; base += PB * kWave) {
-            K key[PB];
-#pragma unroll
-            for (int r = 0; r < PB; ++r) {
-                const uint32_t i = base + r * kWave + lane;
-                key[r] = i < we ? skey[s0 + i] : K(0);
-            }
-            bool valid[PB];
-#pragma unroll
-            for (int r = 0; r < PB; ++r) valid[r] = base + r * kWave + lane < we;
-            uint32_t c[PB], e1[PB];
-            probe_rows<K, PB>(s_rkey, s_b, key, valid, skip_bits, log2nb, rn, c, e1);
-#pragma unroll
-            for (int r = 0; r < PB; ++r) {
-                const uint32_t i = base + r * kWave + lane;
-                if (valid[r]) {
-                    cnt += c[r];
-                    multi |= c[r] > 1;
-                    if (a.midx) a.midx[s0 + i] = c[r] ? s_entry[e1[r]] : kNoMatch;
-                }
-            }
-        }
-        const uint64_t tot = wave_sum<uint64_t>((uint64_t)cnt);
-        if (lane == 0) a.wcnt[(uint64_t)u * kWv + w] = tot;
-        if (a.flags && __ballot(multi) && lane == 0) atomicOr(&a.flags[1], 1u);
-    } else {
+    {
         uint64_t outpos = out_base + a.woff[(uint64_t)u * kWv + w];
         K *__restrict__ tkey = static_cast<K *>(a.tkey);
         for (uint32_t base = ws; base < we; base += PB * kWave) {
@@ -479,6 +544,12 @@ __device__ __forceinline__ void join_unit(const JoinArgs &a, uint32_t u, uint64_
             }
         }
     }
+}
+
+template <typename K, uint32_t BUILD, bool WRITE>
+__device__ __forceinline__ void join_unit(const JoinArgs &a, uint32_t u, uint64_t out_base, JoinShared<K, BUILD> &sh) {
+    if constexpr (WRITE) write_unit<K, BUILD>(a, u, out_base, sh);
+    else count_unit<K, BUILD>(a, u, sh);
 }
 
 // One work unit per workgroup (eager calls: the grid is the unit count).
