@@ -378,7 +378,12 @@ __device__ __forceinline__ void scatter_tile_wide(const PassArgs &a, const Digit
                                                   K (&key)[ITEMS], uint32_t (&v)[ITEMS], uint32_t next0,
                                                   uint32_t next_nt) {
     constexpr int W = BLOCK / kWave;
-    const int tid = threadIdx.x, w = tid / kWave, lane = lane_id();
+    // the thread index passes through an empty asm statement, so that nothing
+    // derived from it is hoisted out of a caller's tile loop (it would hold
+    // registers across the whole loop)
+    int tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
+    const int w = tid / kWave, lane = tid % kWave;
     K *__restrict__ kout = static_cast<K *>(a.key_out);
     K *sk = reinterpret_cast<K *>(&s_buf[0][0]);
     uint64_t *s8 = reinterpret_cast<uint64_t *>(&s_buf[0][0]);
@@ -621,6 +626,7 @@ constexpr Shape kVariants[kScatterVariants] = {{256, 8, 4},  {512, 8, 4},  {1024
                                                {512, 16, 4}, {1024, 8, 2},  {1024, 16, 2}, {1024, 16, 1},
                                                {512, 16, 1}, {1024, 16, 0}};
 thread_local int g_variant = 0;
+
 Shape scatter_shape() {
     if (g_variant >= 1 && g_variant <= kScatterVariants) return kVariants[g_variant - 1];
     static Shape sh = [] {
