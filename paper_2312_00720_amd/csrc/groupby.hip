@@ -771,7 +771,7 @@ __global__ void k_pgb_units(const uint32_t *__restrict__ poff, const uint32_t *_
     atomicMax(max_units, mx);
 }
 
-template <typename K, int NV>
+template <typename K, int NV, int BT>
 __device__ __forceinline__ void pgb_unit(const PgbArgs &a, uint32_t u, uint64_t out_base, uint32_t *s_dyn,
                                          uint32_t *s_unit, uint32_t &s_sent_id) {
     constexpr int RB = NV <= 2 ? 8 : 16 / NV;  // rows loaded per thread before they are aggregated
@@ -806,23 +806,23 @@ __device__ __forceinline__ void pgb_unit(const PgbArgs &a, uint32_t u, uint64_t 
     const K *__restrict__ tk = static_cast<const K *>(a.tmp_keys);
     if (j == 0) {
         K *ok = static_cast<K *>(a.out_key);
-        for (uint32_t i = tid; i < g; i += kBlock) ok[gb + i] = tk[p0 + i];
+        for (uint32_t i = tid; i < g; i += BT) ok[gb + i] = tk[p0 + i];
     }
     const AggSpec &s = a.spec;
     if (g == 1) {
         // one group (case 1): registers, then a block-wide reduction
         Acc<NV> x;
         acc_clear(x);
-        for (uint32_t base = r0; base < r1; base += kBlock * RB) {
+        for (uint32_t base = r0; base < r1; base += BT * RB) {
             Row<NV> rr[RB];
 #pragma unroll
             for (int r = 0; r < RB; ++r) {
-                const uint32_t i = base + r * kBlock + tid;
+                const uint32_t i = base + r * BT + tid;
                 if (i < r1) rr[r] = load_row<NV>(a.vals, i);
             }
 #pragma unroll
             for (int r = 0; r < RB; ++r)
-                if (base + r * kBlock + tid < r1) acc_row(x, rr[r]);
+                if (base + r * BT + tid < r1) acc_row(x, rr[r]);
         }
         x = acc_wave_reduce(x);
         Acc<NV> *s_acc = reinterpret_cast<Acc<NV> *>(s_dyn);
@@ -830,7 +830,7 @@ __device__ __forceinline__ void pgb_unit(const PgbArgs &a, uint32_t u, uint64_t 
         __syncthreads();
         if (tid == 0) {
             Acc<NV> t = s_acc[0];
-            for (int w = 1; w < kWaves; ++w) acc_merge(t, s_acc[w]);
+            for (int w = 1; w < (BT / kWave); ++w) acc_merge(t, s_acc[w]);
             acc_flush(t, s, gb, multi);
         }
         return;
@@ -850,11 +850,11 @@ __device__ __forceinline__ void pgb_unit(const PgbArgs &a, uint32_t u, uint64_t 
     uint32_t *recs = reinterpret_cast<uint32_t *>(id_of + cap);
     recs = reinterpret_cast<uint32_t *>((reinterpret_cast<uintptr_t>(recs) + 7) & ~uintptr_t(7));
     const K e = empty_key<K>();
-    for (uint32_t i = tid; i < cap; i += kBlock) tab[i] = e;
+    for (uint32_t i = tid; i < cap; i += BT) tab[i] = e;
     if (lds_records)
-        for (uint32_t i = tid; i < g; i += kBlock) rec_init(recs + (uint64_t)i * s.words, s);
+        for (uint32_t i = tid; i < g; i += BT) rec_init(recs + (uint64_t)i * s.words, s);
     __syncthreads();
-    for (uint32_t i = tid; i < g; i += kBlock) {
+    for (uint32_t i = tid; i < g; i += BT) {
         const K k = tk[p0 + i];
         if (k == e) {
             s_sent_id = i;
@@ -867,18 +867,18 @@ __device__ __forceinline__ void pgb_unit(const PgbArgs &a, uint32_t u, uint64_t 
     // case 2 (records in LDS) or case 3 (global atomics); few groups per
     // partition means colliding lanes, which are combined per wave first
     const bool few = g <= 2;
-    for (uint32_t base = r0; base < r1; base += kBlock * RB) {
+    for (uint32_t base = r0; base < r1; base += BT * RB) {
         K kk[RB];
         Row<NV> rr[RB];
 #pragma unroll
         for (int r = 0; r < RB; ++r) {
-            const uint32_t i = base + r * kBlock + tid;
+            const uint32_t i = base + r * BT + tid;
             kk[r] = i < r1 ? keys[i] : e;
             if (i < r1) rr[r] = load_row<NV>(a.vals, i);
         }
 #pragma unroll
         for (int r = 0; r < RB; ++r) {
-            const bool valid = base + r * kBlock + tid < r1;
+            const bool valid = base + r * BT + tid < r1;
             uint32_t id = 0;
             if (valid) id = (kk[r] == e) ? s_sent_id : id_of[lds_find<K>(tab, log2cap, kk[r])];
             if (lds_records) {
@@ -891,12 +891,15 @@ __device__ __forceinline__ void pgb_unit(const PgbArgs &a, uint32_t u, uint64_t 
     }
     if (lds_records) {
         __syncthreads();
-        for (uint32_t i = tid; i < g; i += kBlock) rec_flush(recs + (uint64_t)i * s.words, s, gb + i, multi);
+        for (uint32_t i = tid; i < g; i += BT) rec_flush(recs + (uint64_t)i * s.words, s, gb + i, multi);
     }
 }
 
-template <typename K, int NV>
-__global__ __launch_bounds__(kBlock) void k_pgb_aggregate(PgbArgs a) {
+// BT threads per workgroup: 256, or 1024 when a partition's table and records
+// take so much LDS that only one or two workgroups fit a compute unit (many
+// groups per partition), so that the unit still runs 16 or more waves.
+template <typename K, int NV, int BT = kBlock>
+__global__ __launch_bounds__(BT) void k_pgb_aggregate(PgbArgs a) {
     extern __shared__ __align__(16) uint32_t s_dyn[];
     __shared__ uint32_t s_unit[5];
     __shared__ uint32_t s_sent_id;
@@ -904,9 +907,21 @@ __global__ __launch_bounds__(kBlock) void k_pgb_aggregate(PgbArgs a) {
     const uint64_t out_base = a.out_base ? *a.out_base : 0ull;
     // persistent: a workgroup takes units blockIdx.x, blockIdx.x + gridDim.x, ...
     for (uint32_t u = blockIdx.x; u < n_units; u += gridDim.x) {
-        pgb_unit<K, NV>(a, u, out_base, s_dyn, s_unit, s_sent_id);
+        pgb_unit<K, NV, BT>(a, u, out_base, s_dyn, s_unit, s_sent_id);
         __syncthreads();  // the unit's LDS state is rebuilt by the next one
     }
+}
+
+template <typename K, int NV>
+void launch_pgb_aggregate(bool wide, uint32_t units, size_t lds, hipStream_t st, const PgbArgs &a, double bytes) {
+    if constexpr (NV <= 2) {
+        if (wide) {
+            GJ_LAUNCH("k_pgb_aggregate", bytes, (k_pgb_aggregate<K, NV, 1024>), dim3(units), dim3(1024), lds, st, a);
+            return;
+        }
+    }
+    (void)wide;
+    GJ_LAUNCH("k_pgb_aggregate", bytes, (k_pgb_aggregate<K, NV>), dim3(units), dim3(kBlock), lds, st, a);
 }
 
 // ---------------------------------------------------------------------------------
@@ -1387,7 +1402,10 @@ int64_t groupby_partition(Ctx &ctx, int key_bytes, const void *key, const int32_
     if (max_units > 1 || !a.lds_records) init_outputs(st, a.spec, g);
     const double bytes = (double)n * (key_bytes + 4.0 * n_vals + (gfur ? 4.0 : 0.0)) +
                          (double)g * (key_bytes + 4.0 * a.spec.words);
-#define GJ_PGB(K, NV) GJ_LAUNCH("k_pgb_aggregate", bytes, (k_pgb_aggregate<K, NV>), dim3(units), dim3(kBlock), lds, st, a)
+    // at most three 256-thread workgroups per compute unit: 1024-thread ones
+    // (one or two value columns; more would spill registers)
+    const bool wide = lds > 40 * 1024;
+#define GJ_PGB(K, NV) launch_pgb_aggregate<K, NV>(wide, units, lds, st, a, bytes)
     const int nvt = nv_tier(n_vals);
     if (key_bytes == 4) {
         if (nvt == 1) GJ_PGB(int32_t, 1); else if (nvt == 2) GJ_PGB(int32_t, 2); else if (nvt == 4) GJ_PGB(int32_t, 4); else GJ_PGB(int32_t, 8);

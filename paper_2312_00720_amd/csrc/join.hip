@@ -10,15 +10,19 @@
 // smallest that holds r_block) and the workgroup 16 table rows per thread.
 //
 // The output size is unknown (Section 2.2), so a count pass runs first: every
-// wave counts its matches; an exclusive scan over (unit, wave) gives every wave
-// its output range, and the write pass enumerates the same matches again and
-// writes (key, R payloads, S payloads) contiguously. GFTR reads payloads from
-// the partitioned copies at partition-local positions (clustered); GFUR reads
-// the original columns through the partitioned row ids (unclustered).
+// wave counts its matches and records each S row's match; an exclusive scan
+// over (unit, wave) gives every wave its output range. The write pass then
+// writes (key, R payloads, S payloads) contiguously. In the common case (one R
+// block per partition, at most one match per S row) it streams S with the
+// recorded matches and needs no table; otherwise it rebuilds the table and
+// enumerates the matches again. GFTR reads payloads from the partitioned
+// copies at partition-local positions (clustered), staged in LDS when they
+// fit; GFUR reads the original columns through the partitioned row ids
+// (unclustered).
 //
-// Chains of the LDS table list R rows in input order, so an S row with several
-// matches emits them in R's input order, and the output is the same on every
-// run.
+// In the write pass, chains of the LDS table list R rows in input order, so an
+// S row with several matches emits them in R's input order, and the output is
+// the same on every run.
 #include "internal.hpp"
 
 namespace gj {

@@ -56,6 +56,16 @@ def test_groupby_matches_oracle(algo, mat, n, card, alpha):
     check(d["key"], d["vals"], algo=algo, mat=mat, sorted_out=(algo == "sort"))
 
 
+@pytest.mark.parametrize("kb,nv", [(4, 1), (4, 2), (8, 2)])
+def test_partition_many_groups_per_partition(kb, nv):
+    """About a thousand groups per partition: the aggregation's table and
+    records take over 40 KB of LDS, which selects its 1024-thread workgroups."""
+    d = datagen.groupby_input(600001, 300000, nv, seed=30 + kb + nv, key_bytes=kb)
+    aggs = AGGS if nv == 2 else AGGS[:4]
+    check(d["key"], d["vals"], aggs, algo="partition", mat="gftr")
+    check(d["key"], d["vals"], aggs, algo="partition", mat="gfur")
+
+
 @pytest.mark.parametrize("algo", ["partition", "hash", "sort"])
 def test_groupby_int64_keys(algo):
     d = datagen.groupby_input(100000, 5000, 2, seed=12, key_bytes=8)
