@@ -364,10 +364,18 @@ int gj_groupby(gj_col key, const gj_col *vals, int32_t n_vals, int64_t n_rows, c
         if (algo == GJ_GB_PARTITION) {
             int bits = o.radix_bits;
             if (bits == 0) {
-                // partitions of about 2048 rows; one pass (at most 8 bits) whenever the
-                // estimated groups leave about 1000 or fewer keys per partition
-                bits = std::min(16, std::max(1, ceil_log2((n + 2047) / 2048)));
-                if (g_est <= (double)(1u << 18)) bits = std::min(bits, 8);
+                // One pass (at most 8 bits, partitions of at least 2048 rows) whenever
+                // the estimated groups leave about 1000 or fewer keys per partition;
+                // else about 512 groups per partition (fewer bits than partitions of
+                // 2048 rows would take, so shorter scatter digits), within the 4096
+                // keys a partition's discovery table holds.
+                const int row_bits = std::min(16, std::max(1, ceil_log2((n + 2047) / 2048)));
+                if (g_est <= (double)(1u << 18)) {
+                    bits = std::min(row_bits, 8);
+                } else {
+                    const int g_bits = ceil_log2((uint64_t)(g_est / 512.0));
+                    bits = std::max(1, std::min({16, row_bits, std::max(9, g_bits)}));
+                }
             }
             int fell_back = 0;
             g = gj::groupby_partition(ctx, kb, key.data, vcols, n_vals, n, aggs, n_aggs, gfur, bits, &okey, oaggs,
