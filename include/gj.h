@@ -159,7 +159,7 @@ typedef struct {
     int8_t part_log2[GJ_TUNE_CLASSES];    /* target rows per partition 2^v, v in 6..12 (rule: 11); the
                                              instance gets clamp(ceil(log2 |R_i|) - v, 0, 8) bits */
     int8_t bucket_shift[GJ_TUNE_CLASSES]; /* LDS hash buckets per build block: 2^(ceil(log2 rows) + shift),
-                                             shift 0 or 1, capped at 4096 (rule: 0) */
+                                             shift 0 or 1, capped at 2048 for 4096-row blocks (rule: 0) */
     int32_t scatter_variant;              /* partition scatter shape, 1..13 (rule: 0 = built-in) */
 } gj_join_tuning;
 

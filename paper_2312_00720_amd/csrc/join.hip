@@ -33,23 +33,25 @@ constexpr uint16_t kNoMatch = 0xFFFF;  // blocks hold at most 16384 rows
 constexpr uint32_t kPersistentGrid = 4096;  // workgroups of a plan's count and write passes
 
 // Shape of a work unit for a table of BUILD rows: threads, waves, S piece rows,
-// bucket-count limit (12 bits up to 8192 rows, 13 for 16384, so that a table
-// filled to half its rows has as many buckets as keys) and probe rounds in
-// flight per lane (the larger shapes have at most 128 registers per lane).
+// bucket-count limit (as many buckets as keys in a table filled to half its
+// rows: 2048 for 4096 rows, whose 32 KB of LDS then let four workgroups share a
+// compute unit; 4096 for 8192 rows; 8192 for 16384) and probe rounds in flight
+// per lane (the larger shapes have at most 128 registers per lane).
 template <uint32_t BUILD>
 struct Geo {
     static constexpr uint32_t kBuild = BUILD;
     static constexpr int kThreads = (int)(BUILD / 16);
     static constexpr int kWv = kThreads / kWave;
     static constexpr uint32_t kSPiece = 2 * BUILD;
-    static constexpr int kMaxLog2nb = BUILD >= 16384 ? 13 : 12;
+    static constexpr int kMaxLog2nb = BUILD >= 16384 ? 13 : (BUILD == 4096 ? 11 : 12);
     static constexpr uint32_t kMaxNb = 1u << kMaxLog2nb;
     static constexpr int kPB = 16;                    // count pass
     static constexpr int kPBWrite = BUILD == 4096 ? 16 : 8;  // LDS write pass
     // waves per SIMD the register allocation must allow: the persistent
     // kernels and the one-unit-per-workgroup kernels (two 512-thread
     // workgroups per compute unit)
-    static constexpr int kMinW = BUILD == 4096 ? 3 : 4;
+    static constexpr int kMinW = 4;
+    static constexpr int kMinWWrite = BUILD == 4096 ? 3 : 4;
     static constexpr int kMinWEager = BUILD == 4096 ? 1 : 4;
     static constexpr int kMinWStaged = BUILD == 4096 ? 2 : 4;
 };
@@ -797,7 +799,7 @@ __global__ __launch_bounds__(Geo<BUILD>::kThreads, Geo<BUILD>::kMinWStaged) void
 
 // Persistent workgroups over the unit count held in device memory (plans).
 template <typename K, uint32_t BUILD, bool WRITE>
-__global__ __launch_bounds__(Geo<BUILD>::kThreads, Geo<BUILD>::kMinW) void k_join_persist(JoinArgs a) {
+__global__ __launch_bounds__(Geo<BUILD>::kThreads, WRITE ? Geo<BUILD>::kMinWWrite : Geo<BUILD>::kMinW) void k_join_persist(JoinArgs a) {
     __shared__ JoinShared<K, BUILD> sh;
     if (WRITE && a.lds_if_complex && !(a.flags[0] | a.flags[1])) return;  // the streaming pass writes
     const uint32_t n_units = min(*a.nunits, a.cap_units);
