@@ -296,6 +296,19 @@ int gj_groupby_plan_create(const gj_gb_batch *B, const gj_agg *aggs, int32_t n_a
  * instance. GJ_ECAPACITY when a partition overflowed its LDS table. */
 int gj_groupby_plan_result(gj_plan *plan, void *stream, gj_groupby_out *out, int64_t *group_offsets);
 
+/*
+ * Eager form of the group-by plan (no counterpart in the paper; the partition
+ * group-by of Section 4.3 applied to every instance at once): plans the batch,
+ * runs it once on `stream` and returns columns of exactly n_groups rows
+ * allocated through `alloc` (owned by the caller; out->aggs has room for n_aggs
+ * pointers; SUM and COUNT are int64, MIN and MAX int32). group_offsets (host,
+ * n_instances + 1) receives the first group of each instance. Same inputs,
+ * options and errors as gj_groupby_plan_create and gj_groupby_plan_result; on
+ * error nothing stays allocated. Synchronizes with `stream`.
+ */
+int gj_groupby_batch(const gj_gb_batch *B, const gj_agg *aggs, int32_t n_aggs, const gj_groupby_opts *opts,
+                     const gj_allocator *alloc, void *stream, gj_groupby_out *out, int64_t *group_offsets);
+
 /* Digit source of the partition primitive. */
 typedef enum {
     GJ_DIGIT_BITS = 0,   /* the key's unsigned two's-complement bit pattern */

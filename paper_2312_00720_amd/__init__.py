@@ -175,6 +175,10 @@ def lib() -> ctypes.CDLL:
                                                  ctypes.POINTER(GroupByOpts), ctypes.POINTER(Allocator), vp, pp]
             L.gj_groupby_plan_result.restype = ctypes.c_int
             L.gj_groupby_plan_result.argtypes = [vp, vp, ctypes.POINTER(GroupByOut), ctypes.POINTER(ctypes.c_int64)]
+            L.gj_groupby_batch.restype = ctypes.c_int
+            L.gj_groupby_batch.argtypes = [ctypes.POINTER(GbBatch), ctypes.POINTER(Agg), i32,
+                                           ctypes.POINTER(GroupByOpts), ctypes.POINTER(Allocator), vp,
+                                           ctypes.POINTER(GroupByOut), ctypes.POINTER(ctypes.c_int64)]
             L.gj_last_error.restype = ctypes.c_char_p
             L.gj_last_error.argtypes = []
             L.gj_version.restype = ctypes.c_char_p
@@ -537,6 +541,35 @@ def groupby(key: torch.Tensor, vals, aggs, *, algo: str = "auto", mat: str = "au
         dt = torch.int64 if op in ("sum", "count") else vals[c].dtype
         res.append(A.take(ao[i], dt, g))
     return keys, res
+
+
+def groupby_batch(key: torch.Tensor, vals, offsets, aggs, *, mat: str = "gftr", radix_bits: int = 0):
+    """Partition group-by of every instance of a batch in one call (gj_groupby_batch).
+    Key and value columns hold the instances back to back; offsets (n+1 host ints)
+    delimit them. Returns (keys, [aggregate columns], group offsets per instance)."""
+    L = lib()
+    vals = list(vals)
+    dev = key.device
+    _check_cols([key, *vals], key.numel(), dev)
+    n = len(offsets) - 1
+    if n < 1 or int(offsets[-1]) != key.numel():
+        raise ValueError("offsets must have >= 2 entries and end at the column length")
+    off = (ctypes.c_int64 * (n + 1))(*[int(x) for x in offsets])
+    vp = (Col * max(1, len(vals)))(*[_col(t) for t in vals])
+    ag = (Agg * max(1, len(aggs)))(*[Agg(int(c), AGG_OP[op]) for c, op in aggs])
+    B = GbBatch(_col(key), vp, len(vals), off, n)
+    o = GroupByOpts(GB_ALGO["partition"], MAT[mat], radix_bits, 0, 0.0, 0)
+    ao = (ctypes.c_void_p * max(1, len(aggs)))()
+    out = GroupByOut(None, ao, 0)
+    goff = (ctypes.c_int64 * (n + 1))()
+    A = _TorchAllocator(dev)
+    _raise(L.gj_groupby_batch(ctypes.byref(B), ag, len(aggs), ctypes.byref(o), ctypes.byref(A.struct),
+                              _stream(dev), ctypes.byref(out), goff))
+    g = out.n_groups
+    keys = A.take(out.key, key.dtype, g)
+    res = [A.take(ao[i], torch.int64 if op in ("sum", "count") else vals[c].dtype, g)
+           for i, (c, op) in enumerate(aggs)]
+    return keys, res, [int(goff[i]) for i in range(n + 1)]
 
 
 MLP_PARAMS = 5317

@@ -145,10 +145,9 @@ __device__ __forceinline__ void gather_cols(int ncols, const void *const *src, c
 // stream_cols_contig reads the contiguous rows row0 + r * 64 (one base address).
 template <int PB>
 __device__ __forceinline__ void gather_cols_wave(int ncols, const void *const *src, const int *width,
-                                                 void *const *dst, uint32_t rbase, const void *unused,
+                                                 void *const *dst, uint32_t rbase,
                                                  const uint32_t *row, const uint32_t *lrow, const uint32_t *pos,
                                                  uint64_t wbase, uint32_t lim) {
-    (void)unused;
     for (int j = 0; j < ncols; ++j) {
         if (width[j] == 4) {
             const uint32_t *__restrict__ in = static_cast<const uint32_t *>(src[j]) + rbase;
@@ -632,16 +631,16 @@ __global__ __launch_bounds__(kBlock, GFUR ? 4 : 1) void k_join_stream(JoinArgs a
             if constexpr (!GFUR) {
                 // GFTR: S rows are contiguous, R rows partition-local
                 stream_cols_contig<PB>(a.ns, a.sp, a.sw, a.ts, s0 + base + lane, lrow, pos, wbase, lim);
-                gather_cols_wave<PB>(a.nr, a.rp, a.rw, a.tr, r0, nullptr, lrow, lrow, pos, wbase, lim);
+                gather_cols_wave<PB>(a.nr, a.rp, a.rw, a.tr, r0, lrow, lrow, pos, wbase, lim);
             } else {
                 // GFUR: original rows through the row ids
                 uint32_t row[PB];
 #pragma unroll
                 for (int r = 0; r < PB; ++r) row[r] = lrow[r] != ~0u ? (uint32_t)a.srow[s0 + base + r * kWave + lane] : 0u;
-                gather_cols_wave<PB>(a.ns, a.sp, a.sw, a.ts, 0u, nullptr, row, lrow, pos, wbase, lim);
+                gather_cols_wave<PB>(a.ns, a.sp, a.sw, a.ts, 0u, row, lrow, pos, wbase, lim);
 #pragma unroll
                 for (int r = 0; r < PB; ++r) row[r] = lrow[r] != ~0u ? (uint32_t)a.rrow[r0 + lrow[r]] : 0u;
-                gather_cols_wave<PB>(a.nr, a.rp, a.rw, a.tr, 0u, nullptr, row, lrow, pos, wbase, lim);
+                gather_cols_wave<PB>(a.nr, a.rp, a.rw, a.tr, 0u, row, lrow, pos, wbase, lim);
             }
         }
     }

@@ -746,6 +746,55 @@ int gj_plan_get_info(const gj_plan *P, gj_plan_info *info) {
     return GJ_OK;
 }
 
+int gj_groupby_batch(const gj_gb_batch *B, const gj_agg *aggs, int32_t n_aggs, const gj_groupby_opts *opts,
+                     const gj_allocator *alloc, void *stream, gj_groupby_out *out, int64_t *group_offsets) {
+    gj::clear_error();
+    if (!out) return plan_error(GJ_EINVAL, "null output");
+    if (n_aggs > 0 && !out->aggs) return plan_error(GJ_EINVAL, "null aggs array");
+    out->n_groups = 0;
+    out->key = nullptr;
+    gj_plan *P = nullptr;
+    int rc = gj_groupby_plan_create(B, aggs, n_aggs, opts, alloc, stream, &P);
+    if (rc != GJ_OK) return rc;
+    try {
+        rc = gj_plan_run(P, stream);
+        void *pa[16] = {nullptr};
+        gj_groupby_out po{};
+        po.aggs = pa;
+        if (rc == GJ_OK) rc = gj_groupby_plan_result(P, stream, &po, group_offsets);
+        if (rc != GJ_OK) {
+            const std::string msg = gj_last_error();
+            gj_plan_destroy(P);
+            return plan_error(rc, msg);
+        }
+        // the plan's columns hold sum(N_i) rows, the first n_groups of them used:
+        // copy those into columns of the caller's allocator
+        hipStream_t st = (hipStream_t)stream;
+        gj::Ctx ctx(alloc, st);
+        const uint64_t g = (uint64_t)po.n_groups;
+        const size_t kbytes = (size_t)P->kb;
+        void *okey = ctx.output(g * kbytes);
+        if (g) GJ_HIP(hipMemcpyAsync(okey, po.key, g * kbytes, hipMemcpyDeviceToDevice, st));
+        for (int j = 0; j < n_aggs; ++j) {
+            const size_t w = (aggs[j].op == GJ_SUM || aggs[j].op == GJ_COUNT) ? 8 : 4;
+            void *o = ctx.output(g * w);
+            if (g) GJ_HIP(hipMemcpyAsync(o, po.aggs[j], g * w, hipMemcpyDeviceToDevice, st));
+            out->aggs[j] = o;
+        }
+        GJ_HIP(hipStreamSynchronize(st));  // the plan's columns are released next
+        ctx.commit();
+        out->key = okey;
+        out->n_groups = (int64_t)g;
+        gj_plan_destroy(P);
+        return GJ_OK;
+    } catch (const Error &e) {
+        gj_plan_destroy(P);
+        out->n_groups = 0;
+        out->key = nullptr;
+        return plan_error(e.code, e.what());
+    }
+}
+
 int gj_plan_destroy(gj_plan *P) {
     if (!P) return GJ_OK;
     P->release();

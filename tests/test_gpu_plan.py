@@ -248,6 +248,33 @@ def test_groupby_plan_matches_oracle(mat):
     plan.close()
 
 
+@pytest.mark.parametrize("kb,mat", [(4, "gftr"), (8, "gfur")])
+def test_groupby_batch_eager_matches_plan_and_oracle(kb, mat):
+    """gj_groupby_batch: one call returns caller-owned columns of exactly the
+    group count, equal row for row to the plan's result, and the oracle's
+    aggregates per instance (empty and one-row instances included)."""
+    import paper_2312_00720_amd as gj
+    from gpu_util import dev, host, say
+    g = datagen.rng(43 + kb)
+    sizes = [(int(round(2 ** g.uniform(0, 15))), int(g.integers(1, 3000))) for _ in range(40)]
+    sizes[5] = (0, 1)
+    sizes[6] = (1, 1)
+    parts, key, vals, off = gb_batch(sizes, seed=15000 + kb, key_bytes=kb)
+    say(f"group-by batch {kb}-byte keys {mat}: {len(parts)} instances, {len(key)} rows")
+    keys, cols, goff = gj.groupby_batch(dev(key), [dev(v) for v in vals], off, GB_AGGS, mat=mat)
+    assert len(goff) == len(parts) + 1 and goff[-1] == keys.numel()
+    assert all(c.numel() == keys.numel() for c in cols)
+    check_gb(parts, (keys, cols, goff))
+    plan = gj.GroupByPlan(dev(key), [dev(v) for v in vals], off, GB_AGGS, mat=mat)
+    plan.run()
+    pk, pc, poff = plan.result()
+    assert poff == goff
+    np.testing.assert_array_equal(host(pk), host(keys))
+    for a, b in zip(pc, cols):
+        np.testing.assert_array_equal(host(a), host(b))
+    plan.close()
+
+
 def test_groupby_plan_groups_skew_int64(monkeypatch):
     import paper_2312_00720_amd as gj
     from gpu_util import dev
