@@ -236,7 +236,8 @@ typedef struct {
     int32_t radix_bits; /* partition group-by: total partition bits, 1..16 */
     int32_t block_size; /* reserved; 0 or 256 */
     float ht_occupancy; /* reserved */
-    int32_t lds_budget; /* bytes of LDS for the aggregation buffer; forces global fallback when small */
+    int32_t lds_budget; /* hash: bytes of LDS for aggregation records (0: 64 KiB); the groups beyond
+                           what fits aggregate with global atomics */
 } gj_groupby_opts;
 
 /* Group-by output A(k, a_1..a_n): one row per distinct key. aggs[i] is the

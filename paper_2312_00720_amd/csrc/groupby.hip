@@ -944,7 +944,7 @@ struct HgbArgs {
     ValSrc vals;
     void *out_key;
     uint32_t g;
-    int lds_records;
+    uint32_t lds_groups;  // groups 0..lds_groups-1 aggregate in LDS records, the rest with global atomics
 };
 
 template <typename K>
@@ -1028,11 +1028,12 @@ __global__ __launch_bounds__(kBlock) void k_hgb_aggregate(HgbArgs a) {
     constexpr int RB = NV <= 2 ? 8 : 16 / NV;
     extern __shared__ __align__(16) uint32_t s_dyn[];
     const AggSpec &s = a.spec;
-    if (a.lds_records) {
-        for (uint32_t i = threadIdx.x; i < a.g; i += kBlock) rec_init(s_dyn + (uint64_t)i * s.words, s);
+    const uint32_t L = a.lds_groups;
+    if (L) {
+        for (uint32_t i = threadIdx.x; i < L; i += kBlock) rec_init(s_dyn + (uint64_t)i * s.words, s);
         __syncthreads();
     }
-    const bool few = a.g <= 2;
+    const bool few = a.g <= 2 && L == a.g;
     const uint32_t stride = gridDim.x * kBlock * RB;
     for (uint32_t base = blockIdx.x * kBlock * RB; base < a.n; base += stride) {
         uint32_t loc[RB], gid[RB];
@@ -1048,17 +1049,17 @@ __global__ __launch_bounds__(kBlock) void k_hgb_aggregate(HgbArgs a) {
 #pragma unroll
         for (int r = 0; r < RB; ++r) {
             const bool valid = base + r * kBlock + threadIdx.x < a.n;
-            if (a.lds_records) {
-                if (few) wave_aggregate<NV>(s_dyn, s, valid, gid[r], rr[r]);
-                else if (valid) rec_add_row<NV>(s_dyn + (uint64_t)gid[r] * s.words, s, rr[r]);
+            if (few) {
+                wave_aggregate<NV>(s_dyn, s, valid, gid[r], rr[r]);
             } else if (valid) {
-                row_add_global_r<NV>(s, rr[r], gid[r]);
+                if (gid[r] < L) rec_add_row<NV>(s_dyn + (uint64_t)gid[r] * s.words, s, rr[r]);
+                else row_add_global_r<NV>(s, rr[r], gid[r]);
             }
         }
     }
-    if (a.lds_records) {
+    if (L) {
         __syncthreads();
-        for (uint32_t i = threadIdx.x; i < a.g; i += kBlock) rec_flush(s_dyn + (uint64_t)i * s.words, s, i, true);
+        for (uint32_t i = threadIdx.x; i < L; i += kBlock) rec_flush(s_dyn + (uint64_t)i * s.words, s, i, true);
     }
 }
 
@@ -1552,14 +1553,18 @@ int64_t groupby_hash(Ctx &ctx, int key_bytes, const void *key, const int32_t *co
     for (int c = 0; c < n_vals; ++c) a.vals.col[c] = vals[c];
     a.vals.rowid = nullptr;
     a.g = g;
-    const size_t rec_bytes = (size_t)g * a.spec.words * 4;
+    // is_smem_enough: every group's record in LDS when they fit the budget. When
+    // they do not, the first groups that fit keep LDS records and the rest take
+    // global atomics: ids follow first occurrence, so under skew the frequent keys
+    // hold the low ids and most rows stay off the contended global atomics.
+    const size_t rec = (size_t)a.spec.words * 4;
     const size_t budget = lds_budget > 0 ? (size_t)lds_budget : (size_t)64 * 1024;
-    a.lds_records = rec_bytes <= budget;  // is_smem_enough
+    a.lds_groups = (uint32_t)std::min<size_t>(g, budget / rec);
     init_outputs(st, a.spec, g);
     const double bytes = (double)n * (4.0 * n_vals + 8.0) + (double)g * (key_bytes + 4.0 * a.spec.words);
     // LDS records are flushed by every workgroup, so fewer workgroups keep the flush cheap
-    const uint32_t agrid = a.lds_records ? std::min<uint32_t>(grid, 512) : grid;
-    const size_t alds = a.lds_records ? rec_bytes : 0;
+    const uint32_t agrid = a.lds_groups ? std::min<uint32_t>(grid, 512) : grid;
+    const size_t alds = (size_t)a.lds_groups * rec;
 #define GJ_HAGG(NV) GJ_LAUNCH("k_hgb_aggregate", bytes, k_hgb_aggregate<NV>, dim3(agrid), dim3(kBlock), alds, st, a)
     const int nvt = nv_tier(n_vals);
     if (nvt == 1) GJ_HAGG(1); else if (nvt == 2) GJ_HAGG(2); else if (nvt == 4) GJ_HAGG(4); else GJ_HAGG(8);

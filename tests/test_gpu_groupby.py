@@ -108,6 +108,14 @@ def test_partition_overflow_falls_back():
     check(d["key"], d["vals"], algo="partition", radix_bits=1)
 
 
+@pytest.mark.parametrize("alpha", [0.0, 1.0])
+def test_hash_partial_lds_records(alpha):
+    """More groups than LDS records: the first group ids keep LDS records, the
+    rest aggregate with global atomics (uniform and skewed keys)."""
+    d = datagen.groupby_input(200000, 3000, 2, seed=66, alpha=alpha)
+    check(d["key"], d["vals"], algo="hash", lds_budget=4000)
+
+
 def test_hash_global_aggregation_path():
     d = datagen.groupby_input(100000, 2000, 2, seed=6)
     check(d["key"], d["vals"], algo="hash", lds_budget=64)
