@@ -1535,10 +1535,25 @@ int64_t groupby_hash(Ctx &ctx, int key_bytes, const void *key, const int32_t *co
     fill_u32(st, a.ngroups, 0u, 1);
     a.tmp_keys = ctx.scratch((size_t)n * key_bytes);
     const uint32_t grid = std::min<uint32_t>(ceil_div_u32(n, kBlock), 256u * 16u);
-    if (key_bytes == 4)
-        GJ_LAUNCH("k_hgb_insert", 16.0 * n, k_hgb_insert<int32_t>, dim3(grid), dim3(kBlock), 0, st, a);
-    else
-        GJ_LAUNCH("k_hgb_insert", 20.0 * n, k_hgb_insert<int64_t>, dim3(grid), dim3(kBlock), 0, st, a);
+    // Group ids come from an atomic counter, so a full grid hands them out in the
+    // order its first tiles happen to win, unrelated to key frequency. One
+    // workgroup first inserts a prefix of the rows a tile at a time: the keys seen
+    // there take the low ids, and under skew those are the frequent keys. Low ids
+    // are the ones that keep LDS records when not every group fits. The full pass
+    // then finds the prefix keys already present.
+    std::vector<void *> no_outs(n_aggs, nullptr);
+    const size_t rec = (size_t)make_spec(aggs, n_aggs, no_outs.data()).words * 4;
+    const size_t budget = lds_budget > 0 ? (size_t)lds_budget : (size_t)64 * 1024;
+    const uint32_t prefix = (uint32_t)std::min<size_t>(n, std::max<size_t>(2048, 2 * (budget / rec)));
+    HgbArgs ap = a;
+    ap.n = prefix;
+    if (key_bytes == 4) {
+        GJ_LAUNCH("k_hgb_insert", 16.0 * prefix, k_hgb_insert<int32_t>, dim3(1), dim3(kBlock), 0, st, ap);
+        if (n > prefix) GJ_LAUNCH("k_hgb_insert", 16.0 * n, k_hgb_insert<int32_t>, dim3(grid), dim3(kBlock), 0, st, a);
+    } else {
+        GJ_LAUNCH("k_hgb_insert", 20.0 * prefix, k_hgb_insert<int64_t>, dim3(1), dim3(kBlock), 0, st, ap);
+        if (n > prefix) GJ_LAUNCH("k_hgb_insert", 20.0 * n, k_hgb_insert<int64_t>, dim3(grid), dim3(kBlock), 0, st, a);
+    }
     const uint32_t g = read_back(a.ngroups, st);
     *out_key = ctx.output((size_t)std::max<uint32_t>(g, 1) * key_bytes);
     std::vector<void *> outs(n_aggs);
@@ -1554,11 +1569,9 @@ int64_t groupby_hash(Ctx &ctx, int key_bytes, const void *key, const int32_t *co
     a.vals.rowid = nullptr;
     a.g = g;
     // is_smem_enough: every group's record in LDS when they fit the budget. When
-    // they do not, the first groups that fit keep LDS records and the rest take
-    // global atomics: ids follow first occurrence, so under skew the frequent keys
-    // hold the low ids and most rows stay off the contended global atomics.
-    const size_t rec = (size_t)a.spec.words * 4;
-    const size_t budget = lds_budget > 0 ? (size_t)lds_budget : (size_t)64 * 1024;
+    // they do not, the lowest ids that fit keep LDS records and the rest take
+    // global atomics; with the prefix insert above, the frequent keys hold those
+    // ids under skew and most rows stay off the contended global atomics.
     a.lds_groups = (uint32_t)std::min<size_t>(g, budget / rec);
     init_outputs(st, a.spec, g);
     const double bytes = (double)n * (4.0 * n_vals + 8.0) + (double)g * (key_bytes + 4.0 * a.spec.words);

@@ -116,6 +116,20 @@ def test_hash_partial_lds_records(alpha):
     check(d["key"], d["vals"], algo="hash", lds_budget=4000)
 
 
+def test_hash_ids_follow_the_first_rows():
+    """When not every group fits in LDS, the lowest group ids keep LDS records.
+    They go to the keys of the first rows (inserted by one workgroup before the
+    full grid), which under skew are the frequent keys. HGB emits groups in id
+    order, so those keys come first in its output. Here 7 aggregates take 40-byte
+    records, so the default 64 KB budget holds 1638 of the 19167 groups, and the
+    first 2048 rows hold 1014 distinct keys."""
+    d = datagen.groupby_input(400000, 20000, 2, seed=5, alpha=1.0)
+    gk, _ = check(d["key"], d["vals"], algo="hash")
+    first = np.unique(d["key"][:2048])
+    assert len(first) == 1014 and len(gk) == 19167
+    assert np.isin(first, gk[:1638]).all()
+
+
 def test_hash_global_aggregation_path():
     d = datagen.groupby_input(100000, 2000, 2, seed=6)
     check(d["key"], d["vals"], algo="hash", lds_budget=64)
