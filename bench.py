@@ -129,7 +129,7 @@ def bench_groupby(args, copy_gbs) -> int:
     mat = args.mat if args.algo != "hash" else "auto"
 
     def step():
-        return gj.groupby(d["key"], d["vals"], GB_AGGS, algo=args.algo, mat=mat)
+        return gj.groupby(d["key"], d["vals"], GB_AGGS, algo=args.algo, mat=mat, radix_bits=args.radix_bits)
 
     ms, stats, out = timed(step, args.steps, args.warmup)
     groups = out[0].numel()
@@ -148,7 +148,8 @@ def bench_groupby(args, copy_gbs) -> int:
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": dk["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": dk["gbs"] / HBM_PEAK_GBS,
                      "traffic": measured_traffic(dom, f"groupby_{args.algo}_n{args.n_log2}_g{args.g_log2}")
-                     if args.alpha == 0 and mat in ("gftr", "auto") else None},
+                     if args.alpha == 0 and mat in ("gftr", "auto") and args.radix_bits == 0 else None},
+        "hbm_gbs_whole_step": sum(v["alg_bytes"] for v in stats.values()) / args.steps / (ms / 1e3) / 1e9,
         "kernels": {k: {"launches_per_step": v["launches"] / args.steps, "ms_per_step": v["ms_per_step"],
                         "alg_gbs": v["gbs"]} for k, v in kern.items()},
     }
@@ -296,7 +297,7 @@ def main() -> int:
     ap.add_argument("--alpha", type=float, default=0.0)
     ap.add_argument("--match-ratio", type=float, default=1.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--radix-bits", type=int, default=0, help="join: partition bits (0 = automatic)")
+    ap.add_argument("--radix-bits", type=int, default=0, help="join / group-by: partition bits (0 = automatic)")
     ap.add_argument("--lds-budget", type=int, default=0, help="join: max R rows per build block (0 = automatic)")
     ap.add_argument("--workload", default="join", choices=["join", "groupby", "batch", "pipeline"])
     ap.add_argument("--pipe-s-log2", type=int, default=26, help="pipeline: log2 |S|")

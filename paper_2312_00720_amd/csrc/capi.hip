@@ -365,13 +365,20 @@ int gj_groupby(gj_col key, const gj_col *vals, int32_t n_vals, int64_t n_rows, c
             int bits = o.radix_bits;
             if (bits == 0) {
                 // One pass (at most 8 bits, partitions of at least 2048 rows) whenever
-                // the estimated groups leave about 1000 or fewer keys per partition;
-                // else about 512 groups per partition (fewer bits than partitions of
-                // 2048 rows would take, so shorter scatter digits), within the 4096
-                // keys a partition's discovery table holds.
+                // the estimated groups leave about 1000 or fewer keys per partition.
+                // Up to ~128 groups, 8 bits leave about one group per partition, which
+                // aggregates in registers. Beyond that, about sqrt(g) partitions of
+                // sqrt(g) groups: a handful of groups per partition would make the
+                // LDS record updates collide within a wave, and fewer bits also make
+                // the scatter's digits longer. Past 2^18 groups, about 512 groups per
+                // partition (fewer bits than partitions of 2048 rows would take),
+                // within the 4096 keys a partition's discovery table holds.
                 const int row_bits = std::min(16, std::max(1, ceil_log2((n + 2047) / 2048)));
-                if (g_est <= (double)(1u << 18)) {
+                if (g_est <= 128.0) {
                     bits = std::min(row_bits, 8);
+                } else if (g_est <= (double)(1u << 18)) {
+                    const int half = (ceil_log2((uint64_t)g_est) + 1) / 2;
+                    bits = std::min(row_bits, std::max(1, std::min(8, half)));
                 } else {
                     const int g_bits = ceil_log2((uint64_t)(g_est / 512.0));
                     bits = std::max(1, std::min({16, row_bits, std::max(9, g_bits)}));

@@ -145,22 +145,6 @@ __device__ __forceinline__ int pick(const Row<NV> &r, int c) {
     return x;
 }
 
-// Accumulate one row (values in registers) into an LDS record.
-template <int NV>
-__device__ __forceinline__ void rec_add_row(uint32_t *rec, const AggSpec &s, const Row<NV> &r) {
-    for (int j = 0; j < s.n; ++j) {
-        uint32_t *p = rec + s.word[j];
-        switch (s.op[j]) {
-            case GJ_SUM:
-                atomicAdd(reinterpret_cast<unsigned long long *>(p), (unsigned long long)(long long)pick(r, s.col[j]));
-                break;
-            case GJ_COUNT: atomicAdd(p, 1u); break;
-            case GJ_MIN: atomicMin(reinterpret_cast<int *>(p), pick(r, s.col[j])); break;
-            default: atomicMax(reinterpret_cast<int *>(p), pick(r, s.col[j])); break;
-        }
-    }
-}
-
 template <int NV>
 __device__ __forceinline__ void row_add_global_r(const AggSpec &s, const Row<NV> &r, uint64_t o) {
     for (int j = 0; j < s.n; ++j) {
@@ -173,6 +157,60 @@ __device__ __forceinline__ void row_add_global_r(const AggSpec &s, const Row<NV>
             default: atomicMax(static_cast<int *>(s.out[j]) + o, pick(r, s.col[j])); break;
         }
     }
+}
+
+// Spare words after the real records, for lanes whose row adds nothing: lane l
+// points its record at spare word 2l, so that no two lanes of one atomic share an
+// address. The spare "records" overlap and nothing reads them; with one record's
+// worth of words beyond the last lane's start they take kSpareWords + words.
+constexpr uint32_t kSpareWords = 2 * kWave;
+__device__ __forceinline__ uint32_t spare_off(uint32_t rec_end) { return rec_end + 2u * lane_id(); }
+
+// Accumulate rows 0..nact-1 of RB (values in registers) into LDS records: row r
+// goes to the record at word off[r]. nact is uniform over the wave (rows past it
+// are empty for every lane), and lanes with nothing to add in an active row point
+// at a spare, so the atomics need no divergent branch. The loop runs over the
+// aggregates outside the rows: each aggregate's atomics issue back to back, and
+// the aggregate list is read once per batch of rows rather than once per row.
+template <int NV, int RB>
+__device__ __forceinline__ void rec_add_rows(uint32_t *recs, const AggSpec &s, const uint32_t (&off)[RB],
+                                             const Row<NV> (&rr)[RB], int nact) {
+    for (int j = 0; j < s.n; ++j) {
+        const int c = s.col[j], w = s.word[j];
+        switch (s.op[j]) {
+            case GJ_SUM:
+#pragma unroll
+                for (int r = 0; r < RB; ++r)
+                    if (r < nact)
+                        atomicAdd(reinterpret_cast<unsigned long long *>(recs + off[r] + w),
+                                  (unsigned long long)(long long)pick(rr[r], c));
+                break;
+            case GJ_COUNT:
+#pragma unroll
+                for (int r = 0; r < RB; ++r)
+                    if (r < nact) atomicAdd(recs + off[r] + w, 1u);
+                break;
+            case GJ_MIN:
+#pragma unroll
+                for (int r = 0; r < RB; ++r)
+                    if (r < nact) atomicMin(reinterpret_cast<int *>(recs + off[r] + w), pick(rr[r], c));
+                break;
+            default:
+#pragma unroll
+                for (int r = 0; r < RB; ++r)
+                    if (r < nact) atomicMax(reinterpret_cast<int *>(recs + off[r] + w), pick(rr[r], c));
+                break;
+        }
+    }
+}
+
+// Rows base + r * stride + (first lane of the wave) for r < RB: how many of them
+// start below end, i.e. the rows in which some lane of the wave has a row.
+template <int RB>
+__device__ __forceinline__ int wave_active_rows(uint32_t base, uint32_t stride, uint32_t end) {
+    const uint32_t w0 = __builtin_amdgcn_readfirstlane(base + (threadIdx.x & ~(uint32_t)(kWave - 1)));
+    if (w0 >= end) return 0;
+    return (int)min((uint32_t)RB, (end - w0 + stride - 1) / stride);
 }
 
 // Running aggregate of a set of rows: count, and per value column sum / min / max.
@@ -546,7 +584,7 @@ __global__ __launch_bounds__(kBlock) void k_pgb_discover(PgbArgs a) {
             const uint32_t local = i - p0;
             if (kk[r] == e) {
                 atomicMin(&s_sent, local);
-            } else {
+            } else if (!__atomic_load_n(&s_over, __ATOMIC_RELAXED)) {  // once full, stop probing
                 const int slot = lds_insert<K>(s_key, log2cap, kk[r]);
                 if (slot < 0) s_over = 1;
                 else if (s_first[slot] > local) atomicMin(&s_first[slot], local);
@@ -649,12 +687,16 @@ __global__ __launch_bounds__(kBlock) void k_pgb_discover_unit(PgbArgs a) {
         for (int r = 0; r < RB; ++r) {
             if (base + r * kBlock + tid >= r1) continue;
             if (kk[r] == e) s_sent = 1;
-            else if (lds_insert<K>(s_key, log2cap, kk[r]) < 0) s_over = 1;
+            else if (!__atomic_load_n(&s_over, __ATOMIC_RELAXED) && lds_insert<K>(s_key, log2cap, kk[r]) < 0)
+                s_over = 1;  // once full, the remaining keys are not probed
         }
     }
     __syncthreads();
     if (s_over) {
-        if (tid == 0) atomicOr(&a.stat[1], 1u);
+        if (tid == 0) {
+            a.dcount[u] = 0;  // the merge reads every slice's count
+            atomicOr(&a.stat[1], 1u);
+        }
         return;
     }
     K *__restrict__ tk = static_cast<K *>(a.tmp_keys);
@@ -686,7 +728,14 @@ __global__ __launch_bounds__(kBlock) void k_pgb_merge(PgbArgs a) {
     const int tid = threadIdx.x;
     const uint32_t u0 = a.dubase[p], u1 = a.dubase[p + 1];
     if (u0 == u1) return;  // not an oversized partition
-    const uint32_t p0 = a.poff[p];
+    // a slice overflowed (here or in another partition): the result is discarded
+    // (hash group-by takes over, or a plan reports the overflow), so nothing is
+    // merged; the group count is still defined for the kernels that follow
+    if (__atomic_load_n(&a.stat[1], __ATOMIC_RELAXED)) {
+        if (tid == 0) a.gcnt[p] = 0;
+        return;
+    }
+    const uint32_t p0 = a.poff[p], p1 = a.poff[p + 1];
     const K e = empty_key<K>();
     for (uint32_t i = tid; i < kDiscoverCap; i += kBlock) s_key[i] = e;
     if (tid == 0) {
@@ -696,11 +745,15 @@ __global__ __launch_bounds__(kBlock) void k_pgb_merge(PgbArgs a) {
     __syncthreads();
     K *__restrict__ tk = static_cast<K *>(a.tmp_keys);
     for (uint32_t u = u0; u < u1; ++u) {
-        const uint32_t r0 = p0 + (u - u0) * kDiscoverUnit, d = a.dcount[u];
+        // a slice's distinct keys sit over its own rows: never more than the rows
+        // of the slice or the slots of its table
+        const uint32_t r0 = p0 + (u - u0) * kDiscoverUnit;
+        const uint32_t d = min(a.dcount[u], min(kDiscoverCap + 1u, p1 - r0));
         for (uint32_t i = tid; i < d; i += kBlock) {
             const K k = tk[r0 + i];
             if (k == e) s_sent = 1;
-            else if (lds_insert<K>(s_key, log2cap, k) < 0) s_over = 1;
+            else if (!__atomic_load_n(&s_over, __ATOMIC_RELAXED) && lds_insert<K>(s_key, log2cap, k) < 0)
+                s_over = 1;
         }
     }
     __syncthreads();
@@ -842,13 +895,15 @@ __device__ __forceinline__ void pgb_unit(const PgbArgs &a, uint32_t u, uint64_t 
         log2cap = 6;
         while ((1u << log2cap) < 2u * g) ++log2cap;
         const uint32_t tab = (1u << log2cap) * (uint32_t)(sizeof(K) + 2) + 8;
-        lds_records = tab + g * (uint32_t)a.spec.words * 4u <= a.lds_bytes;
+        lds_records = tab + ((g + 1) * (uint32_t)a.spec.words + kSpareWords) * 4u <= a.lds_bytes;  // and spares
     }
     const uint32_t cap = 1u << log2cap;
     K *tab = reinterpret_cast<K *>(s_dyn);
     uint16_t *id_of = reinterpret_cast<uint16_t *>(tab + cap);  // slot -> group id
-    uint32_t *recs = reinterpret_cast<uint32_t *>(id_of + cap);
-    recs = reinterpret_cast<uint32_t *>((reinterpret_cast<uintptr_t>(recs) + 7) & ~uintptr_t(7));
+    // records from the first 8-byte boundary after the table and its ids; an index
+    // into s_dyn (not integer pointer arithmetic) keeps them addressed as LDS, so the
+    // record updates compile to LDS atomics rather than flat ones
+    uint32_t *recs = s_dyn + ((cap * (uint32_t)(sizeof(K) + 2) + 7u) & ~7u) / 4u;
     const K e = empty_key<K>();
     for (uint32_t i = tid; i < cap; i += BT) tab[i] = e;
     if (lds_records)
@@ -876,16 +931,37 @@ __device__ __forceinline__ void pgb_unit(const PgbArgs &a, uint32_t u, uint64_t 
             kk[r] = i < r1 ? keys[i] : e;
             if (i < r1) rr[r] = load_row<NV>(a.vals, i);
         }
+        // group ids: every row's first probe is read before any is resolved (the
+        // table is at most half full, so most rows stop there)
+        bool ok[RB];
+        uint32_t hs[RB], ids[RB];
+        K t0[RB];
 #pragma unroll
         for (int r = 0; r < RB; ++r) {
-            const bool valid = base + r * BT + tid < r1;
-            uint32_t id = 0;
-            if (valid) id = (kk[r] == e) ? s_sent_id : id_of[lds_find<K>(tab, log2cap, kk[r])];
-            if (lds_records) {
-                if (few) wave_aggregate<NV>(recs, s, valid, id, rr[r]);
-                else if (valid) rec_add_row<NV>(recs + (uint64_t)id * s.words, s, rr[r]);
-            } else if (valid) {
-                row_add_global_r<NV>(s, rr[r], gb + id);
+            ok[r] = base + r * BT + tid < r1;
+            hs[r] = slot_hash<K>(kk[r], log2cap);
+        }
+#pragma unroll
+        for (int r = 0; r < RB; ++r) t0[r] = tab[hs[r]];
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+            if (ok[r] && kk[r] != e && t0[r] != kk[r]) hs[r] = (uint32_t)lds_find<K>(tab, log2cap, kk[r]);
+        }
+#pragma unroll
+        for (int r = 0; r < RB; ++r) ids[r] = ok[r] && kk[r] != e ? (uint32_t)id_of[hs[r]] : 0u;
+#pragma unroll
+        for (int r = 0; r < RB; ++r)
+            if (ok[r] && kk[r] == e) ids[r] = s_sent_id;
+        if (lds_records && !few) {
+            uint32_t off[RB];
+#pragma unroll
+            for (int r = 0; r < RB; ++r) off[r] = ok[r] ? ids[r] * (uint32_t)s.words : spare_off(g * s.words);
+            rec_add_rows<NV, RB>(recs, s, off, rr, wave_active_rows<RB>(base, BT, r1));
+        } else {
+#pragma unroll
+            for (int r = 0; r < RB; ++r) {
+                if (lds_records) wave_aggregate<NV>(recs, s, ok[r], ids[r], rr[r]);
+                else if (ok[r]) row_add_global_r<NV>(s, rr[r], gb + ids[r]);
             }
         }
     }
@@ -1046,16 +1122,24 @@ __global__ __launch_bounds__(kBlock) void k_hgb_aggregate(HgbArgs a) {
         }
 #pragma unroll
         for (int r = 0; r < RB; ++r) gid[r] = a.gid[loc[r]];
+        if (few) {
+#pragma unroll
+            for (int r = 0; r < RB; ++r)
+                wave_aggregate<NV>(s_dyn, s, base + r * kBlock + threadIdx.x < a.n, gid[r], rr[r]);
+            continue;
+        }
+        uint32_t off[RB];  // rows that do not use LDS point at the spare words
+        bool any = false;
 #pragma unroll
         for (int r = 0; r < RB; ++r) {
-            const bool valid = base + r * kBlock + threadIdx.x < a.n;
-            if (few) {
-                wave_aggregate<NV>(s_dyn, s, valid, gid[r], rr[r]);
-            } else if (valid) {
-                if (gid[r] < L) rec_add_row<NV>(s_dyn + (uint64_t)gid[r] * s.words, s, rr[r]);
-                else row_add_global_r<NV>(s, rr[r], gid[r]);
-            }
+            const bool in_lds = base + r * kBlock + threadIdx.x < a.n && gid[r] < L;
+            off[r] = in_lds ? gid[r] * (uint32_t)s.words : spare_off(L * s.words);
+            any |= in_lds;
         }
+        if (__any(any)) rec_add_rows<NV, RB>(s_dyn, s, off, rr, wave_active_rows<RB>(base, kBlock, a.n));
+#pragma unroll
+        for (int r = 0; r < RB; ++r)
+            if (base + r * kBlock + threadIdx.x < a.n && gid[r] >= L) row_add_global_r<NV>(s, rr[r], gid[r]);
     }
     if (L) {
         __syncthreads();
@@ -1385,12 +1469,12 @@ int64_t groupby_partition(Ctx &ctx, int key_bytes, const void *key, const int32_
     a.cap_units = units;
     a.out_base = nullptr;
     a.lds_bytes = 0;
-    // LDS: table of 2*maxg slots (key + 16-bit id), then maxg records
+    // LDS: table of 2*maxg slots (key + 16-bit id), then maxg records and the spare words
     int log2cap = 6;
     while ((1u << log2cap) < 2u * maxg) ++log2cap;
     a.log2cap = log2cap;
     const size_t tab_bytes = ((size_t)1 << log2cap) * (key_bytes + 2) + 8;
-    const size_t rec_bytes = (size_t)maxg * a.spec.words * 4;
+    const size_t rec_bytes = (((size_t)maxg + 1) * a.spec.words + kSpareWords) * 4;
     size_t lds = tab_bytes + rec_bytes;
     a.lds_records = 1;
     if (lds > 120 * 1024 || log2cap > 16) {
@@ -1575,9 +1659,14 @@ int64_t groupby_hash(Ctx &ctx, int key_bytes, const void *key, const int32_t *co
     a.lds_groups = (uint32_t)std::min<size_t>(g, budget / rec);
     init_outputs(st, a.spec, g);
     const double bytes = (double)n * (4.0 * n_vals + 8.0) + (double)g * (key_bytes + 4.0 * a.spec.words);
-    // LDS records are flushed by every workgroup, so fewer workgroups keep the flush cheap
-    const uint32_t agrid = a.lds_groups ? std::min<uint32_t>(grid, 512) : grid;
-    const size_t alds = (size_t)a.lds_groups * rec;
+    const size_t alds = a.lds_groups ? ((size_t)a.lds_groups + 1) * rec + kSpareWords * 4 : 0;
+    // every workgroup folds its LDS records into the output with global atomics:
+    // the grid keeps that near 2^19 record flushes, but never drops below one
+    // round of resident workgroups (by LDS, and at most 7 per compute unit by
+    // registers)
+    const uint32_t per_cu = alds ? (uint32_t)std::max<size_t>(1, std::min<size_t>(7, (160u * 1024u) / alds)) : 0;
+    const uint32_t agrid =
+        alds ? std::min<uint32_t>(grid, std::max<uint32_t>(256u * per_cu, (1u << 19) / a.lds_groups)) : grid;
 #define GJ_HAGG(NV) GJ_LAUNCH("k_hgb_aggregate", bytes, k_hgb_aggregate<NV>, dim3(agrid), dim3(kBlock), alds, st, a)
     const int nvt = nv_tier(n_vals);
     if (nvt == 1) GJ_HAGG(1); else if (nvt == 2) GJ_HAGG(2); else if (nvt == 4) GJ_HAGG(4); else GJ_HAGG(8);

@@ -108,6 +108,16 @@ def test_partition_overflow_falls_back():
     check(d["key"], d["vals"], algo="partition", radix_bits=1)
 
 
+def test_partition_slice_overflow_falls_back():
+    """Partitions of 150000 rows are discovered in slices of 65536 rows, and each
+    slice here holds about 14000 distinct keys, more than a slice's LDS table: the
+    partition group-by hands over to hash group-by and the result stays exact
+    (the merge must not read the counts the overflowing slices never produced)."""
+    d = datagen.groupby_input(300000, 30000, 2, seed=31)
+    check(d["key"], d["vals"], algo="partition", radix_bits=1)
+    check(d["key"], d["vals"], algo="partition", radix_bits=1, mat="gfur")
+
+
 @pytest.mark.parametrize("alpha", [0.0, 1.0])
 def test_hash_partial_lds_records(alpha):
     """More groups than LDS records: the first group ids keep LDS records, the
