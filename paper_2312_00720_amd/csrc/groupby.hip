@@ -174,7 +174,7 @@ __device__ __forceinline__ uint32_t spare_off(uint32_t rec_end) { return rec_end
 // the aggregate list is read once per batch of rows rather than once per row.
 template <int NV, int RB>
 __device__ __forceinline__ void rec_add_rows(uint32_t *recs, const AggSpec &s, const uint32_t (&off)[RB],
-                                             const Row<NV> (&rr)[RB], int nact) {
+                                             const Row<NV> (&rr)[RB], int nact, bool skewed) {
     for (int j = 0; j < s.n; ++j) {
         const int c = s.col[j], w = s.word[j];
         switch (s.op[j]) {
@@ -190,16 +190,45 @@ __device__ __forceinline__ void rec_add_rows(uint32_t *recs, const AggSpec &s, c
                 for (int r = 0; r < RB; ++r)
                     if (r < nact) atomicAdd(recs + off[r] + w, 1u);
                 break;
-            case GJ_MIN:
+            case GJ_MIN: {
+                if (!skewed) {
+#pragma unroll
+                    for (int r = 0; r < RB; ++r)
+                        if (r < nact) atomicMin(reinterpret_cast<int *>(recs + off[r] + w), pick(rr[r], c));
+                    break;
+                }
+                // skewed keys: a minimum only falls, so a row no lower than what the
+                // record holds (even a stale read of it) cannot change it; the
+                // frequent groups' extremes settle early and most rows skip the
+                // atomic that many lanes of a wave would contend for. Uniform keys
+                // skip the read: it would wait behind the atomics issued before it.
+                int cur[RB];
 #pragma unroll
                 for (int r = 0; r < RB; ++r)
-                    if (r < nact) atomicMin(reinterpret_cast<int *>(recs + off[r] + w), pick(rr[r], c));
-                break;
-            default:
+                    if (r < nact) cur[r] = __atomic_load_n(reinterpret_cast<int *>(recs + off[r] + w), __ATOMIC_RELAXED);
 #pragma unroll
                 for (int r = 0; r < RB; ++r)
-                    if (r < nact) atomicMax(reinterpret_cast<int *>(recs + off[r] + w), pick(rr[r], c));
+                    if (r < nact && pick(rr[r], c) < cur[r])
+                        atomicMin(reinterpret_cast<int *>(recs + off[r] + w), pick(rr[r], c));
                 break;
+            }
+            default: {
+                if (!skewed) {
+#pragma unroll
+                    for (int r = 0; r < RB; ++r)
+                        if (r < nact) atomicMax(reinterpret_cast<int *>(recs + off[r] + w), pick(rr[r], c));
+                    break;
+                }
+                int cur[RB];
+#pragma unroll
+                for (int r = 0; r < RB; ++r)
+                    if (r < nact) cur[r] = __atomic_load_n(reinterpret_cast<int *>(recs + off[r] + w), __ATOMIC_RELAXED);
+#pragma unroll
+                for (int r = 0; r < RB; ++r)
+                    if (r < nact && pick(rr[r], c) > cur[r])
+                        atomicMax(reinterpret_cast<int *>(recs + off[r] + w), pick(rr[r], c));
+                break;
+            }
         }
     }
 }
@@ -824,7 +853,7 @@ __global__ void k_pgb_units(const uint32_t *__restrict__ poff, const uint32_t *_
     atomicMax(max_units, mx);
 }
 
-template <typename K, int NV, int BT>
+template <typename K, int NV, int BT, bool SKEW>
 __device__ __forceinline__ void pgb_unit(const PgbArgs &a, uint32_t u, uint64_t out_base, uint32_t *s_dyn,
                                          uint32_t *s_unit, uint32_t &s_sent_id) {
     constexpr int RB = NV <= 2 ? 8 : 16 / NV;  // rows loaded per thread before they are aggregated
@@ -956,7 +985,7 @@ __device__ __forceinline__ void pgb_unit(const PgbArgs &a, uint32_t u, uint64_t 
             uint32_t off[RB];
 #pragma unroll
             for (int r = 0; r < RB; ++r) off[r] = ok[r] ? ids[r] * (uint32_t)s.words : spare_off(g * s.words);
-            rec_add_rows<NV, RB>(recs, s, off, rr, wave_active_rows<RB>(base, BT, r1));
+            rec_add_rows<NV, RB>(recs, s, off, rr, wave_active_rows<RB>(base, BT, r1), SKEW);
         } else {
 #pragma unroll
             for (int r = 0; r < RB; ++r) {
@@ -974,7 +1003,7 @@ __device__ __forceinline__ void pgb_unit(const PgbArgs &a, uint32_t u, uint64_t 
 // BT threads per workgroup: 256, or 1024 when a partition's table and records
 // take so much LDS that only one or two workgroups fit a compute unit (many
 // groups per partition), so that the unit still runs 16 or more waves.
-template <typename K, int NV, int BT = kBlock>
+template <typename K, int NV, int BT = kBlock, bool SKEW = false>
 __global__ __launch_bounds__(BT) void k_pgb_aggregate(PgbArgs a) {
     extern __shared__ __align__(16) uint32_t s_dyn[];
     __shared__ uint32_t s_unit[5];
@@ -983,21 +1012,30 @@ __global__ __launch_bounds__(BT) void k_pgb_aggregate(PgbArgs a) {
     const uint64_t out_base = a.out_base ? *a.out_base : 0ull;
     // persistent: a workgroup takes units blockIdx.x, blockIdx.x + gridDim.x, ...
     for (uint32_t u = blockIdx.x; u < n_units; u += gridDim.x) {
-        pgb_unit<K, NV, BT>(a, u, out_base, s_dyn, s_unit, s_sent_id);
+        pgb_unit<K, NV, BT, SKEW>(a, u, out_base, s_dyn, s_unit, s_sent_id);
         __syncthreads();  // the unit's LDS state is rebuilt by the next one
     }
 }
 
 template <typename K, int NV>
-void launch_pgb_aggregate(bool wide, uint32_t units, size_t lds, hipStream_t st, const PgbArgs &a, double bytes) {
+void launch_pgb_aggregate(bool wide, bool skewed, uint32_t units, size_t lds, hipStream_t st, const PgbArgs &a,
+                          double bytes) {
     if constexpr (NV <= 2) {
         if (wide) {
-            GJ_LAUNCH("k_pgb_aggregate", bytes, (k_pgb_aggregate<K, NV, 1024>), dim3(units), dim3(1024), lds, st, a);
+            if (skewed)
+                GJ_LAUNCH("k_pgb_aggregate", bytes, (k_pgb_aggregate<K, NV, 1024, true>), dim3(units), dim3(1024), lds,
+                          st, a);
+            else
+                GJ_LAUNCH("k_pgb_aggregate", bytes, (k_pgb_aggregate<K, NV, 1024>), dim3(units), dim3(1024), lds, st, a);
             return;
         }
     }
     (void)wide;
-    GJ_LAUNCH("k_pgb_aggregate", bytes, (k_pgb_aggregate<K, NV>), dim3(units), dim3(kBlock), lds, st, a);
+    if (skewed)
+        GJ_LAUNCH("k_pgb_aggregate", bytes, (k_pgb_aggregate<K, NV, kBlock, true>), dim3(units), dim3(kBlock), lds, st,
+                  a);
+    else
+        GJ_LAUNCH("k_pgb_aggregate", bytes, (k_pgb_aggregate<K, NV>), dim3(units), dim3(kBlock), lds, st, a);
 }
 
 // ---------------------------------------------------------------------------------
@@ -1136,7 +1174,7 @@ __global__ __launch_bounds__(kBlock) void k_hgb_aggregate(HgbArgs a) {
             off[r] = in_lds ? gid[r] * (uint32_t)s.words : spare_off(L * s.words);
             any |= in_lds;
         }
-        if (__any(any)) rec_add_rows<NV, RB>(s_dyn, s, off, rr, wave_active_rows<RB>(base, kBlock, a.n));
+        if (__any(any)) rec_add_rows<NV, RB>(s_dyn, s, off, rr, wave_active_rows<RB>(base, kBlock, a.n), false);
 #pragma unroll
         for (int r = 0; r < RB; ++r)
             if (base + r * kBlock + threadIdx.x < a.n && gid[r] >= L) row_add_global_r<NV>(s, rr[r], gid[r]);
@@ -1485,12 +1523,14 @@ int64_t groupby_partition(Ctx &ctx, int key_bytes, const void *key, const int32_
     lds = std::max<size_t>(lds, (size_t)kWaves * 160 + 16);  // the one-group path keeps a per-wave total
     // outputs of partitions split over several units are folded with atomics
     if (max_units > 1 || !a.lds_records) init_outputs(st, a.spec, g);
+    // skew: the largest partition holds at least twice the mean partition's units
+    const bool skewed = (uint64_t)max_units * np >= 2ull * units && max_units >= 4;
     const double bytes = (double)n * (key_bytes + 4.0 * n_vals + (gfur ? 4.0 : 0.0)) +
                          (double)g * (key_bytes + 4.0 * a.spec.words);
     // at most three 256-thread workgroups per compute unit: 1024-thread ones
     // (one or two value columns; more would spill registers)
     const bool wide = lds > 40 * 1024;
-#define GJ_PGB(K, NV) launch_pgb_aggregate<K, NV>(wide, units, lds, st, a, bytes)
+#define GJ_PGB(K, NV) launch_pgb_aggregate<K, NV>(wide, skewed, units, lds, st, a, bytes)
     const int nvt = nv_tier(n_vals);
     if (key_bytes == 4) {
         if (nvt == 1) GJ_PGB(int32_t, 1); else if (nvt == 2) GJ_PGB(int32_t, 2); else if (nvt == 4) GJ_PGB(int32_t, 4); else GJ_PGB(int32_t, 8);

@@ -108,6 +108,16 @@ def test_partition_overflow_falls_back():
     check(d["key"], d["vals"], algo="partition", radix_bits=1)
 
 
+@pytest.mark.parametrize("kb", [4, 8])
+def test_partition_skewed_keys(kb):
+    """Zipf 1.0 keys: the hottest key's partition holds several times the mean
+    partition's work units, which switches MIN/MAX to reading the record before
+    the atomic. Results stay exact."""
+    d = datagen.groupby_input(2_000_000, 20000, 2, seed=41, alpha=1.0, key_bytes=kb)
+    check(d["key"], d["vals"], algo="partition", mat="gftr")
+    check(d["key"], d["vals"], algo="partition", mat="gfur")
+
+
 def test_partition_slice_overflow_falls_back():
     """Partitions of 150000 rows are discovered in slices of 65536 rows, and each
     slice here holds about 14000 distinct keys, more than a slice's LDS table: the
