@@ -22,6 +22,22 @@ namespace {
 constexpr int kMaxAggs = 16;
 constexpr int kMaxVals = 8;
 constexpr uint32_t kDiscoverCap = 4096;  // LDS table slots of the discover pass
+
+// Bytes per slot of a partition's aggregation table in LDS: 4-byte keys share one
+// 8-byte word with their group id (one read finds both), 8-byte keys keep the ids
+// in a 16-bit array beside the keys.
+constexpr uint32_t agg_slot_bytes(int key_bytes) { return key_bytes == 4 ? 8u : (uint32_t)key_bytes + 2u; }
+
+// Slots (log2) of the aggregation table for a partition of g groups: a power of
+// two of at least 1.5 g (load at most 2/3, short linear probes) and 64. At most
+// kDiscoverCap keys go in; the key equal to the empty marker, when present, is
+// counted in g but kept apart.
+__host__ __device__ inline int agg_table_log2(uint32_t g) {
+    const uint32_t keys = g < kDiscoverCap ? g : kDiscoverCap;
+    int l = 6;
+    while ((1u << l) * 2u < 3u * keys) ++l;
+    return l;
+}
 constexpr uint32_t kUnitRows = 8192;     // rows per aggregation work unit
 constexpr uint32_t kDiscoverUnit = 65536; // partitions above this size are discovered by several workgroups
 
@@ -920,21 +936,32 @@ __device__ __forceinline__ void pgb_unit(const PgbArgs &a, uint32_t u, uint64_t 
     int log2cap = a.log2cap;
     bool lds_records = a.lds_records != 0;
     if (a.lds_bytes) {
-        // the table holds 2g slots; records stay in LDS when they fit beside it
-        log2cap = 6;
-        while ((1u << log2cap) < 2u * g) ++log2cap;
-        const uint32_t tab = (1u << log2cap) * (uint32_t)(sizeof(K) + 2) + 8;
-        lds_records = tab + ((g + 1) * (uint32_t)a.spec.words + kSpareWords) * 4u <= a.lds_bytes;  // and spares
+        // the table holds at least 1.5 slots per group; records (and the spare
+        // words) stay in LDS when they fit beside it. The plan's LDS is fixed, so
+        // the table then grows into what is left, up to 4 slots per group: fewer
+        // lookups probe past their first slot.
+        const auto tab_bytes = [](int l) { return (1u << l) * agg_slot_bytes(sizeof(K)) + 8u; };
+        const uint32_t rec = ((g + 1) * (uint32_t)a.spec.words + kSpareWords) * 4u;
+        log2cap = agg_table_log2(g);
+        lds_records = tab_bytes(log2cap) + rec <= a.lds_bytes;
+        const uint32_t keys = max(min(g, kDiscoverCap), 16u), need = lds_records ? rec : 0u;
+        while ((2u << log2cap) <= 4u * keys && tab_bytes(log2cap + 1) + need <= a.lds_bytes) ++log2cap;
     }
     const uint32_t cap = 1u << log2cap;
-    K *tab = reinterpret_cast<K *>(s_dyn);
-    uint16_t *id_of = reinterpret_cast<uint16_t *>(tab + cap);  // slot -> group id
-    // records from the first 8-byte boundary after the table and its ids; an index
-    // into s_dyn (not integer pointer arithmetic) keeps them addressed as LDS, so the
-    // record updates compile to LDS atomics rather than flat ones
-    uint32_t *recs = s_dyn + ((cap * (uint32_t)(sizeof(K) + 2) + 7u) & ~7u) / 4u;
+    K *tab = reinterpret_cast<K *>(s_dyn);                      // 8-byte keys
+    uint16_t *id_of = reinterpret_cast<uint16_t *>(tab + cap);  // 8-byte keys: slot -> group id
+    unsigned long long *tab64 = reinterpret_cast<unsigned long long *>(s_dyn);  // 4-byte keys: id << 32 | key
     const K e = empty_key<K>();
-    for (uint32_t i = tid; i < cap; i += BT) tab[i] = e;
+    const unsigned long long e64 = (0xFFFFFFFFull << 32) | (uint32_t)e;
+    // records from the first 8-byte boundary after the table; an index into s_dyn
+    // (not integer pointer arithmetic) keeps them addressed as LDS, so the record
+    // updates compile to LDS atomics rather than flat ones
+    uint32_t *recs = s_dyn + ((cap * agg_slot_bytes(sizeof(K)) + 7u) & ~7u) / 4u;
+    if constexpr (sizeof(K) == 4) {
+        for (uint32_t i = tid; i < cap; i += BT) tab64[i] = e64;
+    } else {
+        for (uint32_t i = tid; i < cap; i += BT) tab[i] = e;
+    }
     if (lds_records)
         for (uint32_t i = tid; i < g; i += BT) rec_init(recs + (uint64_t)i * s.words, s);
     __syncthreads();
@@ -942,6 +969,13 @@ __device__ __forceinline__ void pgb_unit(const PgbArgs &a, uint32_t u, uint64_t 
         const K k = tk[p0 + i];
         if (k == e) {
             s_sent_id = i;
+        } else if constexpr (sizeof(K) == 4) {
+            // the partition's keys are distinct: the first empty slot of the probe takes it
+            uint32_t h = slot_hash<K>(k, log2cap);
+            for (uint32_t step = 0; step < cap; ++step) {
+                if (atomicCAS(&tab64[h], e64, ((unsigned long long)i << 32) | (uint32_t)k) == e64) break;
+                h = (h + 1) & (cap - 1);
+            }
         } else {
             const int slot = lds_insert<K>(tab, log2cap, k);
             id_of[slot] = (uint16_t)i;
@@ -964,20 +998,39 @@ __device__ __forceinline__ void pgb_unit(const PgbArgs &a, uint32_t u, uint64_t 
         // table is at most half full, so most rows stop there)
         bool ok[RB];
         uint32_t hs[RB], ids[RB];
-        K t0[RB];
 #pragma unroll
         for (int r = 0; r < RB; ++r) {
             ok[r] = base + r * BT + tid < r1;
             hs[r] = slot_hash<K>(kk[r], log2cap);
         }
+        if constexpr (sizeof(K) == 4) {
+            unsigned long long v[RB];
 #pragma unroll
-        for (int r = 0; r < RB; ++r) t0[r] = tab[hs[r]];
+            for (int r = 0; r < RB; ++r) v[r] = tab64[hs[r]];
 #pragma unroll
-        for (int r = 0; r < RB; ++r) {
-            if (ok[r] && kk[r] != e && t0[r] != kk[r]) hs[r] = (uint32_t)lds_find<K>(tab, log2cap, kk[r]);
+            for (int r = 0; r < RB; ++r) {
+                if (ok[r] && kk[r] != e && (uint32_t)v[r] != (uint32_t)kk[r]) {
+                    // the key is in the table: probe on until it turns up
+                    uint32_t h = hs[r];
+                    for (uint32_t step = 1; step < cap; ++step) {
+                        h = (h + 1) & (cap - 1);
+                        v[r] = tab64[h];
+                        if ((uint32_t)v[r] == (uint32_t)kk[r]) break;
+                    }
+                }
+                ids[r] = ok[r] && kk[r] != e ? (uint32_t)(v[r] >> 32) : 0u;
+            }
+        } else {
+            K t0[RB];
+#pragma unroll
+            for (int r = 0; r < RB; ++r) t0[r] = tab[hs[r]];
+#pragma unroll
+            for (int r = 0; r < RB; ++r) {
+                if (ok[r] && kk[r] != e && t0[r] != kk[r]) hs[r] = (uint32_t)lds_find<K>(tab, log2cap, kk[r]);
+            }
+#pragma unroll
+            for (int r = 0; r < RB; ++r) ids[r] = ok[r] && kk[r] != e ? (uint32_t)id_of[hs[r]] : 0u;
         }
-#pragma unroll
-        for (int r = 0; r < RB; ++r) ids[r] = ok[r] && kk[r] != e ? (uint32_t)id_of[hs[r]] : 0u;
 #pragma unroll
         for (int r = 0; r < RB; ++r)
             if (ok[r] && kk[r] == e) ids[r] = s_sent_id;
@@ -1507,19 +1560,32 @@ int64_t groupby_partition(Ctx &ctx, int key_bytes, const void *key, const int32_
     a.cap_units = units;
     a.out_base = nullptr;
     a.lds_bytes = 0;
-    // LDS: table of 2*maxg slots (key + 16-bit id), then maxg records and the spare words
-    int log2cap = 6;
-    while ((1u << log2cap) < 2u * maxg) ++log2cap;
-    a.log2cap = log2cap;
-    const size_t tab_bytes = ((size_t)1 << log2cap) * (key_bytes + 2) + 8;
+    // LDS: the aggregation table (key and group id per slot), then maxg records and
+    // the spare words
+    const auto tab_bytes = [&](int l) { return ((size_t)1 << l) * agg_slot_bytes(key_bytes) + 8; };
     const size_t rec_bytes = (((size_t)maxg + 1) * a.spec.words + kSpareWords) * 4;
-    size_t lds = tab_bytes + rec_bytes;
+    int log2cap = agg_table_log2(maxg);
+    size_t lds = tab_bytes(log2cap) + rec_bytes;
     a.lds_records = 1;
     if (lds > 120 * 1024 || log2cap > 16) {
         a.lds_records = 0;  // too many groups per partition for LDS records: global atomics
-        lds = tab_bytes;
+        lds = tab_bytes(log2cap);
     }
     require(lds <= 150 * 1024, "partition group-by: too many groups per partition", GJ_EUNSUPPORTED);
+    // fewer than three 256-thread workgroups per compute unit (by LDS): 1024-thread
+    // ones (one or two value columns; more would spill registers)
+    const bool wide = lds > 160 * 1024 / 3 && nv_tier(n_vals) <= 2;
+    // The table starts at 1.5 slots per group and grows, up to 4 per group (fewer
+    // lookups probe past their first slot), within the LDS that the workgroups
+    // the registers allow per compute unit leave: 32 KB for 256-thread ones (five
+    // per compute unit), the whole budget for a 1024-thread one.
+    {
+        const size_t room = wide ? (size_t)150 * 1024 : std::max<size_t>((size_t)32 * 1024, lds);
+        const size_t keys = std::max<size_t>(std::min(maxg, kDiscoverCap), 16), need = a.lds_records ? rec_bytes : 0;
+        while (((size_t)2 << log2cap) <= 4 * keys && tab_bytes(log2cap + 1) + need <= room) ++log2cap;
+        lds = tab_bytes(log2cap) + need;
+    }
+    a.log2cap = log2cap;
     lds = std::max<size_t>(lds, (size_t)kWaves * 160 + 16);  // the one-group path keeps a per-wave total
     // outputs of partitions split over several units are folded with atomics
     if (max_units > 1 || !a.lds_records) init_outputs(st, a.spec, g);
@@ -1527,9 +1593,6 @@ int64_t groupby_partition(Ctx &ctx, int key_bytes, const void *key, const int32_
     const bool skewed = (uint64_t)max_units * np >= 2ull * units && max_units >= 4;
     const double bytes = (double)n * (key_bytes + 4.0 * n_vals + (gfur ? 4.0 : 0.0)) +
                          (double)g * (key_bytes + 4.0 * a.spec.words);
-    // at most three 256-thread workgroups per compute unit: 1024-thread ones
-    // (one or two value columns; more would spill registers)
-    const bool wide = lds > 40 * 1024;
 #define GJ_PGB(K, NV) launch_pgb_aggregate<K, NV>(wide, skewed, units, lds, st, a, bytes)
     const int nvt = nv_tier(n_vals);
     if (key_bytes == 4) {
@@ -1543,9 +1606,9 @@ int64_t groupby_partition(Ctx &ctx, int key_bytes, const void *key, const int32_
 
 uint32_t pgb_plan_lds_bytes(int key_bytes) {
     // room for the largest per-partition table (2 x kDiscoverCap slots of key and
-    // 16-bit id), and at least 64 KiB so that records of ~1000 groups fit beside
+    // group id), and at least 64 KiB so that records of ~1000 groups fit beside
     // a small table
-    return std::max<uint32_t>(2u * kDiscoverCap * (uint32_t)(key_bytes + 2) + 8, 65536u);
+    return std::max<uint32_t>(2u * kDiscoverCap * agg_slot_bytes(key_bytes) + 8, 65536u);
 }
 
 void groupby_partition_segments(Ctx &ctx, int key_bytes, const void *key, const int32_t *const *vals, int n_vals,

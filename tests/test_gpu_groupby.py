@@ -58,12 +58,13 @@ def test_groupby_matches_oracle(algo, mat, n, card, alpha):
 
 @pytest.mark.parametrize("kb,nv", [(4, 1), (4, 2), (8, 2)])
 def test_partition_many_groups_per_partition(kb, nv):
-    """About a thousand groups per partition: the aggregation's table and
-    records take over 40 KB of LDS, which selects its 1024-thread workgroups."""
+    """About 1200 groups in each of 256 partitions: the aggregation's table and
+    records take over 53 KB of LDS, fewer than three 256-thread workgroups'
+    worth, which selects its 1024-thread workgroups."""
     d = datagen.groupby_input(600001, 300000, nv, seed=30 + kb + nv, key_bytes=kb)
     aggs = AGGS if nv == 2 else AGGS[:4]
-    check(d["key"], d["vals"], aggs, algo="partition", mat="gftr")
-    check(d["key"], d["vals"], aggs, algo="partition", mat="gfur")
+    check(d["key"], d["vals"], aggs, algo="partition", mat="gftr", radix_bits=8)
+    check(d["key"], d["vals"], aggs, algo="partition", mat="gfur", radix_bits=8)
 
 
 @pytest.mark.parametrize("algo", ["partition", "hash", "sort"])
