@@ -235,7 +235,11 @@ typedef struct {
     int32_t mat;        /* gj_mat, for sort and partition */
     int32_t radix_bits; /* partition group-by: total partition bits, 1..16 */
     int32_t block_size; /* reserved; 0 or 256 */
-    float ht_occupancy; /* reserved */
+    float ht_occupancy; /* hash: target load of the global table, sized from the HyperLogLog
+                           estimate of the group count (0: 0.45; at most 64). A table that turns
+                           out too small (a row finds no slot within 4096 probes, as loads above 1
+                           make sure of) is replaced by one of 1.5 slots per row and the insert
+                           runs again; the result does not depend on it. */
     int32_t lds_budget; /* hash: bytes of LDS for aggregation records (0: 64 KiB); the groups beyond
                            what fits aggregate with global atomics */
 } gj_groupby_opts;

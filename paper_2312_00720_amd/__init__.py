@@ -517,7 +517,7 @@ def partition(key: torch.Tensor, cols=(), *, bit_lo: int = 0, bits: int = 8, pas
 
 
 def groupby(key: torch.Tensor, vals, aggs, *, algo: str = "auto", mat: str = "auto",
-            radix_bits: int = 0, lds_budget: int = 0):
+            radix_bits: int = 0, lds_budget: int = 0, ht_occupancy: float = 0.0):
     """Grouped aggregation. `aggs` is a list of (column index, op) with op in
     {"sum", "count", "min", "max"}. Returns (keys, [aggregate columns])."""
     L = lib()
@@ -527,7 +527,7 @@ def groupby(key: torch.Tensor, vals, aggs, *, algo: str = "auto", mat: str = "au
     _check_cols([key, *vals], n, dev)
     vp = (Col * max(1, len(vals)))(*[_col(t) for t in vals])
     ag = (Agg * max(1, len(aggs)))(*[Agg(int(c), AGG_OP[op]) for c, op in aggs])
-    o = GroupByOpts(GB_ALGO[algo], MAT[mat], radix_bits, 0, 0.0, lds_budget)
+    o = GroupByOpts(GB_ALGO[algo], MAT[mat], radix_bits, 0, float(ht_occupancy), lds_budget)
     ao = (ctypes.c_void_p * max(1, len(aggs)))()
     out = GroupByOut(None, ao, 0)
     A = _TorchAllocator(dev)

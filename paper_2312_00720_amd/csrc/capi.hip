@@ -334,6 +334,7 @@ int gj_groupby(gj_col key, const gj_col *vals, int32_t n_vals, int64_t n_rows, c
         gj::require(o.radix_bits >= 0 && o.radix_bits <= 16, "radix_bits must be 0..16");
         gj::require(o.block_size == 0 || o.block_size == gj::kBlock, "block_size must be 0 or 256");
         gj::require(o.lds_budget >= 0, "negative lds_budget");
+        gj::require(o.ht_occupancy >= 0.0f && o.ht_occupancy <= 64.0f, "ht_occupancy must be 0..64");
 
         out->n_groups = 0;
         out->key = nullptr;
@@ -350,7 +351,7 @@ int gj_groupby(gj_col key, const gj_col *vals, int32_t n_vals, int64_t n_rows, c
         gj::Ctx ctx(alloc, (hipStream_t)stream);
         // the group count decides the algorithm and the partition passes: estimate it
         double g_est = 0.0;
-        if (algo == GJ_GB_AUTO || (algo == GJ_GB_PARTITION && o.radix_bits == 0))
+        if (algo == GJ_GB_AUTO || algo == GJ_GB_HASH || (algo == GJ_GB_PARTITION && o.radix_bits == 0))
             g_est = gj::estimate_groups(ctx, kb, key.data, n);
         if (algo == GJ_GB_AUTO) {
             float f[12];
@@ -390,7 +391,8 @@ int gj_groupby(gj_col key, const gj_col *vals, int32_t n_vals, int64_t n_rows, c
             if (fell_back) algo = GJ_GB_HASH;  // too many distinct keys per partition
         }
         if (algo == GJ_GB_HASH)
-            g = gj::groupby_hash(ctx, kb, key.data, vcols, n_vals, n, aggs, n_aggs, o.lds_budget, &okey, oaggs);
+            g = gj::groupby_hash(ctx, kb, key.data, vcols, n_vals, n, aggs, n_aggs, o.lds_budget, g_est,
+                                 o.ht_occupancy, &okey, oaggs);
         else if (algo == GJ_GB_SORT)
             g = gj::groupby_sort(ctx, kb, key.data, vcols, n_vals, n, aggs, n_aggs, gfur, &okey, oaggs);
         out->n_groups = g;

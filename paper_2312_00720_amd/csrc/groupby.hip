@@ -1102,9 +1102,10 @@ struct HgbArgs {
     uint32_t n;
     void *table;          // 4-byte keys: packed (key << 32 | row); 8-byte keys: row index
     int log2cap;
+    uint32_t max_probe;   // slots a row probes before it flags the table as too small
     uint32_t *gid;        // group id of inserting rows
     uint32_t *gid_loc;    // row with which the key was inserted
-    uint32_t *ngroups;
+    uint32_t *ngroups;    // [0] groups so far, [1] set when a row found no slot
     void *tmp_keys;       // key of each group id
     // stage 2
     AggSpec spec;
@@ -1129,7 +1130,7 @@ template <typename K>
 __device__ __forceinline__ void hgb_insert_one(const HgbArgs &a, const K *keys, uint32_t i, K k) {
     const uint64_t mask = (1ull << a.log2cap) - 1ull;
     uint64_t h = global_slot_hash<K>(k) & mask;
-    for (uint64_t step = 0; step <= mask; ++step) {
+    for (uint64_t step = 0; step <= mask && step < a.max_probe; ++step) {
         if constexpr (sizeof(K) == 4) {
             unsigned long long *t = static_cast<unsigned long long *>(a.table);
             unsigned long long cur = __atomic_load_n(&t[h], __ATOMIC_RELAXED);
@@ -1168,6 +1169,7 @@ __device__ __forceinline__ void hgb_insert_one(const HgbArgs &a, const K *keys, 
         }
         h = (h + 1) & mask;
     }
+    atomicOr(&a.ngroups[1], 1u);  // no slot within the probe limit: the table is too small
 }
 
 template <typename K>
@@ -1704,22 +1706,16 @@ void groupby_partition_segments(Ctx &ctx, int key_bytes, const void *key, const 
 }
 
 int64_t groupby_hash(Ctx &ctx, int key_bytes, const void *key, const int32_t *const *vals, int n_vals, uint32_t n,
-                     const gj_agg *aggs, int n_aggs, int lds_budget, void **out_key, void **out_aggs) {
+                     const gj_agg *aggs, int n_aggs, int lds_budget, double g_est, float occupancy, void **out_key,
+                     void **out_aggs) {
     hipStream_t st = ctx.stream;
     HgbArgs a{};
     a.keys = key;
     a.n = n;
-    int log2cap = 4;
-    while ((1ull << log2cap) < (uint64_t)n + n / 2) ++log2cap;
-    a.log2cap = log2cap;
     const size_t slot = key_bytes == 4 ? 8 : 4;
-    a.table = ctx.scratch(((size_t)1 << log2cap) * slot);
-    if (key_bytes == 4) fill_u64(st, static_cast<uint64_t *>(a.table), ~0ull, (uint64_t)1 << log2cap);
-    else fill_u32(st, static_cast<uint32_t *>(a.table), 0xFFFFFFFFu, (uint64_t)1 << log2cap);
     a.gid = ctx.scratch_n<uint32_t>(n);
     a.gid_loc = ctx.scratch_n<uint32_t>(n);
-    a.ngroups = ctx.scratch_n<uint32_t>(1);
-    fill_u32(st, a.ngroups, 0u, 1);
+    a.ngroups = ctx.scratch_n<uint32_t>(2);
     a.tmp_keys = ctx.scratch((size_t)n * key_bytes);
     const uint32_t grid = std::min<uint32_t>(ceil_div_u32(n, kBlock), 256u * 16u);
     // Group ids come from an atomic counter, so a full grid hands them out in the
@@ -1732,16 +1728,43 @@ int64_t groupby_hash(Ctx &ctx, int key_bytes, const void *key, const int32_t *co
     const size_t rec = (size_t)make_spec(aggs, n_aggs, no_outs.data()).words * 4;
     const size_t budget = lds_budget > 0 ? (size_t)lds_budget : (size_t)64 * 1024;
     const uint32_t prefix = (uint32_t)std::min<size_t>(n, std::max<size_t>(2048, 2 * (budget / rec)));
-    HgbArgs ap = a;
-    ap.n = prefix;
-    if (key_bytes == 4) {
-        GJ_LAUNCH("k_hgb_insert", 16.0 * prefix, k_hgb_insert<int32_t>, dim3(1), dim3(kBlock), 0, st, ap);
-        if (n > prefix) GJ_LAUNCH("k_hgb_insert", 16.0 * n, k_hgb_insert<int32_t>, dim3(grid), dim3(kBlock), 0, st, a);
-    } else {
-        GJ_LAUNCH("k_hgb_insert", 20.0 * prefix, k_hgb_insert<int64_t>, dim3(1), dim3(kBlock), 0, st, ap);
-        if (n > prefix) GJ_LAUNCH("k_hgb_insert", 20.0 * n, k_hgb_insert<int64_t>, dim3(grid), dim3(kBlock), 0, st, a);
+    // the table: 1.5 slots per row always holds every group; with a group-count
+    // estimate it is sized for that instead (load `occupancy`, default 0.45), and a
+    // row that finds no slot within 4096 probes sends the insert back to the
+    // row-sized table
+    int log2rows = 4;
+    while ((1ull << log2rows) < (uint64_t)n + n / 2) ++log2rows;
+    const auto insert = [&](int log2cap, uint32_t max_probe) {
+        a.log2cap = log2cap;
+        a.max_probe = max_probe;
+        a.table = ctx.scratch(((size_t)1 << log2cap) * slot);
+        if (key_bytes == 4) fill_u64(st, static_cast<uint64_t *>(a.table), ~0ull, (uint64_t)1 << log2cap);
+        else fill_u32(st, static_cast<uint32_t *>(a.table), 0xFFFFFFFFu, (uint64_t)1 << log2cap);
+        fill_u32(st, a.ngroups, 0u, 2);
+        HgbArgs ap = a;
+        ap.n = prefix;
+        if (key_bytes == 4) {
+            GJ_LAUNCH("k_hgb_insert", 16.0 * prefix, k_hgb_insert<int32_t>, dim3(1), dim3(kBlock), 0, st, ap);
+            if (n > prefix) GJ_LAUNCH("k_hgb_insert", 16.0 * n, k_hgb_insert<int32_t>, dim3(grid), dim3(kBlock), 0, st, a);
+        } else {
+            GJ_LAUNCH("k_hgb_insert", 20.0 * prefix, k_hgb_insert<int64_t>, dim3(1), dim3(kBlock), 0, st, ap);
+            if (n > prefix) GJ_LAUNCH("k_hgb_insert", 20.0 * n, k_hgb_insert<int64_t>, dim3(grid), dim3(kBlock), 0, st, a);
+        }
+        uint32_t h[2];
+        GJ_HIP(hipMemcpyAsync(h, a.ngroups, 8, hipMemcpyDeviceToHost, st));
+        GJ_HIP(hipStreamSynchronize(st));
+        return std::make_pair(h[0], h[1] != 0);
+    };
+    std::pair<uint32_t, bool> r{0, true};
+    if (g_est > 0.0) {
+        const double occ = occupancy > 0.0f ? (double)occupancy : 0.45;
+        int log2est = 12;
+        while (log2est < log2rows && (double)(1ull << log2est) * occ < g_est) ++log2est;
+        if (log2est < log2rows) r = insert(log2est, 4096);
     }
-    const uint32_t g = read_back(a.ngroups, st);
+    if (r.second) r = insert(log2rows, 0xFFFFFFFFu);
+    require(!r.second, "hash group-by: no table slot for a key", GJ_EUNSUPPORTED);  // cannot happen: slots > rows
+    const uint32_t g = r.first;
     *out_key = ctx.output((size_t)std::max<uint32_t>(g, 1) * key_bytes);
     std::vector<void *> outs(n_aggs);
     for (int j = 0; j < n_aggs; ++j) {

@@ -203,8 +203,11 @@ double estimate_groups(Ctx &ctx, int key_bytes, const void *key, uint32_t n);
 int64_t groupby_partition(Ctx &ctx, int key_bytes, const void *key, const int32_t *const *vals, int n_vals,
                           uint32_t n, const gj_agg *aggs, int n_aggs, bool gfur, int bits, void **out_key,
                           void **out_aggs, int *fell_back);
+// g_est > 0 sizes the global table for about that many groups at load `occupancy`
+// (<= 0: 0.45); a table found too small is replaced by one of 1.5 slots per row.
 int64_t groupby_hash(Ctx &ctx, int key_bytes, const void *key, const int32_t *const *vals, int n_vals, uint32_t n,
-                     const gj_agg *aggs, int n_aggs, int lds_budget, void **out_key, void **out_aggs);
+                     const gj_agg *aggs, int n_aggs, int lds_budget, double g_est, float occupancy, void **out_key,
+                     void **out_aggs);
 int64_t groupby_sort(Ctx &ctx, int key_bytes, const void *key, const int32_t *const *vals, int n_vals, uint32_t n,
                      const gj_agg *aggs, int n_aggs, bool gfur, void **out_key, void **out_aggs);
 

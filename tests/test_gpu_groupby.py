@@ -151,6 +151,17 @@ def test_hash_ids_follow_the_first_rows():
     assert np.isin(first, gk[:1638]).all()
 
 
+@pytest.mark.parametrize("occ", [0.0, 0.9, 8.0])
+def test_hash_table_sizing(occ):
+    """The global table is sized from the group-count estimate at load `occ`; at
+    8.0 it is far too small, rows run out of probes, and the insert runs again
+    on a table of 1.5 slots per row. Results are exact either way."""
+    d = datagen.groupby_input(300000, 50000, 2, seed=67)
+    check(d["key"], d["vals"], algo="hash", ht_occupancy=occ)
+    d = datagen.groupby_input(100000, 7, 2, seed=68, key_bytes=8)
+    check(d["key"], d["vals"], algo="hash", ht_occupancy=occ)
+
+
 def test_hash_global_aggregation_path():
     d = datagen.groupby_input(100000, 2000, 2, seed=6)
     check(d["key"], d["vals"], algo="hash", lds_budget=64)
