@@ -56,11 +56,6 @@ struct ValSrc {
     const int32_t *rowid;          // GFUR: row ids aligned with the keys; else nullptr
 };
 
-__device__ __forceinline__ int32_t load_val(const ValSrc &v, int c, uint32_t row) {
-    const uint32_t r = v.rowid ? (uint32_t)v.rowid[row] : row;
-    return v.col[c][r];
-}
-
 __device__ __forceinline__ void rec_init(uint32_t *rec, const AggSpec &s) {
     for (int j = 0; j < s.n; ++j) {
         uint32_t *p = rec + s.word[j];
@@ -69,21 +64,6 @@ __device__ __forceinline__ void rec_init(uint32_t *rec, const AggSpec &s) {
             case GJ_COUNT: p[0] = 0; break;
             case GJ_MIN: p[0] = (uint32_t)INT32_MAX; break;
             default: p[0] = (uint32_t)INT32_MIN; break;
-        }
-    }
-}
-
-// Accumulate one row into an LDS record.
-__device__ __forceinline__ void rec_add_lds(uint32_t *rec, const AggSpec &s, const ValSrc &v, uint32_t row) {
-    for (int j = 0; j < s.n; ++j) {
-        uint32_t *p = rec + s.word[j];
-        switch (s.op[j]) {
-            case GJ_SUM:
-                atomicAdd(reinterpret_cast<unsigned long long *>(p), (unsigned long long)(long long)load_val(v, s.col[j], row));
-                break;
-            case GJ_COUNT: atomicAdd(p, 1u); break;
-            case GJ_MIN: atomicMin(reinterpret_cast<int *>(p), load_val(v, s.col[j], row)); break;
-            default: atomicMax(reinterpret_cast<int *>(p), load_val(v, s.col[j], row)); break;
         }
     }
 }
@@ -118,21 +98,6 @@ __device__ __forceinline__ void rec_flush(const uint32_t *rec, const AggSpec &s,
                 else *q = (int)p[0];
                 break;
             }
-        }
-    }
-}
-
-// Fold one row directly into output group o with global atomics.
-__device__ __forceinline__ void row_add_global(const AggSpec &s, const ValSrc &v, uint32_t row, uint64_t o) {
-    for (int j = 0; j < s.n; ++j) {
-        switch (s.op[j]) {
-            case GJ_SUM:
-                atomicAdd(static_cast<unsigned long long *>(s.out[j]) + o,
-                          (unsigned long long)(long long)load_val(v, s.col[j], row));
-                break;
-            case GJ_COUNT: atomicAdd(static_cast<unsigned long long *>(s.out[j]) + o, 1ull); break;
-            case GJ_MIN: atomicMin(static_cast<int *>(s.out[j]) + o, load_val(v, s.col[j], row)); break;
-            default: atomicMax(static_cast<int *>(s.out[j]) + o, load_val(v, s.col[j], row)); break;
         }
     }
 }
