@@ -35,7 +35,7 @@ extern "C" {
 #define GJ_EINVAL (-1)       /* null pointer, negative size, mismatched dtypes, bad option */
 #define GJ_ENOMEM (-2)       /* the allocator returned NULL */
 #define GJ_EHIP (-3)         /* a HIP runtime error; text in gj_last_error() */
-#define GJ_EUNSUPPORTED (-4) /* a valid request this build does not implement */
+#define GJ_EUNSUPPORTED (-4) /* a valid request the library does not implement */
 #define GJ_ECAPACITY (-5)    /* a caller-sized output is too small */
 #define GJ_EOVERFLOW (-6)    /* more than 2^31 - 1 rows in one relation */
 
