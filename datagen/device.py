@@ -5,6 +5,7 @@ that multi-gigabyte inputs take seconds. This module draws random numbers only.
 """
 from __future__ import annotations
 
+import numpy as np
 import torch
 
 INT32_MIN = -(2 ** 31)
@@ -120,3 +121,22 @@ def join_batch(r_sizes, s_sizes, c: int, seed: int, device="cuda", chunk_rows: i
     s_pay = payloads(g, int(so[-1]), c, device)
     return {"r_key": r_key, "r_pay": r_pay, "s_key": s_key, "s_pay": s_pay,
             "r_off": [int(x) for x in ro], "s_off": [int(x) for x in so]}
+
+
+def groupby_batch(sizes, cards, n_vals: int, seed: int, *, lo: int = -(2 ** 20), hi: int = 2 ** 20,
+                  device="cuda") -> dict:
+    """A batch of independent group-bys stored back to back: instance i has
+    sizes[i] rows whose int32 keys are uniform over 0..cards[i]-1, and n_vals int32
+    value columns uniform in [lo, hi]. Returns the columns and the host offsets."""
+    g = generator(seed, device)
+    sizes = np.asarray(sizes, dtype=np.int64)
+    off = np.concatenate([[0], np.cumsum(sizes)])
+    n = int(off[-1])
+    card = torch.repeat_interleave(torch.as_tensor(np.asarray(cards, dtype=np.int64), device=device),
+                                   torch.as_tensor(sizes, device=device))
+    u = torch.rand(n, generator=g, device=device, dtype=torch.float64)
+    key = torch.minimum((u * card).to(torch.int64), card - 1).to(torch.int32)
+    del u, card
+    vals = [torch.randint(lo, hi + 1, (n,), generator=g, device=device, dtype=torch.int64)
+            .to(torch.int32) for _ in range(n_vals)]
+    return {"key": key, "vals": vals, "off": [int(x) for x in off]}
