@@ -37,7 +37,7 @@ extern "C" {
 #define GJ_EHIP (-3)         /* a HIP runtime error; text in gj_last_error() */
 #define GJ_EUNSUPPORTED (-4) /* a valid request the library does not implement */
 #define GJ_ECAPACITY (-5)    /* a caller-sized output is too small */
-#define GJ_EOVERFLOW (-6)    /* more than 2^31 - 1 rows in one relation */
+#define GJ_EOVERFLOW (-6)    /* more than 2^31 - 1 rows in one relation, or join work units */
 
 typedef enum { GJ_I32 = 1, GJ_I64 = 2 } gj_dtype;
 
@@ -67,21 +67,31 @@ typedef struct {
  * partitions (key, row id) only and gathers from the original columns. */
 typedef enum { GJ_MAT_AUTO = 0, GJ_MAT_GFTR = 1, GJ_MAT_GFUR = 2 } gj_mat;
 
+/* Join algorithm: the partitioned hash join of Section 4.1.4 (PHJ) or the
+ * sort-merge join of Section 3.1.1 (SMJ: full-key radix sort of both
+ * relations, Merge Path match finding; its output comes in ascending key
+ * order). Either takes GFTR or GFUR materialization. */
+typedef enum { GJ_JOIN_AUTO = 0, GJ_JOIN_PHJ = 1, GJ_JOIN_SMJ = 2 } gj_join_algo;
+
 /* Join options; 0 in any field means "choose automatically". Options change
- * speed, never results. */
+ * speed, never results (SMJ additionally fixes the output order). */
 typedef struct {
     int32_t mat;               /* gj_mat */
-    int32_t unique_build_keys; /* hint that R.key is unique; results stay exact if wrong */
+    int32_t unique_build_keys; /* accepted and ignored: the count pass already detects, on the
+                                  device, whether any S row matches twice, and picks the
+                                  streaming write pass when none does */
     int32_t radix_bits;        /* total partition bits, 1..16 */
     int32_t passes;            /* 1 or 2 (each pass uses at most 8 bits) */
     int32_t block_size;        /* reserved; must be 0 or 256 */
-    float ht_occupancy;        /* reserved */
+    float ht_occupancy;        /* ignored by joins (the LDS table has at least as many buckets
+                                  as rows of its build block) */
     int32_t lds_budget;        /* max R rows per build block, 64..16384 (8-byte keys: 64..8192);
                                   0: 4096 below |R| = 2^24; from there 16384 for GFTR with
                                   4-byte keys and at most 18 bytes of R payload per row,
                                   else 8192; the LDS table
                                   has 4096, 8192 or 16384 rows, the smallest that holds it */
     uint64_t flags;            /* reserved, must be 0 */
+    int32_t algo;              /* gj_join_algo */
 } gj_join_opts;
 
 /* Join output T(key, r_1..r_cR, s_1..s_cS). The library allocates every column
@@ -105,7 +115,12 @@ typedef struct {
  * GJ_I32 or GJ_I64. Output row order is unspecified but deterministic for a
  * given input and options. Empty inputs give n_rows = 0 and NULL columns.
  * Default radix_bits: partitions of about lds_budget / 2 R rows (at least 1 bit).
- * Synchronizes with `stream` twice (unit count and output size).
+ * Partition digits are the low key bits; when the largest R partition holds more
+ * than four times the mean plus a build block (keys whose low bits barely vary),
+ * both relations are partitioned again on the MurmurHash3 finalizer of the key.
+ * More than 2^31 - 1 work units (partitions far beyond the build block, as with
+ * very many duplicate keys and a tiny lds_budget) return GJ_EOVERFLOW before any
+ * match is sought. Synchronizes with `stream` twice (unit count and output size).
  */
 int gj_join(const gj_rel *R, const gj_rel *S, const gj_join_opts *opts,
             const gj_allocator *alloc, void *stream, gj_join_out *out);
@@ -227,9 +242,17 @@ typedef struct {
     int32_t op;  /* gj_agg_op */
 } gj_agg;
 
-/* Group-by algorithm: hash (Section 4.2, Algorithm 1), sort (Section 4.1.3)
- * or partition (Section 4.3). */
-typedef enum { GJ_GB_AUTO = 0, GJ_GB_HASH = 1, GJ_GB_SORT = 2, GJ_GB_PARTITION = 3 } gj_gb_algo;
+/* Group-by algorithm: hash (Section 4.2, Algorithm 1), sort (Section 4.1.3),
+ * partition (Section 4.3), or sort on dictionary-encoded keys (Section 4.4:
+ * the distinct keys get codes 0..g-1 in key order from a global hash table,
+ * rows are sorted on the code bytes that vary, then reduced; always GFTR). */
+typedef enum {
+    GJ_GB_AUTO = 0,
+    GJ_GB_HASH = 1,
+    GJ_GB_SORT = 2,
+    GJ_GB_PARTITION = 3,
+    GJ_GB_SORT_DE = 4
+} gj_gb_algo;
 typedef struct {
     int32_t algo;       /* gj_gb_algo */
     int32_t mat;        /* gj_mat, for sort and partition */
@@ -240,8 +263,12 @@ typedef struct {
                            out too small (a row finds no slot within 4096 probes, as loads above 1
                            make sure of) is replaced by one of 1.5 slots per row and the insert
                            runs again; the result does not depend on it. */
-    int32_t lds_budget; /* hash: bytes of LDS for aggregation records (0: 64 KiB); the groups beyond
-                           what fits aggregate with global atomics */
+    int32_t lds_budget; /* hash: bytes of LDS per workgroup for aggregation records (0: 160 KB,
+                           a compute unit's LDS). When the group ids, cut into at most 16
+                           consecutive ranges, fit that budget per range, every group
+                           aggregates in LDS (one workgroup per row chunk and id range);
+                           otherwise the ids that fit min(budget, 64 KiB) aggregate in LDS
+                           and the rest with global atomics */
 } gj_groupby_opts;
 
 /* Group-by output A(k, a_1..a_n): one row per distinct key. aggs[i] is the
@@ -258,8 +285,9 @@ typedef struct {
  * Grouped aggregation with one group key and reducible aggregates
  * (Section 2.2): for each distinct key, COUNT(*) and SUM/MIN/MAX of value
  * columns. Keys are GJ_I32 or GJ_I64; value columns GJ_I32. SUM is exact in
- * int64. Group order: ascending key for the sort algorithm; unspecified (but
- * deterministic) for partition; unspecified for hash.
+ * int64. Group order: ascending key for the sort algorithms (with or without
+ * dictionary encoding); unspecified (but deterministic) for partition;
+ * unspecified for hash.
  * Synchronizes with `stream` to read the group count.
  */
 int gj_groupby(gj_col key, const gj_col *vals, int32_t n_vals, int64_t n_rows,
@@ -336,6 +364,24 @@ int gj_partition(gj_col key, const gj_col *cols, int32_t n_cols, int64_t n_rows,
                  void *out_key, void *const *out_cols, void *out_rowid, int32_t *out_offsets,
                  const gj_allocator *alloc, void *stream);
 
+/* ---- Machine measurements ----------------------------------------------------
+ * The two kernels behind the cost model's constants (Section 4.1.1, Table 1).
+ *
+ * gj_stream_copy: dst[0..bytes) = src[0..bytes) with 16-byte loads and stores
+ * (both buffers device memory, 16-byte aligned, not overlapping): the plain
+ * streaming rate that bounds every pass over HBM.
+ *
+ * gj_gather_i32: out[i] = values[map[i]] for i < n (device buffers): map and
+ * out are streamed, values is read where map points. A map that walks
+ * partition-local rows (clustered) reads values in few cache lines; a random
+ * permutation (unclustered) reads one line per value. Their time ratio s gives
+ * B_G / B_R = (12 s - 8) / 4 (Section 4.1.1). Entries of map outside
+ * [0, n_values) give 0. Returns GJ_EOVERFLOW for n_values > 2^31 - 1.
+ */
+int gj_stream_copy(const void *src, void *dst, size_t bytes, void *stream);
+int gj_gather_i32(const int32_t *map, const int32_t *values, int64_t n_values, int32_t *out, int64_t n,
+                  void *stream);
+
 /* ---- Algorithm selection -----------------------------------------------------
  * Workload features (12 floats, each scaled to about [0, 1]):
  *   [0] 1 for a join, 0 for a group-by
@@ -371,6 +417,9 @@ int gj_selector_set_weights(const float *params, int32_t n);
 /* Override the cost model's constants (bytes/s of streaming, B_G/B_R of 4-byte
  * gathers, scattered global atomics per second). */
 int gj_set_cost_constants(double seq_bytes_per_s, double rand_ratio, double atomic_rate);
+
+/* The cost model's current constants (host pointers). */
+int gj_get_cost_constants(double *seq_bytes_per_s, double *rand_ratio, double *atomic_rate);
 
 /* ---- Selector network ------------------------------------------------------
  * 12 workload features -> 64 -> 64 (ReLU) -> 5 logits over {GFTR, GFUR, hash,

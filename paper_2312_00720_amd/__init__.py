@@ -18,7 +18,8 @@ LIB_PATH = os.path.join(_HERE, "libgj.so")
 
 GJ_I32, GJ_I64 = 1, 2
 MAT = {"auto": 0, "gftr": 1, "gfur": 2}
-GB_ALGO = {"auto": 0, "hash": 1, "sort": 2, "partition": 3}
+JOIN_ALGO = {"auto": 0, "phj": 1, "smj": 2}
+GB_ALGO = {"auto": 0, "hash": 1, "sort": 2, "partition": 3, "sort_de": 4}
 AGG_OP = {"sum": 1, "count": 2, "min": 3, "max": 4}
 DIGIT = {"bits": 0, "hash": 1, "ordered": 2}
 ERRORS = {-1: "GJ_EINVAL", -2: "GJ_ENOMEM", -3: "GJ_EHIP", -4: "GJ_EUNSUPPORTED",
@@ -57,7 +58,7 @@ class JoinOpts(ctypes.Structure):
     _fields_ = [("mat", ctypes.c_int32), ("unique_build_keys", ctypes.c_int32),
                 ("radix_bits", ctypes.c_int32), ("passes", ctypes.c_int32),
                 ("block_size", ctypes.c_int32), ("ht_occupancy", ctypes.c_float),
-                ("lds_budget", ctypes.c_int32), ("flags", ctypes.c_uint64)]
+                ("lds_budget", ctypes.c_int32), ("flags", ctypes.c_uint64), ("algo", ctypes.c_int32)]
 
 
 class JoinOut(ctypes.Structure):
@@ -125,6 +126,12 @@ def lib() -> ctypes.CDLL:
             L.gj_partition.restype = ctypes.c_int
             L.gj_partition.argtypes = [Col, ctypes.POINTER(Col), i32, i64, i32, i32, i32, i32,
                                        vp, ctypes.POINTER(vp), vp, vp, ctypes.POINTER(Allocator), vp]
+            L.gj_get_cost_constants.restype = ctypes.c_int
+            L.gj_get_cost_constants.argtypes = [ctypes.POINTER(ctypes.c_double)] * 3
+            L.gj_stream_copy.restype = ctypes.c_int
+            L.gj_stream_copy.argtypes = [vp, vp, ctypes.c_size_t, vp]
+            L.gj_gather_i32.restype = ctypes.c_int
+            L.gj_gather_i32.argtypes = [vp, vp, i64, vp, i64, vp]
             L.gj_groupby.restype = ctypes.c_int
             L.gj_groupby.argtypes = [Col, ctypes.POINTER(Col), i32, i64, ctypes.POINTER(Agg), i32,
                                      ctypes.POINTER(GroupByOpts), ctypes.POINTER(Allocator), vp,
@@ -264,9 +271,11 @@ def _raise(rc: int):
 
 
 def join(r_key: torch.Tensor, r_pay, s_key: torch.Tensor, s_pay, *, mat: str = "auto",
-         radix_bits: int = 0, passes: int = 0, lds_budget: int = 0, unique_build_keys: bool = False):
+         radix_bits: int = 0, passes: int = 0, lds_budget: int = 0, unique_build_keys: bool = False,
+         algo: str = "auto"):
     """Inner equi-join on key. Returns (key, [R payloads], [S payloads]) as
-    device tensors; row order is unspecified but deterministic."""
+    device tensors; row order is unspecified but deterministic (ascending key
+    for algo="smj")."""
     L = lib()
     r_pay, s_pay = list(r_pay), list(s_pay)
     dev = r_key.device
@@ -276,7 +285,7 @@ def join(r_key: torch.Tensor, r_pay, s_key: torch.Tensor, s_pay, *, mat: str = "
     sp = (Col * max(1, len(s_pay)))(*[_col(t) for t in s_pay])
     R = Rel(_col(r_key), rp, len(r_pay), r_key.numel())
     S = Rel(_col(s_key), sp, len(s_pay), s_key.numel())
-    o = JoinOpts(MAT[mat], int(unique_build_keys), radix_bits, passes, 0, 0.0, lds_budget, 0)
+    o = JoinOpts(MAT[mat], int(unique_build_keys), radix_bits, passes, 0, 0.0, lds_budget, 0, JOIN_ALGO[algo])
     ro = (ctypes.c_void_p * max(1, len(r_pay)))()
     so = (ctypes.c_void_p * max(1, len(s_pay)))()
     out = JoinOut(None, ro, so, 0)
@@ -572,6 +581,25 @@ def groupby_batch(key: torch.Tensor, vals, offsets, aggs, *, mat: str = "gftr", 
     return keys, res, [int(goff[i]) for i in range(n + 1)]
 
 
+def stream_copy(src: torch.Tensor, dst: torch.Tensor) -> None:
+    """dst = src byte for byte with the library's streaming kernel (contiguous
+    device tensors of equal byte size)."""
+    nb = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nb or not (src.is_contiguous() and dst.is_contiguous()):
+        raise ValueError("contiguous tensors of equal byte size")
+    _raise(lib().gj_stream_copy(src.data_ptr(), dst.data_ptr(), nb, _stream(src.device)))
+
+
+def gather_i32(map_: torch.Tensor, values: torch.Tensor, out: torch.Tensor) -> None:
+    """out[i] = values[map_[i]] (int32 device tensors; out of range map entries give 0)."""
+    if map_.dtype != torch.int32 or values.dtype != torch.int32 or out.dtype != torch.int32:
+        raise TypeError("int32 tensors")
+    if out.numel() != map_.numel():
+        raise ValueError("out and map must have equal length")
+    _raise(lib().gj_gather_i32(map_.data_ptr(), values.data_ptr(), values.numel(), out.data_ptr(), map_.numel(),
+                               _stream(map_.device)))
+
+
 MLP_PARAMS = 5317
 CLASSES = ["gftr", "gfur", "hash", "sort", "partition"]
 
@@ -604,6 +632,13 @@ def selector_set_weights(params) -> None:
 
 def set_cost_constants(seq_bytes_per_s: float, rand_ratio: float, atomic_rate: float) -> None:
     _raise(lib().gj_set_cost_constants(seq_bytes_per_s, rand_ratio, atomic_rate))
+
+
+def get_cost_constants() -> tuple:
+    """(streaming bytes/s, B_G/B_R, scattered global atomics/s) of the cost model."""
+    x = [ctypes.c_double() for _ in range(3)]
+    _raise(lib().gj_get_cost_constants(*[ctypes.byref(v) for v in x]))
+    return tuple(v.value for v in x)
 
 
 def mlp_forward(params: torch.Tensor, X: torch.Tensor, mask: torch.Tensor) -> torch.Tensor:

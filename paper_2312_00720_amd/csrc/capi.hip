@@ -2,6 +2,8 @@
 // scratch management and dispatch to the kernel drivers.
 #include <string.h>
 
+#include <algorithm>
+
 #include <string>
 #include <vector>
 
@@ -113,6 +115,7 @@ int gj_join(const gj_rel *R, const gj_rel *S, const gj_join_opts *opts, const gj
         gj::require(o.block_size == 0 || o.block_size == gj::kBlock, "block_size must be 0 or 256");
         gj::check_join_lds_budget(o.lds_budget, dtype_bytes(R->key.dtype));
         gj::require(o.flags == 0, "flags must be 0");
+        gj::require(o.algo >= GJ_JOIN_AUTO && o.algo <= GJ_JOIN_SMJ, "bad join algorithm");
 
         out->n_rows = 0;
         out->key = nullptr;
@@ -140,38 +143,98 @@ int gj_join(const gj_rel *R, const gj_rel *S, const gj_join_opts *opts, const gj
         gj::Ctx ctx(alloc, (hipStream_t)stream);
         gj::JoinSide side[2];
         const gj_rel *rel[2] = {R, S};
+        if (o.algo == GJ_JOIN_SMJ) {
+            // transformation: full-key LSD radix sort of (key, payloads) or (key, row id)
+            for (int t = 0; t < 2; ++t) {
+                const gj_rel *X = rel[t];
+                const uint32_t n = (uint32_t)X->n_rows;
+                gj::JoinSide &js = side[t];
+                js.key = ctx.scratch((size_t)n * kb);
+                js.rows = n;
+                js.n_pay = X->n_payloads;
+                js.poff = nullptr;
+                gj::PartCols pc;
+                for (int i = 0; i < X->n_payloads; ++i) js.width[i] = dtype_bytes(X->payloads[i].dtype);
+                if (!gfur) {
+                    pc.n = X->n_payloads;
+                    for (int i = 0; i < X->n_payloads; ++i) {
+                        pc.in[i] = X->payloads[i].data;
+                        pc.width[i] = js.width[i];
+                        pc.out[i] = ctx.scratch((size_t)n * js.width[i]);
+                        js.pay[i] = pc.out[i];
+                    }
+                    js.rowid = nullptr;
+                } else {
+                    for (int i = 0; i < X->n_payloads; ++i) js.pay[i] = X->payloads[i].data;
+                    pc.gen_rowid = true;
+                    pc.rowid_out = ctx.scratch_n<int32_t>(n);
+                    js.rowid = static_cast<const int32_t *>(pc.rowid_out);
+                }
+                gj::sort_run(ctx, kb, X->key.data, const_cast<void *>(js.key), pc, n);
+            }
+            gj::JoinOut jo{};
+            const int64_t T = gj::join_sort_merge(ctx, kb, side[0], side[1], gfur, &jo);
+            out->n_rows = T;
+            if (T > 0) {
+                out->key = jo.key;
+                for (int i = 0; i < R->n_payloads; ++i) out->r_payloads[i] = jo.r[i];
+                for (int i = 0; i < S->n_payloads; ++i) out->s_payloads[i] = jo.s[i];
+            }
+            ctx.commit();
+            return GJ_OK;
+        }
+        // Join digits are the low key bits (dense keys spread evenly over them).
+        // Keys whose low bits barely vary (multiples of a power of two, say) pile
+        // into a few partitions: when the largest R partition holds more than four
+        // times the mean plus a build block, both sides are partitioned again on
+        // hashed keys, into the same buffers. The result is the same either way.
+        gj::JoinStats st;
+        st.check_spread = true;
+        const uint64_t mean_r = ((uint64_t)R->n_rows + (1ull << bits) - 1) >> bits;
+        st.spread_limit = (uint32_t)std::min<uint64_t>(4 * mean_r + (uint64_t)r_block, 0xFFFFFFFFull);
         for (int t = 0; t < 2; ++t) {
             const gj_rel *X = rel[t];
             const uint32_t n = (uint32_t)X->n_rows;
-            gj::PartCols pc;
-            void *kout = ctx.scratch((size_t)n * kb);
             gj::JoinSide &js = side[t];
-            js.key = kout;
+            js.key = ctx.scratch((size_t)n * kb);
             js.rows = n;
             js.n_pay = X->n_payloads;
             for (int i = 0; i < X->n_payloads; ++i) js.width[i] = dtype_bytes(X->payloads[i].dtype);
             if (!gfur) {
-                pc.n = X->n_payloads;
-                for (int i = 0; i < X->n_payloads; ++i) {
-                    pc.in[i] = X->payloads[i].data;
-                    pc.width[i] = js.width[i];
-                    pc.out[i] = ctx.scratch((size_t)n * js.width[i]);
-                    js.pay[i] = pc.out[i];
-                }
+                for (int i = 0; i < X->n_payloads; ++i) js.pay[i] = ctx.scratch((size_t)n * js.width[i]);
                 js.rowid = nullptr;
             } else {
-                pc.n = 0;
-                pc.gen_rowid = true;
-                pc.rowid_out = ctx.scratch((size_t)n * 4);
                 for (int i = 0; i < X->n_payloads; ++i) js.pay[i] = X->payloads[i].data;
-                js.rowid = static_cast<const int32_t *>(pc.rowid_out);
+                js.rowid = ctx.scratch_n<int32_t>(n);
             }
-            uint32_t *poff = ctx.scratch_n<uint32_t>(((size_t)1 << bits) + 1);
-            js.poff = poff;
-            gj::partition_run(ctx, kb, X->key.data, kout, pc, n, 0, bits, passes, gj::kDigitBits, poff);
+            js.poff = ctx.scratch_n<uint32_t>(((size_t)1 << bits) + 1);
         }
         gj::JoinOut jo{};
-        const int64_t T = gj::join_partitioned(ctx, kb, side[0], side[1], bits, r_block, gfur, &jo);
+        int64_t T = -1;
+        for (int digit_mode = gj::kDigitBits; T < 0; digit_mode = gj::kDigitHash) {
+            for (int t = 0; t < 2; ++t) {
+                const gj_rel *X = rel[t];
+                gj::JoinSide &js = side[t];
+                gj::PartCols pc;
+                if (!gfur) {
+                    pc.n = X->n_payloads;
+                    for (int i = 0; i < X->n_payloads; ++i) {
+                        pc.in[i] = X->payloads[i].data;
+                        pc.width[i] = js.width[i];
+                        pc.out[i] = const_cast<void *>(js.pay[i]);
+                    }
+                } else {
+                    pc.gen_rowid = true;
+                    pc.rowid_out = const_cast<int32_t *>(js.rowid);
+                }
+                gj::partition_run(ctx, kb, X->key.data, const_cast<void *>(js.key), pc, js.rows, 0, bits, passes,
+                                  digit_mode, const_cast<uint32_t *>(js.poff));
+            }
+            st.hashed_digits = digit_mode == gj::kDigitHash;
+            st.check_spread = !st.hashed_digits;
+            T = gj::join_partitioned(ctx, kb, side[0], side[1], bits, r_block, gfur, &jo, nullptr, 0, nullptr,
+                                     nullptr, &st);
+        }
         out->n_rows = T;
         if (T > 0) {
             out->key = jo.key;
@@ -218,6 +281,8 @@ int gj_join_batch(const gj_rel_batch *R, const gj_rel_batch *S, const gj_join_op
         gj::require(o.mat >= 0 && o.mat <= 2, "bad materialization");
         gj::check_join_lds_budget(o.lds_budget, dtype_bytes(R->key.dtype));
         gj::require(o.flags == 0, "flags must be 0");
+        gj::require(o.algo == GJ_JOIN_AUTO || o.algo == GJ_JOIN_PHJ, "batches run the partitioned hash join only",
+                    GJ_EUNSUPPORTED);
         out->n_rows = 0;
         out->key = nullptr;
         for (int i = 0; i < R->n_payloads; ++i) out->r_payloads[i] = nullptr;
@@ -329,7 +394,7 @@ int gj_groupby(gj_col key, const gj_col *vals, int32_t n_vals, int64_t n_rows, c
         }
         gj_groupby_opts o{};
         if (opts) o = *opts;
-        gj::require(o.algo >= GJ_GB_AUTO && o.algo <= GJ_GB_PARTITION, "bad group-by algorithm");
+        gj::require(o.algo >= GJ_GB_AUTO && o.algo <= GJ_GB_SORT_DE, "bad group-by algorithm");
         gj::require(o.mat >= 0 && o.mat <= 2, "bad materialization");
         gj::require(o.radix_bits >= 0 && o.radix_bits <= 16, "radix_bits must be 0..16");
         gj::require(o.block_size == 0 || o.block_size == gj::kBlock, "block_size must be 0 or 256");
@@ -351,7 +416,8 @@ int gj_groupby(gj_col key, const gj_col *vals, int32_t n_vals, int64_t n_rows, c
         gj::Ctx ctx(alloc, (hipStream_t)stream);
         // the group count decides the algorithm and the partition passes: estimate it
         double g_est = 0.0;
-        if (algo == GJ_GB_AUTO || algo == GJ_GB_HASH || (algo == GJ_GB_PARTITION && o.radix_bits == 0))
+        if (algo == GJ_GB_AUTO || algo == GJ_GB_HASH || algo == GJ_GB_SORT_DE ||
+            (algo == GJ_GB_PARTITION && o.radix_bits == 0))
             g_est = gj::estimate_groups(ctx, kb, key.data, n);
         if (algo == GJ_GB_AUTO) {
             float f[12];
@@ -395,6 +461,9 @@ int gj_groupby(gj_col key, const gj_col *vals, int32_t n_vals, int64_t n_rows, c
                                  o.ht_occupancy, &okey, oaggs);
         else if (algo == GJ_GB_SORT)
             g = gj::groupby_sort(ctx, kb, key.data, vcols, n_vals, n, aggs, n_aggs, gfur, &okey, oaggs);
+        else if (algo == GJ_GB_SORT_DE)
+            g = gj::groupby_sort_de(ctx, kb, key.data, vcols, n_vals, n, aggs, n_aggs, g_est, o.ht_occupancy, &okey,
+                                    oaggs);
         out->n_groups = g;
         out->key = okey;
         for (int j = 0; j < n_aggs; ++j) out->aggs[j] = oaggs[j];

@@ -1078,7 +1078,16 @@ struct HgbArgs {
     void *out_key;
     uint32_t g;
     uint32_t lds_groups;  // groups 0..lds_groups-1 aggregate in LDS records, the rest with global atomics
+    // sliced stage 2 (every group in LDS): consecutive id ranges of slice_groups
+    // groups, rows cut into `chunks` chunks of chunk_rows rows
+    uint32_t slices, slice_groups, chunks, chunk_rows;
 };
+
+// Workgroups are dispatched to the 8 XCDs of the chip round robin by index.
+constexpr uint32_t kXcds = 8;
+// Most id slices of the sliced hash aggregation: every slice re-reads the rows'
+// group ids (from L2), so beyond this the global-atomic stage 2 is used.
+constexpr uint32_t kHgbMaxSlices = 16;
 
 template <typename K>
 __device__ __forceinline__ uint64_t global_slot_hash(K key) {
@@ -1203,6 +1212,52 @@ __global__ __launch_bounds__(kBlock) void k_hgb_aggregate(HgbArgs a) {
         __syncthreads();
         for (uint32_t i = threadIdx.x; i < L; i += kBlock) rec_flush(s_dyn + (uint64_t)i * s.words, s, i, true);
     }
+}
+
+// Stage 2 with every group's record in LDS (is_smem_enough once the groups are
+// cut into id ranges): workgroup (chunk, slice) aggregates the rows of its chunk
+// whose group id falls in its slice of at most slice_groups consecutive ids, then
+// folds its records into the output with global atomics. All slices of a chunk
+// run on one XCD, so the chunk's group ids come from HBM once and from that
+// XCD's L2 for the other slices; value columns are read only for rows in the
+// slice.
+template <int NV, int BT>
+__global__ __launch_bounds__(BT) void k_hgb_aggregate_sliced(HgbArgs a) {
+    constexpr int RB = NV <= 2 ? 8 : 16 / NV;
+    extern __shared__ __align__(16) uint32_t s_dyn[];
+    const AggSpec &s = a.spec;
+    const uint32_t b = blockIdx.x, q = b / kXcds;
+    const uint32_t slice = q % a.slices, chunk = (q / a.slices) * kXcds + b % kXcds;
+    if (chunk >= a.chunks) return;
+    const uint32_t g0 = slice * a.slice_groups;
+    if (g0 >= a.g) return;
+    const uint32_t L = min(a.slice_groups, a.g - g0);
+    for (uint32_t i = threadIdx.x; i < L; i += BT) rec_init(s_dyn + (uint64_t)i * s.words, s);
+    __syncthreads();
+    const uint32_t row0 = chunk * a.chunk_rows;
+    const uint32_t row1 = (uint32_t)min<uint64_t>((uint64_t)row0 + a.chunk_rows, a.n);
+    for (uint32_t base = row0; base < row1; base += BT * RB) {
+        uint32_t loc[RB], off[RB];
+        Row<NV> rr[RB];
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+            const uint32_t i = base + r * BT + threadIdx.x;
+            loc[r] = i < row1 ? a.gid_loc[i] : 0u;
+        }
+        bool any = false;
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+            const uint32_t i = base + r * BT + threadIdx.x;
+            const uint32_t local = a.gid[loc[r]] - g0;  // wraps for ids below the slice
+            const bool in = i < row1 && local < L;
+            off[r] = in ? local * (uint32_t)s.words : spare_off(L * s.words);
+            rr[r] = in ? load_row<NV>(a.vals, i) : Row<NV>{};
+            any |= in;
+        }
+        if (__any(any)) rec_add_rows<NV, RB>(s_dyn, s, off, rr, wave_active_rows<RB>(base, BT, row1), false);
+    }
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < L; i += BT) rec_flush(s_dyn + (uint64_t)i * s.words, s, g0 + i, true);
 }
 
 template <typename K>
@@ -1360,7 +1415,7 @@ __global__ __launch_bounds__(kBlock) void k_sgb_reduce(SgbArgs a) {
                 acc_clear(cur);
                 cur_gid += 1;
                 cur_in_tile = true;
-                ok[cur_gid] = kk[k];
+                if (ok) ok[cur_gid] = kk[k];
             }
             acc_row(cur, rr[k]);
         }
@@ -1368,6 +1423,37 @@ __global__ __launch_bounds__(kBlock) void k_sgb_reduce(SgbArgs a) {
     // the thread holding the tile's last row flushes the run that reaches it
     const uint32_t tile_end = min(t0 + kSgbTile, a.n);
     if (first < tile_end && first + IT >= tile_end && cur.cnt > 0) acc_flush(cur, a.spec, cur_gid, true);
+}
+
+// ---------------------------------------------------------------------------------
+// Dictionary encoding for the sort-based group-by (Section 4.4). The dictionary
+// is the global table of Algorithm 1 (ids in first-come order); sorting its g
+// distinct keys gives every id its rank, so that codes follow key order and the
+// group-by of the codes comes out in key order, as a sort-based group-by does.
+
+// rank[id[p]] = p for the sorted dictionary (id[p]: the id of the p-th smallest key).
+__global__ void k_de_rank(const int32_t *__restrict__ sorted_id, uint32_t g, uint32_t *__restrict__ rank) {
+    for (uint32_t p = blockIdx.x * blockDim.x + threadIdx.x; p < g; p += gridDim.x * blockDim.x)
+        rank[sorted_id[p]] = p;
+}
+
+// code[i] = rank of row i's group: its key's position among the distinct keys.
+__global__ void k_de_encode(const uint32_t *__restrict__ gid_loc, const uint32_t *__restrict__ gid,
+                            const uint32_t *__restrict__ rank, uint32_t n, int32_t *__restrict__ code) {
+    constexpr int RB = 8;
+    for (uint32_t base = blockIdx.x * kBlock * RB; base < n; base += gridDim.x * kBlock * RB) {
+        uint32_t loc[RB];
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+            const uint32_t i = base + r * kBlock + threadIdx.x;
+            loc[r] = i < n ? gid_loc[i] : 0u;
+        }
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+            const uint32_t i = base + r * kBlock + threadIdx.x;
+            if (i < n) code[i] = (int32_t)rank[gid[loc[r]]];
+        }
+    }
 }
 
 }  // namespace
@@ -1670,11 +1756,17 @@ void groupby_partition_segments(Ctx &ctx, int key_bytes, const void *key, const 
 #undef GJ_PGB
 }
 
-int64_t groupby_hash(Ctx &ctx, int key_bytes, const void *key, const int32_t *const *vals, int n_vals, uint32_t n,
-                     const gj_agg *aggs, int n_aggs, int lds_budget, double g_est, float occupancy, void **out_key,
-                     void **out_aggs) {
+// Stage 1 of Algorithm 1: dense group ids from a global table. Fills a.gid (for
+// the inserting rows), a.gid_loc, a.tmp_keys (the key of each id) and returns
+// the group count. One workgroup first inserts the first `prefix` rows a tile at
+// a time, so that the keys seen there take the lowest ids (see groupby_hash).
+// The table: 1.5 slots per row always holds every group; with a group-count
+// estimate it is sized for that instead (load `occupancy`, default 0.45), and a
+// row that finds no slot within 4096 probes sends the insert back to the
+// row-sized table.
+static uint32_t hgb_assign_ids(Ctx &ctx, HgbArgs &a, int key_bytes, const void *key, uint32_t n, uint32_t prefix,
+                        double g_est, float occupancy) {
     hipStream_t st = ctx.stream;
-    HgbArgs a{};
     a.keys = key;
     a.n = n;
     const size_t slot = key_bytes == 4 ? 8 : 4;
@@ -1682,21 +1774,8 @@ int64_t groupby_hash(Ctx &ctx, int key_bytes, const void *key, const int32_t *co
     a.gid_loc = ctx.scratch_n<uint32_t>(n);
     a.ngroups = ctx.scratch_n<uint32_t>(2);
     a.tmp_keys = ctx.scratch((size_t)n * key_bytes);
+    prefix = std::min(prefix, n);
     const uint32_t grid = std::min<uint32_t>(ceil_div_u32(n, kBlock), 256u * 16u);
-    // Group ids come from an atomic counter, so a full grid hands them out in the
-    // order its first tiles happen to win, unrelated to key frequency. One
-    // workgroup first inserts a prefix of the rows a tile at a time: the keys seen
-    // there take the low ids, and under skew those are the frequent keys. Low ids
-    // are the ones that keep LDS records when not every group fits. The full pass
-    // then finds the prefix keys already present.
-    std::vector<void *> no_outs(n_aggs, nullptr);
-    const size_t rec = (size_t)make_spec(aggs, n_aggs, no_outs.data()).words * 4;
-    const size_t budget = lds_budget > 0 ? (size_t)lds_budget : (size_t)64 * 1024;
-    const uint32_t prefix = (uint32_t)std::min<size_t>(n, std::max<size_t>(2048, 2 * (budget / rec)));
-    // the table: 1.5 slots per row always holds every group; with a group-count
-    // estimate it is sized for that instead (load `occupancy`, default 0.45), and a
-    // row that finds no slot within 4096 probes sends the insert back to the
-    // row-sized table
     int log2rows = 4;
     while ((1ull << log2rows) < (uint64_t)n + n / 2) ++log2rows;
     const auto insert = [&](int log2cap, uint32_t max_probe) {
@@ -1729,7 +1808,26 @@ int64_t groupby_hash(Ctx &ctx, int key_bytes, const void *key, const int32_t *co
     }
     if (r.second) r = insert(log2rows, 0xFFFFFFFFu);
     require(!r.second, "hash group-by: no table slot for a key", GJ_EUNSUPPORTED);  // cannot happen: slots > rows
-    const uint32_t g = r.first;
+    return r.first;
+}
+
+int64_t groupby_hash(Ctx &ctx, int key_bytes, const void *key, const int32_t *const *vals, int n_vals, uint32_t n,
+                     const gj_agg *aggs, int n_aggs, int lds_budget, double g_est, float occupancy, void **out_key,
+                     void **out_aggs) {
+    hipStream_t st = ctx.stream;
+    HgbArgs a{};
+    const uint32_t grid = std::min<uint32_t>(ceil_div_u32(n, kBlock), 256u * 16u);
+    // Group ids come from an atomic counter, so a full grid hands them out in the
+    // order its first tiles happen to win, unrelated to key frequency. One
+    // workgroup first inserts a prefix of the rows a tile at a time: the keys seen
+    // there take the low ids, and under skew those are the frequent keys. Low ids
+    // are the ones that keep LDS records when not every group fits. The full pass
+    // then finds the prefix keys already present.
+    std::vector<void *> no_outs(n_aggs, nullptr);
+    const size_t rec = (size_t)make_spec(aggs, n_aggs, no_outs.data()).words * 4;
+    const size_t budget = std::min(lds_budget > 0 ? (size_t)lds_budget : (size_t)64 * 1024, (size_t)64 * 1024);
+    const uint32_t prefix = (uint32_t)std::max<size_t>(2048, 2 * (budget / rec));
+    const uint32_t g = hgb_assign_ids(ctx, a, key_bytes, key, n, prefix, g_est, occupancy);
     *out_key = ctx.output((size_t)std::max<uint32_t>(g, 1) * key_bytes);
     std::vector<void *> outs(n_aggs);
     for (int j = 0; j < n_aggs; ++j) {
@@ -1743,25 +1841,56 @@ int64_t groupby_hash(Ctx &ctx, int key_bytes, const void *key, const int32_t *co
     for (int c = 0; c < n_vals; ++c) a.vals.col[c] = vals[c];
     a.vals.rowid = nullptr;
     a.g = g;
-    // is_smem_enough: every group's record in LDS when they fit the budget. When
-    // they do not, the lowest ids that fit keep LDS records and the rest take
-    // global atomics; with the prefix insert above, the frequent keys hold those
-    // ids under skew and most rows stay off the contended global atomics.
-    a.lds_groups = (uint32_t)std::min<size_t>(g, budget / rec);
     init_outputs(st, a.spec, g);
     const double bytes = (double)n * (4.0 * n_vals + 8.0) + (double)g * (key_bytes + 4.0 * a.spec.words);
-    const size_t alds = a.lds_groups ? ((size_t)a.lds_groups + 1) * rec + kSpareWords * 4 : 0;
-    // every workgroup folds its LDS records into the output with global atomics:
-    // the grid keeps that near 2^19 record flushes, but never drops below one
-    // round of resident workgroups (by LDS, and at most 7 per compute unit by
-    // registers)
-    const uint32_t per_cu = alds ? (uint32_t)std::max<size_t>(1, std::min<size_t>(7, (160u * 1024u) / alds)) : 0;
-    const uint32_t agrid =
-        alds ? std::min<uint32_t>(grid, std::max<uint32_t>(256u * per_cu, (1u << 19) / a.lds_groups)) : grid;
-#define GJ_HAGG(NV) GJ_LAUNCH("k_hgb_aggregate", bytes, k_hgb_aggregate<NV>, dim3(agrid), dim3(kBlock), alds, st, a)
     const int nvt = nv_tier(n_vals);
-    if (nvt == 1) GJ_HAGG(1); else if (nvt == 2) GJ_HAGG(2); else if (nvt == 4) GJ_HAGG(4); else GJ_HAGG(8);
+    // is_smem_enough, per slice: when the groups fit the LDS of a workgroup (at
+    // most the 160 KB of a compute unit) in at most kHgbMaxSlices consecutive id
+    // ranges, every record stays in LDS.
+    const size_t max_lds = (size_t)160 * 1024;
+    const size_t sbudget = std::min(lds_budget > 0 ? (size_t)lds_budget : max_lds, max_lds);
+    const size_t per_wg = sbudget > kSpareWords * 4 + rec ? (sbudget - kSpareWords * 4) / rec - 1 : 0;
+    const uint32_t slices = per_wg >= 64 ? (uint32_t)((g + per_wg - 1) / per_wg) : 0u;
+    if (g > 2 && slices >= 1 && slices <= kHgbMaxSlices) {
+        a.slices = slices;
+        a.slice_groups = ceil_div_u32(g, slices);
+        const size_t alds = ((size_t)a.slice_groups + 1) * rec + kSpareWords * 4;
+        const bool wide = alds > max_lds / 4;  // fewer than four 256-thread workgroups per compute unit
+        const uint32_t per_cu = (uint32_t)std::max<size_t>(1, std::min<size_t>(wide ? 2 : 8, max_lds / alds));
+        // about two rounds of resident workgroups over all slices, chunks a multiple of the XCDs
+        uint32_t chunks = ceil_div_u32(2u * 256u * per_cu, slices);
+        chunks = std::max<uint32_t>(kXcds, (chunks + kXcds - 1) / kXcds * kXcds);
+        a.chunks = chunks;
+        a.chunk_rows = ceil_div_u32(n, chunks);
+        const uint32_t sgrid = chunks * slices;
+#define GJ_HAGG_S(NV, BT) \
+    GJ_LAUNCH("k_hgb_aggregate", bytes, (k_hgb_aggregate_sliced<NV, BT>), dim3(sgrid), dim3(BT), alds, st, a)
+        if (wide) {
+            if (nvt == 1) GJ_HAGG_S(1, 1024); else if (nvt == 2) GJ_HAGG_S(2, 1024);
+            else if (nvt == 4) GJ_HAGG_S(4, 1024); else GJ_HAGG_S(8, 1024);
+        } else {
+            if (nvt == 1) GJ_HAGG_S(1, 256); else if (nvt == 2) GJ_HAGG_S(2, 256);
+            else if (nvt == 4) GJ_HAGG_S(4, 256); else GJ_HAGG_S(8, 256);
+        }
+#undef GJ_HAGG_S
+    } else {
+        // Otherwise the lowest ids that fit (at most the budget, 64 KiB by default)
+        // keep LDS records and the rest take global atomics; with the prefix insert
+        // above, the frequent keys hold those ids under skew and most rows stay off
+        // the contended global atomics.
+        a.lds_groups = (uint32_t)std::min<size_t>(g, budget / rec);
+        const size_t alds = a.lds_groups ? ((size_t)a.lds_groups + 1) * rec + kSpareWords * 4 : 0;
+        // every workgroup folds its LDS records into the output with global atomics:
+        // the grid keeps that near 2^19 record flushes, but never drops below one
+        // round of resident workgroups (by LDS, and at most 7 per compute unit by
+        // registers)
+        const uint32_t per_cu = alds ? (uint32_t)std::max<size_t>(1, std::min<size_t>(7, (160u * 1024u) / alds)) : 0;
+        const uint32_t agrid =
+            alds ? std::min<uint32_t>(grid, std::max<uint32_t>(256u * per_cu, (1u << 19) / a.lds_groups)) : grid;
+#define GJ_HAGG(NV) GJ_LAUNCH("k_hgb_aggregate", bytes, k_hgb_aggregate<NV>, dim3(agrid), dim3(kBlock), alds, st, a)
+        if (nvt == 1) GJ_HAGG(1); else if (nvt == 2) GJ_HAGG(2); else if (nvt == 4) GJ_HAGG(4); else GJ_HAGG(8);
 #undef GJ_HAGG
+    }
     const uint32_t cb = std::min<uint32_t>(ceil_div_u32(g, 256), 4096);
     if (key_bytes == 4)
         GJ_LAUNCH("k_copy_keys", 8.0 * g, k_copy_keys<int32_t>, dim3(cb), dim3(256), 0, st,
@@ -1828,6 +1957,67 @@ int64_t groupby_sort(Ctx &ctx, int key_bytes, const void *key, const int32_t *co
     } else {
         if (nvt == 1) GJ_SGB(int64_t, 1); else if (nvt == 2) GJ_SGB(int64_t, 2); else if (nvt == 4) GJ_SGB(int64_t, 4); else GJ_SGB(int64_t, 8);
     }
+#undef GJ_SGB
+    return g;
+}
+
+int64_t groupby_sort_de(Ctx &ctx, int key_bytes, const void *key, const int32_t *const *vals, int n_vals, uint32_t n,
+                        const gj_agg *aggs, int n_aggs, double g_est, float occupancy, void **out_key,
+                        void **out_aggs) {
+    hipStream_t st = ctx.stream;
+    // the dictionary: Algorithm 1's dense ids over the distinct keys
+    HgbArgs h{};
+    const uint32_t g = hgb_assign_ids(ctx, h, key_bytes, key, n, 2048, g_est, occupancy);
+    *out_key = ctx.output((size_t)std::max<uint32_t>(g, 1) * key_bytes);
+    std::vector<void *> outs(n_aggs);
+    for (int j = 0; j < n_aggs; ++j) {
+        const bool wide = aggs[j].op == GJ_SUM || aggs[j].op == GJ_COUNT;
+        outs[j] = ctx.output((size_t)std::max<uint32_t>(g, 1) * (wide ? 8 : 4));
+        out_aggs[j] = outs[j];
+    }
+    if (g == 0) return 0;
+    // the distinct keys in order (they are the output keys) and each id's rank
+    PartCols dc;
+    dc.gen_rowid = true;
+    int32_t *sorted_id = ctx.scratch_n<int32_t>(g);
+    dc.rowid_out = sorted_id;
+    sort_run(ctx, key_bytes, h.tmp_keys, *out_key, dc, g);
+    uint32_t *rank = ctx.scratch_n<uint32_t>(g);
+    GJ_LAUNCH("k_de_rank", 8.0 * g, k_de_rank, dim3(std::min<uint32_t>(ceil_div_u32(g, 256), 4096)), dim3(256), 0,
+              st, sorted_id, g, rank);
+    // encoding: one 4-byte code per row
+    int32_t *code = ctx.scratch_n<int32_t>(n);
+    GJ_LAUNCH("k_de_encode", 8.0 * n, k_de_encode, dim3(std::min<uint32_t>(ceil_div_u32(n, kBlock * 8), 4096)),
+              dim3(kBlock), 0, st, h.gid_loc, h.gid, rank, n, code);
+    // sort (code, values) on the code bytes that vary: ceil(log2 g / 8) passes
+    int32_t *scode = ctx.scratch_n<int32_t>(n);
+    PartCols pc;
+    ValSrc vs{};
+    vs.n = n_vals;
+    pc.n = n_vals;
+    for (int c = 0; c < n_vals; ++c) {
+        pc.in[c] = vals[c];
+        pc.width[c] = 4;
+        pc.out[c] = ctx.scratch((size_t)n * 4);
+        vs.col[c] = static_cast<const int32_t *>(pc.out[c]);
+    }
+    sort_run(ctx, 4, code, scode, pc, n);
+    // segmented reduction over the sorted codes: group j is code j
+    SgbArgs a{};
+    a.keys = scode;
+    a.n = n;
+    const uint32_t tiles = ceil_div_u32(n, kSgbTile);
+    a.tile_heads = ctx.scratch_n<uint32_t>(tiles + 1);
+    GJ_LAUNCH("k_sgb_heads", 4.0 * n, k_sgb_heads<int32_t>, dim3(tiles), dim3(kBlock), 0, st, a);
+    scan_exclusive_u32(ctx, a.tile_heads, a.tile_heads, tiles, a.tile_heads + tiles);
+    a.spec = make_spec(aggs, n_aggs, outs.data());
+    a.vals = vs;
+    a.out_key = nullptr;
+    init_outputs(st, a.spec, g);
+    const double bytes = (double)n * (4.0 + 4.0 * n_vals) + (double)g * (key_bytes + 4.0 * a.spec.words);
+#define GJ_SGB(NV) GJ_LAUNCH("k_sgb_reduce", bytes, (k_sgb_reduce<int32_t, NV>), dim3(tiles), dim3(kBlock), 0, st, a)
+    const int nvt = nv_tier(n_vals);
+    if (nvt == 1) GJ_SGB(1); else if (nvt == 2) GJ_SGB(2); else if (nvt == 4) GJ_SGB(4); else GJ_SGB(8);
 #undef GJ_SGB
     return g;
 }

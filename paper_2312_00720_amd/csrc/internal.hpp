@@ -210,6 +210,12 @@ int64_t groupby_hash(Ctx &ctx, int key_bytes, const void *key, const int32_t *co
                      void **out_aggs);
 int64_t groupby_sort(Ctx &ctx, int key_bytes, const void *key, const int32_t *const *vals, int n_vals, uint32_t n,
                      const gj_agg *aggs, int n_aggs, bool gfur, void **out_key, void **out_aggs);
+// Sort-based group-by with dictionary-encoded keys (SGB-DE-TR): Algorithm 1's
+// table assigns ids, the sorted distinct keys give each id its rank, rows are
+// sorted on 4-byte codes over the code bytes that vary, then reduced in order.
+int64_t groupby_sort_de(Ctx &ctx, int key_bytes, const void *key, const int32_t *const *vals, int n_vals, uint32_t n,
+                        const gj_agg *aggs, int n_aggs, double g_est, float occupancy, void **out_key,
+                        void **out_aggs);
 
 // Partition group-by of a batch of instances (segments seg_off[0..nseg] of the
 // columns) without any host read: one hashed segmented partition pass (instance i
@@ -310,8 +316,26 @@ struct JoinPlanned {
     uint64_t expect_rows;       // for the profiler's byte count only
     uint32_t *units_out;        // device: receives the unit count
 };
+// Eager single joins only: what the unit count found, and the spread check. With
+// check_spread set, a largest R partition beyond spread_limit rows returns -1
+// before any pass runs (nothing was written, the caller may partition again).
+// hashed_digits: the partitions come from hashed keys, so the LDS bucket hash
+// uses every key bit (with key-bit digits it skips the partition bits).
+// Sort-merge join (Section 3.1.1) on R and S already sorted by key (sort_run):
+// Merge Path lower bounds, counts, scan and write. JoinSide::poff is unused.
+// Output allocated through ctx.output(); returns the output rows (in key order).
+int64_t join_sort_merge(Ctx &ctx, int key_bytes, const JoinSide &R, const JoinSide &S, bool gfur, JoinOut *out);
+
+struct JoinStats {
+    bool check_spread = false;
+    uint32_t spread_limit = 0;
+    bool hashed_digits = false;
+    uint32_t max_r_rows = 0;
+    bool multi_block = false;
+};
 int64_t join_partitioned(Ctx &ctx, int key_bytes, const JoinSide &R, const JoinSide &S, int bits,
                          int r_block, bool gfur, JoinOut *out, const uint8_t *seg_bits = nullptr,
-                         uint32_t n_inst = 0, uint64_t *inst_off = nullptr, const JoinPlanned *pl = nullptr);
+                         uint32_t n_inst = 0, uint64_t *inst_off = nullptr, const JoinPlanned *pl = nullptr,
+                         JoinStats *stats = nullptr);
 
 }  // namespace gj

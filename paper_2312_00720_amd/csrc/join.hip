@@ -93,15 +93,35 @@ struct JoinArgs {
     uint32_t rlds_off[8];       // staged streaming pass: byte offset of R column j in LDS
 };
 
+// Most work units one call may have: unit indices and their scanned offsets
+// are 32-bit.
+constexpr uint64_t kMaxUnits = 0x7FFFFFFFull;
+
+// Units per partition pair. flags[0]: a partition spans several R blocks;
+// flags[2]: most R rows in a partition that S rows probe; flags[3]: the units
+// exceed kMaxUnits (their 64-bit total accumulates at flags + 4), and then no
+// pass processes any unit, so a wrapped 32-bit scan is never read.
 __global__ void k_unit_count(const uint32_t *__restrict__ rpo, const uint32_t *__restrict__ spo,
                              uint32_t np, uint32_t rc, uint32_t spiece, uint32_t *__restrict__ ucnt,
                              uint32_t *__restrict__ flags) {
+    unsigned long long *total = reinterpret_cast<unsigned long long *>(flags + 4);
     for (uint32_t p = blockIdx.x * blockDim.x + threadIdx.x; p < np; p += gridDim.x * blockDim.x) {
         const uint32_t nr = rpo[p + 1] - rpo[p], ns = spo[p + 1] - spo[p];
-        ucnt[p] = (nr && ns) ? ceil_div_u32(nr, rc) * ceil_div_u32(ns, spiece) : 0u;
+        const uint64_t units = (nr && ns) ? (uint64_t)ceil_div_u32(nr, rc) * ceil_div_u32(ns, spiece) : 0ull;
+        ucnt[p] = (uint32_t)min<uint64_t>(units, kMaxUnits);
+        if (units) {
+            const unsigned long long before = atomicAdd(total, (unsigned long long)units);
+            if (before + units > kMaxUnits) atomicOr(&flags[3], 1u);
+        }
         if (nr > rc && ns) atomicOr(&flags[0], 1u);  // a partition spans several R blocks
         if (ns) atomicMax(&flags[2], nr);
     }
+}
+
+// Units the passes process: none once the count overflowed, else at most the
+// launch's (or plan's) capacity.
+__device__ __forceinline__ uint32_t units_to_run(const uint32_t *nunits, const uint32_t *flags, uint32_t cap) {
+    return flags[3] ? 0u : min(*nunits, cap);
 }
 
 __device__ __forceinline__ void copy_val(void *dst, int dw, uint64_t di, const void *src, uint64_t si) {
@@ -561,7 +581,7 @@ __device__ __forceinline__ void join_unit(const JoinArgs &a, uint32_t u, uint64_
 template <typename K, uint32_t BUILD, bool WRITE>
 __global__ __launch_bounds__(Geo<BUILD>::kThreads, Geo<BUILD>::kMinWEager) void k_join(JoinArgs a) {
     __shared__ JoinShared<K, BUILD> sh;
-    if (blockIdx.x < min(*a.nunits, a.cap_units)) join_unit<K, BUILD, WRITE>(a, blockIdx.x, 0ull, sh);
+    if (blockIdx.x < units_to_run(a.nunits, a.flags, a.cap_units)) join_unit<K, BUILD, WRITE>(a, blockIdx.x, 0ull, sh);
 }
 
 // Write pass without a hash table, for the common case recorded by the count
@@ -579,7 +599,7 @@ __global__ __launch_bounds__(kBlock, GFUR ? 4 : 1) void k_join_stream(JoinArgs a
     constexpr uint32_t kSPiece = G::kSPiece;
     if (a.flags[0] | a.flags[1]) return;  // the LDS write pass handles this input
     const int lane = lane_id();
-    const uint32_t n_units = min(*a.nunits, a.cap_units);
+    const uint32_t n_units = units_to_run(a.nunits, a.flags, a.cap_units);
     const uint64_t n_slots = (uint64_t)n_units * kWv;
     const uint64_t out_base = a.out_base ? *a.out_base : 0ull;
     const K *__restrict__ skey = static_cast<const K *>(a.skey);
@@ -668,7 +688,7 @@ __global__ __launch_bounds__(Geo<BUILD>::kThreads, Geo<BUILD>::kMinWStaged) void
     __shared__ uint32_t s_unit[4];
     if (a.flags[0] | a.flags[1]) return;
     const int tid = threadIdx.x, w = tid / kWave, lane = lane_id();
-    const uint32_t n_units = min(*a.nunits, a.cap_units);
+    const uint32_t n_units = units_to_run(a.nunits, a.flags, a.cap_units);
     const uint64_t out_base = a.out_base ? *a.out_base : 0ull;
     const K *__restrict__ skey = static_cast<const K *>(a.skey);
     K *__restrict__ tkey = static_cast<K *>(a.tkey);
@@ -801,7 +821,7 @@ template <typename K, uint32_t BUILD, bool WRITE>
 __global__ __launch_bounds__(Geo<BUILD>::kThreads, WRITE ? Geo<BUILD>::kMinWWrite : Geo<BUILD>::kMinW) void k_join_persist(JoinArgs a) {
     __shared__ JoinShared<K, BUILD> sh;
     if (WRITE && a.lds_if_complex && !(a.flags[0] | a.flags[1])) return;  // the streaming pass writes
-    const uint32_t n_units = min(*a.nunits, a.cap_units);
+    const uint32_t n_units = units_to_run(a.nunits, a.flags, a.cap_units);
     const uint64_t out_base = a.out_base ? *a.out_base : 0ull;
     for (uint32_t u = blockIdx.x; u < n_units; u += gridDim.x) {
         join_unit<K, BUILD, WRITE>(a, u, out_base, sh);
@@ -813,9 +833,10 @@ __global__ __launch_bounds__(Geo<BUILD>::kThreads, WRITE ? Geo<BUILD>::kMinWWrit
 // Units past the processed count (a plan's capacity) contribute nothing.
 __global__ void k_instance_offsets(const uint32_t *__restrict__ ubase, const uint64_t *__restrict__ woff,
                                    uint32_t waves_per_unit, uint32_t n_inst, const uint32_t *__restrict__ nunits,
-                                   uint32_t cap_units, const uint64_t *__restrict__ total,
-                                   const uint64_t *__restrict__ base, uint64_t *__restrict__ out) {
-    const uint32_t nu = min(*nunits, cap_units);
+                                   const uint32_t *__restrict__ flags, uint32_t cap_units,
+                                   const uint64_t *__restrict__ total, const uint64_t *__restrict__ base,
+                                   uint64_t *__restrict__ out) {
+    const uint32_t nu = units_to_run(nunits, flags, cap_units);
     const uint64_t b = base ? *base : 0ull;
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i <= n_inst; i += gridDim.x * blockDim.x) {
         const uint32_t u = (i == n_inst) ? nu : min(ubase[i << 8], nu);
@@ -825,12 +846,14 @@ __global__ void k_instance_offsets(const uint32_t *__restrict__ ubase, const uin
 
 // next = base + total (the first output row of a plan's next group), and the
 // group's unit count for the plan's capacity check.
+// An overflowed unit count reports the largest count, so that the plan's result
+// flags the group as beyond its capacity.
 __global__ void k_advance_base(const uint64_t *__restrict__ base, const uint64_t *__restrict__ total,
                                uint64_t *__restrict__ next, const uint32_t *__restrict__ nunits,
-                               uint32_t *__restrict__ units_out) {
+                               const uint32_t *__restrict__ flags, uint32_t *__restrict__ units_out) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         if (next) *next = (base ? *base : 0ull) + *total;
-        if (units_out) *units_out = *nunits;
+        if (units_out) *units_out = flags[3] ? 0xFFFFFFFFu : *nunits;
     }
 }
 
@@ -895,7 +918,7 @@ size_t staged_lds_limit() {
 
 int64_t join_partitioned(Ctx &ctx, int key_bytes, const JoinSide &R, const JoinSide &S, int bits,
                          int r_block, bool gfur, JoinOut *out, const uint8_t *seg_bits, uint32_t n_inst,
-                         uint64_t *inst_off, const JoinPlanned *pl) {
+                         uint64_t *inst_off, const JoinPlanned *pl, JoinStats *stats) {
     hipStream_t s = ctx.stream;
     require(r_block >= 64 && r_block <= join_max_r_block(key_bytes),
             key_bytes == 4 ? "R build block must be 64..16384 rows" : "R build block must be 64..8192 rows for 8-byte keys");
@@ -903,8 +926,8 @@ int64_t join_partitioned(Ctx &ctx, int key_bytes, const JoinSide &R, const JoinS
     const uint32_t wpu = waves_per_unit(table_rows);
     const uint32_t np = seg_bits ? (n_inst << 8) : (1u << bits);
     uint32_t *ucnt = ctx.scratch_n<uint32_t>(np + 1);
-    uint32_t *flags = ctx.scratch_n<uint32_t>(3);
-    fill_u32(s, flags, 0u, 3);
+    uint32_t *flags = ctx.scratch_n<uint32_t>(6);  // [0..3] flags, [4..5] 64-bit unit total
+    fill_u32(s, flags, 0u, 6);
     GJ_LAUNCH("k_unit_count", 20.0 * np, k_unit_count, dim3(std::min<uint32_t>((np + 255) / 256, 1024)),
               dim3(256), 0, s, R.poff, S.poff, np, (uint32_t)r_block, join_s_piece(r_block), ucnt, flags);
     scan_exclusive_u32(ctx, ucnt, ucnt, np, ucnt + np);
@@ -915,7 +938,17 @@ int64_t join_partitioned(Ctx &ctx, int key_bytes, const JoinSide &R, const JoinS
         cap_units = pl->cap_units;
         grid = std::max<uint32_t>(1, std::min<uint32_t>(cap_units, kPersistentGrid));
     } else {
-        cap_units = read_back(ucnt + np, s);
+        uint32_t hf[6];
+        GJ_HIP(hipMemcpyAsync(&cap_units, ucnt + np, 4, hipMemcpyDeviceToHost, s));
+        GJ_HIP(hipMemcpyAsync(hf, flags, sizeof(hf), hipMemcpyDeviceToHost, s));
+        GJ_HIP(hipStreamSynchronize(s));
+        if (hf[3]) throw Error(GJ_EOVERFLOW, "more than 2^31-1 join work units (R partitions far larger than the "
+                                             "build block)");
+        if (stats) {
+            stats->max_r_rows = hf[2];
+            stats->multi_block = hf[0] != 0;
+            if (stats->check_spread && hf[2] > stats->spread_limit) return -1;
+        }
         grid = cap_units;
         if (cap_units == 0) {
             if (inst_off) fill_u64(s, inst_off, 0ull, (uint64_t)n_inst + 1);
@@ -931,7 +964,7 @@ int64_t join_partitioned(Ctx &ctx, int key_bytes, const JoinSide &R, const JoinS
     a.np = np;
     a.ubase = ucnt;
     a.rc = (uint32_t)r_block;
-    a.skip_bits = bits;
+    a.skip_bits = (stats && stats->hashed_digits) ? 0 : bits;
     a.seg_bits = seg_bits;
     a.seg_bshift = pl ? pl->seg_bshift : nullptr;
     a.bshift = 0;
@@ -967,10 +1000,10 @@ int64_t join_partitioned(Ctx &ctx, int key_bytes, const JoinSide &R, const JoinS
     if (inst_off)
         GJ_LAUNCH("k_instance_offsets", 16.0 * n_inst, k_instance_offsets,
                   dim3(std::min<uint32_t>(ceil_div_u32(n_inst + 1, 256), 1024)), dim3(256), 0, s, ucnt, wcnt, wpu,
-                  n_inst, ucnt + np, cap_units, total, a.out_base, inst_off);
+                  n_inst, ucnt + np, (const uint32_t *)flags, cap_units, total, a.out_base, inst_off);
     if (pl && (pl->next_base || pl->units_out))
         GJ_LAUNCH("k_advance_base", 16.0, k_advance_base, dim3(1), dim3(64), 0, s, a.out_base, total, pl->next_base,
-                  (const uint32_t *)(ucnt + np), pl->units_out);
+                  (const uint32_t *)(ucnt + np), (const uint32_t *)flags, pl->units_out);
     if (T == 0) return 0;
 
     if (!pl) {

@@ -277,6 +277,7 @@ void build_join_plan(gj_plan *P, const gj_rel_batch *R, const gj_rel_batch *S, c
     require(o.mat >= 0 && o.mat <= 2, "bad materialization");
     gj::check_join_lds_budget(o.lds_budget, dtype_bytes(R->key.dtype));
     require(o.flags == 0, "flags must be 0");
+    require(o.algo == GJ_JOIN_AUTO || o.algo == GJ_JOIN_PHJ, "plans run the partitioned hash join only", GJ_EUNSUPPORTED);
     require(out_capacity >= 0, "negative output capacity");
     const int n = R->n_instances;
     P->n = n;

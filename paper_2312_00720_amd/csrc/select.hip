@@ -226,6 +226,14 @@ int gj_selector_set_weights(const float *params, int32_t n) {
     return GJ_OK;
 }
 
+int gj_get_cost_constants(double *seq_bytes_per_s, double *rand_ratio, double *atomic_rate) {
+    if (!seq_bytes_per_s || !rand_ratio || !atomic_rate) return GJ_EINVAL;
+    *seq_bytes_per_s = gj::g_c.seq;
+    *rand_ratio = gj::g_c.rand_ratio;
+    *atomic_rate = gj::g_c.atomic_rate;
+    return GJ_OK;
+}
+
 int gj_set_cost_constants(double seq_bytes_per_s, double rand_ratio, double atomic_rate) {
     if (!(seq_bytes_per_s > 0) || !(rand_ratio >= 1) || !(atomic_rate > 0)) return GJ_EINVAL;
     gj::g_c.seq = seq_bytes_per_s;

@@ -45,7 +45,8 @@ def check(keys, vals, aggs=AGGS, sorted_out=False, **kw):
     return gk, gcols
 
 
-ALGOS = [("partition", "gftr"), ("partition", "gfur"), ("hash", "auto"), ("sort", "gftr"), ("sort", "gfur")]
+ALGOS = [("partition", "gftr"), ("partition", "gfur"), ("hash", "auto"), ("sort", "gftr"), ("sort", "gfur"),
+         ("sort_de", "gftr")]
 
 
 @pytest.mark.parametrize("algo,mat", ALGOS)
@@ -53,7 +54,27 @@ ALGOS = [("partition", "gftr"), ("partition", "gfur"), ("hash", "auto"), ("sort"
                                           (200003, 150000, 0.0), (300001, 4096, 1.0)])
 def test_groupby_matches_oracle(algo, mat, n, card, alpha):
     d = datagen.groupby_input(n, card, 2, seed=datagen.seed_for(2, card + n), alpha=alpha)
-    check(d["key"], d["vals"], algo=algo, mat=mat, sorted_out=(algo == "sort"))
+    check(d["key"], d["vals"], algo=algo, mat=mat, sorted_out=algo.startswith("sort"))
+
+
+@pytest.mark.parametrize("kb", [4, 8])
+@pytest.mark.parametrize("g_card,alpha", [(1, 0.0), (200, 0.0), (70000, 0.0), (5000, 1.1)])
+def test_sort_de_sparse_keys(kb, g_card, alpha):
+    """Dictionary-encoded sort group-by (Section 4.4) on sparse keys: g distinct
+    values spread over the whole key range (all 4 or 8 key bytes vary, so the
+    plain sort needs 4 or 8 passes, the codes ceil(log2 g / 8)); keys come out
+    in ascending signed order, including negative keys and both extremes."""
+    g = datagen.rng(900 + g_card + kb)
+    lo, hi = (-2**31, 2**31 - 1) if kb == 4 else (-2**63, 2**63 - 1)
+    dom = np.unique(g.integers(lo, hi, size=g_card, endpoint=True, dtype=np.int64))
+    if g_card > 1:
+        dom[0], dom[-1] = lo, hi
+    ranks = datagen.zipf_ranks(g, 250007, len(dom), alpha) - 1
+    keys = dom[g.permutation(len(dom))][ranks].astype(np.int32 if kb == 4 else np.int64)
+    vals = [g.integers(-2**31, 2**31, size=len(keys)).astype(np.int32) for _ in range(2)]
+    check(keys, vals, algo="sort_de", sorted_out=True)
+    check(keys, vals, AGGS[:4], algo="sort_de", sorted_out=True)
+    check(keys, [], [(0, "count")], algo="sort_de", sorted_out=True)
 
 
 @pytest.mark.parametrize("kb,nv", [(4, 1), (4, 2), (8, 2)])
@@ -138,12 +159,12 @@ def test_hash_partial_lds_records(alpha):
 
 
 def test_hash_ids_follow_the_first_rows():
-    """When not every group fits in LDS, the lowest group ids keep LDS records.
-    They go to the keys of the first rows (inserted by one workgroup before the
-    full grid), which under skew are the frequent keys. HGB emits groups in id
-    order, so those keys come first in its output. Here 7 aggregates take 40-byte
-    records, so the default 64 KB budget holds 1638 of the 19167 groups, and the
-    first 2048 rows hold 1014 distinct keys."""
+    """Group ids go to the keys of the first rows (inserted by one workgroup
+    before the full grid), which under skew are the frequent keys; when not every
+    group fits in LDS, those lowest ids keep LDS records. HGB emits groups in id
+    order, so those keys come first in its output. Here the first 2048 rows hold
+    1014 distinct keys, and 1638 is what a 64 KB budget holds of 40-byte records
+    (7 aggregates)."""
     d = datagen.groupby_input(400000, 20000, 2, seed=5, alpha=1.0)
     gk, _ = check(d["key"], d["vals"], algo="hash")
     first = np.unique(d["key"][:2048])
@@ -160,6 +181,18 @@ def test_hash_table_sizing(occ):
     check(d["key"], d["vals"], algo="hash", ht_occupancy=occ)
     d = datagen.groupby_input(100000, 7, 2, seed=68, key_bytes=8)
     check(d["key"], d["vals"], algo="hash", ht_occupancy=occ)
+
+
+@pytest.mark.parametrize("g_card,budget,alpha", [(3000, 8192, 0.0), (2000, 16384, 1.0), (20000, 0, 0.0),
+                                                  (65000, 0, 1.0), (5, 0, 0.0)])
+def test_hash_sliced_lds_records(g_card, budget, alpha):
+    """Every group in LDS, the ids cut into up to 16 consecutive ranges that each
+    fit one workgroup's LDS (budget 0: 160 KB); each (row chunk, id range)
+    workgroup aggregates its chunk's rows of that range."""
+    d = datagen.groupby_input(300001, g_card, 2, seed=69 + g_card, alpha=alpha)
+    check(d["key"], d["vals"], algo="hash", lds_budget=budget)
+    d = datagen.groupby_input(100003, g_card, 2, seed=70 + g_card, alpha=alpha, key_bytes=8)
+    check(d["key"], d["vals"], algo="hash", lds_budget=budget)
 
 
 def test_hash_global_aggregation_path():

@@ -114,6 +114,7 @@ def test_edge_cases():
         d = {"r_key": rk, "r_pay": pay(len(rk)), "s_key": sk, "s_pay": pay(len(sk))}
         for mat in ("gftr", "gfur"):
             check(d, mat)
+            check(d, mat, algo="smj")
 
 
 def test_no_payload_columns():
@@ -153,3 +154,74 @@ def test_bad_arguments_raise():
             gj.join(r, [], r, [], **kw)
     with pytest.raises(gj.GJError):
         gj.join(r8, [], s, [], lds_budget=16384)
+
+
+@pytest.mark.parametrize("mat", ["gftr", "gfur"])
+@pytest.mark.parametrize("kb", [4, 8])
+def test_keys_with_constant_low_bits(mat, kb):
+    """R keys that are all multiples of 2^16 (2^32 for 8-byte keys) fall into one
+    key-bit partition; the join notices the pile-up and partitions on hashed
+    keys instead. The result is the plain join either way."""
+    g = datagen.rng(4040)
+    n_r, n_s = 30000, 90000
+    shift = 16 if kb == 4 else 32
+    dt = np.int32 if kb == 4 else np.int64
+    rk = (g.permutation(n_r).astype(np.int64) << shift).astype(dt)
+    sk = rk[g.integers(0, n_r, size=n_s)]
+    sk[:1000] = (np.arange(1000, dtype=np.int64) * 7 + 1).astype(dt)  # unmatched (odd) keys
+    d = {"r_key": rk, "s_key": sk, "r_pay": datagen.payload_columns(g, n_r, 2),
+         "s_pay": datagen.payload_columns(g, n_s, 1)}
+    got = check(d, mat)
+    assert len(got[0]) == n_s - 1000
+
+
+def test_work_unit_overflow_is_an_error():
+    """One partition of 2^24 R rows probed by 2^26 S rows with 64-row build
+    blocks needs 2^31 work units, one more than the 32-bit unit index allows:
+    GJ_EOVERFLOW before any pass runs, nothing left allocated."""
+    import torch
+    import paper_2312_00720_amd as gj
+    from gpu_util import say
+    say("join unit overflow: 2^24 x 2^26 even keys, radix_bits=1, lds_budget=64")
+    rk = torch.arange(0, 1 << 25, 2, dtype=torch.int32, device="cuda")
+    sk = torch.zeros(1 << 26, dtype=torch.int32, device="cuda")
+    before = torch.cuda.memory_allocated()
+    with pytest.raises(gj.GJError) as e:
+        gj.join(rk, [], sk, [], mat="gftr", radix_bits=1, lds_budget=64)
+    assert e.value.code == -6 and "work units" in str(e.value)
+    torch.cuda.synchronize()
+    assert torch.cuda.memory_allocated() == before
+
+
+@pytest.mark.parametrize("mat", ["gftr", "gfur"])
+@pytest.mark.parametrize("kb", [4, 8])
+@pytest.mark.parametrize("case", ["pkfk", "zipf_half", "m2n", "tiny"])
+def test_sort_merge_join(mat, kb, case):
+    """Sort-merge join (Section 3.1.1): radix sort of both relations, Merge Path
+    lower bounds, galloping upper bounds, count / scan / write. Same multiset
+    as the oracle, and keys in ascending order."""
+    if case == "pkfk":
+        d = datagen.pk_fk_join(50000, 170001, 2, 3, seed=datagen.seed_for(1, 40), key_bytes=kb)
+    elif case == "zipf_half":
+        d = datagen.pk_fk_join(30000, 90001, 1, 1, seed=datagen.seed_for(1, 41), alpha=1.1, match_ratio=0.5,
+                               key_bytes=kb)
+    elif case == "m2n":
+        d = datagen.many_to_many_join(20000, 30000, 700, 2, 1, seed=42, key_bytes=kb)
+    else:
+        d = datagen.pk_fk_join(3, 5, 1, 1, seed=43, key_bytes=kb)
+    got = check(d, mat, algo="smj")
+    assert np.all(got[0][1:] >= got[0][:-1]), "sort-merge join output is in key order"
+
+
+def test_sort_merge_join_long_runs_and_extreme_keys():
+    """Runs of equal keys longer than a merge tile on both sides (the galloping
+    search and tiles cut inside a run), keys at both ends of the signed range."""
+    g = datagen.rng(44)
+    lo, hi = np.iinfo(np.int32).min, np.iinfo(np.int32).max
+    rk = np.concatenate([np.full(9000, 5), np.full(3, lo), np.full(2, hi), g.integers(-1000, 1000, size=5000)])
+    sk = np.concatenate([np.full(70, 5), np.full(4, lo), np.full(5, hi), g.integers(-1200, 1200, size=20000)])
+    rk, sk = g.permutation(rk).astype(np.int32), g.permutation(sk).astype(np.int32)
+    d = {"r_key": rk, "s_key": sk, "r_pay": datagen.payload_columns(g, len(rk), 1),
+         "s_pay": datagen.payload_columns(g, len(sk), 1)}
+    for mat in ("gftr", "gfur"):
+        check(d, mat, algo="smj")

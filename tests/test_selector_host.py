@@ -95,3 +95,35 @@ def test_non_finite_weights_fall_back_to_cost_model(gj):
     c, p = gj.select(f, 1)
     assert c == int(np.argmin(gj.cost_model(f, 1)))
     gj.selector_set_weights(None)
+
+
+def test_cost_model_with_a100_constants_follows_the_papers_join_model(gj):
+    """With the paper's GPU constants (B_G = 1555 GB/s, B_G/B_R = 24), the
+    library's join model and the paper's model of Section 4.1.4 (oracle) agree
+    on the sign of Time(GFUR) - Time(GFTR) at |R| = |S| = 2^27 with 2 payload
+    columns per side, both fall with the match ratio, and the library's
+    crossover lies between 1/16 and 1/4. It sits below the paper's (72/368):
+    one multi-column scatter moves every GFTR payload with a single key read, so
+    GFTR's extra columns cost less here than one key-and-column partition each."""
+    from oracle import costmodel
+    saved = gj.get_cost_constants()
+    try:
+        gj.set_cost_constants(1555e9, 24.0, saved[2])
+        mrs = [1.0, 0.5, 0.25, 0.0625]
+        lib = []
+        for mr in mrs:
+            f = join_features(27, 27, mr)
+            t = gj.cost_model(f, 0)
+            lib.append(t[1] - t[0])
+        paper = [costmodel.phj_ur_minus_tr(2**27, 2**27, mr * 2**27) for mr in mrs]
+        assert [x > 0 for x in lib] == [x > 0 for x in paper] == [True, True, True, False]
+        assert all(b < a for a, b in zip(lib, lib[1:]))
+        assert lib[0] == pytest.approx(paper[0], rel=0.25)  # 29.7 vs 25.6 ms at mr = 1
+        lo, hi = 1 / 16, 1 / 4
+        for _ in range(40):
+            mid = (lo + hi) / 2
+            t = gj.cost_model(join_features(27, 27, mid), 0)
+            lo, hi = (lo, mid) if t[1] - t[0] > 0 else (mid, hi)
+        assert 1 / 16 < lo < 1 / 4
+    finally:
+        gj.set_cost_constants(*saved)
