@@ -284,8 +284,10 @@ typedef struct {
 /*
  * Grouped aggregation with one group key and reducible aggregates
  * (Section 2.2): for each distinct key, COUNT(*) and SUM/MIN/MAX of value
- * columns. Keys are GJ_I32 or GJ_I64; value columns GJ_I32. SUM is exact in
- * int64. Group order: ascending key for the sort algorithms (with or without
+ * columns. Keys are GJ_I32 or GJ_I64; value columns GJ_I32 or GJ_I64 (Section
+ * 5.2 evaluates 8-byte payloads), mixed freely. SUM is int64: exact for int32
+ * values (at most 2^31 rows), modulo 2^64 for int64 values; MIN and MAX keep
+ * the value column's dtype. Group order: ascending key for the sort algorithms (with or without
  * dictionary encoding); unspecified (but deterministic) for partition;
  * unspecified for hash.
  * Synchronizes with `stream` to read the group count.

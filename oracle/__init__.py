@@ -48,6 +48,8 @@ def lib():
                                               vp, i64, vp, vp, i32, vp]
         L.oracle_groupby.restype = i64
         L.oracle_groupby.argtypes = [ctypes.c_int, vp, i64, vp, i32, vp, vp, vp, vp, vp]
+        L.oracle_groupby64.restype = i64
+        L.oracle_groupby64.argtypes = [ctypes.c_int, vp, i64, vp, i32, vp, vp, vp, vp, vp]
         L.oracle_partition.restype = ctypes.c_int
         L.oracle_partition.argtypes = [ctypes.c_int, vp, i64, ctypes.c_int, ctypes.c_int,
                                        ctypes.c_int, vp, vp]
@@ -133,8 +135,12 @@ def join_fingerprint(r_key, r_pay, s_key, s_pay) -> tuple[int, int, int]:
 
 
 def groupby(keys: np.ndarray, vals) -> dict:
-    """Per distinct key (ascending): count, and per value column sum/min/max."""
+    """Per distinct key (ascending): count, and per value column sum/min/max.
+    Any int64 value column makes every column int64 (oracle_groupby64: min and
+    max come back as int64, sums modulo 2^64)."""
     keys = np.ascontiguousarray(keys)
+    if any(np.asarray(v).dtype == np.int64 for v in vals):
+        return _groupby64(keys, [np.ascontiguousarray(v, dtype=np.int64) for v in vals])
     vals = [np.ascontiguousarray(v, dtype=np.int32) for v in vals]
     n = len(keys)
     nv = len(vals)
@@ -152,6 +158,28 @@ def groupby(keys: np.ndarray, vals) -> dict:
     kd = keys.dtype
     return {
         "key": ok[:g].astype(kd),
+        "count": oc[:g].copy(),
+        "sum": [osum[v * cap: v * cap + g].copy() for v in range(nv)],
+        "min": [omin[v * cap: v * cap + g].copy() for v in range(nv)],
+        "max": [omax[v * cap: v * cap + g].copy() for v in range(nv)],
+    }
+
+
+def _groupby64(keys: np.ndarray, vals) -> dict:
+    n, nv = len(keys), len(vals)
+    cap = max(n, 1)
+    ok = np.empty(cap, np.int64)
+    oc = np.empty(cap, np.int64)
+    osum = np.empty(max(nv, 1) * cap, np.int64)
+    omin = np.empty(max(nv, 1) * cap, np.int64)
+    omax = np.empty(max(nv, 1) * cap, np.int64)
+    vp = (ctypes.c_void_p * max(1, nv))(*[v.ctypes.data for v in vals])
+    g = lib().oracle_groupby64(_key_bytes(keys), _ptr(keys), n, ctypes.cast(vp, ctypes.c_void_p), nv,
+                               _ptr(ok), _ptr(oc), _ptr(osum), _ptr(omin), _ptr(omax))
+    if g < 0:
+        raise MemoryError("oracle_groupby64")
+    return {
+        "key": ok[:g].astype(keys.dtype),
         "count": oc[:g].copy(),
         "sum": [osum[v * cap: v * cap + g].copy() for v in range(nv)],
         "min": [omin[v * cap: v * cap + g].copy() for v in range(nv)],

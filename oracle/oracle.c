@@ -17,6 +17,8 @@
  *                            PK-FK inputs, the sum over keys of |R_k|*|S_k|
  *   oracle_groupby           pinned: brute force per distinct key, bincount
  *                            closed form, sum invariants
+ *   oracle_groupby64         pinned: brute force per distinct key over int64
+ *                            values, np.add.at / minimum.at closed forms
  *   oracle_partition         pinned: Python's stable sort on tiny inputs,
  *                            permutation and order invariants
  *   oracle_hgb_ids           pinned: dictionary brute force, bijection invariant
@@ -193,6 +195,45 @@ int64_t oracle_groupby(int key_bytes, const void *keys, int64_t n,
                 if (x > mx) mx = x;
             }
             out_sum[(int64_t)v * n + g] = s;
+            out_min[(int64_t)v * n + g] = mn;
+            out_max[(int64_t)v * n + g] = mx;
+        }
+        ++g;
+        p = q;
+    }
+    free(a);
+    return g;
+}
+
+/*
+ * The same group-by over 8-byte value columns (Section 5.2 evaluates 8-byte
+ * payloads): per distinct key, COUNT, SUM, MIN and MAX of int64 values. SUM is
+ * taken modulo 2^64 (two's complement), which is exact whenever the true sum
+ * fits in int64. Same output layout as oracle_groupby, with int64 minima and
+ * maxima.
+ */
+int64_t oracle_groupby64(int key_bytes, const void *keys, int64_t n,
+                         const int64_t *const *vals, int32_t n_vals,
+                         int64_t *out_key, int64_t *out_count,
+                         int64_t *out_sum, int64_t *out_min, int64_t *out_max) {
+    kv_t *a = sorted_index(keys, key_bytes, n);
+    if (!a) return -1;
+    int64_t g = 0;
+    for (int64_t p = 0; p < n;) {
+        int64_t q = p;
+        while (q < n && a[q].key == a[p].key) ++q;
+        out_key[g] = a[p].key;
+        out_count[g] = q - p;
+        for (int32_t v = 0; v < n_vals; ++v) {
+            uint64_t s = 0;
+            int64_t mn = INT64_MAX, mx = INT64_MIN;
+            for (int64_t r = p; r < q; ++r) {
+                int64_t x = vals[v][a[r].idx];
+                s += (uint64_t)x;
+                if (x < mn) mn = x;
+                if (x > mx) mx = x;
+            }
+            out_sum[(int64_t)v * n + g] = (int64_t)s;
             out_min[(int64_t)v * n + g] = mn;
             out_max[(int64_t)v * n + g] = mx;
         }

@@ -381,10 +381,7 @@ int gj_groupby(gj_col key, const gj_col *vals, int32_t n_vals, int64_t n_rows, c
         check_col(key, n_rows, "key");
         gj::require(n_vals >= 0 && n_vals <= 8, "0..8 value columns");
         gj::require(n_vals == 0 || vals != nullptr, "null value array");
-        for (int i = 0; i < n_vals; ++i) {
-            check_col(vals[i], n_rows, "value");
-            gj::require(vals[i].dtype == GJ_I32, "value columns must be GJ_I32");
-        }
+        for (int i = 0; i < n_vals; ++i) check_col(vals[i], n_rows, "value");
         gj::require(n_aggs >= 1 && n_aggs <= 16, "1..16 aggregates");
         gj::require(aggs != nullptr && out->aggs != nullptr, "null aggregate arrays");
         for (int j = 0; j < n_aggs; ++j) {
@@ -410,8 +407,12 @@ int gj_groupby(gj_col key, const gj_col *vals, int32_t n_vals, int64_t n_rows, c
         const uint32_t n = (uint32_t)n_rows;
         const bool gfur = (o.mat == GJ_MAT_GFUR);
         int algo = o.algo;
-        const int32_t *vcols[8];
-        for (int i = 0; i < n_vals; ++i) vcols[i] = static_cast<const int32_t *>(vals[i].data);
+        gj::ValCols vcols;
+        vcols.n = n_vals;
+        for (int i = 0; i < n_vals; ++i) {
+            vcols.col[i] = vals[i].data;
+            vcols.width[i] = dtype_bytes(vals[i].dtype);
+        }
 
         gj::Ctx ctx(alloc, (hipStream_t)stream);
         // the group count decides the algorithm and the partition passes: estimate it
@@ -452,17 +453,17 @@ int gj_groupby(gj_col key, const gj_col *vals, int32_t n_vals, int64_t n_rows, c
                 }
             }
             int fell_back = 0;
-            g = gj::groupby_partition(ctx, kb, key.data, vcols, n_vals, n, aggs, n_aggs, gfur, bits, &okey, oaggs,
+            g = gj::groupby_partition(ctx, kb, key.data, vcols, n, aggs, n_aggs, gfur, bits, &okey, oaggs,
                                       &fell_back);
             if (fell_back) algo = GJ_GB_HASH;  // too many distinct keys per partition
         }
         if (algo == GJ_GB_HASH)
-            g = gj::groupby_hash(ctx, kb, key.data, vcols, n_vals, n, aggs, n_aggs, o.lds_budget, g_est,
+            g = gj::groupby_hash(ctx, kb, key.data, vcols, n, aggs, n_aggs, o.lds_budget, g_est,
                                  o.ht_occupancy, &okey, oaggs);
         else if (algo == GJ_GB_SORT)
-            g = gj::groupby_sort(ctx, kb, key.data, vcols, n_vals, n, aggs, n_aggs, gfur, &okey, oaggs);
+            g = gj::groupby_sort(ctx, kb, key.data, vcols, n, aggs, n_aggs, gfur, &okey, oaggs);
         else if (algo == GJ_GB_SORT_DE)
-            g = gj::groupby_sort_de(ctx, kb, key.data, vcols, n_vals, n, aggs, n_aggs, g_est, o.ht_occupancy, &okey,
+            g = gj::groupby_sort_de(ctx, kb, key.data, vcols, n, aggs, n_aggs, g_est, o.ht_occupancy, &okey,
                                     oaggs);
         out->n_groups = g;
         out->key = okey;

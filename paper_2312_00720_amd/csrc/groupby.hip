@@ -1,10 +1,14 @@
 // Grouped aggregation: partition-based (Section 4.3), hash-based (Section 4.2,
-// Algorithm 1) and sort-based (Sections 3.2.2 and 4.1.3).
+// Algorithm 1) and sort-based (Sections 3.2.2 and 4.1.3), the last also on
+// dictionary-encoded keys (Section 4.4).
 //
-// Aggregates: COUNT, and SUM / MIN / MAX of int32 value columns. While a group
-// is being aggregated in LDS, its record holds the 64-bit sums first, then
-// 32-bit counts, minima and maxima (one 4-byte word each), padded to an even
-// number of words. Outputs: SUM and COUNT as int64, MIN and MAX as int32.
+// Aggregates: COUNT, and SUM / MIN / MAX of int32 or int64 value columns. While
+// a group is being aggregated in LDS, its record holds the 64-bit fields first
+// (sums, and minima and maxima of 8-byte columns), then 32-bit counts, minima
+// and maxima, padded to an even number of words. Outputs: SUM and COUNT as
+// int64 (a sum of 8-byte values is taken modulo 2^64), MIN and MAX in the value
+// column's type. Kernels hold a row's values as int when every column is 4
+// bytes, else as long long.
 #include <math.h>
 #include <stdio.h>
 #include <stdlib.h>
@@ -46,15 +50,22 @@ struct AggSpec {
     int op[kMaxAggs];   // GJ_SUM / GJ_COUNT / GJ_MIN / GJ_MAX
     int col[kMaxAggs];  // value column
     int word[kMaxAggs]; // word offset in the LDS record
+    int w8[kMaxAggs];   // MIN / MAX of an 8-byte column: a 64-bit field and output
     int words;          // record size in 4-byte words (even)
     void *out[kMaxAggs];
 };
 
 struct ValSrc {
     int n;
-    const int32_t *col[kMaxVals];  // GFTR: partitioned/sorted columns; GFUR: original columns
+    const void *col[kMaxVals];     // GFTR: partitioned/sorted columns; GFUR: original columns
+    int w8[kMaxVals];              // 1 for an 8-byte column
     const int32_t *rowid;          // GFUR: row ids aligned with the keys; else nullptr
 };
+
+// MIN and MAX fields start at the identity of their width; a 4-byte field
+// narrows a 64-bit running value, whose identity lies beyond int32.
+__device__ __forceinline__ int narrow_min(long long x) { return (int)(x < INT32_MAX ? x : INT32_MAX); }
+__device__ __forceinline__ int narrow_max(long long x) { return (int)(x > INT32_MIN ? x : INT32_MIN); }
 
 __device__ __forceinline__ void rec_init(uint32_t *rec, const AggSpec &s) {
     for (int j = 0; j < s.n; ++j) {
@@ -62,8 +73,14 @@ __device__ __forceinline__ void rec_init(uint32_t *rec, const AggSpec &s) {
         switch (s.op[j]) {
             case GJ_SUM: p[0] = 0; p[1] = 0; break;
             case GJ_COUNT: p[0] = 0; break;
-            case GJ_MIN: p[0] = (uint32_t)INT32_MAX; break;
-            default: p[0] = (uint32_t)INT32_MIN; break;
+            case GJ_MIN:
+                if (s.w8[j]) *reinterpret_cast<long long *>(p) = INT64_MAX;
+                else p[0] = (uint32_t)INT32_MAX;
+                break;
+            default:
+                if (s.w8[j]) *reinterpret_cast<long long *>(p) = INT64_MIN;
+                else p[0] = (uint32_t)INT32_MIN;
+                break;
         }
     }
 }
@@ -87,55 +104,85 @@ __device__ __forceinline__ void rec_flush(const uint32_t *rec, const AggSpec &s,
                 break;
             }
             case GJ_MIN: {
-                int *q = static_cast<int *>(s.out[j]) + o;
-                if (atomic) atomicMin(q, (int)p[0]);
-                else *q = (int)p[0];
+                if (s.w8[j]) {
+                    const long long x = *reinterpret_cast<const long long *>(p);
+                    long long *q = static_cast<long long *>(s.out[j]) + o;
+                    if (atomic) atomicMin(q, x);
+                    else *q = x;
+                } else {
+                    int *q = static_cast<int *>(s.out[j]) + o;
+                    if (atomic) atomicMin(q, (int)p[0]);
+                    else *q = (int)p[0];
+                }
                 break;
             }
             default: {
-                int *q = static_cast<int *>(s.out[j]) + o;
-                if (atomic) atomicMax(q, (int)p[0]);
-                else *q = (int)p[0];
+                if (s.w8[j]) {
+                    const long long x = *reinterpret_cast<const long long *>(p);
+                    long long *q = static_cast<long long *>(s.out[j]) + o;
+                    if (atomic) atomicMax(q, x);
+                    else *q = x;
+                } else {
+                    int *q = static_cast<int *>(s.out[j]) + o;
+                    if (atomic) atomicMax(q, (int)p[0]);
+                    else *q = (int)p[0];
+                }
                 break;
             }
         }
     }
 }
 
-// Values of one row for value columns 0..NV-1 (NV >= the number of columns in use).
-template <int NV>
+// Values of one row for value columns 0..NV-1 (NV >= the number of columns in
+// use), held as V: int when every column is 4 bytes, long long otherwise.
+template <int NV, typename V = int>
 struct Row {
-    int v[NV];
+    V v[NV];
 };
 
-template <int NV>
-__device__ __forceinline__ Row<NV> load_row(const ValSrc &vs, uint32_t row) {
-    Row<NV> r;
+template <int NV, typename V = int>
+__device__ __forceinline__ Row<NV, V> load_row(const ValSrc &vs, uint32_t row) {
+    Row<NV, V> r;
     const uint32_t src = vs.rowid ? (uint32_t)vs.rowid[row] : row;
 #pragma unroll
-    for (int c = 0; c < NV; ++c) r.v[c] = c < vs.n ? vs.col[c][src] : 0;
+    for (int c = 0; c < NV; ++c) {
+        if constexpr (sizeof(V) == 4) {
+            r.v[c] = c < vs.n ? static_cast<const int32_t *>(vs.col[c])[src] : 0;
+        } else {
+            r.v[c] = c < vs.n ? (vs.w8[c] ? static_cast<const long long *>(vs.col[c])[src]
+                                          : (long long)static_cast<const int32_t *>(vs.col[c])[src])
+                              : 0ll;
+        }
+    }
     return r;
 }
 
-template <int NV>
-__device__ __forceinline__ int pick(const Row<NV> &r, int c) {
-    int x = r.v[0];
+template <int NV, typename V>
+__device__ __forceinline__ V pick(const Row<NV, V> &r, int c) {
+    V x = r.v[0];
 #pragma unroll
     for (int cc = 1; cc < NV; ++cc)
         if (cc == c) x = r.v[cc];
     return x;
 }
 
-template <int NV>
-__device__ __forceinline__ void row_add_global_r(const AggSpec &s, const Row<NV> &r, uint64_t o) {
+template <int NV, typename V>
+__device__ __forceinline__ void row_add_global_r(const AggSpec &s, const Row<NV, V> &r, uint64_t o) {
     for (int j = 0; j < s.n; ++j) {
+        const V x = pick(r, s.col[j]);
         switch (s.op[j]) {
             case GJ_SUM:
-                atomicAdd(static_cast<unsigned long long *>(s.out[j]) + o, (unsigned long long)(long long)pick(r, s.col[j]));
+                atomicAdd(static_cast<unsigned long long *>(s.out[j]) + o, (unsigned long long)(long long)x);
                 break;
             case GJ_COUNT: atomicAdd(static_cast<unsigned long long *>(s.out[j]) + o, 1ull); break;
-            case GJ_MIN: atomicMin(static_cast<int *>(s.out[j]) + o, pick(r, s.col[j])); break;
-            default: atomicMax(static_cast<int *>(s.out[j]) + o, pick(r, s.col[j])); break;
+            case GJ_MIN:
+                if (sizeof(V) == 8 && s.w8[j]) atomicMin(static_cast<long long *>(s.out[j]) + o, (long long)x);
+                else atomicMin(static_cast<int *>(s.out[j]) + o, (int)x);
+                break;
+            default:
+                if (sizeof(V) == 8 && s.w8[j]) atomicMax(static_cast<long long *>(s.out[j]) + o, (long long)x);
+                else atomicMax(static_cast<int *>(s.out[j]) + o, (int)x);
+                break;
         }
     }
 }
@@ -147,15 +194,51 @@ __device__ __forceinline__ void row_add_global_r(const AggSpec &s, const Row<NV>
 constexpr uint32_t kSpareWords = 2 * kWave;
 __device__ __forceinline__ uint32_t spare_off(uint32_t rec_end) { return rec_end + 2u * lane_id(); }
 
+// LDS atomic MIN / MAX on a record field of T (int, or long long for an 8-byte
+// column); with `skewed`, a row that cannot change the field (checked against a
+// possibly stale read) skips the atomic.
+template <typename T, int RB, bool IS_MIN>
+__device__ __forceinline__ void rec_minmax(uint32_t *recs, const uint32_t (&off)[RB], int w, const T (&x)[RB],
+                                           int nact, bool skewed) {
+    if (!skewed) {
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+            if (r < nact) {
+                T *p = reinterpret_cast<T *>(recs + off[r] + w);
+                if (IS_MIN) atomicMin(p, x[r]);
+                else atomicMax(p, x[r]);
+            }
+        }
+        return;
+    }
+    // skewed keys: a minimum only falls (a maximum only rises), so a row no lower
+    // (higher) than what the record holds, even a stale read of it, cannot change
+    // it; the frequent groups' extremes settle early and most rows skip the
+    // atomic that many lanes of a wave would contend for. Uniform keys skip the
+    // read: it would wait behind the atomics issued before it.
+    T cur[RB];
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+        if (r < nact) cur[r] = __atomic_load_n(reinterpret_cast<T *>(recs + off[r] + w), __ATOMIC_RELAXED);
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+        if (r < nact && (IS_MIN ? x[r] < cur[r] : x[r] > cur[r])) {
+            T *p = reinterpret_cast<T *>(recs + off[r] + w);
+            if (IS_MIN) atomicMin(p, x[r]);
+            else atomicMax(p, x[r]);
+        }
+    }
+}
+
 // Accumulate rows 0..nact-1 of RB (values in registers) into LDS records: row r
 // goes to the record at word off[r]. nact is uniform over the wave (rows past it
 // are empty for every lane), and lanes with nothing to add in an active row point
 // at a spare, so the atomics need no divergent branch. The loop runs over the
 // aggregates outside the rows: each aggregate's atomics issue back to back, and
 // the aggregate list is read once per batch of rows rather than once per row.
-template <int NV, int RB>
+template <int NV, int RB, typename V>
 __device__ __forceinline__ void rec_add_rows(uint32_t *recs, const AggSpec &s, const uint32_t (&off)[RB],
-                                             const Row<NV> (&rr)[RB], int nact, bool skewed) {
+                                             const Row<NV, V> (&rr)[RB], int nact, bool skewed) {
     for (int j = 0; j < s.n; ++j) {
         const int c = s.col[j], w = s.word[j];
         switch (s.op[j]) {
@@ -171,43 +254,24 @@ __device__ __forceinline__ void rec_add_rows(uint32_t *recs, const AggSpec &s, c
                 for (int r = 0; r < RB; ++r)
                     if (r < nact) atomicAdd(recs + off[r] + w, 1u);
                 break;
-            case GJ_MIN: {
-                if (!skewed) {
-#pragma unroll
-                    for (int r = 0; r < RB; ++r)
-                        if (r < nact) atomicMin(reinterpret_cast<int *>(recs + off[r] + w), pick(rr[r], c));
-                    break;
-                }
-                // skewed keys: a minimum only falls, so a row no lower than what the
-                // record holds (even a stale read of it) cannot change it; the
-                // frequent groups' extremes settle early and most rows skip the
-                // atomic that many lanes of a wave would contend for. Uniform keys
-                // skip the read: it would wait behind the atomics issued before it.
-                int cur[RB];
-#pragma unroll
-                for (int r = 0; r < RB; ++r)
-                    if (r < nact) cur[r] = __atomic_load_n(reinterpret_cast<int *>(recs + off[r] + w), __ATOMIC_RELAXED);
-#pragma unroll
-                for (int r = 0; r < RB; ++r)
-                    if (r < nact && pick(rr[r], c) < cur[r])
-                        atomicMin(reinterpret_cast<int *>(recs + off[r] + w), pick(rr[r], c));
-                break;
-            }
+            case GJ_MIN:
             default: {
-                if (!skewed) {
+                const bool is_min = s.op[j] == GJ_MIN;
+                if constexpr (sizeof(V) == 8) {
+                    if (s.w8[j]) {
+                        long long x[RB];
 #pragma unroll
-                    for (int r = 0; r < RB; ++r)
-                        if (r < nact) atomicMax(reinterpret_cast<int *>(recs + off[r] + w), pick(rr[r], c));
-                    break;
+                        for (int r = 0; r < RB; ++r) x[r] = pick(rr[r], c);
+                        if (is_min) rec_minmax<long long, RB, true>(recs, off, w, x, nact, skewed);
+                        else rec_minmax<long long, RB, false>(recs, off, w, x, nact, skewed);
+                        break;
+                    }
                 }
-                int cur[RB];
+                int x[RB];
 #pragma unroll
-                for (int r = 0; r < RB; ++r)
-                    if (r < nact) cur[r] = __atomic_load_n(reinterpret_cast<int *>(recs + off[r] + w), __ATOMIC_RELAXED);
-#pragma unroll
-                for (int r = 0; r < RB; ++r)
-                    if (r < nact && pick(rr[r], c) > cur[r])
-                        atomicMax(reinterpret_cast<int *>(recs + off[r] + w), pick(rr[r], c));
+                for (int r = 0; r < RB; ++r) x[r] = (int)pick(rr[r], c);
+                if (is_min) rec_minmax<int, RB, true>(recs, off, w, x, nact, skewed);
+                else rec_minmax<int, RB, false>(recs, off, w, x, nact, skewed);
                 break;
             }
         }
@@ -224,47 +288,52 @@ __device__ __forceinline__ int wave_active_rows(uint32_t base, uint32_t stride, 
 }
 
 // Running aggregate of a set of rows: count, and per value column sum / min / max.
-template <int NV>
+template <int NV, typename V = int>
 struct Acc {
     uint32_t cnt;
     long long sum[NV];
-    int mn[NV], mx[NV];
+    V mn[NV], mx[NV];
 };
 
-template <int NV>
-__device__ __forceinline__ void acc_clear(Acc<NV> &x) {
+template <typename V>
+__device__ __forceinline__ V v_max() { return sizeof(V) == 4 ? (V)INT32_MAX : (V)INT64_MAX; }
+template <typename V>
+__device__ __forceinline__ V v_min() { return sizeof(V) == 4 ? (V)INT32_MIN : (V)INT64_MIN; }
+
+template <int NV, typename V>
+__device__ __forceinline__ void acc_clear(Acc<NV, V> &x) {
     x.cnt = 0;
 #pragma unroll
     for (int c = 0; c < NV; ++c) {
         x.sum[c] = 0;
-        x.mn[c] = INT32_MAX;
-        x.mx[c] = INT32_MIN;
+        x.mn[c] = v_max<V>();
+        x.mx[c] = v_min<V>();
     }
 }
-template <int NV>
-__device__ __forceinline__ void acc_merge(Acc<NV> &x, const Acc<NV> &y) {
+template <int NV, typename V>
+__device__ __forceinline__ void acc_merge(Acc<NV, V> &x, const Acc<NV, V> &y) {
     x.cnt += y.cnt;
 #pragma unroll
     for (int c = 0; c < NV; ++c) {
-        x.sum[c] += y.sum[c];
+        x.sum[c] = (long long)((unsigned long long)x.sum[c] + (unsigned long long)y.sum[c]);  // wraps mod 2^64
         x.mn[c] = min(x.mn[c], y.mn[c]);
         x.mx[c] = max(x.mx[c], y.mx[c]);
     }
 }
-template <int NV>
-__device__ __forceinline__ void acc_row(Acc<NV> &x, const Row<NV> &r) {
+template <int NV, typename V>
+__device__ __forceinline__ void acc_row(Acc<NV, V> &x, const Row<NV, V> &r) {
     x.cnt += 1;
 #pragma unroll
     for (int c = 0; c < NV; ++c) {
-        x.sum[c] += r.v[c];
+        x.sum[c] = (long long)((unsigned long long)x.sum[c] + (unsigned long long)(long long)r.v[c]);
         x.mn[c] = min(x.mn[c], r.v[c]);
         x.mx[c] = max(x.mx[c], r.v[c]);
     }
 }
 // Acc of the lane `src` (all lanes call).
-template <int NV>
-__device__ __forceinline__ Acc<NV> acc_shfl(const Acc<NV> &x, int src) {
-    Acc<NV> y;
+template <int NV, typename V>
+__device__ __forceinline__ Acc<NV, V> acc_shfl(const Acc<NV, V> &x, int src) {
+    Acc<NV, V> y;
     y.cnt = __shfl(x.cnt, src, kWave);
 #pragma unroll
     for (int c = 0; c < NV; ++c) {
@@ -274,11 +343,11 @@ __device__ __forceinline__ Acc<NV> acc_shfl(const Acc<NV> &x, int src) {
     }
     return y;
 }
-template <int NV>
-__device__ __forceinline__ Acc<NV> acc_wave_reduce(Acc<NV> x) {
+template <int NV, typename V>
+__device__ __forceinline__ Acc<NV, V> acc_wave_reduce(Acc<NV, V> x) {
 #pragma unroll
     for (int d = kWave / 2; d > 0; d >>= 1) {
-        Acc<NV> y;
+        Acc<NV, V> y;
         y.cnt = __shfl_xor(x.cnt, d, kWave);
 #pragma unroll
         for (int c = 0; c < NV; ++c) {
@@ -291,20 +360,27 @@ __device__ __forceinline__ Acc<NV> acc_wave_reduce(Acc<NV> x) {
     return x;
 }
 
-template <int NV>
-__device__ __forceinline__ void acc_flush(const Acc<NV> &x, const AggSpec &s, uint64_t o, bool atomic) {
-    for (int j = 0; j < s.n; ++j) {
-        const int c = s.col[j];
-        long long sum = x.sum[0];
-        int mn = x.mn[0], mx = x.mx[0];
+template <int NV, typename V>
+__device__ __forceinline__ void acc_pick(const Acc<NV, V> &x, int c, long long &sum, V &mn, V &mx) {
+    sum = x.sum[0];
+    mn = x.mn[0];
+    mx = x.mx[0];
 #pragma unroll
-        for (int cc = 1; cc < NV; ++cc) {
-            if (cc == c) {
-                sum = x.sum[cc];
-                mn = x.mn[cc];
-                mx = x.mx[cc];
-            }
+    for (int cc = 1; cc < NV; ++cc) {
+        if (cc == c) {
+            sum = x.sum[cc];
+            mn = x.mn[cc];
+            mx = x.mx[cc];
         }
+    }
+}
+
+template <int NV, typename V>
+__device__ __forceinline__ void acc_flush(const Acc<NV, V> &x, const AggSpec &s, uint64_t o, bool atomic) {
+    for (int j = 0; j < s.n; ++j) {
+        long long sum;
+        V mn, mx;
+        acc_pick(x, s.col[j], sum, mn, mx);
         switch (s.op[j]) {
             case GJ_SUM: {
                 unsigned long long *q = static_cast<unsigned long long *>(s.out[j]) + o;
@@ -319,15 +395,27 @@ __device__ __forceinline__ void acc_flush(const Acc<NV> &x, const AggSpec &s, ui
                 break;
             }
             case GJ_MIN: {
-                int *q = static_cast<int *>(s.out[j]) + o;
-                if (atomic) atomicMin(q, mn);
-                else *q = mn;
+                if (sizeof(V) == 8 && s.w8[j]) {
+                    long long *q = static_cast<long long *>(s.out[j]) + o;
+                    if (atomic) atomicMin(q, (long long)mn);
+                    else *q = (long long)mn;
+                } else {
+                    int *q = static_cast<int *>(s.out[j]) + o;
+                    if (atomic) atomicMin(q, narrow_min(mn));
+                    else *q = narrow_min(mn);
+                }
                 break;
             }
             default: {
-                int *q = static_cast<int *>(s.out[j]) + o;
-                if (atomic) atomicMax(q, mx);
-                else *q = mx;
+                if (sizeof(V) == 8 && s.w8[j]) {
+                    long long *q = static_cast<long long *>(s.out[j]) + o;
+                    if (atomic) atomicMax(q, (long long)mx);
+                    else *q = (long long)mx;
+                } else {
+                    int *q = static_cast<int *>(s.out[j]) + o;
+                    if (atomic) atomicMax(q, narrow_max(mx));
+                    else *q = narrow_max(mx);
+                }
                 break;
             }
         }
@@ -335,26 +423,24 @@ __device__ __forceinline__ void acc_flush(const Acc<NV> &x, const AggSpec &s, ui
 }
 
 // Fold an Acc into an LDS record (leader lane of a wave-aggregated update).
-template <int NV>
-__device__ __forceinline__ void rec_add_acc(uint32_t *rec, const AggSpec &s, const Acc<NV> &x) {
+template <int NV, typename V>
+__device__ __forceinline__ void rec_add_acc(uint32_t *rec, const AggSpec &s, const Acc<NV, V> &x) {
     for (int j = 0; j < s.n; ++j) {
         uint32_t *p = rec + s.word[j];
-        const int c = s.col[j];
-        long long sum = x.sum[0];
-        int mn = x.mn[0], mx = x.mx[0];
-#pragma unroll
-        for (int cc = 1; cc < NV; ++cc) {
-            if (cc == c) {
-                sum = x.sum[cc];
-                mn = x.mn[cc];
-                mx = x.mx[cc];
-            }
-        }
+        long long sum;
+        V mn, mx;
+        acc_pick(x, s.col[j], sum, mn, mx);
         switch (s.op[j]) {
             case GJ_SUM: atomicAdd(reinterpret_cast<unsigned long long *>(p), (unsigned long long)sum); break;
             case GJ_COUNT: atomicAdd(p, x.cnt); break;
-            case GJ_MIN: atomicMin(reinterpret_cast<int *>(p), mn); break;
-            default: atomicMax(reinterpret_cast<int *>(p), mx); break;
+            case GJ_MIN:
+                if (sizeof(V) == 8 && s.w8[j]) atomicMin(reinterpret_cast<long long *>(p), (long long)mn);
+                else atomicMin(reinterpret_cast<int *>(p), narrow_min(mn));
+                break;
+            default:
+                if (sizeof(V) == 8 && s.w8[j]) atomicMax(reinterpret_cast<long long *>(p), (long long)mx);
+                else atomicMax(reinterpret_cast<int *>(p), narrow_max(mx));
+                break;
         }
     }
 }
@@ -362,16 +448,16 @@ __device__ __forceinline__ void rec_add_acc(uint32_t *rec, const AggSpec &s, con
 // Rows of one wave round with group ids: lanes sharing an id are combined in
 // registers first, so each distinct id costs one set of LDS atomics per wave
 // instead of one per lane (the case of few groups, where lanes collide).
-template <int NV>
+template <int NV, typename V>
 __device__ __forceinline__ void wave_aggregate(uint32_t *recs, const AggSpec &s, bool valid, uint32_t id,
-                                               const Row<NV> &r) {
+                                               const Row<NV, V> &r) {
     uint64_t todo = __ballot(valid);
     while (todo) {
         const int leader = __ffsll((long long)todo) - 1;
         const uint32_t lid = __shfl(id, leader, kWave);
         const bool mine = valid && id == lid;
         const uint64_t peers = __ballot(mine);
-        Acc<NV> x;
+        Acc<NV, V> x;
         acc_clear(x);
         if (mine) acc_row(x, r);
         x = acc_wave_reduce(x);
@@ -380,35 +466,35 @@ __device__ __forceinline__ void wave_aggregate(uint32_t *recs, const AggSpec &s,
     }
 }
 
-// Identity values for every output column over groups [0, g).
-__global__ void k_out_init(AggSpec s, uint64_t g) {
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < g; i += (uint64_t)gridDim.x * blockDim.x) {
-        for (int j = 0; j < s.n; ++j) {
-            switch (s.op[j]) {
-                case GJ_SUM:
-                case GJ_COUNT: static_cast<long long *>(s.out[j])[i] = 0; break;
-                case GJ_MIN: static_cast<int *>(s.out[j])[i] = INT32_MAX; break;
-                default: static_cast<int *>(s.out[j])[i] = INT32_MIN; break;
-            }
+__device__ __forceinline__ void out_identity(const AggSpec &s, uint64_t i) {
+    for (int j = 0; j < s.n; ++j) {
+        switch (s.op[j]) {
+            case GJ_SUM:
+            case GJ_COUNT: static_cast<long long *>(s.out[j])[i] = 0; break;
+            case GJ_MIN:
+                if (s.w8[j]) static_cast<long long *>(s.out[j])[i] = INT64_MAX;
+                else static_cast<int *>(s.out[j])[i] = INT32_MAX;
+                break;
+            default:
+                if (s.w8[j]) static_cast<long long *>(s.out[j])[i] = INT64_MIN;
+                else static_cast<int *>(s.out[j])[i] = INT32_MIN;
+                break;
         }
     }
+}
+
+// Identity values for every output column over groups [0, g).
+__global__ void k_out_init(AggSpec s, uint64_t g) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < g; i += (uint64_t)gridDim.x * blockDim.x)
+        out_identity(s, i);
 }
 
 // The same for groups [base, base + min(g, cap)), base and g read on the device.
 __global__ void k_out_init_dev(AggSpec s, const uint64_t *__restrict__ base, const uint32_t *__restrict__ g_dev,
                                uint64_t cap) {
     const uint64_t b = base ? *base : 0ull, g = min((uint64_t)*g_dev, cap);
-    for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < g; k += (uint64_t)gridDim.x * blockDim.x) {
-        const uint64_t i = b + k;
-        for (int j = 0; j < s.n; ++j) {
-            switch (s.op[j]) {
-                case GJ_SUM:
-                case GJ_COUNT: static_cast<long long *>(s.out[j])[i] = 0; break;
-                case GJ_MIN: static_cast<int *>(s.out[j])[i] = INT32_MAX; break;
-                default: static_cast<int *>(s.out[j])[i] = INT32_MIN; break;
-            }
-        }
-    }
+    for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < g; k += (uint64_t)gridDim.x * blockDim.x)
+        out_identity(s, b + k);
 }
 
 // Batches: first output group of each instance (partitions are instance * 256 + digit).
@@ -834,7 +920,7 @@ __global__ void k_pgb_units(const uint32_t *__restrict__ poff, const uint32_t *_
     atomicMax(max_units, mx);
 }
 
-template <typename K, int NV, int BT, bool SKEW>
+template <typename K, int NV, int BT, bool SKEW, typename V>
 __device__ __forceinline__ void pgb_unit(const PgbArgs &a, uint32_t u, uint64_t out_base, uint32_t *s_dyn,
                                          uint32_t *s_unit, uint32_t &s_sent_id) {
     constexpr int RB = NV <= 2 ? 8 : 16 / NV;  // rows loaded per thread before they are aggregated
@@ -874,25 +960,25 @@ __device__ __forceinline__ void pgb_unit(const PgbArgs &a, uint32_t u, uint64_t 
     const AggSpec &s = a.spec;
     if (g == 1) {
         // one group (case 1): registers, then a block-wide reduction
-        Acc<NV> x;
+        Acc<NV, V> x;
         acc_clear(x);
         for (uint32_t base = r0; base < r1; base += BT * RB) {
-            Row<NV> rr[RB];
+            Row<NV, V> rr[RB];
 #pragma unroll
             for (int r = 0; r < RB; ++r) {
                 const uint32_t i = base + r * BT + tid;
-                if (i < r1) rr[r] = load_row<NV>(a.vals, i);
+                if (i < r1) rr[r] = load_row<NV, V>(a.vals, i);
             }
 #pragma unroll
             for (int r = 0; r < RB; ++r)
                 if (base + r * BT + tid < r1) acc_row(x, rr[r]);
         }
         x = acc_wave_reduce(x);
-        Acc<NV> *s_acc = reinterpret_cast<Acc<NV> *>(s_dyn);
+        Acc<NV, V> *s_acc = reinterpret_cast<Acc<NV, V> *>(s_dyn);
         if (lane == 0) s_acc[tid / kWave] = x;
         __syncthreads();
         if (tid == 0) {
-            Acc<NV> t = s_acc[0];
+            Acc<NV, V> t = s_acc[0];
             for (int w = 1; w < (BT / kWave); ++w) acc_merge(t, s_acc[w]);
             acc_flush(t, s, gb, multi);
         }
@@ -952,12 +1038,12 @@ __device__ __forceinline__ void pgb_unit(const PgbArgs &a, uint32_t u, uint64_t 
     const bool few = g <= 2;
     for (uint32_t base = r0; base < r1; base += BT * RB) {
         K kk[RB];
-        Row<NV> rr[RB];
+        Row<NV, V> rr[RB];
 #pragma unroll
         for (int r = 0; r < RB; ++r) {
             const uint32_t i = base + r * BT + tid;
             kk[r] = i < r1 ? keys[i] : e;
-            if (i < r1) rr[r] = load_row<NV>(a.vals, i);
+            if (i < r1) rr[r] = load_row<NV, V>(a.vals, i);
         }
         // group ids: every row's first probe is read before any is resolved (the
         // table is at most half full, so most rows stop there)
@@ -1021,7 +1107,7 @@ __device__ __forceinline__ void pgb_unit(const PgbArgs &a, uint32_t u, uint64_t 
 // BT threads per workgroup: 256, or 1024 when a partition's table and records
 // take so much LDS that only one or two workgroups fit a compute unit (many
 // groups per partition), so that the unit still runs 16 or more waves.
-template <typename K, int NV, int BT = kBlock, bool SKEW = false>
+template <typename K, int NV, int BT = kBlock, bool SKEW = false, typename V = int>
 __global__ __launch_bounds__(BT) void k_pgb_aggregate(PgbArgs a) {
     extern __shared__ __align__(16) uint32_t s_dyn[];
     __shared__ uint32_t s_unit[5];
@@ -1030,30 +1116,32 @@ __global__ __launch_bounds__(BT) void k_pgb_aggregate(PgbArgs a) {
     const uint64_t out_base = a.out_base ? *a.out_base : 0ull;
     // persistent: a workgroup takes units blockIdx.x, blockIdx.x + gridDim.x, ...
     for (uint32_t u = blockIdx.x; u < n_units; u += gridDim.x) {
-        pgb_unit<K, NV, BT, SKEW>(a, u, out_base, s_dyn, s_unit, s_sent_id);
+        pgb_unit<K, NV, BT, SKEW, V>(a, u, out_base, s_dyn, s_unit, s_sent_id);
         __syncthreads();  // the unit's LDS state is rebuilt by the next one
     }
 }
 
-template <typename K, int NV>
+template <typename K, int NV, typename V = int>
 void launch_pgb_aggregate(bool wide, bool skewed, uint32_t units, size_t lds, hipStream_t st, const PgbArgs &a,
                           double bytes) {
     if constexpr (NV <= 2) {
         if (wide) {
             if (skewed)
-                GJ_LAUNCH("k_pgb_aggregate", bytes, (k_pgb_aggregate<K, NV, 1024, true>), dim3(units), dim3(1024), lds,
-                          st, a);
+                GJ_LAUNCH("k_pgb_aggregate", bytes, (k_pgb_aggregate<K, NV, 1024, true, V>), dim3(units), dim3(1024),
+                          lds, st, a);
             else
-                GJ_LAUNCH("k_pgb_aggregate", bytes, (k_pgb_aggregate<K, NV, 1024>), dim3(units), dim3(1024), lds, st, a);
+                GJ_LAUNCH("k_pgb_aggregate", bytes, (k_pgb_aggregate<K, NV, 1024, false, V>), dim3(units), dim3(1024),
+                          lds, st, a);
             return;
         }
     }
     (void)wide;
     if (skewed)
-        GJ_LAUNCH("k_pgb_aggregate", bytes, (k_pgb_aggregate<K, NV, kBlock, true>), dim3(units), dim3(kBlock), lds, st,
-                  a);
+        GJ_LAUNCH("k_pgb_aggregate", bytes, (k_pgb_aggregate<K, NV, kBlock, true, V>), dim3(units), dim3(kBlock), lds,
+                  st, a);
     else
-        GJ_LAUNCH("k_pgb_aggregate", bytes, (k_pgb_aggregate<K, NV>), dim3(units), dim3(kBlock), lds, st, a);
+        GJ_LAUNCH("k_pgb_aggregate", bytes, (k_pgb_aggregate<K, NV, kBlock, false, V>), dim3(units), dim3(kBlock), lds,
+                  st, a);
 }
 
 // ---------------------------------------------------------------------------------
@@ -1166,7 +1254,7 @@ __global__ __launch_bounds__(kBlock) void k_hgb_insert(HgbArgs a) {
     }
 }
 
-template <int NV>
+template <int NV, typename V = int>
 __global__ __launch_bounds__(kBlock) void k_hgb_aggregate(HgbArgs a) {
     constexpr int RB = NV <= 2 ? 8 : 16 / NV;
     extern __shared__ __align__(16) uint32_t s_dyn[];
@@ -1180,12 +1268,12 @@ __global__ __launch_bounds__(kBlock) void k_hgb_aggregate(HgbArgs a) {
     const uint32_t stride = gridDim.x * kBlock * RB;
     for (uint32_t base = blockIdx.x * kBlock * RB; base < a.n; base += stride) {
         uint32_t loc[RB], gid[RB];
-        Row<NV> rr[RB];
+        Row<NV, V> rr[RB];
 #pragma unroll
         for (int r = 0; r < RB; ++r) {
             const uint32_t i = base + r * kBlock + threadIdx.x;
             loc[r] = i < a.n ? a.gid_loc[i] : 0u;
-            if (i < a.n) rr[r] = load_row<NV>(a.vals, i);
+            if (i < a.n) rr[r] = load_row<NV, V>(a.vals, i);
         }
 #pragma unroll
         for (int r = 0; r < RB; ++r) gid[r] = a.gid[loc[r]];
@@ -1221,7 +1309,7 @@ __global__ __launch_bounds__(kBlock) void k_hgb_aggregate(HgbArgs a) {
 // run on one XCD, so the chunk's group ids come from HBM once and from that
 // XCD's L2 for the other slices; value columns are read only for rows in the
 // slice.
-template <int NV, int BT>
+template <int NV, int BT, typename V = int>
 __global__ __launch_bounds__(BT) void k_hgb_aggregate_sliced(HgbArgs a) {
     constexpr int RB = NV <= 2 ? 8 : 16 / NV;
     extern __shared__ __align__(16) uint32_t s_dyn[];
@@ -1238,7 +1326,7 @@ __global__ __launch_bounds__(BT) void k_hgb_aggregate_sliced(HgbArgs a) {
     const uint32_t row1 = (uint32_t)min<uint64_t>((uint64_t)row0 + a.chunk_rows, a.n);
     for (uint32_t base = row0; base < row1; base += BT * RB) {
         uint32_t loc[RB], off[RB];
-        Row<NV> rr[RB];
+        Row<NV, V> rr[RB];
 #pragma unroll
         for (int r = 0; r < RB; ++r) {
             const uint32_t i = base + r * BT + threadIdx.x;
@@ -1251,7 +1339,7 @@ __global__ __launch_bounds__(BT) void k_hgb_aggregate_sliced(HgbArgs a) {
             const uint32_t local = a.gid[loc[r]] - g0;  // wraps for ids below the slice
             const bool in = i < row1 && local < L;
             off[r] = in ? local * (uint32_t)s.words : spare_off(L * s.words);
-            rr[r] = in ? load_row<NV>(a.vals, i) : Row<NV>{};
+            rr[r] = in ? load_row<NV, V>(a.vals, i) : Row<NV, V>{};
             any |= in;
         }
         if (__any(any)) rec_add_rows<NV, RB>(s_dyn, s, off, rr, wave_active_rows<RB>(base, BT, row1), false);
@@ -1302,9 +1390,9 @@ __global__ __launch_bounds__(kBlock) void k_sgb_heads(SgbArgs a) {
     if (threadIdx.x == 0) a.tile_heads[blockIdx.x] = tot;
 }
 
-template <int NV>
-__device__ __forceinline__ Acc<NV> acc_shfl_up(const Acc<NV> &x, int d) {
-    Acc<NV> y;
+template <int NV, typename V>
+__device__ __forceinline__ Acc<NV, V> acc_shfl_up(const Acc<NV, V> &x, int d) {
+    Acc<NV, V> y;
     y.cnt = __shfl_up(x.cnt, d, kWave);
 #pragma unroll
     for (int c = 0; c < NV; ++c) {
@@ -1316,10 +1404,10 @@ __device__ __forceinline__ Acc<NV> acc_shfl_up(const Acc<NV> &x, int d) {
 }
 
 // Segmented combine: (f1, A1) then (f2, A2) = (f1 | f2, f2 ? A2 : A1 + A2).
-template <typename K, int NV>
+template <typename K, int NV, typename V = int>
 __global__ __launch_bounds__(kBlock) void k_sgb_reduce(SgbArgs a) {
     constexpr int IT = kSgbItems;
-    __shared__ Acc<NV> s_wacc[kWaves];
+    __shared__ Acc<NV, V> s_wacc[kWaves];
     __shared__ uint32_t s_wf[kWaves];
     __shared__ uint32_t s_tmp[kWaves];
     const K *__restrict__ keys = static_cast<const K *>(a.keys);
@@ -1327,14 +1415,14 @@ __global__ __launch_bounds__(kBlock) void k_sgb_reduce(SgbArgs a) {
     const uint32_t t0 = blockIdx.x * kSgbTile;
     const uint32_t first = t0 + tid * IT;  // this thread's rows: [first, first + IT)
     K kk[IT];
-    Row<NV> rr[IT];
+    Row<NV, V> rr[IT];
 #pragma unroll
     for (int k = 0; k < IT; ++k) {
         const uint32_t i = first + k;
         kk[k] = K(0);
         if (i < a.n) {
             kk[k] = keys[i];
-            rr[k] = load_row<NV>(a.vals, i);
+            rr[k] = load_row<NV, V>(a.vals, i);
         }
     }
     K prev = (first > 0 && first <= a.n) ? keys[first - 1] : K(0);
@@ -1352,7 +1440,7 @@ __global__ __launch_bounds__(kBlock) void k_sgb_reduce(SgbArgs a) {
     }
     const uint32_t hpre = block_exclusive_sum<uint32_t>(hc, s_tmp, (uint32_t *)nullptr);
     // this thread's tail: rows after its last head (all rows if it has none)
-    Acc<NV> A;
+    Acc<NV, V> A;
     acc_clear(A);
 #pragma unroll
     for (int k = 0; k < IT; ++k) {
@@ -1366,7 +1454,7 @@ __global__ __launch_bounds__(kBlock) void k_sgb_reduce(SgbArgs a) {
 #pragma unroll
     for (int d = 1; d < kWave; d <<= 1) {
         const uint32_t fo = __shfl_up(f, d, kWave);
-        Acc<NV> Ao = acc_shfl_up(A, d);
+        Acc<NV, V> Ao = acc_shfl_up(A, d);
         if (lane >= d) {
             if (!f) {
                 acc_merge(Ao, A);
@@ -1380,14 +1468,14 @@ __global__ __launch_bounds__(kBlock) void k_sgb_reduce(SgbArgs a) {
         s_wf[w] = f;
     }
     uint32_t fx = __shfl_up(f, 1, kWave);
-    Acc<NV> Ax = acc_shfl_up(A, 1);
+    Acc<NV, V> Ax = acc_shfl_up(A, 1);
     if (lane == 0) {
         fx = 0;
         acc_clear(Ax);
     }
     __syncthreads();
     // carry into this thread = (earlier waves) then (earlier lanes of this wave)
-    Acc<NV> carry;
+    Acc<NV, V> carry;
     if (fx) {
         carry = Ax;
     } else {
@@ -1402,7 +1490,7 @@ __global__ __launch_bounds__(kBlock) void k_sgb_reduce(SgbArgs a) {
     // A run that began before this thread began inside the tile iff an earlier
     // thread of the tile had a head; only runs inside the tile are written plainly.
     const uint64_t gbase = a.tile_heads[blockIdx.x];
-    Acc<NV> cur = carry;
+    Acc<NV, V> cur = carry;
     bool cur_in_tile = hpre > 0;
     uint64_t cur_gid = gbase + hpre - 1;  // wraps only before row 0, where cur is empty
     K *ok = static_cast<K *>(a.out_key);
@@ -1465,24 +1553,72 @@ namespace {
 // Register tier for the value columns: kernels are built for 1, 2, 4 and 8.
 int nv_tier(int n_vals) { return n_vals <= 1 ? 1 : n_vals <= 2 ? 2 : n_vals <= 4 ? 4 : 8; }
 
-AggSpec make_spec(const gj_agg *aggs, int n_aggs, void *const *outs) {
+// Record layout: 64-bit fields first (sums, and MIN / MAX of 8-byte columns),
+// then 32-bit ones, so that every 64-bit field is 8-byte aligned. val_w: value
+// column widths (nullptr: all 4 bytes).
+AggSpec make_spec(const gj_agg *aggs, int n_aggs, void *const *outs, const int *val_w = nullptr) {
     AggSpec s{};
     s.n = n_aggs;
     int w = 0;
-    for (int pass = 0; pass < 2; ++pass) {  // 64-bit sums first, then 32-bit fields
+    for (int pass = 0; pass < 2; ++pass) {
         for (int j = 0; j < n_aggs; ++j) {
-            const bool is_sum = aggs[j].op == GJ_SUM;
-            if ((pass == 0) != is_sum) continue;
-            s.op[j] = aggs[j].op;
-            s.col[j] = aggs[j].op == GJ_COUNT ? 0 : aggs[j].col;
+            const int op = aggs[j].op;
+            const bool w8 = (op == GJ_MIN || op == GJ_MAX) && val_w && val_w[aggs[j].col] == 8;
+            const bool is64 = op == GJ_SUM || w8;
+            if ((pass == 0) != is64) continue;
+            s.op[j] = op;
+            s.col[j] = op == GJ_COUNT ? 0 : aggs[j].col;
+            s.w8[j] = w8 ? 1 : 0;
             s.word[j] = w;
-            w += is_sum ? 2 : 1;
+            w += is64 ? 2 : 1;
             s.out[j] = outs[j];
         }
     }
     s.words = (w + 1) & ~1;
     if (s.words == 0) s.words = 2;
     return s;
+}
+
+// Value source over the caller's columns (GFUR, or no transformation).
+ValSrc val_src(const ValCols &vc) {
+    ValSrc vs{};
+    vs.n = vc.n;
+    for (int c = 0; c < vc.n; ++c) {
+        vs.col[c] = vc.col[c];
+        vs.w8[c] = vc.width[c] == 8;
+    }
+    vs.rowid = nullptr;
+    return vs;
+}
+
+bool any_wide(const ValCols &vc) {
+    for (int c = 0; c < vc.n; ++c)
+        if (vc.width[c] == 8) return true;
+    return false;
+}
+
+double val_bytes(const ValCols &vc) {
+    double b = 0;
+    for (int c = 0; c < vc.n; ++c) b += vc.width[c];
+    return b;
+}
+
+// Output column of aggregate j: SUM and COUNT int64, MIN and MAX the column's width.
+size_t agg_out_width(const gj_agg &a, const ValCols &vc) {
+    if (a.op == GJ_SUM || a.op == GJ_COUNT) return 8;
+    return (size_t)vc.width[a.col];
+}
+
+// GFTR: value columns move with the keys into scratch columns of the same widths.
+void val_transform(Ctx &ctx, const ValCols &vc, uint32_t n, PartCols &pc, ValSrc &vs) {
+    pc.n = vc.n;
+    vs = val_src(vc);
+    for (int c = 0; c < vc.n; ++c) {
+        pc.in[c] = vc.col[c];
+        pc.width[c] = vc.width[c];
+        pc.out[c] = ctx.scratch((size_t)n * vc.width[c]);
+        vs.col[c] = pc.out[c];
+    }
 }
 
 void init_outputs(hipStream_t st, const AggSpec &s, uint64_t g) {
@@ -1521,31 +1657,24 @@ double estimate_groups(Ctx &ctx, int key_bytes, const void *key, uint32_t n) {
     return std::min(e, (double)n);
 }
 
-int64_t groupby_partition(Ctx &ctx, int key_bytes, const void *key, const int32_t *const *vals, int n_vals,
+int64_t groupby_partition(Ctx &ctx, int key_bytes, const void *key, const ValCols &vc,
                           uint32_t n, const gj_agg *aggs, int n_aggs, bool gfur, int bits, void **out_key,
                           void **out_aggs, int *fell_back) {
     hipStream_t st = ctx.stream;
     *fell_back = 0;
     const int passes = bits > 8 ? 2 : 1;
+    const int n_vals = vc.n;
     // transformation: partition keys (and, under GFTR, the value columns) on the hashed key
     void *pkey = ctx.scratch((size_t)n * key_bytes);
     PartCols pc;
     ValSrc vs{};
-    vs.n = n_vals;
     if (!gfur) {
-        pc.n = n_vals;
-        for (int c = 0; c < n_vals; ++c) {
-            pc.in[c] = vals[c];
-            pc.width[c] = 4;
-            pc.out[c] = ctx.scratch((size_t)n * 4);
-            vs.col[c] = static_cast<const int32_t *>(pc.out[c]);
-        }
-        vs.rowid = nullptr;
+        val_transform(ctx, vc, n, pc, vs);
     } else {
+        vs = val_src(vc);
         pc.n = 0;
         pc.gen_rowid = true;
         pc.rowid_out = ctx.scratch((size_t)n * 4);
-        for (int c = 0; c < n_vals; ++c) vs.col[c] = vals[c];
         vs.rowid = static_cast<const int32_t *>(pc.rowid_out);
     }
     const uint32_t np = 1u << bits;
@@ -1599,12 +1728,11 @@ int64_t groupby_partition(Ctx &ctx, int key_bytes, const void *key, const int32_
     *out_key = ctx.output((size_t)std::max<uint32_t>(g, 1) * key_bytes);
     std::vector<void *> outs(n_aggs);
     for (int j = 0; j < n_aggs; ++j) {
-        const bool wide = aggs[j].op == GJ_SUM || aggs[j].op == GJ_COUNT;
-        outs[j] = ctx.output((size_t)std::max<uint32_t>(g, 1) * (wide ? 8 : 4));
+        outs[j] = ctx.output((size_t)std::max<uint32_t>(g, 1) * agg_out_width(aggs[j], vc));
         out_aggs[j] = outs[j];
     }
     if (g == 0) return 0;
-    a.spec = make_spec(aggs, n_aggs, outs.data());
+    a.spec = make_spec(aggs, n_aggs, outs.data(), vc.width);
     a.vals = vs;
     a.goff = gcnt;
     a.ubase = ucnt;
@@ -1639,20 +1767,23 @@ int64_t groupby_partition(Ctx &ctx, int key_bytes, const void *key, const int32_
         lds = tab_bytes(log2cap) + need;
     }
     a.log2cap = log2cap;
-    lds = std::max<size_t>(lds, (size_t)kWaves * 160 + 16);  // the one-group path keeps a per-wave total
+    lds = std::max<size_t>(lds, (size_t)16 * 256 + 16);  // the one-group path keeps a per-wave total
     // outputs of partitions split over several units are folded with atomics
     if (max_units > 1 || !a.lds_records) init_outputs(st, a.spec, g);
     // skew: the largest partition holds at least twice the mean partition's units
     const bool skewed = (uint64_t)max_units * np >= 2ull * units && max_units >= 4;
-    const double bytes = (double)n * (key_bytes + 4.0 * n_vals + (gfur ? 4.0 : 0.0)) +
+    const double bytes = (double)n * (key_bytes + val_bytes(vc) + (gfur ? 4.0 : 0.0)) +
                          (double)g * (key_bytes + 4.0 * a.spec.words);
-#define GJ_PGB(K, NV) launch_pgb_aggregate<K, NV>(wide, skewed, units, lds, st, a, bytes)
     const int nvt = nv_tier(n_vals);
-    if (key_bytes == 4) {
-        if (nvt == 1) GJ_PGB(int32_t, 1); else if (nvt == 2) GJ_PGB(int32_t, 2); else if (nvt == 4) GJ_PGB(int32_t, 4); else GJ_PGB(int32_t, 8);
+#define GJ_PGB(K, NV, V) launch_pgb_aggregate<K, NV, V>(wide, skewed, units, lds, st, a, bytes)
+#define GJ_PGB_NV(K, V) \
+    if (nvt == 1) GJ_PGB(K, 1, V); else if (nvt == 2) GJ_PGB(K, 2, V); else if (nvt == 4) GJ_PGB(K, 4, V); else GJ_PGB(K, 8, V)
+    if (any_wide(vc)) {
+        if (key_bytes == 4) { GJ_PGB_NV(int32_t, long long); } else { GJ_PGB_NV(int64_t, long long); }
     } else {
-        if (nvt == 1) GJ_PGB(int64_t, 1); else if (nvt == 2) GJ_PGB(int64_t, 2); else if (nvt == 4) GJ_PGB(int64_t, 4); else GJ_PGB(int64_t, 8);
+        if (key_bytes == 4) { GJ_PGB_NV(int32_t, int); } else { GJ_PGB_NV(int64_t, int); }
     }
+#undef GJ_PGB_NV
 #undef GJ_PGB
     return g;
 }
@@ -1811,7 +1942,7 @@ static uint32_t hgb_assign_ids(Ctx &ctx, HgbArgs &a, int key_bytes, const void *
     return r.first;
 }
 
-int64_t groupby_hash(Ctx &ctx, int key_bytes, const void *key, const int32_t *const *vals, int n_vals, uint32_t n,
+int64_t groupby_hash(Ctx &ctx, int key_bytes, const void *key, const ValCols &vc, uint32_t n,
                      const gj_agg *aggs, int n_aggs, int lds_budget, double g_est, float occupancy, void **out_key,
                      void **out_aggs) {
     hipStream_t st = ctx.stream;
@@ -1823,26 +1954,25 @@ int64_t groupby_hash(Ctx &ctx, int key_bytes, const void *key, const int32_t *co
     // there take the low ids, and under skew those are the frequent keys. Low ids
     // are the ones that keep LDS records when not every group fits. The full pass
     // then finds the prefix keys already present.
+    const int n_vals = vc.n;
     std::vector<void *> no_outs(n_aggs, nullptr);
-    const size_t rec = (size_t)make_spec(aggs, n_aggs, no_outs.data()).words * 4;
+    const size_t rec = (size_t)make_spec(aggs, n_aggs, no_outs.data(), vc.width).words * 4;
     const size_t budget = std::min(lds_budget > 0 ? (size_t)lds_budget : (size_t)64 * 1024, (size_t)64 * 1024);
     const uint32_t prefix = (uint32_t)std::max<size_t>(2048, 2 * (budget / rec));
     const uint32_t g = hgb_assign_ids(ctx, a, key_bytes, key, n, prefix, g_est, occupancy);
     *out_key = ctx.output((size_t)std::max<uint32_t>(g, 1) * key_bytes);
     std::vector<void *> outs(n_aggs);
     for (int j = 0; j < n_aggs; ++j) {
-        const bool wide = aggs[j].op == GJ_SUM || aggs[j].op == GJ_COUNT;
-        outs[j] = ctx.output((size_t)std::max<uint32_t>(g, 1) * (wide ? 8 : 4));
+        outs[j] = ctx.output((size_t)std::max<uint32_t>(g, 1) * agg_out_width(aggs[j], vc));
         out_aggs[j] = outs[j];
     }
     if (g == 0) return 0;
-    a.spec = make_spec(aggs, n_aggs, outs.data());
-    a.vals.n = n_vals;
-    for (int c = 0; c < n_vals; ++c) a.vals.col[c] = vals[c];
-    a.vals.rowid = nullptr;
+    a.spec = make_spec(aggs, n_aggs, outs.data(), vc.width);
+    a.vals = val_src(vc);
     a.g = g;
     init_outputs(st, a.spec, g);
-    const double bytes = (double)n * (4.0 * n_vals + 8.0) + (double)g * (key_bytes + 4.0 * a.spec.words);
+    const double bytes = (double)n * (val_bytes(vc) + 8.0) + (double)g * (key_bytes + 4.0 * a.spec.words);
+    const bool v64 = any_wide(vc);
     const int nvt = nv_tier(n_vals);
     // is_smem_enough, per slice: when the groups fit the LDS of a workgroup (at
     // most the 160 KB of a compute unit) in at most kHgbMaxSlices consecutive id
@@ -1863,15 +1993,17 @@ int64_t groupby_hash(Ctx &ctx, int key_bytes, const void *key, const int32_t *co
         a.chunks = chunks;
         a.chunk_rows = ceil_div_u32(n, chunks);
         const uint32_t sgrid = chunks * slices;
-#define GJ_HAGG_S(NV, BT) \
-    GJ_LAUNCH("k_hgb_aggregate", bytes, (k_hgb_aggregate_sliced<NV, BT>), dim3(sgrid), dim3(BT), alds, st, a)
-        if (wide) {
-            if (nvt == 1) GJ_HAGG_S(1, 1024); else if (nvt == 2) GJ_HAGG_S(2, 1024);
-            else if (nvt == 4) GJ_HAGG_S(4, 1024); else GJ_HAGG_S(8, 1024);
+#define GJ_HAGG_S(NV, BT, V) \
+    GJ_LAUNCH("k_hgb_aggregate", bytes, (k_hgb_aggregate_sliced<NV, BT, V>), dim3(sgrid), dim3(BT), alds, st, a)
+#define GJ_HAGG_S_NV(BT, V) \
+    if (nvt == 1) GJ_HAGG_S(1, BT, V); else if (nvt == 2) GJ_HAGG_S(2, BT, V); \
+    else if (nvt == 4) GJ_HAGG_S(4, BT, V); else GJ_HAGG_S(8, BT, V)
+        if (v64) {
+            if (wide) { GJ_HAGG_S_NV(1024, long long); } else { GJ_HAGG_S_NV(256, long long); }
         } else {
-            if (nvt == 1) GJ_HAGG_S(1, 256); else if (nvt == 2) GJ_HAGG_S(2, 256);
-            else if (nvt == 4) GJ_HAGG_S(4, 256); else GJ_HAGG_S(8, 256);
+            if (wide) { GJ_HAGG_S_NV(1024, int); } else { GJ_HAGG_S_NV(256, int); }
         }
+#undef GJ_HAGG_S_NV
 #undef GJ_HAGG_S
     } else {
         // Otherwise the lowest ids that fit (at most the budget, 64 KiB by default)
@@ -1887,8 +2019,15 @@ int64_t groupby_hash(Ctx &ctx, int key_bytes, const void *key, const int32_t *co
         const uint32_t per_cu = alds ? (uint32_t)std::max<size_t>(1, std::min<size_t>(7, (160u * 1024u) / alds)) : 0;
         const uint32_t agrid =
             alds ? std::min<uint32_t>(grid, std::max<uint32_t>(256u * per_cu, (1u << 19) / a.lds_groups)) : grid;
-#define GJ_HAGG(NV) GJ_LAUNCH("k_hgb_aggregate", bytes, k_hgb_aggregate<NV>, dim3(agrid), dim3(kBlock), alds, st, a)
-        if (nvt == 1) GJ_HAGG(1); else if (nvt == 2) GJ_HAGG(2); else if (nvt == 4) GJ_HAGG(4); else GJ_HAGG(8);
+#define GJ_HAGG(NV, V) \
+    GJ_LAUNCH("k_hgb_aggregate", bytes, (k_hgb_aggregate<NV, V>), dim3(agrid), dim3(kBlock), alds, st, a)
+        if (v64) {
+            if (nvt == 1) GJ_HAGG(1, long long); else if (nvt == 2) GJ_HAGG(2, long long);
+            else if (nvt == 4) GJ_HAGG(4, long long); else GJ_HAGG(8, long long);
+        } else {
+            if (nvt == 1) GJ_HAGG(1, int); else if (nvt == 2) GJ_HAGG(2, int); else if (nvt == 4) GJ_HAGG(4, int);
+            else GJ_HAGG(8, int);
+        }
 #undef GJ_HAGG
     }
     const uint32_t cb = std::min<uint32_t>(ceil_div_u32(g, 256), 4096);
@@ -1901,26 +2040,20 @@ int64_t groupby_hash(Ctx &ctx, int key_bytes, const void *key, const int32_t *co
     return g;
 }
 
-int64_t groupby_sort(Ctx &ctx, int key_bytes, const void *key, const int32_t *const *vals, int n_vals, uint32_t n,
+int64_t groupby_sort(Ctx &ctx, int key_bytes, const void *key, const ValCols &vc, uint32_t n,
                      const gj_agg *aggs, int n_aggs, bool gfur, void **out_key, void **out_aggs) {
     hipStream_t st = ctx.stream;
+    const int n_vals = vc.n;
     // transformation: LSD radix sort on the order-preserving key bits
     void *skey = ctx.scratch((size_t)n * key_bytes);
     PartCols pc;
     ValSrc vs{};
-    vs.n = n_vals;
     if (!gfur) {
-        pc.n = n_vals;
-        for (int c = 0; c < n_vals; ++c) {
-            pc.in[c] = vals[c];
-            pc.width[c] = 4;
-            pc.out[c] = ctx.scratch((size_t)n * 4);
-            vs.col[c] = static_cast<const int32_t *>(pc.out[c]);
-        }
+        val_transform(ctx, vc, n, pc, vs);
     } else {
+        vs = val_src(vc);
         pc.gen_rowid = true;
         pc.rowid_out = ctx.scratch((size_t)n * 4);
-        for (int c = 0; c < n_vals; ++c) vs.col[c] = vals[c];
         vs.rowid = static_cast<const int32_t *>(pc.rowid_out);
     }
     sort_run(ctx, key_bytes, key, skey, pc, n);
@@ -1939,29 +2072,33 @@ int64_t groupby_sort(Ctx &ctx, int key_bytes, const void *key, const int32_t *co
     *out_key = ctx.output((size_t)std::max<uint32_t>(g, 1) * key_bytes);
     std::vector<void *> outs(n_aggs);
     for (int j = 0; j < n_aggs; ++j) {
-        const bool wide = aggs[j].op == GJ_SUM || aggs[j].op == GJ_COUNT;
-        outs[j] = ctx.output((size_t)std::max<uint32_t>(g, 1) * (wide ? 8 : 4));
+        outs[j] = ctx.output((size_t)std::max<uint32_t>(g, 1) * agg_out_width(aggs[j], vc));
         out_aggs[j] = outs[j];
     }
     if (g == 0) return 0;
-    a.spec = make_spec(aggs, n_aggs, outs.data());
+    a.spec = make_spec(aggs, n_aggs, outs.data(), vc.width);
     a.vals = vs;
     a.out_key = *out_key;
     init_outputs(st, a.spec, g);
-    const double bytes = (double)n * (key_bytes + 4.0 * n_vals + (gfur ? 4.0 : 0.0)) +
+    const double bytes = (double)n * (key_bytes + val_bytes(vc) + (gfur ? 4.0 : 0.0)) +
                          (double)g * (key_bytes + 4.0 * a.spec.words);
-#define GJ_SGB(K, NV) GJ_LAUNCH("k_sgb_reduce", bytes, (k_sgb_reduce<K, NV>), dim3(tiles), dim3(kBlock), 0, st, a)
     const int nvt = nv_tier(n_vals);
-    if (key_bytes == 4) {
-        if (nvt == 1) GJ_SGB(int32_t, 1); else if (nvt == 2) GJ_SGB(int32_t, 2); else if (nvt == 4) GJ_SGB(int32_t, 4); else GJ_SGB(int32_t, 8);
+#define GJ_SGB(K, NV, V) \
+    GJ_LAUNCH("k_sgb_reduce", bytes, (k_sgb_reduce<K, NV, V>), dim3(tiles), dim3(kBlock), 0, st, a)
+#define GJ_SGB_NV(K, V) \
+    if (nvt == 1) GJ_SGB(K, 1, V); else if (nvt == 2) GJ_SGB(K, 2, V); else if (nvt == 4) GJ_SGB(K, 4, V); \
+    else GJ_SGB(K, 8, V)
+    if (any_wide(vc)) {
+        if (key_bytes == 4) { GJ_SGB_NV(int32_t, long long); } else { GJ_SGB_NV(int64_t, long long); }
     } else {
-        if (nvt == 1) GJ_SGB(int64_t, 1); else if (nvt == 2) GJ_SGB(int64_t, 2); else if (nvt == 4) GJ_SGB(int64_t, 4); else GJ_SGB(int64_t, 8);
+        if (key_bytes == 4) { GJ_SGB_NV(int32_t, int); } else { GJ_SGB_NV(int64_t, int); }
     }
+#undef GJ_SGB_NV
 #undef GJ_SGB
     return g;
 }
 
-int64_t groupby_sort_de(Ctx &ctx, int key_bytes, const void *key, const int32_t *const *vals, int n_vals, uint32_t n,
+int64_t groupby_sort_de(Ctx &ctx, int key_bytes, const void *key, const ValCols &vc, uint32_t n,
                         const gj_agg *aggs, int n_aggs, double g_est, float occupancy, void **out_key,
                         void **out_aggs) {
     hipStream_t st = ctx.stream;
@@ -1971,8 +2108,7 @@ int64_t groupby_sort_de(Ctx &ctx, int key_bytes, const void *key, const int32_t 
     *out_key = ctx.output((size_t)std::max<uint32_t>(g, 1) * key_bytes);
     std::vector<void *> outs(n_aggs);
     for (int j = 0; j < n_aggs; ++j) {
-        const bool wide = aggs[j].op == GJ_SUM || aggs[j].op == GJ_COUNT;
-        outs[j] = ctx.output((size_t)std::max<uint32_t>(g, 1) * (wide ? 8 : 4));
+        outs[j] = ctx.output((size_t)std::max<uint32_t>(g, 1) * agg_out_width(aggs[j], vc));
         out_aggs[j] = outs[j];
     }
     if (g == 0) return 0;
@@ -1993,14 +2129,7 @@ int64_t groupby_sort_de(Ctx &ctx, int key_bytes, const void *key, const int32_t 
     int32_t *scode = ctx.scratch_n<int32_t>(n);
     PartCols pc;
     ValSrc vs{};
-    vs.n = n_vals;
-    pc.n = n_vals;
-    for (int c = 0; c < n_vals; ++c) {
-        pc.in[c] = vals[c];
-        pc.width[c] = 4;
-        pc.out[c] = ctx.scratch((size_t)n * 4);
-        vs.col[c] = static_cast<const int32_t *>(pc.out[c]);
-    }
+    val_transform(ctx, vc, n, pc, vs);
     sort_run(ctx, 4, code, scode, pc, n);
     // segmented reduction over the sorted codes: group j is code j
     SgbArgs a{};
@@ -2010,14 +2139,21 @@ int64_t groupby_sort_de(Ctx &ctx, int key_bytes, const void *key, const int32_t 
     a.tile_heads = ctx.scratch_n<uint32_t>(tiles + 1);
     GJ_LAUNCH("k_sgb_heads", 4.0 * n, k_sgb_heads<int32_t>, dim3(tiles), dim3(kBlock), 0, st, a);
     scan_exclusive_u32(ctx, a.tile_heads, a.tile_heads, tiles, a.tile_heads + tiles);
-    a.spec = make_spec(aggs, n_aggs, outs.data());
+    a.spec = make_spec(aggs, n_aggs, outs.data(), vc.width);
     a.vals = vs;
     a.out_key = nullptr;
     init_outputs(st, a.spec, g);
-    const double bytes = (double)n * (4.0 + 4.0 * n_vals) + (double)g * (key_bytes + 4.0 * a.spec.words);
-#define GJ_SGB(NV) GJ_LAUNCH("k_sgb_reduce", bytes, (k_sgb_reduce<int32_t, NV>), dim3(tiles), dim3(kBlock), 0, st, a)
-    const int nvt = nv_tier(n_vals);
-    if (nvt == 1) GJ_SGB(1); else if (nvt == 2) GJ_SGB(2); else if (nvt == 4) GJ_SGB(4); else GJ_SGB(8);
+    const double bytes = (double)n * (4.0 + val_bytes(vc)) + (double)g * (key_bytes + 4.0 * a.spec.words);
+    const int nvt = nv_tier(vc.n);
+#define GJ_SGB(NV, V) \
+    GJ_LAUNCH("k_sgb_reduce", bytes, (k_sgb_reduce<int32_t, NV, V>), dim3(tiles), dim3(kBlock), 0, st, a)
+    if (any_wide(vc)) {
+        if (nvt == 1) GJ_SGB(1, long long); else if (nvt == 2) GJ_SGB(2, long long);
+        else if (nvt == 4) GJ_SGB(4, long long); else GJ_SGB(8, long long);
+    } else {
+        if (nvt == 1) GJ_SGB(1, int); else if (nvt == 2) GJ_SGB(2, int); else if (nvt == 4) GJ_SGB(4, int);
+        else GJ_SGB(8, int);
+    }
 #undef GJ_SGB
     return g;
 }

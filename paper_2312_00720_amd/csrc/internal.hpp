@@ -194,26 +194,32 @@ constexpr int kScatterVariants = 14;
 void set_scatter_variant(int v);
 
 // ---- groupby.hip ----------------------------------------------------------------------
+// Value columns of a group-by: device pointers and widths (4 or 8 bytes).
+struct ValCols {
+    int n = 0;
+    const void *col[8] = {};
+    int width[8] = {};
+};
 // Each returns the number of groups and allocates the key and aggregate outputs
 // through ctx.output(). groupby_partition returns -1 with *fell_back = 1 when a
 // partition holds more distinct keys than its LDS table.
 // Estimated number of distinct keys (HyperLogLog, about 3% standard error);
 // synchronizes with the stream.
 double estimate_groups(Ctx &ctx, int key_bytes, const void *key, uint32_t n);
-int64_t groupby_partition(Ctx &ctx, int key_bytes, const void *key, const int32_t *const *vals, int n_vals,
+int64_t groupby_partition(Ctx &ctx, int key_bytes, const void *key, const ValCols &vc,
                           uint32_t n, const gj_agg *aggs, int n_aggs, bool gfur, int bits, void **out_key,
                           void **out_aggs, int *fell_back);
 // g_est > 0 sizes the global table for about that many groups at load `occupancy`
 // (<= 0: 0.45); a table found too small is replaced by one of 1.5 slots per row.
-int64_t groupby_hash(Ctx &ctx, int key_bytes, const void *key, const int32_t *const *vals, int n_vals, uint32_t n,
+int64_t groupby_hash(Ctx &ctx, int key_bytes, const void *key, const ValCols &vc, uint32_t n,
                      const gj_agg *aggs, int n_aggs, int lds_budget, double g_est, float occupancy, void **out_key,
                      void **out_aggs);
-int64_t groupby_sort(Ctx &ctx, int key_bytes, const void *key, const int32_t *const *vals, int n_vals, uint32_t n,
+int64_t groupby_sort(Ctx &ctx, int key_bytes, const void *key, const ValCols &vc, uint32_t n,
                      const gj_agg *aggs, int n_aggs, bool gfur, void **out_key, void **out_aggs);
 // Sort-based group-by with dictionary-encoded keys (SGB-DE-TR): Algorithm 1's
 // table assigns ids, the sorted distinct keys give each id its rank, rows are
 // sorted on 4-byte codes over the code bytes that vary, then reduced in order.
-int64_t groupby_sort_de(Ctx &ctx, int key_bytes, const void *key, const int32_t *const *vals, int n_vals, uint32_t n,
+int64_t groupby_sort_de(Ctx &ctx, int key_bytes, const void *key, const ValCols &vc, uint32_t n,
                         const gj_agg *aggs, int n_aggs, double g_est, float occupancy, void **out_key,
                         void **out_aggs);
 

@@ -40,7 +40,7 @@ def check(keys, vals, aggs=AGGS, sorted_out=False, **kw):
     order = np.argsort(gk, kind="stable")
     np.testing.assert_array_equal(gk[order], ek)
     for (c, op), g, e in zip(aggs, gcols, ecols):
-        assert g.dtype == (np.int64 if op in ("sum", "count") else np.int32)
+        assert g.dtype == (np.int64 if op in ("sum", "count") else np.asarray(vals[c]).dtype)
         np.testing.assert_array_equal(g[order], e, err_msg=f"{op}({c})")
     return gk, gcols
 
@@ -231,3 +231,18 @@ def test_partition_oversized_partitions(dt):
     check(keys, vals, algo="partition", radix_bits=2, mat="gfur")
     d = datagen.groupby_input(n, 16, 2, seed=22, alpha=1.0)
     check(d["key"], d["vals"], algo="partition")
+
+
+@pytest.mark.parametrize("algo,mat", ALGOS)
+@pytest.mark.parametrize("kb,card,alpha", [(4, 3000, 0.0), (8, 150000, 0.0), (4, 4096, 1.1), (8, 5, 0.0)])
+def test_eight_byte_values(algo, mat, kb, card, alpha):
+    """8-byte value columns (Section 5.2's 8-byte payloads), alone and next to a
+    4-byte column: SUM in int64 (wrapping like two's complement once values reach
+    2^62), MIN and MAX as int64, the 4-byte column's MIN and MAX as int32."""
+    d = datagen.groupby_input(200003, card, 1, seed=datagen.seed_for(2, 300 + card), alpha=alpha, key_bytes=kb)
+    g = datagen.rng(301 + card)
+    v8 = g.integers(-2**62, 2**62, size=len(d["key"]), dtype=np.int64)
+    v8[:3] = [np.iinfo(np.int64).min, np.iinfo(np.int64).max, 0]
+    gk, gcols = check(d["key"], [d["vals"][0], v8], algo=algo, mat=mat, sorted_out=algo.startswith("sort"))
+    assert gcols[2].dtype == np.int32 and gcols[5].dtype == np.int64
+    check(d["key"], [v8], AGGS[:4], algo=algo, mat=mat)

@@ -143,3 +143,54 @@ def test_hgb_ids(n, card):
     ids = gid[gid >= 0]
     assert sorted(ids.tolist()) == list(range(ng))
     assert np.all(keys[loc] == keys)
+
+
+def brute_groupby64(keys, vals):
+    """Per distinct key: count, and per column the sum reduced to a signed 64-bit
+    value (two's complement), min and max, with Python integers."""
+    out = []
+    for rec in brute_groupby(keys, vals):
+        rec = list(rec)
+        for v in range(len(vals)):
+            s = rec[2 + 3 * v] % 2**64
+            rec[2 + 3 * v] = s - 2**64 if s >= 2**63 else s
+        out.append(tuple(rec))
+    return out
+
+
+@pytest.mark.parametrize("n,nv,span", [(0, 1, 10), (1, 2, 10), (400, 2, 2**62), (300, 3, 2**40),
+                                       (200, 1, 2**63)])
+def test_groupby64_matches_brute_force(n, nv, span):
+    """8-byte value columns (oracle_groupby64): brute force per key; with values
+    up to 2^63 in magnitude the sums wrap, as 64-bit two's complement does."""
+    g = datagen.rng(7000 + n + nv)
+    keys = g.integers(-5, 6, size=n).astype(np.int32)
+    vals = [g.integers(-span, span, size=n, dtype=np.int64) for _ in range(nv)]
+    if n > 3:
+        vals[0][:2] = [np.iinfo(np.int64).min, np.iinfo(np.int64).max]
+    assert flatten(oracle.groupby(keys, vals), nv) == brute_groupby64(keys, vals)
+
+
+def test_groupby64_closed_form_and_mixed_widths():
+    """A 4-byte and an 8-byte column together: np.add.at / np.minimum.at /
+    np.maximum.at on int64 per key of {0..g-1}; the 4-byte column's results equal
+    the int32 oracle's."""
+    d = datagen.groupby_input(1 << 15, 777, 1, seed=91)
+    g = datagen.rng(92)
+    v8 = g.integers(-2**50, 2**50, size=1 << 15, dtype=np.int64)
+    res = oracle.groupby(d["key"], [d["vals"][0], v8])
+    k = d["key"].astype(np.int64)
+    present = np.nonzero(np.bincount(k, minlength=777))[0]
+    np.testing.assert_array_equal(res["key"], present)
+    s = np.zeros(777, np.int64)
+    np.add.at(s, k, v8)
+    mn = np.full(777, np.iinfo(np.int64).max)
+    np.minimum.at(mn, k, v8)
+    mx = np.full(777, np.iinfo(np.int64).min)
+    np.maximum.at(mx, k, v8)
+    np.testing.assert_array_equal(res["sum"][1], s[present])
+    np.testing.assert_array_equal(res["min"][1], mn[present])
+    np.testing.assert_array_equal(res["max"][1], mx[present])
+    r32 = oracle.groupby(d["key"], d["vals"])
+    for f in ("sum", "min", "max"):
+        np.testing.assert_array_equal(res[f][0], r32[f][0])
