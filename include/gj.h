@@ -366,6 +366,30 @@ int gj_partition(gj_col key, const gj_col *cols, int32_t n_cols, int64_t n_rows,
                  void *out_key, void *const *out_cols, void *out_rowid, int32_t *out_offsets,
                  const gj_allocator *alloc, void *stream);
 
+/*
+ * gj_partition without any device allocation, for callers that cannot
+ * allocate: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc. One pass only (bits 1..8, so passes is implied); otherwise
+ * the arguments, the output layout and the result are those of gj_partition,
+ * except that out_offsets (2^bits + 1 int32, device) is required. The caller
+ * owns every input and output buffer. The scratch of the pass (chunk table,
+ * per-chunk digit histograms, scan partials: about 4.2 MB at most, for any row
+ * count) lives in one statically allocated device array of
+ * gj_partition_noalloc_scratch_bytes() bytes per device, which the library
+ * holds until the process ends. A request needing more returns GJ_ECAPACITY.
+ * All calls on one device share that array: calls that overlap on a device
+ * (concurrent streams or threads) race and must not be issued; calls in
+ * sequence on any streams of the device are fine. Enqueues kernels only (no
+ * allocation, copy, memset or synchronization); the first call on a device
+ * looks up the array's device address.
+ */
+int gj_partition_noalloc(gj_col key, const gj_col *cols, int32_t n_cols, int64_t n_rows,
+                         int32_t bit_lo, int32_t bits, int32_t mode, void *out_key,
+                         void *const *out_cols, void *out_rowid, int32_t *out_offsets, void *stream);
+
+/* Size in bytes of the static scratch array of gj_partition_noalloc (per device). */
+size_t gj_partition_noalloc_scratch_bytes(void);
+
 /* ---- Machine measurements ----------------------------------------------------
  * The two kernels behind the cost model's constants (Section 4.1.1, Table 1).
  *

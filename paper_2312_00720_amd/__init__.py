@@ -126,6 +126,11 @@ def lib() -> ctypes.CDLL:
             L.gj_partition.restype = ctypes.c_int
             L.gj_partition.argtypes = [Col, ctypes.POINTER(Col), i32, i64, i32, i32, i32, i32,
                                        vp, ctypes.POINTER(vp), vp, vp, ctypes.POINTER(Allocator), vp]
+            L.gj_partition_noalloc.restype = ctypes.c_int
+            L.gj_partition_noalloc.argtypes = [Col, ctypes.POINTER(Col), i32, i64, i32, i32, i32,
+                                               vp, ctypes.POINTER(vp), vp, vp, vp]
+            L.gj_partition_noalloc_scratch_bytes.restype = ctypes.c_size_t
+            L.gj_partition_noalloc_scratch_bytes.argtypes = []
             L.gj_get_cost_constants.restype = ctypes.c_int
             L.gj_get_cost_constants.argtypes = [ctypes.POINTER(ctypes.c_double)] * 3
             L.gj_stream_copy.restype = ctypes.c_int
@@ -523,6 +528,34 @@ def partition(key: torch.Tensor, cols=(), *, bit_lo: int = 0, bits: int = 8, pas
                         ctypes.byref(A.struct), _stream(dev))
     _raise(rc)
     return ok, oc, orow, off
+
+
+def partition_noalloc(key: torch.Tensor, cols, out_key: torch.Tensor, out_cols, out_offsets: torch.Tensor, *,
+                      bit_lo: int = 0, bits: int = 8, mode: str = "bits", out_rowid: torch.Tensor | None = None):
+    """One-pass stable radix partition into caller-provided outputs, with no
+    device allocation by the library (gj_partition_noalloc): out_key and
+    out_cols like key and cols, out_offsets int32 of 2^bits + 1, out_rowid
+    int32 of n (optional)."""
+    L = lib()
+    cols, out_cols = list(cols), list(out_cols)
+    n = key.numel()
+    dev = key.device
+    _check_cols([key, *cols, out_key, *out_cols], n, dev)
+    if len(out_cols) != len(cols):
+        raise ValueError("one output column per input column")
+    if out_key.dtype != key.dtype or any(o.dtype != c.dtype for o, c in zip(out_cols, cols)):
+        raise ValueError("output columns must have the input columns' dtypes")
+    if out_offsets.dtype != torch.int32 or out_offsets.numel() != (1 << bits) + 1:
+        raise ValueError("out_offsets must be int32 with 2^bits + 1 entries")
+    if out_rowid is not None:
+        _check_cols([out_rowid], n, dev)
+    ci = (Col * max(1, len(cols)))(*[_col(t) for t in cols])
+    co = (ctypes.c_void_p * max(1, len(cols)))(*[t.data_ptr() if n else None for t in out_cols])
+    rc = L.gj_partition_noalloc(_col(key), ci, len(cols), n, bit_lo, bits, DIGIT[mode],
+                                out_key.data_ptr() if n else None, co,
+                                out_rowid.data_ptr() if (out_rowid is not None and n) else None,
+                                out_offsets.data_ptr(), _stream(dev))
+    _raise(rc)
 
 
 def groupby(key: torch.Tensor, vals, aggs, *, algo: str = "auto", mat: str = "auto",

@@ -53,6 +53,8 @@ def test_groupby_and_partition_overflow(gj):
     assert rc == GJ_EOVERFLOW and out.n_groups == 0
     rc = L.gj_partition(gj.Col(FAKE, gj.GJ_I32), None, 0, BIG, 0, 8, 1, 0, FAKE, None, None, None, None, None)
     assert rc == GJ_EOVERFLOW
+    rc = L.gj_partition_noalloc(gj.Col(FAKE, gj.GJ_I32), None, 0, BIG, 0, 8, 0, FAKE, None, None, FAKE, None)
+    assert rc == GJ_EOVERFLOW
 
 
 def test_join_batch_overflow(gj):
@@ -80,3 +82,9 @@ def test_argument_errors(gj):
     assert L.gj_join(ctypes.byref(R), ctypes.byref(S), None, None, None, ctypes.byref(out)) == GJ_EINVAL
     R = gj.Rel(gj.Col(FAKE, 7), None, 0, 10)
     assert L.gj_join(ctypes.byref(R), ctypes.byref(S), None, None, None, ctypes.byref(out)) == GJ_EINVAL
+    # the no-allocation partition takes one pass only, and needs the offsets
+    assert L.gj_partition_noalloc(gj.Col(FAKE, gj.GJ_I32), None, 0, 10, 0, 9, 0, FAKE, None, None, FAKE,
+                                  None) == GJ_EINVAL
+    assert L.gj_partition_noalloc(gj.Col(FAKE, gj.GJ_I32), None, 0, 10, 0, 8, 0, FAKE, None, None, None,
+                                  None) == GJ_EINVAL
+    assert L.gj_partition_noalloc_scratch_bytes() == 8 << 20
