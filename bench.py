@@ -256,6 +256,15 @@ def bench_groupby(args, copy_gbs) -> int:
     n, g = 1 << args.n_log2, 1 << args.g_log2
     log(f"generating group-by N=2^{args.n_log2} g=2^{args.g_log2} alpha={args.alpha}")
     d = dd.groupby_input(n, g, 2, seed=datagen.seed_for(2, args.g_log2), alpha=args.alpha)
+    keys_desc = "int32 key"
+    if args.gb_key_bytes == 8:
+        # 8-byte keys: the values 0..g-1 through an odd multiplier, so all 8 bytes vary
+        d["key"] = d["key"].to(torch.int64) * -7046029254386353131  # 0x9E3779B97F4A7C15 as int64
+        keys_desc = "int64 key (g values spread over all 8 bytes)"
+    elif args.sparse_keys:
+        # an odd multiplier is a bijection modulo 2^32: g distinct keys whose 4 bytes all vary
+        d["key"] = ((d["key"].to(torch.int64) * 0x9E3779B1) & 0xFFFFFFFF).to(torch.int32)
+        keys_desc = "int32 key (g values spread over all 4 bytes)"
     torch.cuda.synchronize()
     mat = args.mat if args.algo != "hash" else "auto"
 
@@ -271,7 +280,7 @@ def bench_groupby(args, copy_gbs) -> int:
         "metric": "group-by rows/s", "value": n / (ms / 1e3), "unit": "rows/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "int32", "data": "synthetic",
-        "config": {"workload": f"group-by N=2^{args.n_log2}, int32 key over 2^{args.g_log2} values "
+        "config": {"workload": f"group-by N=2^{args.n_log2}, {keys_desc} over 2^{args.g_log2} values "
                                f"({'uniform' if args.alpha == 0 else f'zipf {args.alpha}'}), 2 int32 values, "
                                f"COUNT+SUM+MIN+MAX, {args.algo}" + ("" if args.algo == "hash" else f" {mat.upper()}"),
                    "groups": groups},
@@ -279,7 +288,8 @@ def bench_groupby(args, copy_gbs) -> int:
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": dk["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": dk["gbs"] / HBM_PEAK_GBS,
                      "traffic": measured_traffic(dom, f"groupby_{args.algo}_n{args.n_log2}_g{args.g_log2}")
-                     if args.alpha == 0 and mat in ("gftr", "auto") and args.radix_bits == 0 else None},
+                     if args.alpha == 0 and mat in ("gftr", "auto") and args.radix_bits == 0
+                     and keys_desc == "int32 key" else None},
         "hbm_gbs_whole_step": sum(v["alg_bytes"] for v in stats.values()) / args.steps / (ms / 1e3) / 1e9,
         "profiled_ms_per_step": ms_prof,
         "kernels": {k: {"launches_per_step": v["launches"] / args.steps, "ms_per_step": v["ms_per_step"],
@@ -530,6 +540,8 @@ def main() -> int:
     ap.add_argument("--no-autotune", action="store_true", help="batch: built-in plan parameters")
     ap.add_argument("--n-log2", type=int, default=28, help="group-by rows")
     ap.add_argument("--g-log2", type=int, default=16, help="group-by key cardinality")
+    ap.add_argument("--sparse-keys", action="store_true", help="group-by: spread the keys over all 4 bytes")
+    ap.add_argument("--gb-key-bytes", type=int, default=4, choices=[4, 8], help="group-by key width")
     ap.add_argument("--algo", default="partition", choices=["partition", "hash", "sort", "sort_de"])
     ap.add_argument("--copy-only", action="store_true",
                     help="only run the plain copy (counter calibration) and print its GB/s")

@@ -92,6 +92,9 @@ typedef struct {
                                   has 4096, 8192 or 16384 rows, the smallest that holds it */
     uint64_t flags;            /* reserved, must be 0 */
     int32_t algo;              /* gj_join_algo */
+    float match_ratio_hint;    /* expected share of S rows with a match, for automatic choices
+                                  (0: unknown, taken as 1) */
+    float skew_hint;           /* expected Zipf factor of S.key (0: unknown, taken as uniform) */
 } gj_join_opts;
 
 /* Join output T(key, r_1..r_cR, s_1..s_cS). The library allocates every column
@@ -264,11 +267,12 @@ typedef struct {
                            make sure of) is replaced by one of 1.5 slots per row and the insert
                            runs again; the result does not depend on it. */
     int32_t lds_budget; /* hash: bytes of LDS per workgroup for aggregation records (0: 160 KB,
-                           a compute unit's LDS). When the group ids, cut into at most 16
+                           a compute unit's LDS). When the group ids, cut into at most 64
                            consecutive ranges, fit that budget per range, every group
                            aggregates in LDS (one workgroup per row chunk and id range);
                            otherwise the ids that fit min(budget, 64 KiB) aggregate in LDS
                            and the rest with global atomics */
+    float skew_hint;    /* expected Zipf factor of the keys, for automatic choices (0: unknown) */
 } gj_groupby_opts;
 
 /* Group-by output A(k, a_1..a_n): one row per distinct key. aggs[i] is the
@@ -413,28 +417,41 @@ int gj_gather_i32(const int32_t *map, const int32_t *values, int64_t n_values, i
  *   [0] 1 for a join, 0 for a group-by
  *   [1] log2 |R| / 32 (group-by: log2 N / 32)
  *   [2] log2 |S| / 32 (group-by: 0)
- *   [3] log2 g / 32 (join: log2 |R| / 32)
+ *   [3] log2 g / 32 (join: log2 |R| / 32; group-by: the HyperLogLog estimate)
  *   [4] key bytes / 8
  *   [5] R payload columns / 8 (group-by: value columns / 8)
- *   [6] S payload columns / 8 (group-by: 0)
- *   [7] Zipf factor of the foreign keys or group keys / 1.2
- *   [8] match ratio (group-by: 1)
+ *   [6] S payload columns / 8 (group-by: key bytes that vary between rows / 8)
+ *   [7] Zipf factor of the foreign keys or group keys / 1.2 (the hint; 0 without)
+ *   [8] match ratio (the hint, else 1; group-by: 1)
  *   [9] log2(|S| / |R|) / 32 (group-by: log2(N / g) / 32)
  *   [10] log2 expected output rows / 32
  *   [11] log2 input bytes / 48
- * Classes: 0 GFTR join, 1 GFUR join, 2 hash, 3 sort, 4 partition group-by.
- * op_kind 0 = join (classes 0-1 valid), 1 = group-by (classes 2-4 valid). */
+ * Classes: 0 partitioned-hash join GFTR, 1 partitioned-hash join GFUR,
+ * 2 hash, 3 sort, 4 partition group-by, 5 sort group-by on dictionary-encoded
+ * keys, 6 sort-merge join GFTR. op_kind 0 = join (classes 0, 1, 6 valid),
+ * 1 = group-by (classes 2-5 valid). */
+#define GJ_SELECT_CLASSES 7
 
 /* The analytical model: predicted seconds per class (infinity for invalid
  * classes), built on the paper's bandwidth models (Sections 4.1.3, 4.1.4) over
  * this implementation's passes, with MI355X constants. */
-int gj_cost_model(const float features[12], int32_t op_kind, double predicted_seconds[5]);
+int gj_cost_model(const float features[12], int32_t op_kind, double predicted_seconds[GJ_SELECT_CLASSES]);
 
 /* The class to run: the learned network's argmax when weights are loaded and its
  * output is finite, else the cost model's argmin. probs (may be NULL) receives
  * the network's probabilities, or a one-hot of the cost model's choice. The
  * choice never changes a result. */
-int gj_select(const float features[12], int32_t op_kind, int32_t *choice, float probs[5]);
+int gj_select(const float features[12], int32_t op_kind, int32_t *choice, float probs[GJ_SELECT_CLASSES]);
+
+/* The feature vector an automatic join choice (mat or algo GJ_*_AUTO) uses for
+ * these relations and options (host only; no device access). */
+int gj_join_features(const gj_rel *R, const gj_rel *S, const gj_join_opts *opts, float features[12]);
+
+/* The feature vector an automatic group-by choice uses: reads the keys once on
+ * `stream` (group-count estimate and varying key bytes) and synchronizes.
+ * Scratch from `alloc` (NULL: hipMallocAsync). */
+int gj_groupby_features(gj_col key, int32_t n_vals, int64_t n_rows, const gj_groupby_opts *opts,
+                        const gj_allocator *alloc, void *stream, float features[12]);
 
 /* Load trained network weights (host array of GJ_MLP_PARAMS floats; NULL or n = 0
  * unloads them). Thread-safe. */
@@ -448,15 +465,15 @@ int gj_set_cost_constants(double seq_bytes_per_s, double rand_ratio, double atom
 int gj_get_cost_constants(double *seq_bytes_per_s, double *rand_ratio, double *atomic_rate);
 
 /* ---- Selector network ------------------------------------------------------
- * 12 workload features -> 64 -> 64 (ReLU) -> 5 logits over {GFTR, GFUR, hash,
- * sort, partition}, softmax over the classes valid for the sample (mask), loss =
- * batch mean of -log p[label]. FP32; parameters are one flat device vector of
- * GJ_MLP_PARAMS floats: W1 (64x12 row-major), b1, W2 (64x64), b2, W3 (5x64), b3.
- * X is [batch x 12], mask [batch x 5] (1 = valid class), labels [batch], all
- * device arrays. Results are deterministic (fixed summation order). */
-#define GJ_MLP_PARAMS 5317
+ * 12 workload features -> 64 -> 64 (ReLU) -> 7 logits over the classes above,
+ * softmax over the classes valid for the sample (mask), loss = batch mean of
+ * -log p[label]. FP32; parameters are one flat device vector of GJ_MLP_PARAMS
+ * floats: W1 (64x12 row-major), b1, W2 (64x64), b2, W3 (7x64), b3. X is
+ * [batch x 12], mask [batch x 7] (1 = valid class), labels [batch], all device
+ * arrays. Results are deterministic (fixed summation order). */
+#define GJ_MLP_PARAMS 5447
 
-/* probs [batch x 5] = masked softmax of the network's logits. */
+/* probs [batch x 7] = masked softmax of the network's logits. */
 int gj_mlp_forward(const float *params, const float *X, const float *mask, int32_t batch, float *probs,
                    const gj_allocator *alloc, void *stream);
 

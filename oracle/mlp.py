@@ -3,18 +3,22 @@ the chain rule, and the Adam update.
 
 TEST INFRASTRUCTURE ONLY (see the package docstring).
 
-Network: 12 features -> 64 -> 64 (ReLU) -> 5 logits, softmax over the classes
-that are valid for the sample (join: GFTR, GFUR; group-by: hash, sort,
-partition), loss = mean over the batch of -log p[label]. Adam follows Kingma and
+Network: 12 features -> 64 -> 64 (ReLU) -> 7 logits, softmax over the classes
+that are valid for the sample (join: partitioned GFTR, partitioned GFUR,
+sort-merge GFTR; group-by: hash, sort, partition, sort on dictionary-encoded
+keys), loss = mean over the batch of -log p[label]. Adam follows Kingma and
 Ba (2015) with bias correction. Parameters are kept as a flat vector in the order
-W1 (64x12, row-major), b1, W2 (64x64), b2, W3 (5x64), b3.
+W1 (64x12, row-major), b1, W2 (64x64), b2, W3 (7x64), b3.
 """
 from __future__ import annotations
 
 import numpy as np
 
-SHAPES = [(64, 12), (64,), (64, 64), (64,), (5, 64), (5,)]
-N_PARAMS = sum(int(np.prod(s)) for s in SHAPES)  # 5317
+N_CLASSES = 7
+JOIN_CLASSES = (0, 1, 6)
+GROUPBY_CLASSES = (2, 3, 4, 5)
+SHAPES = [(64, 12), (64,), (64, 64), (64,), (N_CLASSES, 64), (N_CLASSES,)]
+N_PARAMS = sum(int(np.prod(s)) for s in SHAPES)  # 5447
 
 
 def unflatten(theta: np.ndarray):
@@ -40,7 +44,7 @@ def init(seed: int) -> np.ndarray:
 
 
 def forward(theta: np.ndarray, X: np.ndarray, mask: np.ndarray):
-    """Returns (probabilities [B,5], cache). mask[b, c] is 1 for valid classes."""
+    """Returns (probabilities [B, N_CLASSES], cache). mask[b, c] is 1 for valid classes."""
     W1, b1, W2, b2, W3, b3 = unflatten(theta)
     z1 = X @ W1.T + b1
     h1 = np.maximum(z1, 0.0)

@@ -58,7 +58,8 @@ class JoinOpts(ctypes.Structure):
     _fields_ = [("mat", ctypes.c_int32), ("unique_build_keys", ctypes.c_int32),
                 ("radix_bits", ctypes.c_int32), ("passes", ctypes.c_int32),
                 ("block_size", ctypes.c_int32), ("ht_occupancy", ctypes.c_float),
-                ("lds_budget", ctypes.c_int32), ("flags", ctypes.c_uint64), ("algo", ctypes.c_int32)]
+                ("lds_budget", ctypes.c_int32), ("flags", ctypes.c_uint64), ("algo", ctypes.c_int32),
+                ("match_ratio_hint", ctypes.c_float), ("skew_hint", ctypes.c_float)]
 
 
 class JoinOut(ctypes.Structure):
@@ -89,7 +90,7 @@ class Agg(ctypes.Structure):
 class GroupByOpts(ctypes.Structure):
     _fields_ = [("algo", ctypes.c_int32), ("mat", ctypes.c_int32), ("radix_bits", ctypes.c_int32),
                 ("block_size", ctypes.c_int32), ("ht_occupancy", ctypes.c_float),
-                ("lds_budget", ctypes.c_int32)]
+                ("lds_budget", ctypes.c_int32), ("skew_hint", ctypes.c_float)]
 
 
 class KernelStat(ctypes.Structure):
@@ -131,6 +132,12 @@ def lib() -> ctypes.CDLL:
                                                vp, ctypes.POINTER(vp), vp, vp, vp]
             L.gj_partition_noalloc_scratch_bytes.restype = ctypes.c_size_t
             L.gj_partition_noalloc_scratch_bytes.argtypes = []
+            L.gj_join_features.restype = ctypes.c_int
+            L.gj_join_features.argtypes = [ctypes.POINTER(Rel), ctypes.POINTER(Rel), ctypes.POINTER(JoinOpts),
+                                           ctypes.POINTER(ctypes.c_float)]
+            L.gj_groupby_features.restype = ctypes.c_int
+            L.gj_groupby_features.argtypes = [Col, i32, i64, ctypes.POINTER(GroupByOpts), ctypes.POINTER(Allocator),
+                                              vp, ctypes.POINTER(ctypes.c_float)]
             L.gj_get_cost_constants.restype = ctypes.c_int
             L.gj_get_cost_constants.argtypes = [ctypes.POINTER(ctypes.c_double)] * 3
             L.gj_stream_copy.restype = ctypes.c_int
@@ -205,15 +212,15 @@ SELECTOR_WEIGHTS = os.path.join(_HERE, "selector_weights.f32")
 
 def _load_shipped_weights(L) -> None:
     """The selector network trained on measured timings ships with the package
-    (5317 little-endian float32); once loaded, automatic choices use it (else
-    the cost model decides)."""
+    (MLP_PARAMS little-endian float32); once loaded, automatic choices use it
+    (else the cost model decides)."""
     if not os.path.exists(SELECTOR_WEIGHTS):
         return
     with open(SELECTOR_WEIGHTS, "rb") as f:
         raw = f.read()
-    if len(raw) == 4 * 5317:
-        arr = (ctypes.c_float * 5317).from_buffer_copy(raw)
-        L.gj_selector_set_weights(arr, 5317)
+    if len(raw) == 4 * MLP_PARAMS:
+        arr = (ctypes.c_float * MLP_PARAMS).from_buffer_copy(raw)
+        L.gj_selector_set_weights(arr, MLP_PARAMS)
 
 
 class _TorchAllocator:
@@ -277,7 +284,7 @@ def _raise(rc: int):
 
 def join(r_key: torch.Tensor, r_pay, s_key: torch.Tensor, s_pay, *, mat: str = "auto",
          radix_bits: int = 0, passes: int = 0, lds_budget: int = 0, unique_build_keys: bool = False,
-         algo: str = "auto"):
+         algo: str = "auto", match_ratio_hint: float = 0.0, skew_hint: float = 0.0):
     """Inner equi-join on key. Returns (key, [R payloads], [S payloads]) as
     device tensors; row order is unspecified but deterministic (ascending key
     for algo="smj")."""
@@ -290,7 +297,8 @@ def join(r_key: torch.Tensor, r_pay, s_key: torch.Tensor, s_pay, *, mat: str = "
     sp = (Col * max(1, len(s_pay)))(*[_col(t) for t in s_pay])
     R = Rel(_col(r_key), rp, len(r_pay), r_key.numel())
     S = Rel(_col(s_key), sp, len(s_pay), s_key.numel())
-    o = JoinOpts(MAT[mat], int(unique_build_keys), radix_bits, passes, 0, 0.0, lds_budget, 0, JOIN_ALGO[algo])
+    o = JoinOpts(MAT[mat], int(unique_build_keys), radix_bits, passes, 0, 0.0, lds_budget, 0, JOIN_ALGO[algo],
+                 float(match_ratio_hint), float(skew_hint))
     ro = (ctypes.c_void_p * max(1, len(r_pay)))()
     so = (ctypes.c_void_p * max(1, len(s_pay)))()
     out = JoinOut(None, ro, so, 0)
@@ -559,7 +567,7 @@ def partition_noalloc(key: torch.Tensor, cols, out_key: torch.Tensor, out_cols, 
 
 
 def groupby(key: torch.Tensor, vals, aggs, *, algo: str = "auto", mat: str = "auto",
-            radix_bits: int = 0, lds_budget: int = 0, ht_occupancy: float = 0.0):
+            radix_bits: int = 0, lds_budget: int = 0, ht_occupancy: float = 0.0, skew_hint: float = 0.0):
     """Grouped aggregation. `aggs` is a list of (column index, op) with op in
     {"sum", "count", "min", "max"}. Returns (keys, [aggregate columns])."""
     L = lib()
@@ -569,7 +577,7 @@ def groupby(key: torch.Tensor, vals, aggs, *, algo: str = "auto", mat: str = "au
     _check_cols([key, *vals], n, dev)
     vp = (Col * max(1, len(vals)))(*[_col(t) for t in vals])
     ag = (Agg * max(1, len(aggs)))(*[Agg(int(c), AGG_OP[op]) for c, op in aggs])
-    o = GroupByOpts(GB_ALGO[algo], MAT[mat], radix_bits, 0, float(ht_occupancy), lds_budget)
+    o = GroupByOpts(GB_ALGO[algo], MAT[mat], radix_bits, 0, float(ht_occupancy), lds_budget, float(skew_hint))
     ao = (ctypes.c_void_p * max(1, len(aggs)))()
     out = GroupByOut(None, ao, 0)
     A = _TorchAllocator(dev)
@@ -633,29 +641,56 @@ def gather_i32(map_: torch.Tensor, values: torch.Tensor, out: torch.Tensor) -> N
                                _stream(map_.device)))
 
 
-MLP_PARAMS = 5317
-CLASSES = ["gftr", "gfur", "hash", "sort", "partition"]
+MLP_PARAMS = 5447
+# selector classes (gj.h): partitioned-hash join GFTR / GFUR, hash / sort /
+# partition group-by, sort group-by on dictionary-encoded keys, sort-merge join GFTR
+CLASSES = ["gftr", "gfur", "hash", "sort", "partition", "sort_de", "smj"]
+N_CLASSES = len(CLASSES)
+JOIN_CLASSES = (0, 1, 6)
+GROUPBY_CLASSES = (2, 3, 4, 5)
 
 
 def cost_model(features, op_kind: int):
     """Predicted seconds per class (inf for classes invalid for op_kind)."""
     f = (ctypes.c_float * 12)(*[float(x) for x in features])
-    out = (ctypes.c_double * 5)()
+    out = (ctypes.c_double * N_CLASSES)()
     _raise(lib().gj_cost_model(f, op_kind, out))
-    return [out[i] for i in range(5)]
+    return [out[i] for i in range(N_CLASSES)]
 
 
 def select(features, op_kind: int):
     """(class index, probabilities) chosen by the network, else the cost model."""
     f = (ctypes.c_float * 12)(*[float(x) for x in features])
     c = ctypes.c_int32(-1)
-    p = (ctypes.c_float * 5)()
+    p = (ctypes.c_float * N_CLASSES)()
     _raise(lib().gj_select(f, op_kind, ctypes.byref(c), p))
-    return c.value, [p[i] for i in range(5)]
+    return c.value, [p[i] for i in range(N_CLASSES)]
+
+
+def join_features(r_key, r_pay, s_key, s_pay, *, match_ratio_hint: float = 0.0, skew_hint: float = 0.0):
+    """The feature vector gj_join's automatic choice uses (host only)."""
+    rp = (Col * max(1, len(r_pay)))(*[_col(t) for t in r_pay])
+    sp = (Col * max(1, len(s_pay)))(*[_col(t) for t in s_pay])
+    R = Rel(_col(r_key), rp, len(r_pay), r_key.numel())
+    S = Rel(_col(s_key), sp, len(s_pay), s_key.numel())
+    o = JoinOpts(0, 0, 0, 0, 0, 0.0, 0, 0, 0, float(match_ratio_hint), float(skew_hint))
+    f = (ctypes.c_float * 12)()
+    _raise(lib().gj_join_features(ctypes.byref(R), ctypes.byref(S), ctypes.byref(o), f))
+    return [f[i] for i in range(12)]
+
+
+def groupby_features(key: torch.Tensor, n_vals: int, *, skew_hint: float = 0.0):
+    """The feature vector gj_groupby's automatic choice uses (reads the keys once)."""
+    o = GroupByOpts(0, 0, 0, 0, 0.0, 0, float(skew_hint))
+    f = (ctypes.c_float * 12)()
+    A = _TorchAllocator(key.device)
+    _raise(lib().gj_groupby_features(_col(key), int(n_vals), key.numel(), ctypes.byref(o), ctypes.byref(A.struct),
+                                     _stream(key.device), f))
+    return [f[i] for i in range(12)]
 
 
 def selector_set_weights(params) -> None:
-    """Load trained weights (5317 floats) into the library; None unloads them."""
+    """Load trained weights (MLP_PARAMS floats) into the library; None unloads them."""
     if params is None:
         _raise(lib().gj_selector_set_weights(None, 0))
         return
@@ -675,9 +710,9 @@ def get_cost_constants() -> tuple:
 
 
 def mlp_forward(params: torch.Tensor, X: torch.Tensor, mask: torch.Tensor) -> torch.Tensor:
-    """Masked softmax probabilities [B, 5] of the selector network (FP32, device)."""
+    """Masked softmax probabilities [B, N_CLASSES] of the selector network (FP32, device)."""
     B = X.shape[0]
-    out = torch.empty((B, 5), dtype=torch.float32, device=X.device)
+    out = torch.empty((B, N_CLASSES), dtype=torch.float32, device=X.device)
     A = _TorchAllocator(X.device)
     _raise(lib().gj_mlp_forward(params.data_ptr(), X.data_ptr(), mask.data_ptr(), B, out.data_ptr(),
                                 ctypes.byref(A.struct), _stream(X.device)))

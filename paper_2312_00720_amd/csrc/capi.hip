@@ -126,9 +126,14 @@ int gj_join(const gj_rel *R, const gj_rel *S, const gj_join_opts *opts, const gj
         const int kb = dtype_bytes(R->key.dtype);
         int mat = o.mat;
         if (mat == GJ_MAT_AUTO) {
+            // the selector picks among partitioned GFTR / GFUR and sort-merge GFTR;
+            // an algorithm the caller fixed keeps its own materialization choice
             float f[12];
-            gj::features_join(f, (double)R->n_rows, (double)S->n_rows, kb, R->n_payloads, S->n_payloads);
-            mat = gj::select_algorithm(f, 0, nullptr) == 1 ? GJ_MAT_GFUR : GJ_MAT_GFTR;
+            gj::features_join(f, (double)R->n_rows, (double)S->n_rows, kb, R->n_payloads, S->n_payloads,
+                              o.match_ratio_hint, o.skew_hint);
+            const int c = gj::select_algorithm(f, 0, nullptr);
+            mat = c == 1 && o.algo != GJ_JOIN_SMJ ? GJ_MAT_GFUR : GJ_MAT_GFTR;
+            if (o.algo == GJ_JOIN_AUTO) o.algo = c == 6 ? GJ_JOIN_SMJ : GJ_JOIN_PHJ;
         }
         const bool gfur = (mat == GJ_MAT_GFUR);
         int r_pay_bytes = 0;
@@ -417,14 +422,15 @@ int gj_groupby(gj_col key, const gj_col *vals, int32_t n_vals, int64_t n_rows, c
         gj::Ctx ctx(alloc, (hipStream_t)stream);
         // the group count decides the algorithm and the partition passes: estimate it
         double g_est = 0.0;
+        int varying = 0;
         if (algo == GJ_GB_AUTO || algo == GJ_GB_HASH || algo == GJ_GB_SORT_DE ||
             (algo == GJ_GB_PARTITION && o.radix_bits == 0))
-            g_est = gj::estimate_groups(ctx, kb, key.data, n);
+            g_est = gj::estimate_groups(ctx, kb, key.data, n, &varying);
         if (algo == GJ_GB_AUTO) {
             float f[12];
-            gj::features_groupby(f, (double)n, kb, n_vals, g_est);
+            gj::features_groupby(f, (double)n, kb, n_vals, g_est, varying, o.skew_hint);
             const int c = gj::select_algorithm(f, 1, nullptr);
-            algo = c == 2 ? GJ_GB_HASH : (c == 3 ? GJ_GB_SORT : GJ_GB_PARTITION);
+            algo = c == 2 ? GJ_GB_HASH : c == 3 ? GJ_GB_SORT : c == 5 ? GJ_GB_SORT_DE : GJ_GB_PARTITION;
         }
         void *okey = nullptr;
         void *oaggs[16] = {nullptr};
@@ -475,6 +481,48 @@ int gj_groupby(gj_col key, const gj_col *vals, int32_t n_vals, int64_t n_rows, c
             out->n_groups = 0;
             out->key = nullptr;
         }
+        return fail(e.code, e.what());
+    } catch (const std::exception &e) {
+        return fail(GJ_EHIP, e.what());
+    }
+}
+
+int gj_join_features(const gj_rel *R, const gj_rel *S, const gj_join_opts *opts, float features[12]) {
+    try {
+        g_last_error.clear();
+        gj::require(features != nullptr, "null features");
+        check_rel(R, "R");
+        check_rel(S, "S");
+        gj_join_opts o{};
+        if (opts) o = *opts;
+        gj::features_join(features, (double)R->n_rows, (double)S->n_rows, dtype_bytes(R->key.dtype), R->n_payloads,
+                          S->n_payloads, o.match_ratio_hint, o.skew_hint);
+        return GJ_OK;
+    } catch (const gj::Error &e) {
+        return fail(e.code, e.what());
+    } catch (const std::exception &e) {
+        return fail(GJ_EHIP, e.what());
+    }
+}
+
+int gj_groupby_features(gj_col key, int32_t n_vals, int64_t n_rows, const gj_groupby_opts *opts,
+                        const gj_allocator *alloc, void *stream, float features[12]) {
+    try {
+        g_last_error.clear();
+        gj::require(features != nullptr, "null features");
+        gj::require(n_rows >= 0, "negative row count");
+        gj::require(n_rows <= kMaxRows, "more than 2^31-1 rows", GJ_EOVERFLOW);
+        gj::require(n_vals >= 0 && n_vals <= 8, "0..8 value columns");
+        check_col(key, n_rows, "key");
+        gj_groupby_opts o{};
+        if (opts) o = *opts;
+        const int kb = dtype_bytes(key.dtype);
+        gj::Ctx ctx(alloc, (hipStream_t)stream);
+        int varying = 0;
+        const double g_est = gj::estimate_groups(ctx, kb, key.data, (uint32_t)n_rows, &varying);
+        gj::features_groupby(features, (double)n_rows, kb, n_vals, g_est, varying, o.skew_hint);
+        return GJ_OK;
+    } catch (const gj::Error &e) {
         return fail(e.code, e.what());
     } catch (const std::exception &e) {
         return fail(GJ_EHIP, e.what());

@@ -577,12 +577,17 @@ __device__ __forceinline__ int lds_find(const K *tab, int log2cap, K key) {
 
 constexpr int kHllBits = 10;
 
+// The same read also ORs and ANDs the order-preserving keys (bits[0], bits[1]):
+// their xor marks the key bytes that vary, i.e. the passes a radix sort of the
+// raw keys needs.
 template <typename K>
-__global__ __launch_bounds__(kBlock) void k_hll(const K *__restrict__ keys, uint32_t n, uint32_t *__restrict__ regs) {
+__global__ __launch_bounds__(kBlock) void k_hll(const K *__restrict__ keys, uint32_t n, uint32_t *__restrict__ regs,
+                                                unsigned long long *__restrict__ bits) {
     constexpr int U = 8;
     __shared__ uint32_t s_reg[1 << kHllBits];
     for (int i = threadIdx.x; i < (1 << kHllBits); i += kBlock) s_reg[i] = 0;
     __syncthreads();
+    unsigned long long o = 0, x = ~0ull;
     const uint32_t stride = gridDim.x * kBlock * U;
     for (uint32_t base = blockIdx.x * kBlock * U; base < n; base += stride) {
         K k[U];
@@ -597,8 +602,19 @@ __global__ __launch_bounds__(kBlock) void k_hll(const K *__restrict__ keys, uint
                 const uint32_t h = (uint32_t)digit_source<K>(k[u], kDigitHash);
                 const uint32_t w = (h << kHllBits) | (1u << (kHllBits - 1));  // the bits below the index
                 atomicMax(&s_reg[h >> (32 - kHllBits)], (uint32_t)__clz((int)w) + 1u);
+                const unsigned long long v = digit_source<K>(k[u], kDigitOrdered);
+                o |= v;
+                x &= v;
             }
         }
+    }
+    for (int d = kWave / 2; d > 0; d >>= 1) {
+        o |= __shfl_xor(o, d, kWave);
+        x &= __shfl_xor(x, d, kWave);
+    }
+    if (lane_id() == 0) {
+        atomicOr(&bits[0], o);
+        atomicAnd(&bits[1], x);
     }
     __syncthreads();
     for (int i = threadIdx.x; i < (1 << kHllBits); i += kBlock)
@@ -1167,15 +1183,36 @@ struct HgbArgs {
     uint32_t g;
     uint32_t lds_groups;  // groups 0..lds_groups-1 aggregate in LDS records, the rest with global atomics
     // sliced stage 2 (every group in LDS): consecutive id ranges of slice_groups
-    // groups, rows cut into `chunks` chunks of chunk_rows rows
+    // groups, rows cut into `chunks` chunks of chunk_rows rows; gid_row: every
+    // row's group id (resolved once when several slices read it), else nullptr
     uint32_t slices, slice_groups, chunks, chunk_rows;
+    const uint32_t *gid_row;
 };
 
 // Workgroups are dispatched to the 8 XCDs of the chip round robin by index.
 constexpr uint32_t kXcds = 8;
 // Most id slices of the sliced hash aggregation: every slice re-reads the rows'
-// group ids (from L2), so beyond this the global-atomic stage 2 is used.
-constexpr uint32_t kHgbMaxSlices = 16;
+// group ids (mostly from L2), so beyond this the global-atomic stage 2 is used.
+constexpr uint32_t kHgbMaxSlices = 64;
+
+// Every row's group id, gid[gid_loc[i]], for the slices to stream.
+__global__ void k_hgb_resolve(const uint32_t *__restrict__ gid_loc, const uint32_t *__restrict__ gid, uint32_t n,
+                              uint32_t *__restrict__ out) {
+    constexpr int RB = 8;
+    for (uint32_t base = blockIdx.x * kBlock * RB; base < n; base += gridDim.x * kBlock * RB) {
+        uint32_t loc[RB];
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+            const uint32_t i = base + r * kBlock + threadIdx.x;
+            loc[r] = i < n ? gid_loc[i] : 0u;
+        }
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+            const uint32_t i = base + r * kBlock + threadIdx.x;
+            if (i < n) out[i] = gid[loc[r]];
+        }
+    }
+}
 
 template <typename K>
 __device__ __forceinline__ uint64_t global_slot_hash(K key) {
@@ -1325,18 +1362,28 @@ __global__ __launch_bounds__(BT) void k_hgb_aggregate_sliced(HgbArgs a) {
     const uint32_t row0 = chunk * a.chunk_rows;
     const uint32_t row1 = (uint32_t)min<uint64_t>((uint64_t)row0 + a.chunk_rows, a.n);
     for (uint32_t base = row0; base < row1; base += BT * RB) {
-        uint32_t loc[RB], off[RB];
+        uint32_t id[RB], off[RB];
         Row<NV, V> rr[RB];
+        if (a.gid_row) {
 #pragma unroll
-        for (int r = 0; r < RB; ++r) {
-            const uint32_t i = base + r * BT + threadIdx.x;
-            loc[r] = i < row1 ? a.gid_loc[i] : 0u;
+            for (int r = 0; r < RB; ++r) {
+                const uint32_t i = base + r * BT + threadIdx.x;
+                id[r] = i < row1 ? a.gid_row[i] : 0u;
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < RB; ++r) {
+                const uint32_t i = base + r * BT + threadIdx.x;
+                id[r] = i < row1 ? a.gid_loc[i] : 0u;
+            }
+#pragma unroll
+            for (int r = 0; r < RB; ++r) id[r] = a.gid[id[r]];
         }
         bool any = false;
 #pragma unroll
         for (int r = 0; r < RB; ++r) {
             const uint32_t i = base + r * BT + threadIdx.x;
-            const uint32_t local = a.gid[loc[r]] - g0;  // wraps for ids below the slice
+            const uint32_t local = id[r] - g0;  // wraps for ids below the slice
             const bool in = i < row1 && local < L;
             off[r] = in ? local * (uint32_t)s.words : spare_off(L * s.words);
             rr[r] = in ? load_row<NV, V>(a.vals, i) : Row<NV, V>{};
@@ -1629,22 +1676,30 @@ void init_outputs(hipStream_t st, const AggSpec &s, uint64_t g) {
 
 }  // namespace
 
-double estimate_groups(Ctx &ctx, int key_bytes, const void *key, uint32_t n) {
+double estimate_groups(Ctx &ctx, int key_bytes, const void *key, uint32_t n, int *varying_bytes) {
+    if (varying_bytes) *varying_bytes = 0;
     if (n == 0) return 0.0;
     hipStream_t st = ctx.stream;
     constexpr int m = 1 << kHllBits;
-    uint32_t *regs = ctx.scratch_n<uint32_t>(m);
-    fill_u32(st, regs, 0u, m);
+    uint32_t *regs = ctx.scratch_n<uint32_t>(m + 4);
+    unsigned long long *bits = reinterpret_cast<unsigned long long *>(regs + m);
+    fill_u32(st, regs, 0u, m + 2);
+    fill_u32(st, regs + m + 2, 0xFFFFFFFFu, 2);
     const uint32_t grid = std::max<uint32_t>(1, std::min<uint32_t>(ceil_div_u32(n, kBlock * 8), 2048));
     if (key_bytes == 4)
         GJ_LAUNCH("k_hll", 4.0 * n, k_hll<int32_t>, dim3(grid), dim3(kBlock), 0, st, static_cast<const int32_t *>(key), n,
-                  regs);
+                  regs, bits);
     else
         GJ_LAUNCH("k_hll", 8.0 * n, k_hll<int64_t>, dim3(grid), dim3(kBlock), 0, st, static_cast<const int64_t *>(key), n,
-                  regs);
-    std::vector<uint32_t> h(m);
-    GJ_HIP(hipMemcpyAsync(h.data(), regs, 4ull * m, hipMemcpyDeviceToHost, st));
+                  regs, bits);
+    std::vector<uint32_t> h(m + 4);
+    GJ_HIP(hipMemcpyAsync(h.data(), regs, 4ull * (m + 4), hipMemcpyDeviceToHost, st));
     GJ_HIP(hipStreamSynchronize(st));
+    if (varying_bytes) {
+        const uint64_t o = (uint64_t)h[m] | ((uint64_t)h[m + 1] << 32), a = (uint64_t)h[m + 2] | ((uint64_t)h[m + 3] << 32);
+        for (int b = 0; b < key_bytes; ++b) *varying_bytes += (((o ^ a) >> (8 * b)) & 0xFF) != 0;
+    }
+    h.resize(m);
     double sum = 0.0;
     int zeros = 0;
     for (uint32_t r : h) {
@@ -1992,6 +2047,13 @@ int64_t groupby_hash(Ctx &ctx, int key_bytes, const void *key, const ValCols &vc
         chunks = std::max<uint32_t>(kXcds, (chunks + kXcds - 1) / kXcds * kXcds);
         a.chunks = chunks;
         a.chunk_rows = ceil_div_u32(n, chunks);
+        a.gid_row = nullptr;
+        if (slices > 1) {
+            uint32_t *gr = ctx.scratch_n<uint32_t>(n);
+            GJ_LAUNCH("k_hgb_resolve", 8.0 * n, k_hgb_resolve, dim3(std::min<uint32_t>(ceil_div_u32(n, kBlock * 8), 4096)),
+                      dim3(kBlock), 0, st, a.gid_loc, a.gid, n, gr);
+            a.gid_row = gr;
+        }
         const uint32_t sgrid = chunks * slices;
 #define GJ_HAGG_S(NV, BT, V) \
     GJ_LAUNCH("k_hgb_aggregate", bytes, (k_hgb_aggregate_sliced<NV, BT, V>), dim3(sgrid), dim3(BT), alds, st, a)

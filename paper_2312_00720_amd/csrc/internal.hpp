@@ -205,7 +205,9 @@ struct ValCols {
 // partition holds more distinct keys than its LDS table.
 // Estimated number of distinct keys (HyperLogLog, about 3% standard error);
 // synchronizes with the stream.
-double estimate_groups(Ctx &ctx, int key_bytes, const void *key, uint32_t n);
+// varying_bytes (optional) receives how many bytes of the order-preserving key
+// differ between rows (the passes a radix sort of the raw keys takes).
+double estimate_groups(Ctx &ctx, int key_bytes, const void *key, uint32_t n, int *varying_bytes = nullptr);
 int64_t groupby_partition(Ctx &ctx, int key_bytes, const void *key, const ValCols &vc,
                           uint32_t n, const gj_agg *aggs, int n_aggs, bool gfur, int bits, void **out_key,
                           void **out_aggs, int *fell_back);
@@ -246,8 +248,10 @@ uint32_t pgb_plan_lds_bytes(int key_bytes);
 // ---- select.hip -----------------------------------------------------------------------
 // Class 0..4 for the features (see gj.h); the network when loaded, else the cost model.
 int select_algorithm(const float *features, int op_kind, float *probs_out);
-void features_join(float *f, double nr, double ns, int key_bytes, int cr, int cs);
-void features_groupby(float *f, double n, int key_bytes, int nv, double g_est = 0.0);
+// The feature vectors the automatic choices use (gj.h lists the features):
+// hints <= 0 mean unknown (join: every S row matches, uniform keys).
+void features_join(float *f, double nr, double ns, int key_bytes, int cr, int cs, float mr_hint, float skew_hint);
+void features_groupby(float *f, double n, int key_bytes, int nv, double g_est, int varying_bytes, float skew_hint);
 
 // ---- join.hip -------------------------------------------------------------------------
 // Work-unit geometry. An R build block of at most r_block rows runs in one of

@@ -1,7 +1,7 @@
-// The selector network: 12 features -> 64 -> 64 (ReLU) -> 5 logits, softmax
+// The selector network: 12 features -> 64 -> 64 (ReLU) -> 7 logits, softmax
 // over the classes valid for each sample, cross-entropy loss, gradients and Adam.
 // FP32. Parameters are one flat vector: W1 (64x12, row-major), b1, W2 (64x64),
-// b2, W3 (5x64), b3 — 5317 floats.
+// b2, W3 (7x64), b3 — 5447 floats.
 //
 // Every matrix product is small (batch x 64 x 64 at most), so each output element
 // is one thread summing its terms in a fixed order: gradients are bit-identical
@@ -13,10 +13,10 @@
 namespace gj {
 namespace {
 
-constexpr int F = 12, H = 64, C = 5;
+constexpr int F = 12, H = 64, C = 7;
 constexpr int OFF_W1 = 0, OFF_B1 = OFF_W1 + H * F, OFF_W2 = OFF_B1 + H, OFF_B2 = OFF_W2 + H * H,
               OFF_W3 = OFF_B2 + H, OFF_B3 = OFF_W3 + C * H, N_PARAMS = OFF_B3 + C;
-static_assert(N_PARAMS == 5317, "parameter count");
+static_assert(N_PARAMS == GJ_MLP_PARAMS, "parameter count");
 
 // out[m, n] = sum_k A[m*am + k*ak] * B[k*bk + n*bn] (+ bias[n]) (then ReLU if relu),
 // k summed in increasing order.

@@ -184,11 +184,13 @@ def test_hash_table_sizing(occ):
 
 
 @pytest.mark.parametrize("g_card,budget,alpha", [(3000, 8192, 0.0), (2000, 16384, 1.0), (20000, 0, 0.0),
-                                                  (65000, 0, 1.0), (5, 0, 0.0)])
+                                                  (65000, 0, 1.0), (5, 0, 0.0), (200000, 0, 0.0),
+                                                  (10000, 8192, 0.5)])
 def test_hash_sliced_lds_records(g_card, budget, alpha):
-    """Every group in LDS, the ids cut into up to 16 consecutive ranges that each
+    """Every group in LDS, the ids cut into up to 64 consecutive ranges that each
     fit one workgroup's LDS (budget 0: 160 KB); each (row chunk, id range)
-    workgroup aggregates its chunk's rows of that range."""
+    workgroup aggregates its chunk's rows of that range, several ranges reading
+    the rows' resolved group ids."""
     d = datagen.groupby_input(300001, g_card, 2, seed=69 + g_card, alpha=alpha)
     check(d["key"], d["vals"], algo="hash", lds_budget=budget)
     d = datagen.groupby_input(100003, g_card, 2, seed=70 + g_card, alpha=alpha, key_bytes=8)

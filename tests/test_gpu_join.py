@@ -183,14 +183,18 @@ def test_work_unit_overflow_is_an_error():
     import paper_2312_00720_amd as gj
     from gpu_util import say
     say("join unit overflow: 2^24 x 2^26 even keys, radix_bits=1, lds_budget=64")
+    import gc
     rk = torch.arange(0, 1 << 25, 2, dtype=torch.int32, device="cuda")
     sk = torch.zeros(1 << 26, dtype=torch.int32, device="cuda")
+    gc.collect()
+    torch.cuda.synchronize()
     before = torch.cuda.memory_allocated()
     with pytest.raises(gj.GJError) as e:
         gj.join(rk, [], sk, [], mat="gftr", radix_bits=1, lds_budget=64)
     assert e.value.code == -6 and "work units" in str(e.value)
+    gc.collect()
     torch.cuda.synchronize()
-    assert torch.cuda.memory_allocated() == before
+    assert torch.cuda.memory_allocated() <= before
 
 
 @pytest.mark.parametrize("mat", ["gftr", "gfur"])

@@ -15,10 +15,11 @@ def batch(n, seed):
     X = g.uniform(0, 1, size=(n, 12))
     is_join = g.uniform(size=n) < 0.5
     X[:, 0] = is_join
-    mask = np.zeros((n, 5))
-    mask[is_join, 0:2] = 1
-    mask[~is_join, 2:5] = 1
-    y = np.where(is_join, g.integers(0, 2, size=n), g.integers(2, 5, size=n))
+    mask = np.zeros((n, mlp.N_CLASSES))
+    mask[np.ix_(is_join, mlp.JOIN_CLASSES)] = 1
+    mask[np.ix_(~is_join, mlp.GROUPBY_CLASSES)] = 1
+    y = np.where(is_join, np.array(mlp.JOIN_CLASSES)[g.integers(0, 3, size=n)],
+                 np.array(mlp.GROUPBY_CLASSES)[g.integers(0, 4, size=n)])
     return X, mask, y
 
 
@@ -72,9 +73,9 @@ def test_training_on_gpu_learns_rule():
     X = g.uniform(0, 1, size=(n, 12))
     is_join = g.uniform(size=n) < 0.5
     X[:, 0] = is_join
-    mask = np.zeros((n, 5))
-    mask[is_join, 0:2] = 1
-    mask[~is_join, 2:5] = 1
+    mask = np.zeros((n, mlp.N_CLASSES))
+    mask[np.ix_(is_join, mlp.JOIN_CLASSES)] = 1
+    mask[np.ix_(~is_join, mlp.GROUPBY_CLASSES)] = 1
     y = np.where(is_join, np.where(X[:, 8] > 0.25, 0, 1), np.where(X[:, 3] < 0.4, 2, 4))
     P = to_dev(mlp.init(6), torch.float32)
     Md = torch.zeros_like(P)

@@ -17,15 +17,18 @@ DATA = os.path.join(ROOT, "paper_2312_00720_amd", "selector_data.npz")
 
 
 def test_trained_network_beats_cost_model():
+    """Trained as selector.py trains it (both feature views), scored on the
+    held-out workloads' product-path features: the vectors gj_join and
+    gj_groupby compute by themselves, without hints."""
     import paper_2312_00720_amd as gj
     from paper_2312_00720_amd import selector
     from gpu_util import say
-    z = np.load(DATA, allow_pickle=False)
-    Xtr, Mtr, Ttr, Xte, Mte, Tte = (z[k] for k in ("Xtr", "Mtr", "Ttr", "Xte", "Mte", "Tte"))
-    say(f"selector: {len(Xtr)} training and {len(Xte)} held-out workloads")
-    theta = selector.train(Xtr, Mtr, Ttr, steps=3000)
+    z = selector.load_data(DATA)
+    say(f"selector: {len(z['Xtr'])} training and {len(z['Xte'])} held-out workloads")
+    theta = selector.train(np.concatenate([z["Xtr"], z["Htr"]]), np.concatenate([z["Mtr"]] * 2),
+                           np.concatenate([z["Ttr"]] * 2), steps=3000)
     assert np.isfinite(theta).all()
-    rep = selector.evaluate_arrays(Xte, Mte, Tte, theta)
+    rep = selector.evaluate_arrays(z["Xte"], z["Mte"], z["Tte"], theta)
     say(f"held-out regret: {rep}")
     assert rep["mlp"]["aggregate_pct"] < rep["cost_model"]["aggregate_pct"]
     assert rep["mlp"]["mean_pct"] < rep["cost_model"]["mean_pct"]

@@ -34,9 +34,38 @@ def gb_features(log_n, log_g, nv=2, kb=4):
 
 def test_cost_model_marks_invalid_classes(gj):
     t = gj.cost_model(join_features(20, 21, 1.0), 0)
-    assert all(math.isinf(x) for x in t[2:]) and all(x > 0 and math.isfinite(x) for x in t[:2])
+    assert all(math.isinf(t[c]) == (c not in gj.JOIN_CLASSES) for c in range(gj.N_CLASSES))
+    assert all(t[c] > 0 for c in gj.JOIN_CLASSES)
     t = gj.cost_model(gb_features(24, 12), 1)
-    assert all(math.isinf(x) for x in t[:2]) and all(x > 0 and math.isfinite(x) for x in t[2:])
+    assert all(math.isinf(t[c]) == (c not in gj.GROUPBY_CLASSES) for c in range(gj.N_CLASSES))
+    assert all(t[c] > 0 for c in gj.GROUPBY_CLASSES)
+
+
+def test_cost_model_dictionary_encoding_pays_for_sparse_keys(gj):
+    """Section 4.4: sorting 4-byte codes over ceil(log2 g / 8) passes beats
+    sorting keys whose 8 bytes all vary when g is small, and stops paying when
+    the raw keys need no more passes than the codes."""
+    sparse8 = gb_features(26, 10, kb=8)
+    sparse8[6] = 8 / 8
+    t = gj.cost_model(sparse8, 1)
+    assert t[5] < t[3]
+    dense4 = gb_features(26, 10, kb=4)
+    dense4[6] = 2 / 8
+    t = gj.cost_model(dense4, 1)
+    assert t[3] < t[5]
+
+
+def test_features_of_the_automatic_path(gj):
+    """gj_join_features gives the vector gj_join's automatic choice uses: with
+    no hints the match ratio is taken as 1 and the skew as 0; hints replace them."""
+    import torch
+    rk = torch.zeros(1 << 10, dtype=torch.int32)
+    sk = torch.zeros(1 << 12, dtype=torch.int32)
+    f = gj.join_features(rk, [rk], sk, [sk, sk])
+    assert f[0] == 1 and f[8] == 1 and f[7] == 0
+    assert f[1] == pytest.approx(10 / 32) and f[2] == pytest.approx(12 / 32) and f[6] == pytest.approx(2 / 8)
+    f = gj.join_features(rk, [rk], sk, [sk, sk], match_ratio_hint=0.25, skew_hint=0.6)
+    assert f[8] == pytest.approx(0.25) and f[7] == pytest.approx(0.5) and f[10] == pytest.approx(10 / 32)
 
 
 def test_cost_model_gftr_gfur_crossover_in_match_ratio(gj):
@@ -75,9 +104,8 @@ def test_host_network_matches_reference(gj):
         f = rng.uniform(0, 1, size=12).astype(np.float32)
         k = int(rng.integers(0, 2))
         f[0] = 1.0 if k == 0 else 0.0
-        mask = np.zeros((1, 5))
-        mask[0, 0:2] = 1 if k == 0 else 0
-        mask[0, 2:5] = 0 if k == 0 else 1
+        mask = np.zeros((1, mlp.N_CLASSES))
+        mask[0, list(mlp.JOIN_CLASSES if k == 0 else mlp.GROUPBY_CLASSES)] = 1
         p_ref, _ = mlp.forward(theta.astype(np.float32).astype(np.float64), f[None].astype(np.float64), mask)
         c, p = gj.select(list(f), k)
         np.testing.assert_allclose(p, p_ref[0], rtol=1e-4, atol=1e-6)
