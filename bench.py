@@ -517,12 +517,67 @@ def bench_gbbatch(args, copy_gbs) -> int:
     return 0
 
 
+def bench_sweep(args, copy_gbs) -> int:
+    """The join sweeps of Section 5.1, one JSON line per point, every point run
+    with partitioned hash join and sort-merge join under GFTR and GFUR:
+      m2n:      |R| = |S| = 2^26, keys uniform over |K| in {2^23, 2^24, 2^25}
+                unique values, 2 int32 payload columns per side (many-to-many);
+      ratio:    |S| = 2^27 PK-FK, |R| = 2^21 .. 2^27, 2 payload columns per side;
+      payloads: |R| = |S| = 2^27 PK-FK, 1, 2, 4 or 8 payload columns per side."""
+    import torch
+    import datagen
+    import datagen.device as dd
+    import paper_2312_00720_amd as gj
+    algos = [("phj", "gftr"), ("phj", "gfur"), ("smj", "gftr"), ("smj", "gfur")]
+
+    def m2n_inputs(n, k, c, seed):
+        g = dd.generator(seed)
+        rk = torch.randint(0, k, (n,), generator=g, device="cuda", dtype=torch.int64).to(torch.int32)
+        sk = torch.randint(0, k, (n,), generator=g, device="cuda", dtype=torch.int64).to(torch.int32)
+        return {"r_key": rk, "s_key": sk, "r_pay": dd.payloads(g, n, c), "s_pay": dd.payloads(g, n, c)}
+
+    points = []
+    if args.sweep in ("all", "m2n"):
+        points += [("m2n", dict(n_r=1 << 26, n_s=1 << 26, c=2, k=1 << kk)) for kk in (23, 24, 25)]
+    if args.sweep in ("all", "ratio"):
+        points += [("ratio", dict(n_r=1 << lr, n_s=1 << 27, c=2)) for lr in (21, 23, 25, 27)]
+    if args.sweep in ("all", "payloads"):
+        points += [("payloads", dict(n_r=1 << 27, n_s=1 << 27, c=c)) for c in (1, 2, 4, 8)]
+    for name, pt in points:
+        if name == "m2n":
+            d = m2n_inputs(pt["n_r"], pt["k"], pt["c"], datagen.seed_for(1, 700 + pt["k"].bit_length()))
+        else:
+            d = dd.pk_fk_join(pt["n_r"], pt["n_s"], pt["c"], pt["c"],
+                              seed=datagen.seed_for(1, 800 + pt["n_r"].bit_length() + 40 * pt["c"]))
+        torch.cuda.synchronize()
+        res = {"sweep": name, **pt, "unit": "ms", "runs": {}}
+        for algo, mat in algos:
+            def step():
+                return gj.join(d["r_key"], d["r_pay"], d["s_key"], d["s_pay"], mat=mat, algo=algo)
+            out = step()
+            t_rows = out[0].numel()
+            del out
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                out = step()
+                del out
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) / args.steps * 1e3
+            res["runs"][f"{algo}-{mat}"] = {"ms": ms, "output_rows": t_rows, "tuples_per_s": t_rows / (ms / 1e3)}
+            log(f"sweep {name} {pt} {algo}-{mat}: {ms:.2f} ms, |T| = {t_rows}")
+        print(json.dumps(res), flush=True)
+        del d
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--mat", default="gftr", choices=["gftr", "gfur"])
+    ap.add_argument("--join-algo", default="phj", choices=["phj", "smj"], help="join: partitioned hash or sort-merge")
     ap.add_argument("--r-log2", type=int, default=27)
     ap.add_argument("--s-log2", type=int, default=28)
     ap.add_argument("--payloads", type=int, default=4)
@@ -533,7 +588,9 @@ def main() -> int:
     ap.add_argument("--radix-bits", type=int, default=0, help="join / group-by: partition bits (0 = automatic)")
     ap.add_argument("--lds-budget", type=int, default=0, help="join: max R rows per build block (0 = automatic)")
     ap.add_argument("--workload", default="join",
-                    choices=["join", "groupby", "batch", "gbbatch", "pipeline", "micro"])
+                    choices=["join", "groupby", "batch", "gbbatch", "pipeline", "micro", "sweep"])
+    ap.add_argument("--sweep", default="all", choices=["all", "m2n", "ratio", "payloads"],
+                    help="sweep workload: which join sweep of Section 5.1")
     ap.add_argument("--gather-log2", type=int, default=27, help="micro: gathered values")
     ap.add_argument("--pipe-s-log2", type=int, default=26, help="pipeline: log2 |S|")
     ap.add_argument("--instances", type=int, default=4096, help="batch: join instances")
@@ -573,6 +630,8 @@ def main() -> int:
         return bench_pipeline(args, copy_gbs)
     if args.workload == "micro":
         return bench_micro(args, copy_gbs)
+    if args.workload == "sweep":
+        return bench_sweep(args, copy_gbs)
 
     n_r, n_s, c = 1 << args.r_log2, 1 << args.s_log2, args.payloads
     log(f"generating |R|=2^{args.r_log2} |S|=2^{args.s_log2} payloads={c} key_bytes={args.key_bytes}")
@@ -582,7 +641,8 @@ def main() -> int:
     rk, rp, sk, sp = d["r_key"], d["r_pay"], d["s_key"], d["s_pay"]
 
     def step():
-        return gj.join(rk, rp, sk, sp, mat=args.mat, radix_bits=args.radix_bits, lds_budget=args.lds_budget)
+        return gj.join(rk, rp, sk, sp, mat=args.mat, radix_bits=args.radix_bits, lds_budget=args.lds_budget,
+                       algo=args.join_algo)
 
     n_out = None
     for i in range(args.warmup):
@@ -616,7 +676,7 @@ def main() -> int:
     ms = (t1 - t0) / args.steps * 1e3
     value = n_out / (ms / 1e3)
     default_join = (args.r_log2, args.s_log2, c, args.key_bytes, args.alpha, args.match_ratio, args.mat,
-                    args.radix_bits, args.lds_budget) == (27, 28, 4, 4, 0.0, 1.0, "gftr", 0, 0)
+                    args.radix_bits, args.lds_budget, args.join_algo) == (27, 28, 4, 4, 0.0, 1.0, "gftr", 0, 0, "phj")
     kern = {k: dict(v, ms_per_step=v["total_ms"] / args.steps,
                     gbs=(v["alg_bytes"] / (v["total_ms"] / 1e3) / 1e9) if v["total_ms"] > 0 else 0.0)
             for k, v in stats.items()}
@@ -656,7 +716,8 @@ def main() -> int:
         "config": {"workload": f"PK-FK join |R|=2^{args.r_log2} |S|=2^{args.s_log2}, "
                                f"{c}+{c} int32 payloads, {'int32' if args.key_bytes == 4 else 'int64'} keys, "
                                f"FK {'uniform' if args.alpha == 0 else f'zipf {args.alpha}'}, "
-                               f"mr={args.match_ratio:g}, {args.mat.upper()}",
+                               f"mr={args.match_ratio:g}, {args.mat.upper()}"
+                               + (", sort-merge join" if args.join_algo == "smj" else ""),
                    "n_r": n_r, "n_s": n_s, "payloads_per_side": c, "mat": args.mat,
                    "output_rows": n_out},
         "paper_throughput_rows_per_s": (n_r + n_s) / (ms / 1e3),

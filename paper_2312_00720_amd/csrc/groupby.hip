@@ -651,6 +651,7 @@ struct PgbArgs {
     uint32_t cap_units;     // units beyond this are not processed
     const uint64_t *out_base; // device: first output group of this call (nullptr = 0)
     uint32_t lds_bytes;     // > 0: table size and records chosen per partition within this LDS
+    uint32_t g_lo, g_hi;    // plans: only partitions with g_lo <= groups <= g_hi (two launches share them)
 };
 
 template <typename K>
@@ -967,6 +968,7 @@ __device__ __forceinline__ void pgb_unit(const PgbArgs &a, uint32_t u, uint64_t 
     const uint32_t g = a.goff[p + 1] - a.goff[p];  // group counts were scanned in place into offsets
     const uint64_t gb = out_base + a.goff[p];
     if (g == 0) return;
+    if (a.lds_bytes && (g < a.g_lo || g > a.g_hi)) return;  // the other launch of a plan takes it
     const K *__restrict__ keys = static_cast<const K *>(a.keys);
     const K *__restrict__ tk = static_cast<const K *>(a.tmp_keys);
     if (j == 0) {
@@ -1930,15 +1932,43 @@ void groupby_partition_segments(Ctx &ctx, int key_bytes, const void *key, const 
               (const uint32_t *)(gcnt + np), pl.next_base, (const uint32_t *)stat, (const uint32_t *)(ucnt + np),
               pl.status);
     const uint32_t grid = std::max<uint32_t>(1, std::min<uint32_t>(pl.cap_units, 4096));
-    const double bytes = (double)n * (key_bytes + 4.0 * n_vals + (gfur ? 4.0 : 0.0));
-    const uint32_t lds = pl.lds_bytes;
-#define GJ_PGB(K, NV) GJ_LAUNCH("k_pgb_aggregate", bytes, (k_pgb_aggregate<K, NV>), dim3(grid), dim3(kBlock), lds, st, a)
-    const int nvt = nv_tier(n_vals);
-    if (key_bytes == 4) {
-        if (nvt == 1) GJ_PGB(int32_t, 1); else if (nvt == 2) GJ_PGB(int32_t, 2); else if (nvt == 4) GJ_PGB(int32_t, 4); else GJ_PGB(int32_t, 8);
-    } else {
-        if (nvt == 1) GJ_PGB(int64_t, 1); else if (nvt == 2) GJ_PGB(int64_t, 2); else if (nvt == 4) GJ_PGB(int64_t, 4); else GJ_PGB(int64_t, 8);
+    // Two launches over the same units: partitions of at most small_g groups run
+    // with a small LDS (more workgroups per compute unit), the rest with the
+    // plan's LDS, which holds the largest discoverable partition. The LDS of a
+    // captured launch is fixed, and the group counts are only known on the device.
+    const uint32_t small_lds = 24u * 1024u;
+    uint32_t small_g = 0;
+    for (uint32_t x = 16; x <= kDiscoverCap; x += 16) {
+        const uint32_t tab = (1u << agg_table_log2(x)) * agg_slot_bytes(key_bytes) + 8u;
+        const uint32_t rec = ((x + 1) * (uint32_t)a.spec.words + kSpareWords) * 4u;
+        if (tab + rec + 8u > small_lds) break;
+        small_g = x;
     }
+    const double bytes = (double)n * (key_bytes + 4.0 * n_vals + (gfur ? 4.0 : 0.0));
+    uint32_t lds = pl.lds_bytes;
+#define GJ_PGB(K, NV) GJ_LAUNCH("k_pgb_aggregate", bytes, (k_pgb_aggregate<K, NV>), dim3(grid), dim3(kBlock), lds, st, a)
+#define GJ_PGB_ALL                                                                                          \
+    do {                                                                                                    \
+        const int nvt = nv_tier(n_vals);                                                                    \
+        if (key_bytes == 4) {                                                                               \
+            if (nvt == 1) GJ_PGB(int32_t, 1); else if (nvt == 2) GJ_PGB(int32_t, 2);                        \
+            else if (nvt == 4) GJ_PGB(int32_t, 4); else GJ_PGB(int32_t, 8);                                 \
+        } else {                                                                                            \
+            if (nvt == 1) GJ_PGB(int64_t, 1); else if (nvt == 2) GJ_PGB(int64_t, 2);                        \
+            else if (nvt == 4) GJ_PGB(int64_t, 4); else GJ_PGB(int64_t, 8);                                 \
+        }                                                                                                   \
+    } while (0)
+    if (small_g > 0) {
+        a.lds_bytes = lds = small_lds;
+        a.g_lo = 1;
+        a.g_hi = small_g;
+        GJ_PGB_ALL;
+    }
+    a.lds_bytes = lds = pl.lds_bytes;
+    a.g_lo = small_g + 1;
+    a.g_hi = 0xFFFFFFFFu;
+    GJ_PGB_ALL;
+#undef GJ_PGB_ALL
 #undef GJ_PGB
 }
 
