@@ -423,9 +423,13 @@ int gj_groupby(gj_col key, const gj_col *vals, int32_t n_vals, int64_t n_rows, c
         // the group count decides the algorithm and the partition passes: estimate it
         double g_est = 0.0;
         int varying = 0;
+        // a partition group-by (chosen, or possibly chosen) takes its first pass's
+        // histogram from the same read of the keys
+        const uint32_t *hist8 = nullptr;
+        const bool want_hist = algo == GJ_GB_AUTO || (algo == GJ_GB_PARTITION && o.radix_bits == 0);
         if (algo == GJ_GB_AUTO || algo == GJ_GB_HASH || algo == GJ_GB_SORT_DE ||
             (algo == GJ_GB_PARTITION && o.radix_bits == 0))
-            g_est = gj::estimate_groups(ctx, kb, key.data, n, &varying);
+            g_est = gj::estimate_groups(ctx, kb, key.data, n, &varying, want_hist ? &hist8 : nullptr);
         if (algo == GJ_GB_AUTO) {
             float f[12];
             gj::features_groupby(f, (double)n, kb, n_vals, g_est, varying, o.skew_hint);
@@ -460,7 +464,7 @@ int gj_groupby(gj_col key, const gj_col *vals, int32_t n_vals, int64_t n_rows, c
             }
             int fell_back = 0;
             g = gj::groupby_partition(ctx, kb, key.data, vcols, n, aggs, n_aggs, gfur, bits, &okey, oaggs,
-                                      &fell_back);
+                                      &fell_back, hist8);
             if (fell_back) algo = GJ_GB_HASH;  // too many distinct keys per partition
         }
         if (algo == GJ_GB_HASH)

@@ -157,12 +157,14 @@ __device__ __forceinline__ Row<NV, V> load_row(const ValSrc &vs, uint32_t row) {
     return r;
 }
 
+// Value of column c (uniform over the wave) of a row held in registers. A
+// branch on c == cc would let the optimizer index the row by c, which sends the
+// row to scratch memory; masks keep every access at a constant index.
 template <int NV, typename V>
 __device__ __forceinline__ V pick(const Row<NV, V> &r, int c) {
-    V x = r.v[0];
+    V x = 0;
 #pragma unroll
-    for (int cc = 1; cc < NV; ++cc)
-        if (cc == c) x = r.v[cc];
+    for (int cc = 0; cc < NV; ++cc) x |= r.v[cc] & -(V)(cc == c);
     return x;
 }
 
@@ -360,18 +362,17 @@ __device__ __forceinline__ Acc<NV, V> acc_wave_reduce(Acc<NV, V> x) {
     return x;
 }
 
+// Column c of an Acc in registers, selected by masks as pick() does.
 template <int NV, typename V>
 __device__ __forceinline__ void acc_pick(const Acc<NV, V> &x, int c, long long &sum, V &mn, V &mx) {
-    sum = x.sum[0];
-    mn = x.mn[0];
-    mx = x.mx[0];
+    sum = 0;
+    mn = 0;
+    mx = 0;
 #pragma unroll
-    for (int cc = 1; cc < NV; ++cc) {
-        if (cc == c) {
-            sum = x.sum[cc];
-            mn = x.mn[cc];
-            mx = x.mx[cc];
-        }
+    for (int cc = 0; cc < NV; ++cc) {
+        sum |= x.sum[cc] & -(long long)(cc == c);
+        mn |= x.mn[cc] & -(V)(cc == c);
+        mx |= x.mx[cc] & -(V)(cc == c);
     }
 }
 
@@ -579,29 +580,47 @@ constexpr int kHllBits = 10;
 
 // The same read also ORs and ANDs the order-preserving keys (bits[0], bits[1]):
 // their xor marks the key bytes that vary, i.e. the passes a radix sort of the
-// raw keys needs.
-template <typename K>
+// raw keys needs. With hist8, workgroup b reads chunk b (chunk_rows rows) and
+// also counts its rows per low 8 bits of the hash, the digit a single partition
+// pass of the partition-based group-by takes, so that pass reads no keys for
+// its histogram.
+template <typename K, bool HIST>
 __global__ __launch_bounds__(kBlock) void k_hll(const K *__restrict__ keys, uint32_t n, uint32_t *__restrict__ regs,
-                                                unsigned long long *__restrict__ bits) {
+                                                unsigned long long *__restrict__ bits, uint32_t chunk_rows,
+                                                uint32_t *__restrict__ hist8) {
     constexpr int U = 8;
     __shared__ uint32_t s_reg[1 << kHllBits];
+    __shared__ uint32_t s_cnt[HIST ? kWaves : 1][HIST ? 256 : 1];
     for (int i = threadIdx.x; i < (1 << kHllBits); i += kBlock) s_reg[i] = 0;
+    if constexpr (HIST)
+        for (int i = threadIdx.x; i < kWaves * 256; i += kBlock) (&s_cnt[0][0])[i] = 0;
     __syncthreads();
     unsigned long long o = 0, x = ~0ull;
-    const uint32_t stride = gridDim.x * kBlock * U;
-    for (uint32_t base = blockIdx.x * kBlock * U; base < n; base += stride) {
+    const int w = threadIdx.x / kWave;
+    uint32_t lo, hi, stride;
+    if constexpr (HIST) {
+        lo = blockIdx.x * chunk_rows;
+        hi = (uint32_t)min<uint64_t>((uint64_t)lo + chunk_rows, n);
+        stride = kBlock * U;
+    } else {
+        lo = blockIdx.x * kBlock * U;
+        hi = n;
+        stride = gridDim.x * kBlock * U;
+    }
+    for (uint32_t base = lo; base < hi; base += stride) {
         K k[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const uint32_t i = base + u * kBlock + threadIdx.x;
-            k[u] = i < n ? keys[i] : K(0);
+            k[u] = i < hi ? keys[i] : K(0);
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            if (base + u * kBlock + threadIdx.x < n) {
+            if (base + u * kBlock + threadIdx.x < hi) {
                 const uint32_t h = (uint32_t)digit_source<K>(k[u], kDigitHash);
-                const uint32_t w = (h << kHllBits) | (1u << (kHllBits - 1));  // the bits below the index
-                atomicMax(&s_reg[h >> (32 - kHllBits)], (uint32_t)__clz((int)w) + 1u);
+                const uint32_t wv = (h << kHllBits) | (1u << (kHllBits - 1));  // the bits below the index
+                atomicMax(&s_reg[h >> (32 - kHllBits)], (uint32_t)__clz((int)wv) + 1u);
+                if constexpr (HIST) atomicAdd(&s_cnt[w][h & 0xFFu], 1u);
                 const unsigned long long v = digit_source<K>(k[u], kDigitOrdered);
                 o |= v;
                 x &= v;
@@ -619,6 +638,14 @@ __global__ __launch_bounds__(kBlock) void k_hll(const K *__restrict__ keys, uint
     __syncthreads();
     for (int i = threadIdx.x; i < (1 << kHllBits); i += kBlock)
         if (s_reg[i]) atomicMax(&regs[i], s_reg[i]);
+    if constexpr (HIST) {
+        for (int d = threadIdx.x; d < 256; d += kBlock) {
+            uint32_t t = 0;
+#pragma unroll
+            for (int q = 0; q < kWaves; ++q) t += s_cnt[q][d];
+            hist8[(size_t)blockIdx.x * 256u + d] = t;
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------------
@@ -1234,7 +1261,10 @@ __device__ __forceinline__ void hgb_insert_one(const HgbArgs &a, const K *keys, 
     for (uint64_t step = 0; step <= mask && step < a.max_probe; ++step) {
         if constexpr (sizeof(K) == 4) {
             unsigned long long *t = static_cast<unsigned long long *>(a.table);
-            unsigned long long cur = __atomic_load_n(&t[h], __ATOMIC_RELAXED);
+            // A filled slot never changes again, so a plain (cacheable) read that
+            // shows a key is final; only an empty read may be stale, and the CAS
+            // below settles it.
+            unsigned long long cur = t[h];
             if (cur == ~0ull) {
                 const unsigned long long mine = ((unsigned long long)(uint32_t)k << 32) | i;
                 cur = atomicCAS(&t[h], ~0ull, mine);
@@ -1252,7 +1282,7 @@ __device__ __forceinline__ void hgb_insert_one(const HgbArgs &a, const K *keys, 
             }
         } else {
             uint32_t *t = static_cast<uint32_t *>(a.table);
-            uint32_t cur = __atomic_load_n(&t[h], __ATOMIC_RELAXED);
+            uint32_t cur = t[h];  // as above: only an empty read may be stale
             if (cur == 0xFFFFFFFFu) {
                 cur = atomicCAS(&t[h], 0xFFFFFFFFu, i);
                 if (cur == 0xFFFFFFFFu) {
@@ -1348,13 +1378,54 @@ __global__ __launch_bounds__(kBlock) void k_hgb_aggregate(HgbArgs a) {
 // run on one XCD, so the chunk's group ids come from HBM once and from that
 // XCD's L2 for the other slices; value columns are read only for rows in the
 // slice.
-template <int NV, int BT, typename V = int>
+//
+// With several slices only about one row in `slices` belongs to a workgroup, so
+// a wave first queues its slice's rows in LDS (ballot + rank, a ring of 128
+// entries per wave) and updates records 64 queued rows at a time: every lane of
+// every record atomic then carries a row, where updating in place would spend a
+// full wave of atomics on a handful of rows. A queue entry is the record offset
+// and the row's values when they fit two words, else the row index (its values
+// are read when the entry is taken).
+template <int NV, typename V>
+struct HgbQueue {
+    static constexpr bool kVals = NV * sizeof(V) <= 8;      // values kept in the entry
+    static constexpr uint32_t kWords = kVals ? 1 + NV * sizeof(V) / 4 : 2;  // per entry
+    static constexpr uint32_t kEntries = 2 * kWave;         // ring size per wave
+};
+
+__host__ __device__ constexpr uint32_t hgb_queue_bytes(int nv_tier, int value_bytes, uint32_t threads) {
+    return (nv_tier * value_bytes <= 8 ? 1u + (uint32_t)(nv_tier * value_bytes) / 4u : 2u) * 4u *
+           (2u * kWave) * (threads / kWave);
+}
+
+template <int NV, int BT, typename V>
+__device__ __forceinline__ void hgb_queue_take(const HgbArgs &a, uint32_t *recs, const uint32_t *q, uint32_t head,
+                                               uint32_t cnt, uint32_t spare) {
+    using Q = HgbQueue<NV, V>;
+    const uint32_t lane = lane_id();
+    const uint32_t e = (head + lane) & (Q::kEntries - 1);
+    const bool on = lane < cnt;
+    uint32_t off[1];
+    Row<NV, V> rr[1];
+    off[0] = on ? q[e] : spare;
+    if constexpr (Q::kVals) {
+        const V *qv = reinterpret_cast<const V *>(q + Q::kEntries);
+#pragma unroll
+        for (int c = 0; c < NV; ++c) rr[0].v[c] = on ? qv[(uint32_t)c * Q::kEntries + e] : V(0);
+    } else {
+        rr[0] = on ? load_row<NV, V>(a.vals, q[Q::kEntries + e]) : Row<NV, V>{};
+    }
+    rec_add_rows<NV, 1>(recs, a.spec, off, rr, 1, false);
+}
+
+template <int NV, int BT, typename V>
 __global__ __launch_bounds__(BT) void k_hgb_aggregate_sliced(HgbArgs a) {
     constexpr int RB = NV <= 2 ? 8 : 16 / NV;
+    using Q = HgbQueue<NV, V>;
     extern __shared__ __align__(16) uint32_t s_dyn[];
     const AggSpec &s = a.spec;
-    const uint32_t b = blockIdx.x, q = b / kXcds;
-    const uint32_t slice = q % a.slices, chunk = (q / a.slices) * kXcds + b % kXcds;
+    const uint32_t b = blockIdx.x, qi = b / kXcds;
+    const uint32_t slice = qi % a.slices, chunk = (qi / a.slices) * kXcds + b % kXcds;
     if (chunk >= a.chunks) return;
     const uint32_t g0 = slice * a.slice_groups;
     if (g0 >= a.g) return;
@@ -1363,16 +1434,12 @@ __global__ __launch_bounds__(BT) void k_hgb_aggregate_sliced(HgbArgs a) {
     __syncthreads();
     const uint32_t row0 = chunk * a.chunk_rows;
     const uint32_t row1 = (uint32_t)min<uint64_t>((uint64_t)row0 + a.chunk_rows, a.n);
-    for (uint32_t base = row0; base < row1; base += BT * RB) {
-        uint32_t id[RB], off[RB];
-        Row<NV, V> rr[RB];
-        if (a.gid_row) {
-#pragma unroll
-            for (int r = 0; r < RB; ++r) {
-                const uint32_t i = base + r * BT + threadIdx.x;
-                id[r] = i < row1 ? a.gid_row[i] : 0u;
-            }
-        } else {
+    const uint32_t spare = spare_off(L * s.words);
+    if (!a.gid_row) {
+        // one slice: every row of the chunk updates a record in place
+        for (uint32_t base = row0; base < row1; base += BT * RB) {
+            uint32_t id[RB], off[RB];
+            Row<NV, V> rr[RB];
 #pragma unroll
             for (int r = 0; r < RB; ++r) {
                 const uint32_t i = base + r * BT + threadIdx.x;
@@ -1380,18 +1447,75 @@ __global__ __launch_bounds__(BT) void k_hgb_aggregate_sliced(HgbArgs a) {
             }
 #pragma unroll
             for (int r = 0; r < RB; ++r) id[r] = a.gid[id[r]];
-        }
-        bool any = false;
 #pragma unroll
-        for (int r = 0; r < RB; ++r) {
-            const uint32_t i = base + r * BT + threadIdx.x;
-            const uint32_t local = id[r] - g0;  // wraps for ids below the slice
-            const bool in = i < row1 && local < L;
-            off[r] = in ? local * (uint32_t)s.words : spare_off(L * s.words);
-            rr[r] = in ? load_row<NV, V>(a.vals, i) : Row<NV, V>{};
-            any |= in;
+            for (int r = 0; r < RB; ++r) {
+                const uint32_t i = base + r * BT + threadIdx.x;
+                const bool in = i < row1 && id[r] - g0 < L;
+                off[r] = in ? (id[r] - g0) * (uint32_t)s.words : spare;
+                rr[r] = in ? load_row<NV, V>(a.vals, i) : Row<NV, V>{};
+            }
+            rec_add_rows<NV, RB>(s_dyn, s, off, rr, wave_active_rows<RB>(base, BT, row1), false);
         }
-        if (__any(any)) rec_add_rows<NV, RB>(s_dyn, s, off, rr, wave_active_rows<RB>(base, BT, row1), false);
+    } else {
+        // queue of this wave, after the records and their spare words
+        const uint32_t rec_words = ((L + 1) * s.words + kSpareWords + 3u) & ~3u;
+        uint32_t *q = s_dyn + rec_words + (threadIdx.x / kWave) * (Q::kWords * Q::kEntries);
+        const uint32_t lane = lane_id();
+        uint32_t head = 0, cnt = 0;  // wave-uniform: first queued entry, entries queued
+        for (uint32_t base = row0; base < row1; base += BT * RB) {
+            uint32_t id[RB];
+#pragma unroll
+            for (int r = 0; r < RB; ++r) {
+                const uint32_t i = base + r * BT + threadIdx.x;
+                id[r] = i < row1 ? a.gid_row[i] : 0xFFFFFFFFu;
+            }
+            Row<NV, V> rr[RB];
+            if constexpr (Q::kVals) {
+#pragma unroll
+                for (int r = 0; r < RB; ++r) {
+                    const uint32_t i = base + r * BT + threadIdx.x;
+                    rr[r] = id[r] - g0 < L ? load_row<NV, V>(a.vals, i) : Row<NV, V>{};
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < RB; ++r) {
+                const uint32_t i = base + r * BT + threadIdx.x;
+                const bool in = id[r] - g0 < L;  // rows past the chunk carry no id in range
+                const uint64_t m = __ballot(in);
+                if (in) {
+                    const uint32_t e = (head + cnt + rank_below(m)) & (Q::kEntries - 1);
+                    q[e] = (id[r] - g0) * (uint32_t)s.words;
+                    if constexpr (Q::kVals) {
+                        V *qv = reinterpret_cast<V *>(q + Q::kEntries);
+#pragma unroll
+                        for (int c = 0; c < NV; ++c) qv[(uint32_t)c * Q::kEntries + e] = rr[r].v[c];
+                    } else {
+                        q[Q::kEntries + e] = i;
+                    }
+                }
+                cnt += (uint32_t)__popcll(m);
+                if (cnt >= kWave) {
+                    // the entries written above by other lanes of this wave
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                    hgb_queue_take<NV, BT, V>(a, s_dyn, q, head, kWave, spare);
+                    head = (head + kWave) & (Q::kEntries - 1);
+                    cnt -= kWave;
+                    // the taken entries are read before later rows reuse them
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                }
+            }
+            (void)lane;
+        }
+        if (cnt) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            hgb_queue_take<NV, BT, V>(a, s_dyn, q, head, cnt, spare);
+        }
     }
     __syncthreads();
     for (uint32_t i = threadIdx.x; i < L; i += BT) rec_flush(s_dyn + (uint64_t)i * s.words, s, g0 + i, true);
@@ -1678,8 +1802,10 @@ void init_outputs(hipStream_t st, const AggSpec &s, uint64_t g) {
 
 }  // namespace
 
-double estimate_groups(Ctx &ctx, int key_bytes, const void *key, uint32_t n, int *varying_bytes) {
+double estimate_groups(Ctx &ctx, int key_bytes, const void *key, uint32_t n, int *varying_bytes,
+                       const uint32_t **hist8) {
     if (varying_bytes) *varying_bytes = 0;
+    if (hist8) *hist8 = nullptr;
     if (n == 0) return 0.0;
     hipStream_t st = ctx.stream;
     constexpr int m = 1 << kHllBits;
@@ -1687,13 +1813,26 @@ double estimate_groups(Ctx &ctx, int key_bytes, const void *key, uint32_t n, int
     unsigned long long *bits = reinterpret_cast<unsigned long long *>(regs + m);
     fill_u32(st, regs, 0u, m + 2);
     fill_u32(st, regs + m + 2, 0xFFFFFFFFu, 2);
-    const uint32_t grid = std::max<uint32_t>(1, std::min<uint32_t>(ceil_div_u32(n, kBlock * 8), 2048));
-    if (key_bytes == 4)
-        GJ_LAUNCH("k_hll", 4.0 * n, k_hll<int32_t>, dim3(grid), dim3(kBlock), 0, st, static_cast<const int32_t *>(key), n,
-                  regs, bits);
-    else
-        GJ_LAUNCH("k_hll", 8.0 * n, k_hll<int64_t>, dim3(grid), dim3(kBlock), 0, st, static_cast<const int64_t *>(key), n,
-                  regs, bits);
+    if (hist8) {
+        // one workgroup per chunk of the partition pass that may follow
+        const uint32_t crows = pass_chunk_rows(n), chunks = ceil_div_u32(n, crows);
+        uint32_t *h8 = ctx.scratch_n<uint32_t>((size_t)chunks * 256);
+        *hist8 = h8;
+        if (key_bytes == 4)
+            GJ_LAUNCH("k_hll", 4.0 * n, (k_hll<int32_t, true>), dim3(chunks), dim3(kBlock), 0, st,
+                      static_cast<const int32_t *>(key), n, regs, bits, crows, h8);
+        else
+            GJ_LAUNCH("k_hll", 8.0 * n, (k_hll<int64_t, true>), dim3(chunks), dim3(kBlock), 0, st,
+                      static_cast<const int64_t *>(key), n, regs, bits, crows, h8);
+    } else {
+        const uint32_t grid = std::max<uint32_t>(1, std::min<uint32_t>(ceil_div_u32(n, kBlock * 8), 2048));
+        if (key_bytes == 4)
+            GJ_LAUNCH("k_hll", 4.0 * n, (k_hll<int32_t, false>), dim3(grid), dim3(kBlock), 0, st,
+                      static_cast<const int32_t *>(key), n, regs, bits, 0u, nullptr);
+        else
+            GJ_LAUNCH("k_hll", 8.0 * n, (k_hll<int64_t, false>), dim3(grid), dim3(kBlock), 0, st,
+                      static_cast<const int64_t *>(key), n, regs, bits, 0u, nullptr);
+    }
     std::vector<uint32_t> h(m + 4);
     GJ_HIP(hipMemcpyAsync(h.data(), regs, 4ull * (m + 4), hipMemcpyDeviceToHost, st));
     GJ_HIP(hipStreamSynchronize(st));
@@ -1716,7 +1855,7 @@ double estimate_groups(Ctx &ctx, int key_bytes, const void *key, uint32_t n, int
 
 int64_t groupby_partition(Ctx &ctx, int key_bytes, const void *key, const ValCols &vc,
                           uint32_t n, const gj_agg *aggs, int n_aggs, bool gfur, int bits, void **out_key,
-                          void **out_aggs, int *fell_back) {
+                          void **out_aggs, int *fell_back, const uint32_t *hist8) {
     hipStream_t st = ctx.stream;
     *fell_back = 0;
     const int passes = bits > 8 ? 2 : 1;
@@ -1736,7 +1875,7 @@ int64_t groupby_partition(Ctx &ctx, int key_bytes, const void *key, const ValCol
     }
     const uint32_t np = 1u << bits;
     uint32_t *poff = ctx.scratch_n<uint32_t>(np + 1);
-    partition_run(ctx, key_bytes, key, pkey, pc, n, 0, bits, passes, kDigitHash, poff);
+    partition_run(ctx, key_bytes, key, pkey, pc, n, 0, bits, passes, kDigitHash, poff, passes == 1 ? hist8 : nullptr);
 
     // discover: groups per partition, distinct keys in first-occurrence order
     PgbArgs a{};
@@ -2064,13 +2203,21 @@ int64_t groupby_hash(Ctx &ctx, int key_bytes, const void *key, const ValCols &vc
     // ranges, every record stays in LDS.
     const size_t max_lds = (size_t)160 * 1024;
     const size_t sbudget = std::min(lds_budget > 0 ? (size_t)lds_budget : max_lds, max_lds);
-    const size_t per_wg = sbudget > kSpareWords * 4 + rec ? (sbudget - kSpareWords * 4) / rec - 1 : 0;
+    const size_t fixed = kSpareWords * 4 + 16;  // spare words, alignment of the queues
+    const auto groups_in = [&](size_t bytes) -> size_t { return bytes > fixed + rec ? (bytes - fixed) / rec - 1 : 0; };
+    // several slices also need the row queues (for the workgroup size they will run)
+    const bool q_wide = sbudget > max_lds / 4;
+    const size_t qbytes = hgb_queue_bytes(nvt, v64 ? 8 : 4, q_wide ? 1024u : kBlock);
+    const size_t per_one = groups_in(sbudget);
+    const size_t per_wg = g <= per_one ? per_one : groups_in(sbudget > qbytes ? sbudget - qbytes : 0);
     const uint32_t slices = per_wg >= 64 ? (uint32_t)((g + per_wg - 1) / per_wg) : 0u;
     if (g > 2 && slices >= 1 && slices <= kHgbMaxSlices) {
         a.slices = slices;
         a.slice_groups = ceil_div_u32(g, slices);
-        const size_t alds = ((size_t)a.slice_groups + 1) * rec + kSpareWords * 4;
-        const bool wide = alds > max_lds / 4;  // fewer than four 256-thread workgroups per compute unit
+        const size_t rec_lds = ((((size_t)a.slice_groups + 1) * rec + kSpareWords * 4) + 15) & ~(size_t)15;
+        const bool wide = slices > 1 ? q_wide : rec_lds > max_lds / 4;  // fewer than four 256-thread workgroups per CU
+        const size_t alds = rec_lds + (slices > 1 ? hgb_queue_bytes(nvt, v64 ? 8 : 4, wide ? 1024u : kBlock) : 0);
+        require(alds <= max_lds, "hash group-by: slice exceeds the LDS", GJ_EUNSUPPORTED);
         const uint32_t per_cu = (uint32_t)std::max<size_t>(1, std::min<size_t>(wide ? 2 : 8, max_lds / alds));
         // about two rounds of resident workgroups over all slices, chunks a multiple of the XCDs
         uint32_t chunks = ceil_div_u32(2u * 256u * per_cu, slices);

@@ -173,8 +173,15 @@ struct PartCols {
 // Stable radix partition of n rows on digit bits [bit_lo, bit_lo + bits) of the
 // digit source `mode`, in `passes` MSD passes. Writes 2^bits + 1 uint32 offsets to
 // poff (device). n == 0 is allowed.
+// hist8 (optional, one pass at bit_lo 0): per chunk of pass_chunk_rows(n) rows,
+// the rows per value of the digit source's low 8 bits (chunk-major, 256 counts
+// each), read by an earlier kernel; the pass then folds it to its own digit
+// instead of reading the keys for a histogram.
 void partition_run(Ctx &ctx, int key_bytes, const void *key_in, void *key_out, const PartCols &cols,
-                   uint32_t n, int bit_lo, int bits, int passes, int mode, uint32_t *poff);
+                   uint32_t n, int bit_lo, int bits, int passes, int mode, uint32_t *poff,
+                   const uint32_t *hist8 = nullptr);
+// Rows per chunk of a single-segment pass over n rows with the current scatter shape.
+uint32_t pass_chunk_rows(uint32_t n);
 
 // One stable pass over nseg segments (device offsets seg_off[0..nseg]), the digit of
 // segment s being the low seg_bits[s] (<= 8) bits of the digit source `mode` (the key
@@ -207,10 +214,15 @@ struct ValCols {
 // synchronizes with the stream.
 // varying_bytes (optional) receives how many bytes of the order-preserving key
 // differ between rows (the passes a radix sort of the raw keys takes).
-double estimate_groups(Ctx &ctx, int key_bytes, const void *key, uint32_t n, int *varying_bytes = nullptr);
+// hist8 (optional): also count, per chunk of pass_chunk_rows(n) rows, the rows
+// per low 8 bits of the key's hash (the partition group-by's digit), in the same
+// read; *hist8 receives the scratch array.
+double estimate_groups(Ctx &ctx, int key_bytes, const void *key, uint32_t n, int *varying_bytes = nullptr,
+                       const uint32_t **hist8 = nullptr);
+// hist8 (optional): the counts estimate_groups made for a single pass.
 int64_t groupby_partition(Ctx &ctx, int key_bytes, const void *key, const ValCols &vc,
                           uint32_t n, const gj_agg *aggs, int n_aggs, bool gfur, int bits, void **out_key,
-                          void **out_aggs, int *fell_back);
+                          void **out_aggs, int *fell_back, const uint32_t *hist8 = nullptr);
 // g_est > 0 sizes the global table for about that many groups at load `occupancy`
 // (<= 0: 0.45); a table found too small is replaced by one of 1.5 slots per row.
 int64_t groupby_hash(Ctx &ctx, int key_bytes, const void *key, const ValCols &vc, uint32_t n,

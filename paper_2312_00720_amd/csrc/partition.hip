@@ -143,6 +143,21 @@ __global__ __launch_bounds__(kBlock) void k_hist(PassArgs a) {
     }
 }
 
+// Histogram of a single-segment pass from per-chunk counts of the low 8 bits
+// of the digit source (made while the keys were read for another purpose):
+// digit d of `bits` bits gathers the 8-bit values congruent to d.
+__global__ void k_fold_hist(const uint32_t *__restrict__ hist8, uint32_t m, int bits, uint32_t *__restrict__ hist) {
+    const uint32_t R = 1u << bits;
+    const uint32_t per = 256u >> bits;  // 8-bit values per digit
+    for (uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x; idx < R * m; idx += gridDim.x * blockDim.x) {
+        const uint32_t d = idx / m, j = idx % m;
+        const uint32_t *h = hist8 + (size_t)j * 256u;
+        uint32_t t = 0;
+        for (uint32_t q = 0; q < per; ++q) t += h[d + (q << bits)];
+        hist[idx] = t;  // (segment 0, digit d, chunk j)
+    }
+}
+
 // Loads of one tile: ITEMS keys per thread and the first group of up to G 4-byte
 // columns (a generated row id is its row index). Rows past nt read as zero.
 template <typename K, int BLOCK, int ITEMS, int G>
@@ -705,16 +720,21 @@ __global__ void k_key_bits(const K *__restrict__ keys, uint32_t n, unsigned long
     }
 }
 
+// Aim for ~4096 chunks: a few per resident workgroup, each a whole number of tiles.
+uint32_t chunk_rows_for(uint32_t n) {
+    const Shape sh = scatter_shape();
+    const uint32_t tile = (uint32_t)(sh.block * sh.items);
+    const uint32_t tiles = ceil_div_u32(n, tile);
+    const uint32_t per = tiles > 4096 ? ceil_div_u32(tiles, 4096) : 1;
+    return per * tile;
+}
+
 template <typename K>
-void run_pass(Ctx &ctx, PassArgs &a, uint32_t n) {
+void run_pass(Ctx &ctx, PassArgs &a, uint32_t n, const uint32_t *hist8 = nullptr) {
     hipStream_t s = ctx.stream;
     const uint32_t R = 1u << a.bits;
     const Shape sh = scatter_shape();
-    const uint32_t tile = (uint32_t)(sh.block * sh.items);
-    // Aim for ~4096 chunks: a few per resident workgroup, each a whole number of tiles.
-    uint32_t tiles = ceil_div_u32(n, tile);
-    uint32_t per = tiles > 4096 ? ceil_div_u32(tiles, 4096) : 1;
-    a.chunk_rows = per * tile;
+    a.chunk_rows = chunk_rows_for(n);
     const uint64_t max_chunks = (uint64_t)ceil_div_u32(n, a.chunk_rows) + a.nseg;
     uint32_t *chunk_base = ctx.scratch_n<uint32_t>(a.nseg + 1);
     a.chunk_base = chunk_base;
@@ -728,7 +748,15 @@ void run_pass(Ctx &ctx, PassArgs &a, uint32_t n) {
     GJ_LAUNCH("k_chunk_table", 8.0 * (a.nseg + 1), k_chunk_table, dim3(1), dim3(kBlock), 0, s, a.seg_off,
               a.nseg, a.chunk_rows, chunk_base);
     fill_u32(s, hist, 0u, hn);
-    GJ_LAUNCH("k_hist", (double)n * sizeof(K), k_hist<K>, dim3((uint32_t)max_chunks), dim3(kBlock), 0, s, a);
+    if (hist8) {
+        // one segment: chunks 0..m-1, the digit the low bits of the same source
+        const uint32_t m = ceil_div_u32(n, a.chunk_rows);
+        GJ_LAUNCH("k_fold_hist", 4.0 * m * 256 + 4.0 * m * R, k_fold_hist,
+                  dim3(std::min<uint32_t>(ceil_div_u32(R * m, kBlock), 4096)), dim3(kBlock), 0, s, hist8, m, a.bits,
+                  hist);
+    } else {
+        GJ_LAUNCH("k_hist", (double)n * sizeof(K), k_hist<K>, dim3((uint32_t)max_chunks), dim3(kBlock), 0, s, a);
+    }
     scan_exclusive_u32(ctx, hist, hist, hn, nullptr);
     launch_scatter<K>(sh, dim3((uint32_t)max_chunks), s, a, (double)n * row_bytes);
 }
@@ -737,8 +765,11 @@ void run_pass(Ctx &ctx, PassArgs &a, uint32_t n) {
 
 void set_scatter_variant(int v) { g_variant = v; }
 
+uint32_t pass_chunk_rows(uint32_t n) { return chunk_rows_for(n); }
+
 void partition_run(Ctx &ctx, int key_bytes, const void *key_in, void *key_out, const PartCols &cols,
-                   uint32_t n, int bit_lo, int bits, int passes, int mode, uint32_t *poff) {
+                   uint32_t n, int bit_lo, int bits, int passes, int mode, uint32_t *poff, const uint32_t *hist8) {
+    require(!hist8 || (passes == 1 && bit_lo == 0), "a precomputed histogram serves one pass from bit 0");
     require(key_bytes == 4 || key_bytes == 8, "key width must be 4 or 8 bytes");
     require(bits >= 1 && bits <= 16, "partition bits must be 1..16");
     require(passes >= 1 && passes <= 2, "partition passes must be 1 or 2");
@@ -782,8 +813,8 @@ void partition_run(Ctx &ctx, int key_bytes, const void *key_in, void *key_out, c
         a.nseg = nseg;
         a.n_rows = n;
         if (n > 0) {
-            if (key_bytes == 4) run_pass<int32_t>(ctx, a, n);
-            else run_pass<int64_t>(ctx, a, n);
+            if (key_bytes == 4) run_pass<int32_t>(ctx, a, n, hist8);
+            else run_pass<int64_t>(ctx, a, n, hist8);
         } else {
             uint32_t *cb = ctx.scratch_n<uint32_t>(nseg + 1);
             fill_u32(s, cb, 0u, nseg + 1);

@@ -197,6 +197,18 @@ def test_hash_sliced_lds_records(g_card, budget, alpha):
     check(d["key"], d["vals"], algo="hash", lds_budget=budget)
 
 
+@pytest.mark.parametrize("nv,alpha", [(4, 0.0), (8, 0.0), (4, 1.0)])
+def test_hash_sliced_many_value_columns(nv, alpha):
+    """Sliced hash aggregation with 4 and 8 value columns: queued rows carry
+    their row index (their values are read when the queue is drained) rather than
+    the values themselves, and the records take 16 aggregates."""
+    d = datagen.groupby_input(250007, 20000, nv, seed=90 + nv, alpha=alpha)
+    aggs = [(0, "count")] + [(c, "sum") for c in range(nv)] + [(c, "min") for c in range(nv)][:14 - nv]
+    aggs += [(nv - 1, "max")]
+    check(d["key"], d["vals"], aggs, algo="hash")
+    check(d["key"], d["vals"], aggs, algo="hash", lds_budget=24576)
+
+
 def test_hash_global_aggregation_path():
     d = datagen.groupby_input(100000, 2000, 2, seed=6)
     check(d["key"], d["vals"], algo="hash", lds_budget=64)
