@@ -9,7 +9,8 @@ Joins (|R| = 2^27, |S| = 2^28, 4 + 4 int32 payloads): R keys are a permutation
 of 0..|R|-1 (through the bijective splitmix64 widening for 8-byte keys), so an
 output row's R payloads must be R.p[inv[key]]; the output holds exactly the
 matched S rows, checked by the row count and the oracle's fingerprint of the
-multiset of (key, S payloads).
+multiset of (key, S payloads). The sort-merge join's rows must also come in
+ascending key order.
 
 Group-by (N = 2^28, 2 value columns): COUNT, SUM (int64) and MIN/MAX per
 present key from direct-address closed forms on the host (integer
@@ -40,28 +41,30 @@ def _key_values(keys: np.ndarray) -> np.ndarray:
 
 
 C2_CASES = [
-    # key bytes, Zipf alpha of the FKs, match ratio, materialization
-    (4, 0.0, 1.0, "gfur"),
-    (8, 0.0, 1.0, "gftr"),
-    (4, 1.0, 1.0, "gftr"),
-    (4, 0.0, 0.5, "gftr"),
-    (4, 0.5, 0.5, "gfur"),
-    (8, 1.0, 0.5, "gfur"),
+    # key bytes, Zipf alpha of the FKs, match ratio, materialization, join algorithm
+    (4, 0.0, 1.0, "gfur", "phj"),
+    (8, 0.0, 1.0, "gftr", "phj"),
+    (4, 1.0, 1.0, "gftr", "phj"),
+    (4, 0.0, 0.5, "gftr", "phj"),
+    (4, 0.5, 0.5, "gfur", "phj"),
+    (8, 1.0, 0.5, "gfur", "phj"),
+    (4, 0.0, 1.0, "gftr", "smj"),
+    (8, 1.0, 0.5, "gfur", "smj"),
 ]
 
 
-@pytest.mark.parametrize("kb,alpha,mr,mat", C2_CASES)
-def test_join_full_size_variants(kb, alpha, mr, mat):
+@pytest.mark.parametrize("kb,alpha,mr,mat,algo", C2_CASES)
+def test_join_full_size_variants(kb, alpha, mr, mat, algo):
     import torch
     import datagen.device as dd
     import paper_2312_00720_amd as gj
     from gpu_util import host, say
-    tag = f"full-size join kb={kb} alpha={alpha} mr={mr} {mat}"
+    tag = f"full-size join kb={kb} alpha={alpha} mr={mr} {mat} {algo}"
     say(f"{tag}: generating")
     variant = 10 * kb + int(10 * alpha) + (100 if mr < 1 else 0)
     d = dd.pk_fk_join(N_R, N_S, 4, 4, seed=datagen.seed_for(1, variant), alpha=alpha, match_ratio=mr, key_bytes=kb)
     say(f"{tag}: running gj.join")
-    k, rp, sp = gj.join(d["r_key"], d["r_pay"], d["s_key"], d["s_pay"], mat=mat)
+    k, rp, sp = gj.join(d["r_key"], d["r_pay"], d["s_key"], d["s_pay"], mat=mat, algo=algo)
     torch.cuda.synchronize()
     assert k.numel() == d["n_match"]
     say(f"{tag}: R payloads of every row by the closed form")
@@ -71,6 +74,8 @@ def test_join_full_size_variants(kb, alpha, mr, mat):
     del rj
     tk = host(k)
     del k
+    if algo == "smj":
+        assert np.all(tk[1:] >= tk[:-1]), "sort-merge join emits keys in ascending order"
     tj = _key_values(tk)
     assert tj.min() >= 0 and tj.max() < N_R
     ridx = inv[tj]
