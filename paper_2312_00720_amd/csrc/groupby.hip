@@ -588,7 +588,7 @@ template <typename K, bool HIST>
 __global__ __launch_bounds__(kBlock) void k_hll(const K *__restrict__ keys, uint32_t n, uint32_t *__restrict__ regs,
                                                 unsigned long long *__restrict__ bits, uint32_t chunk_rows,
                                                 uint32_t *__restrict__ hist8) {
-    constexpr int U = 8;
+    constexpr int U = 16;  // keys loaded per thread before they are counted
     __shared__ uint32_t s_reg[1 << kHllBits];
     __shared__ uint32_t s_cnt[HIST ? kWaves : 1][HIST ? 256 : 1];
     for (int i = threadIdx.x; i < (1 << kHllBits); i += kBlock) s_reg[i] = 0;
@@ -1227,7 +1227,7 @@ constexpr uint32_t kHgbMaxSlices = 64;
 // Every row's group id, gid[gid_loc[i]], for the slices to stream.
 __global__ void k_hgb_resolve(const uint32_t *__restrict__ gid_loc, const uint32_t *__restrict__ gid, uint32_t n,
                               uint32_t *__restrict__ out) {
-    constexpr int RB = 8;
+    constexpr int RB = 16;
     for (uint32_t base = blockIdx.x * kBlock * RB; base < n; base += gridDim.x * kBlock * RB) {
         uint32_t loc[RB];
 #pragma unroll
@@ -1305,7 +1305,7 @@ __device__ __forceinline__ void hgb_insert_one(const HgbArgs &a, const K *keys, 
 
 template <typename K>
 __global__ __launch_bounds__(kBlock) void k_hgb_insert(HgbArgs a) {
-    constexpr int RB = 8;
+    constexpr int RB = 16;
     const K *__restrict__ keys = static_cast<const K *>(a.keys);
     const uint32_t stride = gridDim.x * kBlock * RB;
     for (uint32_t base = blockIdx.x * kBlock * RB; base < a.n; base += stride) {
@@ -1701,7 +1701,7 @@ __global__ void k_de_rank(const int32_t *__restrict__ sorted_id, uint32_t g, uin
 // code[i] = rank of row i's group: its key's position among the distinct keys.
 __global__ void k_de_encode(const uint32_t *__restrict__ gid_loc, const uint32_t *__restrict__ gid,
                             const uint32_t *__restrict__ rank, uint32_t n, int32_t *__restrict__ code) {
-    constexpr int RB = 8;
+    constexpr int RB = 16;
     for (uint32_t base = blockIdx.x * kBlock * RB; base < n; base += gridDim.x * kBlock * RB) {
         uint32_t loc[RB];
 #pragma unroll
@@ -1825,7 +1825,7 @@ double estimate_groups(Ctx &ctx, int key_bytes, const void *key, uint32_t n, int
             GJ_LAUNCH("k_hll", 8.0 * n, (k_hll<int64_t, true>), dim3(chunks), dim3(kBlock), 0, st,
                       static_cast<const int64_t *>(key), n, regs, bits, crows, h8);
     } else {
-        const uint32_t grid = std::max<uint32_t>(1, std::min<uint32_t>(ceil_div_u32(n, kBlock * 8), 2048));
+        const uint32_t grid = std::max<uint32_t>(1, std::min<uint32_t>(ceil_div_u32(n, kBlock * 16), 2048));
         if (key_bytes == 4)
             GJ_LAUNCH("k_hll", 4.0 * n, (k_hll<int32_t, false>), dim3(grid), dim3(kBlock), 0, st,
                       static_cast<const int32_t *>(key), n, regs, bits, 0u, nullptr);
@@ -2227,7 +2227,7 @@ int64_t groupby_hash(Ctx &ctx, int key_bytes, const void *key, const ValCols &vc
         a.gid_row = nullptr;
         if (slices > 1) {
             uint32_t *gr = ctx.scratch_n<uint32_t>(n);
-            GJ_LAUNCH("k_hgb_resolve", 8.0 * n, k_hgb_resolve, dim3(std::min<uint32_t>(ceil_div_u32(n, kBlock * 8), 4096)),
+            GJ_LAUNCH("k_hgb_resolve", 8.0 * n, k_hgb_resolve, dim3(std::min<uint32_t>(ceil_div_u32(n, kBlock * 16), 4096)),
                       dim3(kBlock), 0, st, a.gid_loc, a.gid, n, gr);
             a.gid_row = gr;
         }
@@ -2362,7 +2362,7 @@ int64_t groupby_sort_de(Ctx &ctx, int key_bytes, const void *key, const ValCols 
               st, sorted_id, g, rank);
     // encoding: one 4-byte code per row
     int32_t *code = ctx.scratch_n<int32_t>(n);
-    GJ_LAUNCH("k_de_encode", 8.0 * n, k_de_encode, dim3(std::min<uint32_t>(ceil_div_u32(n, kBlock * 8), 4096)),
+    GJ_LAUNCH("k_de_encode", 8.0 * n, k_de_encode, dim3(std::min<uint32_t>(ceil_div_u32(n, kBlock * 16), 4096)),
               dim3(kBlock), 0, st, h.gid_loc, h.gid, rank, n, code);
     // sort (code, values) on the code bytes that vary: ceil(log2 g / 8) passes
     int32_t *scode = ctx.scratch_n<int32_t>(n);

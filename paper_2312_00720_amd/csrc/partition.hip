@@ -703,12 +703,24 @@ void assign_cols(PassArgs &a, const PartCols &cols, const void *const *cin, void
 
 template <typename K>
 __global__ void k_key_bits(const K *__restrict__ keys, uint32_t n, unsigned long long *__restrict__ acc) {
-    // OR and AND of the order-preserving key bits over all keys
+    // OR and AND of the order-preserving key bits over all keys, 16 loads in
+    // flight per thread
+    constexpr int U = 16;
     unsigned long long o = 0, x = ~0ull;
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        const unsigned long long v = digit_source<K>(keys[i], kDigitOrdered);
-        o |= v;
-        x &= v;
+    const uint32_t step = gridDim.x * blockDim.x;
+    for (uint32_t base = blockIdx.x * blockDim.x * U + threadIdx.x; base < n; base += step * U) {
+        K k[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint32_t i = base + u * blockDim.x;
+            k[u] = i < n ? keys[i] : keys[base];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const unsigned long long v = digit_source<K>(k[u], kDigitOrdered);
+            o |= v;
+            x &= v;
+        }
     }
     for (int d = kWave / 2; d > 0; d >>= 1) {
         o |= __shfl_xor(o, d, kWave);
@@ -843,7 +855,7 @@ void sort_run(Ctx &ctx, int key_bytes, const void *key_in, void *key_out, const 
         unsigned long long *acc = reinterpret_cast<unsigned long long *>(ctx.scratch_n<uint64_t>(2));
         fill_u64(s, reinterpret_cast<uint64_t *>(acc), 0ull, 1);
         fill_u64(s, reinterpret_cast<uint64_t *>(acc) + 1, ~0ull, 1);
-        const uint32_t grid = std::min<uint32_t>(ceil_div_u32(n, 256), 2048);
+        const uint32_t grid = std::min<uint32_t>(ceil_div_u32(n, 256 * 16), 2048);
         if (key_bytes == 4)
             GJ_LAUNCH("k_key_bits", 4.0 * n, k_key_bits<int32_t>, dim3(grid), dim3(256), 0, s,
                       static_cast<const int32_t *>(key_in), n, acc);
