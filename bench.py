@@ -266,7 +266,7 @@ def bench_groupby(args, copy_gbs) -> int:
         d["key"] = ((d["key"].to(torch.int64) * 0x9E3779B1) & 0xFFFFFFFF).to(torch.int32)
         keys_desc = "int32 key (g values spread over all 4 bytes)"
     torch.cuda.synchronize()
-    mat = args.mat if args.algo != "hash" else "auto"
+    mat = args.mat if args.algo not in ("hash", "auto") else "auto"
 
     def step():
         return gj.groupby(d["key"], d["vals"], GB_AGGS, algo=args.algo, mat=mat, radix_bits=args.radix_bits)
@@ -599,7 +599,7 @@ def main() -> int:
     ap.add_argument("--g-log2", type=int, default=16, help="group-by key cardinality")
     ap.add_argument("--sparse-keys", action="store_true", help="group-by: spread the keys over all 4 bytes")
     ap.add_argument("--gb-key-bytes", type=int, default=4, choices=[4, 8], help="group-by key width")
-    ap.add_argument("--algo", default="partition", choices=["partition", "hash", "sort", "sort_de"])
+    ap.add_argument("--algo", default="partition", choices=["partition", "hash", "sort", "sort_de", "auto"])
     ap.add_argument("--copy-only", action="store_true",
                     help="only run the plain copy (counter calibration) and print its GB/s")
     args = ap.parse_args()
