@@ -2143,11 +2143,11 @@ static uint32_t hgb_assign_ids(Ctx &ctx, HgbArgs &a, int key_bytes, const void *
         HgbArgs ap = a;
         ap.n = prefix;
         if (key_bytes == 4) {
-            GJ_LAUNCH("k_hgb_insert", 16.0 * prefix, k_hgb_insert<int32_t>, dim3(1), dim3(kBlock), 0, st, ap);
-            if (n > prefix) GJ_LAUNCH("k_hgb_insert", 16.0 * n, k_hgb_insert<int32_t>, dim3(grid), dim3(kBlock), 0, st, a);
+            GJ_LAUNCH("k_hgb_insert", 8.0 * prefix, k_hgb_insert<int32_t>, dim3(1), dim3(kBlock), 0, st, ap);
+            if (n > prefix) GJ_LAUNCH("k_hgb_insert", 8.0 * n, k_hgb_insert<int32_t>, dim3(grid), dim3(kBlock), 0, st, a);
         } else {
-            GJ_LAUNCH("k_hgb_insert", 20.0 * prefix, k_hgb_insert<int64_t>, dim3(1), dim3(kBlock), 0, st, ap);
-            if (n > prefix) GJ_LAUNCH("k_hgb_insert", 20.0 * n, k_hgb_insert<int64_t>, dim3(grid), dim3(kBlock), 0, st, a);
+            GJ_LAUNCH("k_hgb_insert", 12.0 * prefix, k_hgb_insert<int64_t>, dim3(1), dim3(kBlock), 0, st, ap);
+            if (n > prefix) GJ_LAUNCH("k_hgb_insert", 12.0 * n, k_hgb_insert<int64_t>, dim3(grid), dim3(kBlock), 0, st, a);
         }
         uint32_t h[2];
         GJ_HIP(hipMemcpyAsync(h, a.ngroups, 8, hipMemcpyDeviceToHost, st));
@@ -2195,7 +2195,9 @@ int64_t groupby_hash(Ctx &ctx, int key_bytes, const void *key, const ValCols &vc
     a.vals = val_src(vc);
     a.g = g;
     init_outputs(st, a.spec, g);
-    const double bytes = (double)n * (val_bytes(vc) + 8.0) + (double)g * (key_bytes + 4.0 * a.spec.words);
+    // stage 2 reads each row's values and its group id (gid_loc and gid[gid_loc], or
+    // the resolved id once for several slices), and writes every group once
+    double bytes = (double)n * (val_bytes(vc) + 8.0) + (double)g * (key_bytes + 4.0 * a.spec.words);
     const bool v64 = any_wide(vc);
     const int nvt = nv_tier(n_vals);
     // is_smem_enough, per slice: when the groups fit the LDS of a workgroup (at
@@ -2230,6 +2232,7 @@ int64_t groupby_hash(Ctx &ctx, int key_bytes, const void *key, const ValCols &vc
             GJ_LAUNCH("k_hgb_resolve", 8.0 * n, k_hgb_resolve, dim3(std::min<uint32_t>(ceil_div_u32(n, kBlock * 16), 4096)),
                       dim3(kBlock), 0, st, a.gid_loc, a.gid, n, gr);
             a.gid_row = gr;
+            bytes -= 4.0 * n;
         }
         const uint32_t sgrid = chunks * slices;
 #define GJ_HAGG_S(NV, BT, V) \
