@@ -49,9 +49,10 @@ struct AggSpec {
     int n;
     int op[kMaxAggs];   // GJ_SUM / GJ_COUNT / GJ_MIN / GJ_MAX
     int col[kMaxAggs];  // value column
-    int word[kMaxAggs]; // word offset in the LDS record
+    int word[kMaxAggs]; // word offset in an LDS record at an even word
+    int word_odd[kMaxAggs];  // word offset in a record at an odd word (odd record sizes)
     int w8[kMaxAggs];   // MIN / MAX of an 8-byte column: a 64-bit field and output
-    int words;          // record size in 4-byte words (even)
+    int words;          // record size in 4-byte words
     void *out[kMaxAggs];
 };
 
@@ -67,9 +68,29 @@ struct ValSrc {
 __device__ __forceinline__ int narrow_min(long long x) { return (int)(x < INT32_MAX ? x : INT32_MAX); }
 __device__ __forceinline__ int narrow_max(long long x) { return (int)(x > INT32_MIN ? x : INT32_MIN); }
 
+// Word offset of field j in a record starting `at` words past an 8-byte aligned
+// base. The hash group-by's records (ODD) take an odd number of words when any
+// field is 32 bits wide (no padding word, so one more group fits every 9 or so):
+// a record at an odd word shifts its first 32-bit field in front of the 64-bit
+// ones, which then stay 8-byte aligned. Other records are padded to an even
+// size (the partition group-by's aggregation keeps one more wave per SIMD
+// without the per-field parity test).
+template <bool ODD>
+__device__ __forceinline__ int field_at(const AggSpec &s, int j, uint32_t at) {
+    if constexpr (ODD) return (at & 1u) ? s.word_odd[j] : s.word[j];
+    else return s.word[j];
+}
+template <bool ODD>
+__device__ __forceinline__ uint32_t word_parity(const uint32_t *rec) {
+    if constexpr (ODD) return (uint32_t)((uintptr_t)rec >> 2) & 1u;
+    else return 0u;
+}
+
+template <bool ODD = false>
 __device__ __forceinline__ void rec_init(uint32_t *rec, const AggSpec &s) {
+    const uint32_t par = word_parity<ODD>(rec);
     for (int j = 0; j < s.n; ++j) {
-        uint32_t *p = rec + s.word[j];
+        uint32_t *p = rec + field_at<ODD>(s, j, par);
         switch (s.op[j]) {
             case GJ_SUM: p[0] = 0; p[1] = 0; break;
             case GJ_COUNT: p[0] = 0; break;
@@ -86,9 +107,11 @@ __device__ __forceinline__ void rec_init(uint32_t *rec, const AggSpec &s) {
 }
 
 // Write (plain) or fold (atomic) an LDS record into output group o.
+template <bool ODD = false>
 __device__ __forceinline__ void rec_flush(const uint32_t *rec, const AggSpec &s, uint64_t o, bool atomic) {
+    const uint32_t par = word_parity<ODD>(rec);
     for (int j = 0; j < s.n; ++j) {
-        const uint32_t *p = rec + s.word[j];
+        const uint32_t *p = rec + field_at<ODD>(s, j, par);
         switch (s.op[j]) {
             case GJ_SUM: {
                 const unsigned long long x = *reinterpret_cast<const unsigned long long *>(p);
@@ -199,14 +222,14 @@ __device__ __forceinline__ uint32_t spare_off(uint32_t rec_end) { return rec_end
 // LDS atomic MIN / MAX on a record field of T (int, or long long for an 8-byte
 // column); with `skewed`, a row that cannot change the field (checked against a
 // possibly stale read) skips the atomic.
-template <typename T, int RB, bool IS_MIN>
-__device__ __forceinline__ void rec_minmax(uint32_t *recs, const uint32_t (&off)[RB], int w, const T (&x)[RB],
-                                           int nact, bool skewed) {
+template <typename T, int RB, bool IS_MIN, bool ODD>
+__device__ __forceinline__ void rec_minmax(uint32_t *recs, const uint32_t (&off)[RB], int w0, int w1,
+                                           const T (&x)[RB], int nact, bool skewed) {
     if (!skewed) {
 #pragma unroll
         for (int r = 0; r < RB; ++r) {
             if (r < nact) {
-                T *p = reinterpret_cast<T *>(recs + off[r] + w);
+                T *p = reinterpret_cast<T *>(recs + off[r] + ((ODD && (off[r] & 1u)) ? w1 : w0));
                 if (IS_MIN) atomicMin(p, x[r]);
                 else atomicMax(p, x[r]);
             }
@@ -221,11 +244,12 @@ __device__ __forceinline__ void rec_minmax(uint32_t *recs, const uint32_t (&off)
     T cur[RB];
 #pragma unroll
     for (int r = 0; r < RB; ++r)
-        if (r < nact) cur[r] = __atomic_load_n(reinterpret_cast<T *>(recs + off[r] + w), __ATOMIC_RELAXED);
+        if (r < nact)
+            cur[r] = __atomic_load_n(reinterpret_cast<T *>(recs + off[r] + ((ODD && (off[r] & 1u)) ? w1 : w0)), __ATOMIC_RELAXED);
 #pragma unroll
     for (int r = 0; r < RB; ++r) {
         if (r < nact && (IS_MIN ? x[r] < cur[r] : x[r] > cur[r])) {
-            T *p = reinterpret_cast<T *>(recs + off[r] + w);
+            T *p = reinterpret_cast<T *>(recs + off[r] + ((ODD && (off[r] & 1u)) ? w1 : w0));
             if (IS_MIN) atomicMin(p, x[r]);
             else atomicMax(p, x[r]);
         }
@@ -238,23 +262,23 @@ __device__ __forceinline__ void rec_minmax(uint32_t *recs, const uint32_t (&off)
 // at a spare, so the atomics need no divergent branch. The loop runs over the
 // aggregates outside the rows: each aggregate's atomics issue back to back, and
 // the aggregate list is read once per batch of rows rather than once per row.
-template <int NV, int RB, typename V>
+template <int NV, int RB, typename V, bool ODD = false>
 __device__ __forceinline__ void rec_add_rows(uint32_t *recs, const AggSpec &s, const uint32_t (&off)[RB],
                                              const Row<NV, V> (&rr)[RB], int nact, bool skewed) {
     for (int j = 0; j < s.n; ++j) {
-        const int c = s.col[j], w = s.word[j];
+        const int c = s.col[j], w = s.word[j], wo = s.word_odd[j];
         switch (s.op[j]) {
             case GJ_SUM:
 #pragma unroll
                 for (int r = 0; r < RB; ++r)
                     if (r < nact)
-                        atomicAdd(reinterpret_cast<unsigned long long *>(recs + off[r] + w),
+                        atomicAdd(reinterpret_cast<unsigned long long *>(recs + off[r] + ((ODD && (off[r] & 1u)) ? wo : w)),
                                   (unsigned long long)(long long)pick(rr[r], c));
                 break;
             case GJ_COUNT:
 #pragma unroll
                 for (int r = 0; r < RB; ++r)
-                    if (r < nact) atomicAdd(recs + off[r] + w, 1u);
+                    if (r < nact) atomicAdd(recs + off[r] + ((ODD && (off[r] & 1u)) ? wo : w), 1u);
                 break;
             case GJ_MIN:
             default: {
@@ -264,16 +288,16 @@ __device__ __forceinline__ void rec_add_rows(uint32_t *recs, const AggSpec &s, c
                         long long x[RB];
 #pragma unroll
                         for (int r = 0; r < RB; ++r) x[r] = pick(rr[r], c);
-                        if (is_min) rec_minmax<long long, RB, true>(recs, off, w, x, nact, skewed);
-                        else rec_minmax<long long, RB, false>(recs, off, w, x, nact, skewed);
+                        if (is_min) rec_minmax<long long, RB, true, ODD>(recs, off, w, wo, x, nact, skewed);
+                        else rec_minmax<long long, RB, false, ODD>(recs, off, w, wo, x, nact, skewed);
                         break;
                     }
                 }
                 int x[RB];
 #pragma unroll
                 for (int r = 0; r < RB; ++r) x[r] = (int)pick(rr[r], c);
-                if (is_min) rec_minmax<int, RB, true>(recs, off, w, x, nact, skewed);
-                else rec_minmax<int, RB, false>(recs, off, w, x, nact, skewed);
+                if (is_min) rec_minmax<int, RB, true, ODD>(recs, off, w, wo, x, nact, skewed);
+                else rec_minmax<int, RB, false, ODD>(recs, off, w, wo, x, nact, skewed);
                 break;
             }
         }
@@ -424,10 +448,11 @@ __device__ __forceinline__ void acc_flush(const Acc<NV, V> &x, const AggSpec &s,
 }
 
 // Fold an Acc into an LDS record (leader lane of a wave-aggregated update).
-template <int NV, typename V>
+template <int NV, typename V, bool ODD = false>
 __device__ __forceinline__ void rec_add_acc(uint32_t *rec, const AggSpec &s, const Acc<NV, V> &x) {
+    const uint32_t par = word_parity<ODD>(rec);
     for (int j = 0; j < s.n; ++j) {
-        uint32_t *p = rec + s.word[j];
+        uint32_t *p = rec + field_at<ODD>(s, j, par);
         long long sum;
         V mn, mx;
         acc_pick(x, s.col[j], sum, mn, mx);
@@ -449,7 +474,7 @@ __device__ __forceinline__ void rec_add_acc(uint32_t *rec, const AggSpec &s, con
 // Rows of one wave round with group ids: lanes sharing an id are combined in
 // registers first, so each distinct id costs one set of LDS atomics per wave
 // instead of one per lane (the case of few groups, where lanes collide).
-template <int NV, typename V>
+template <int NV, typename V, bool ODD = false>
 __device__ __forceinline__ void wave_aggregate(uint32_t *recs, const AggSpec &s, bool valid, uint32_t id,
                                                const Row<NV, V> &r) {
     uint64_t todo = __ballot(valid);
@@ -462,7 +487,7 @@ __device__ __forceinline__ void wave_aggregate(uint32_t *recs, const AggSpec &s,
         acc_clear(x);
         if (mine) acc_row(x, r);
         x = acc_wave_reduce(x);
-        if (lane_id() == leader) rec_add_acc(recs + (uint64_t)lid * s.words, s, x);
+        if (lane_id() == leader) rec_add_acc<NV, V, ODD>(recs + (uint64_t)lid * s.words, s, x);
         todo &= ~peers;
     }
 }
@@ -1398,7 +1423,7 @@ __host__ __device__ constexpr uint32_t hgb_queue_bytes(int nv_tier, int value_by
            (2u * kWave) * (threads / kWave);
 }
 
-template <int NV, int BT, typename V>
+template <int NV, int BT, typename V, bool ODD>
 __device__ __forceinline__ void hgb_queue_take(const HgbArgs &a, uint32_t *recs, const uint32_t *q, uint32_t head,
                                                uint32_t cnt, uint32_t spare) {
     using Q = HgbQueue<NV, V>;
@@ -1415,10 +1440,10 @@ __device__ __forceinline__ void hgb_queue_take(const HgbArgs &a, uint32_t *recs,
     } else {
         rr[0] = on ? load_row<NV, V>(a.vals, q[Q::kEntries + e]) : Row<NV, V>{};
     }
-    rec_add_rows<NV, 1>(recs, a.spec, off, rr, 1, false);
+    rec_add_rows<NV, 1, V, ODD>(recs, a.spec, off, rr, 1, false);
 }
 
-template <int NV, int BT, typename V>
+template <int NV, int BT, typename V, bool ODD>
 __global__ __launch_bounds__(BT) void k_hgb_aggregate_sliced(HgbArgs a) {
     constexpr int RB = NV <= 2 ? 8 : 16 / NV;
     using Q = HgbQueue<NV, V>;
@@ -1430,7 +1455,7 @@ __global__ __launch_bounds__(BT) void k_hgb_aggregate_sliced(HgbArgs a) {
     const uint32_t g0 = slice * a.slice_groups;
     if (g0 >= a.g) return;
     const uint32_t L = min(a.slice_groups, a.g - g0);
-    for (uint32_t i = threadIdx.x; i < L; i += BT) rec_init(s_dyn + (uint64_t)i * s.words, s);
+    for (uint32_t i = threadIdx.x; i < L; i += BT) rec_init<ODD>(s_dyn + (uint64_t)i * s.words, s);
     __syncthreads();
     const uint32_t row0 = chunk * a.chunk_rows;
     const uint32_t row1 = (uint32_t)min<uint64_t>((uint64_t)row0 + a.chunk_rows, a.n);
@@ -1454,7 +1479,7 @@ __global__ __launch_bounds__(BT) void k_hgb_aggregate_sliced(HgbArgs a) {
                 off[r] = in ? (id[r] - g0) * (uint32_t)s.words : spare;
                 rr[r] = in ? load_row<NV, V>(a.vals, i) : Row<NV, V>{};
             }
-            rec_add_rows<NV, RB>(s_dyn, s, off, rr, wave_active_rows<RB>(base, BT, row1), false);
+            rec_add_rows<NV, RB, V, ODD>(s_dyn, s, off, rr, wave_active_rows<RB>(base, BT, row1), false);
         }
     } else {
         // queue of this wave, after the records and their spare words
@@ -1499,7 +1524,7 @@ __global__ __launch_bounds__(BT) void k_hgb_aggregate_sliced(HgbArgs a) {
                     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                     __builtin_amdgcn_wave_barrier();
                     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                    hgb_queue_take<NV, BT, V>(a, s_dyn, q, head, kWave, spare);
+                    hgb_queue_take<NV, BT, V, ODD>(a, s_dyn, q, head, kWave, spare);
                     head = (head + kWave) & (Q::kEntries - 1);
                     cnt -= kWave;
                     // the taken entries are read before later rows reuse them
@@ -1514,11 +1539,11 @@ __global__ __launch_bounds__(BT) void k_hgb_aggregate_sliced(HgbArgs a) {
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            hgb_queue_take<NV, BT, V>(a, s_dyn, q, head, cnt, spare);
+            hgb_queue_take<NV, BT, V, ODD>(a, s_dyn, q, head, cnt, spare);
         }
     }
     __syncthreads();
-    for (uint32_t i = threadIdx.x; i < L; i += BT) rec_flush(s_dyn + (uint64_t)i * s.words, s, g0 + i, true);
+    for (uint32_t i = threadIdx.x; i < L; i += BT) rec_flush<ODD>(s_dyn + (uint64_t)i * s.words, s, g0 + i, true);
 }
 
 template <typename K>
@@ -1729,10 +1754,12 @@ int nv_tier(int n_vals) { return n_vals <= 1 ? 1 : n_vals <= 2 ? 2 : n_vals <= 4
 // Record layout: 64-bit fields first (sums, and MIN / MAX of 8-byte columns),
 // then 32-bit ones, so that every 64-bit field is 8-byte aligned. val_w: value
 // column widths (nullptr: all 4 bytes).
-AggSpec make_spec(const gj_agg *aggs, int n_aggs, void *const *outs, const int *val_w = nullptr) {
+AggSpec make_spec(const gj_agg *aggs, int n_aggs, void *const *outs, const int *val_w = nullptr,
+                  bool odd_records = false) {
     AggSpec s{};
     s.n = n_aggs;
-    int w = 0;
+    // even-word records: 64-bit fields first, then 32-bit ones
+    int w = 0, n64 = 0, first32 = -1;
     for (int pass = 0; pass < 2; ++pass) {
         for (int j = 0; j < n_aggs; ++j) {
             const int op = aggs[j].op;
@@ -1744,11 +1771,21 @@ AggSpec make_spec(const gj_agg *aggs, int n_aggs, void *const *outs, const int *
             s.w8[j] = w8 ? 1 : 0;
             s.word[j] = w;
             w += is64 ? 2 : 1;
+            n64 += is64 ? 1 : 0;
+            if (!is64 && first32 < 0) first32 = j;
             s.out[j] = outs[j];
         }
     }
-    s.words = (w + 1) & ~1;
-    if (s.words == 0) s.words = 2;
+    // odd-word records (an odd size needs a 32-bit field): that field first, the
+    // 64-bit fields from word 1, the other 32-bit fields after them
+    if (!odd_records) w = (w + 1) & ~1;  // padded to an even size
+    for (int j = 0; j < n_aggs; ++j) {
+        if (w % 2 == 0) s.word_odd[j] = s.word[j];
+        else if (j == first32) s.word_odd[j] = 0;
+        else if (s.word[j] < 2 * n64) s.word_odd[j] = s.word[j] + 1;
+        else s.word_odd[j] = s.word[j] < s.word[first32] ? s.word[j] + 1 : s.word[j];
+    }
+    s.words = w > 0 ? w : 2;
     return s;
 }
 
@@ -2180,9 +2217,10 @@ int64_t groupby_hash(Ctx &ctx, int key_bytes, const void *key, const ValCols &vc
     // then finds the prefix keys already present.
     const int n_vals = vc.n;
     std::vector<void *> no_outs(n_aggs, nullptr);
-    const size_t rec = (size_t)make_spec(aggs, n_aggs, no_outs.data(), vc.width).words * 4;
+    const size_t rec_even = (size_t)make_spec(aggs, n_aggs, no_outs.data(), vc.width, false).words * 4;
+    const size_t rec_odd = (size_t)make_spec(aggs, n_aggs, no_outs.data(), vc.width, true).words * 4;
     const size_t budget = std::min(lds_budget > 0 ? (size_t)lds_budget : (size_t)64 * 1024, (size_t)64 * 1024);
-    const uint32_t prefix = (uint32_t)std::max<size_t>(2048, 2 * (budget / rec));
+    const uint32_t prefix = (uint32_t)std::max<size_t>(2048, 2 * (budget / rec_even));
     const uint32_t g = hgb_assign_ids(ctx, a, key_bytes, key, n, prefix, g_est, occupancy);
     *out_key = ctx.output((size_t)std::max<uint32_t>(g, 1) * key_bytes);
     std::vector<void *> outs(n_aggs);
@@ -2191,13 +2229,8 @@ int64_t groupby_hash(Ctx &ctx, int key_bytes, const void *key, const ValCols &vc
         out_aggs[j] = outs[j];
     }
     if (g == 0) return 0;
-    a.spec = make_spec(aggs, n_aggs, outs.data(), vc.width);
     a.vals = val_src(vc);
     a.g = g;
-    init_outputs(st, a.spec, g);
-    // stage 2 reads each row's values and its group id (gid_loc and gid[gid_loc], or
-    // the resolved id once for several slices), and writes every group once
-    double bytes = (double)n * (val_bytes(vc) + 8.0) + (double)g * (key_bytes + 4.0 * a.spec.words);
     const bool v64 = any_wide(vc);
     const int nvt = nv_tier(n_vals);
     // is_smem_enough, per slice: when the groups fit the LDS of a workgroup (at
@@ -2206,13 +2239,28 @@ int64_t groupby_hash(Ctx &ctx, int key_bytes, const void *key, const ValCols &vc
     const size_t max_lds = (size_t)160 * 1024;
     const size_t sbudget = std::min(lds_budget > 0 ? (size_t)lds_budget : max_lds, max_lds);
     const size_t fixed = kSpareWords * 4 + 16;  // spare words, alignment of the queues
-    const auto groups_in = [&](size_t bytes) -> size_t { return bytes > fixed + rec ? (bytes - fixed) / rec - 1 : 0; };
     // several slices also need the row queues (for the workgroup size they will run)
     const bool q_wide = sbudget > max_lds / 4;
     const size_t qbytes = hgb_queue_bytes(nvt, v64 ? 8 : 4, q_wide ? 1024u : kBlock);
-    const size_t per_one = groups_in(sbudget);
-    const size_t per_wg = g <= per_one ? per_one : groups_in(sbudget > qbytes ? sbudget - qbytes : 0);
-    const uint32_t slices = per_wg >= 64 ? (uint32_t)((g + per_wg - 1) / per_wg) : 0u;
+    const auto slices_for = [&](size_t rec) -> uint32_t {
+        const auto groups_in = [&](size_t bytes) -> size_t {
+            return bytes > fixed + rec ? (bytes - fixed) / rec - 1 : 0;
+        };
+        const size_t per_one = groups_in(sbudget);
+        const size_t per_wg = g <= per_one ? per_one : groups_in(sbudget > qbytes ? sbudget - qbytes : 0);
+        return per_wg >= 64 ? (uint32_t)((g + per_wg - 1) / per_wg) : 0u;
+    };
+    // Records without the padding word (odd sizes) hold about one group in nine more
+    // but cost a parity test per field and row: taken only where they save a slice.
+    const uint32_t s_even = slices_for(rec_even), s_odd = slices_for(rec_odd);
+    const bool odd = s_odd >= 1 && s_odd <= kHgbMaxSlices && (s_even == 0 || s_even > kHgbMaxSlices || s_odd < s_even);
+    const uint32_t slices = odd ? s_odd : s_even;
+    const size_t rec = odd ? rec_odd : rec_even;
+    a.spec = make_spec(aggs, n_aggs, outs.data(), vc.width, odd);
+    init_outputs(st, a.spec, g);
+    // stage 2 reads each row's values and its group id (gid_loc and gid[gid_loc], or
+    // the resolved id once for several slices), and writes every group once
+    double bytes = (double)n * (val_bytes(vc) + 8.0) + (double)g * (key_bytes + 4.0 * a.spec.words);
     if (g > 2 && slices >= 1 && slices <= kHgbMaxSlices) {
         a.slices = slices;
         a.slice_groups = ceil_div_u32(g, slices);
@@ -2235,8 +2283,11 @@ int64_t groupby_hash(Ctx &ctx, int key_bytes, const void *key, const ValCols &vc
             bytes -= 4.0 * n;
         }
         const uint32_t sgrid = chunks * slices;
-#define GJ_HAGG_S(NV, BT, V) \
-    GJ_LAUNCH("k_hgb_aggregate", bytes, (k_hgb_aggregate_sliced<NV, BT, V>), dim3(sgrid), dim3(BT), alds, st, a)
+#define GJ_HAGG_S(NV, BT, V)                                                                                       \
+    if (odd) GJ_LAUNCH("k_hgb_aggregate", bytes, (k_hgb_aggregate_sliced<NV, BT, V, true>), dim3(sgrid), dim3(BT),  \
+                       alds, st, a);                                                                                  \
+    else GJ_LAUNCH("k_hgb_aggregate", bytes, (k_hgb_aggregate_sliced<NV, BT, V, false>), dim3(sgrid), dim3(BT), alds, \
+                   st, a)
 #define GJ_HAGG_S_NV(BT, V) \
     if (nvt == 1) GJ_HAGG_S(1, BT, V); else if (nvt == 2) GJ_HAGG_S(2, BT, V); \
     else if (nvt == 4) GJ_HAGG_S(4, BT, V); else GJ_HAGG_S(8, BT, V)
