@@ -1602,6 +1602,22 @@ __device__ __forceinline__ Acc<NV, V> acc_shfl_up(const Acc<NV, V> &x, int d) {
 }
 
 // Segmented combine: (f1, A1) then (f2, A2) = (f1 | f2, f2 ? A2 : A1 + A2).
+// IT consecutive values of T from p (16-byte aligned: a run starts at a multiple
+// of 16 rows), in 16-byte loads.
+template <typename T, int IT>
+__device__ __forceinline__ void sgb_load_vec(const T *__restrict__ p, T (&out)[IT]) {
+    constexpr int PER = 16 / (int)sizeof(T);  // values per 16-byte load
+    static_assert(IT % PER == 0, "whole 16-byte loads");
+    const uint4 *__restrict__ q = reinterpret_cast<const uint4 *>(p);
+#pragma unroll
+    for (int l = 0; l < IT / PER; ++l) {
+        const uint4 v = q[l];
+        const T *t = reinterpret_cast<const T *>(&v);
+#pragma unroll
+        for (int e = 0; e < PER; ++e) out[l * PER + e] = t[e];
+    }
+}
+
 template <typename K, int NV, typename V = int>
 __global__ __launch_bounds__(kBlock) void k_sgb_reduce(SgbArgs a) {
     constexpr int IT = kSgbItems;
@@ -1614,13 +1630,38 @@ __global__ __launch_bounds__(kBlock) void k_sgb_reduce(SgbArgs a) {
     const uint32_t first = t0 + tid * IT;  // this thread's rows: [first, first + IT)
     K kk[IT];
     Row<NV, V> rr[IT];
+    if (first + IT <= a.n && !a.vals.rowid) {
+        // a full run of consecutive rows: 16-byte loads (each lane's rows are
+        // contiguous, so a wave's 4-byte loads would touch 64 lines per instruction)
+        sgb_load_vec<K>(keys + first, kk);
 #pragma unroll
-    for (int k = 0; k < IT; ++k) {
-        const uint32_t i = first + k;
-        kk[k] = K(0);
-        if (i < a.n) {
-            kk[k] = keys[i];
-            rr[k] = load_row<NV, V>(a.vals, i);
+        for (int c = 0; c < NV; ++c) {
+            if (c < a.vals.n) {
+                if (sizeof(V) == 8 && a.vals.w8[c]) {
+                    long long t[IT];
+                    sgb_load_vec<long long>(static_cast<const long long *>(a.vals.col[c]) + first, t);
+#pragma unroll
+                    for (int k = 0; k < IT; ++k) rr[k].v[c] = (V)t[k];
+                } else {
+                    int t[IT];
+                    sgb_load_vec<int>(static_cast<const int *>(a.vals.col[c]) + first, t);
+#pragma unroll
+                    for (int k = 0; k < IT; ++k) rr[k].v[c] = (V)t[k];
+                }
+            } else {
+#pragma unroll
+                for (int k = 0; k < IT; ++k) rr[k].v[c] = V(0);
+            }
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < IT; ++k) {
+            const uint32_t i = first + k;
+            kk[k] = K(0);
+            if (i < a.n) {
+                kk[k] = keys[i];
+                rr[k] = load_row<NV, V>(a.vals, i);
+            }
         }
     }
     K prev = (first > 0 && first <= a.n) ? keys[first - 1] : K(0);
