@@ -124,4 +124,35 @@ __device__ __forceinline__ uint32_t bucket_of(K key, int skip_bits, int log2b) {
 
 __host__ __device__ constexpr uint32_t ceil_div_u32(uint32_t a, uint32_t b) { return (a + b - 1) / b; }
 
+// A thread's run of IT consecutive values of T at p (16-byte aligned), moved in
+// 16-byte accesses. Where each lane of a wave owns a run, plain element accesses
+// would touch one line per lane and instruction; these touch each line once.
+template <typename T, int IT>
+__device__ __forceinline__ void load_run16(const T *__restrict__ p, T (&out)[IT]) {
+    constexpr int PER = 16 / (int)sizeof(T);  // values per 16-byte access
+    static_assert(IT % PER == 0, "whole 16-byte accesses");
+    const uint4 *__restrict__ q = reinterpret_cast<const uint4 *>(p);
+#pragma unroll
+    for (int l = 0; l < IT / PER; ++l) {
+        const uint4 v = q[l];
+        const T *t = reinterpret_cast<const T *>(&v);
+#pragma unroll
+        for (int e = 0; e < PER; ++e) out[l * PER + e] = t[e];
+    }
+}
+template <typename T, int IT>
+__device__ __forceinline__ void store_run16(T *__restrict__ p, const T (&in)[IT]) {
+    constexpr int PER = 16 / (int)sizeof(T);
+    static_assert(IT % PER == 0, "whole 16-byte accesses");
+    uint4 *__restrict__ q = reinterpret_cast<uint4 *>(p);
+#pragma unroll
+    for (int l = 0; l < IT / PER; ++l) {
+        uint4 v;
+        T *t = reinterpret_cast<T *>(&v);
+#pragma unroll
+        for (int e = 0; e < PER; ++e) t[e] = in[l * PER + e];
+        q[l] = v;
+    }
+}
+
 }  // namespace gj

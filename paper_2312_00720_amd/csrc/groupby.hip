@@ -764,36 +764,54 @@ __global__ __launch_bounds__(kBlock) void k_pgb_discover(PgbArgs a) {
         }
         return;
     }
-    // ids in order of first occurrence: a block scan over head flags in row order,
-    // each thread taking 16 consecutive rows so that one scan covers 4096 rows
+    // ids in order of first occurrence. Rows are read coalesced: round r of a
+    // 4096-row chunk is rows c0 + 256 r + tid, so row order is (round, wave, lane).
+    // Every (round, wave) counts its heads by ballot; one barrier later each thread
+    // knows how many heads come before its row from those counts and its rank.
     K *__restrict__ tk = static_cast<K *>(a.tmp_keys);
     constexpr int HB = 16;
+    __shared__ uint32_t s_rw[HB][kWaves];
+    const int w = tid / kWave;
     uint32_t ids = 0;
     for (uint32_t c0 = p0; c0 < p1; c0 += kBlock * HB) {
-        const uint32_t mine = c0 + tid * HB;
         K kk[HB];
-        uint32_t hmask = 0, hc = 0;
-#pragma unroll
-        for (int r = 0; r < HB; ++r) kk[r] = mine + r < p1 ? keys[mine + r] : e;
 #pragma unroll
         for (int r = 0; r < HB; ++r) {
-            const uint32_t i = mine + r;
+            const uint32_t i = c0 + r * kBlock + tid;
+            kk[r] = i < p1 ? keys[i] : e;
+        }
+        uint32_t hmask = 0, rk[HB];
+#pragma unroll
+        for (int r = 0; r < HB; ++r) {
+            const uint32_t i = c0 + r * kBlock + tid;
+            bool head = false;
             if (i < p1) {
                 const uint32_t local = i - p0;
-                const bool head = (kk[r] == e) ? (s_sent == local)
-                                               : (s_first[lds_find<K>(s_key, log2cap, kk[r])] == local);
-                if (head) {
-                    hmask |= 1u << r;
-                    ++hc;
-                }
+                head = (kk[r] == e) ? (s_sent == local) : (s_first[lds_find<K>(s_key, log2cap, kk[r])] == local);
             }
+            const uint64_t m = __ballot(head);
+            rk[r] = rank_below(m);
+            if (head) hmask |= 1u << r;
+            if (lane_id() == 0) s_rw[r][w] = (uint32_t)__popcll(m);
         }
-        uint32_t tot;
-        uint32_t pre = block_exclusive_sum<uint32_t>(hc, s_tmp, &tot);
+        __syncthreads();
+        uint32_t before = 0, tot = 0;  // heads before (round r, this wave), and in the chunk
 #pragma unroll
-        for (int r = 0; r < HB; ++r)
-            if (hmask & (1u << r)) tk[p0 + ids + pre++] = kk[r];
+        for (int r = 0; r < HB; ++r) {
+#pragma unroll
+            for (int q = 0; q < kWaves; ++q) {
+                const uint32_t c = s_rw[r][q];
+                if (q < w) before += c;
+                tot += c;
+            }
+            if (hmask & (1u << r)) tk[p0 + ids + before + rk[r]] = kk[r];
+            // the rest of round r (this and later waves) precedes round r + 1
+#pragma unroll
+            for (int q = 0; q < kWaves; ++q)
+                if (q >= w) before += s_rw[r][q];
+        }
         ids += tot;
+        __syncthreads();  // the counts are rewritten by the next chunk
     }
     if (tid == 0) {
         a.gcnt[p] = ids;
@@ -1602,22 +1620,6 @@ __device__ __forceinline__ Acc<NV, V> acc_shfl_up(const Acc<NV, V> &x, int d) {
 }
 
 // Segmented combine: (f1, A1) then (f2, A2) = (f1 | f2, f2 ? A2 : A1 + A2).
-// IT consecutive values of T from p (16-byte aligned: a run starts at a multiple
-// of 16 rows), in 16-byte loads.
-template <typename T, int IT>
-__device__ __forceinline__ void sgb_load_vec(const T *__restrict__ p, T (&out)[IT]) {
-    constexpr int PER = 16 / (int)sizeof(T);  // values per 16-byte load
-    static_assert(IT % PER == 0, "whole 16-byte loads");
-    const uint4 *__restrict__ q = reinterpret_cast<const uint4 *>(p);
-#pragma unroll
-    for (int l = 0; l < IT / PER; ++l) {
-        const uint4 v = q[l];
-        const T *t = reinterpret_cast<const T *>(&v);
-#pragma unroll
-        for (int e = 0; e < PER; ++e) out[l * PER + e] = t[e];
-    }
-}
-
 template <typename K, int NV, typename V = int>
 __global__ __launch_bounds__(kBlock) void k_sgb_reduce(SgbArgs a) {
     constexpr int IT = kSgbItems;
@@ -1633,18 +1635,18 @@ __global__ __launch_bounds__(kBlock) void k_sgb_reduce(SgbArgs a) {
     if (first + IT <= a.n && !a.vals.rowid) {
         // a full run of consecutive rows: 16-byte loads (each lane's rows are
         // contiguous, so a wave's 4-byte loads would touch 64 lines per instruction)
-        sgb_load_vec<K>(keys + first, kk);
+        load_run16<K>(keys + first, kk);
 #pragma unroll
         for (int c = 0; c < NV; ++c) {
             if (c < a.vals.n) {
                 if (sizeof(V) == 8 && a.vals.w8[c]) {
                     long long t[IT];
-                    sgb_load_vec<long long>(static_cast<const long long *>(a.vals.col[c]) + first, t);
+                    load_run16<long long>(static_cast<const long long *>(a.vals.col[c]) + first, t);
 #pragma unroll
                     for (int k = 0; k < IT; ++k) rr[k].v[c] = (V)t[k];
                 } else {
                     int t[IT];
-                    sgb_load_vec<int>(static_cast<const int *>(a.vals.col[c]) + first, t);
+                    load_run16<int>(static_cast<const int *>(a.vals.col[c]) + first, t);
 #pragma unroll
                     for (int k = 0; k < IT; ++k) rr[k].v[c] = (V)t[k];
                 }

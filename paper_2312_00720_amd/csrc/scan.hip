@@ -74,20 +74,38 @@ __global__ __launch_bounds__(kBlock) void k_scan_down(const T *in, T *out, uint6
     const uint64_t n = scan_len(nmax, n_dev, mult);
     if ((uint64_t)blockIdx.x * kTile >= n) return;
     const uint64_t first = (uint64_t)blockIdx.x * kTile + (uint64_t)threadIdx.x * kItems;
+    // a whole run of this thread's items at 16-byte aligned addresses moves in
+    // 16-byte accesses
+    const bool vec = first + kItems <= n && (((uintptr_t)in | (uintptr_t)out) & 15u) == 0;
     T v[kItems];
     T sum = 0;
+    if (vec) {
+        load_run16<T>(in + first, v);
+    } else {
 #pragma unroll
-    for (int k = 0; k < kItems; ++k) {
-        const uint64_t i = first + k;
-        v[k] = i < n ? in[i] : T(0);
-        sum += v[k];
+        for (int k = 0; k < kItems; ++k) {
+            const uint64_t i = first + k;
+            v[k] = i < n ? in[i] : T(0);
+        }
     }
-    T run = partial[blockIdx.x] + block_exclusive_sum<T>(sum, s_tmp, (T *)nullptr);
 #pragma unroll
-    for (int k = 0; k < kItems; ++k) {
-        const uint64_t i = first + k;
-        if (i < n) out[i] = run;
-        run += v[k];
+    for (int k = 0; k < kItems; ++k) sum += v[k];
+    T run = partial[blockIdx.x] + block_exclusive_sum<T>(sum, s_tmp, (T *)nullptr);
+    if (vec) {
+        T o[kItems];
+#pragma unroll
+        for (int k = 0; k < kItems; ++k) {
+            o[k] = run;
+            run += v[k];
+        }
+        store_run16<T>(out + first, o);
+    } else {
+#pragma unroll
+        for (int k = 0; k < kItems; ++k) {
+            const uint64_t i = first + k;
+            if (i < n) out[i] = run;
+            run += v[k];
+        }
     }
 }
 
