@@ -267,7 +267,7 @@ def main(argv=None) -> int:
     ap.add_argument("--train", type=int, default=20000)
     ap.add_argument("--test", type=int, default=2000)
     ap.add_argument("--steps", type=int, default=3000)
-    ap.add_argument("--out", default="gpurun_out/selector")
+    ap.add_argument("--out", default="selector_out")
     ap.add_argument("--data", default=None, help="reuse timings from this .npz (no re-timing)")
     ap.add_argument("--part", type=int, default=None)
     ap.add_argument("--parts", type=int, default=1)
