@@ -183,7 +183,7 @@ def bench_micro(args, copy_gbs) -> int:
         "partition_plus_clustered_speedup": t_u / (t_p + t_c),
         "roofline": {"bound": "hbm", "kernel": "k_gather (clustered)", "achieved": 12.0 * n / (t_c / 1e3) / 1e9,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": 12.0 * n / (t_c / 1e3) / 1e9 / HBM_PEAK_GBS,
-                     "traffic": None},
+                     "traffic": None, "alg_bytes_per_launch": 12.0 * n, "avg_launch_ms": t_c},
     }
     print(json.dumps(res), flush=True)
     return 0
@@ -248,6 +248,17 @@ def kernel_table(stats, steps):
     return dict(sorted(kern.items(), key=lambda x: -x[1]["total_ms"]))
 
 
+def roofline(dom, dk, traffic=None,
+             source="HIP events around every launch of the profiled run, on the library's stream"):
+    """Roofline object of the dominant kernel: algorithmic bytes per launch over
+    its average launch time (both from per-launch HIP events)."""
+    return {"bound": "hbm", "kernel": dom, "achieved": dk["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": dk["gbs"] / HBM_PEAK_GBS, "traffic": traffic,
+            "alg_bytes_per_launch": dk["alg_bytes"] / max(1, dk["launches"]),
+            "avg_launch_ms": dk["total_ms"] / max(1, dk["launches"]),
+            "source": source}
+
+
 def bench_groupby(args, copy_gbs) -> int:
     import torch
     import datagen
@@ -285,11 +296,10 @@ def bench_groupby(args, copy_gbs) -> int:
                                f"COUNT+SUM+MIN+MAX, {args.algo}" + ("" if args.algo == "hash" else f" {mat.upper()}"),
                    "groups": groups},
         "copy_ceiling_gbs": copy_gbs,
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": dk["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": dk["gbs"] / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(dom, f"groupby_{args.algo}_n{args.n_log2}_g{args.g_log2}")
-                     if args.alpha == 0 and mat in ("gftr", "auto") and args.radix_bits == 0
-                     and keys_desc == "int32 key" else None},
+        "roofline": roofline(dom, dk,
+                             measured_traffic(dom, f"groupby_{args.algo}_n{args.n_log2}_g{args.g_log2}")
+                             if args.alpha == 0 and mat in ("gftr", "auto") and args.radix_bits == 0
+                             and keys_desc == "int32 key" else None),
         "hbm_gbs_whole_step": sum(v["alg_bytes"] for v in stats.values()) / args.steps / (ms / 1e3) / 1e9,
         "profiled_ms_per_step": ms_prof,
         "kernels": {k: {"launches_per_step": v["launches"] / args.steps, "ms_per_step": v["ms_per_step"],
@@ -328,8 +338,7 @@ def bench_pipeline(args, copy_gbs) -> int:
                                "then group-by on the R payload, COUNT/SUM/MIN/MAX of the S payload, algorithm auto",
                    "groups": int(out[0].numel())},
         "copy_ceiling_gbs": copy_gbs,
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": dk["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": dk["gbs"] / HBM_PEAK_GBS, "traffic": None},
+        "roofline": roofline(dom, dk),
         "profiled_ms_per_step": ms_prof,
         "kernels": {k: {"launches_per_step": v["launches"] / args.steps, "ms_per_step": v["ms_per_step"],
                         "alg_gbs": v["gbs"]} for k, v in kern.items()},
@@ -422,9 +431,7 @@ def bench_batch(args, copy_gbs) -> int:
         "per_instance": {"ms": ms_single, "tuples_per_s": T / (ms_single / 1e3), "launches": single_launches},
         "speedup_vs_per_instance": ms_single / ms,
         "copy_ceiling_gbs": copy_gbs,
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": dk["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": dk["gbs"] / HBM_PEAK_GBS, "traffic": None,
-                     "source": "one eager run of the plan with per-launch events"},
+        "roofline": roofline(dom, dk, source="one eager run of the plan with per-launch events"),
         "kernels": {k: {"launches": v["launches"], "ms": v["ms_per_step"], "alg_gbs": v["gbs"]}
                     for k, v in kern.items()},
     }
@@ -507,9 +514,7 @@ def bench_gbbatch(args, copy_gbs) -> int:
         "per_instance": {"ms": ms_single, "rows_per_s": rows / (ms_single / 1e3), "launches": single_launches},
         "speedup_vs_per_instance": ms_single / ms,
         "copy_ceiling_gbs": copy_gbs,
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": dk["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": dk["gbs"] / HBM_PEAK_GBS, "traffic": None,
-                     "source": "one eager run of the plan with per-launch events"},
+        "roofline": roofline(dom, dk, source="one eager run of the plan with per-launch events"),
         "kernels": {k: {"launches": v["launches"], "ms": v["ms_per_step"], "alg_gbs": v["gbs"]}
                     for k, v in kern.items()},
     }
@@ -682,7 +687,6 @@ def main() -> int:
             for k, v in stats.items()}
     dom = max(kern, key=lambda k: kern[k]["total_ms"])
     dk = kern[dom]
-    achieved = dk["gbs"]
     alg_total = sum(v["alg_bytes"] for v in stats.values()) / args.steps
     # Phases as the paper counts them (Section 5.1): under GFTR, moving payload
     # columns through the partitioning passes is materialization work. One
@@ -724,12 +728,7 @@ def main() -> int:
         "profiled_ms_per_step": (t3 - t2) / args.steps * 1e3,
         "hbm_gbs_whole_step": alg_total / (ms / 1e3) / 1e9,
         "copy_ceiling_gbs": copy_gbs,
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(dom, "join_default") if default_join else None,
-                     "alg_bytes_per_launch": dk["alg_bytes"] / max(1, dk["launches"]),
-                     "avg_launch_ms": dk["total_ms"] / max(1, dk["launches"]),
-                     "source": "HIP events around every launch of the profiled run, on the library's stream"},
+        "roofline": roofline(dom, dk, measured_traffic(dom, "join_default") if default_join else None),
         "phases_ms": phases,
         "kernels": {k: {"launches_per_step": v["launches"] / args.steps, "ms_per_step": v["ms_per_step"],
                         "alg_gbs": v["gbs"]} for k, v in sorted(kern.items(), key=lambda x: -x[1]["total_ms"])},
