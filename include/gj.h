@@ -449,6 +449,9 @@ int gj_join_features(const gj_rel *R, const gj_rel *S, const gj_join_opts *opts,
 
 /* The feature vector an automatic group-by choice uses: reads the keys once on
  * `stream` (group-count estimate and varying key bytes) and synchronizes.
+ * The estimate comes from the sketch kernel gj_groupby runs for the same
+ * opts->algo and opts->radix_bits (automatic and partition choices also count a
+ * per-chunk hash histogram there); both kernels give the same estimate.
  * Scratch from `alloc` (NULL: hipMallocAsync). */
 int gj_groupby_features(gj_col key, int32_t n_vals, int64_t n_rows, const gj_groupby_opts *opts,
                         const gj_allocator *alloc, void *stream, float features[12]);

@@ -11,6 +11,7 @@ output columns.
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 import subprocess
 
@@ -55,6 +56,8 @@ def lib():
                                        ctypes.c_int, vp, vp]
         L.oracle_digit_source.restype = ctypes.c_uint64
         L.oracle_digit_source.argtypes = [ctypes.c_int, i64, ctypes.c_int]
+        L.oracle_hll_registers.restype = None
+        L.oracle_hll_registers.argtypes = [ctypes.c_int, vp, i64, ctypes.c_int, vp]
         L.oracle_hgb_ids.restype = i64
         L.oracle_hgb_ids.argtypes = [ctypes.c_int, vp, i64, vp, vp]
         _lib = L
@@ -206,6 +209,43 @@ def partition(keys: np.ndarray, lo: int, bits: int, mode: int = DIGIT_BITS):
 
 def digit_source(key: int, key_bytes: int, mode: int) -> int:
     return int(lib().oracle_digit_source(key_bytes, key, mode))
+
+
+def hll_registers(keys: np.ndarray, bits: int = 10) -> np.ndarray:
+    """HyperLogLog registers of the keys (see oracle_hll_registers)."""
+    keys = np.ascontiguousarray(keys)
+    regs = np.zeros(1 << bits, np.uint32)
+    lib().oracle_hll_registers(_key_bytes(keys), _ptr(keys), len(keys), bits, _ptr(regs))
+    return regs
+
+
+def hll_estimate(keys: np.ndarray, bits: int = 10) -> float:
+    """Distinct-key estimate of Flajolet et al. (2007) from hll_registers: the
+    raw estimate alpha_m m^2 / sum_j 2^-M[j] with alpha_m = 0.7213 / (1 + 1.079 / m)
+    (their constant for m >= 128), replaced by linear counting m ln(m / V) when
+    it is at most 5m/2 and V registers are still zero. The estimate is capped at
+    the row count (a reading of ours: n rows hold at most n distinct keys); with
+    no rows it is 0."""
+    n = len(keys)
+    if n == 0:
+        return 0.0
+    regs = hll_registers(keys, bits)
+    m = float(1 << bits)
+    raw = (0.7213 / (1.0 + 1.079 / m)) * m * m / float(np.sum(np.ldexp(1.0, -regs.astype(np.int64))))
+    zeros = int(np.count_nonzero(regs == 0))
+    est = m * math.log(m / zeros) if raw <= 2.5 * m and zeros > 0 else raw
+    return min(est, float(n))
+
+
+def varying_key_bytes(keys: np.ndarray) -> int:
+    """Key bytes (of the key width) whose value differs between some two rows:
+    the passes a radix sort of the raw keys cannot skip. 0 with no rows."""
+    keys = np.ascontiguousarray(keys)
+    if len(keys) == 0:
+        return 0
+    kb = _key_bytes(keys)
+    b = keys.view(np.uint8).reshape(len(keys), kb)
+    return int(np.count_nonzero((b != b[0]).any(axis=0)))
 
 
 def hgb_ids(keys: np.ndarray):

@@ -24,6 +24,9 @@
  *   oracle_hgb_ids           pinned: dictionary brute force, bijection invariant
  *   oracle_rows_fingerprint  pinned: equals the sum computed in Python
  *   oracle_join_fingerprint  pinned: equals the fingerprint of oracle_join_pairs
+ *   oracle_hll_registers     pinned: union is the register-wise max, duplicates
+ *                            change nothing, and the estimate built on it stays
+ *                            within the sketch's published error bound
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -273,6 +276,23 @@ static uint64_t digit_source(int64_t key, int key_bytes, int mode) {
  * published test vectors). */
 uint64_t oracle_digit_source(int key_bytes, int64_t key, int mode) {
     return digit_source(key, key_bytes, mode);
+}
+
+/* HyperLogLog registers (Flajolet, Fusy, Gandouet and Meunier, 2007) over the
+ * 32-bit MurmurHash3 finalizer of the keys (digit source mode 1): the top
+ * `bits` bits of a key's hash name its register, and the register keeps the
+ * largest position, counted from 1, of the first 1 bit among the remaining
+ * 32 - bits bits (33 - bits when they are all zero). regs has 2^bits entries. */
+void oracle_hll_registers(int key_bytes, const void *keys, int64_t n, int bits, uint32_t *regs) {
+    const uint32_t m = 1u << bits;
+    for (uint32_t j = 0; j < m; ++j) regs[j] = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        const uint32_t h = (uint32_t)digit_source(load_key(keys, key_bytes, i), key_bytes, 1);
+        const uint32_t j = h >> (32 - bits);
+        uint32_t rho = 1;
+        for (int b = 31 - bits; b >= 0 && !((h >> b) & 1u); --b) ++rho;
+        if (rho > regs[j]) regs[j] = rho;
+    }
 }
 
 typedef struct {

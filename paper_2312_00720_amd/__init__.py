@@ -679,9 +679,10 @@ def join_features(r_key, r_pay, s_key, s_pay, *, match_ratio_hint: float = 0.0, 
     return [f[i] for i in range(12)]
 
 
-def groupby_features(key: torch.Tensor, n_vals: int, *, skew_hint: float = 0.0):
-    """The feature vector gj_groupby's automatic choice uses (reads the keys once)."""
-    o = GroupByOpts(0, 0, 0, 0, 0.0, 0, float(skew_hint))
+def groupby_features(key: torch.Tensor, n_vals: int, *, skew_hint: float = 0.0, algo: str = "auto"):
+    """The feature vector gj_groupby's automatic choice uses (reads the keys once).
+    `algo` picks the sketch kernel gj_groupby would run for that algorithm."""
+    o = GroupByOpts(GB_ALGO[algo], 0, 0, 0, 0.0, 0, float(skew_hint))
     f = (ctypes.c_float * 12)()
     A = _TorchAllocator(key.device)
     _raise(lib().gj_groupby_features(_col(key), int(n_vals), key.numel(), ctypes.byref(o), ctypes.byref(A.struct),

@@ -523,7 +523,12 @@ int gj_groupby_features(gj_col key, int32_t n_vals, int64_t n_rows, const gj_gro
         const int kb = dtype_bytes(key.dtype);
         gj::Ctx ctx(alloc, (hipStream_t)stream);
         int varying = 0;
-        const double g_est = gj::estimate_groups(ctx, kb, key.data, (uint32_t)n_rows, &varying);
+        // the same sketch kernel gj_groupby runs for these options (with the
+        // per-chunk hash histogram for a partition pass, which is dropped here)
+        const bool want_hist = o.algo == GJ_GB_AUTO || (o.algo == GJ_GB_PARTITION && o.radix_bits == 0);
+        const uint32_t *hist8 = nullptr;
+        const double g_est =
+            gj::estimate_groups(ctx, kb, key.data, (uint32_t)n_rows, &varying, want_hist ? &hist8 : nullptr);
         gj::features_groupby(features, (double)n_rows, kb, n_vals, g_est, varying, o.skew_hint);
         return GJ_OK;
     } catch (const gj::Error &e) {

@@ -603,25 +603,37 @@ __device__ __forceinline__ int lds_find(const K *tab, int log2cap, K key) {
 
 constexpr int kHllBits = 10;
 
-// The same read also ORs and ANDs the order-preserving keys (bits[0], bits[1]):
-// their xor marks the key bytes that vary, i.e. the passes a radix sort of the
-// raw keys needs. With hist8, workgroup b reads chunk b (chunk_rows rows) and
-// also counts its rows per low 8 bits of the hash, the digit a single partition
-// pass of the partition-based group-by takes, so that pass reads no keys for
-// its histogram.
+// The same read also ORs and ANDs the key bits (bits[0], bits[1]): their xor
+// marks the key bytes that vary, i.e. the passes a radix sort of the raw keys
+// needs. With hist8, workgroup b reads chunk b (chunk_rows rows) and also
+// counts its rows per low 8 bits of the hash, the digit a single partition pass
+// of the partition-based group-by takes, so that pass reads no keys for its
+// histogram.
+template <typename K, bool HIST, typename B>
+__device__ __forceinline__ void hll_key(K k, uint32_t *s_reg, uint32_t *s_cnt, B &o, B &x) {
+    const uint32_t h = (uint32_t)digit_source<K>(k, kDigitHash);
+    const uint32_t wv = (h << kHllBits) | (1u << (kHllBits - 1));  // the bits below the index
+    atomicMax(&s_reg[h >> (32 - kHllBits)], (uint32_t)__clz((int)wv) + 1u);
+    if constexpr (HIST) atomicAdd(&s_cnt[h & 0xFFu], 1u);
+    o |= (B)k;
+    x &= (B)k;
+}
+
 template <typename K, bool HIST>
 __global__ __launch_bounds__(kBlock) void k_hll(const K *__restrict__ keys, uint32_t n, uint32_t *__restrict__ regs,
                                                 unsigned long long *__restrict__ bits, uint32_t chunk_rows,
                                                 uint32_t *__restrict__ hist8) {
-    constexpr int U = 16;  // keys loaded per thread before they are counted
+    constexpr int U = 16;                   // keys per thread and round
+    constexpr int V = 16 / (int)sizeof(K);  // keys per 16-byte load
+    using B = std::conditional_t<sizeof(K) == 4, uint32_t, unsigned long long>;
     __shared__ uint32_t s_reg[1 << kHllBits];
     __shared__ uint32_t s_cnt[HIST ? kWaves : 1][HIST ? 256 : 1];
     for (int i = threadIdx.x; i < (1 << kHllBits); i += kBlock) s_reg[i] = 0;
     if constexpr (HIST)
         for (int i = threadIdx.x; i < kWaves * 256; i += kBlock) (&s_cnt[0][0])[i] = 0;
     __syncthreads();
-    unsigned long long o = 0, x = ~0ull;
-    const int w = threadIdx.x / kWave;
+    B o = 0, x = ~B(0);
+    uint32_t *cnt = &s_cnt[HIST ? threadIdx.x / kWave : 0][0];
     uint32_t lo, hi, stride;
     if constexpr (HIST) {
         lo = blockIdx.x * chunk_rows;
@@ -632,7 +644,25 @@ __global__ __launch_bounds__(kBlock) void k_hll(const K *__restrict__ keys, uint
         hi = n;
         stride = gridDim.x * kBlock * U;
     }
-    for (uint32_t base = lo; base < hi; base += stride) {
+    uint32_t base = lo;
+    if ((reinterpret_cast<uintptr_t>(keys) & 15u) == 0) {
+        // whole rounds: a wave's 16-byte loads cover 1 KB of consecutive keys
+        // (rounds start at multiples of kBlock * U rows, so every load is aligned)
+        for (; (uint64_t)base + kBlock * U <= hi; base += stride) {
+            const uint4 *__restrict__ q = reinterpret_cast<const uint4 *>(keys + base) + threadIdx.x;
+            uint4 v[U / V];
+#pragma unroll
+            for (int j = 0; j < U / V; ++j) v[j] = q[j * kBlock];
+#pragma unroll
+            for (int j = 0; j < U / V; ++j) {
+                const K *t = reinterpret_cast<const K *>(&v[j]);
+#pragma unroll
+                for (int e = 0; e < V; ++e) hll_key<K, HIST, B>(t[e], s_reg, cnt, o, x);
+            }
+        }
+    }
+    // the rest (a partial round, or keys that are not 16-byte aligned), row by row
+    for (; base < hi; base += stride) {
         K k[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -640,25 +670,17 @@ __global__ __launch_bounds__(kBlock) void k_hll(const K *__restrict__ keys, uint
             k[u] = i < hi ? keys[i] : K(0);
         }
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            if (base + u * kBlock + threadIdx.x < hi) {
-                const uint32_t h = (uint32_t)digit_source<K>(k[u], kDigitHash);
-                const uint32_t wv = (h << kHllBits) | (1u << (kHllBits - 1));  // the bits below the index
-                atomicMax(&s_reg[h >> (32 - kHllBits)], (uint32_t)__clz((int)wv) + 1u);
-                if constexpr (HIST) atomicAdd(&s_cnt[w][h & 0xFFu], 1u);
-                const unsigned long long v = digit_source<K>(k[u], kDigitOrdered);
-                o |= v;
-                x &= v;
-            }
-        }
+        for (int u = 0; u < U; ++u)
+            if (base + u * kBlock + threadIdx.x < hi) hll_key<K, HIST, B>(k[u], s_reg, cnt, o, x);
     }
     for (int d = kWave / 2; d > 0; d >>= 1) {
         o |= __shfl_xor(o, d, kWave);
         x &= __shfl_xor(x, d, kWave);
     }
     if (lane_id() == 0) {
-        atomicOr(&bits[0], o);
-        atomicAnd(&bits[1], x);
+        // 4-byte keys leave the upper word alone (set in the AND, clear in the OR)
+        atomicOr(&bits[0], (unsigned long long)o);
+        atomicAnd(&bits[1], (unsigned long long)x | (sizeof(K) == 4 ? 0xFFFFFFFF00000000ull : 0ull));
     }
     __syncthreads();
     for (int i = threadIdx.x; i < (1 << kHllBits); i += kBlock)
@@ -1297,10 +1319,12 @@ __device__ __forceinline__ uint64_t global_slot_hash(K key) {
     return u ^ (u >> 31);
 }
 
+// Inserts row i (key k) from slot h on and returns the row whose insert holds
+// the key (gid_loc). The first row to claim a slot for its key takes the next
+// group id.
 template <typename K>
-__device__ __forceinline__ void hgb_insert_one(const HgbArgs &a, const K *keys, uint32_t i, K k) {
+__device__ __forceinline__ uint32_t hgb_insert_from(const HgbArgs &a, const K *keys, uint32_t i, K k, uint64_t h) {
     const uint64_t mask = (1ull << a.log2cap) - 1ull;
-    uint64_t h = global_slot_hash<K>(k) & mask;
     for (uint64_t step = 0; step <= mask && step < a.max_probe; ++step) {
         if constexpr (sizeof(K) == 4) {
             unsigned long long *t = static_cast<unsigned long long *>(a.table);
@@ -1315,14 +1339,10 @@ __device__ __forceinline__ void hgb_insert_one(const HgbArgs &a, const K *keys, 
                     const uint32_t g = atomicAdd(a.ngroups, 1u);
                     a.gid[i] = g;
                     static_cast<K *>(a.tmp_keys)[g] = k;
-                    a.gid_loc[i] = i;
-                    return;
+                    return i;
                 }
             }
-            if ((uint32_t)(cur >> 32) == (uint32_t)k) {
-                a.gid_loc[i] = (uint32_t)cur;
-                return;
-            }
+            if ((uint32_t)(cur >> 32) == (uint32_t)k) return (uint32_t)cur;
         } else {
             uint32_t *t = static_cast<uint32_t *>(a.table);
             uint32_t cur = t[h];  // as above: only an empty read may be stale
@@ -1332,24 +1352,27 @@ __device__ __forceinline__ void hgb_insert_one(const HgbArgs &a, const K *keys, 
                     const uint32_t g = atomicAdd(a.ngroups, 1u);
                     a.gid[i] = g;
                     static_cast<K *>(a.tmp_keys)[g] = k;
-                    a.gid_loc[i] = i;
-                    return;
+                    return i;
                 }
             }
-            if (keys[cur] == k) {
-                a.gid_loc[i] = cur;
-                return;
-            }
+            if (keys[cur] == k) return cur;
         }
         h = (h + 1) & mask;
     }
     atomicOr(&a.ngroups[1], 1u);  // no slot within the probe limit: the table is too small
+    return i;
 }
 
+// Algorithm 1, stage 1. Every round reads RB keys per thread and then their
+// home slots all at once: a row whose home slot already holds its key (every
+// row but a group's first, at low load) is settled by that one read. Only the
+// others probe on and claim slots, one by one. The gid_loc stores of a round
+// go out together at its end, so no table read waits behind them.
 template <typename K>
 __global__ __launch_bounds__(kBlock) void k_hgb_insert(HgbArgs a) {
-    constexpr int RB = 16;
+    constexpr int RB = 8;
     const K *__restrict__ keys = static_cast<const K *>(a.keys);
+    const uint64_t mask = (1ull << a.log2cap) - 1ull;
     const uint32_t stride = gridDim.x * kBlock * RB;
     for (uint32_t base = blockIdx.x * kBlock * RB; base < a.n; base += stride) {
         K kk[RB];
@@ -1358,11 +1381,155 @@ __global__ __launch_bounds__(kBlock) void k_hgb_insert(HgbArgs a) {
             const uint32_t i = base + r * kBlock + threadIdx.x;
             kk[r] = i < a.n ? keys[i] : K(0);
         }
+        uint32_t hs[RB], loc[RB];
+        if constexpr (sizeof(K) == 4) {
+            const unsigned long long *t = static_cast<const unsigned long long *>(a.table);
+            unsigned long long cur[RB];
+#pragma unroll
+            for (int r = 0; r < RB; ++r) {
+                hs[r] = (uint32_t)(global_slot_hash<K>(kk[r]) & mask);
+                cur[r] = t[hs[r]];
+            }
+#pragma unroll
+            for (int r = 0; r < RB; ++r)
+                loc[r] = (cur[r] != ~0ull && (uint32_t)(cur[r] >> 32) == (uint32_t)kk[r]) ? (uint32_t)cur[r]
+                                                                                          : 0xFFFFFFFFu;
+        } else {
+            const uint32_t *t = static_cast<const uint32_t *>(a.table);
+            uint32_t cur[RB];
+#pragma unroll
+            for (int r = 0; r < RB; ++r) {
+                hs[r] = (uint32_t)(global_slot_hash<K>(kk[r]) & mask);
+                cur[r] = t[hs[r]];
+            }
+            K ck[RB];
+#pragma unroll
+            for (int r = 0; r < RB; ++r) ck[r] = keys[cur[r] != 0xFFFFFFFFu ? cur[r] : 0u];
+#pragma unroll
+            for (int r = 0; r < RB; ++r) loc[r] = (cur[r] != 0xFFFFFFFFu && ck[r] == kk[r]) ? cur[r] : 0xFFFFFFFFu;
+        }
 #pragma unroll
         for (int r = 0; r < RB; ++r) {
             const uint32_t i = base + r * kBlock + threadIdx.x;
-            if (i < a.n) hgb_insert_one<K>(a, keys, i, kk[r]);
+            if (i < a.n && loc[r] == 0xFFFFFFFFu) loc[r] = hgb_insert_from<K>(a, keys, i, kk[r], hs[r]);
         }
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+            const uint32_t i = base + r * kBlock + threadIdx.x;
+            if (i < a.n) a.gid_loc[i] = loc[r];
+        }
+    }
+}
+
+// Stage 1 for 4-byte keys and a few thousand groups: each workgroup keeps the
+// keys it has resolved, with their gid_loc, in an LDS table (Fibonacci hashing,
+// linear probing over at most kCacheProbe slots), so that a row whose key the
+// workgroup has met before never touches the global table. Rows the cache does
+// not hold go to the global table exactly as in k_hgb_insert and are then
+// entered in the cache; the cache only remembers what the global table
+// answered, so the ids are the same. Entries are key << 32 | gid_loc
+// (gid_loc < 2^31, so no entry equals the empty ~0). Whole rounds move keys and
+// gid_loc as 16-byte runs of 4 rows (both arrays 16-byte aligned).
+constexpr int kInsBlock = 1024;
+constexpr int kInsRows = 8;  // rows per thread and round
+constexpr int kCacheProbe = 8;
+
+template <int LOG2C>
+__device__ __forceinline__ uint32_t cache_home(int32_t k) {
+    return ((uint32_t)k * 0x9E3779B1u) >> (32 - LOG2C);
+}
+
+template <int LOG2C, int RB>
+__device__ __forceinline__ void insert_cached_rows(const HgbArgs &a, unsigned long long *s_c, const int32_t (&kk)[RB],
+                                                   const uint32_t (&row)[RB], uint32_t valid, uint32_t (&loc)[RB]) {
+    constexpr uint32_t CM = (1u << LOG2C) - 1u;
+    uint32_t ch[RB];
+    uint32_t open = valid;  // bit r: row r still looks for its key in the cache
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+        ch[r] = cache_home<LOG2C>(kk[r]);
+        loc[r] = 0xFFFFFFFFu;
+    }
+    for (int p = 0; p < kCacheProbe && open; ++p) {
+        unsigned long long e[RB];
+#pragma unroll
+        for (int r = 0; r < RB; ++r) e[r] = ((open >> r) & 1u) ? s_c[(ch[r] + p) & CM] : 0ull;
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+            if (!((open >> r) & 1u)) continue;
+            if (e[r] == ~0ull) {
+                open &= ~(1u << r);  // an empty slot: the key is not cached
+            } else if ((uint32_t)(e[r] >> 32) == (uint32_t)kk[r]) {
+                loc[r] = (uint32_t)e[r];
+                open &= ~(1u << r);
+            }
+        }
+    }
+    uint32_t miss = 0;
+#pragma unroll
+    for (int r = 0; r < RB; ++r) miss |= (((valid >> r) & 1u) && loc[r] == 0xFFFFFFFFu ? 1u : 0u) << r;
+    if (!miss) return;
+    // misses (a workgroup's first rows of each key) one at a time
+    const int32_t *keys = static_cast<const int32_t *>(a.keys);
+    const uint64_t mask = (1ull << a.log2cap) - 1ull;
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+        if (!((miss >> r) & 1u)) continue;
+        loc[r] = hgb_insert_from<int32_t>(a, keys, row[r], kk[r], global_slot_hash<int32_t>(kk[r]) & mask);
+        const unsigned long long ent = ((unsigned long long)(uint32_t)kk[r] << 32) | loc[r];
+        for (int p = 0; p < kCacheProbe; ++p) {
+            const unsigned long long old = atomicCAS(&s_c[(ch[r] + p) & CM], ~0ull, ent);
+            if (old == ~0ull || (uint32_t)(old >> 32) == (uint32_t)kk[r]) break;
+        }
+    }
+}
+
+template <int LOG2C>
+__global__ __launch_bounds__(kInsBlock, 8) void k_hgb_insert_cached(HgbArgs a) {
+    constexpr int RB = kInsRows;
+    constexpr uint32_t kRound = (uint32_t)kInsBlock * RB;
+    __shared__ unsigned long long s_c[1u << LOG2C];
+    for (uint32_t j = threadIdx.x; j < (1u << LOG2C); j += kInsBlock) s_c[j] = ~0ull;
+    __syncthreads();
+    const int32_t *__restrict__ keys = static_cast<const int32_t *>(a.keys);
+    const uint32_t stride = gridDim.x * kRound;
+    uint32_t base = blockIdx.x * kRound;
+    for (; (uint64_t)base + kRound <= a.n; base += stride) {
+        // thread t: rows base + (j * kInsBlock + t) * 4 .. + 3, j < RB / 4
+        int32_t kk[RB];
+        uint32_t row[RB], loc[RB];
+#pragma unroll
+        for (int j = 0; j < RB / 4; ++j) {
+            const uint32_t r0 = base + (uint32_t)(j * kInsBlock + threadIdx.x) * 4u;
+            const int4 v = *reinterpret_cast<const int4 *>(keys + r0);
+            kk[4 * j] = v.x;
+            kk[4 * j + 1] = v.y;
+            kk[4 * j + 2] = v.z;
+            kk[4 * j + 3] = v.w;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) row[4 * j + e] = r0 + e;
+        }
+        insert_cached_rows<LOG2C, RB>(a, s_c, kk, row, (1u << RB) - 1u, loc);
+#pragma unroll
+        for (int j = 0; j < RB / 4; ++j)
+            *reinterpret_cast<uint4 *>(a.gid_loc + row[4 * j]) =
+                make_uint4(loc[4 * j], loc[4 * j + 1], loc[4 * j + 2], loc[4 * j + 3]);
+    }
+    // the last, partial round of this workgroup (if any), row by row
+    if (base < a.n) {
+        int32_t kk[RB];
+        uint32_t row[RB], loc[RB];
+        uint32_t valid = 0;
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+            row[r] = base + (uint32_t)r * kInsBlock + threadIdx.x;
+            kk[r] = row[r] < a.n ? keys[row[r]] : 0;
+            valid |= (row[r] < a.n ? 1u : 0u) << r;
+        }
+        insert_cached_rows<LOG2C, RB>(a, s_c, kk, row, valid, loc);
+#pragma unroll
+        for (int r = 0; r < RB; ++r)
+            if (row[r] < a.n) a.gid_loc[row[r]] = loc[r];
     }
 }
 
@@ -2224,7 +2391,17 @@ static uint32_t hgb_assign_ids(Ctx &ctx, HgbArgs &a, int key_bytes, const void *
         ap.n = prefix;
         if (key_bytes == 4) {
             GJ_LAUNCH("k_hgb_insert", 8.0 * prefix, k_hgb_insert<int32_t>, dim3(1), dim3(kBlock), 0, st, ap);
-            if (n > prefix) GJ_LAUNCH("k_hgb_insert", 8.0 * n, k_hgb_insert<int32_t>, dim3(grid), dim3(kBlock), 0, st, a);
+            if (n > prefix) {
+                // up to a few thousand groups: every workgroup caches the keys it
+                // resolved (an 8192-entry LDS table, at most three quarters full);
+                // a few dozen groups hit a handful of cached global slots anyway
+                if (g_est > 48.0 && g_est <= 6144.0 && ((uintptr_t)key & 15u) == 0 && ((uintptr_t)a.gid_loc & 15u) == 0)
+                    GJ_LAUNCH("k_hgb_insert", 8.0 * n, k_hgb_insert_cached<13>,
+                              dim3(std::min<uint32_t>(ceil_div_u32(n, kInsBlock * kInsRows), 512)), dim3(kInsBlock), 0, st,
+                              a);
+                else
+                    GJ_LAUNCH("k_hgb_insert", 8.0 * n, k_hgb_insert<int32_t>, dim3(grid), dim3(kBlock), 0, st, a);
+            }
         } else {
             GJ_LAUNCH("k_hgb_insert", 12.0 * prefix, k_hgb_insert<int64_t>, dim3(1), dim3(kBlock), 0, st, ap);
             if (n > prefix) GJ_LAUNCH("k_hgb_insert", 12.0 * n, k_hgb_insert<int64_t>, dim3(grid), dim3(kBlock), 0, st, a);

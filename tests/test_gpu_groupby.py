@@ -260,3 +260,30 @@ def test_eight_byte_values(algo, mat, kb, card, alpha):
     gk, gcols = check(d["key"], [d["vals"][0], v8], algo=algo, mat=mat, sorted_out=algo.startswith("sort"))
     assert gcols[2].dtype == np.int32 and gcols[5].dtype == np.int64
     check(d["key"], [v8], AGGS[:4], algo=algo, mat=mat)
+
+
+@pytest.mark.parametrize("kb", [4, 8])
+@pytest.mark.parametrize("n,card,alpha", [(1, 1, 0.0), (1000, 7, 0.0), (200003, 3000, 0.0),
+                                          (1 << 20, 1 << 16, 0.0), ((1 << 21) + 77, 1 << 20, 0.0),
+                                          (300001, 4096, 1.0)])
+@pytest.mark.parametrize("algo", ["auto", "hash"])
+def test_group_count_sketch_matches_oracle(kb, n, card, alpha, algo):
+    """The group-count estimate an automatic choice feeds the selector equals the
+    oracle's HyperLogLog estimate, through both sketch kernels (with the
+    partition histogram for automatic choices, without it for the hash
+    group-by's table sizing), and the varying key bytes match."""
+    import paper_2312_00720_amd as gj
+    from gpu_util import dev, say
+    d = datagen.groupby_input(n, card, 0, seed=datagen.seed_for(7, card + n), alpha=alpha)
+    keys = d["key"] if kb == 4 else datagen.widen_keys(d["key"])
+    say(f"sketch n={n} card={card} kb={kb} algo={algo}")
+    f = gj.groupby_features(dev(keys), 2, algo=algo)
+    # keys one element past a 16-byte boundary take the row-by-row loads
+    shifted = dev(np.concatenate([keys[:1], keys]))[1:]
+    assert shifted.data_ptr() % 16 != 0
+    assert gj.groupby_features(shifted, 2, algo=algo) == f
+    est = max(1.0, oracle.hll_estimate(keys))
+    # one float ulp: a register off by one moves this feature by far more
+    want = np.float32(np.log2(est) / 32.0)
+    assert abs(np.float32(f[3]) - want) <= np.spacing(want), (f[3], want)
+    assert f[6] == np.float32((oracle.varying_key_bytes(keys) or kb) / 8.0)
