@@ -609,21 +609,48 @@ constexpr int kHllBits = 10;
 // counts its rows per low 8 bits of the hash, the digit a single partition pass
 // of the partition-based group-by takes, so that pass reads no keys for its
 // histogram.
-template <typename K, bool HIST, typename B>
-__device__ __forceinline__ void hll_key(K k, uint32_t *s_reg, uint32_t *s_cnt, B &o, B &x) {
-    const uint32_t h = (uint32_t)digit_source<K>(k, kDigitHash);
-    const uint32_t wv = (h << kHllBits) | (1u << (kHllBits - 1));  // the bits below the index
-    atomicMax(&s_reg[h >> (32 - kHllBits)], (uint32_t)__clz((int)wv) + 1u);
-    if constexpr (HIST) atomicAdd(&s_cnt[h & 0xFFu], 1u);
-    o |= (B)k;
-    x &= (B)k;
+// U keys of the sketch read: their hash digits counted, their registers raised,
+// their bits ORed and ANDed. A register only grows, so a key whose rank does
+// not exceed the value read now cannot change it: the U registers are read
+// first and only larger ranks take an atomic (with few distinct keys nearly
+// none do, where atomics on one address would serialize a wave).
+template <typename K, bool HIST, typename B, int U>
+__device__ __forceinline__ void hll_keys(const K (&k)[U], uint32_t valid, uint32_t *s_reg, uint32_t *s_cnt, B &o,
+                                         B &x) {
+    uint32_t ir[U], cur[U];  // register index | rank << 16
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const bool ok = (valid >> u) & 1u;
+        const uint32_t h = (uint32_t)digit_source<K>(k[u], kDigitHash);
+        const uint32_t wv = (h << kHllBits) | (1u << (kHllBits - 1));  // the bits below the index
+        ir[u] = (h >> (32 - kHllBits)) | (ok ? ((uint32_t)__clz((int)wv) + 1u) << 16 : 0u);
+        if constexpr (HIST) {
+            // a wave whose rows all share one digit (few distinct keys) adds once
+            const uint32_t d = h & 0xFFu, d0 = __builtin_amdgcn_readfirstlane(d);
+            const uint32_t lanes = (uint32_t)__popcll(__ballot(ok));  // taken by the whole wave
+            if (__all(ok && d == d0)) {
+                if (lane_id() == 0) atomicAdd(&s_cnt[d0], lanes);
+            } else if (ok) {
+                atomicAdd(&s_cnt[d], 1u);
+            }
+        }
+        if (ok) {
+            o |= (B)k[u];
+            x &= (B)k[u];
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) cur[u] = s_reg[ir[u] & 0xFFFFu];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+        if ((ir[u] >> 16) > cur[u]) atomicMax(&s_reg[ir[u] & 0xFFFFu], ir[u] >> 16);
 }
 
 template <typename K, bool HIST>
 __global__ __launch_bounds__(kBlock) void k_hll(const K *__restrict__ keys, uint32_t n, uint32_t *__restrict__ regs,
                                                 unsigned long long *__restrict__ bits, uint32_t chunk_rows,
                                                 uint32_t *__restrict__ hist8) {
-    constexpr int U = 16;                   // keys per thread and round
+    constexpr int U = sizeof(K) == 4 ? 16 : 8;  // keys per thread and round
     constexpr int V = 16 / (int)sizeof(K);  // keys per 16-byte load
     using B = std::conditional_t<sizeof(K) == 4, uint32_t, unsigned long long>;
     __shared__ uint32_t s_reg[1 << kHllBits];
@@ -653,25 +680,31 @@ __global__ __launch_bounds__(kBlock) void k_hll(const K *__restrict__ keys, uint
             uint4 v[U / V];
 #pragma unroll
             for (int j = 0; j < U / V; ++j) v[j] = q[j * kBlock];
+            // the keys in two halves keep the register count down
 #pragma unroll
-            for (int j = 0; j < U / V; ++j) {
-                const K *t = reinterpret_cast<const K *>(&v[j]);
+            for (int half = 0; half < 2; ++half) {
+                K k[U / 2];
 #pragma unroll
-                for (int e = 0; e < V; ++e) hll_key<K, HIST, B>(t[e], s_reg, cnt, o, x);
+                for (int e = 0; e < U / 2; ++e)
+                    k[e] = reinterpret_cast<const K *>(&v[0])[half * (U / 2) + e];
+                hll_keys<K, HIST, B, U / 2>(k, (1u << (U / 2)) - 1u, s_reg, cnt, o, x);
             }
         }
     }
     // the rest (a partial round, or keys that are not 16-byte aligned), row by row
     for (; base < hi; base += stride) {
-        K k[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const uint32_t i = base + u * kBlock + threadIdx.x;
-            k[u] = i < hi ? keys[i] : K(0);
+        for (int half = 0; half < 2; ++half) {
+            K k[U / 2];
+            uint32_t valid = 0;
+#pragma unroll
+            for (int u = 0; u < U / 2; ++u) {
+                const uint32_t i = base + (half * (U / 2) + u) * kBlock + threadIdx.x;
+                k[u] = i < hi ? keys[i] : K(0);
+                valid |= (i < hi ? 1u : 0u) << u;
+            }
+            hll_keys<K, HIST, B, U / 2>(k, valid, s_reg, cnt, o, x);
         }
-#pragma unroll
-        for (int u = 0; u < U; ++u)
-            if (base + u * kBlock + threadIdx.x < hi) hll_key<K, HIST, B>(k[u], s_reg, cnt, o, x);
     }
     for (int d = kWave / 2; d > 0; d >>= 1) {
         o |= __shfl_xor(o, d, kWave);
@@ -1363,14 +1396,13 @@ __device__ __forceinline__ uint32_t hgb_insert_from(const HgbArgs &a, const K *k
     return i;
 }
 
-// Algorithm 1, stage 1. Every round reads RB keys per thread and then their
-// home slots all at once: a row whose home slot already holds its key (every
-// row but a group's first, at low load) is settled by that one read. Only the
-// others probe on and claim slots, one by one. The gid_loc stores of a round
-// go out together at its end, so no table read waits behind them.
+// Algorithm 1, stage 1: every row in turn probes the global table from its
+// home slot. (Reading a round's home slots together first was faster with a
+// few dozen groups but 10-20% slower from 2^14 groups up; the cached kernel
+// below serves the small counts.)
 template <typename K>
 __global__ __launch_bounds__(kBlock) void k_hgb_insert(HgbArgs a) {
-    constexpr int RB = 8;
+    constexpr int RB = 16;
     const K *__restrict__ keys = static_cast<const K *>(a.keys);
     const uint64_t mask = (1ull << a.log2cap) - 1ull;
     const uint32_t stride = gridDim.x * kBlock * RB;
@@ -1381,42 +1413,10 @@ __global__ __launch_bounds__(kBlock) void k_hgb_insert(HgbArgs a) {
             const uint32_t i = base + r * kBlock + threadIdx.x;
             kk[r] = i < a.n ? keys[i] : K(0);
         }
-        uint32_t hs[RB], loc[RB];
-        if constexpr (sizeof(K) == 4) {
-            const unsigned long long *t = static_cast<const unsigned long long *>(a.table);
-            unsigned long long cur[RB];
-#pragma unroll
-            for (int r = 0; r < RB; ++r) {
-                hs[r] = (uint32_t)(global_slot_hash<K>(kk[r]) & mask);
-                cur[r] = t[hs[r]];
-            }
-#pragma unroll
-            for (int r = 0; r < RB; ++r)
-                loc[r] = (cur[r] != ~0ull && (uint32_t)(cur[r] >> 32) == (uint32_t)kk[r]) ? (uint32_t)cur[r]
-                                                                                          : 0xFFFFFFFFu;
-        } else {
-            const uint32_t *t = static_cast<const uint32_t *>(a.table);
-            uint32_t cur[RB];
-#pragma unroll
-            for (int r = 0; r < RB; ++r) {
-                hs[r] = (uint32_t)(global_slot_hash<K>(kk[r]) & mask);
-                cur[r] = t[hs[r]];
-            }
-            K ck[RB];
-#pragma unroll
-            for (int r = 0; r < RB; ++r) ck[r] = keys[cur[r] != 0xFFFFFFFFu ? cur[r] : 0u];
-#pragma unroll
-            for (int r = 0; r < RB; ++r) loc[r] = (cur[r] != 0xFFFFFFFFu && ck[r] == kk[r]) ? cur[r] : 0xFFFFFFFFu;
-        }
 #pragma unroll
         for (int r = 0; r < RB; ++r) {
             const uint32_t i = base + r * kBlock + threadIdx.x;
-            if (i < a.n && loc[r] == 0xFFFFFFFFu) loc[r] = hgb_insert_from<K>(a, keys, i, kk[r], hs[r]);
-        }
-#pragma unroll
-        for (int r = 0; r < RB; ++r) {
-            const uint32_t i = base + r * kBlock + threadIdx.x;
-            if (i < a.n) a.gid_loc[i] = loc[r];
+            if (i < a.n) a.gid_loc[i] = hgb_insert_from<K>(a, keys, i, kk[r], global_slot_hash<K>(kk[r]) & mask);
         }
     }
 }
@@ -1533,6 +1533,50 @@ __global__ __launch_bounds__(kInsBlock, 8) void k_hgb_insert_cached(HgbArgs a) {
     }
 }
 
+// Stage 2 for at most G groups: every thread folds its rows into one
+// accumulator per group in registers, and only at the end do the waves reduce
+// them into the workgroup's LDS records, which are then folded into the output.
+// (LDS records updated per row would have every lane of a wave contend for the
+// same few addresses.)
+template <int NV, typename V, int G>
+__global__ __launch_bounds__(kBlock) void k_hgb_aggregate_few(HgbArgs a) {
+    constexpr int RB = NV <= 2 ? 8 : 16 / NV;
+    extern __shared__ __align__(16) uint32_t s_dyn[];
+    const AggSpec &s = a.spec;
+    for (uint32_t i = threadIdx.x; i < a.g; i += kBlock) rec_init(s_dyn + (uint64_t)i * s.words, s);
+    __syncthreads();
+    Acc<NV, V> acc[G];
+#pragma unroll
+    for (int q = 0; q < G; ++q) acc_clear(acc[q]);
+    const uint32_t stride = gridDim.x * kBlock * RB;
+    for (uint32_t base = blockIdx.x * kBlock * RB; base < a.n; base += stride) {
+        uint32_t loc[RB], gid[RB];
+        Row<NV, V> rr[RB];
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+            const uint32_t i = base + r * kBlock + threadIdx.x;
+            loc[r] = i < a.n ? a.gid_loc[i] : 0u;
+            if (i < a.n) rr[r] = load_row<NV, V>(a.vals, i);
+        }
+#pragma unroll
+        for (int r = 0; r < RB; ++r) gid[r] = base + r * kBlock + threadIdx.x < a.n ? a.gid[loc[r]] : (uint32_t)G;
+#pragma unroll
+        for (int r = 0; r < RB; ++r)
+#pragma unroll
+            for (int q = 0; q < G; ++q)
+                if (gid[r] == (uint32_t)q) acc_row(acc[q], rr[r]);
+    }
+#pragma unroll
+    for (int q = 0; q < G; ++q) {
+        if ((uint32_t)q < a.g) {
+            const Acc<NV, V> x = acc_wave_reduce(acc[q]);
+            if (lane_id() == 0) rec_add_acc<NV, V>(s_dyn + (uint64_t)q * s.words, s, x);
+        }
+    }
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < a.g; i += kBlock) rec_flush(s_dyn + (uint64_t)i * s.words, s, i, true);
+}
+
 template <int NV, typename V = int>
 __global__ __launch_bounds__(kBlock) void k_hgb_aggregate(HgbArgs a) {
     constexpr int RB = NV <= 2 ? 8 : 16 / NV;
@@ -1543,7 +1587,6 @@ __global__ __launch_bounds__(kBlock) void k_hgb_aggregate(HgbArgs a) {
         for (uint32_t i = threadIdx.x; i < L; i += kBlock) rec_init(s_dyn + (uint64_t)i * s.words, s);
         __syncthreads();
     }
-    const bool few = a.g <= 2 && L == a.g;
     const uint32_t stride = gridDim.x * kBlock * RB;
     for (uint32_t base = blockIdx.x * kBlock * RB; base < a.n; base += stride) {
         uint32_t loc[RB], gid[RB];
@@ -1556,12 +1599,6 @@ __global__ __launch_bounds__(kBlock) void k_hgb_aggregate(HgbArgs a) {
         }
 #pragma unroll
         for (int r = 0; r < RB; ++r) gid[r] = a.gid[loc[r]];
-        if (few) {
-#pragma unroll
-            for (int r = 0; r < RB; ++r)
-                wave_aggregate<NV>(s_dyn, s, base + r * kBlock + threadIdx.x < a.n, gid[r], rr[r]);
-            continue;
-        }
         uint32_t off[RB];  // rows that do not use LDS point at the spare words
         bool any = false;
 #pragma unroll
@@ -2393,9 +2430,8 @@ static uint32_t hgb_assign_ids(Ctx &ctx, HgbArgs &a, int key_bytes, const void *
             GJ_LAUNCH("k_hgb_insert", 8.0 * prefix, k_hgb_insert<int32_t>, dim3(1), dim3(kBlock), 0, st, ap);
             if (n > prefix) {
                 // up to a few thousand groups: every workgroup caches the keys it
-                // resolved (an 8192-entry LDS table, at most three quarters full);
-                // a few dozen groups hit a handful of cached global slots anyway
-                if (g_est > 48.0 && g_est <= 6144.0 && ((uintptr_t)key & 15u) == 0 && ((uintptr_t)a.gid_loc & 15u) == 0)
+                // resolved (an 8192-entry LDS table, at most three quarters full)
+                if (g_est > 0.0 && g_est <= 6144.0 && ((uintptr_t)key & 15u) == 0 && ((uintptr_t)a.gid_loc & 15u) == 0)
                     GJ_LAUNCH("k_hgb_insert", 8.0 * n, k_hgb_insert_cached<13>,
                               dim3(std::min<uint32_t>(ceil_div_u32(n, kInsBlock * kInsRows), 512)), dim3(kInsBlock), 0, st,
                               a);
@@ -2481,7 +2517,23 @@ int64_t groupby_hash(Ctx &ctx, int key_bytes, const void *key, const ValCols &vc
     // stage 2 reads each row's values and its group id (gid_loc and gid[gid_loc], or
     // the resolved id once for several slices), and writes every group once
     double bytes = (double)n * (val_bytes(vc) + 8.0) + (double)g * (key_bytes + 4.0 * a.spec.words);
-    if (g > 2 && slices >= 1 && slices <= kHgbMaxSlices) {
+    // a handful of groups: register accumulators (four for up to two 4-byte value
+    // columns, else two)
+    const uint32_t few_max = (!v64 && nvt <= 2) ? 4u : 2u;
+    if (g <= few_max) {
+        a.lds_groups = g;
+        const size_t alds = ((size_t)g + 1) * rec + kSpareWords * 4;
+        const uint32_t fgrid = std::min<uint32_t>(grid, 2048);
+#define GJ_HFEW(NV, V, G)     GJ_LAUNCH("k_hgb_aggregate", bytes, (k_hgb_aggregate_few<NV, V, G>), dim3(fgrid), dim3(kBlock), alds, st, a)
+        if (v64) {
+            if (nvt == 1) GJ_HFEW(1, long long, 2); else if (nvt == 2) GJ_HFEW(2, long long, 2);
+            else if (nvt == 4) GJ_HFEW(4, long long, 2); else GJ_HFEW(8, long long, 2);
+        } else {
+            if (nvt == 1) GJ_HFEW(1, int, 4); else if (nvt == 2) GJ_HFEW(2, int, 4); else if (nvt == 4) GJ_HFEW(4, int, 2);
+            else GJ_HFEW(8, int, 2);
+        }
+#undef GJ_HFEW
+    } else if (slices >= 1 && slices <= kHgbMaxSlices) {
         a.slices = slices;
         a.slice_groups = ceil_div_u32(g, slices);
         const size_t rec_lds = ((((size_t)a.slice_groups + 1) * rec + kSpareWords * 4) + 15) & ~(size_t)15;

@@ -209,6 +209,26 @@ def test_hash_sliced_many_value_columns(nv, alpha):
     check(d["key"], d["vals"], aggs, algo="hash", lds_budget=24576)
 
 
+@pytest.mark.parametrize("g_card", [1, 2, 3, 4, 5])
+@pytest.mark.parametrize("nv,v64", [(1, False), (2, False), (4, False), (2, True), (8, True)])
+def test_hash_few_groups(g_card, nv, v64):
+    """A handful of groups (register accumulators per thread, folded once per
+    wave): every column type and count, int32 extremes in the values, a ragged
+    row count, and the automatic choice on the same input."""
+    n = 300007
+    d = datagen.groupby_input(n, g_card, nv, seed=datagen.seed_for(11, g_card * 10 + nv))
+    vals = d["vals"]
+    if v64:
+        g = datagen.rng(400 + g_card + nv)
+        vals = [g.integers(-2**62, 2**62, size=n, dtype=np.int64) for _ in range(nv)]
+        vals[0][:2] = [np.iinfo(np.int64).min, np.iinfo(np.int64).max]
+    else:
+        vals[0][:2] = [np.iinfo(np.int32).min, np.iinfo(np.int32).max]
+    aggs = [(0, "count")] + [(c, op) for c in range(nv) for op in ("sum", "min", "max")][:15]
+    check(d["key"], vals, aggs, algo="hash")
+    check(d["key"], vals, aggs, algo="auto")
+
+
 def test_hash_global_aggregation_path():
     d = datagen.groupby_input(100000, 2000, 2, seed=6)
     check(d["key"], d["vals"], algo="hash", lds_budget=64)
