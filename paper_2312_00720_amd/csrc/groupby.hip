@@ -2180,13 +2180,15 @@ int64_t groupby_partition(Ctx &ctx, int key_bytes, const void *key, const ValCol
     a.dubase = du;
     const uint32_t max_du = 2 * ceil_div_u32(n, kDiscoverUnit) + 1;
     a.dcount = ctx.scratch_n<uint32_t>(max_du);
+    // the two discovery kernels (partitions up to kDiscoverUnit rows, and slices of
+    // larger ones) share one tag: together they read the keys twice
     if (key_bytes == 4) {
         GJ_LAUNCH("k_pgb_discover", 8.0 * n, k_pgb_discover<int32_t>, dim3(np), dim3(kBlock), 0, st, a);
-        GJ_LAUNCH("k_pgb_discover_unit", 0.0, k_pgb_discover_unit<int32_t>, dim3(max_du), dim3(kBlock), 0, st, a);
+        GJ_LAUNCH("k_pgb_discover", 0.0, k_pgb_discover_unit<int32_t>, dim3(max_du), dim3(kBlock), 0, st, a);
         GJ_LAUNCH("k_pgb_merge", 8.0 * np, k_pgb_merge<int32_t>, dim3(np), dim3(kBlock), 0, st, a);
     } else {
         GJ_LAUNCH("k_pgb_discover", 16.0 * n, k_pgb_discover<int64_t>, dim3(np), dim3(kBlock), 0, st, a);
-        GJ_LAUNCH("k_pgb_discover_unit", 0.0, k_pgb_discover_unit<int64_t>, dim3(max_du), dim3(kBlock), 0, st, a);
+        GJ_LAUNCH("k_pgb_discover", 0.0, k_pgb_discover_unit<int64_t>, dim3(max_du), dim3(kBlock), 0, st, a);
         GJ_LAUNCH("k_pgb_merge", 16.0 * np, k_pgb_merge<int64_t>, dim3(np), dim3(kBlock), 0, st, a);
     }
     scan_exclusive_u32(ctx, gcnt, gcnt, np, gcnt + np);
@@ -2319,13 +2321,15 @@ void groupby_partition_segments(Ctx &ctx, int key_bytes, const void *key, const 
     a.dubase = du;
     const uint32_t max_du = 2 * ceil_div_u32(n, kDiscoverUnit) + 1;
     a.dcount = ctx.scratch_n<uint32_t>(max_du);
+    // the two discovery kernels (partitions up to kDiscoverUnit rows, and slices of
+    // larger ones) share one tag: together they read the keys twice
     if (key_bytes == 4) {
         GJ_LAUNCH("k_pgb_discover", 8.0 * n, k_pgb_discover<int32_t>, dim3(np), dim3(kBlock), 0, st, a);
-        GJ_LAUNCH("k_pgb_discover_unit", 0.0, k_pgb_discover_unit<int32_t>, dim3(max_du), dim3(kBlock), 0, st, a);
+        GJ_LAUNCH("k_pgb_discover", 0.0, k_pgb_discover_unit<int32_t>, dim3(max_du), dim3(kBlock), 0, st, a);
         GJ_LAUNCH("k_pgb_merge", 8.0 * np, k_pgb_merge<int32_t>, dim3(np), dim3(kBlock), 0, st, a);
     } else {
         GJ_LAUNCH("k_pgb_discover", 16.0 * n, k_pgb_discover<int64_t>, dim3(np), dim3(kBlock), 0, st, a);
-        GJ_LAUNCH("k_pgb_discover_unit", 0.0, k_pgb_discover_unit<int64_t>, dim3(max_du), dim3(kBlock), 0, st, a);
+        GJ_LAUNCH("k_pgb_discover", 0.0, k_pgb_discover_unit<int64_t>, dim3(max_du), dim3(kBlock), 0, st, a);
         GJ_LAUNCH("k_pgb_merge", 16.0 * np, k_pgb_merge<int64_t>, dim3(np), dim3(kBlock), 0, st, a);
     }
     scan_exclusive_u32(ctx, gcnt, gcnt, np, gcnt + np);
