@@ -1353,9 +1353,11 @@ __device__ __forceinline__ uint64_t global_slot_hash(K key) {
 }
 
 // Inserts row i (key k) from slot h on and returns the row whose insert holds
-// the key (gid_loc). The first row to claim a slot for its key takes the next
-// group id.
-template <typename K>
+// the key (gid_loc); STORE also writes it to gid_loc[i] where it is found (in
+// the row-by-row kernel, one store after the probe loop instead measured twice
+// as slow from 2^24 groups up). The first row to claim a slot for its key takes
+// the next group id.
+template <typename K, bool STORE>
 __device__ __forceinline__ uint32_t hgb_insert_from(const HgbArgs &a, const K *keys, uint32_t i, K k, uint64_t h) {
     const uint64_t mask = (1ull << a.log2cap) - 1ull;
     for (uint64_t step = 0; step <= mask && step < a.max_probe; ++step) {
@@ -1372,10 +1374,14 @@ __device__ __forceinline__ uint32_t hgb_insert_from(const HgbArgs &a, const K *k
                     const uint32_t g = atomicAdd(a.ngroups, 1u);
                     a.gid[i] = g;
                     static_cast<K *>(a.tmp_keys)[g] = k;
+                    if constexpr (STORE) a.gid_loc[i] = i;
                     return i;
                 }
             }
-            if ((uint32_t)(cur >> 32) == (uint32_t)k) return (uint32_t)cur;
+            if ((uint32_t)(cur >> 32) == (uint32_t)k) {
+                if constexpr (STORE) a.gid_loc[i] = (uint32_t)cur;
+                return (uint32_t)cur;
+            }
         } else {
             uint32_t *t = static_cast<uint32_t *>(a.table);
             uint32_t cur = t[h];  // as above: only an empty read may be stale
@@ -1385,10 +1391,14 @@ __device__ __forceinline__ uint32_t hgb_insert_from(const HgbArgs &a, const K *k
                     const uint32_t g = atomicAdd(a.ngroups, 1u);
                     a.gid[i] = g;
                     static_cast<K *>(a.tmp_keys)[g] = k;
+                    if constexpr (STORE) a.gid_loc[i] = i;
                     return i;
                 }
             }
-            if (keys[cur] == k) return cur;
+            if (keys[cur] == k) {
+                if constexpr (STORE) a.gid_loc[i] = cur;
+                return cur;
+            }
         }
         h = (h + 1) & mask;
     }
@@ -1416,7 +1426,7 @@ __global__ __launch_bounds__(kBlock) void k_hgb_insert(HgbArgs a) {
 #pragma unroll
         for (int r = 0; r < RB; ++r) {
             const uint32_t i = base + r * kBlock + threadIdx.x;
-            if (i < a.n) a.gid_loc[i] = hgb_insert_from<K>(a, keys, i, kk[r], global_slot_hash<K>(kk[r]) & mask);
+            if (i < a.n) hgb_insert_from<K, true>(a, keys, i, kk[r], global_slot_hash<K>(kk[r]) & mask);
         }
     }
 }
@@ -1475,7 +1485,7 @@ __device__ __forceinline__ void insert_cached_rows(const HgbArgs &a, unsigned lo
 #pragma unroll
     for (int r = 0; r < RB; ++r) {
         if (!((miss >> r) & 1u)) continue;
-        loc[r] = hgb_insert_from<int32_t>(a, keys, row[r], kk[r], global_slot_hash<int32_t>(kk[r]) & mask);
+        loc[r] = hgb_insert_from<int32_t, false>(a, keys, row[r], kk[r], global_slot_hash<int32_t>(kk[r]) & mask);
         const unsigned long long ent = ((unsigned long long)(uint32_t)kk[r] << 32) | loc[r];
         for (int p = 0; p < kCacheProbe; ++p) {
             const unsigned long long old = atomicCAS(&s_c[(ch[r] + p) & CM], ~0ull, ent);
