@@ -45,7 +45,7 @@ struct Geo {
     static constexpr uint32_t kSPiece = 2 * BUILD;
     static constexpr int kMaxLog2nb = BUILD >= 16384 ? 13 : (BUILD == 4096 ? 11 : 12);
     static constexpr uint32_t kMaxNb = 1u << kMaxLog2nb;
-    static constexpr int kPB = 16;                    // count pass
+    static constexpr int kPB = BUILD == 16384 ? 8 : 16;  // count pass
     static constexpr int kPBWrite = BUILD == 4096 ? 16 : 8;  // LDS write pass
     // waves per SIMD the register allocation must allow: the persistent
     // kernels and the one-unit-per-workgroup kernels (two 512-thread
@@ -53,6 +53,9 @@ struct Geo {
     static constexpr int kMinW = 4;
     static constexpr int kMinWWrite = BUILD == 4096 ? 3 : 4;
     static constexpr int kMinWEager = BUILD == 4096 ? 1 : 4;
+    // the eager count pass: two 1024-thread workgroups per compute unit when their
+    // LDS (sized by the largest R block) fits twice
+    static constexpr int kMinWCount = BUILD == 16384 ? 8 : kMinWEager;
     static constexpr int kMinWStaged = BUILD == 4096 ? 2 : 4;
 };
 
@@ -82,6 +85,8 @@ struct JoinArgs {
     const uint8_t *seg_bshift;  // batches: extra LDS bucket bits of instance p >> 8 (else bshift)
     int bshift;                 // LDS buckets = 2^(ceil(log2 rows) + bshift), within the table's limit
     const uint32_t *nunits;     // device: work units (the kernels loop over them)
+    const uint32_t *umap;       // partition of every unit (written by k_unit_map)
+    uint32_t lds_rows;          // count and LDS write passes: rows of the largest R block
     uint32_t cap_units;         // units beyond this are not processed (a plan's capacity)
     const uint64_t *out_base;   // device: first output row of this call (nullptr = 0)
     // Streaming write path: the count pass records each S row's match (its row
@@ -122,6 +127,23 @@ __global__ void k_unit_count(const uint32_t *__restrict__ rpo, const uint32_t *_
 // launch's (or plan's) capacity.
 __device__ __forceinline__ uint32_t units_to_run(const uint32_t *nunits, const uint32_t *flags, uint32_t cap) {
     return flags[3] ? 0u : min(*nunits, cap);
+}
+
+// The partition of every unit to run, found once for all passes: each pass then
+// reads it with one load, where a binary search over the unit offsets made a
+// workgroup wait on 14 dependent loads per unit at 2^14 partitions.
+__global__ void k_unit_map(const uint32_t *__restrict__ ubase, uint32_t np, const uint32_t *__restrict__ nunits,
+                           const uint32_t *__restrict__ flags, uint32_t cap, uint32_t *__restrict__ umap) {
+    const uint32_t n = units_to_run(nunits, flags, cap);
+    for (uint32_t u = blockIdx.x * blockDim.x + threadIdx.x; u < n; u += gridDim.x * blockDim.x) {
+        uint32_t lo = 0, hi = np;  // ubase[lo] <= u < ubase[hi]
+        while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (ubase[mid] <= u) lo = mid;
+            else hi = mid;
+        }
+        umap[u] = lo;
+    }
 }
 
 __device__ __forceinline__ void copy_val(void *dst, int dw, uint64_t di, const void *src, uint64_t si) {
@@ -218,16 +240,50 @@ __device__ __forceinline__ void stream_cols_contig(int ncols, const void *const 
     }
 }
 
-template <typename K, uint32_t BUILD>
-struct JoinShared {
-    using G = Geo<BUILD>;
-    K rkey[BUILD];               // R block keys: input order while building, bucket order after
-    uint32_t b[G::kMaxNb + 1];   // bucket boundaries
-    uint16_t entry[BUILD];       // R block rows, grouped by bucket
-    uint32_t tmp[G::kWv];
-    uint32_t unit[6];
-    int is_long;
+// LDS of a count or LDS-write unit, carved from dynamic shared memory for R
+// blocks of at most `rows` rows (the largest block the call has, known after the
+// unit count): the block's keys and rows, the bucket bounds (16-bit: a block
+// holds at most 16384 rows) and a few words of workgroup state. Blocks of about
+// 8192 rows then take 64-68 KB, and two 1024-thread workgroups share a compute
+// unit, one building or loading while the other probes.
+template <typename K>
+struct JoinLds {
+    K *rkey;         // R block keys: input order while building, bucket order after
+    uint16_t *entry; // R block rows, grouped by bucket
+    uint16_t *b;     // bucket boundaries
+    uint32_t *tmp;   // kWv words
+    uint32_t *unit;  // 6 words
+    int *is_long;
 };
+constexpr size_t align8(size_t x) { return (x + 7) & ~(size_t)7; }
+template <typename K, uint32_t BUILD>
+constexpr size_t join_lds_bytes(uint32_t rows) {
+    return align8((size_t)rows * sizeof(K)) + align8((size_t)rows * 2) + align8(((size_t)Geo<BUILD>::kMaxNb + 1) * 2) +
+           4 * ((size_t)Geo<BUILD>::kWv + 8);
+}
+template <typename K, uint32_t BUILD>
+__device__ __forceinline__ JoinLds<K> join_lds(uint8_t *p, uint32_t rows) {
+    JoinLds<K> L;
+    L.rkey = reinterpret_cast<K *>(p);
+    p += align8((size_t)rows * sizeof(K));
+    L.entry = reinterpret_cast<uint16_t *>(p);
+    p += align8((size_t)rows * 2);
+    L.b = reinterpret_cast<uint16_t *>(p);
+    p += align8(((size_t)Geo<BUILD>::kMaxNb + 1) * 2);
+    L.tmp = reinterpret_cast<uint32_t *>(p);
+    L.unit = L.tmp + Geo<BUILD>::kWv;
+    L.is_long = reinterpret_cast<int *>(L.unit + 6);
+    return L;
+}
+// 16-bit bucket counters updated through their 32-bit word (no carry or borrow
+// crosses the halves: counts stay below 2^16 and never drop below zero).
+__device__ __forceinline__ void b16_add1(uint16_t *b, uint32_t i) {
+    atomicAdd(reinterpret_cast<uint32_t *>(b) + (i >> 1), 1u << ((i & 1u) * 16u));
+}
+__device__ __forceinline__ uint32_t b16_dec(uint16_t *b, uint32_t i) {  // the value before
+    const uint32_t sh = (i & 1u) * 16u;
+    return (atomicSub(reinterpret_cast<uint32_t *>(b) + (i >> 1), 1u << sh) >> sh) & 0xFFFFu;
+}
 
 // Build on the R block of unit u and probe it with the unit's S piece: count
 // (WRITE = false) or write (WRITE = true) the matches.
@@ -237,7 +293,7 @@ struct JoinShared {
 // one entry, rare with at least as many buckets as rows, are walked afterwards.
 // c[r] = matches of key r, e1[r] = its first match's entry (bucket order).
 template <typename K, int PB>
-__device__ __forceinline__ void probe_rows(const K *s_rkey, const uint32_t *s_b, const K (&key)[PB],
+__device__ __forceinline__ void probe_rows(const K *s_rkey, const uint16_t *s_b, const K (&key)[PB],
                                            const bool (&valid)[PB], int skip_bits, int log2nb, uint32_t rn,
                                            uint32_t (&c)[PB], uint32_t (&e1)[PB]) {
     uint32_t lo[PB], hi[PB];
@@ -268,13 +324,7 @@ __device__ __forceinline__ void probe_rows(const K *s_rkey, const uint32_t *s_b,
 // row, R rows, first S row, S rows, partition bits, extra bucket bits.
 template <uint32_t kSPiece>
 __device__ __forceinline__ void decode_unit(const JoinArgs &a, uint32_t u, uint32_t *s_unit) {
-    uint32_t lo = 0, hi = a.np;  // ubase[lo] <= u < ubase[hi] (ubase[np] = units)
-    while (hi - lo > 1) {
-        const uint32_t mid = (lo + hi) >> 1;
-        if (a.ubase[mid] <= u) lo = mid;
-        else hi = mid;
-    }
-    const uint32_t p = lo;
+    const uint32_t p = a.umap[u];
     const uint32_t nr = a.rpo[p + 1] - a.rpo[p], ns = a.spo[p + 1] - a.spo[p];
     const uint32_t nsb = ceil_div_u32(ns, kSPiece);
     const uint32_t local = u - a.ubase[p];
@@ -290,7 +340,7 @@ __device__ __forceinline__ void decode_unit(const JoinArgs &a, uint32_t u, uint3
 // Inclusive scan of the nb bucket counts in s_b (s_b[b] = end of bucket b), and
 // s_b[nb] = rn.
 template <uint32_t BUILD>
-__device__ __forceinline__ void scan_buckets(uint32_t *s_b, uint32_t *s_tmp, uint32_t nb, uint32_t rn) {
+__device__ __forceinline__ void scan_buckets(uint16_t *s_b, uint32_t *s_tmp, uint32_t nb, uint32_t rn) {
     using G = Geo<BUILD>;
     constexpr int per = (int)((G::kMaxNb + G::kThreads - 1) / G::kThreads);
     const uint32_t first = threadIdx.x * per;
@@ -305,9 +355,9 @@ __device__ __forceinline__ void scan_buckets(uint32_t *s_b, uint32_t *s_tmp, uin
 #pragma unroll
     for (int k = 0; k < per; ++k) {
         run += v[k];
-        if (first + k < nb) s_b[first + k] = run;
+        if (first + k < nb) s_b[first + k] = (uint16_t)run;
     }
-    if (threadIdx.x == 0) s_b[nb] = rn;
+    if (threadIdx.x == 0) s_b[nb] = (uint16_t)rn;
 }
 
 // Count pass of unit u: matches per (unit, wave), each S row's match recorded
@@ -316,14 +366,14 @@ __device__ __forceinline__ void scan_buckets(uint32_t *s_b, uint32_t *s_tmp, uin
 // this thread: counts, scan, placement), since counts need no ordered chains;
 // the wave's first round of S keys loads during the build.
 template <typename K, uint32_t BUILD>
-__device__ __forceinline__ void count_unit(const JoinArgs &a, uint32_t u, JoinShared<K, BUILD> &sh) {
+__device__ __forceinline__ void count_unit(const JoinArgs &a, uint32_t u, const JoinLds<K> &sh) {
     using G = Geo<BUILD>;
     constexpr int PB = G::kPB;
     constexpr int kT = G::kThreads;
     constexpr int kWv = G::kWv;
     constexpr int PER = (int)(BUILD / kT);
     K *s_rkey = sh.rkey;
-    uint32_t *s_b = sh.b;
+    uint16_t *s_b = sh.b;
     uint16_t *s_entry = sh.entry;
     uint32_t *s_unit = sh.unit;
     const int tid = threadIdx.x, w = tid / kWave, lane = lane_id();
@@ -352,7 +402,7 @@ __device__ __forceinline__ void count_unit(const JoinArgs &a, uint32_t u, JoinSh
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < PER; ++k)
-        if ((uint32_t)(tid + k * kT) < rn) atomicAdd(&s_b[bucket_of<K>(kr[k], skip_bits, log2nb)], 1u);
+        if ((uint32_t)(tid + k * kT) < rn) b16_add1(s_b, bucket_of<K>(kr[k], skip_bits, log2nb));
     __syncthreads();
     scan_buckets<BUILD>(s_b, sh.tmp, nb, rn);
     __syncthreads();
@@ -360,7 +410,7 @@ __device__ __forceinline__ void count_unit(const JoinArgs &a, uint32_t u, JoinSh
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
         if ((uint32_t)(tid + k * kT) < rn) {
-            const uint32_t slot = atomicSub(&s_b[bucket_of<K>(kr[k], skip_bits, log2nb)], 1u) - 1u;
+            const uint32_t slot = b16_dec(s_b, bucket_of<K>(kr[k], skip_bits, log2nb)) - 1u;
             s_rkey[slot] = kr[k];
             s_entry[slot] = (uint16_t)(tid + k * kT);
         }
@@ -397,17 +447,17 @@ __device__ __forceinline__ void count_unit(const JoinArgs &a, uint32_t u, JoinSh
 // several R blocks, or S rows with several matches): build with chains in row
 // order, probe, and write every match at the positions the count pass sized.
 template <typename K, uint32_t BUILD>
-__device__ __forceinline__ void write_unit(const JoinArgs &a, uint32_t u, uint64_t out_base, JoinShared<K, BUILD> &sh) {
+__device__ __forceinline__ void write_unit(const JoinArgs &a, uint32_t u, uint64_t out_base, const JoinLds<K> &sh) {
     using G = Geo<BUILD>;
     constexpr int PB = G::kPBWrite;
     constexpr int kBlockT = G::kThreads;
     constexpr int kWv = G::kWv;
     constexpr uint32_t kSPiece = G::kSPiece;
     K *s_rkey = sh.rkey;
-    uint32_t *s_b = sh.b;
+    uint16_t *s_b = sh.b;
     uint16_t *s_entry = sh.entry;
     uint32_t *s_unit = sh.unit;
-    int &s_long = sh.is_long;
+    int &s_long = *sh.is_long;
     const int tid = threadIdx.x, w = tid / kWave, lane = lane_id();
     if (tid == 0) {
         decode_unit<kSPiece>(a, u, s_unit);
@@ -426,14 +476,13 @@ __device__ __forceinline__ void write_unit(const JoinArgs &a, uint32_t u, uint64
     for (uint32_t i = tid; i < rn; i += kBlockT) s_rkey[i] = rkey[r0 + i];
     for (uint32_t b = tid; b <= nb; b += kBlockT) s_b[b] = 0;
     __syncthreads();
-    for (uint32_t i = tid; i < rn; i += kBlockT) atomicAdd(&s_b[bucket_of<K>(s_rkey[i], skip_bits, log2nb)], 1u);
+    for (uint32_t i = tid; i < rn; i += kBlockT) b16_add1(s_b, bucket_of<K>(s_rkey[i], skip_bits, log2nb));
     __syncthreads();
     scan_buckets<BUILD>(s_b, sh.tmp, nb, rn);
     __syncthreads();
     // placement from the end of each bucket; afterwards s_b[b] = start of bucket b
     for (uint32_t i = tid; i < rn; i += kBlockT) {
-        const uint32_t b = bucket_of<K>(s_rkey[i], skip_bits, log2nb);
-        const uint32_t slot = atomicSub(&s_b[b], 1u) - 1u;
+        const uint32_t slot = b16_dec(s_b, bucket_of<K>(s_rkey[i], skip_bits, log2nb)) - 1u;
         s_entry[slot] = (uint16_t)i;
     }
     __syncthreads();
@@ -467,7 +516,7 @@ __device__ __forceinline__ void write_unit(const JoinArgs &a, uint32_t u, uint64
                 if (valid) {
                     const uint32_t rk = rank_below(peers);
                     const uint32_t st = s_b[b];
-                    if (rk == 0) s_b[b] = st + (uint32_t)__popcll(peers);
+                    if (rk == 0) s_b[b] = (uint16_t)(st + (uint32_t)__popcll(peers));
                     s_entry[st + rk] = (uint16_t)i;
                 }
             }
@@ -475,7 +524,7 @@ __device__ __forceinline__ void write_unit(const JoinArgs &a, uint32_t u, uint64
             for (int c = (int)((nb + kWave - 1) / kWave) - 1; c >= 0; --c) {
                 const uint32_t b = (uint32_t)c * kWave + lane;
                 const uint32_t v = b < nb ? s_b[b] : 0u;
-                if (b < nb) s_b[b + 1] = v;
+                if (b < nb) s_b[b + 1] = (uint16_t)v;
             }
             if (lane == 0) s_b[0] = 0;
         }
@@ -572,15 +621,16 @@ __device__ __forceinline__ void write_unit(const JoinArgs &a, uint32_t u, uint64
 }
 
 template <typename K, uint32_t BUILD, bool WRITE>
-__device__ __forceinline__ void join_unit(const JoinArgs &a, uint32_t u, uint64_t out_base, JoinShared<K, BUILD> &sh) {
+__device__ __forceinline__ void join_unit(const JoinArgs &a, uint32_t u, uint64_t out_base, const JoinLds<K> &sh) {
     if constexpr (WRITE) write_unit<K, BUILD>(a, u, out_base, sh);
     else count_unit<K, BUILD>(a, u, sh);
 }
 
 // One work unit per workgroup (eager calls: the grid is the unit count).
 template <typename K, uint32_t BUILD, bool WRITE>
-__global__ __launch_bounds__(Geo<BUILD>::kThreads, Geo<BUILD>::kMinWEager) void k_join(JoinArgs a) {
-    __shared__ JoinShared<K, BUILD> sh;
+__global__ __launch_bounds__(Geo<BUILD>::kThreads, WRITE ? Geo<BUILD>::kMinWEager : Geo<BUILD>::kMinWCount) void k_join(JoinArgs a) {
+    extern __shared__ uint4 s_dyn4[];
+    const JoinLds<K> sh = join_lds<K, BUILD>(reinterpret_cast<uint8_t *>(s_dyn4), a.lds_rows);
     if (blockIdx.x < units_to_run(a.nunits, a.flags, a.cap_units)) join_unit<K, BUILD, WRITE>(a, blockIdx.x, 0ull, sh);
 }
 
@@ -607,13 +657,7 @@ __global__ __launch_bounds__(kBlock, GFUR ? 4 : 1) void k_join_stream(JoinArgs a
     for (uint64_t slot = (uint64_t)blockIdx.x * kWaves + threadIdx.x / kWave; slot < n_slots;
          slot += (uint64_t)gridDim.x * kWaves) {
         const uint32_t u = (uint32_t)(slot / kWv), w = (uint32_t)(slot % kWv);
-        uint32_t lo = 0, hi = a.np;  // ubase[lo] <= u < ubase[hi]
-        while (hi - lo > 1) {
-            const uint32_t mid = (lo + hi) >> 1;
-            if (a.ubase[mid] <= u) lo = mid;
-            else hi = mid;
-        }
-        const uint32_t p = lo, sb = u - a.ubase[p];  // one R block: the unit is the S piece
+        const uint32_t p = a.umap[u], sb = u - a.ubase[p];  // one R block: the unit is the S piece
         const uint32_t ns = a.spo[p + 1] - a.spo[p];
         const uint32_t s0 = a.spo[p] + sb * kSPiece, sn = min(kSPiece, ns - sb * kSPiece);
         const uint32_t r0 = a.rpo[p], rn = a.rpo[p + 1] - r0;
@@ -694,13 +738,7 @@ __global__ __launch_bounds__(Geo<BUILD>::kThreads, Geo<BUILD>::kMinWStaged) void
     K *__restrict__ tkey = static_cast<K *>(a.tkey);
     for (uint32_t u = blockIdx.x; u < n_units; u += gridDim.x) {
         if (tid == 0) {
-            uint32_t lo = 0, hi = a.np;  // ubase[lo] <= u < ubase[hi]
-            while (hi - lo > 1) {
-                const uint32_t mid = (lo + hi) >> 1;
-                if (a.ubase[mid] <= u) lo = mid;
-                else hi = mid;
-            }
-            const uint32_t p = lo, sb = u - a.ubase[p];  // one R block: the unit is the S piece
+            const uint32_t p = a.umap[u], sb = u - a.ubase[p];  // one R block: the unit is the S piece
             const uint32_t ns = a.spo[p + 1] - a.spo[p];
             s_unit[0] = a.rpo[p];
             s_unit[1] = min(a.rpo[p + 1] - a.rpo[p], a.flags[2]);  // never past the staged rows
@@ -819,7 +857,8 @@ __global__ __launch_bounds__(Geo<BUILD>::kThreads, Geo<BUILD>::kMinWStaged) void
 // Persistent workgroups over the unit count held in device memory (plans).
 template <typename K, uint32_t BUILD, bool WRITE>
 __global__ __launch_bounds__(Geo<BUILD>::kThreads, WRITE ? Geo<BUILD>::kMinWWrite : Geo<BUILD>::kMinW) void k_join_persist(JoinArgs a) {
-    __shared__ JoinShared<K, BUILD> sh;
+    extern __shared__ uint4 s_dyn4[];
+    const JoinLds<K> sh = join_lds<K, BUILD>(reinterpret_cast<uint8_t *>(s_dyn4), a.lds_rows);
     if (WRITE && a.lds_if_complex && !(a.flags[0] | a.flags[1])) return;  // the streaming pass writes
     const uint32_t n_units = units_to_run(a.nunits, a.flags, a.cap_units);
     const uint64_t out_base = a.out_base ? *a.out_base : 0ull;
@@ -862,8 +901,9 @@ template <typename K, uint32_t BUILD>
 struct JoinKernels {
     using G = Geo<BUILD>;
     static void count(hipStream_t s, bool planned, uint32_t grid, const JoinArgs &a, double bytes) {
-        if (planned) GJ_LAUNCH("k_join_count", bytes, (k_join_persist<K, BUILD, false>), dim3(grid), dim3(G::kThreads), 0, s, a);
-        else GJ_LAUNCH("k_join_count", bytes, (k_join<K, BUILD, false>), dim3(grid), dim3(G::kThreads), 0, s, a);
+        const size_t shm = join_lds_bytes<K, BUILD>(a.lds_rows);
+        if (planned) GJ_LAUNCH("k_join_count", bytes, (k_join_persist<K, BUILD, false>), dim3(grid), dim3(G::kThreads), shm, s, a);
+        else GJ_LAUNCH("k_join_count", bytes, (k_join<K, BUILD, false>), dim3(grid), dim3(G::kThreads), shm, s, a);
     }
     // grid: workgroups of the unit passes; the streaming pass has kWaves-wave workgroups
     static void stream(hipStream_t s, uint32_t grid, const JoinArgs &a, double bytes) {
@@ -875,8 +915,9 @@ struct JoinKernels {
         GJ_LAUNCH("k_join_write", bytes, (k_join_stream_staged<K, BUILD>), dim3(grid), dim3(G::kThreads), shm, s, a);
     }
     static void write_lds(hipStream_t s, bool planned, uint32_t grid, const JoinArgs &a, double bytes) {
-        if (planned) GJ_LAUNCH("k_join_write_lds", bytes, (k_join_persist<K, BUILD, true>), dim3(grid), dim3(G::kThreads), 0, s, a);
-        else GJ_LAUNCH("k_join_write_lds", bytes, (k_join<K, BUILD, true>), dim3(grid), dim3(G::kThreads), 0, s, a);
+        const size_t shm = join_lds_bytes<K, BUILD>(a.lds_rows);
+        if (planned) GJ_LAUNCH("k_join_write_lds", bytes, (k_join_persist<K, BUILD, true>), dim3(grid), dim3(G::kThreads), shm, s, a);
+        else GJ_LAUNCH("k_join_write_lds", bytes, (k_join<K, BUILD, true>), dim3(grid), dim3(G::kThreads), shm, s, a);
     }
 };
 
@@ -934,6 +975,7 @@ int64_t join_partitioned(Ctx &ctx, int key_bytes, const JoinSide &R, const JoinS
     // Eager calls read the unit count and size every launch exactly; a plan sizes
     // for its capacity and the kernels read the count from device memory.
     uint32_t cap_units, grid;
+    uint32_t lds_rows = (uint32_t)r_block;  // rows of the largest R block a unit builds on
     if (pl) {
         cap_units = pl->cap_units;
         grid = std::max<uint32_t>(1, std::min<uint32_t>(cap_units, kPersistentGrid));
@@ -942,6 +984,8 @@ int64_t join_partitioned(Ctx &ctx, int key_bytes, const JoinSide &R, const JoinS
         GJ_HIP(hipMemcpyAsync(&cap_units, ucnt + np, 4, hipMemcpyDeviceToHost, s));
         GJ_HIP(hipMemcpyAsync(hf, flags, sizeof(hf), hipMemcpyDeviceToHost, s));
         GJ_HIP(hipStreamSynchronize(s));
+        // hf[2]: most R rows in a partition that S probes (a block holds at most r_block)
+        lds_rows = std::max<uint32_t>(64, (std::min<uint32_t>(hf[2], (uint32_t)r_block) + 63) & ~63u);
         if (hf[3]) throw Error(GJ_EOVERFLOW, "more than 2^31-1 join work units (R partitions far larger than the "
                                              "build block)");
         if (stats) {
@@ -964,6 +1008,7 @@ int64_t join_partitioned(Ctx &ctx, int key_bytes, const JoinSide &R, const JoinS
     a.np = np;
     a.ubase = ucnt;
     a.rc = (uint32_t)r_block;
+    a.lds_rows = lds_rows;
     a.skip_bits = (stats && stats->hashed_digits) ? 0 : bits;
     a.seg_bits = seg_bits;
     a.seg_bshift = pl ? pl->seg_bshift : nullptr;
@@ -974,6 +1019,11 @@ int64_t join_partitioned(Ctx &ctx, int key_bytes, const JoinSide &R, const JoinS
     a.midx = ctx.scratch_n<uint16_t>(std::max<uint32_t>(S.rows, 1));
     a.flags = flags;
     a.lds_if_complex = pl ? 1 : 0;
+    uint32_t *umap = ctx.scratch_n<uint32_t>(cap_units);
+    GJ_LAUNCH("k_unit_map", 4.0 * cap_units, k_unit_map,
+              dim3(std::max<uint32_t>(1, std::min<uint32_t>(ceil_div_u32(cap_units, 256), 1024))),
+              dim3(256), 0, s, ucnt, np, ucnt + np, (const uint32_t *)flags, cap_units, umap);
+    a.umap = umap;
     const uint64_t nw = (uint64_t)cap_units * wpu;
     uint64_t *wcnt = ctx.scratch_n<uint64_t>(nw + 1);
     uint64_t *total = pl ? pl->total : wcnt + nw;
