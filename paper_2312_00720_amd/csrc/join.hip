@@ -379,11 +379,13 @@ __device__ __forceinline__ void count_unit(const JoinArgs &a, uint32_t u, const 
     const int tid = threadIdx.x, w = tid / kWave, lane = lane_id();
     if (tid == 0) decode_unit<G::kSPiece>(a, u, s_unit);
     __syncthreads();
-    const uint32_t r0 = s_unit[0], rn = s_unit[1], s0 = s_unit[2], sn = s_unit[3];
-    const int skip_bits = (int)s_unit[4];
+    // the unit's shape is uniform: scalar registers (in vector ones they spilled)
+    const uint32_t r0 = __builtin_amdgcn_readfirstlane(s_unit[0]), rn = __builtin_amdgcn_readfirstlane(s_unit[1]);
+    const uint32_t s0 = __builtin_amdgcn_readfirstlane(s_unit[2]), sn = __builtin_amdgcn_readfirstlane(s_unit[3]);
+    const int skip_bits = (int)__builtin_amdgcn_readfirstlane(s_unit[4]);
     int log2nb = 0;
     while ((1u << log2nb) < rn) ++log2nb;
-    log2nb = min(log2nb + (int)s_unit[5], G::kMaxLog2nb);
+    log2nb = min(log2nb + (int)__builtin_amdgcn_readfirstlane(s_unit[5]), G::kMaxLog2nb);
     const uint32_t nb = 1u << log2nb;
 
     // loads in flight during the build: this thread's R keys, its wave's first S keys
@@ -392,7 +394,7 @@ __device__ __forceinline__ void count_unit(const JoinArgs &a, uint32_t u, const 
 #pragma unroll
     for (int k = 0; k < PER; ++k) kr[k] = (uint32_t)(tid + k * kT) < rn ? rk[tid + k * kT] : K(0);
     const uint32_t q = ceil_div_u32(sn, kWv);
-    const uint32_t ws = min(sn, w * q), we = min(sn, ws + q);
+    const uint32_t ws = __builtin_amdgcn_readfirstlane(min(sn, w * q)), we = __builtin_amdgcn_readfirstlane(min(sn, ws + q));
     const K *__restrict__ skey = static_cast<const K *>(a.skey) + s0;
     K key[PB];
 #pragma unroll

@@ -229,6 +229,27 @@ def test_hash_few_groups(g_card, nv, v64):
     check(d["key"], vals, aggs, algo="auto")
 
 
+@pytest.mark.parametrize("card", [3000, 20])
+def test_hash_misaligned_keys(card):
+    """Keys one element past a 16-byte boundary: the hash insert's cached kernel
+    (16-byte runs) steps aside for the row-by-row one, with the same result."""
+    import paper_2312_00720_amd as gj
+    from gpu_util import dev, host, say
+    d = datagen.groupby_input(100003, card, 2, seed=datagen.seed_for(13, card))
+    keys, vals = d["key"], d["vals"]
+    kd = dev(np.concatenate([keys[:1], keys]))[1:]
+    vd = [dev(np.concatenate([v[:1], v]))[1:] for v in vals]
+    assert kd.data_ptr() % 16 != 0
+    say(f"groupby misaligned keys card={card}")
+    gk, res = gj.groupby(kd, vd, AGGS, algo="hash")
+    gk = host(gk)
+    ek, ecols = expected(keys, vals, AGGS)
+    order = np.argsort(gk, kind="stable")
+    np.testing.assert_array_equal(gk[order], ek)
+    for r, e in zip(res, ecols):
+        np.testing.assert_array_equal(host(r)[order], e)
+
+
 def test_hash_global_aggregation_path():
     d = datagen.groupby_input(100000, 2000, 2, seed=6)
     check(d["key"], d["vals"], algo="hash", lds_budget=64)
