@@ -424,7 +424,8 @@ int gj_gather_i32(const int32_t *map, const int32_t *values, int64_t n_values, i
  *   [7] Zipf factor of the foreign keys or group keys / 1.2 (the hint; 0 without)
  *   [8] match ratio (the hint, else 1; group-by: 1)
  *   [9] log2(|S| / |R|) / 32 (group-by: log2(N / g) / 32)
- *   [10] log2 expected output rows / 32
+ *   [10] log2 expected output rows / 32 (group-by: log2 of the LDS bytes the hash
+ *        group-by's records of all groups take, estimate x record bytes / 32)
  *   [11] log2 input bytes / 48
  * Classes: 0 partitioned-hash join GFTR, 1 partitioned-hash join GFUR,
  * 2 hash, 3 sort, 4 partition group-by, 5 sort group-by on dictionary-encoded
@@ -447,14 +448,17 @@ int gj_select(const float features[12], int32_t op_kind, int32_t *choice, float 
  * these relations and options (host only; no device access). */
 int gj_join_features(const gj_rel *R, const gj_rel *S, const gj_join_opts *opts, float features[12]);
 
-/* The feature vector an automatic group-by choice uses: reads the keys once on
- * `stream` (group-count estimate and varying key bytes) and synchronizes.
+/* The feature vector an automatic group-by choice uses for these columns and
+ * aggregates (value columns and aggregates as gj_groupby takes them; only the
+ * value widths are read): reads the keys once on `stream` (group-count estimate
+ * and varying key bytes) and synchronizes.
  * The estimate comes from the sketch kernel gj_groupby runs for the same
  * opts->algo and opts->radix_bits (automatic and partition choices also count a
  * per-chunk hash histogram there); both kernels give the same estimate.
  * Scratch from `alloc` (NULL: hipMallocAsync). */
-int gj_groupby_features(gj_col key, int32_t n_vals, int64_t n_rows, const gj_groupby_opts *opts,
-                        const gj_allocator *alloc, void *stream, float features[12]);
+int gj_groupby_features(gj_col key, const gj_col *vals, int32_t n_vals, const gj_agg *aggs, int32_t n_aggs,
+                        int64_t n_rows, const gj_groupby_opts *opts, const gj_allocator *alloc, void *stream,
+                        float features[12]);
 
 /* Load trained network weights (host array of GJ_MLP_PARAMS floats; NULL or n = 0
  * unloads them). Thread-safe. */

@@ -136,8 +136,9 @@ def lib() -> ctypes.CDLL:
             L.gj_join_features.argtypes = [ctypes.POINTER(Rel), ctypes.POINTER(Rel), ctypes.POINTER(JoinOpts),
                                            ctypes.POINTER(ctypes.c_float)]
             L.gj_groupby_features.restype = ctypes.c_int
-            L.gj_groupby_features.argtypes = [Col, i32, i64, ctypes.POINTER(GroupByOpts), ctypes.POINTER(Allocator),
-                                              vp, ctypes.POINTER(ctypes.c_float)]
+            L.gj_groupby_features.argtypes = [Col, ctypes.POINTER(Col), i32, ctypes.POINTER(Agg), i32, i64,
+                                              ctypes.POINTER(GroupByOpts), ctypes.POINTER(Allocator), vp,
+                                              ctypes.POINTER(ctypes.c_float)]
             L.gj_get_cost_constants.restype = ctypes.c_int
             L.gj_get_cost_constants.argtypes = [ctypes.POINTER(ctypes.c_double)] * 3
             L.gj_stream_copy.restype = ctypes.c_int
@@ -679,14 +680,20 @@ def join_features(r_key, r_pay, s_key, s_pay, *, match_ratio_hint: float = 0.0, 
     return [f[i] for i in range(12)]
 
 
-def groupby_features(key: torch.Tensor, n_vals: int, *, skew_hint: float = 0.0, algo: str = "auto"):
-    """The feature vector gj_groupby's automatic choice uses (reads the keys once).
+def groupby_features(key: torch.Tensor, vals, aggs, *, skew_hint: float = 0.0, algo: str = "auto"):
+    """The feature vector gj_groupby's automatic choice uses for these columns and
+    aggregates (reads the keys once; of the value columns only their widths).
     `algo` picks the sketch kernel gj_groupby would run for that algorithm."""
+    vals = list(vals)
+    n = key.numel()
+    _check_cols([key, *vals], n, key.device)
+    vp = (Col * max(1, len(vals)))(*[_col(t) for t in vals])
+    ag = (Agg * max(1, len(aggs)))(*[Agg(int(c), AGG_OP[op]) for c, op in aggs])
     o = GroupByOpts(GB_ALGO[algo], 0, 0, 0, 0.0, 0, float(skew_hint))
     f = (ctypes.c_float * 12)()
     A = _TorchAllocator(key.device)
-    _raise(lib().gj_groupby_features(_col(key), int(n_vals), key.numel(), ctypes.byref(o), ctypes.byref(A.struct),
-                                     _stream(key.device), f))
+    _raise(lib().gj_groupby_features(_col(key), vp, len(vals), ag, len(aggs), n, ctypes.byref(o),
+                                     ctypes.byref(A.struct), _stream(key.device), f))
     return [f[i] for i in range(12)]
 
 

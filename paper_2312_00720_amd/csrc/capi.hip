@@ -432,7 +432,8 @@ int gj_groupby(gj_col key, const gj_col *vals, int32_t n_vals, int64_t n_rows, c
             g_est = gj::estimate_groups(ctx, kb, key.data, n, &varying, want_hist ? &hist8 : nullptr);
         if (algo == GJ_GB_AUTO) {
             float f[12];
-            gj::features_groupby(f, (double)n, kb, n_vals, g_est, varying, o.skew_hint);
+            gj::features_groupby(f, (double)n, kb, n_vals, g_est, varying, o.skew_hint,
+                                 (double)gj::hgb_record_bytes(aggs, n_aggs, vcols.width));
             const int c = gj::select_algorithm(f, 1, nullptr);
             algo = c == 2 ? GJ_GB_HASH : c == 3 ? GJ_GB_SORT : c == 5 ? GJ_GB_SORT_DE : GJ_GB_PARTITION;
         }
@@ -509,15 +510,28 @@ int gj_join_features(const gj_rel *R, const gj_rel *S, const gj_join_opts *opts,
     }
 }
 
-int gj_groupby_features(gj_col key, int32_t n_vals, int64_t n_rows, const gj_groupby_opts *opts,
-                        const gj_allocator *alloc, void *stream, float features[12]) {
+int gj_groupby_features(gj_col key, const gj_col *vals, int32_t n_vals, const gj_agg *aggs, int32_t n_aggs,
+                        int64_t n_rows, const gj_groupby_opts *opts, const gj_allocator *alloc, void *stream,
+                        float features[12]) {
     try {
         g_last_error.clear();
         gj::require(features != nullptr, "null features");
         gj::require(n_rows >= 0, "negative row count");
         gj::require(n_rows <= kMaxRows, "more than 2^31-1 rows", GJ_EOVERFLOW);
         gj::require(n_vals >= 0 && n_vals <= 8, "0..8 value columns");
+        gj::require(n_vals == 0 || vals != nullptr, "null value array");
         check_col(key, n_rows, "key");
+        int vw[8] = {0};
+        for (int i = 0; i < n_vals; ++i) {
+            check_col(vals[i], n_rows, "value");
+            vw[i] = dtype_bytes(vals[i].dtype);
+        }
+        gj::require(n_aggs >= 1 && n_aggs <= 16 && aggs != nullptr, "1..16 aggregates");
+        for (int j = 0; j < n_aggs; ++j) {
+            gj::require(aggs[j].op >= GJ_SUM && aggs[j].op <= GJ_MAX, "unknown aggregate");
+            gj::require(aggs[j].op == GJ_COUNT || (aggs[j].col >= 0 && aggs[j].col < n_vals),
+                        "aggregate column out of range");
+        }
         gj_groupby_opts o{};
         if (opts) o = *opts;
         const int kb = dtype_bytes(key.dtype);
@@ -529,7 +543,8 @@ int gj_groupby_features(gj_col key, int32_t n_vals, int64_t n_rows, const gj_gro
         const uint32_t *hist8 = nullptr;
         const double g_est =
             gj::estimate_groups(ctx, kb, key.data, (uint32_t)n_rows, &varying, want_hist ? &hist8 : nullptr);
-        gj::features_groupby(features, (double)n_rows, kb, n_vals, g_est, varying, o.skew_hint);
+        gj::features_groupby(features, (double)n_rows, kb, n_vals, g_est, varying, o.skew_hint,
+                             (double)gj::hgb_record_bytes(aggs, n_aggs, vw));
         return GJ_OK;
     } catch (const gj::Error &e) {
         return fail(e.code, e.what());

@@ -2098,6 +2098,11 @@ void init_outputs(hipStream_t st, const AggSpec &s, uint64_t g) {
 
 }  // namespace
 
+size_t hgb_record_bytes(const gj_agg *aggs, int n_aggs, const int *val_w) {
+    std::vector<void *> no_outs(n_aggs, nullptr);
+    return (size_t)make_spec(aggs, n_aggs, no_outs.data(), val_w, false).words * 4;
+}
+
 double estimate_groups(Ctx &ctx, int key_bytes, const void *key, uint32_t n, int *varying_bytes,
                        const uint32_t **hist8) {
     if (varying_bytes) *varying_bytes = 0;

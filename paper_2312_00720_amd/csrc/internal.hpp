@@ -263,7 +263,10 @@ int select_algorithm(const float *features, int op_kind, float *probs_out);
 // The feature vectors the automatic choices use (gj.h lists the features):
 // hints <= 0 mean unknown (join: every S row matches, uniform keys).
 void features_join(float *f, double nr, double ns, int key_bytes, int cr, int cs, float mr_hint, float skew_hint);
-void features_groupby(float *f, double n, int key_bytes, int nv, double g_est, int varying_bytes, float skew_hint);
+void features_groupby(float *f, double n, int key_bytes, int nv, double g_est, int varying_bytes, float skew_hint,
+                      double rec_bytes);
+// Bytes of one group's LDS record in the hash group-by (padded to whole 64-bit words).
+size_t hgb_record_bytes(const gj_agg *aggs, int n_aggs, const int *val_w);
 
 // ---- join.hip -------------------------------------------------------------------------
 // Work-unit geometry. An R build block of at most r_block rows runs in one of

@@ -210,7 +210,8 @@ void features_join(float *f, double nr, double ns, int key_bytes, int cr, int cs
     f[11] = (float)(std::log2(std::max(1.0, nr * (key_bytes + 4.0 * cr) + ns * (key_bytes + 4.0 * cs))) / 48.0);
 }
 
-void features_groupby(float *f, double n, int key_bytes, int nv, double g_est, int varying_bytes, float skew_hint) {
+void features_groupby(float *f, double n, int key_bytes, int nv, double g_est, int varying_bytes, float skew_hint,
+                      double rec_bytes) {
     memset(f, 0, 12 * sizeof(float));
     f[0] = 0.f;
     f[1] = (float)(std::log2(std::max(1.0, n)) / 32.0);
@@ -225,7 +226,9 @@ void features_groupby(float *f, double n, int key_bytes, int nv, double g_est, i
     f[7] = skew_hint > 0.f ? (float)(skew_hint / 1.2) : 0.f;
     f[8] = 1.f;
     f[9] = (float)(std::log2(std::max(1.0, n / g)) / 32.0);
-    f[10] = f[3];
+    // the LDS the hash group-by's records of all groups take: whether they fit one
+    // workgroup (Algorithm 1's is_smem_enough) depends on the aggregates, not on g alone
+    f[10] = (float)(std::log2(std::max(1.0, g * std::max(4.0, rec_bytes))) / 32.0);
     f[11] = (float)(std::log2(std::max(1.0, n * (key_bytes + 4.0 * nv))) / 48.0);
 }
 

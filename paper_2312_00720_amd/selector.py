@@ -3,7 +3,8 @@
 1. Sample seeded workloads over the feature ranges (joins: log2|R| in [10, 24],
    |S|/|R| in [1, 16], 1-8 payload columns, 4- or 8-byte keys, Zipf factor in
    [0, 1.2], match ratio in [0.05, 1]; group-bys: log2 N in [16, 26],
-   log2 g in [2, min(24, log2 N)], 1-8 value columns).
+   log2 g in [2, min(24, log2 N)], 1-8 value columns), plus (`--large`) sets of
+   group-bys at log2 N in [26, 28], the grouped-aggregation benchmark's size.
 2. Time every valid algorithm of each workload with libgj (median of 5 runs
    after one warm-up). Timing can be split into parts (`--part i --parts K`),
    each saving its own file, and merged afterwards (`--merge`).
@@ -18,7 +19,8 @@
 
 Usage: python -m paper_2312_00720_amd.selector --train 20000 --test 2000 --out DIR
        [--part i --parts K]   time only part i of K of both sets
-       [--merge PARTS_DIR --parts K]   merge the timed parts, train and report
+       [--large A,B --large-only --part i --parts K]   time part i of the extension sets
+       [--merge PARTS_DIR --parts K [--large A,B]]   merge the timed parts, train and report
 """
 from __future__ import annotations
 
@@ -59,6 +61,20 @@ def sample(n: int, seed: int) -> list[dict]:
     return out
 
 
+def sample_large(n: int, seed: int) -> list[dict]:
+    """Group-bys at 2^26-2^28 rows (the size of the grouped-aggregation benchmark),
+    timed as an extension of the main sets, whose row counts stop at 2^26."""
+    g = np.random.default_rng(seed)
+    out = []
+    for i in range(n):
+        ln = g.uniform(26, 28)
+        lg = g.uniform(2, 24)
+        out.append(dict(kind="groupby", log_n=ln, log_g=lg, nv=int(g.integers(1, 9)), kb=int(g.choice([4, 8])),
+                        alpha=float(g.choice([0.0, g.uniform(0, 1.2)])), sparse=bool(g.uniform() < 0.5),
+                        seed=seed * 100000 + i))
+    return out
+
+
 def valid(w: dict) -> list[int]:
     return list(gj.JOIN_CLASSES) if w["kind"] == "join" else list(gj.GROUPBY_CLASSES)
 
@@ -86,7 +102,13 @@ def product_features(w: dict, d, hinted: bool) -> list[float]:
         return gj.join_features(d["r_key"], d["r_pay"], d["s_key"], d["s_pay"],
                                 match_ratio_hint=w["mr"] if hinted else 0.0,
                                 skew_hint=w["alpha"] if hinted else 0.0)
-    return gj.groupby_features(d["key"], w["nv"], skew_hint=w["alpha"] if hinted else 0.0)
+    return gj.groupby_features(d["key"], d["vals"], gb_aggs(w["nv"]), skew_hint=w["alpha"] if hinted else 0.0)
+
+
+def gb_aggs(nv: int) -> list:
+    """The aggregates a timed group-by computes: COUNT, then SUM of every value
+    column and MAX of the first seven (16 aggregates at most)."""
+    return [(0, "count")] + [(c, "sum") for c in range(nv)] + [(c, "max") for c in range(min(nv, 7))]
 
 
 def run(w: dict, d, cls: int):
@@ -94,10 +116,8 @@ def run(w: dict, d, cls: int):
         if cls == 6:
             return gj.join(d["r_key"], d["r_pay"], d["s_key"], d["s_pay"], mat="gftr", algo="smj")
         return gj.join(d["r_key"], d["r_pay"], d["s_key"], d["s_pay"], mat=CLASSES[cls], algo="phj")
-    # COUNT, then SUM of every value column and MAX of the first seven (16 aggregates at most)
-    aggs = [(0, "count")] + [(c, "sum") for c in range(w["nv"])] + [(c, "max") for c in range(min(w["nv"], 7))]
     algo = CLASSES[cls]
-    return gj.groupby(d["key"], d["vals"], aggs, algo=algo, mat="auto" if algo == "hash" else "gftr")
+    return gj.groupby(d["key"], d["vals"], gb_aggs(w["nv"]), algo=algo, mat="auto" if algo == "hash" else "gftr")
 
 
 def time_workload(w: dict, reps: int = 5):
@@ -272,28 +292,39 @@ def main(argv=None) -> int:
     ap.add_argument("--part", type=int, default=None)
     ap.add_argument("--parts", type=int, default=1)
     ap.add_argument("--merge", default=None, metavar="DIR", help="merge the timed parts found in DIR")
+    ap.add_argument("--large", default="0,0", metavar="TRAIN,TEST",
+                    help="extension sets of group-bys at 2^26-2^28 rows (sample_large), appended to the main sets")
+    ap.add_argument("--large-only", action="store_true", help="with --part: time only the extension sets")
     args = ap.parse_args(argv)
     os.makedirs(args.out, exist_ok=True)
+    n_ltr, n_lte = (int(x) for x in args.large.split(","))
+    ltr, lte = sample_large(n_ltr, 3), sample_large(n_lte, 4)
     tr, te = sample(args.train, 1), sample(args.test, 2)
     keys = ("Xtr", "Htr", "Mtr", "Ttr", "Xte", "Hte", "Mte", "Tte")
     if args.part is not None:
-        a, b = part_slice(len(tr), args.part, args.parts), part_slice(len(te), args.part, args.parts)
-        print(f"[selector] part {args.part}/{args.parts}: train {a.start}..{a.stop}, test {b.start}..{b.stop}",
+        src_tr, src_te, tag = (ltr, lte, "large_part") if args.large_only else (tr, te, "part")
+        a, b = part_slice(len(src_tr), args.part, args.parts), part_slice(len(src_te), args.part, args.parts)
+        print(f"[selector] {tag} {args.part}/{args.parts}: train {a.start}..{a.stop}, test {b.start}..{b.stop}",
               flush=True)
-        arrs = build(tr[a]) + build(te[b])
-        np.savez(os.path.join(args.out, f"selector_part{args.part:03d}of{args.parts:03d}.npz"),
+        arrs = build(src_tr[a]) + build(src_te[b])
+        np.savez(os.path.join(args.out, f"selector_{tag}{args.part:03d}of{args.parts:03d}.npz"),
                  **dict(zip(keys, arrs)))
         return 0
     if args.merge:
-        z = [np.load(os.path.join(args.merge, f"selector_part{i:03d}of{args.parts:03d}.npz"))
-             for i in range(args.parts)]
-        data = {k: np.concatenate([q[k] for q in z]) for k in keys}
+        # the main parts, then (if asked for) the extension's parts
+        names = [f"selector_part{i:03d}of{args.parts:03d}.npz" for i in range(args.parts)]
+        if n_ltr or n_lte:
+            names += [f for f in sorted(os.listdir(args.merge)) if f.startswith("selector_large_part")]
+        z = [np.load(os.path.join(args.merge, f)) for f in names]
+        data = {k: np.concatenate([q[k] for q in z if q[k].size]) for k in keys}
         np.savez(os.path.join(args.out, "selector_data.npz"), **data)
     elif args.data:
         data = load_data(args.data)
     else:
-        data = dict(zip(keys, build(tr) + build(te)))
+        data = dict(zip(keys, build(tr + ltr) + build(te + lte)))
         np.savez(os.path.join(args.out, "selector_data.npz"), **data)
+    tr, te = tr + ltr, te + lte
+    assert len(tr) == len(data["Xtr"]) and len(te) == len(data["Xte"]), "timed sets and samples differ"
     # train on both feature views: what the library computes alone, and with the
     # caller's hints of match ratio and skew
     Xall = np.concatenate([data["Xtr"], data["Htr"]])

@@ -318,13 +318,18 @@ def test_group_count_sketch_matches_oracle(kb, n, card, alpha, algo):
     d = datagen.groupby_input(n, card, 0, seed=datagen.seed_for(7, card + n), alpha=alpha)
     keys = d["key"] if kb == 4 else datagen.widen_keys(d["key"])
     say(f"sketch n={n} card={card} kb={kb} algo={algo}")
-    f = gj.groupby_features(dev(keys), 2, algo=algo)
+    vals = [dev(np.zeros(n, np.int32))]
+    aggs = [(0, "count"), (0, "sum"), (0, "max")]  # a 4-word record: 16 bytes per group
+    f = gj.groupby_features(dev(keys), vals, aggs, algo=algo)
     # keys one element past a 16-byte boundary take the row-by-row loads
     shifted = dev(np.concatenate([keys[:1], keys]))[1:]
     assert shifted.data_ptr() % 16 != 0
-    assert gj.groupby_features(shifted, 2, algo=algo) == f
+    assert gj.groupby_features(shifted, vals, aggs, algo=algo) == f
     est = max(1.0, oracle.hll_estimate(keys))
     # one float ulp: a register off by one moves this feature by far more
     want = np.float32(np.log2(est) / 32.0)
     assert abs(np.float32(f[3]) - want) <= np.spacing(want), (f[3], want)
+    want = np.float32(np.log2(est * 16.0) / 32.0)  # the records' LDS bytes
+    assert abs(np.float32(f[10]) - want) <= np.spacing(want), (f[10], want)
+    assert f[5] == np.float32(1 / 8)
     assert f[6] == np.float32((oracle.varying_key_bytes(keys) or kb) / 8.0)

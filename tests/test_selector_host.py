@@ -29,7 +29,9 @@ def join_features(log_r, log_s, mr, cols=2, kb=4):
 
 
 def gb_features(log_n, log_g, nv=2, kb=4):
-    return [0, log_n / 32, 0, log_g / 32, kb / 8, nv / 8, 0, 0, 1, (log_n - log_g) / 32, log_g / 32, 30 / 48]
+    rec = 8 + 16 * nv  # COUNT and SUM/MIN/MAX per column, in bytes
+    return [0, log_n / 32, 0, log_g / 32, kb / 8, nv / 8, 0, 0, 1, (log_n - log_g) / 32,
+            (log_g + math.log2(rec)) / 32, 30 / 48]
 
 
 def test_cost_model_marks_invalid_classes(gj):
