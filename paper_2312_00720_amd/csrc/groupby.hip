@@ -1550,6 +1550,118 @@ __global__ __launch_bounds__(kInsBlock, 8) void k_hgb_insert_cached(HgbArgs a) {
 // them into the workgroup's LDS records, which are then folded into the output.
 // (LDS records updated per row would have every lane of a wave contend for the
 // same few addresses.)
+// The same for 8-byte keys, whose entries do not fit one 64-bit word: a key
+// array and a gid_loc array. A slot is claimed by a 64-bit CAS of its key from
+// the sentinel kCacheNoKey (rows with that key bypass the cache), and its
+// gid_loc, written once afterwards, reads as empty until then: a reader that
+// sees the key before its gid_loc treats the row as a miss. So a gid_loc read
+// in a slot always belongs to the key there.
+constexpr long long kCacheNoKey = (long long)0x8000000000000001ull;
+constexpr int kInsRows8 = 4;  // rows per thread and round, 8-byte keys
+
+template <int LOG2C>
+__device__ __forceinline__ uint32_t cache_home8(long long k) {
+    const uint64_t u = (uint64_t)k;
+    return ((uint32_t)(u ^ (u >> 32)) * 0x9E3779B1u) >> (32 - LOG2C);
+}
+
+template <int LOG2C, int RB>
+__device__ __forceinline__ void insert_cached_rows8(const HgbArgs &a, long long *s_k, uint32_t *s_l,
+                                                    const long long (&kk)[RB], const uint32_t (&row)[RB],
+                                                    uint32_t valid, uint32_t (&loc)[RB]) {
+    constexpr uint32_t CM = (1u << LOG2C) - 1u;
+    uint32_t ch[RB];
+    uint32_t open = 0;  // bit r: row r still looks for its key in the cache
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+        ch[r] = cache_home8<LOG2C>(kk[r]);
+        loc[r] = 0xFFFFFFFFu;
+        open |= (((valid >> r) & 1u) && kk[r] != kCacheNoKey ? 1u : 0u) << r;
+    }
+    for (int p = 0; p < kCacheProbe && open; ++p) {
+        long long e[RB];
+#pragma unroll
+        for (int r = 0; r < RB; ++r) e[r] = ((open >> r) & 1u) ? s_k[(ch[r] + p) & CM] : kCacheNoKey;
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+            if (!((open >> r) & 1u)) continue;
+            if (e[r] == kCacheNoKey) {
+                open &= ~(1u << r);  // an empty slot: the key is not cached
+            } else if (e[r] == kk[r]) {
+                loc[r] = s_l[(ch[r] + p) & CM];  // still empty while its writer is between the two stores
+                open &= ~(1u << r);
+            }
+        }
+    }
+    uint32_t miss = 0;
+#pragma unroll
+    for (int r = 0; r < RB; ++r) miss |= (((valid >> r) & 1u) && loc[r] == 0xFFFFFFFFu ? 1u : 0u) << r;
+    if (!miss) return;
+    const long long *keys = static_cast<const long long *>(a.keys);
+    const uint64_t mask = (1ull << a.log2cap) - 1ull;
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+        if (!((miss >> r) & 1u)) continue;
+        loc[r] = hgb_insert_from<long long, false>(a, keys, row[r], kk[r], global_slot_hash<long long>(kk[r]) & mask);
+        if (kk[r] == kCacheNoKey) continue;
+        for (int p = 0; p < kCacheProbe; ++p) {
+            const uint32_t slot = (ch[r] + p) & CM;
+            const long long old = (long long)atomicCAS(reinterpret_cast<unsigned long long *>(&s_k[slot]),
+                                                       (unsigned long long)kCacheNoKey, (unsigned long long)kk[r]);
+            if (old == kCacheNoKey) s_l[slot] = loc[r];
+            if (old == kCacheNoKey || old == kk[r]) break;
+        }
+    }
+}
+
+template <int LOG2C>
+__global__ __launch_bounds__(kInsBlock, 8) void k_hgb_insert_cached8(HgbArgs a) {
+    constexpr int RB = kInsRows8;
+    constexpr uint32_t kRound = (uint32_t)kInsBlock * RB;
+    __shared__ long long s_k[1u << LOG2C];
+    __shared__ uint32_t s_l[1u << LOG2C];
+    for (uint32_t j = threadIdx.x; j < (1u << LOG2C); j += kInsBlock) {
+        s_k[j] = kCacheNoKey;
+        s_l[j] = 0xFFFFFFFFu;
+    }
+    __syncthreads();
+    const long long *__restrict__ keys = static_cast<const long long *>(a.keys);
+    const uint32_t stride = gridDim.x * kRound;
+    uint32_t base = blockIdx.x * kRound;
+    for (; (uint64_t)base + kRound <= a.n; base += stride) {
+        // thread t: rows base + t * 4 .. + 3 (two 16-byte loads, one 16-byte store)
+        long long kk[RB];
+        uint32_t row[RB], loc[RB];
+        const uint32_t r0 = base + (uint32_t)threadIdx.x * 4u;
+        const longlong2 v0 = *reinterpret_cast<const longlong2 *>(keys + r0);
+        const longlong2 v1 = *reinterpret_cast<const longlong2 *>(keys + r0 + 2);
+        kk[0] = v0.x;
+        kk[1] = v0.y;
+        kk[2] = v1.x;
+        kk[3] = v1.y;
+#pragma unroll
+        for (int e = 0; e < RB; ++e) row[e] = r0 + e;
+        insert_cached_rows8<LOG2C, RB>(a, s_k, s_l, kk, row, (1u << RB) - 1u, loc);
+        *reinterpret_cast<uint4 *>(a.gid_loc + r0) = make_uint4(loc[0], loc[1], loc[2], loc[3]);
+    }
+    // the last, partial round of this workgroup (if any), row by row
+    if (base < a.n) {
+        long long kk[RB];
+        uint32_t row[RB], loc[RB];
+        uint32_t valid = 0;
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+            row[r] = base + (uint32_t)r * kInsBlock + threadIdx.x;
+            kk[r] = row[r] < a.n ? keys[row[r]] : 0;
+            valid |= (row[r] < a.n ? 1u : 0u) << r;
+        }
+        insert_cached_rows8<LOG2C, RB>(a, s_k, s_l, kk, row, valid, loc);
+#pragma unroll
+        for (int r = 0; r < RB; ++r)
+            if (row[r] < a.n) a.gid_loc[row[r]] = loc[r];
+    }
+}
+
 template <int NV, typename V, int G>
 __global__ __launch_bounds__(kBlock) void k_hgb_aggregate_few(HgbArgs a) {
     constexpr int RB = NV <= 2 ? 8 : 16 / NV;
@@ -2461,7 +2573,15 @@ static uint32_t hgb_assign_ids(Ctx &ctx, HgbArgs &a, int key_bytes, const void *
             }
         } else {
             GJ_LAUNCH("k_hgb_insert", 12.0 * prefix, k_hgb_insert<int64_t>, dim3(1), dim3(kBlock), 0, st, ap);
-            if (n > prefix) GJ_LAUNCH("k_hgb_insert", 12.0 * n, k_hgb_insert<int64_t>, dim3(grid), dim3(kBlock), 0, st, a);
+            if (n > prefix) {
+                // up to a few thousand groups: a 4096-entry LDS cache per workgroup
+                if (g_est > 0.0 && g_est <= 3072.0 && ((uintptr_t)key & 15u) == 0 && ((uintptr_t)a.gid_loc & 15u) == 0)
+                    GJ_LAUNCH("k_hgb_insert", 12.0 * n, k_hgb_insert_cached8<12>,
+                              dim3(std::min<uint32_t>(ceil_div_u32(n, kInsBlock * kInsRows8), 512)), dim3(kInsBlock),
+                              0, st, a);
+                else
+                    GJ_LAUNCH("k_hgb_insert", 12.0 * n, k_hgb_insert<int64_t>, dim3(grid), dim3(kBlock), 0, st, a);
+            }
         }
         uint32_t h[2];
         GJ_HIP(hipMemcpyAsync(h, a.ngroups, 8, hipMemcpyDeviceToHost, st));

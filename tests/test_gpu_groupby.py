@@ -250,6 +250,19 @@ def test_hash_misaligned_keys(card):
         np.testing.assert_array_equal(host(r)[order], e)
 
 
+@pytest.mark.parametrize("algo", ["hash", "sort_de"])
+def test_eight_byte_keys_cached_insert(algo):
+    """8-byte keys with few groups go through the insert's LDS cache of resolved
+    keys, whose empty marker is a key value (-2^63 + 1): rows holding that key
+    bypass the cache. Keys at and around the marker and both extremes."""
+    g = datagen.rng(77)
+    dom = np.array([-2**63, -2**63 + 1, -2**63 + 2, -1, 0, 1, 2**63 - 1], np.int64)
+    dom = np.concatenate([dom, g.integers(-2**62, 2**62, size=300, dtype=np.int64)])
+    keys = dom[g.integers(0, len(dom), size=200003)]
+    vals = [g.integers(-2**31, 2**31, size=len(keys)).astype(np.int32) for _ in range(2)]
+    check(keys, vals, algo=algo, sorted_out=(algo == "sort_de"))
+
+
 def test_hash_global_aggregation_path():
     d = datagen.groupby_input(100000, 2000, 2, seed=6)
     check(d["key"], d["vals"], algo="hash", lds_budget=64)
